@@ -1,0 +1,188 @@
+"""Plain FP64 CPU oracle for the direct-sum n-body hot path (test
+infrastructure).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The HIP library and its Python
+binding never import it; the two sides share no code, only the seeded
+inputs from ``ics``.
+
+The arithmetic lives in ``nbody_oracle.c`` (plain C, FP64, OpenMP over
+targets, built with ``-O2 -ffp-contract=off``); this module builds it with
+gcc and wraps it with numpy.  Each wrapper names the passage of the paper it
+follows; the C file states the formulas.
+
+Array conventions: ``pos_mass`` (N, 4) = (x, y, z, m); ``vel`` (N, 3) or
+(N, 4) (w ignored); FP32 inputs are widened exactly to FP64.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "nbody_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+_d = ctypes.POINTER(ctypes.c_double)
+_f = ctypes.POINTER(ctypes.c_float)
+_i64 = ctypes.POINTER(ctypes.c_int64)
+_i32 = ctypes.POINTER(ctypes.c_int32)
+
+
+def build(force: bool = True) -> str:
+    """Compile nbody_oracle.c into liboracle.so next to it (gcc, OpenMP)."""
+    if not force and os.path.exists(_LIB_PATH) and os.path.getmtime(_LIB_PATH) >= os.path.getmtime(_SRC):
+        return _LIB_PATH
+    tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+           "-Wall", "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        build(force=False)
+        lib = ctypes.CDLL(_LIB_PATH)
+        lib.oracle_accel.argtypes = [ctypes.c_int64, _d, _d, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_int64, _i64, _d, _d]
+        lib.oracle_accel.restype = None
+        lib.oracle_energy.argtypes = [ctypes.c_int64, _d, _d, _d, _d]
+        lib.oracle_energy.restype = None
+        lib.oracle_leapfrog.argtypes = [ctypes.c_int64, _d, _d, _d, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_int32, _d, _d, _d]
+        lib.oracle_leapfrog.restype = None
+        lib.oracle_orb_order.argtypes = [ctypes.c_int64, _f, ctypes.c_int32, _i32]
+        lib.oracle_orb_order.restype = ctypes.c_int
+        lib.oracle_vjp.argtypes = [ctypes.c_int64, _d, _d, ctypes.c_double, ctypes.c_double, _d, _d, _d, _d]
+        lib.oracle_vjp.restype = None
+        lib.oracle_traj_grad.argtypes = [ctypes.c_int64, _d, _d, _d, _d, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_int32, _d, _d, _d]
+        lib.oracle_traj_grad.restype = ctypes.c_double
+        lib.oracle_num_threads.argtypes = []
+        lib.oracle_num_threads.restype = ctypes.c_int
+        _lib = lib
+        return lib
+
+
+def _c64(a, shape_last=None) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    return a
+
+
+def _ptr(a: np.ndarray, t):
+    return a.ctypes.data_as(t)
+
+
+def _split(pos_mass):
+    pm = np.asarray(pos_mass)
+    x = np.ascontiguousarray(pm[:, :3], dtype=np.float64)
+    m = np.ascontiguousarray(pm[:, 3], dtype=np.float64)
+    return x, m
+
+
+def num_threads() -> int:
+    return int(_load().oracle_num_threads())
+
+
+def accel(pos_mass, eps: float, G: float = 1.0, targets=None):
+    """Exact softened direct sum (Section IV; force loop of Section IV.A with
+    every cell opened).  Returns (acc (T, 3), pot (T,)) for the targets
+    (all bodies when ``targets`` is None)."""
+    lib = _load()
+    x, m = _split(pos_mass)
+    n = x.shape[0]
+    if targets is None:
+        nt, tp = n, None
+    else:
+        t = np.ascontiguousarray(np.asarray(targets, dtype=np.int64))
+        if t.size and (t.min() < 0 or t.max() >= n):
+            raise IndexError("target index out of range")
+        nt, tp = t.shape[0], t
+    acc = np.empty((nt, 3))
+    pot = np.empty(nt)
+    lib.oracle_accel(n, _ptr(x, _d), _ptr(m, _d), float(G), float(eps), nt,
+                     None if tp is None else _ptr(tp, _i64), _ptr(acc, _d), _ptr(pot, _d))
+    return acc, pot
+
+
+def energy(vel, pos_mass, pot):
+    """(K, U) = (1/2 sum m |v|^2, 1/2 sum m phi)."""
+    lib = _load()
+    _, m = _split(pos_mass)
+    v = np.ascontiguousarray(np.asarray(vel)[:, :3], dtype=np.float64)
+    p = np.ascontiguousarray(pot, dtype=np.float64)
+    out = np.empty(2)
+    lib.oracle_energy(m.shape[0], _ptr(v, _d), _ptr(m, _d), _ptr(p, _d), _ptr(out, _d))
+    return float(out[0]), float(out[1])
+
+
+def leapfrog(pos_mass, vel, eps: float, dt: float, nsteps: int, G: float = 1.0):
+    """Kick-drift-kick leapfrog (Move_bodies after Calculate_forces, Section
+    IV.B pseudo-code).  Returns dict with x, v (N, 3), acc (N, 3), pot (N,)
+    at the final state and energy ((nsteps+1), 2)."""
+    lib = _load()
+    x, m = _split(pos_mass)
+    v = np.ascontiguousarray(np.asarray(vel)[:, :3], dtype=np.float64).copy()
+    x = x.copy()
+    n = x.shape[0]
+    acc = np.empty((n, 3))
+    pot = np.empty(n)
+    en = np.empty((nsteps + 1, 2))
+    lib.oracle_leapfrog(n, _ptr(x, _d), _ptr(v, _d), _ptr(m, _d), float(G), float(eps), float(dt),
+                        int(nsteps), _ptr(acc, _d), _ptr(pot, _d), _ptr(en, _d))
+    return dict(x=x, v=v, acc=acc, pot=pot, energy=en)
+
+
+def orb_order(pos, leaf: int) -> np.ndarray:
+    """Orthogonal Recursive Bisection order (Section IV.B) on the FP32
+    coordinates of ``pos`` (N, >=3); perm[p] = original index at position p."""
+    lib = _load()
+    xf = np.ascontiguousarray(np.asarray(pos)[:, :3], dtype=np.float32)
+    n = xf.shape[0]
+    perm = np.empty(n, dtype=np.int32)
+    rc = lib.oracle_orb_order(n, _ptr(xf, _f), int(leaf), _ptr(perm, _i32))
+    if rc != 0:
+        raise ValueError("oracle_orb_order: bad arguments")
+    return perm
+
+
+def vjp(pos_mass, eps: float, acc_cot, pot_cot=None, G: float = 1.0):
+    """Vector-Jacobian product of the direct sum with respect to positions and
+    masses.  Returns (x_cot (N, 3), m_cot (N,))."""
+    lib = _load()
+    x, m = _split(pos_mass)
+    n = x.shape[0]
+    ab = np.ascontiguousarray(np.asarray(acc_cot)[:, :3], dtype=np.float64)
+    pb = None if pot_cot is None else np.ascontiguousarray(pot_cot, dtype=np.float64)
+    xb = np.empty((n, 3))
+    mb = np.empty(n)
+    lib.oracle_vjp(n, _ptr(x, _d), _ptr(m, _d), float(G), float(eps), _ptr(ab, _d),
+                   None if pb is None else _ptr(pb, _d), _ptr(xb, _d), _ptr(mb, _d))
+    return xb, mb
+
+
+def traj_grad(pos_mass, vel, y, eps: float, dt: float, nsteps: int, G: float = 1.0):
+    """Loss L = sum |x(T) - y|^2 through ``nsteps`` leapfrog steps and its
+    gradient (dL/dx0 (N,3), dL/dv0 (N,3), dL/dm (N,))."""
+    lib = _load()
+    x, m = _split(pos_mass)
+    n = x.shape[0]
+    v = np.ascontiguousarray(np.asarray(vel)[:, :3], dtype=np.float64)
+    yy = np.ascontiguousarray(np.asarray(y)[:, :3], dtype=np.float64)
+    gx = np.empty((n, 3))
+    gv = np.empty((n, 3))
+    gm = np.empty(n)
+    L = lib.oracle_traj_grad(n, _ptr(x, _d), _ptr(v, _d), _ptr(m, _d), _ptr(yy, _d), float(G), float(eps),
+                             float(dt), int(nsteps), _ptr(gx, _d), _ptr(gv, _d), _ptr(gm, _d))
+    return float(L), gx, gv, gm
