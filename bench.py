@@ -1,0 +1,252 @@
+#!/usr/bin/env python3
+"""Benchmark of the direct-sum n-body hot path on one MI355X.
+
+Workload (the throughput headline): two colliding Plummer spheres,
+N = 2^20 = 1,048,576 bodies, mass ratio 1:3, centres (+-2, 0, 0), relative
+speed 0.3, eps = 0.005, FP32 pair arithmetic with FP64 sums across source
+tiles (NBODY_F32_F64ACC), leapfrog KDK with dt = 5e-4.  Synthetic inputs,
+seeded, resident in HBM before the timed region.
+
+One step = one force + potential evaluation over all N^2 pairs (nbody_accel)
+plus the elementwise kick/drift pass (nbody_kick_drift), i.e. one KDK step.
+value = N^2 / (seconds per step) / 1e9 = G-interactions/s.
+
+Also reported on the same JSON line:
+* roofline: the force kernel (VALU-bound, 20 flop per pair) against the
+  MI355X FP32 vector peak, from HIP events around every force launch of the
+  timed region;
+* cpu_baseline: the FP64 oracle on a bounded sample of targets of the same
+  workload, on the host cores, and the GPU's error against it;
+* adjoint: forward+adjoint time / plain forward time for the differentiation
+  workload (Plummer N = 16384, 200 steps, checkpoints every 20);
+* batched: aggregate G-interactions/s for 512 ragged Plummer systems, 50
+  steps captured in one HIP graph.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (AMD), packed FP32 counted
+FLOP_PER_PAIR = 20
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-extras", action="store_true", help="skip adjoint, batched and CPU legs")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU target sharding is designed, not built)"}))
+        sys.exit(2)
+
+    import torch
+    import ics
+    import paper_1211_2292_amd as nb
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    nb.lib()
+    dev = torch.device("cuda:0")
+    w = ics.WORKLOADS["collide1m"]
+    n, eps, dt = w["n"], w["eps"], w["dt"]
+    prec = nb.F32_F64ACC
+    log(f"[bench] generating colliding pair N={n}")
+    pm_np, v_np = ics.colliding_pair(n, w["seed"])
+    pm = torch.as_tensor(pm_np, dtype=torch.float32).to(dev).contiguous()
+    vel = torch.as_tensor(v_np, dtype=torch.float32).to(dev).contiguous()
+    acc = torch.empty_like(pm)
+    pm0_host = pm.cpu().double().numpy()
+
+    # first evaluation (step 0 forces, kept for the accuracy check)
+    nb.accel(pm, eps, prec=prec, out=acc)
+    torch.cuda.synchronize()
+    acc0 = acc.cpu().double().numpy()
+    h = 0.5 * dt
+    nb.kick_drift(pm, vel, acc, h, dt, close=False, open=True, prec=prec)
+
+    def step(e0=None, e1=None):
+        if e0 is not None:
+            e0.record()
+        nb.accel(pm, eps, prec=prec, out=acc)
+        if e1 is not None:
+            e1.record()
+        nb.kick_drift(pm, vel, acc, h, dt, close=True, open=True, prec=prec)
+
+    log(f"[bench] warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    log(f"[bench] timing {args.steps} steps")
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t_start.record()
+    for k in range(args.steps):
+        step(*ev[k])
+    t_end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = t_start.elapsed_time(t_end)
+    ms_per_step = total_ms / args.steps
+    kern_ms = [a.elapsed_time(b) for a, b in ev]
+    kern_avg = float(np.mean(kern_ms))
+    pairs = float(n) * float(n)
+    value = pairs / (ms_per_step * 1e-3) / 1e9
+    achieved = FLOP_PER_PAIR * pairs / (kern_avg * 1e-3) / 1e12
+    tune = nb.get_tuning(0, prec, n)
+    log(f"[bench] {ms_per_step:.2f} ms/step, force kernel {kern_avg:.2f} ms, {value:.1f} Gint/s, "
+        f"{achieved:.2f} TFLOP/s ({100 * achieved / PEAK_FP32_TFLOPS:.1f}% of FP32 peak), tune {tune}")
+
+    result = {
+        "metric": "G-interactions/s and % FP32 peak at N=1M; fwd+adjoint step time vs plain fwd",
+        "value": round(value, 2),
+        "unit": "G-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 pair arithmetic, f64 cross-tile sums",
+        "data": "synthetic (seeded colliding Plummer spheres)",
+        "config": {"workload": "colliding Plummer pair, N=1048576, mass ratio 1:3, eps=0.005, "
+                               "dt=5e-4, leapfrog KDK, NBODY_F32_F64ACC",
+                   "n": n, "eps": eps, "dt": dt, "precision": "F32_F64ACC",
+                   "kernel_shape": {"tpl": tune[0], "jsplit": tune[1], "jtile": tune[2]}},
+        "pct_fp32_peak": round(100 * achieved / PEAK_FP32_TFLOPS, 2),
+        "wall_s_timed": round(wall, 3),
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                     "kernel": "k_accel_f32<TPL, F64ACC>", "flop_per_pair": FLOP_PER_PAIR,
+                     "avg_launch_ms": round(kern_avg, 4)},
+    }
+
+    if not args.no_extras:
+        result["adjoint"] = adjoint_leg(torch, nb, ics, dev)
+        result["batched"] = batched_leg(torch, nb, ics, dev)
+        result["cpu_baseline"] = cpu_leg(ics, pm0_host, acc0, eps, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+def adjoint_leg(torch, nb, ics, dev):
+    """Plummer N = 16384, FP32 + Kahan, 200 steps, dt = 1e-3, checkpoints
+    every 20: [forward with checkpoints + adjoint] / [plain forward]."""
+    w = ics.WORKLOADS["adjoint16384"]
+    n, eps, dt, steps, C = w["n"], w["eps"], w["dt"], w["steps"], w["ckpt"]
+    log(f"[bench] adjoint leg N={n}, {steps} steps")
+    pm_np, v_np = ics.plummer(n, w["seed"])
+    y = torch.as_tensor(ics.perturbed_snapshot(pm_np, w["seed"] + 2), dtype=torch.float32, device=dev)
+    p0 = torch.as_tensor(pm_np, dtype=torch.float32, device=dev).contiguous()
+    v0 = torch.as_tensor(v_np, dtype=torch.float32, device=dev).contiguous()
+    prec = nb.F32_KAHAN
+
+    def plain():
+        p, v = p0.clone(), v0.clone()
+        a = torch.empty_like(p)
+        nb.leapfrog_kdk(p, v, a, eps, dt, steps, prec=prec)
+        return p
+
+    def fwd_adj():
+        p, v = p0.clone(), v0.clone()
+        ck = nb.trajectory_forward(p, v, eps, dt, steps, C, prec=prec)
+        xb = torch.zeros_like(p)
+        xb[:, :3] = 2 * (p[:, :3] - y)
+        vb = torch.zeros_like(p)
+        return nb.trajectory_adjoint(ck, eps, dt, steps, C, xb, vb, prec=prec)
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts))
+
+    t_plain = timed(plain)
+    t_fa = timed(fwd_adj)
+    log(f"[bench] adjoint: plain {t_plain:.1f} ms, fwd+adj {t_fa:.1f} ms, ratio {t_fa / t_plain:.2f}")
+    return {"workload": "Plummer N=16384, F32_KAHAN, 200 steps dt=1e-3, checkpoints every 20",
+            "plain_forward_ms": round(t_plain, 3), "fwd_plus_adjoint_ms": round(t_fa, 3),
+            "ratio": round(t_fa / t_plain, 3), "scheme": "segment recompute from checkpoints"}
+
+
+def batched_leg(torch, nb, ics, dev):
+    """512 Plummer systems, N_s log-uniform in [256, 32768], FP32 + Kahan,
+    50 KDK steps dt = 1e-3 captured in one HIP graph."""
+    w = ics.WORKLOADS["batch512"]
+    log("[bench] batched leg: generating 512 systems")
+    pm_np, v_np, off = ics.ragged_batch(w["nsys"], w["seed"])
+    p = torch.as_tensor(pm_np, dtype=torch.float32, device=dev).contiguous()
+    v = torch.as_tensor(v_np, dtype=torch.float32, device=dev).contiguous()
+    a = torch.empty_like(p)
+    steps = w["steps"]
+    nb.leapfrog_kdk(p, v, a, w["eps"], w["dt"], steps, offsets=off, graph=True)  # capture + warm
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    nb.leapfrog_kdk(p, v, a, w["eps"], w["dt"], steps, offsets=off, graph=True, acc_valid=True)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    sizes = np.diff(off).astype(np.float64)
+    pairs = float((sizes ** 2).sum()) * steps
+    gint = pairs / (ms * 1e-3) / 1e9
+    log(f"[bench] batched: {ms:.1f} ms for {steps} steps, {gint:.1f} Gint/s")
+    return {"workload": "512 Plummer systems, N_s log-uniform [256, 32768], F32_KAHAN, 50 steps in one graph",
+            "bodies": int(off[-1]), "ms": round(ms, 3), "g_interactions_per_s": round(gint, 2)}
+
+
+def cpu_leg(ics, pm0_host, acc0, eps, seconds):
+    """FP64 oracle on a bounded sample of targets of the headline workload."""
+    import oracle
+    n = pm0_host.shape[0]
+    threads = oracle.num_threads()
+    cal = ics.sample_targets(n, 16, 7)
+    t0 = time.perf_counter()
+    oracle.accel(pm0_host, eps, targets=cal)
+    rate = 16 * n / (time.perf_counter() - t0)
+    k = int(max(32, min(1024, seconds * rate / n)))
+    tg = ics.sample_targets(n, k, 1003)
+    log(f"[bench] cpu oracle: {k} targets x {n} sources on {threads} threads")
+    t0 = time.perf_counter()
+    ref_a, ref_p = oracle.accel(pm0_host, eps, targets=tg)
+    secs = time.perf_counter() - t0
+    gint = k * n / secs / 1e9
+    da = np.linalg.norm(acc0[tg, :3] - ref_a, axis=1) / np.linalg.norm(ref_a, axis=1)
+    dp = np.abs(acc0[tg, 3] - ref_p) / np.abs(ref_p)
+    return {"value": round(gint, 5), "unit": "G-interactions/s", "cores": threads, "kind": "oracle",
+            "sample": f"{k} sampled targets x {n} sources of the colliding pair, FP64 Neumaier sums",
+            "seconds": round(secs, 2),
+            "gpu_error_vs_oracle": {"force_rms_rel": float(np.sqrt(np.mean(da ** 2))),
+                                    "force_max_rel": float(da.max()),
+                                    "pot_rms_rel": float(np.sqrt(np.mean(dp ** 2)))}}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,223 @@
+/*
+ * nbody.h -- C ABI of the MI355X (gfx950) direct-sum n-body library.
+ *
+ * The library computes the hot path of the n-body simulation in Duy,
+ * Yamazaki, Ikegami and Oyanagi, "Hybrid MPI-OpenMP Paradigm on SMP clusters:
+ * MPEG-2 Encoder and n-body Simulation": the force calculation that the
+ * paper's Section IV.B says takes upwards of 90% of the cycles, evaluated
+ * exactly (every body against every other body, the limit of the tree code of
+ * Section IV.A with every cell opened), and the position/velocity update
+ * around it (Move_bodies in the Section IV.B pseudo-code).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers are DEVICE pointers unless the parameter says "host".  The
+ *   caller owns every buffer passed in.  The library owns only internal
+ *   scratch (released by nbody_release()).
+ * - Body records are 4-vectors, array-of-structures:
+ *     pos_mass  (x, y, z, m)        float4 (FP32 modes) or double4 (NBODY_F64)
+ *     vel       (vx, vy, vz, unused)
+ *     acc_pot   (ax, ay, az, phi)   the output of the force evaluation
+ *   float4 buffers must be 16-byte aligned, double4 buffers 32-byte aligned.
+ * - Law (Section IV; G and Plummer softening eps are parameters):
+ *     a_i   =  G sum_{j != i} m_j (x_j - x_i) / (|x_j - x_i|^2 + eps^2)^(3/2)
+ *     phi_i = -G sum_{j != i} m_j / (|x_j - x_i|^2 + eps^2)^(1/2)
+ *   The self pair j == i is excluded from both sums.  eps = 0 is allowed;
+ *   then two distinct bodies at the same position give IEEE inf/NaN.
+ * - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *   Every call is stream-ordered and asynchronous: it validates its
+ *   arguments on the host, enqueues kernels and returns.  No call below
+ *   synchronises the device except nbody_autotune().
+ * - Return value: NBODY_OK (0) or a negative status.  On a validation error
+ *   nothing has been enqueued.  nbody_last_error() gives a thread-local
+ *   message for the last failing call.  The library never aborts or exits.
+ * - Sizes: 1 <= n <= 2^31 - 4096.  Non-finite positions or masses are a
+ *   precondition violation (results then unspecified).
+ */
+#ifndef NBODY_H
+#define NBODY_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Arithmetic of the force evaluation. */
+typedef enum {
+    NBODY_F64 = 0,        /* FP64 state, FP64 pair arithmetic and sums          */
+    NBODY_F32 = 1,        /* FP32 state, FP32 pair arithmetic, FP32 running sum */
+    NBODY_F32_KAHAN = 2,  /* FP32 pair arithmetic, FP32 per-tile partial sums,
+                             Kahan-compensated FP32 sum across tiles           */
+    NBODY_F32_F64ACC = 3  /* FP32 pair arithmetic, FP32 per-tile partial sums,
+                             FP64 sum across tiles                             */
+} nbody_prec;
+
+enum {
+    NBODY_OK = 0,
+    NBODY_E_INVAL = -1,       /* bad size, pointer, enum or non-finite scalar */
+    NBODY_E_ALIGN = -2,       /* a vector buffer is not naturally aligned     */
+    NBODY_E_NOMEM = -3,       /* library scratch could not be allocated       */
+    NBODY_E_HIP = -4,         /* a HIP call failed (see nbody_last_error)     */
+    NBODY_E_UNSUPPORTED = -5  /* valid but unsupported combination            */
+};
+
+/* Flags of nbody_leapfrog_kdk. */
+#define NBODY_ACC_VALID 0x1u /* acc_pot already holds a(x) at the input state */
+#define NBODY_GRAPH 0x2u     /* capture the step loop in a HIP graph, reuse it */
+#define NBODY_ENERGY 0x4u    /* write FP64 energies to energy_out             */
+
+/*
+ * Orthogonal Recursive Bisection order (Section IV.B: divide space into
+ * non-overlapping sub-spaces with about equal numbers of bodies), used here
+ * as a body ordering on one device: leaves of at most `leaf` spatially close
+ * bodies become contiguous.
+ *   ORB(S): if |S| <= leaf, S by ascending original index.  Otherwise split
+ *   on the axis of largest FP32 extent fl32(max - min) (ties: x, then y, then
+ *   z); keys (IEEE total order of the FP32 coordinate, original index); the
+ *   left part is the k = leaf * ceil(ceil(|S|/leaf) / 2) smallest keys; emit
+ *   ORB(left) then ORB(right).  Coordinates of NBODY_F64 input are rounded to
+ *   FP32 first.  The result is a pure function of the input (bit-exact).
+ * pos_mass: n records (float4 or double4 by prec).  perm_out: int32[n],
+ * perm_out[p] = original index of the body at position p.  Uses library
+ * scratch of about 40 bytes per body.
+ */
+int nbody_orb_order(const void *pos_mass, int32_t prec, int64_t n, int32_t leaf,
+                    int32_t *perm_out, void *stream);
+
+/*
+ * Gather or scatter of 16- or 32-byte records through a permutation:
+ *   inverse == 0: dst[p] = src[perm[p]]   (apply an ORB order)
+ *   inverse != 0: dst[perm[p]] = src[p]   (return results to input order)
+ * rec_bytes is 16 or 32.  src and dst must not overlap.
+ */
+int nbody_permute(const void *src, void *dst, const int32_t *perm, int64_t n,
+                  int32_t rec_bytes, int32_t inverse, void *stream);
+
+/*
+ * Force and potential (the paper's Calculate_forces, Section IV.B, with every
+ * body on every interaction list) for targets [target_begin,
+ * target_begin + target_count) against all n sources.
+ * acc_pot_out: target_count records, entry t for target target_begin + t;
+ * it must not overlap pos_mass.  Deterministic: the same inputs and tuning
+ * give bitwise the same output.
+ */
+int nbody_accel(const void *pos_mass, int64_t n, int32_t prec, double G, double eps,
+                void *acc_pot_out, int64_t target_begin, int64_t target_count, void *stream);
+
+/*
+ * Fused force + vector-Jacobian product at one configuration (derivative of
+ * the law above; the paper has no derivatives).  Given cotangents
+ * acc_pot_cot = (abar, phibar) per body, writes
+ *   pos_cot_out[k]  = xbar_k = sum_i (da_i/dx_k)^T abar_i + (dphi_i/dx_k) phibar_i
+ *                     (record (x, y, z, 0))
+ *   mass_cot_out[k] = mbar_k = sum_i abar_i . da_i/dm_k + phibar_i dphi_i/dm_k
+ *                     (float or double by prec)
+ *   acc_pot_out     = the forward force, if not NULL.
+ * All outputs have n entries and must not overlap the inputs.
+ */
+int nbody_accel_vjp(const void *pos_mass, const void *acc_pot_cot, int64_t n, int32_t prec,
+                    double G, double eps, void *pos_cot_out, void *mass_cot_out,
+                    void *acc_pot_out, void *stream);
+
+/*
+ * nsteps of kick-drift-kick leapfrog with one force evaluation per step
+ * (Move_bodies after Calculate_forces, Section IV.B), h = dt / 2:
+ *   v += h a(x);  x += dt v;  a = a(x);  v += h a
+ * pos_mass, vel, acc_pot are updated in place (acc_pot ends as a(x_final)).
+ * Unless flags has NBODY_ACC_VALID, a(x) is evaluated first.
+ * offsets_host (host, int64[nsys+1], NULL for one system): independent
+ * systems stored back to back, offsets[0] = 0, offsets[nsys] = n,
+ * nondecreasing; forces act only within a system.
+ * NBODY_ENERGY: energy_out (device, double[(nsteps+1)*2]) receives
+ * (K, U) = (1/2 sum m|v|^2, 1/2 sum m phi) in FP64 after each step, entry 0
+ * at the input state (one system only).
+ * NBODY_GRAPH: the whole step loop is captured once into a HIP graph keyed by
+ * (pointers, sizes, scalars, flags) and replayed on later identical calls.
+ */
+int nbody_leapfrog_kdk(void *pos_mass, void *vel, void *acc_pot, int64_t n,
+                       const int64_t *offsets_host, int32_t nsys, int32_t prec, double G,
+                       double eps, double dt, int32_t nsteps, uint32_t flags,
+                       double *energy_out, void *stream);
+
+/*
+ * The elementwise half of one leapfrog step, for callers that drive the loop
+ * themselves (nbody_leapfrog_kdk is nbody_accel plus this):
+ *   close != 0: v += h a             (closing kick with a = acc_pot)
+ *   open  != 0: v += h a; x += dt v  (opening kick and drift)
+ * Both may be set (closing kick of one step, then opening kick and drift of
+ * the next, h = dt/2 for both).  pos_mass and vel are updated in place.
+ */
+int nbody_kick_drift(void *pos_mass, void *vel, const void *acc_pot, int64_t n, int32_t prec,
+                     double h, double dt, int32_t close, int32_t open, void *stream);
+
+/*
+ * Force and potential of nsys independent systems stored back to back
+ * (offsets_host as above) in one persistent launch over a longest-first
+ * work list of (system, target tile) units.  eps_per_sys: device float[nsys]
+ * or NULL to use `eps` for all.  Each system's result is bitwise the result
+ * of nbody_accel on that system alone with the same tuning.
+ */
+int nbody_batched_accel(const void *pos_mass, const int64_t *offsets_host, int32_t nsys,
+                        int32_t prec, double G, const float *eps_per_sys, double eps,
+                        void *acc_pot_out, void *stream);
+
+/*
+ * FP64 energy diagnostics of one system: energy_out (device, double[2]) =
+ * (K, U) with K = 1/2 sum m |v|^2 and U = 1/2 sum m phi (phi from acc_pot).
+ * Deterministic fixed-order reduction.
+ */
+int nbody_energy(const void *pos_mass, const void *vel, const void *acc_pot, int64_t n,
+                 int32_t prec, double *energy_out, void *stream);
+
+/*
+ * Leapfrog trajectory with checkpoints, and its adjoint.
+ * nbody_trajectory_forward runs nsteps of nbody_leapfrog_kdk from
+ * (pos_mass, vel) in place and stores (pos_mass, vel) every ckpt_every steps
+ * into ckpt (device), slot c holding step c*ckpt_every for
+ * c = 0..nsteps/ckpt_every: slot size 2 records per body.  nsteps must be a
+ * multiple of ckpt_every.
+ * nbody_trajectory_adjoint takes the cotangents (xbar_T, vbar_T) of the
+ * final positions and velocities (records, w unused) and returns the
+ * gradients with respect to the initial positions (pos_cot, record x,y,z),
+ * velocities (vel_cot) and masses (mass_cot, float/double[n]).  It re-runs
+ * each segment forward from its checkpoint and applies one fused force+VJP
+ * per position.  xbar_T / vbar_T are read only.
+ */
+int nbody_trajectory_forward(void *pos_mass, void *vel, int64_t n, int32_t prec, double G,
+                             double eps, double dt, int32_t nsteps, int32_t ckpt_every,
+                             void *ckpt, void *stream);
+int nbody_trajectory_adjoint(const void *ckpt, int64_t n, int32_t prec, double G, double eps,
+                             double dt, int32_t nsteps, int32_t ckpt_every,
+                             const void *xbar_T, const void *vbar_T, void *pos_cot,
+                             void *vel_cot, void *mass_cot, void *stream);
+
+/*
+ * Tuning.  nbody_autotune times the candidate kernel shapes for one problem
+ * (kernel 0 = nbody_accel at size n, 1 = nbody_batched_accel for the given
+ * offsets, 2 = nbody_accel_vjp) on library-owned synthetic inputs,
+ * synchronously, and records the fastest in the in-process table (and in the
+ * JSON file named by the environment variable NBODY_TUNE_CACHE, if set).
+ * nbody_set_tuning pins a shape for later calls: tpl (targets per lane:
+ * 1, 2, 4), jsplit (waves sharing targets: 1, 2, 4), jtile (sources per
+ * partial sum, multiple of 8); kernel and prec as above; all -1 clears it.
+ * nbody_get_tuning reports the shape the library would use.
+ */
+int nbody_autotune(int32_t kernel, int32_t prec, int64_t n, const int64_t *offsets_host,
+                   int32_t nsys, void *stream);
+int nbody_set_tuning(int32_t kernel, int32_t prec, int32_t tpl, int32_t jsplit, int32_t jtile);
+int nbody_get_tuning(int32_t kernel, int32_t prec, int64_t n, int32_t *tpl, int32_t *jsplit,
+                     int32_t *jtile);
+
+const char *nbody_status_string(int status);
+const char *nbody_last_error(void);
+/* Frees library scratch, cached graphs and work lists on every device. */
+void nbody_release(void);
+/* Library ABI version (major * 100 + minor). */
+int nbody_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NBODY_H */

@@ -1,0 +1,336 @@
+"""Python binding of the gfx950 direct-sum n-body library (include/nbody.h).
+
+Argument marshalling only: every entry point checks dtypes, devices, shapes
+and contiguity, then calls the C ABI of ``libnbody.so`` with raw device
+pointers and torch's current HIP stream.  All arithmetic runs in the HIP
+kernels of the library; there is no fallback.  If the library has not been
+built (``python -m paper_1211_2292_amd.build``), the first call raises.
+
+Records are (N, 4) tensors on the GPU: pos_mass = (x, y, z, m),
+vel = (vx, vy, vz, unused), acc_pot = (ax, ay, az, phi).  float64 tensors use
+the FP64 path; float32 tensors use one of the FP32 modes (default
+NBODY_F32_KAHAN).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+__all__ = [
+    "F64", "F32", "F32_KAHAN", "F32_F64ACC", "ACC_VALID", "GRAPH", "ENERGY",
+    "lib", "accel", "accel_vjp", "leapfrog_kdk", "kick_drift", "batched_accel", "energy", "orb_order",
+    "permute", "trajectory_forward", "trajectory_adjoint", "NBodyTrajectory", "autotune",
+    "set_tuning", "get_tuning", "release", "NBodyError",
+]
+
+F64, F32, F32_KAHAN, F32_F64ACC = 0, 1, 2, 3
+ACC_VALID, GRAPH, ENERGY = 0x1, 0x2, 0x4
+KERNEL_ACCEL, KERNEL_BATCHED, KERNEL_VJP = 0, 1, 2
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnbody.so")
+_lock = threading.Lock()
+_lib = None
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_dbl = ctypes.c_double
+
+_SIGS = {
+    "nbody_orb_order": [_vp, _i32, _i64, _i32, _vp, _vp],
+    "nbody_permute": [_vp, _vp, _vp, _i64, _i32, _i32, _vp],
+    "nbody_accel": [_vp, _i64, _i32, _dbl, _dbl, _vp, _i64, _i64, _vp],
+    "nbody_accel_vjp": [_vp, _vp, _i64, _i32, _dbl, _dbl, _vp, _vp, _vp, _vp],
+    "nbody_leapfrog_kdk": [_vp, _vp, _vp, _i64, _vp, _i32, _i32, _dbl, _dbl, _dbl, _i32,
+                           ctypes.c_uint32, _vp, _vp],
+    "nbody_kick_drift": [_vp, _vp, _vp, _i64, _i32, _dbl, _dbl, _i32, _i32, _vp],
+    "nbody_batched_accel": [_vp, _vp, _i32, _i32, _dbl, _vp, _dbl, _vp, _vp],
+    "nbody_energy": [_vp, _vp, _vp, _i64, _i32, _vp, _vp],
+    "nbody_trajectory_forward": [_vp, _vp, _i64, _i32, _dbl, _dbl, _dbl, _i32, _i32, _vp, _vp],
+    "nbody_trajectory_adjoint": [_vp, _i64, _i32, _dbl, _dbl, _dbl, _i32, _i32, _vp, _vp, _vp,
+                                 _vp, _vp, _vp],
+    "nbody_autotune": [_i32, _i32, _i64, _vp, _i32, _vp],
+    "nbody_set_tuning": [_i32, _i32, _i32, _i32, _i32],
+    "nbody_get_tuning": [_i32, _i32, _i64, _vp, _vp, _vp],
+    "nbody_status_string": [ctypes.c_int],
+    "nbody_last_error": [],
+    "nbody_release": [],
+    "nbody_version": [],
+}
+
+
+class NBodyError(RuntimeError):
+    pass
+
+
+def lib():
+    """Load libnbody.so (in-tree build) and declare its signatures."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise NBodyError(f"{LIB_PATH} is not built; run `python -m paper_1211_2292_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.nbody_status_string.restype = ctypes.c_char_p
+        L.nbody_last_error.restype = ctypes.c_char_p
+        L.nbody_release.restype = None
+        _lib = L
+        return L
+
+
+def _check(rc: int):
+    if rc != 0:
+        L = lib()
+        raise NBodyError(f"{L.nbody_status_string(rc).decode()} ({rc}): {L.nbody_last_error().decode()}")
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _rec(t: torch.Tensor, name: str, dtype=None) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on the GPU")
+    if t.dim() != 2 or t.shape[1] != 4:
+        raise ValueError(f"{name} must have shape (N, 4), got {tuple(t.shape)}")
+    if t.dtype not in (torch.float32, torch.float64):
+        raise TypeError(f"{name} must be float32 or float64")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _prec(t: torch.Tensor, prec):
+    if t.dtype == torch.float64:
+        if prec not in (None, F64):
+            raise ValueError("float64 tensors use prec=F64")
+        return F64
+    if prec is None:
+        return F32_KAHAN
+    if prec not in (F32, F32_KAHAN, F32_F64ACC):
+        raise ValueError("float32 tensors use prec F32, F32_KAHAN or F32_F64ACC")
+    return prec
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def accel(pos_mass, eps, G=1.0, prec=None, target_begin=0, target_count=None, out=None):
+    """Force and potential records for targets [target_begin, +target_count)."""
+    pm = _rec(pos_mass, "pos_mass")
+    p = _prec(pm, prec)
+    n = pm.shape[0]
+    tc = n - target_begin if target_count is None else target_count
+    if out is None:
+        out = torch.empty((tc, 4), dtype=pm.dtype, device=pm.device)
+    else:
+        _rec(out, "out", pm.dtype)
+    _check(lib().nbody_accel(_ptr(pm), n, p, float(G), float(eps), _ptr(out), int(target_begin), int(tc),
+                             _stream()))
+    return out
+
+
+def accel_vjp(pos_mass, acc_pot_cot, eps, G=1.0, prec=None, forward=True):
+    """(pos_cot (N,4), mass_cot (N,), acc_pot (N,4) or None) at one configuration."""
+    pm = _rec(pos_mass, "pos_mass")
+    cot = _rec(acc_pot_cot, "acc_pot_cot", pm.dtype)
+    p = _prec(pm, prec)
+    n = pm.shape[0]
+    pc = torch.empty_like(pm)
+    mc = torch.empty(n, dtype=pm.dtype, device=pm.device)
+    ap = torch.empty_like(pm) if forward else None
+    _check(lib().nbody_accel_vjp(_ptr(pm), _ptr(cot), n, p, float(G), float(eps), _ptr(pc), _ptr(mc),
+                                 _ptr(ap), _stream()))
+    return pc, mc, ap
+
+
+def _offsets(offsets):
+    if offsets is None:
+        return None, 0, None
+    o = torch.as_tensor(offsets, dtype=torch.int64).cpu().contiguous()
+    return o, int(o.numel() - 1), ctypes.c_void_p(o.data_ptr())
+
+
+def leapfrog_kdk(pos_mass, vel, acc_pot, eps, dt, nsteps, G=1.0, prec=None, offsets=None,
+                 acc_valid=False, graph=False, energy=False, energy_out=None):
+    """nsteps of KDK leapfrog in place; returns the (nsteps+1, 2) FP64 energy
+    tensor when energy=True (``energy_out`` if given), else None."""
+    pm = _rec(pos_mass, "pos_mass")
+    v = _rec(vel, "vel", pm.dtype)
+    a = _rec(acc_pot, "acc_pot", pm.dtype)
+    p = _prec(pm, prec)
+    o, nsys, optr = _offsets(offsets)
+    flags = (ACC_VALID if acc_valid else 0) | (GRAPH if graph else 0) | (ENERGY if energy else 0)
+    en = None
+    if energy:
+        en = energy_out
+        if en is None:
+            en = torch.empty((nsteps + 1, 2), dtype=torch.float64, device=pm.device)
+        elif en.dtype != torch.float64 or not en.is_contiguous() or en.numel() < 2 * (nsteps + 1):
+            raise ValueError("energy_out must be a contiguous float64 tensor of (nsteps+1)*2 entries")
+    _check(lib().nbody_leapfrog_kdk(_ptr(pm), _ptr(v), _ptr(a), pm.shape[0], optr, nsys, p, float(G),
+                                    float(eps), float(dt), int(nsteps), flags, _ptr(en), _stream()))
+    return en
+
+
+def kick_drift(pos_mass, vel, acc_pot, h, dt, close, open, prec=None):
+    """Elementwise leapfrog half-step in place (see nbody.h)."""
+    pm = _rec(pos_mass, "pos_mass")
+    v = _rec(vel, "vel", pm.dtype)
+    a = _rec(acc_pot, "acc_pot", pm.dtype)
+    p = _prec(pm, prec)
+    _check(lib().nbody_kick_drift(_ptr(pm), _ptr(v), _ptr(a), pm.shape[0], p, float(h), float(dt),
+                                  1 if close else 0, 1 if open else 0, _stream()))
+
+
+def batched_accel(pos_mass, offsets, eps, G=1.0, prec=None, eps_per_sys=None, out=None):
+    pm = _rec(pos_mass, "pos_mass")
+    p = _prec(pm, prec)
+    o, nsys, optr = _offsets(offsets)
+    if o is None:
+        raise ValueError("offsets required")
+    if out is None:
+        out = torch.empty_like(pm)
+    else:
+        _rec(out, "out", pm.dtype)
+    eptr = None
+    if eps_per_sys is not None:
+        if eps_per_sys.dtype != torch.float32 or eps_per_sys.device.type != "cuda" or \
+                not eps_per_sys.is_contiguous() or eps_per_sys.numel() != nsys:
+            raise ValueError("eps_per_sys must be a contiguous float32 GPU tensor of nsys entries")
+        eptr = _ptr(eps_per_sys)
+    _check(lib().nbody_batched_accel(_ptr(pm), optr, nsys, p, float(G), eptr, float(eps), _ptr(out),
+                                     _stream()))
+    return out
+
+
+def energy(pos_mass, vel, acc_pot, prec=None):
+    """FP64 (K, U) of one system as a 2-element float64 GPU tensor."""
+    pm = _rec(pos_mass, "pos_mass")
+    v = _rec(vel, "vel", pm.dtype)
+    a = _rec(acc_pot, "acc_pot", pm.dtype)
+    p = _prec(pm, prec)
+    out = torch.empty(2, dtype=torch.float64, device=pm.device)
+    _check(lib().nbody_energy(_ptr(pm), _ptr(v), _ptr(a), pm.shape[0], p, _ptr(out), _stream()))
+    return out
+
+
+def orb_order(pos_mass, leaf):
+    """int32 permutation, perm[p] = original index at position p."""
+    pm = _rec(pos_mass, "pos_mass")
+    p = F64 if pm.dtype == torch.float64 else F32
+    perm = torch.empty(pm.shape[0], dtype=torch.int32, device=pm.device)
+    _check(lib().nbody_orb_order(_ptr(pm), p, pm.shape[0], int(leaf), _ptr(perm), _stream()))
+    return perm
+
+
+def permute(src, perm, inverse=False, out=None):
+    s = _rec(src, "src")
+    if perm.dtype != torch.int32 or perm.device != s.device or not perm.is_contiguous() or \
+            perm.numel() != s.shape[0]:
+        raise ValueError("perm must be a contiguous int32 GPU tensor of N entries")
+    if out is None:
+        out = torch.empty_like(s)
+    _check(lib().nbody_permute(_ptr(s), _ptr(out), _ptr(perm), s.shape[0], s.element_size() * 4,
+                               1 if inverse else 0, _stream()))
+    return out
+
+
+def trajectory_forward(pos_mass, vel, eps, dt, nsteps, ckpt_every, G=1.0, prec=None):
+    """Runs the leapfrog in place and returns the checkpoint tensor
+    (nsteps/ckpt_every + 1, 2, N, 4)."""
+    pm = _rec(pos_mass, "pos_mass")
+    v = _rec(vel, "vel", pm.dtype)
+    p = _prec(pm, prec)
+    n = pm.shape[0]
+    ck = torch.empty((nsteps // ckpt_every + 1, 2, n, 4), dtype=pm.dtype, device=pm.device)
+    _check(lib().nbody_trajectory_forward(_ptr(pm), _ptr(v), n, p, float(G), float(eps), float(dt),
+                                          int(nsteps), int(ckpt_every), _ptr(ck), _stream()))
+    return ck
+
+
+def trajectory_adjoint(ckpt, eps, dt, nsteps, ckpt_every, xbar_T, vbar_T, G=1.0, prec=None):
+    """(pos_cot (N,4), vel_cot (N,4), mass_cot (N,)) = gradients at the
+    initial state for final-state cotangents (xbar_T, vbar_T)."""
+    xb = _rec(xbar_T, "xbar_T")
+    vb = _rec(vbar_T, "vbar_T", xb.dtype)
+    if ckpt.dtype != xb.dtype or not ckpt.is_contiguous() or ckpt.device != xb.device:
+        raise ValueError("ckpt must be a contiguous tensor of the same dtype and device")
+    p = _prec(xb, prec)
+    n = xb.shape[0]
+    pc = torch.empty_like(xb)
+    vc = torch.empty_like(xb)
+    mc = torch.empty(n, dtype=xb.dtype, device=xb.device)
+    _check(lib().nbody_trajectory_adjoint(_ptr(ckpt), n, p, float(G), float(eps), float(dt), int(nsteps),
+                                          int(ckpt_every), _ptr(xb), _ptr(vb), _ptr(pc), _ptr(vc),
+                                          _ptr(mc), _stream()))
+    return pc, vc, mc
+
+
+class NBodyTrajectory(torch.autograd.Function):
+    """x_T = leapfrog^nsteps(x0, v0; m), differentiable in (x0, v0, m).
+
+    forward: checkpointed trajectory (nbody_trajectory_forward); backward:
+    checkpointed adjoint (nbody_trajectory_adjoint).  x0, v0: (N, 3); m: (N,).
+    Returns (x_T (N, 3), v_T (N, 3))."""
+
+    @staticmethod
+    def forward(ctx, x0, v0, m, eps, dt, nsteps, ckpt_every=20, G=1.0, prec=None):
+        n = x0.shape[0]
+        pm = torch.empty((n, 4), dtype=x0.dtype, device=x0.device)
+        pm[:, :3] = x0.detach()
+        pm[:, 3] = m.detach()
+        vel = torch.zeros((n, 4), dtype=x0.dtype, device=x0.device)
+        vel[:, :3] = v0.detach()
+        ck = trajectory_forward(pm, vel, eps, dt, nsteps, ckpt_every, G, prec)
+        ctx.save_for_backward(ck)
+        ctx.args = (eps, dt, nsteps, ckpt_every, G, prec)
+        return pm[:, :3].clone(), vel[:, :3].clone()
+
+    @staticmethod
+    def backward(ctx, gx, gv):
+        (ck,) = ctx.saved_tensors
+        eps, dt, nsteps, ckpt_every, G, prec = ctx.args
+        n = ck.shape[2]
+        xb = torch.zeros((n, 4), dtype=ck.dtype, device=ck.device)
+        vb = torch.zeros((n, 4), dtype=ck.dtype, device=ck.device)
+        if gx is not None:
+            xb[:, :3] = gx
+        if gv is not None:
+            vb[:, :3] = gv
+        pc, vc, mc = trajectory_adjoint(ck, eps, dt, nsteps, ckpt_every, xb, vb, G, prec)
+        return pc[:, :3], vc[:, :3], mc, None, None, None, None, None, None
+
+
+def autotune(kernel, prec, n, offsets=None):
+    o, nsys, optr = _offsets(offsets)
+    _check(lib().nbody_autotune(int(kernel), int(prec), int(n), optr, nsys, _stream()))
+
+
+def set_tuning(kernel, prec, tpl=-1, jsplit=-1, jtile=-1):
+    _check(lib().nbody_set_tuning(int(kernel), int(prec), int(tpl), int(jsplit), int(jtile)))
+
+
+def get_tuning(kernel, prec, n):
+    a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().nbody_get_tuning(int(kernel), int(prec), int(n), ctypes.byref(a), ctypes.byref(b),
+                                  ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def release():
+    lib().nbody_release()

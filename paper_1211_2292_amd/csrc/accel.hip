@@ -1,0 +1,640 @@
+// Direct-sum force and potential kernels for gfx950.
+//
+// Computes, for each target i, the paper's force calculation (Section IV.B,
+// Calculate_forces) with every other body on the interaction list, i.e. the
+// exact softened pair sum
+//     a_i   =  G sum_{j != i} m_j d_ij (|d_ij|^2 + eps^2)^(-3/2),  d_ij = x_j - x_i
+//     phi_i = -G sum_{j != i} m_j (|d_ij|^2 + eps^2)^(-1/2)
+//
+// Design (CDNA4, wave64):
+// * A wave owns 64*TPL targets held in VGPRs.  Sources are streamed with
+//   wave-uniform addresses, so every source record arrives through a scalar
+//   load into SGPRs and feeds the VALU directly as the one scalar operand an
+//   instruction may take: no LDS staging, no barriers, and the 16-byte source
+//   record is fetched once per wave for 64*TPL interactions.
+// * Pair arithmetic (FP32 modes): 3 sub, 3 FMA, 1 v_rsq_f32, 3 mul, 1 add,
+//   3 FMA = 14 VALU instructions = 20 flop by the usual count.
+// * Sources are processed in tiles of `jtile`; the FP32 partial sum of a tile
+//   is folded into the running per-target sum by the precision mode (plain
+//   FP32, Kahan-compensated FP32, or FP64).  Pure FP32 mode keeps a single
+//   running FP32 sum.
+// * The self pair is removed exactly: only the sub-range of sources that
+//   overlaps the wave's own targets runs the masked variant (one compare and
+//   one select per pair); every other source range runs unmasked.
+// * Small problems split the source range over gridDim.y workgroup rows; the
+//   per-split records go to scratch and are reduced in split order by a
+//   second kernel, so the result never depends on scheduling.
+#include "internal.h"
+
+namespace nbi {
+namespace {
+
+enum { M_F32 = 1, M_KAHAN = 2, M_F64ACC = 3 };
+
+template <int MODE>
+struct Run;
+
+template <>
+struct Run<M_F32> {
+    float s;
+    __device__ void zero() { s = 0.0f; }
+    __device__ void fold(float p) { s += p; }
+    __device__ double get() const { return s; }
+};
+
+// Classic Kahan: y = p - c; t = s + y; c = (t - s) - y; s = t.  The reported
+// value applies the final compensation, s - c, formed in FP64.
+template <>
+struct Run<M_KAHAN> {
+    float s, c;
+    __device__ void zero() { s = 0.0f; c = 0.0f; }
+    __device__ void fold(float p)
+    {
+        const float y = p - c;
+        const float t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+    __device__ double get() const { return (double)s - (double)c; }
+};
+
+template <>
+struct Run<M_F64ACC> {
+    double s;
+    __device__ void zero() { s = 0.0; }
+    __device__ void fold(float p) { s += (double)p; }
+    __device__ double get() const { return s; }
+};
+
+template <typename T, int TPL>
+struct Targets {
+    T x[TPL], y[TPL], z[TPL];
+    int i[TPL];
+};
+
+template <typename T, int TPL>
+struct Sums {
+    T ax[TPL], ay[TPL], az[TPL], ph[TPL];
+    __device__ void zero()
+    {
+#pragma unroll
+        for (int t = 0; t < TPL; ++t) ax[t] = ay[t] = az[t] = ph[t] = T(0);
+    }
+};
+
+// ---- FP32 pair ---------------------------------------------------------------
+template <int TPL, bool MASK>
+__device__ __forceinline__ void pair_f32(const float4 b, const int j, const Targets<float, TPL> &T,
+                                         const float eps2, Sums<float, TPL> &S)
+{
+#pragma unroll
+    for (int t = 0; t < TPL; ++t) {
+        const float dx = b.x - T.x[t];
+        const float dy = b.y - T.y[t];
+        const float dz = b.z - T.z[t];
+        const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
+        float rho = __builtin_amdgcn_rsqf(r2);
+        if (MASK) rho = (j == T.i[t]) ? 0.0f : rho;
+        const float mr = b.w * rho;
+        const float s = mr * (rho * rho);
+        S.ph[t] += mr;
+        S.ax[t] = __builtin_fmaf(s, dx, S.ax[t]);
+        S.ay[t] = __builtin_fmaf(s, dy, S.ay[t]);
+        S.az[t] = __builtin_fmaf(s, dz, S.az[t]);
+    }
+}
+
+template <int TPL, bool MASK>
+__device__ __forceinline__ void sweep_f32(const float4 *__restrict__ src, int j0, int j1,
+                                          const Targets<float, TPL> &T, float eps2,
+                                          Sums<float, TPL> &S)
+{
+    int j = j0;
+    for (; j + kUnroll <= j1; j += kUnroll) {
+        float4 b[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) b[u] = src[j + u];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) pair_f32<TPL, MASK>(b[u], j + u, T, eps2, S);
+    }
+    for (; j < j1; ++j) pair_f32<TPL, MASK>(src[j], j, T, eps2, S);
+}
+
+// Sources [j0, j1) against the wave's targets [d0, d1): only the overlap runs
+// the masked variant.
+template <int TPL>
+__device__ __forceinline__ void range_f32(const float4 *__restrict__ src, int j0, int j1, int d0,
+                                          int d1, const Targets<float, TPL> &T, float eps2,
+                                          Sums<float, TPL> &S)
+{
+    const int lo = min(max(d0, j0), j1);
+    const int hi = min(max(d1, j0), j1);
+    sweep_f32<TPL, false>(src, j0, lo, T, eps2, S);
+    sweep_f32<TPL, true>(src, lo, hi, T, eps2, S);
+    sweep_f32<TPL, false>(src, hi, j1, T, eps2, S);
+}
+
+// Sums over sources [jb, je) of one system (records src[0..n)) for the wave
+// whose first target is t0; returns the unscaled sums per target and
+// component (ax, ay, az, sum m rho) through `res`.
+template <int TPL, int MODE>
+__device__ __forceinline__ void wave_f32(const float4 *__restrict__ src, int n, int t0, int jb,
+                                         int je, int jtile, float eps2, double (&res)[TPL][4])
+{
+    const int lane = threadIdx.x & 63;
+    Targets<float, TPL> T;
+#pragma unroll
+    for (int t = 0; t < TPL; ++t) {
+        const int i = t0 + t * 64 + lane;
+        T.i[t] = i;
+        const float4 p = src[min(i, n - 1)];
+        T.x[t] = p.x;
+        T.y[t] = p.y;
+        T.z[t] = p.z;
+    }
+    const int d0 = t0, d1 = t0 + 64 * TPL;
+    Sums<float, TPL> S;
+    S.zero();
+    if constexpr (MODE == M_F32) {
+        range_f32<TPL>(src, jb, je, d0, d1, T, eps2, S);
+#pragma unroll
+        for (int t = 0; t < TPL; ++t) {
+            res[t][0] = S.ax[t];
+            res[t][1] = S.ay[t];
+            res[t][2] = S.az[t];
+            res[t][3] = S.ph[t];
+        }
+    } else {
+        Run<MODE> R[TPL][4];
+#pragma unroll
+        for (int t = 0; t < TPL; ++t)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) R[t][c].zero();
+        for (int jc = jb; jc < je; jc += jtile) {
+            const int ce = min(jc + jtile, je);
+            S.zero();
+            range_f32<TPL>(src, jc, ce, d0, d1, T, eps2, S);
+#pragma unroll
+            for (int t = 0; t < TPL; ++t) {
+                R[t][0].fold(S.ax[t]);
+                R[t][1].fold(S.ay[t]);
+                R[t][2].fold(S.az[t]);
+                R[t][3].fold(S.ph[t]);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < TPL; ++t)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) res[t][c] = R[t][c].get();
+    }
+}
+
+// ---- FP64 pair ---------------------------------------------------------------
+// 1/sqrt(q) from the hardware estimate and two Newton-Raphson steps
+// y <- y + y (1 - q y^2) / 2.
+__device__ __forceinline__ double rsqrt_f64(double q)
+{
+    double y = __builtin_amdgcn_rsq(q);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const double e = __builtin_fma(-q, y * y, 1.0);
+        y = __builtin_fma(0.5 * y, e, y);
+    }
+    return y;
+}
+
+template <int TPL, bool MASK>
+__device__ __forceinline__ void pair_f64(const double4 b, const int j, const Targets<double, TPL> &T,
+                                         const double eps2, Sums<double, TPL> &S)
+{
+#pragma unroll
+    for (int t = 0; t < TPL; ++t) {
+        const double dx = b.x - T.x[t];
+        const double dy = b.y - T.y[t];
+        const double dz = b.z - T.z[t];
+        const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, __builtin_fma(dx, dx, eps2)));
+        double rho = rsqrt_f64(r2);
+        if (MASK) rho = (j == T.i[t]) ? 0.0 : rho;
+        const double mr = b.w * rho;
+        const double s = mr * (rho * rho);
+        S.ph[t] += mr;
+        S.ax[t] = __builtin_fma(s, dx, S.ax[t]);
+        S.ay[t] = __builtin_fma(s, dy, S.ay[t]);
+        S.az[t] = __builtin_fma(s, dz, S.az[t]);
+    }
+}
+
+template <int TPL, bool MASK>
+__device__ __forceinline__ void sweep_f64(const double4 *__restrict__ src, int j0, int j1,
+                                          const Targets<double, TPL> &T, double eps2,
+                                          Sums<double, TPL> &S)
+{
+    int j = j0;
+    for (; j + kUnroll <= j1; j += kUnroll) {
+        double4 b[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) b[u] = src[j + u];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) pair_f64<TPL, MASK>(b[u], j + u, T, eps2, S);
+    }
+    for (; j < j1; ++j) pair_f64<TPL, MASK>(src[j], j, T, eps2, S);
+}
+
+template <int TPL>
+__device__ __forceinline__ void wave_f64(const double4 *__restrict__ src, int n, int t0, int jb,
+                                         int je, int jtile, double eps2, double (&res)[TPL][4])
+{
+    const int lane = threadIdx.x & 63;
+    Targets<double, TPL> T;
+#pragma unroll
+    for (int t = 0; t < TPL; ++t) {
+        const int i = t0 + t * 64 + lane;
+        T.i[t] = i;
+        const double4 p = src[min(i, n - 1)];
+        T.x[t] = p.x;
+        T.y[t] = p.y;
+        T.z[t] = p.z;
+    }
+    const int d0 = t0, d1 = t0 + 64 * TPL;
+    double R[TPL][4];
+#pragma unroll
+    for (int t = 0; t < TPL; ++t)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) R[t][c] = 0.0;
+    Sums<double, TPL> S;
+    for (int jc = jb; jc < je; jc += jtile) {
+        const int ce = min(jc + jtile, je);
+        S.zero();
+        const int lo = min(max(d0, jc), ce);
+        const int hi = min(max(d1, jc), ce);
+        sweep_f64<TPL, false>(src, jc, lo, T, eps2, S);
+        sweep_f64<TPL, true>(src, lo, hi, T, eps2, S);
+        sweep_f64<TPL, false>(src, hi, ce, T, eps2, S);
+#pragma unroll
+        for (int t = 0; t < TPL; ++t) {
+            R[t][0] += S.ax[t];
+            R[t][1] += S.ay[t];
+            R[t][2] += S.az[t];
+            R[t][3] += S.ph[t];
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < TPL; ++t)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) res[t][c] = R[t][c];
+}
+
+// ---- output records ------------------------------------------------------------
+__device__ __forceinline__ void put(float4 *out, long k, const double (&r)[4], double G)
+{
+    out[k] = make_float4((float)(G * r[0]), (float)(G * r[1]), (float)(G * r[2]), (float)(-G * r[3]));
+}
+__device__ __forceinline__ void put(double4 *out, long k, const double (&r)[4], double G)
+{
+    out[k] = make_double4(G * r[0], G * r[1], G * r[2], -G * r[3]);
+}
+// Pure FP32 mode scales in FP32.
+__device__ __forceinline__ void put_f32(float4 *out, long k, const double (&r)[4], float G)
+{
+    out[k] = make_float4(G * (float)r[0], G * (float)r[1], G * (float)r[2], -G * (float)r[3]);
+}
+
+// ---- kernels -------------------------------------------------------------------
+// Source range of split `split` out of `js` over n sources.
+__device__ __forceinline__ void split_range(int n, int js, int split, int &jb, int &je)
+{
+    const long per = ((long)n + js - 1) / js;
+    jb = (int)min((long)n, (long)split * per);
+    je = (int)min((long)n, (long)jb + per);
+}
+
+template <int TPL, int MODE>
+__global__ __launch_bounds__(kBlock) void k_accel_f32(const float4 *__restrict__ src, int n,
+                                                      float eps2, double G, int tbeg, int tcount,
+                                                      int jtile, float4 *__restrict__ out,
+                                                      void *__restrict__ partial)
+{
+    constexpr int WT = 64 * TPL;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t0 = tbeg + (blockIdx.x * (kBlock / 64) + wave) * WT;
+    const int tend = tbeg + tcount;
+    if (t0 >= tend) return;
+    int jb, je;
+    split_range(n, gridDim.y, blockIdx.y, jb, je);
+    double res[TPL][4];
+    wave_f32<TPL, MODE>(src, n, t0, jb, je, jtile, eps2, res);
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int t = 0; t < TPL; ++t) {
+        const int i = t0 + t * 64 + lane;
+        if (i >= tend) continue;
+        const long k = i - tbeg;
+        if (gridDim.y == 1) {
+            if constexpr (MODE == M_F32)
+                put_f32(out, k, res[t], (float)G);
+            else
+                put(out, k, res[t], G);
+        } else if constexpr (MODE == M_F32) {
+            reinterpret_cast<float4 *>(partial)[(long)blockIdx.y * tcount + k] =
+                make_float4((float)res[t][0], (float)res[t][1], (float)res[t][2], (float)res[t][3]);
+        } else {
+            reinterpret_cast<double4 *>(partial)[(long)blockIdx.y * tcount + k] =
+                make_double4(res[t][0], res[t][1], res[t][2], res[t][3]);
+        }
+    }
+}
+
+template <int TPL>
+__global__ __launch_bounds__(kBlock) void k_accel_f64(const double4 *__restrict__ src, int n,
+                                                      double eps2, double G, int tbeg, int tcount,
+                                                      int jtile, double4 *__restrict__ out,
+                                                      double4 *__restrict__ partial)
+{
+    constexpr int WT = 64 * TPL;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t0 = tbeg + (blockIdx.x * (kBlock / 64) + wave) * WT;
+    const int tend = tbeg + tcount;
+    if (t0 >= tend) return;
+    int jb, je;
+    split_range(n, gridDim.y, blockIdx.y, jb, je);
+    double res[TPL][4];
+    wave_f64<TPL>(src, n, t0, jb, je, jtile, eps2, res);
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int t = 0; t < TPL; ++t) {
+        const int i = t0 + t * 64 + lane;
+        if (i >= tend) continue;
+        const long k = i - tbeg;
+        if (gridDim.y == 1)
+            put(out, k, res[t], G);
+        else
+            partial[(long)blockIdx.y * tcount + k] = make_double4(res[t][0], res[t][1], res[t][2], res[t][3]);
+    }
+}
+
+// Fixed-order reduction of the per-split records.
+template <typename OUT>
+__global__ __launch_bounds__(kBlock) void k_split_reduce(const double4 *__restrict__ partial,
+                                                         int js, int tcount, double G,
+                                                         OUT *__restrict__ out)
+{
+    const long k = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= tcount) return;
+    double r[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int s = 0; s < js; ++s) {
+        const double4 p = partial[(long)s * tcount + k];
+        r[0] += p.x;
+        r[1] += p.y;
+        r[2] += p.z;
+        r[3] += p.w;
+    }
+    put(out, k, r, G);
+}
+
+__global__ __launch_bounds__(kBlock) void k_split_reduce_f32(const float4 *__restrict__ partial,
+                                                             int js, int tcount, float G,
+                                                             float4 *__restrict__ out)
+{
+    const long k = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= tcount) return;
+    float r[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int s = 0; s < js; ++s) {
+        const float4 p = partial[(long)s * tcount + k];
+        r[0] += p.x;
+        r[1] += p.y;
+        r[2] += p.z;
+        r[3] += p.w;
+    }
+    out[k] = make_float4(G * r[0], G * r[1], G * r[2], -G * r[3]);
+}
+
+// ---- batched persistent kernel -------------------------------------------------
+// Each wave pops (system, first target) units from a longest-first list with
+// one integer atomic; a unit is one wave's worth of targets of one system
+// swept over that system's sources with the same tiles as k_accel_f32 with
+// one split, so each system's result equals its standalone evaluation
+// bit for bit.  The wave that finishes last returns both counters to zero,
+// which keeps repeated launches and graph replays self-contained.
+template <int TPL, int MODE>
+__global__ __launch_bounds__(kBlock) void k_batched_f32(const float4 *__restrict__ pm,
+                                                        const int64_t *__restrict__ offsets,
+                                                        const int2 *__restrict__ units, int nunits,
+                                                        const float *__restrict__ eps_sys,
+                                                        float eps2_all, double G, int jtile,
+                                                        float4 *__restrict__ out,
+                                                        unsigned *__restrict__ counter)
+{
+    constexpr int WT = 64 * TPL;
+    const int lane = threadIdx.x & 63;
+    const unsigned nwaves = gridDim.x * (kBlock / 64);
+    for (;;) {
+        unsigned u = 0;
+        if (lane == 0) u = atomicAdd(&counter[0], 1u);
+        u = __builtin_amdgcn_readfirstlane(u);
+        if (u >= (unsigned)nunits) break;
+        const int2 w = units[u];
+        const int64_t base = offsets[w.x];
+        const int n = (int)(offsets[w.x + 1] - base);
+        const float4 *src = pm + base;
+        float eps2 = eps2_all;
+        if (eps_sys) {
+            const double e = eps_sys[w.x];
+            eps2 = (float)(e * e);
+        }
+        double res[TPL][4];
+        wave_f32<TPL, MODE>(src, n, w.y, 0, n, jtile, eps2, res);
+#pragma unroll
+        for (int t = 0; t < TPL; ++t) {
+            const int i = w.y + t * 64 + lane;
+            if (i >= n) continue;
+            if constexpr (MODE == M_F32)
+                put_f32(out + base, i, res[t], (float)G);
+            else
+                put(out + base, i, res[t], G);
+        }
+    }
+    (void)WT;
+    if (lane == 0) {
+        const unsigned done = atomicAdd(&counter[1], 1u);
+        if (done == nwaves - 1) {
+            atomicExch(&counter[0], 0u);
+            atomicExch(&counter[1], 0u);
+        }
+    }
+}
+
+template <int TPL>
+__global__ __launch_bounds__(kBlock) void k_batched_f64(const double4 *__restrict__ pm,
+                                                        const int64_t *__restrict__ offsets,
+                                                        const int2 *__restrict__ units, int nunits,
+                                                        const float *__restrict__ eps_sys,
+                                                        double eps2_all, double G, int jtile,
+                                                        double4 *__restrict__ out,
+                                                        unsigned *__restrict__ counter)
+{
+    const int lane = threadIdx.x & 63;
+    const unsigned nwaves = gridDim.x * (kBlock / 64);
+    for (;;) {
+        unsigned u = 0;
+        if (lane == 0) u = atomicAdd(&counter[0], 1u);
+        u = __builtin_amdgcn_readfirstlane(u);
+        if (u >= (unsigned)nunits) break;
+        const int2 w = units[u];
+        const int64_t base = offsets[w.x];
+        const int n = (int)(offsets[w.x + 1] - base);
+        double eps2 = eps2_all;
+        if (eps_sys) {
+            const double e = eps_sys[w.x];
+            eps2 = e * e;
+        }
+        double res[TPL][4];
+        wave_f64<TPL>(pm + base, n, w.y, 0, n, jtile, eps2, res);
+#pragma unroll
+        for (int t = 0; t < TPL; ++t) {
+            const int i = w.y + t * 64 + lane;
+            if (i < n) put(out + base, i, res[t], G);
+        }
+    }
+    if (lane == 0) {
+        const unsigned done = atomicAdd(&counter[1], 1u);
+        if (done == nwaves - 1) {
+            atomicExch(&counter[0], 0u);
+            atomicExch(&counter[1], 0u);
+        }
+    }
+}
+
+template <int TPL, int MODE>
+hipError_t go_f32(const float4 *pm, int n, float eps2, double G, float4 *out, int tbeg, int tcount,
+                  const Tune &t, void *partial, hipStream_t s)
+{
+    const int per_block = (kBlock / 64) * 64 * TPL;
+    dim3 grid((tcount + per_block - 1) / per_block, t.jsplit);
+    hipLaunchKernelGGL((k_accel_f32<TPL, MODE>), grid, dim3(kBlock), 0, s, pm, n, eps2, G, tbeg,
+                       tcount, t.jtile, out, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || t.jsplit == 1) return e;
+    const int rb = (tcount + kBlock - 1) / kBlock;
+    if constexpr (MODE == M_F32)
+        hipLaunchKernelGGL(k_split_reduce_f32, dim3(rb), dim3(kBlock), 0, s,
+                           (const float4 *)partial, t.jsplit, tcount, (float)G, out);
+    else
+        hipLaunchKernelGGL(k_split_reduce<float4>, dim3(rb), dim3(kBlock), 0, s,
+                           (const double4 *)partial, t.jsplit, tcount, G, out);
+    return hipGetLastError();
+}
+
+template <int TPL>
+hipError_t go_f64(const double4 *pm, int n, double eps2, double G, double4 *out, int tbeg,
+                  int tcount, const Tune &t, void *partial, hipStream_t s)
+{
+    const int per_block = (kBlock / 64) * 64 * TPL;
+    dim3 grid((tcount + per_block - 1) / per_block, t.jsplit);
+    hipLaunchKernelGGL((k_accel_f64<TPL>), grid, dim3(kBlock), 0, s, pm, n, eps2, G, tbeg, tcount,
+                       t.jtile, out, (double4 *)partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || t.jsplit == 1) return e;
+    const int rb = (tcount + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_split_reduce<double4>, dim3(rb), dim3(kBlock), 0, s,
+                       (const double4 *)partial, t.jsplit, tcount, G, out);
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t by_tpl_f32(const float4 *pm, int n, float eps2, double G, float4 *out, int tbeg,
+                      int tcount, const Tune &t, void *partial, hipStream_t s)
+{
+    switch (t.tpl) {
+    case 1: return go_f32<1, MODE>(pm, n, eps2, G, out, tbeg, tcount, t, partial, s);
+    case 2: return go_f32<2, MODE>(pm, n, eps2, G, out, tbeg, tcount, t, partial, s);
+    default: return go_f32<4, MODE>(pm, n, eps2, G, out, tbeg, tcount, t, partial, s);
+    }
+}
+
+template <int TPL, int MODE>
+hipError_t go_batched_f32(const float4 *pm, const int64_t *off, const int2 *units, int nunits,
+                          const float *eps_sys, float eps2, double G, float4 *out, const Tune &t,
+                          unsigned *counter, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_batched_f32<TPL, MODE>), dim3(grid), dim3(kBlock), 0, s, pm, off, units,
+                       nunits, eps_sys, eps2, G, t.jtile, out, counter);
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t batched_by_tpl(const float4 *pm, const int64_t *off, const int2 *units, int nunits,
+                          const float *eps_sys, float eps2, double G, float4 *out, const Tune &t,
+                          unsigned *counter, int grid, hipStream_t s)
+{
+    switch (t.tpl) {
+    case 1: return go_batched_f32<1, MODE>(pm, off, units, nunits, eps_sys, eps2, G, out, t, counter, grid, s);
+    case 2: return go_batched_f32<2, MODE>(pm, off, units, nunits, eps_sys, eps2, G, out, t, counter, grid, s);
+    default: return go_batched_f32<4, MODE>(pm, off, units, nunits, eps_sys, eps2, G, out, t, counter, grid, s);
+    }
+}
+
+}  // namespace
+
+bool tune_valid(const Tune &t)
+{
+    return (t.tpl == 1 || t.tpl == 2 || t.tpl == 4) && t.jsplit >= 1 && t.jsplit <= 32 &&
+           t.jtile >= 8 && t.jtile % kUnroll == 0 && t.jtile <= (1 << 24);
+}
+
+size_t accel_partial_bytes(int prec, int tcount, const Tune &t)
+{
+    if (t.jsplit <= 1) return 0;
+    const size_t rec = (prec == NBODY_F32) ? sizeof(float4) : sizeof(double4);
+    return rec * (size_t)t.jsplit * (size_t)tcount;
+}
+
+static float eps2_f32(double eps) { return (float)((double)eps * (double)eps); }
+
+hipError_t launch_accel(int prec, const void *pm, int n, double G, double eps, void *out, int tbeg,
+                        int tcount, const Tune &t, void *partial, hipStream_t s)
+{
+    if (prec == NBODY_F64) {
+        const double4 *p = (const double4 *)pm;
+        double4 *o = (double4 *)out;
+        const double e2 = eps * eps;
+        switch (t.tpl) {
+        case 1: return go_f64<1>(p, n, e2, G, o, tbeg, tcount, t, partial, s);
+        default: return go_f64<2>(p, n, e2, G, o, tbeg, tcount, t, partial, s);
+        }
+    }
+    const float4 *p = (const float4 *)pm;
+    float4 *o = (float4 *)out;
+    const float e2 = eps2_f32(eps);
+    switch (prec) {
+    case NBODY_F32: return by_tpl_f32<M_F32>(p, n, e2, G, o, tbeg, tcount, t, partial, s);
+    case NBODY_F32_KAHAN: return by_tpl_f32<M_KAHAN>(p, n, e2, G, o, tbeg, tcount, t, partial, s);
+    default: return by_tpl_f32<M_F64ACC>(p, n, e2, G, o, tbeg, tcount, t, partial, s);
+    }
+}
+
+hipError_t launch_batched(int prec, const void *pm, const int64_t *offsets, const int2 *units,
+                          int nunits, double G, const float *eps_sys, double eps, void *out,
+                          const Tune &t, unsigned *counter, int grid, hipStream_t s)
+{
+    if (prec == NBODY_F64) {
+        const double4 *p = (const double4 *)pm;
+        double4 *o = (double4 *)out;
+        if (t.tpl == 1)
+            hipLaunchKernelGGL((k_batched_f64<1>), dim3(grid), dim3(kBlock), 0, s, p, offsets, units,
+                               nunits, eps_sys, eps * eps, G, t.jtile, o, counter);
+        else
+            hipLaunchKernelGGL((k_batched_f64<2>), dim3(grid), dim3(kBlock), 0, s, p, offsets, units,
+                               nunits, eps_sys, eps * eps, G, t.jtile, o, counter);
+        return hipGetLastError();
+    }
+    const float4 *p = (const float4 *)pm;
+    float4 *o = (float4 *)out;
+    const float e2 = eps2_f32(eps);
+    switch (prec) {
+    case NBODY_F32: return batched_by_tpl<M_F32>(p, offsets, units, nunits, eps_sys, e2, G, o, t, counter, grid, s);
+    case NBODY_F32_KAHAN: return batched_by_tpl<M_KAHAN>(p, offsets, units, nunits, eps_sys, e2, G, o, t, counter, grid, s);
+    default: return batched_by_tpl<M_F64ACC>(p, offsets, units, nunits, eps_sys, e2, G, o, t, counter, grid, s);
+    }
+}
+
+}  // namespace nbi

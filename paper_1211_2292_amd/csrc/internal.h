@@ -1,0 +1,85 @@
+// Internal declarations of the gfx950 n-body library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "nbody.h"
+
+namespace nbi {
+
+// Kernel shape of the force sweep.
+//   tpl    targets held per lane (1, 2 or 4): a wave owns 64*tpl targets
+//   jsplit number of independent source ranges per target (1..32); each
+//          range is a separate workgroup row, reduced in fixed order after
+//   jtile  sources per partial sum (multiple of 8); the partials are folded
+//          into the running sum by the precision mode
+struct Tune {
+    int tpl = 2;
+    int jsplit = 1;
+    int jtile = 512;
+};
+
+constexpr int kBlock = 256;  // threads per workgroup: four independent waves
+constexpr int kUnroll = 8;   // sources per unrolled step of the sweep
+
+bool tune_valid(const Tune &t);
+
+// ---- force (accel.hip) -----------------------------------------------------
+// pm: float4/double4 records; out: target_count records; partial: scratch of
+// jsplit * target_count double4 (F32 mode: float4) records when jsplit > 1.
+hipError_t launch_accel(int prec, const void *pm, int n, double G, double eps, void *out,
+                        int tbeg, int tcount, const Tune &t, void *partial, hipStream_t s);
+size_t accel_partial_bytes(int prec, int tcount, const Tune &t);
+
+// Batched force over a work list of (system, first target) units sorted
+// longest first.  units: int2[nunits] = (system, target offset within the
+// system); offsets: int64 device copy [nsys+1]; counter: one zeroed uint32
+// pair, left zeroed again by the kernel on exit.
+hipError_t launch_batched(int prec, const void *pm, const int64_t *offsets, const int2 *units,
+                          int nunits, double G, const float *eps_sys, double eps, void *out,
+                          const Tune &t, unsigned *counter, int grid, hipStream_t s);
+
+// ---- fused force + VJP (vjp.hip) -------------------------------------------
+hipError_t launch_vjp(int prec, const void *pm, const void *cot, int n, double G, double eps,
+                      void *pos_cot, void *mass_cot, void *acc_out, const Tune &t,
+                      hipStream_t s);
+// scale multiplies the cotangent; accumulate adds into pos_cot/mass_cot;
+// phi = false ignores the phibar component of the cotangent records.
+hipError_t launch_vjp_ex(int prec, const void *pm, const void *cot, int n, double G, double eps,
+                         bool phi, double scale, bool accumulate, void *pos_cot, void *mass_cot,
+                         void *acc_out, const Tune &t, hipStream_t s);
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+
+// ---- elementwise steps (step.hip) ------------------------------------------
+// One pass between two force evaluations:
+//   close: v += h a          (closing kick of the previous step)
+//   energy partials of (v, phi) after the closing kick, if epart != nullptr
+//   open:  v += h a; x += dt v  (opening kick and drift of the next step)
+hipError_t launch_step(int prec, void *pm, void *vel, const void *acc, int n, double h, double dt,
+                       bool close, bool open, double *epart, int *eblocks, hipStream_t s);
+int step_blocks(int n);
+hipError_t launch_energy_final(const double *epart, int nblocks, double *out, hipStream_t s);
+hipError_t launch_permute(const void *src, void *dst, const int32_t *perm, int n, int rec_bytes,
+                          bool inverse, hipStream_t s);
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
+
+// Adjoint of one leapfrog step pair, elementwise (vjp.hip).
+hipError_t launch_adj_axpy(int prec, void *y, const void *x, double a, int n, hipStream_t s);
+
+// ---- ORB (orb.hip) -----------------------------------------------------------
+int orb_order(const void *pm, int prec, int n, int leaf, int32_t *perm, hipStream_t s);
+void orb_release();
+
+// ---- runtime helpers (runtime.hip) -----------------------------------------
+void set_error(const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+// Library scratch, one growable buffer per slot and device.
+enum ScratchSlot { kSlotPartial = 0, kSlotEnergy, kSlotBatch, kSlotOrb0, kSlotOrb1, kSlotOrb2,
+                   kSlotOrb3, kSlotOrb4, kSlotAdj0, kSlotAdj1, kSlotAdj2, kSlotAdj3, kSlotTune,
+                   kNumSlots };
+void *scratch(int slot, size_t bytes);
+
+}  // namespace nbi

@@ -1,0 +1,1045 @@
+// Host runtime and C ABI of the gfx950 n-body library: argument validation,
+// library scratch, kernel-shape tuning, the leapfrog driver with optional
+// HIP-graph capture, the ragged batch planner and the checkpointed trajectory
+// adjoint.  The kernels live in accel.hip, vjp.hip, step.hip and orb.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "internal.h"
+
+namespace nbi {
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return NBODY_E_HIP;
+}
+
+#define NB_TRY(expr, what)                                  \
+    do {                                                    \
+        hipError_t e_ = (expr);                             \
+        if (e_ != hipSuccess) return hip_fail(e_, (what));  \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Library scratch: one growable device buffer per slot and device.
+// ---------------------------------------------------------------------------
+static std::mutex g_mu;
+
+struct DevScratch {
+    void *ptr[kNumSlots] = {};
+    size_t size[kNumSlots] = {};
+};
+static std::map<int, DevScratch> g_scratch;
+
+void *scratch(int slot, size_t bytes)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevScratch &d = g_scratch[dev];
+    if (d.size[slot] >= bytes && d.ptr[slot]) return d.ptr[slot];
+    if (d.ptr[slot]) {
+        // Work already enqueued may still use the old buffer.
+        (void)hipDeviceSynchronize();
+        (void)hipFree(d.ptr[slot]);
+        d.ptr[slot] = nullptr;
+        d.size[slot] = 0;
+    }
+    size_t want = std::max<size_t>(bytes, 256);
+    want = (want + 4095) & ~size_t(4095);
+    void *p = nullptr;
+    if (hipMalloc(&p, want) != hipSuccess) return nullptr;
+    d.ptr[slot] = p;
+    d.size[slot] = want;
+    return p;
+}
+
+// ---------------------------------------------------------------------------
+// Validation helpers
+// ---------------------------------------------------------------------------
+static bool prec_ok(int prec) { return prec >= NBODY_F64 && prec <= NBODY_F32_F64ACC; }
+static size_t rec_bytes(int prec) { return prec == NBODY_F64 ? 32 : 16; }
+
+static int check_n(int64_t n)
+{
+    // Kernels index targets with 32-bit integers and may run up to one wave
+    // (256 targets) past the end before masking.
+    if (n < 1 || n > (int64_t(1) << 31) - 4096) {
+        set_error("n = %lld out of range [1, 2^31 - 4096]", (long long)n);
+        return NBODY_E_INVAL;
+    }
+    return NBODY_OK;
+}
+
+static int check_vec(const void *p, int prec, const char *name, bool nullable = false)
+{
+    if (!p) {
+        if (nullable) return NBODY_OK;
+        set_error("%s is NULL", name);
+        return NBODY_E_INVAL;
+    }
+    if ((uintptr_t)p % rec_bytes(prec)) {
+        set_error("%s is not %zu-byte aligned", name, rec_bytes(prec));
+        return NBODY_E_ALIGN;
+    }
+    return NBODY_OK;
+}
+
+static bool overlap(const void *a, size_t na, const void *b, size_t nb)
+{
+    const char *x = (const char *)a, *y = (const char *)b;
+    return a && b && x < y + nb && y < x + na;
+}
+
+#define NB_CHECK(expr)                 \
+    do {                               \
+        int rc_ = (expr);              \
+        if (rc_ != NBODY_OK) return rc_; \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Tuning table
+// ---------------------------------------------------------------------------
+// key: (kernel, prec, ceil(log2 n))
+using TuneKey = std::tuple<int, int, int>;
+static std::map<TuneKey, Tune> g_tuned;      // measured by nbody_autotune
+static std::map<std::pair<int, int>, Tune> g_pinned;  // nbody_set_tuning
+static bool g_cache_loaded = false;
+
+static int log2ceil(int64_t n)
+{
+    int b = 0;
+    while ((int64_t(1) << b) < n) ++b;
+    return b;
+}
+
+static void load_cache_locked()
+{
+    if (g_cache_loaded) return;
+    g_cache_loaded = true;
+    const char *path = getenv("NBODY_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    // One entry per line: "k,p,b": [tpl, jsplit, jtile]
+    char line[256];
+    while (fgets(line, sizeof line, f)) {
+        int k, p, b, t, j, jt;
+        if (sscanf(line, " \"%d,%d,%d\" : [ %d , %d , %d ]", &k, &p, &b, &t, &j, &jt) == 6) {
+            Tune tu;
+            tu.tpl = t;
+            tu.jsplit = j;
+            tu.jtile = jt;
+            if (tune_valid(tu)) g_tuned[TuneKey(k, p, b)] = tu;
+        }
+    }
+    fclose(f);
+}
+
+static void save_cache_locked()
+{
+    const char *path = getenv("NBODY_TUNE_CACHE");
+    if (!path) return;
+    std::string tmp = std::string(path) + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return;
+    fprintf(f, "{\n");
+    size_t i = 0;
+    for (auto &kv : g_tuned) {
+        fprintf(f, "  \"%d,%d,%d\": [%d, %d, %d]%s\n", std::get<0>(kv.first), std::get<1>(kv.first),
+                std::get<2>(kv.first), kv.second.tpl, kv.second.jsplit, kv.second.jtile,
+                ++i < g_tuned.size() ? "," : "");
+    }
+    fprintf(f, "}\n");
+    fclose(f);
+    rename(tmp.c_str(), path);
+}
+
+// Heuristic shape: enough waves to cover 1024 SIMDs about four deep; the
+// source range is split only when the targets alone cannot do it.
+static Tune default_tune(int kernel, int prec, int64_t n)
+{
+    Tune t;
+    t.jtile = 512;
+    if (kernel == 2) {  // VJP: heavier pair, more registers
+        t.tpl = 1;
+        t.jsplit = 1;
+        return t;
+    }
+    t.tpl = (prec == NBODY_F64) ? 1 : (n >= (1 << 17) ? 2 : 1);
+    if (kernel == 1) {
+        t.jsplit = 1;
+        return t;
+    }
+    const int64_t waves = (n + 64 * t.tpl - 1) / (64 * t.tpl);
+    int js = 1;
+    while (js < 32 && waves * js < 4096 && n / (js * 2) >= 512) js *= 2;
+    t.jsplit = js;
+    return t;
+}
+
+static Tune lookup_tune(int kernel, int prec, int64_t n)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_cache_locked();
+    auto p = g_pinned.find({kernel, prec});
+    if (p != g_pinned.end()) return p->second;
+    auto it = g_tuned.find(TuneKey(kernel, prec, log2ceil(n)));
+    if (it != g_tuned.end()) return it->second;
+    return default_tune(kernel, prec, n);
+}
+
+// ---------------------------------------------------------------------------
+// Force dispatch shared by the entry points
+// ---------------------------------------------------------------------------
+static int force(int prec, const void *pm, int n, double G, double eps, void *out, int tbeg,
+                 int tcount, hipStream_t s, void *partial_override = nullptr)
+{
+    Tune t = lookup_tune(0, prec, n);
+    void *partial = nullptr;
+    const size_t pb = accel_partial_bytes(prec, tcount, t);
+    if (pb) {
+        partial = partial_override ? partial_override : scratch(kSlotPartial, pb);
+        if (!partial) {
+            set_error("cannot allocate %zu bytes of split scratch", pb);
+            return NBODY_E_NOMEM;
+        }
+    }
+    NB_TRY(launch_accel(prec, pm, n, G, eps, out, tbeg, tcount, t, partial, s), "force kernel");
+    return NBODY_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batch plans: device offsets and a longest-first work list, cached per
+// offsets content.
+// ---------------------------------------------------------------------------
+struct BatchPlan {
+    int nsys = 0;
+    int64_t total = 0;
+    int nunits = 0;
+    int tpl = 0;
+    int64_t *d_off = nullptr;
+    int2 *d_units = nullptr;
+    unsigned *d_counter = nullptr;
+    int grid = 0;
+};
+
+static std::map<std::vector<int64_t>, BatchPlan> g_plans;
+
+static int validate_offsets(const int64_t *off, int32_t nsys, int64_t n)
+{
+    if (!off || nsys < 1) {
+        set_error("batch needs offsets_host and nsys >= 1");
+        return NBODY_E_INVAL;
+    }
+    if (off[0] != 0 || off[nsys] != n) {
+        set_error("offsets must start at 0 and end at n (%lld)", (long long)n);
+        return NBODY_E_INVAL;
+    }
+    for (int s = 0; s < nsys; ++s)
+        if (off[s + 1] < off[s]) {
+            set_error("offsets decrease at system %d", s);
+            return NBODY_E_INVAL;
+        }
+    return NBODY_OK;
+}
+
+static int get_plan(const int64_t *off, int32_t nsys, const Tune &t, BatchPlan **out)
+{
+    std::vector<int64_t> key(off, off + nsys + 1);
+    key.push_back(t.tpl);
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    key.push_back(dev);
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_plans.find(key);
+    if (it != g_plans.end()) {
+        *out = &it->second;
+        return NBODY_OK;
+    }
+    // (system, first target) units of one wave each, longest system first:
+    // the cost of a unit is proportional to its system's body count.
+    const int wt = 64 * t.tpl;
+    std::vector<int> order(nsys);
+    for (int s = 0; s < nsys; ++s) order[s] = s;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return (off[a + 1] - off[a]) > (off[b + 1] - off[b]);
+    });
+    std::vector<int2> units;
+    for (int s : order) {
+        const int64_t ns = off[s + 1] - off[s];
+        for (int64_t t0 = 0; t0 < ns; t0 += wt) units.push_back(make_int2(s, (int)t0));
+    }
+    BatchPlan p;
+    p.nsys = nsys;
+    p.total = off[nsys];
+    p.nunits = (int)units.size();
+    p.tpl = t.tpl;
+    if (hipMalloc(&p.d_off, sizeof(int64_t) * (nsys + 1)) != hipSuccess ||
+        hipMalloc(&p.d_units, sizeof(int2) * std::max<size_t>(1, units.size())) != hipSuccess ||
+        hipMalloc(&p.d_counter, 2 * sizeof(unsigned)) != hipSuccess) {
+        set_error("cannot allocate batch plan");
+        return NBODY_E_NOMEM;
+    }
+    NB_TRY(hipMemcpy(p.d_off, off, sizeof(int64_t) * (nsys + 1), hipMemcpyHostToDevice), "plan upload");
+    if (!units.empty())
+        NB_TRY(hipMemcpy(p.d_units, units.data(), sizeof(int2) * units.size(), hipMemcpyHostToDevice),
+               "plan upload");
+    NB_TRY(hipMemset(p.d_counter, 0, 2 * sizeof(unsigned)), "plan counter");
+    int cus = 256;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+    // Persistent grid: four workgroups (16 waves) per CU, never more waves
+    // than units.
+    p.grid = std::max(1, std::min(cus * 4, (p.nunits + 3) / 4));
+    auto ins = g_plans.emplace(key, p);
+    *out = &ins.first->second;
+    return NBODY_OK;
+}
+
+static int batched_force(int prec, const void *pm, const BatchPlan &p, double G, const float *eps_sys,
+                         double eps, void *out, const Tune &t, hipStream_t s)
+{
+    NB_TRY(launch_batched(prec, pm, p.d_off, p.d_units, p.nunits, G, eps_sys, eps, out, t, p.d_counter,
+                          p.grid, s),
+           "batched force kernel");
+    return NBODY_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Leapfrog driver
+// ---------------------------------------------------------------------------
+struct StepBuffers {
+    double *epart = nullptr;  // energy block partials
+    void *partial = nullptr;  // split scratch of the force kernel
+};
+
+static int leapfrog_enqueue(void *pm, void *vel, void *acc, int n, const BatchPlan *plan, int prec,
+                            double G, double eps, double dt, int nsteps, uint32_t flags,
+                            double *energy, const StepBuffers &buf, hipStream_t s)
+{
+    const double h = 0.5 * dt;
+    Tune bt = lookup_tune(1, prec, n);
+    auto eval = [&]() -> int {
+        if (plan) return batched_force(prec, pm, *plan, G, nullptr, eps, acc, bt, s);
+        return force(prec, pm, n, G, eps, acc, 0, n, s, buf.partial);
+    };
+    if (!(flags & NBODY_ACC_VALID)) NB_CHECK(eval());
+    double *ep = energy ? buf.epart : nullptr;
+    int eb = 0;
+    if (nsteps == 0) {
+        if (energy) {
+            NB_TRY(launch_step(prec, pm, vel, acc, n, h, dt, false, false, ep, &eb, s), "step kernel");
+            NB_TRY(launch_energy_final(ep, eb, energy, s), "energy kernel");
+        }
+        return NBODY_OK;
+    }
+    NB_TRY(launch_step(prec, pm, vel, acc, n, h, dt, false, true, ep, &eb, s), "step kernel");
+    if (energy) NB_TRY(launch_energy_final(ep, eb, energy, s), "energy kernel");
+    for (int k = 0; k < nsteps; ++k) {
+        NB_CHECK(eval());
+        const bool last = (k == nsteps - 1);
+        NB_TRY(launch_step(prec, pm, vel, acc, n, h, dt, true, !last, ep, &eb, s), "step kernel");
+        if (energy) NB_TRY(launch_energy_final(ep, eb, energy + 2 * (k + 1), s), "energy kernel");
+    }
+    return NBODY_OK;
+}
+
+// Graph cache
+struct GraphKey {
+    std::vector<uint64_t> v;
+    bool operator<(const GraphKey &o) const { return v < o.v; }
+};
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    double *epart = nullptr;
+    void *partial = nullptr;
+};
+static std::map<GraphKey, GraphEntry> g_graphs;
+static std::map<int, hipStream_t> g_capture_stream;
+
+static uint64_t dbits(double d)
+{
+    uint64_t u;
+    memcpy(&u, &d, 8);
+    return u;
+}
+
+}  // namespace nbi
+
+using namespace nbi;
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int nbody_version(void) { return 100; }
+
+const char *nbody_status_string(int status)
+{
+    switch (status) {
+    case NBODY_OK: return "ok";
+    case NBODY_E_INVAL: return "invalid argument";
+    case NBODY_E_ALIGN: return "misaligned buffer";
+    case NBODY_E_NOMEM: return "out of memory";
+    case NBODY_E_HIP: return "HIP error";
+    case NBODY_E_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+    }
+}
+
+const char *nbody_last_error(void) { return g_err; }
+
+static int check_scalars(double G, double eps, double dt = 0.0)
+{
+    if (!std::isfinite(G) || !std::isfinite(eps) || !std::isfinite(dt) || eps < 0.0) {
+        set_error("G, eps and dt must be finite and eps >= 0");
+        return NBODY_E_INVAL;
+    }
+    return NBODY_OK;
+}
+
+int nbody_accel(const void *pos_mass, int64_t n, int32_t prec, double G, double eps,
+                void *acc_pot_out, int64_t target_begin, int64_t target_count, void *stream)
+{
+    NB_CHECK(check_n(n));
+    if (!prec_ok(prec)) {
+        set_error("bad precision %d", prec);
+        return NBODY_E_INVAL;
+    }
+    NB_CHECK(check_scalars(G, eps));
+    NB_CHECK(check_vec(pos_mass, prec, "pos_mass"));
+    NB_CHECK(check_vec(acc_pot_out, prec, "acc_pot_out"));
+    if (target_begin < 0 || target_count < 0 || target_begin + target_count > n) {
+        set_error("targets [%lld, %lld) outside [0, %lld)", (long long)target_begin,
+                  (long long)(target_begin + target_count), (long long)n);
+        return NBODY_E_INVAL;
+    }
+    const size_t rb = rec_bytes(prec);
+    if (overlap(pos_mass, rb * n, acc_pot_out, rb * target_count)) {
+        set_error("acc_pot_out overlaps pos_mass");
+        return NBODY_E_INVAL;
+    }
+    if (target_count == 0) return NBODY_OK;
+    return force(prec, pos_mass, (int)n, G, eps, acc_pot_out, (int)target_begin, (int)target_count,
+                 (hipStream_t)stream);
+}
+
+int nbody_batched_accel(const void *pos_mass, const int64_t *offsets_host, int32_t nsys,
+                        int32_t prec, double G, const float *eps_per_sys, double eps,
+                        void *acc_pot_out, void *stream)
+{
+    if (!prec_ok(prec)) {
+        set_error("bad precision %d", prec);
+        return NBODY_E_INVAL;
+    }
+    if (!offsets_host || nsys < 1) {
+        set_error("batch needs offsets_host and nsys >= 1");
+        return NBODY_E_INVAL;
+    }
+    const int64_t n = offsets_host[nsys];
+    NB_CHECK(check_n(n));
+    NB_CHECK(validate_offsets(offsets_host, nsys, n));
+    NB_CHECK(check_scalars(G, eps));
+    NB_CHECK(check_vec(pos_mass, prec, "pos_mass"));
+    NB_CHECK(check_vec(acc_pot_out, prec, "acc_pot_out"));
+    if (eps_per_sys && ((uintptr_t)eps_per_sys % 4)) {
+        set_error("eps_per_sys misaligned");
+        return NBODY_E_ALIGN;
+    }
+    const size_t rb = rec_bytes(prec);
+    if (overlap(pos_mass, rb * n, acc_pot_out, rb * n)) {
+        set_error("acc_pot_out overlaps pos_mass");
+        return NBODY_E_INVAL;
+    }
+    Tune t = lookup_tune(1, prec, n);
+    BatchPlan *plan = nullptr;
+    NB_CHECK(get_plan(offsets_host, nsys, t, &plan));
+    return batched_force(prec, pos_mass, *plan, G, eps_per_sys, eps, acc_pot_out, t,
+                         (hipStream_t)stream);
+}
+
+int nbody_accel_vjp(const void *pos_mass, const void *acc_pot_cot, int64_t n, int32_t prec,
+                    double G, double eps, void *pos_cot_out, void *mass_cot_out, void *acc_pot_out,
+                    void *stream)
+{
+    NB_CHECK(check_n(n));
+    if (!prec_ok(prec)) {
+        set_error("bad precision %d", prec);
+        return NBODY_E_INVAL;
+    }
+    NB_CHECK(check_scalars(G, eps));
+    NB_CHECK(check_vec(pos_mass, prec, "pos_mass"));
+    NB_CHECK(check_vec(acc_pot_cot, prec, "acc_pot_cot"));
+    NB_CHECK(check_vec(pos_cot_out, prec, "pos_cot_out"));
+    NB_CHECK(check_vec(acc_pot_out, prec, "acc_pot_out", true));
+    if (!mass_cot_out || (uintptr_t)mass_cot_out % (prec == NBODY_F64 ? 8 : 4)) {
+        set_error("mass_cot_out NULL or misaligned");
+        return mass_cot_out ? NBODY_E_ALIGN : NBODY_E_INVAL;
+    }
+    const size_t rb = rec_bytes(prec), mb = (prec == NBODY_F64 ? 8 : 4);
+    const void *ins[2] = {pos_mass, acc_pot_cot};
+    for (const void *in : ins) {
+        if (overlap(in, rb * n, pos_cot_out, rb * n) || overlap(in, rb * n, mass_cot_out, mb * n) ||
+            overlap(in, rb * n, acc_pot_out, rb * n)) {
+            set_error("outputs overlap inputs");
+            return NBODY_E_INVAL;
+        }
+    }
+    Tune t = lookup_tune(2, prec, n);
+    NB_TRY(launch_vjp(prec, pos_mass, acc_pot_cot, (int)n, G, eps, pos_cot_out, mass_cot_out,
+                      acc_pot_out, t, (hipStream_t)stream),
+           "vjp kernel");
+    return NBODY_OK;
+}
+
+int nbody_energy(const void *pos_mass, const void *vel, const void *acc_pot, int64_t n,
+                 int32_t prec, double *energy_out, void *stream)
+{
+    NB_CHECK(check_n(n));
+    if (!prec_ok(prec)) {
+        set_error("bad precision %d", prec);
+        return NBODY_E_INVAL;
+    }
+    NB_CHECK(check_vec(pos_mass, prec, "pos_mass"));
+    NB_CHECK(check_vec(vel, prec, "vel"));
+    NB_CHECK(check_vec(acc_pot, prec, "acc_pot"));
+    if (!energy_out || (uintptr_t)energy_out % 8) {
+        set_error("energy_out NULL or misaligned");
+        return NBODY_E_INVAL;
+    }
+    const int nb = step_blocks((int)n);
+    double *ep = (double *)scratch(kSlotEnergy, sizeof(double) * 2 * nb);
+    if (!ep) {
+        set_error("cannot allocate energy scratch");
+        return NBODY_E_NOMEM;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    // close = open = false: the step kernel only reads and reports energies
+    // (it writes vel back unchanged).
+    NB_TRY(launch_step(prec, const_cast<void *>(pos_mass), const_cast<void *>(vel), acc_pot, (int)n,
+                       0.0, 0.0, false, false, ep, nullptr, s),
+           "energy kernel");
+    NB_TRY(launch_energy_final(ep, nb, energy_out, s), "energy kernel");
+    return NBODY_OK;
+}
+
+int nbody_leapfrog_kdk(void *pos_mass, void *vel, void *acc_pot, int64_t n,
+                       const int64_t *offsets_host, int32_t nsys, int32_t prec, double G,
+                       double eps, double dt, int32_t nsteps, uint32_t flags, double *energy_out,
+                       void *stream)
+{
+    NB_CHECK(check_n(n));
+    if (!prec_ok(prec) || nsteps < 0 || (flags & ~7u)) {
+        set_error("bad precision, nsteps or flags");
+        return NBODY_E_INVAL;
+    }
+    NB_CHECK(check_scalars(G, eps, dt));
+    NB_CHECK(check_vec(pos_mass, prec, "pos_mass"));
+    NB_CHECK(check_vec(vel, prec, "vel"));
+    NB_CHECK(check_vec(acc_pot, prec, "acc_pot"));
+    const size_t rb = rec_bytes(prec);
+    if (overlap(pos_mass, rb * n, vel, rb * n) || overlap(pos_mass, rb * n, acc_pot, rb * n) ||
+        overlap(vel, rb * n, acc_pot, rb * n)) {
+        set_error("pos_mass, vel and acc_pot must not overlap");
+        return NBODY_E_INVAL;
+    }
+    const bool want_energy = (flags & NBODY_ENERGY) != 0;
+    if (want_energy && (!energy_out || (uintptr_t)energy_out % 8)) {
+        set_error("NBODY_ENERGY needs an aligned energy_out");
+        return NBODY_E_INVAL;
+    }
+    const BatchPlan *plan = nullptr;
+    if (offsets_host) {
+        NB_CHECK(validate_offsets(offsets_host, nsys, n));
+        if (want_energy && nsys > 1) {
+            set_error("energies are reported for one system only");
+            return NBODY_E_UNSUPPORTED;
+        }
+        Tune bt = lookup_tune(1, prec, n);
+        BatchPlan *p = nullptr;
+        NB_CHECK(get_plan(offsets_host, nsys, bt, &p));
+        plan = p;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    double *en = want_energy ? energy_out : nullptr;
+    const int nb = step_blocks((int)n);
+    if (!(flags & NBODY_GRAPH)) {
+        StepBuffers buf;
+        if (en) {
+            buf.epart = (double *)scratch(kSlotEnergy, sizeof(double) * 2 * nb);
+            if (!buf.epart) {
+                set_error("cannot allocate energy scratch");
+                return NBODY_E_NOMEM;
+            }
+        }
+        return leapfrog_enqueue(pos_mass, vel, acc_pot, (int)n, plan, prec, G, eps, dt, nsteps, flags,
+                                en, buf, s);
+    }
+    // Graph path: capture once per key on a library stream, replay on `s`.
+    GraphKey key;
+    key.v = {(uint64_t)(uintptr_t)pos_mass, (uint64_t)(uintptr_t)vel, (uint64_t)(uintptr_t)acc_pot,
+             (uint64_t)n, (uint64_t)prec, dbits(G), dbits(eps), dbits(dt), (uint64_t)nsteps,
+             (uint64_t)flags, (uint64_t)(uintptr_t)en, (uint64_t)(uintptr_t)plan};
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    key.v.push_back((uint64_t)dev);
+    {
+        Tune t = lookup_tune(0, prec, n), bt = lookup_tune(1, prec, n);
+        key.v.insert(key.v.end(), {(uint64_t)t.tpl, (uint64_t)t.jsplit, (uint64_t)t.jtile,
+                                   (uint64_t)bt.tpl, (uint64_t)bt.jtile});
+    }
+    GraphEntry *ge = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_graphs.find(key);
+        if (it != g_graphs.end()) ge = &it->second;
+    }
+    if (!ge) {
+        GraphEntry e;
+        Tune t = lookup_tune(0, prec, n);
+        const size_t pb = plan ? 0 : accel_partial_bytes(prec, (int)n, t);
+        if (pb) NB_TRY(hipMalloc(&e.partial, pb), "graph scratch");
+        if (en) NB_TRY(hipMalloc((void **)&e.epart, sizeof(double) * 2 * nb), "graph scratch");
+        hipStream_t cs;
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            auto it = g_capture_stream.find(dev);
+            if (it == g_capture_stream.end()) {
+                hipStream_t ns;
+                if (hipStreamCreateWithFlags(&ns, hipStreamNonBlocking) != hipSuccess) {
+                    set_error("cannot create capture stream");
+                    return NBODY_E_HIP;
+                }
+                it = g_capture_stream.emplace(dev, ns).first;
+            }
+            cs = it->second;
+        }
+        NB_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
+        StepBuffers buf;
+        buf.epart = e.epart;
+        buf.partial = e.partial;
+        int rc = leapfrog_enqueue(pos_mass, vel, acc_pot, (int)n, plan, prec, G, eps, dt, nsteps, flags,
+                                  en, buf, cs);
+        hipGraph_t g = nullptr;
+        hipError_t ce = hipStreamEndCapture(cs, &g);
+        if (rc != NBODY_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (ce != hipSuccess) return hip_fail(ce, "end capture");
+        NB_TRY(hipGraphInstantiate(&e.exec, g, nullptr, nullptr, 0), "graph instantiate");
+        e.graph = g;
+        std::lock_guard<std::mutex> lk(g_mu);
+        ge = &g_graphs.emplace(key, e).first->second;
+    }
+    NB_TRY(hipGraphLaunch(ge->exec, s), "graph launch");
+    return NBODY_OK;
+}
+
+int nbody_kick_drift(void *pos_mass, void *vel, const void *acc_pot, int64_t n, int32_t prec,
+                     double h, double dt, int32_t close, int32_t open, void *stream)
+{
+    NB_CHECK(check_n(n));
+    if (!prec_ok(prec)) {
+        set_error("bad precision %d", prec);
+        return NBODY_E_INVAL;
+    }
+    NB_CHECK(check_scalars(1.0, 0.0, dt));
+    if (!std::isfinite(h)) {
+        set_error("h must be finite");
+        return NBODY_E_INVAL;
+    }
+    NB_CHECK(check_vec(pos_mass, prec, "pos_mass"));
+    NB_CHECK(check_vec(vel, prec, "vel"));
+    NB_CHECK(check_vec(acc_pot, prec, "acc_pot"));
+    const size_t rb = rec_bytes(prec);
+    if (overlap(pos_mass, rb * n, vel, rb * n) || overlap(pos_mass, rb * n, acc_pot, rb * n) ||
+        overlap(vel, rb * n, acc_pot, rb * n)) {
+        set_error("pos_mass, vel and acc_pot must not overlap");
+        return NBODY_E_INVAL;
+    }
+    if (!close && !open) return NBODY_OK;
+    NB_TRY(launch_step(prec, pos_mass, vel, acc_pot, (int)n, h, dt, close != 0, open != 0, nullptr,
+                       nullptr, (hipStream_t)stream),
+           "step kernel");
+    return NBODY_OK;
+}
+
+int nbody_permute(const void *src, void *dst, const int32_t *perm, int64_t n, int32_t rec_bytes_,
+                  int32_t inverse, void *stream)
+{
+    NB_CHECK(check_n(n));
+    if (rec_bytes_ != 16 && rec_bytes_ != 32) {
+        set_error("rec_bytes must be 16 or 32");
+        return NBODY_E_INVAL;
+    }
+    if (!src || !dst || !perm) {
+        set_error("NULL pointer");
+        return NBODY_E_INVAL;
+    }
+    if ((uintptr_t)src % rec_bytes_ || (uintptr_t)dst % rec_bytes_ || (uintptr_t)perm % 4) {
+        set_error("misaligned buffer");
+        return NBODY_E_ALIGN;
+    }
+    if (overlap(src, (size_t)rec_bytes_ * n, dst, (size_t)rec_bytes_ * n)) {
+        set_error("src and dst overlap");
+        return NBODY_E_INVAL;
+    }
+    NB_TRY(launch_permute(src, dst, perm, (int)n, rec_bytes_, inverse != 0, (hipStream_t)stream),
+           "permute kernel");
+    return NBODY_OK;
+}
+
+int nbody_orb_order(const void *pos_mass, int32_t prec, int64_t n, int32_t leaf, int32_t *perm_out,
+                    void *stream)
+{
+    NB_CHECK(check_n(n));
+    if (!prec_ok(prec) || leaf < 1) {
+        set_error("bad precision or leaf");
+        return NBODY_E_INVAL;
+    }
+    NB_CHECK(check_vec(pos_mass, prec, "pos_mass"));
+    if (!perm_out || (uintptr_t)perm_out % 4) {
+        set_error("perm_out NULL or misaligned");
+        return NBODY_E_INVAL;
+    }
+    return orb_order(pos_mass, prec, (int)n, leaf, perm_out, (hipStream_t)stream);
+}
+
+// ---- trajectory + adjoint ---------------------------------------------------
+int nbody_trajectory_forward(void *pos_mass, void *vel, int64_t n, int32_t prec, double G,
+                             double eps, double dt, int32_t nsteps, int32_t ckpt_every, void *ckpt,
+                             void *stream)
+{
+    NB_CHECK(check_n(n));
+    if (!prec_ok(prec) || nsteps < 0 || ckpt_every < 1 || nsteps % ckpt_every) {
+        set_error("bad precision, nsteps or ckpt_every (nsteps must be a multiple)");
+        return NBODY_E_INVAL;
+    }
+    NB_CHECK(check_scalars(G, eps, dt));
+    NB_CHECK(check_vec(pos_mass, prec, "pos_mass"));
+    NB_CHECK(check_vec(vel, prec, "vel"));
+    NB_CHECK(check_vec(ckpt, prec, "ckpt"));
+    const size_t rb = rec_bytes(prec) * (size_t)n;
+    void *acc = scratch(kSlotAdj0, rb);
+    if (!acc) {
+        set_error("cannot allocate trajectory scratch");
+        return NBODY_E_NOMEM;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const int nseg = nsteps / ckpt_every;
+    char *ck = (char *)ckpt;
+    NB_TRY(launch_copy(ck, pos_mass, rb, s), "checkpoint copy");
+    NB_TRY(launch_copy(ck + rb, vel, rb, s), "checkpoint copy");
+    StepBuffers buf;
+    for (int c = 0; c < nseg; ++c) {
+        NB_CHECK(leapfrog_enqueue(pos_mass, vel, acc, (int)n, nullptr, prec, G, eps, dt, ckpt_every,
+                                  c ? NBODY_ACC_VALID : 0u, nullptr, buf, s));
+        char *slot = ck + (size_t)(c + 1) * 2 * rb;
+        NB_TRY(launch_copy(slot, pos_mass, rb, s), "checkpoint copy");
+        NB_TRY(launch_copy(slot + rb, vel, rb, s), "checkpoint copy");
+    }
+    return NBODY_OK;
+}
+
+int nbody_trajectory_adjoint(const void *ckpt, int64_t n, int32_t prec, double G, double eps,
+                             double dt, int32_t nsteps, int32_t ckpt_every, const void *xbar_T,
+                             const void *vbar_T, void *pos_cot, void *vel_cot, void *mass_cot,
+                             void *stream)
+{
+    NB_CHECK(check_n(n));
+    if (!prec_ok(prec) || nsteps < 0 || ckpt_every < 1 || nsteps % ckpt_every) {
+        set_error("bad precision, nsteps or ckpt_every (nsteps must be a multiple)");
+        return NBODY_E_INVAL;
+    }
+    NB_CHECK(check_scalars(G, eps, dt));
+    NB_CHECK(check_vec(ckpt, prec, "ckpt"));
+    NB_CHECK(check_vec(xbar_T, prec, "xbar_T"));
+    NB_CHECK(check_vec(vbar_T, prec, "vbar_T"));
+    NB_CHECK(check_vec(pos_cot, prec, "pos_cot"));
+    NB_CHECK(check_vec(vel_cot, prec, "vel_cot"));
+    const size_t mb = (prec == NBODY_F64 ? 8 : 4);
+    if (!mass_cot || (uintptr_t)mass_cot % mb) {
+        set_error("mass_cot NULL or misaligned");
+        return NBODY_E_INVAL;
+    }
+    const size_t rb = rec_bytes(prec) * (size_t)n;
+    const int C = ckpt_every;
+    const int nseg = nsteps / C;
+    void *acc = scratch(kSlotAdj0, rb);
+    char *xs = (char *)scratch(kSlotAdj1, rb * (size_t)(C + 1));
+    void *vt = scratch(kSlotAdj2, rb);
+    if (!acc || !xs || !vt) {
+        set_error("cannot allocate adjoint scratch");
+        return NBODY_E_NOMEM;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const double h = 0.5 * dt;
+    const int ni = (int)n;
+    Tune vt_tune = lookup_tune(2, prec, n);
+    NB_TRY(launch_copy(pos_cot, xbar_T, rb, s), "adjoint init");
+    NB_TRY(launch_copy(vel_cot, vbar_T, rb, s), "adjoint init");
+    NB_TRY(launch_fill_zero(mass_cot, mb * (size_t)n, s), "adjoint init");
+    // The force at x_{s+1} receives h vbar from the closing kick of step s and
+    // h vbar from the opening kick of step s+1 (vbar unchanged in between):
+    // 2h vbar in the interior, h vbar at the last step and at x_0.
+    bool first = true;
+    const char *ck = (const char *)ckpt;
+    for (int c = nseg - 1; c >= 0; --c) {
+        // recompute positions of the segment from its checkpoint
+        const char *slot = ck + (size_t)c * 2 * rb;
+        NB_TRY(launch_copy(xs, slot, rb, s), "segment copy");
+        NB_TRY(launch_copy(vt, slot + rb, rb, s), "segment copy");
+        NB_CHECK(force(prec, xs, ni, G, eps, acc, 0, ni, s));
+        for (int k = 0; k < C; ++k) {
+            char *cur = xs + (size_t)k * rb, *nxt = xs + (size_t)(k + 1) * rb;
+            NB_TRY(launch_copy(nxt, cur, rb, s), "segment copy");
+            NB_TRY(launch_step(prec, nxt, vt, acc, ni, h, dt, k > 0, true, nullptr, nullptr, s), "segment step");
+            if (k + 1 < C) NB_CHECK(force(prec, nxt, ni, G, eps, acc, 0, ni, s));
+        }
+        // reverse sweep over the segment
+        for (int k = C - 1; k >= 0; --k) {
+            const double scale = first ? h : 2.0 * h;
+            first = false;
+            NB_TRY(launch_vjp_ex(prec, xs + (size_t)(k + 1) * rb, vel_cot, ni, G, eps, false, scale,
+                                 true, pos_cot, mass_cot, nullptr, vt_tune, s),
+                   "adjoint vjp");
+            NB_TRY(launch_adj_axpy(prec, vel_cot, pos_cot, dt, ni, s), "adjoint axpy");
+        }
+        if (c == 0 && nsteps > 0)
+            NB_TRY(launch_vjp_ex(prec, xs, vel_cot, ni, G, eps, false, h, true, pos_cot, mass_cot,
+                                 nullptr, vt_tune, s),
+                   "adjoint vjp");
+    }
+    return NBODY_OK;
+}
+
+// ---- tuning -----------------------------------------------------------------
+int nbody_set_tuning(int32_t kernel, int32_t prec, int32_t tpl, int32_t jsplit, int32_t jtile)
+{
+    if (kernel < 0 || kernel > 2 || !prec_ok(prec)) {
+        set_error("bad kernel or precision");
+        return NBODY_E_INVAL;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (tpl == -1 && jsplit == -1 && jtile == -1) {
+        g_pinned.erase({kernel, prec});
+        return NBODY_OK;
+    }
+    Tune t;
+    t.tpl = tpl;
+    t.jsplit = jsplit;
+    t.jtile = jtile;
+    if (!tune_valid(t) || (prec == NBODY_F64 && tpl == 4) || (kernel != 0 && jsplit != 1) ||
+        (kernel == 2 && tpl == 4)) {
+        set_error("unsupported tuning (tpl %d, jsplit %d, jtile %d)", tpl, jsplit, jtile);
+        return NBODY_E_INVAL;
+    }
+    g_pinned[{kernel, prec}] = t;
+    return NBODY_OK;
+}
+
+int nbody_get_tuning(int32_t kernel, int32_t prec, int64_t n, int32_t *tpl, int32_t *jsplit,
+                     int32_t *jtile)
+{
+    if (kernel < 0 || kernel > 2 || !prec_ok(prec) || n < 1 || !tpl || !jsplit || !jtile) {
+        set_error("bad arguments");
+        return NBODY_E_INVAL;
+    }
+    Tune t = lookup_tune(kernel, prec, n);
+    *tpl = t.tpl;
+    *jsplit = t.jsplit;
+    *jtile = t.jtile;
+    return NBODY_OK;
+}
+
+}  // extern "C"
+
+// ---- autotuner ----------------------------------------------------------------
+namespace nbi {
+namespace {
+
+__global__ void k_synth(float4 *p, int n, uint32_t seed)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    // xorshift-multiply hash of (seed, i) -> positions in [-1, 1)^3, mass 1/n
+    auto h = [](uint32_t x) {
+        x ^= x >> 16; x *= 0x7feb352dU; x ^= x >> 15; x *= 0x846ca68bU; x ^= x >> 16;
+        return x;
+    };
+    const uint32_t a = h(seed ^ (uint32_t)(3 * i)), b = h(a + 1u), c = h(b + 2u);
+    const float s = 1.0f / 2147483648.0f;
+    p[i] = make_float4((float)a * s - 1.0f, (float)b * s - 1.0f, (float)c * s - 1.0f, 1.0f / n);
+}
+
+__global__ void k_widen(const float4 *src, double4 *dst, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const float4 p = src[i];
+        dst[i] = make_double4(p.x, p.y, p.z, p.w);
+    }
+}
+
+}  // namespace
+}  // namespace nbi
+
+extern "C" int nbody_autotune(int32_t kernel, int32_t prec, int64_t n, const int64_t *offsets_host,
+                              int32_t nsys, void *stream)
+{
+    NB_CHECK(check_n(n));
+    if (kernel < 0 || kernel > 2 || !prec_ok(prec)) {
+        set_error("bad kernel or precision");
+        return NBODY_E_INVAL;
+    }
+    if (kernel == 1) {
+        NB_CHECK(validate_offsets(offsets_host, nsys, n));
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const size_t rb = rec_bytes(prec);
+    // inputs (pm), outputs (out), cotangents (cot), mass cotangent (mc)
+    char *buf = (char *)scratch(kSlotTune, rb * (size_t)n * 4 + 64);
+    if (!buf) {
+        set_error("cannot allocate tuning scratch");
+        return NBODY_E_NOMEM;
+    }
+    void *pm = buf, *out = buf + rb * n, *cot = buf + 2 * rb * n, *mc = buf + 3 * rb * n;
+    const int tb = 256, nb = (int)((n + tb - 1) / tb);
+    if (prec == NBODY_F64) {
+        float4 *tmp = (float4 *)out;
+        hipLaunchKernelGGL(k_synth, dim3(nb), dim3(tb), 0, s, tmp, (int)n, 12345u);
+        hipLaunchKernelGGL(k_widen, dim3(nb), dim3(tb), 0, s, tmp, (double4 *)pm, (int)n);
+        hipLaunchKernelGGL(k_widen, dim3(nb), dim3(tb), 0, s, tmp, (double4 *)cot, (int)n);
+    } else {
+        hipLaunchKernelGGL(k_synth, dim3(nb), dim3(tb), 0, s, (float4 *)pm, (int)n, 12345u);
+        hipLaunchKernelGGL(k_synth, dim3(nb), dim3(tb), 0, s, (float4 *)cot, (int)n, 777u);
+    }
+    NB_TRY(hipGetLastError(), "tuning inputs");
+    std::vector<Tune> cands;
+    const int tpls[3] = {1, 2, 4};
+    const int jts[3] = {256, 512, 2048};
+    for (int tp : tpls) {
+        if ((prec == NBODY_F64 || kernel == 2) && tp == 4) continue;
+        for (int jt : jts) {
+            if (kernel == 0) {
+                for (int js = 1; js <= 32; js *= 2) {
+                    if (js > 1 && n / js < 512) break;
+                    const int64_t waves = (n + 64 * tp - 1) / (64 * tp);
+                    if (waves * js > 65536 && js > 1) break;
+                    Tune t;
+                    t.tpl = tp;
+                    t.jsplit = js;
+                    t.jtile = jt;
+                    cands.push_back(t);
+                }
+            } else {
+                Tune t;
+                t.tpl = tp;
+                t.jsplit = 1;
+                t.jtile = jt;
+                cands.push_back(t);
+            }
+        }
+    }
+    BatchPlan *plan = nullptr;
+    hipEvent_t e0, e1;
+    NB_TRY(hipEventCreate(&e0), "event");
+    NB_TRY(hipEventCreate(&e1), "event");
+    Tune best = cands.front();
+    float best_ms = 1e30f;
+    const int reps = n >= (1 << 19) ? 1 : 3;
+    for (const Tune &t : cands) {
+        void *partial = nullptr;
+        if (kernel == 0) {
+            const size_t pb = accel_partial_bytes(prec, (int)n, t);
+            if (pb && !(partial = scratch(kSlotPartial, pb))) continue;
+        } else if (kernel == 1) {
+            if (get_plan(offsets_host, nsys, t, &plan) != NBODY_OK) continue;
+        }
+        auto run = [&]() -> hipError_t {
+            if (kernel == 0) return launch_accel(prec, pm, (int)n, 1.0, 0.01, out, 0, (int)n, t, partial, s);
+            if (kernel == 1)
+                return launch_batched(prec, pm, plan->d_off, plan->d_units, plan->nunits, 1.0, nullptr,
+                                      0.01, out, t, plan->d_counter, plan->grid, s);
+            return launch_vjp(prec, pm, cot, (int)n, 1.0, 0.01, out, mc, nullptr, t, s);
+        };
+        if (run() != hipSuccess) continue;  // warm-up
+        std::vector<float> ms;
+        for (int r = 0; r < reps; ++r) {
+            (void)hipEventRecord(e0, s);
+            (void)run();
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            float m = 0;
+            (void)hipEventElapsedTime(&m, e0, e1);
+            ms.push_back(m);
+        }
+        std::sort(ms.begin(), ms.end());
+        const float med = ms[ms.size() / 2];
+        if (med < best_ms) {
+            best_ms = med;
+            best = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    NB_TRY(hipStreamSynchronize(s), "autotune sync");
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_cache_locked();
+    g_tuned[TuneKey(kernel, prec, log2ceil(n))] = best;
+    save_cache_locked();
+    return NBODY_OK;
+}
+
+extern "C" void nbody_release(void)
+{
+    (void)hipDeviceSynchronize();
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto &kv : g_graphs) {
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+        if (kv.second.epart) (void)hipFree(kv.second.epart);
+        if (kv.second.partial) (void)hipFree(kv.second.partial);
+    }
+    g_graphs.clear();
+    for (auto &kv : g_plans) {
+        (void)hipFree(kv.second.d_off);
+        (void)hipFree(kv.second.d_units);
+        (void)hipFree(kv.second.d_counter);
+    }
+    g_plans.clear();
+    for (auto &kv : g_scratch)
+        for (int k = 0; k < kNumSlots; ++k)
+            if (kv.second.ptr[k]) (void)hipFree(kv.second.ptr[k]);
+    g_scratch.clear();
+    orb_release();
+}

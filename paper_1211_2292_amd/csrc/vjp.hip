@@ -1,0 +1,310 @@
+// Fused force + vector-Jacobian product of the direct sum (gfx950).
+//
+// The paper has no derivatives; this is the reverse-mode derivative of the
+// force law of Section IV (see nbody.h).  With d = x_j - x_k,
+// q = |d|^2 + eps^2, rho = q^(-1/2), w = rho^3, u = rho^5 and
+// T_kj = w I - 3 u d d^T:
+//     xbar_k = G sum_{j != k} T_kj (m_k abar_j - m_j abar_k)
+//              - G m_k sum_{j != k} phibar_j w d  - phibar_k a_k
+//     mbar_k = -G sum_{j != k} w d . abar_j  - G sum_{j != k} phibar_j rho
+// and, in the same sweep, the forward a_k and phi_k.
+//
+// Per wave: 64*TPL targets in VGPRs; each source brings its position/mass
+// and its cotangent record through wave-uniform scalar loads.  Per pair the
+// sweep accumulates
+//     P  += w e                 e = m_k abar_j - m_j abar_k
+//     Q  += (w rho^2)(d . e) d  -> xbar = G (P - 3 Q) + ...
+//     M  += w (d . abar_j)      -> mbar = -G M + ...
+//     A  += m_j w d, F += m_j rho        (forward force and potential)
+//     B  += phibar_j w d, H += phibar_j rho   (only with phibar)
+// FP32 tile partials are folded into FP64 running sums for the FP32 modes;
+// the FP64 mode runs the same sweep in FP64.
+//
+// `scale` multiplies the cotangent (the product is linear in it) and
+// `accumulate` adds the result into the existing pos_cot/mass_cot, which is
+// how the trajectory adjoint applies one VJP per position without extra
+// passes.
+#include "internal.h"
+
+namespace nbi {
+namespace {
+
+constexpr int kVjpUnroll = 4;
+
+template <typename T, int TPL, bool PHI>
+struct VAcc {
+    T P[TPL][3], Q[TPL][3], M[TPL], A[TPL][3], F[TPL];
+    T B[TPL][3], H[TPL];
+    __device__ void zero()
+    {
+#pragma unroll
+        for (int t = 0; t < TPL; ++t) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) P[t][c] = Q[t][c] = A[t][c] = B[t][c] = T(0);
+            M[t] = F[t] = H[t] = T(0);
+        }
+    }
+};
+
+template <typename T, int TPL>
+struct VTgt {
+    T x[TPL][3], m[TPL], ab[TPL][3], pb[TPL];
+    int i[TPL];
+};
+
+template <typename T>
+__device__ __forceinline__ T rsq_t(T q);
+template <>
+__device__ __forceinline__ float rsq_t<float>(float q)
+{
+    return __builtin_amdgcn_rsqf(q);
+}
+template <>
+__device__ __forceinline__ double rsq_t<double>(double q)
+{
+    double y = __builtin_amdgcn_rsq(q);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const double e = __builtin_fma(-q, y * y, 1.0);
+        y = __builtin_fma(0.5 * y, e, y);
+    }
+    return y;
+}
+
+template <typename T, typename V, int TPL, bool PHI, bool MASK>
+__device__ __forceinline__ void vpair(const V p, const V c, const int j, const VTgt<T, TPL> &K,
+                                      const T eps2, VAcc<T, TPL, PHI> &S)
+{
+#pragma unroll
+    for (int t = 0; t < TPL; ++t) {
+        const T d0 = p.x - K.x[t][0];
+        const T d1 = p.y - K.x[t][1];
+        const T d2 = p.z - K.x[t][2];
+        const T q = __builtin_fma(d2, d2, __builtin_fma(d1, d1, __builtin_fma(d0, d0, eps2)));
+        T rho = rsq_t<T>(q);
+        if (MASK) rho = (j == K.i[t]) ? T(0) : rho;
+        const T r2 = rho * rho;
+        const T w = rho * r2;
+        const T e0 = __builtin_fma(-p.w, K.ab[t][0], K.m[t] * c.x);
+        const T e1 = __builtin_fma(-p.w, K.ab[t][1], K.m[t] * c.y);
+        const T e2 = __builtin_fma(-p.w, K.ab[t][2], K.m[t] * c.z);
+        const T de = __builtin_fma(d2, e2, __builtin_fma(d1, e1, d0 * e0));
+        const T da = __builtin_fma(d2, c.z, __builtin_fma(d1, c.y, d0 * c.x));
+        const T uq = (w * r2) * de;
+        S.P[t][0] = __builtin_fma(w, e0, S.P[t][0]);
+        S.P[t][1] = __builtin_fma(w, e1, S.P[t][1]);
+        S.P[t][2] = __builtin_fma(w, e2, S.P[t][2]);
+        S.Q[t][0] = __builtin_fma(uq, d0, S.Q[t][0]);
+        S.Q[t][1] = __builtin_fma(uq, d1, S.Q[t][1]);
+        S.Q[t][2] = __builtin_fma(uq, d2, S.Q[t][2]);
+        S.M[t] = __builtin_fma(w, da, S.M[t]);
+        const T mw = p.w * w;
+        S.A[t][0] = __builtin_fma(mw, d0, S.A[t][0]);
+        S.A[t][1] = __builtin_fma(mw, d1, S.A[t][1]);
+        S.A[t][2] = __builtin_fma(mw, d2, S.A[t][2]);
+        S.F[t] = __builtin_fma(p.w, rho, S.F[t]);
+        if (PHI) {
+            const T pw = c.w * w;
+            S.B[t][0] = __builtin_fma(pw, d0, S.B[t][0]);
+            S.B[t][1] = __builtin_fma(pw, d1, S.B[t][1]);
+            S.B[t][2] = __builtin_fma(pw, d2, S.B[t][2]);
+            S.H[t] = __builtin_fma(c.w, rho, S.H[t]);
+        }
+    }
+}
+
+template <typename T, typename V, int TPL, bool PHI, bool MASK>
+__device__ __forceinline__ void vsweep(const V *__restrict__ pm, const V *__restrict__ cot, int j0,
+                                       int j1, const VTgt<T, TPL> &K, T eps2,
+                                       VAcc<T, TPL, PHI> &S)
+{
+    int j = j0;
+    for (; j + kVjpUnroll <= j1; j += kVjpUnroll) {
+        V p[kVjpUnroll], c[kVjpUnroll];
+#pragma unroll
+        for (int u = 0; u < kVjpUnroll; ++u) {
+            p[u] = pm[j + u];
+            c[u] = cot[j + u];
+        }
+#pragma unroll
+        for (int u = 0; u < kVjpUnroll; ++u) vpair<T, V, TPL, PHI, MASK>(p[u], c[u], j + u, K, eps2, S);
+    }
+    for (; j < j1; ++j) vpair<T, V, TPL, PHI, MASK>(pm[j], cot[j], j, K, eps2, S);
+}
+
+// Number of accumulated scalars per target.
+constexpr int kVN = 17;
+
+template <typename T, int TPL, bool PHI>
+__device__ __forceinline__ void vflatten(const VAcc<T, TPL, PHI> &S, int t, T (&f)[kVN])
+{
+    f[0] = S.P[t][0]; f[1] = S.P[t][1]; f[2] = S.P[t][2];
+    f[3] = S.Q[t][0]; f[4] = S.Q[t][1]; f[5] = S.Q[t][2];
+    f[6] = S.M[t];
+    f[7] = S.A[t][0]; f[8] = S.A[t][1]; f[9] = S.A[t][2];
+    f[10] = S.F[t];
+    f[11] = S.B[t][0]; f[12] = S.B[t][1]; f[13] = S.B[t][2];
+    f[14] = S.H[t];
+    f[15] = 0; f[16] = 0;
+}
+
+template <typename T, typename V, typename MT, int TPL, bool PHI>
+__global__ __launch_bounds__(kBlock) void k_vjp(const V *__restrict__ pm, const V *__restrict__ cot,
+                                                int n, T eps2, double G, int jtile, double scale,
+                                                int accumulate, V *__restrict__ pos_cot,
+                                                MT *__restrict__ mass_cot, V *__restrict__ acc_out)
+{
+    constexpr int WT = 64 * TPL;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t0 = (blockIdx.x * (kBlock / 64) + wave) * WT;
+    if (t0 >= n) return;
+    VTgt<T, TPL> K;
+#pragma unroll
+    for (int t = 0; t < TPL; ++t) {
+        const int i = t0 + t * 64 + lane;
+        K.i[t] = i;
+        const int ic = min(i, n - 1);
+        const V p = pm[ic];
+        const V c = cot[ic];
+        K.x[t][0] = p.x; K.x[t][1] = p.y; K.x[t][2] = p.z;
+        K.m[t] = p.w;
+        K.ab[t][0] = c.x; K.ab[t][1] = c.y; K.ab[t][2] = c.z;
+        K.pb[t] = c.w;
+    }
+    const int d0 = t0, d1 = t0 + WT;
+    double R[TPL][kVN];
+#pragma unroll
+    for (int t = 0; t < TPL; ++t)
+#pragma unroll
+        for (int c = 0; c < kVN; ++c) R[t][c] = 0.0;
+    VAcc<T, TPL, PHI> S;
+    for (int jc = 0; jc < n; jc += jtile) {
+        const int ce = min(jc + jtile, n);
+        const int lo = min(max(d0, jc), ce);
+        const int hi = min(max(d1, jc), ce);
+        S.zero();
+        vsweep<T, V, TPL, PHI, false>(pm, cot, jc, lo, K, eps2, S);
+        vsweep<T, V, TPL, PHI, true>(pm, cot, lo, hi, K, eps2, S);
+        vsweep<T, V, TPL, PHI, false>(pm, cot, hi, ce, K, eps2, S);
+#pragma unroll
+        for (int t = 0; t < TPL; ++t) {
+            T f[kVN];
+            vflatten(S, t, f);
+#pragma unroll
+            for (int c = 0; c < 15; ++c) R[t][c] += (double)f[c];
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < TPL; ++t) {
+        const int i = t0 + t * 64 + lane;
+        if (i >= n) continue;
+        const double mk = K.m[t];
+        const double pbk = PHI ? (double)K.pb[t] : 0.0;
+        const double ax = G * R[t][7], ay = G * R[t][8], az = G * R[t][9];
+        double gx = G * (R[t][0] - 3.0 * R[t][3]);
+        double gy = G * (R[t][1] - 3.0 * R[t][4]);
+        double gz = G * (R[t][2] - 3.0 * R[t][5]);
+        double gm = -G * R[t][6];
+        if (PHI) {
+            gx += -G * mk * R[t][11] - pbk * ax;
+            gy += -G * mk * R[t][12] - pbk * ay;
+            gz += -G * mk * R[t][13] - pbk * az;
+            gm += -G * R[t][14];
+        }
+        gx *= scale;
+        gy *= scale;
+        gz *= scale;
+        gm *= scale;
+        if (accumulate) {
+            const V o = pos_cot[i];
+            gx += (double)o.x;
+            gy += (double)o.y;
+            gz += (double)o.z;
+            gm += (double)mass_cot[i];
+        }
+        V g;
+        g.x = (T)gx; g.y = (T)gy; g.z = (T)gz; g.w = (T)0;
+        pos_cot[i] = g;
+        mass_cot[i] = (MT)gm;
+        if (acc_out) {
+            V a;
+            a.x = (T)ax; a.y = (T)ay; a.z = (T)az; a.w = (T)(-G * R[t][10]);
+            acc_out[i] = a;
+        }
+    }
+}
+
+template <typename V, typename S>
+__global__ __launch_bounds__(kBlock) void k_axpy(V *__restrict__ y, const V *__restrict__ x, S a,
+                                                 int n)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    V v = y[i];
+    const V u = x[i];
+    v.x = v.x + a * u.x;
+    v.y = v.y + a * u.y;
+    v.z = v.z + a * u.z;
+    y[i] = v;
+}
+
+template <typename T, typename V, typename MT, int TPL>
+hipError_t go_vjp(const void *pm, const void *cot, int n, T eps2, double G, int jtile, double scale,
+                  int accumulate, bool phi, void *pos_cot, void *mass_cot, void *acc_out,
+                  hipStream_t s)
+{
+    const int per_block = (kBlock / 64) * 64 * TPL;
+    const dim3 grid((n + per_block - 1) / per_block);
+    if (phi)
+        hipLaunchKernelGGL((k_vjp<T, V, MT, TPL, true>), grid, dim3(kBlock), 0, s, (const V *)pm,
+                           (const V *)cot, n, eps2, G, jtile, scale, accumulate, (V *)pos_cot,
+                           (MT *)mass_cot, (V *)acc_out);
+    else
+        hipLaunchKernelGGL((k_vjp<T, V, MT, TPL, false>), grid, dim3(kBlock), 0, s, (const V *)pm,
+                           (const V *)cot, n, eps2, G, jtile, scale, accumulate, (V *)pos_cot,
+                           (MT *)mass_cot, (V *)acc_out);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// Internal entry with scale/accumulate, used by the trajectory adjoint.
+hipError_t launch_vjp_ex(int prec, const void *pm, const void *cot, int n, double G, double eps,
+                         bool phi, double scale, bool accumulate, void *pos_cot, void *mass_cot,
+                         void *acc_out, const Tune &t, hipStream_t s)
+{
+    if (prec == NBODY_F64) {
+        if (t.tpl == 1)
+            return go_vjp<double, double4, double, 1>(pm, cot, n, eps * eps, G, t.jtile, scale,
+                                                      accumulate, phi, pos_cot, mass_cot, acc_out, s);
+        return go_vjp<double, double4, double, 2>(pm, cot, n, eps * eps, G, t.jtile, scale,
+                                                  accumulate, phi, pos_cot, mass_cot, acc_out, s);
+    }
+    const float e2 = (float)(eps * eps);
+    if (t.tpl == 1)
+        return go_vjp<float, float4, float, 1>(pm, cot, n, e2, G, t.jtile, scale, accumulate, phi,
+                                               pos_cot, mass_cot, acc_out, s);
+    return go_vjp<float, float4, float, 2>(pm, cot, n, e2, G, t.jtile, scale, accumulate, phi,
+                                           pos_cot, mass_cot, acc_out, s);
+}
+
+hipError_t launch_vjp(int prec, const void *pm, const void *cot, int n, double G, double eps,
+                      void *pos_cot, void *mass_cot, void *acc_out, const Tune &t, hipStream_t s)
+{
+    return launch_vjp_ex(prec, pm, cot, n, G, eps, true, 1.0, false, pos_cot, mass_cot, acc_out, t, s);
+}
+
+hipError_t launch_adj_axpy(int prec, void *y, const void *x, double a, int n, hipStream_t s)
+{
+    const dim3 grid((n + kBlock - 1) / kBlock);
+    if (prec == NBODY_F64)
+        hipLaunchKernelGGL((k_axpy<double4, double>), grid, dim3(kBlock), 0, s, (double4 *)y,
+                           (const double4 *)x, a, n);
+    else
+        hipLaunchKernelGGL((k_axpy<float4, float>), grid, dim3(kBlock), 0, s, (float4 *)y,
+                           (const float4 *)x, (float)a, n);
+    return hipGetLastError();
+}
+
+}  // namespace nbi

@@ -1,0 +1,89 @@
+"""The C ABI: the library loads, exports every entry point the header
+declares, and rejects bad arguments before enqueueing anything (these calls
+return on the host without touching a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    import paper_1211_2292_amd as nb
+    if not os.path.exists(nb.LIB_PATH):
+        pytest.skip("libnbody.so not built")
+    return nb, nb.lib()
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "nbody.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(nbody_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    nb, L = _lib()
+    names = _declared()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+        assert name in nb._SIGS, name
+
+
+def test_version_and_status_strings():
+    nb, L = _lib()
+    assert L.nbody_version() == 100
+    for rc in (0, -1, -2, -3, -4, -5):
+        assert L.nbody_status_string(rc)
+
+
+P = ctypes.c_void_p
+
+
+@pytest.mark.parametrize("args,rc", [
+    ((None, 10, 1, 1.0, 0.01, P(64), 0, 10, None), -1),            # NULL input
+    ((P(64), 0, 1, 1.0, 0.01, P(128), 0, 0, None), -1),             # n = 0
+    ((P(64), 1 << 31, 1, 1.0, 0.01, P(128), 0, 1, None), -1),       # n too large
+    ((P(64), 10, 7, 1.0, 0.01, P(128), 0, 10, None), -1),           # bad precision
+    ((P(64), 10, 1, 1.0, -0.5, P(1024), 0, 10, None), -1),          # eps < 0
+    ((P(64), 10, 1, float("nan"), 0.5, P(1024), 0, 10, None), -1),  # G not finite
+    ((P(72), 10, 1, 1.0, 0.01, P(1024), 0, 10, None), -2),          # misaligned float4
+    ((P(80), 10, 0, 1.0, 0.01, P(2048), 0, 10, None), -2),          # double4 needs 32 B
+    ((P(64), 10, 1, 1.0, 0.01, P(1024), 5, 6, None), -1),           # targets beyond n
+    ((P(64), 10, 1, 1.0, 0.01, P(96), 0, 10, None), -1),            # output overlaps input
+])
+def test_accel_validation(args, rc):
+    nb, L = _lib()
+    assert L.nbody_accel(*args) == rc
+    assert L.nbody_last_error()
+
+
+def test_other_entry_points_validate():
+    nb, L = _lib()
+    off = (ctypes.c_int64 * 3)(0, 5, 4)  # decreasing
+    assert L.nbody_batched_accel(P(64), off, 2, 1, 1.0, None, 0.01, P(1024), None) == -1
+    off = (ctypes.c_int64 * 3)(1, 5, 9)  # does not start at 0
+    assert L.nbody_batched_accel(P(64), off, 2, 1, 1.0, None, 0.01, P(1024), None) == -1
+    assert L.nbody_leapfrog_kdk(P(64), P(1024), P(4096), 10, None, 0, 1, 1.0, 0.01, 1e-3, -1, 0, None, None) == -1
+    assert L.nbody_leapfrog_kdk(P(64), P(1024), P(4096), 10, None, 0, 1, 1.0, 0.01, 1e-3, 1, 0x100, None, None) == -1
+    assert L.nbody_leapfrog_kdk(P(64), P(1024), P(4096), 10, None, 0, 1, 1.0, 0.01, 1e-3, 1, 0x4, None, None) == -1
+    assert L.nbody_leapfrog_kdk(P(64), P(64), P(4096), 10, None, 0, 1, 1.0, 0.01, 1e-3, 1, 0, None, None) == -1
+    assert L.nbody_accel_vjp(P(64), P(1024), 10, 1, 1.0, 0.01, P(4096), None, None, None) == -1
+    assert L.nbody_orb_order(P(64), 1, 10, 0, P(1024), None) == -1
+    assert L.nbody_permute(P(64), P(1024), P(4096), 10, 24, 0, None) == -1
+    assert L.nbody_trajectory_forward(P(64), P(1024), 10, 1, 1.0, 0.01, 1e-3, 30, 20, P(4096), None) == -1
+    assert L.nbody_set_tuning(0, 1, 3, 1, 512) == -1
+    assert L.nbody_set_tuning(0, 1, 2, 1, 100) == -1
+    assert L.nbody_set_tuning(1, 1, 2, 4, 512) == -1
+    assert L.nbody_energy(P(64), P(1024), P(4096), 10, 1, None, None) == -1
+
+
+def test_tuning_pin_roundtrip():
+    nb, L = _lib()
+    assert L.nbody_set_tuning(0, 2, 4, 8, 1024) == 0
+    assert nb.get_tuning(0, 2, 1 << 20) == (4, 8, 1024)
+    assert L.nbody_set_tuning(0, 2, -1, -1, -1) == 0
+    t = nb.get_tuning(0, 2, 1 << 20)
+    assert t[0] in (1, 2, 4) and t[2] % 8 == 0

@@ -1,0 +1,174 @@
+"""Parity of the HIP force/potential kernels (nbody_accel) with the FP64
+oracle: the exact softened pair sum of the paper's force calculation
+(Section IV.B, Calculate_forces with every body on the interaction list)."""
+import numpy as np
+import pytest
+
+import ics
+from nbtest import gpu, host, max_rel, normwise, rms_rel, to_dev, widen32
+
+pytestmark = pytest.mark.gpu
+
+MODES32 = ["F32", "F32_KAHAN", "F32_F64ACC"]
+
+
+def _run(nb, torch, pm_np, eps, prec, dtype, **kw):
+    pm = to_dev(torch, pm_np, dtype)
+    out = nb.accel(pm, eps, prec=getattr(nb, prec), **kw)
+    torch.cuda.synchronize()
+    return host(out)
+
+
+def test_f64_plain_method_ball4096(orc):
+    """Uniform ball N = 4096, FP64, eps = 0.01: <= 1e-12 RMS relative."""
+    torch, nb = gpu()
+    w = ics.WORKLOADS["ball4096_f64"]
+    pm, _ = ics.uniform_ball(w["n"], w["seed"])
+    out = _run(nb, torch, pm, w["eps"], "F64", torch.float64)
+    acc, pot = orc.accel(pm, w["eps"])
+    assert rms_rel(out[:, :3], acc) <= 1e-12
+    assert rms_rel(out[:, 3], pot) <= 1e-12
+    mom = (pm[:, 3:4] * out[:, :3]).sum(axis=0)
+    assert np.linalg.norm(mom) / (pm[:, 3] * np.linalg.norm(out[:, :3], axis=1)).sum() <= 1e-13
+
+
+@pytest.mark.parametrize("mode", MODES32)
+def test_f32_modes_plummer65536_sampled(orc, mode):
+    """Plummer N = 65536, eps = 0.01, 1024 sampled targets: compensated modes
+    <= 1e-5 RMS relative, pure FP32 reported with a looser bar."""
+    torch, nb = gpu()
+    w = ics.WORKLOADS["plummer65536"]
+    pm, _ = ics.plummer(w["n"], w["seed"])
+    pm32 = widen32(pm)
+    tg = ics.sample_targets(w["n"], 1024, w["seed"] + 1)
+    out = _run(nb, torch, pm32, w["eps"], mode, torch.float32)
+    acc, pot = orc.accel(pm32, w["eps"], targets=tg)
+    e_a = rms_rel(out[tg, :3], acc)
+    e_p = rms_rel(out[tg, 3], pot)
+    print(f"{mode}: force rms rel {e_a:.3e} max {max_rel(out[tg, :3], acc):.3e}; pot rms rel {e_p:.3e}")
+    bar = 1e-4 if mode == "F32" else 1e-5
+    assert e_a <= bar and e_p <= bar
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 257, 1000, 4097])
+@pytest.mark.parametrize("mode", ["F64"] + MODES32)
+def test_ragged_sizes(orc, n, mode):
+    torch, nb = gpu()
+    pm, _ = ics.plummer(max(n, 2), 100 + n)
+    pm = pm[:n].copy()
+    pm[:, 3] *= np.linspace(0.5, 1.5, n)
+    dtype = torch.float64 if mode == "F64" else torch.float32
+    src = pm if mode == "F64" else widen32(pm)
+    out = _run(nb, torch, src, 0.02, mode, dtype)
+    acc, pot = orc.accel(src, 0.02)
+    if n == 1:
+        assert np.all(out == 0.0)
+        return
+    bar = 1e-12 if mode == "F64" else 2e-6
+    assert rms_rel(out[:, :3], acc) <= bar
+    assert rms_rel(out[:, 3], pot) <= bar
+
+
+@pytest.mark.parametrize("tpl,js,jt", [(1, 1, 8), (2, 3, 64), (4, 5, 256), (1, 32, 2048), (2, 8, 16)])
+@pytest.mark.parametrize("mode", ["F64", "F32_KAHAN", "F32"])
+def test_kernel_shapes(orc, tpl, js, jt, mode):
+    """Every tuning shape gives the same answer (to rounding) as the oracle."""
+    torch, nb = gpu()
+    if mode == "F64" and tpl == 4:
+        pytest.skip("FP64 kernel has tpl 1 and 2")
+    n = 3001
+    pm, _ = ics.uniform_ball(n, 7)
+    prec = getattr(nb, mode)
+    nb.set_tuning(0, prec, tpl, js, jt)
+    try:
+        dtype = torch.float64 if mode == "F64" else torch.float32
+        src = pm if mode == "F64" else widen32(pm)
+        out = _run(nb, torch, src, 0.01, mode, dtype)
+    finally:
+        nb.set_tuning(0, prec)
+    acc, pot = orc.accel(src, 0.01)
+    bar = 1e-12 if mode == "F64" else 2e-6
+    assert rms_rel(out[:, :3], acc) <= bar and rms_rel(out[:, 3], pot) <= bar
+
+
+@pytest.mark.parametrize("mode", ["F64", "F32_KAHAN"])
+def test_target_subsets(orc, mode):
+    torch, nb = gpu()
+    n = 2000
+    pm, _ = ics.plummer(n, 8)
+    dtype = torch.float64 if mode == "F64" else torch.float32
+    src = pm if mode == "F64" else widen32(pm)
+    full = _run(nb, torch, src, 0.01, mode, dtype)
+    for tb, tc in [(0, 1), (5, 300), (1999, 1), (700, 1300), (123, 0)]:
+        part = _run(nb, torch, src, 0.01, mode, dtype, target_begin=tb, target_count=tc)
+        assert part.shape[0] == tc
+        # the same wave shape covers different target ranges; only rounding
+        # order at tile edges can differ from the full evaluation
+        if tc:
+            acc, pot = orc.accel(src, 0.01, targets=np.arange(tb, tb + tc))
+            bar = 1e-12 if mode == "F64" else 2e-6
+            assert rms_rel(part[:, :3], acc) <= bar
+
+
+def test_deterministic_and_mirror_exact():
+    torch, nb = gpu()
+    pm, _ = ics.plummer(5000, 9)
+    for mode in ["F64", "F32", "F32_KAHAN", "F32_F64ACC"]:
+        dtype = torch.float64 if mode == "F64" else torch.float32
+        a = _run(nb, torch, pm, 0.01, mode, dtype)
+        b = _run(nb, torch, pm, 0.01, mode, dtype)
+        assert np.array_equal(a, b), mode
+        q = pm.copy()
+        q[:, :3] = -q[:, :3]
+        c = _run(nb, torch, q, 0.01, mode, dtype)
+        assert np.array_equal(c[:, :3], -a[:, :3]) and np.array_equal(c[:, 3], a[:, 3]), mode
+
+
+def test_closed_forms_on_gpu():
+    """Cube vertices (eps = 0): a = -(1/4 + 1/(4 sqrt2) + 1/(12 sqrt3)) G m x."""
+    torch, nb = gpu()
+    pts = np.array([[sx, sy, sz, 0.5] for sx in (-1.0, 1.0) for sy in (-1.0, 1.0) for sz in (-1.0, 1.0)])
+    amag = 0.25 + 1 / (4 * np.sqrt(2)) + 1 / (12 * np.sqrt(3))
+    out = _run(nb, torch, pts, 0.0, "F64", torch.float64)
+    np.testing.assert_allclose(out[:, :3], -0.5 * amag * pts[:, :3], rtol=1e-14)
+    out = _run(nb, torch, pts, 0.0, "F32_KAHAN", torch.float32)
+    np.testing.assert_allclose(out[:, :3], -0.5 * amag * pts[:, :3], rtol=1e-6)
+
+
+def test_eps_zero_and_coincident():
+    torch, nb = gpu()
+    pm = np.array([[0.0, 0, 0, 1.0], [0.0, 0, 0, 1.0], [1.0, 0, 0, 1.0]])
+    out = _run(nb, torch, pm, 0.0, "F32_KAHAN", torch.float32)
+    assert not np.isfinite(out[0, 3]) and not np.isfinite(out[1, 3])
+    pm[1, 0] = 2.0
+    out = _run(nb, torch, pm, 0.0, "F32_KAHAN", torch.float32)
+    assert np.all(np.isfinite(out))
+    np.testing.assert_allclose(out[0, 3], -1.5, rtol=1e-6)
+
+
+def test_energy_entry_point(orc):
+    torch, nb = gpu()
+    pm, v = ics.plummer(3000, 12)
+    for mode, dtype in [("F64", torch.float64), ("F32_KAHAN", torch.float32)]:
+        p = to_dev(torch, pm, dtype)
+        vv = to_dev(torch, v, dtype)
+        a = nb.accel(p, 0.01, prec=getattr(nb, mode))
+        e = nb.energy(p, vv, a).cpu().numpy()
+        K, U = orc.energy(host(vv), host(p), host(a)[:, 3])
+        np.testing.assert_allclose(e, [K, U], rtol=1e-12)
+
+
+def test_full_size_collide1m_sampled(orc):
+    """Two colliding Plummer spheres, N = 2^20, eps = 0.005, FP32 with FP64
+    cross-tile sums, the launch shape the benchmark uses: sampled targets."""
+    torch, nb = gpu()
+    w = ics.WORKLOADS["collide1m"]
+    pm, _ = ics.colliding_pair(w["n"], w["seed"])
+    pm32 = widen32(pm)
+    tg = ics.sample_targets(w["n"], 256, w["seed"] + 1)
+    acc, pot = orc.accel(pm32, w["eps"], targets=tg)
+    for mode in ["F32_F64ACC", "F32_KAHAN", "F32"]:
+        out = _run(nb, torch, pm32, w["eps"], mode, torch.float32)
+        e = rms_rel(out[tg, :3], acc)
+        print(f"collide1m {mode}: force rms rel {e:.3e}, pot rms rel {rms_rel(out[tg, 3], pot):.3e}")
+        assert e <= (1e-4 if mode == "F32" else 1e-5)

@@ -1,0 +1,111 @@
+"""Parity of the fused force + VJP kernel (nbody_accel_vjp) and of the
+checkpointed trajectory adjoint with the FP64 oracle (reverse-mode
+derivative of the paper's force law and of the leapfrog around it)."""
+import numpy as np
+import pytest
+
+import ics
+from nbtest import gpu, host, normwise, rms_rel, to_dev, widen32
+
+pytestmark = pytest.mark.gpu
+
+
+def _cot(n, seed, phi):
+    g = ics.rng(seed)
+    c = np.zeros((n, 4))
+    c[:, :3] = g.standard_normal((n, 3))
+    if phi:
+        c[:, 3] = g.standard_normal(n)
+    return c
+
+
+@pytest.mark.parametrize("n", [1, 2, 65, 300, 1029])
+@pytest.mark.parametrize("phi", [False, True])
+def test_vjp_f64(orc, n, phi):
+    torch, nb = gpu()
+    pm, _ = ics.plummer(max(n, 2), 60 + n)
+    pm = pm[:n].copy()
+    pm[:, 3] *= np.linspace(0.5, 1.5, n)
+    cot = _cot(n, 61, phi)
+    pc, mc, ap = nb.accel_vjp(to_dev(torch, pm, torch.float64), to_dev(torch, cot, torch.float64), 0.03)
+    torch.cuda.synchronize()
+    xb, mb = orc.vjp(pm, 0.03, cot[:, :3], cot[:, 3] if phi else None)
+    if n == 1:
+        assert np.all(host(pc) == 0) and np.all(host(mc) == 0)
+        return
+    assert normwise(host(pc)[:, :3], xb) <= 1e-12
+    assert normwise(host(mc), mb) <= 1e-12
+    assert np.all(host(pc)[:, 3] == 0)
+    acc, pot = orc.accel(pm, 0.03)
+    assert rms_rel(host(ap)[:, :3], acc) <= 1e-12 and rms_rel(host(ap)[:, 3], pot) <= 1e-12
+
+
+@pytest.mark.parametrize("mode", ["F32_KAHAN", "F32_F64ACC", "F32"])
+def test_vjp_f32(orc, mode):
+    torch, nb = gpu()
+    n = 4000
+    pm, _ = ics.plummer(n, 62)
+    cot = _cot(n, 63, True)
+    pm32, cot32 = widen32(pm), widen32(cot)
+    pc, mc, ap = nb.accel_vjp(to_dev(torch, pm32, torch.float32), to_dev(torch, cot32, torch.float32), 0.01,
+                              prec=getattr(nb, mode))
+    torch.cuda.synchronize()
+    xb, mb = orc.vjp(pm32, 0.01, cot32[:, :3], cot32[:, 3])
+    assert normwise(host(pc)[:, :3], xb) <= 1e-5
+    assert normwise(host(mc), mb) <= 1e-5
+
+
+def test_vjp_invariants_on_gpu():
+    """Translation invariance (sum xbar = 0) and mass homogeneity
+    (sum m mbar = sum abar . a + phibar phi) of the GPU result."""
+    torch, nb = gpu()
+    n = 2000
+    pm, _ = ics.plummer(n, 64)
+    cot = _cot(n, 65, True)
+    pc, mc, ap = nb.accel_vjp(to_dev(torch, pm, torch.float64), to_dev(torch, cot, torch.float64), 0.02)
+    torch.cuda.synchronize()
+    pc, mc, ap = host(pc), host(mc), host(ap)
+    assert np.abs(pc[:, :3].sum(axis=0)).max() <= 1e-11 * np.abs(pc).sum()
+    lhs = (pm[:, 3] * mc).sum()
+    rhs = (cot[:, :3] * ap[:, :3]).sum() + (cot[:, 3] * ap[:, 3]).sum()
+    assert abs(lhs - rhs) <= 1e-11 * np.abs(pm[:, 3] * mc).sum()
+
+
+def test_trajectory_gradient_f64(orc):
+    torch, nb = gpu()
+    n, eps, dt, steps, C = 64, 0.05, 2e-3, 40, 10
+    pm, v = ics.plummer(n, 66)
+    pm[:, 3] *= np.linspace(0.5, 1.5, n)
+    y = ics.perturbed_snapshot(pm, 67, 0.05)
+    L, gx, gv, gm = orc.traj_grad(pm, v, y, eps, dt, steps)
+    p, vv = to_dev(torch, pm, torch.float64), to_dev(torch, v, torch.float64)
+    ck = nb.trajectory_forward(p, vv, eps, dt, steps, C)
+    xb = torch.zeros_like(p)
+    xb[:, :3] = 2 * (p[:, :3] - to_dev(torch, y, torch.float64))
+    vb = torch.zeros_like(p)
+    pc, vc, mc = nb.trajectory_adjoint(ck, eps, dt, steps, C, xb, vb)
+    torch.cuda.synchronize()
+    assert abs(float(((host(p)[:, :3] - y) ** 2).sum()) - L) <= 1e-12 * L
+    assert normwise(host(pc)[:, :3], gx) <= 1e-11
+    assert normwise(host(vc)[:, :3], gv) <= 1e-11
+    assert normwise(host(mc), gm) <= 1e-11
+
+
+def test_trajectory_gradient_f32_and_autograd(orc):
+    torch, nb = gpu()
+    n, eps, dt, steps, C = 1024, 0.01, 1e-3, 40, 20
+    pm, v = ics.plummer(n, 68)
+    y = ics.perturbed_snapshot(pm, 69)
+    pm32, v32 = widen32(pm), widen32(v)
+    L, gx, gv, gm = orc.traj_grad(pm32, v32, y, eps, dt, steps)
+    x0 = to_dev(torch, pm32[:, :3], torch.float32).requires_grad_(True)
+    v0 = to_dev(torch, v32[:, :3], torch.float32).requires_grad_(True)
+    m = to_dev(torch, pm32[:, 3], torch.float32).requires_grad_(True)
+    xT, vT = nb.NBodyTrajectory.apply(x0, v0, m, eps, dt, steps, C)
+    loss = ((xT - to_dev(torch, y, torch.float32)) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    print("f32 grad errors", normwise(host(x0.grad), gx), normwise(host(v0.grad), gv), normwise(host(m.grad), gm))
+    assert normwise(host(x0.grad), gx) <= 1e-4
+    assert normwise(host(v0.grad), gv) <= 1e-4
+    assert normwise(host(m.grad), gm) <= 1e-4
