@@ -50,6 +50,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-extras", action="store_true", help="skip adjoint, batched and CPU legs")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--counters", action="store_true",
+                    help="counter-collection mode: two force launches of the headline workload "
+                         "and one 1 GiB device copy (the copy calibrates byte counters); no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -74,6 +77,16 @@ def main():
     vel = torch.as_tensor(v_np, dtype=torch.float32).to(dev).contiguous()
     acc = torch.empty_like(pm)
     pm0_host = pm.cpu().double().numpy()
+
+    if args.counters:
+        for _ in range(2):
+            nb.accel(pm, eps, prec=prec, out=acc)
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] counters mode: 2 force launches, 1 GiB copy (1073741824 B read + written)")
+        return
 
     # first evaluation (step 0 forces, kept for the accuracy check)
     nb.accel(pm, eps, prec=prec, out=acc)
@@ -167,13 +180,15 @@ def adjoint_leg(torch, nb, ics, dev):
         nb.leapfrog_kdk(p, v, a, eps, dt, steps, prec=prec)
         return p
 
-    def fwd_adj():
-        p, v = p0.clone(), v0.clone()
-        ck = nb.trajectory_forward(p, v, eps, dt, steps, C, prec=prec)
-        xb = torch.zeros_like(p)
-        xb[:, :3] = 2 * (p[:, :3] - y)
-        vb = torch.zeros_like(p)
-        return nb.trajectory_adjoint(ck, eps, dt, steps, C, xb, vb, prec=prec)
+    def fwd_adj(scheme):
+        def run():
+            p, v = p0.clone(), v0.clone()
+            ck = nb.trajectory_forward(p, v, eps, dt, steps, C, prec=prec)
+            xb = torch.zeros_like(p)
+            xb[:, :3] = 2 * (p[:, :3] - y)
+            vb = torch.zeros_like(p)
+            return nb.trajectory_adjoint(ck, eps, dt, steps, C, xb, vb, prec=prec, scheme=scheme)
+        return run
 
     def timed(fn, reps=3):
         fn()
@@ -189,11 +204,15 @@ def adjoint_leg(torch, nb, ics, dev):
         return float(np.median(ts))
 
     t_plain = timed(plain)
-    t_fa = timed(fwd_adj)
-    log(f"[bench] adjoint: plain {t_plain:.1f} ms, fwd+adj {t_fa:.1f} ms, ratio {t_fa / t_plain:.2f}")
+    t_rev = timed(fwd_adj(nb.ADJ_REVERSE))
+    t_rec = timed(fwd_adj(nb.ADJ_RECOMPUTE))
+    log(f"[bench] adjoint: plain {t_plain:.1f} ms, fwd+adj reversal {t_rev:.1f} ms "
+        f"(ratio {t_rev / t_plain:.2f}), recompute {t_rec:.1f} ms (ratio {t_rec / t_plain:.2f})")
     return {"workload": "Plummer N=16384, F32_KAHAN, 200 steps dt=1e-3, checkpoints every 20",
-            "plain_forward_ms": round(t_plain, 3), "fwd_plus_adjoint_ms": round(t_fa, 3),
-            "ratio": round(t_fa / t_plain, 3), "scheme": "segment recompute from checkpoints"}
+            "plain_forward_ms": round(t_plain, 3),
+            "fwd_plus_adjoint_ms": round(t_rev, 3), "ratio": round(t_rev / t_plain, 3),
+            "scheme": "time reversal re-anchored at checkpoints (fused force+VJP)",
+            "recompute_scheme_ms": round(t_rec, 3), "recompute_scheme_ratio": round(t_rec / t_plain, 3)}
 
 
 def batched_leg(torch, nb, ics, dev):
@@ -227,16 +246,22 @@ def cpu_leg(ics, pm0_host, acc0, eps, seconds):
     import oracle
     n = pm0_host.shape[0]
     threads = oracle.num_threads()
-    cal = ics.sample_targets(n, 16, 7)
+    # chunks of sampled targets until about `seconds` of CPU work
+    order = ics.sample_targets(n, min(n, 65536), 1003)
+    ics.rng(1004).shuffle(order)
+    log(f"[bench] cpu oracle on {threads} threads for ~{seconds:.0f} s")
+    done, parts_a, parts_p = 0, [], []
     t0 = time.perf_counter()
-    oracle.accel(pm0_host, eps, targets=cal)
-    rate = 16 * n / (time.perf_counter() - t0)
-    k = int(max(32, min(1024, seconds * rate / n)))
-    tg = ics.sample_targets(n, k, 1003)
-    log(f"[bench] cpu oracle: {k} targets x {n} sources on {threads} threads")
-    t0 = time.perf_counter()
-    ref_a, ref_p = oracle.accel(pm0_host, eps, targets=tg)
+    while done < order.shape[0] and time.perf_counter() - t0 < seconds:
+        chunk = order[done:done + 512]
+        a, p = oracle.accel(pm0_host, eps, targets=chunk)
+        parts_a.append(a)
+        parts_p.append(p)
+        done += chunk.shape[0]
     secs = time.perf_counter() - t0
+    tg = order[:done]
+    ref_a, ref_p = np.concatenate(parts_a), np.concatenate(parts_p)
+    k = done
     gint = k * n / secs / 1e9
     da = np.linalg.norm(acc0[tg, :3] - ref_a, axis=1) / np.linalg.norm(ref_a, axis=1)
     dp = np.abs(acc0[tg, 3] - ref_p) / np.abs(ref_p)

@@ -180,17 +180,28 @@ int nbody_energy(const void *pos_mass, const void *vel, const void *acc_pot, int
  * nbody_trajectory_adjoint takes the cotangents (xbar_T, vbar_T) of the
  * final positions and velocities (records, w unused) and returns the
  * gradients with respect to the initial positions (pos_cot, record x,y,z),
- * velocities (vel_cot) and masses (mass_cot, float/double[n]).  It re-runs
- * each segment forward from its checkpoint and applies one fused force+VJP
- * per position.  xbar_T / vbar_T are read only.
+ * velocities (vel_cot) and masses (mass_cot, float/double[n]), applying one
+ * force VJP per position x_n with cotangent h vbar (first and last) or
+ * 2h vbar (interior).  The positions come from
+ *   NBODY_ADJ_RECOMPUTE: re-running each segment forward from its checkpoint
+ *                        (exactly the forward positions; one extra force
+ *                        evaluation per step), or
+ *   NBODY_ADJ_REVERSE:   running the leapfrog backwards from the end of each
+ *                        segment (x_n = x_{n+1} - dt v_{n+1/2}) with the force
+ *                        returned by the fused VJP kernel, re-anchored at every
+ *                        checkpoint (no extra force evaluation; positions
+ *                        differ from the forward ones by rounding).
+ * xbar_T / vbar_T are read only.
  */
 int nbody_trajectory_forward(void *pos_mass, void *vel, int64_t n, int32_t prec, double G,
                              double eps, double dt, int32_t nsteps, int32_t ckpt_every,
                              void *ckpt, void *stream);
+#define NBODY_ADJ_RECOMPUTE 0
+#define NBODY_ADJ_REVERSE 1
 int nbody_trajectory_adjoint(const void *ckpt, int64_t n, int32_t prec, double G, double eps,
                              double dt, int32_t nsteps, int32_t ckpt_every,
                              const void *xbar_T, const void *vbar_T, void *pos_cot,
-                             void *vel_cot, void *mass_cot, void *stream);
+                             void *vel_cot, void *mass_cot, int32_t scheme, void *stream);
 
 /*
  * Tuning.  nbody_autotune times the candidate kernel shapes for one problem

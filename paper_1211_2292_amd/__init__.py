@@ -20,13 +20,15 @@ import threading
 import torch
 
 __all__ = [
-    "F64", "F32", "F32_KAHAN", "F32_F64ACC", "ACC_VALID", "GRAPH", "ENERGY",
+    "F64", "F32", "F32_KAHAN", "F32_F64ACC", "ACC_VALID", "GRAPH", "ENERGY", "ADJ_RECOMPUTE",
+    "ADJ_REVERSE",
     "lib", "accel", "accel_vjp", "leapfrog_kdk", "kick_drift", "batched_accel", "energy", "orb_order",
     "permute", "trajectory_forward", "trajectory_adjoint", "NBodyTrajectory", "autotune",
     "set_tuning", "get_tuning", "release", "NBodyError",
 ]
 
 F64, F32, F32_KAHAN, F32_F64ACC = 0, 1, 2, 3
+ADJ_RECOMPUTE, ADJ_REVERSE = 0, 1
 ACC_VALID, GRAPH, ENERGY = 0x1, 0x2, 0x4
 KERNEL_ACCEL, KERNEL_BATCHED, KERNEL_VJP = 0, 1, 2
 
@@ -52,7 +54,7 @@ _SIGS = {
     "nbody_energy": [_vp, _vp, _vp, _i64, _i32, _vp, _vp],
     "nbody_trajectory_forward": [_vp, _vp, _i64, _i32, _dbl, _dbl, _dbl, _i32, _i32, _vp, _vp],
     "nbody_trajectory_adjoint": [_vp, _i64, _i32, _dbl, _dbl, _dbl, _i32, _i32, _vp, _vp, _vp,
-                                 _vp, _vp, _vp],
+                                 _vp, _vp, _i32, _vp],
     "nbody_autotune": [_i32, _i32, _i64, _vp, _i32, _vp],
     "nbody_set_tuning": [_i32, _i32, _i32, _i32, _i32],
     "nbody_get_tuning": [_i32, _i32, _i64, _vp, _vp, _vp],
@@ -263,9 +265,12 @@ def trajectory_forward(pos_mass, vel, eps, dt, nsteps, ckpt_every, G=1.0, prec=N
     return ck
 
 
-def trajectory_adjoint(ckpt, eps, dt, nsteps, ckpt_every, xbar_T, vbar_T, G=1.0, prec=None):
+def trajectory_adjoint(ckpt, eps, dt, nsteps, ckpt_every, xbar_T, vbar_T, G=1.0, prec=None,
+                       scheme=ADJ_REVERSE):
     """(pos_cot (N,4), vel_cot (N,4), mass_cot (N,)) = gradients at the
-    initial state for final-state cotangents (xbar_T, vbar_T)."""
+    initial state for final-state cotangents (xbar_T, vbar_T).  scheme:
+    ADJ_RECOMPUTE (segments re-run from checkpoints) or ADJ_REVERSE
+    (time reversal from each checkpoint, no extra force evaluations)."""
     xb = _rec(xbar_T, "xbar_T")
     vb = _rec(vbar_T, "vbar_T", xb.dtype)
     if ckpt.dtype != xb.dtype or not ckpt.is_contiguous() or ckpt.device != xb.device:
@@ -277,7 +282,7 @@ def trajectory_adjoint(ckpt, eps, dt, nsteps, ckpt_every, xbar_T, vbar_T, G=1.0,
     mc = torch.empty(n, dtype=xb.dtype, device=xb.device)
     _check(lib().nbody_trajectory_adjoint(_ptr(ckpt), n, p, float(G), float(eps), float(dt), int(nsteps),
                                           int(ckpt_every), _ptr(xb), _ptr(vb), _ptr(pc), _ptr(vc),
-                                          _ptr(mc), _stream()))
+                                          _ptr(mc), int(scheme), _stream()))
     return pc, vc, mc
 
 
@@ -289,7 +294,8 @@ class NBodyTrajectory(torch.autograd.Function):
     Returns (x_T (N, 3), v_T (N, 3))."""
 
     @staticmethod
-    def forward(ctx, x0, v0, m, eps, dt, nsteps, ckpt_every=20, G=1.0, prec=None):
+    def forward(ctx, x0, v0, m, eps, dt, nsteps, ckpt_every=20, G=1.0, prec=None,
+                scheme=ADJ_REVERSE):
         n = x0.shape[0]
         pm = torch.empty((n, 4), dtype=x0.dtype, device=x0.device)
         pm[:, :3] = x0.detach()
@@ -298,13 +304,13 @@ class NBodyTrajectory(torch.autograd.Function):
         vel[:, :3] = v0.detach()
         ck = trajectory_forward(pm, vel, eps, dt, nsteps, ckpt_every, G, prec)
         ctx.save_for_backward(ck)
-        ctx.args = (eps, dt, nsteps, ckpt_every, G, prec)
+        ctx.args = (eps, dt, nsteps, ckpt_every, G, prec, scheme)
         return pm[:, :3].clone(), vel[:, :3].clone()
 
     @staticmethod
     def backward(ctx, gx, gv):
         (ck,) = ctx.saved_tensors
-        eps, dt, nsteps, ckpt_every, G, prec = ctx.args
+        eps, dt, nsteps, ckpt_every, G, prec, scheme = ctx.args
         n = ck.shape[2]
         xb = torch.zeros((n, 4), dtype=ck.dtype, device=ck.device)
         vb = torch.zeros((n, 4), dtype=ck.dtype, device=ck.device)
@@ -312,8 +318,8 @@ class NBodyTrajectory(torch.autograd.Function):
             xb[:, :3] = gx
         if gv is not None:
             vb[:, :3] = gv
-        pc, vc, mc = trajectory_adjoint(ck, eps, dt, nsteps, ckpt_every, xb, vb, G, prec)
-        return pc[:, :3], vc[:, :3], mc, None, None, None, None, None, None
+        pc, vc, mc = trajectory_adjoint(ck, eps, dt, nsteps, ckpt_every, xb, vb, G, prec, scheme)
+        return pc[:, :3], vc[:, :3], mc, None, None, None, None, None, None, None
 
 
 def autotune(kernel, prec, n, offsets=None):

@@ -12,8 +12,12 @@
 //   load into SGPRs and feeds the VALU directly as the one scalar operand an
 //   instruction may take: no LDS staging, no barriers, and the 16-byte source
 //   record is fetched once per wave for 64*TPL interactions.
-// * Pair arithmetic (FP32 modes): 3 sub, 3 FMA, 1 v_rsq_f32, 3 mul, 1 add,
-//   3 FMA = 14 VALU instructions = 20 flop by the usual count.
+// * Pair arithmetic (FP32 modes): 3 sub, 3 FMA, 1 v_rsq_f32, 2 mul, 1 mul,
+//   1 FMA (potential), 3 FMA = 14 VALU instructions = 20 flop by the usual
+//   count.  The library is built with contraction off and every fused
+//   multiply-add is written out, so the same arithmetic is emitted in every
+//   kernel that shares these routines (batched results equal standalone ones
+//   bit for bit).
 // * Sources are processed in tiles of `jtile`; the FP32 partial sum of a tile
 //   is folded into the running per-target sum by the precision mode (plain
 //   FP32, Kahan-compensated FP32, or FP64).  Pure FP32 mode keeps a single
@@ -97,7 +101,7 @@ __device__ __forceinline__ void pair_f32(const float4 b, const int j, const Targ
         if (MASK) rho = (j == T.i[t]) ? 0.0f : rho;
         const float mr = b.w * rho;
         const float s = mr * (rho * rho);
-        S.ph[t] += mr;
+        S.ph[t] = __builtin_fmaf(b.w, rho, S.ph[t]);
         S.ax[t] = __builtin_fmaf(s, dx, S.ax[t]);
         S.ay[t] = __builtin_fmaf(s, dy, S.ay[t]);
         S.az[t] = __builtin_fmaf(s, dz, S.az[t]);
@@ -217,7 +221,7 @@ __device__ __forceinline__ void pair_f64(const double4 b, const int j, const Tar
         if (MASK) rho = (j == T.i[t]) ? 0.0 : rho;
         const double mr = b.w * rho;
         const double s = mr * (rho * rho);
-        S.ph[t] += mr;
+        S.ph[t] = __builtin_fma(b.w, rho, S.ph[t]);
         S.ax[t] = __builtin_fma(s, dx, S.ax[t]);
         S.ay[t] = __builtin_fma(s, dy, S.ay[t]);
         S.az[t] = __builtin_fma(s, dz, S.az[t]);

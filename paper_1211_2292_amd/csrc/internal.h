@@ -43,14 +43,16 @@ hipError_t launch_batched(int prec, const void *pm, const int64_t *offsets, cons
                           const Tune &t, unsigned *counter, int grid, hipStream_t s);
 
 // ---- fused force + VJP (vjp.hip) -------------------------------------------
+// partial: scratch of vjp_partial_bytes(n, t) when t.jsplit > 1.
 hipError_t launch_vjp(int prec, const void *pm, const void *cot, int n, double G, double eps,
-                      void *pos_cot, void *mass_cot, void *acc_out, const Tune &t,
+                      void *pos_cot, void *mass_cot, void *acc_out, const Tune &t, void *partial,
                       hipStream_t s);
 // scale multiplies the cotangent; accumulate adds into pos_cot/mass_cot;
 // phi = false ignores the phibar component of the cotangent records.
 hipError_t launch_vjp_ex(int prec, const void *pm, const void *cot, int n, double G, double eps,
                          bool phi, double scale, bool accumulate, void *pos_cot, void *mass_cot,
-                         void *acc_out, const Tune &t, hipStream_t s);
+                         void *acc_out, const Tune &t, void *partial, hipStream_t s);
+size_t vjp_partial_bytes(int n, const Tune &t);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
 
 // ---- elementwise steps (step.hip) ------------------------------------------
@@ -66,6 +68,9 @@ hipError_t launch_permute(const void *src, void *dst, const int32_t *perm, int n
                           bool inverse, hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 
+// Reverse leapfrog step by time reversal plus vbar += dt xbar (vjp.hip).
+hipError_t launch_reverse_step(int prec, void *x, void *vh, const void *acc, const void *xbar,
+                               void *vbar, int n, double hk, double dt, hipStream_t s);
 // Adjoint of one leapfrog step pair, elementwise (vjp.hip).
 hipError_t launch_adj_axpy(int prec, void *y, const void *x, double a, int n, hipStream_t s);
 

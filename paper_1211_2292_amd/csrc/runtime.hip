@@ -186,12 +186,10 @@ static Tune default_tune(int kernel, int prec, int64_t n)
 {
     Tune t;
     t.jtile = 512;
-    if (kernel == 2) {  // VJP: heavier pair, more registers
+    if (kernel == 2)  // VJP: heavier pair, more registers
         t.tpl = 1;
-        t.jsplit = 1;
-        return t;
-    }
-    t.tpl = (prec == NBODY_F64) ? 1 : (n >= (1 << 17) ? 2 : 1);
+    else
+        t.tpl = (prec == NBODY_F64) ? 1 : (n >= (1 << 17) ? 2 : 1);
     if (kernel == 1) {
         t.jsplit = 1;
         return t;
@@ -436,7 +434,7 @@ int nbody_accel(const void *pos_mass, int64_t n, int32_t prec, double G, double 
     }
     NB_CHECK(check_scalars(G, eps));
     NB_CHECK(check_vec(pos_mass, prec, "pos_mass"));
-    NB_CHECK(check_vec(acc_pot_out, prec, "acc_pot_out"));
+    NB_CHECK(check_vec(acc_pot_out, prec, "acc_pot_out", target_count == 0));
     if (target_begin < 0 || target_count < 0 || target_begin + target_count > n) {
         set_error("targets [%lld, %lld) outside [0, %lld)", (long long)target_begin,
                   (long long)(target_begin + target_count), (long long)n);
@@ -514,8 +512,16 @@ int nbody_accel_vjp(const void *pos_mass, const void *acc_pot_cot, int64_t n, in
         }
     }
     Tune t = lookup_tune(2, prec, n);
+    void *partial = nullptr;
+    if (const size_t pb = vjp_partial_bytes((int)n, t)) {
+        partial = scratch(kSlotPartial, pb);
+        if (!partial) {
+            set_error("cannot allocate %zu bytes of split scratch", pb);
+            return NBODY_E_NOMEM;
+        }
+    }
     NB_TRY(launch_vjp(prec, pos_mass, acc_pot_cot, (int)n, G, eps, pos_cot_out, mass_cot_out,
-                      acc_pot_out, t, (hipStream_t)stream),
+                      acc_pot_out, t, partial, (hipStream_t)stream),
            "vjp kernel");
     return NBODY_OK;
 }
@@ -773,8 +779,12 @@ int nbody_trajectory_forward(void *pos_mass, void *vel, int64_t n, int32_t prec,
 int nbody_trajectory_adjoint(const void *ckpt, int64_t n, int32_t prec, double G, double eps,
                              double dt, int32_t nsteps, int32_t ckpt_every, const void *xbar_T,
                              const void *vbar_T, void *pos_cot, void *vel_cot, void *mass_cot,
-                             void *stream)
+                             int32_t scheme, void *stream)
 {
+    if (scheme != NBODY_ADJ_RECOMPUTE && scheme != NBODY_ADJ_REVERSE) {
+        set_error("bad adjoint scheme %d", scheme);
+        return NBODY_E_INVAL;
+    }
     NB_CHECK(check_n(n));
     if (!prec_ok(prec) || nsteps < 0 || ckpt_every < 1 || nsteps % ckpt_every) {
         set_error("bad precision, nsteps or ckpt_every (nsteps must be a multiple)");
@@ -805,6 +815,14 @@ int nbody_trajectory_adjoint(const void *ckpt, int64_t n, int32_t prec, double G
     const double h = 0.5 * dt;
     const int ni = (int)n;
     Tune vt_tune = lookup_tune(2, prec, n);
+    void *vpart = nullptr;
+    if (const size_t pb = vjp_partial_bytes(ni, vt_tune)) {
+        vpart = scratch(kSlotAdj3, pb);
+        if (!vpart) {
+            set_error("cannot allocate adjoint split scratch");
+            return NBODY_E_NOMEM;
+        }
+    }
     NB_TRY(launch_copy(pos_cot, xbar_T, rb, s), "adjoint init");
     NB_TRY(launch_copy(vel_cot, vbar_T, rb, s), "adjoint init");
     NB_TRY(launch_fill_zero(mass_cot, mb * (size_t)n, s), "adjoint init");
@@ -813,6 +831,32 @@ int nbody_trajectory_adjoint(const void *ckpt, int64_t n, int32_t prec, double G
     // 2h vbar in the interior, h vbar at the last step and at x_0.
     bool first = true;
     const char *ck = (const char *)ckpt;
+    if (scheme == NBODY_ADJ_REVERSE) {
+        // Positions are rebuilt backwards by time reversal of the leapfrog,
+        // re-anchored at every checkpoint; the fused kernel returns the force
+        // that the reversal needs, so no force is evaluated twice.
+        char *xc = xs;  // one slot of the segment buffer: current position
+        for (int c = nseg - 1; c >= 0; --c) {
+            const char *end = ck + (size_t)(c + 1) * 2 * rb;
+            NB_TRY(launch_copy(xc, end, rb, s), "segment copy");
+            NB_TRY(launch_copy(vt, end + rb, rb, s), "segment copy");
+            for (int k = C - 1; k >= 0; --k) {
+                const double scale = first ? h : 2.0 * h;
+                first = false;
+                NB_TRY(launch_vjp_ex(prec, xc, vel_cot, ni, G, eps, false, scale, true, pos_cot,
+                                     mass_cot, acc, vt_tune, vpart, s),
+                       "adjoint vjp");
+                NB_TRY(launch_reverse_step(prec, xc, vt, acc, pos_cot, vel_cot, ni,
+                                           k == C - 1 ? h : 2.0 * h, dt, s),
+                       "reverse step");
+            }
+        }
+        if (nsteps > 0)
+            NB_TRY(launch_vjp_ex(prec, ck, vel_cot, ni, G, eps, false, h, true, pos_cot, mass_cot,
+                                 nullptr, vt_tune, vpart, s),
+                   "adjoint vjp");
+        return NBODY_OK;
+    }
     for (int c = nseg - 1; c >= 0; --c) {
         // recompute positions of the segment from its checkpoint
         const char *slot = ck + (size_t)c * 2 * rb;
@@ -830,13 +874,13 @@ int nbody_trajectory_adjoint(const void *ckpt, int64_t n, int32_t prec, double G
             const double scale = first ? h : 2.0 * h;
             first = false;
             NB_TRY(launch_vjp_ex(prec, xs + (size_t)(k + 1) * rb, vel_cot, ni, G, eps, false, scale,
-                                 true, pos_cot, mass_cot, nullptr, vt_tune, s),
+                                 true, pos_cot, mass_cot, nullptr, vt_tune, vpart, s),
                    "adjoint vjp");
             NB_TRY(launch_adj_axpy(prec, vel_cot, pos_cot, dt, ni, s), "adjoint axpy");
         }
         if (c == 0 && nsteps > 0)
             NB_TRY(launch_vjp_ex(prec, xs, vel_cot, ni, G, eps, false, h, true, pos_cot, mass_cot,
-                                 nullptr, vt_tune, s),
+                                 nullptr, vt_tune, vpart, s),
                    "adjoint vjp");
     }
     return NBODY_OK;
@@ -858,7 +902,7 @@ int nbody_set_tuning(int32_t kernel, int32_t prec, int32_t tpl, int32_t jsplit, 
     t.tpl = tpl;
     t.jsplit = jsplit;
     t.jtile = jtile;
-    if (!tune_valid(t) || (prec == NBODY_F64 && tpl == 4) || (kernel != 0 && jsplit != 1) ||
+    if (!tune_valid(t) || (prec == NBODY_F64 && tpl == 4) || (kernel == 1 && jsplit != 1) ||
         (kernel == 2 && tpl == 4)) {
         set_error("unsupported tuning (tpl %d, jsplit %d, jtile %d)", tpl, jsplit, jtile);
         return NBODY_E_INVAL;
@@ -950,7 +994,7 @@ extern "C" int nbody_autotune(int32_t kernel, int32_t prec, int64_t n, const int
     for (int tp : tpls) {
         if ((prec == NBODY_F64 || kernel == 2) && tp == 4) continue;
         for (int jt : jts) {
-            if (kernel == 0) {
+            if (kernel == 0 || kernel == 2) {
                 for (int js = 1; js <= 32; js *= 2) {
                     if (js > 1 && n / js < 512) break;
                     const int64_t waves = (n + 64 * tp - 1) / (64 * tp);
@@ -979,8 +1023,8 @@ extern "C" int nbody_autotune(int32_t kernel, int32_t prec, int64_t n, const int
     const int reps = n >= (1 << 19) ? 1 : 3;
     for (const Tune &t : cands) {
         void *partial = nullptr;
-        if (kernel == 0) {
-            const size_t pb = accel_partial_bytes(prec, (int)n, t);
+        if (kernel == 0 || kernel == 2) {
+            const size_t pb = kernel == 0 ? accel_partial_bytes(prec, (int)n, t) : vjp_partial_bytes((int)n, t);
             if (pb && !(partial = scratch(kSlotPartial, pb))) continue;
         } else if (kernel == 1) {
             if (get_plan(offsets_host, nsys, t, &plan) != NBODY_OK) continue;
@@ -990,7 +1034,7 @@ extern "C" int nbody_autotune(int32_t kernel, int32_t prec, int64_t n, const int
             if (kernel == 1)
                 return launch_batched(prec, pm, plan->d_off, plan->d_units, plan->nunits, 1.0, nullptr,
                                       0.01, out, t, plan->d_counter, plan->grid, s);
-            return launch_vjp(prec, pm, cot, (int)n, 1.0, 0.01, out, mc, nullptr, t, s);
+            return launch_vjp(prec, pm, cot, (int)n, 1.0, 0.01, out, mc, nullptr, t, partial, s);
         };
         if (run() != hipSuccess) continue;  // warm-up
         std::vector<float> ms;

@@ -148,17 +148,55 @@ __device__ __forceinline__ void vflatten(const VAcc<T, TPL, PHI> &S, int t, T (&
     f[15] = 0; f[16] = 0;
 }
 
+// Output of one target: xbar (3), mbar, a (3), phi, all linear in the sums,
+// so per-split values add up to the full result.
+__device__ __forceinline__ void apply_out(double (&o)[8], double scale, int accumulate, int i,
+                                          float4 *pos_cot, float *mass_cot, float4 *acc_out)
+{
+    double gx = o[0] * scale, gy = o[1] * scale, gz = o[2] * scale, gm = o[3] * scale;
+    if (accumulate) {
+        const float4 p = pos_cot[i];
+        gx += (double)p.x;
+        gy += (double)p.y;
+        gz += (double)p.z;
+        gm += (double)mass_cot[i];
+    }
+    pos_cot[i] = make_float4((float)gx, (float)gy, (float)gz, 0.0f);
+    mass_cot[i] = (float)gm;
+    if (acc_out) acc_out[i] = make_float4((float)o[4], (float)o[5], (float)o[6], (float)o[7]);
+}
+__device__ __forceinline__ void apply_out(double (&o)[8], double scale, int accumulate, int i,
+                                          double4 *pos_cot, double *mass_cot, double4 *acc_out)
+{
+    double gx = o[0] * scale, gy = o[1] * scale, gz = o[2] * scale, gm = o[3] * scale;
+    if (accumulate) {
+        const double4 p = pos_cot[i];
+        gx += p.x;
+        gy += p.y;
+        gz += p.z;
+        gm += mass_cot[i];
+    }
+    pos_cot[i] = make_double4(gx, gy, gz, 0.0);
+    mass_cot[i] = gm;
+    if (acc_out) acc_out[i] = make_double4(o[4], o[5], o[6], o[7]);
+}
+
 template <typename T, typename V, typename MT, int TPL, bool PHI>
 __global__ __launch_bounds__(kBlock) void k_vjp(const V *__restrict__ pm, const V *__restrict__ cot,
                                                 int n, T eps2, double G, int jtile, double scale,
                                                 int accumulate, V *__restrict__ pos_cot,
-                                                MT *__restrict__ mass_cot, V *__restrict__ acc_out)
+                                                MT *__restrict__ mass_cot, V *__restrict__ acc_out,
+                                                double4 *__restrict__ partial)
 {
     constexpr int WT = 64 * TPL;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int t0 = (blockIdx.x * (kBlock / 64) + wave) * WT;
     if (t0 >= n) return;
+    // source range of this split
+    const long per = ((long)n + gridDim.y - 1) / gridDim.y;
+    const int jb = (int)min((long)n, (long)blockIdx.y * per);
+    const int je = (int)min((long)n, (long)jb + per);
     VTgt<T, TPL> K;
 #pragma unroll
     for (int t = 0; t < TPL; ++t) {
@@ -179,8 +217,8 @@ __global__ __launch_bounds__(kBlock) void k_vjp(const V *__restrict__ pm, const 
 #pragma unroll
         for (int c = 0; c < kVN; ++c) R[t][c] = 0.0;
     VAcc<T, TPL, PHI> S;
-    for (int jc = 0; jc < n; jc += jtile) {
-        const int ce = min(jc + jtile, n);
+    for (int jc = jb; jc < je; jc += jtile) {
+        const int ce = min(jc + jtile, je);
         const int lo = min(max(d0, jc), ce);
         const int hi = min(max(d1, jc), ce);
         S.zero();
@@ -201,38 +239,49 @@ __global__ __launch_bounds__(kBlock) void k_vjp(const V *__restrict__ pm, const 
         if (i >= n) continue;
         const double mk = K.m[t];
         const double pbk = PHI ? (double)K.pb[t] : 0.0;
-        const double ax = G * R[t][7], ay = G * R[t][8], az = G * R[t][9];
-        double gx = G * (R[t][0] - 3.0 * R[t][3]);
-        double gy = G * (R[t][1] - 3.0 * R[t][4]);
-        double gz = G * (R[t][2] - 3.0 * R[t][5]);
-        double gm = -G * R[t][6];
+        double o[8];
+        o[4] = G * R[t][7];
+        o[5] = G * R[t][8];
+        o[6] = G * R[t][9];
+        o[7] = -G * R[t][10];
+        o[0] = G * (R[t][0] - 3.0 * R[t][3]);
+        o[1] = G * (R[t][1] - 3.0 * R[t][4]);
+        o[2] = G * (R[t][2] - 3.0 * R[t][5]);
+        o[3] = -G * R[t][6];
         if (PHI) {
-            gx += -G * mk * R[t][11] - pbk * ax;
-            gy += -G * mk * R[t][12] - pbk * ay;
-            gz += -G * mk * R[t][13] - pbk * az;
-            gm += -G * R[t][14];
+            o[0] += -G * mk * R[t][11] - pbk * o[4];
+            o[1] += -G * mk * R[t][12] - pbk * o[5];
+            o[2] += -G * mk * R[t][13] - pbk * o[6];
+            o[3] += -G * R[t][14];
         }
-        gx *= scale;
-        gy *= scale;
-        gz *= scale;
-        gm *= scale;
-        if (accumulate) {
-            const V o = pos_cot[i];
-            gx += (double)o.x;
-            gy += (double)o.y;
-            gz += (double)o.z;
-            gm += (double)mass_cot[i];
-        }
-        V g;
-        g.x = (T)gx; g.y = (T)gy; g.z = (T)gz; g.w = (T)0;
-        pos_cot[i] = g;
-        mass_cot[i] = (MT)gm;
-        if (acc_out) {
-            V a;
-            a.x = (T)ax; a.y = (T)ay; a.z = (T)az; a.w = (T)(-G * R[t][10]);
-            acc_out[i] = a;
+        if (gridDim.y == 1) {
+            apply_out(o, scale, accumulate, i, pos_cot, mass_cot, acc_out);
+        } else {
+            double4 *dst = partial + 2 * ((long)blockIdx.y * n + i);
+            dst[0] = make_double4(o[0], o[1], o[2], o[3]);
+            dst[1] = make_double4(o[4], o[5], o[6], o[7]);
         }
     }
+}
+
+// Fixed-order sum of the per-split records, then the same output step.
+template <typename V, typename MT>
+__global__ __launch_bounds__(kBlock) void k_vjp_reduce(const double4 *__restrict__ partial, int js,
+                                                       int n, double scale, int accumulate,
+                                                       V *__restrict__ pos_cot,
+                                                       MT *__restrict__ mass_cot,
+                                                       V *__restrict__ acc_out)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double o[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int s = 0; s < js; ++s) {
+        const double4 *src = partial + 2 * ((long)s * n + i);
+        const double4 a = src[0], b = src[1];
+        o[0] += a.x; o[1] += a.y; o[2] += a.z; o[3] += a.w;
+        o[4] += b.x; o[5] += b.y; o[6] += b.z; o[7] += b.w;
+    }
+    apply_out(o, scale, accumulate, i, pos_cot, mass_cot, acc_out);
 }
 
 template <typename V, typename S>
@@ -249,50 +298,107 @@ __global__ __launch_bounds__(kBlock) void k_axpy(V *__restrict__ y, const V *__r
     y[i] = v;
 }
 
+// One reverse step of the leapfrog by exact time reversal (scheme used by
+// the reversal adjoint):  given x_{s+1}, the force a_{s+1} and either the
+// synchronised velocity v_{s+1} (first step of a segment) or v_{s+3/2},
+//   v_{s+1/2} = v_{s+1} - h a_{s+1}   or   v_{s+3/2} - 2h a_{s+1}
+//   x_s       = x_{s+1} - dt v_{s+1/2}
+// and the adjoint of the drift, vbar += dt xbar.
+template <typename V, typename S>
+__global__ __launch_bounds__(kBlock) void k_reverse(V *__restrict__ x, V *__restrict__ vh,
+                                                    const V *__restrict__ acc,
+                                                    const V *__restrict__ xbar,
+                                                    V *__restrict__ vbar, int n, S hk, S dt)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    V p = x[i], v = vh[i], w = vbar[i];
+    const V a = acc[i], g = xbar[i];
+    v.x = v.x - hk * a.x;
+    v.y = v.y - hk * a.y;
+    v.z = v.z - hk * a.z;
+    p.x = p.x - dt * v.x;
+    p.y = p.y - dt * v.y;
+    p.z = p.z - dt * v.z;
+    w.x = w.x + dt * g.x;
+    w.y = w.y + dt * g.y;
+    w.z = w.z + dt * g.z;
+    x[i] = p;
+    vh[i] = v;
+    vbar[i] = w;
+}
+
 template <typename T, typename V, typename MT, int TPL>
-hipError_t go_vjp(const void *pm, const void *cot, int n, T eps2, double G, int jtile, double scale,
+hipError_t go_vjp(const void *pm, const void *cot, int n, T eps2, double G, const Tune &t, double scale,
                   int accumulate, bool phi, void *pos_cot, void *mass_cot, void *acc_out,
-                  hipStream_t s)
+                  void *partial, hipStream_t s)
 {
     const int per_block = (kBlock / 64) * 64 * TPL;
-    const dim3 grid((n + per_block - 1) / per_block);
+    const dim3 grid((n + per_block - 1) / per_block, t.jsplit);
     if (phi)
         hipLaunchKernelGGL((k_vjp<T, V, MT, TPL, true>), grid, dim3(kBlock), 0, s, (const V *)pm,
-                           (const V *)cot, n, eps2, G, jtile, scale, accumulate, (V *)pos_cot,
-                           (MT *)mass_cot, (V *)acc_out);
+                           (const V *)cot, n, eps2, G, t.jtile, scale, accumulate, (V *)pos_cot,
+                           (MT *)mass_cot, (V *)acc_out, (double4 *)partial);
     else
         hipLaunchKernelGGL((k_vjp<T, V, MT, TPL, false>), grid, dim3(kBlock), 0, s, (const V *)pm,
-                           (const V *)cot, n, eps2, G, jtile, scale, accumulate, (V *)pos_cot,
-                           (MT *)mass_cot, (V *)acc_out);
+                           (const V *)cot, n, eps2, G, t.jtile, scale, accumulate, (V *)pos_cot,
+                           (MT *)mass_cot, (V *)acc_out, (double4 *)partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || t.jsplit == 1) return e;
+    hipLaunchKernelGGL((k_vjp_reduce<V, MT>), dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                       (const double4 *)partial, t.jsplit, n, scale, accumulate, (V *)pos_cot,
+                       (MT *)mass_cot, (V *)acc_out);
     return hipGetLastError();
 }
 
 }  // namespace
 
+size_t vjp_partial_bytes(int n, const Tune &t)
+{
+    return t.jsplit > 1 ? 2 * sizeof(double4) * (size_t)t.jsplit * (size_t)n : 0;
+}
+
 // Internal entry with scale/accumulate, used by the trajectory adjoint.
 hipError_t launch_vjp_ex(int prec, const void *pm, const void *cot, int n, double G, double eps,
                          bool phi, double scale, bool accumulate, void *pos_cot, void *mass_cot,
-                         void *acc_out, const Tune &t, hipStream_t s)
+                         void *acc_out, const Tune &t, void *partial, hipStream_t s)
 {
     if (prec == NBODY_F64) {
         if (t.tpl == 1)
-            return go_vjp<double, double4, double, 1>(pm, cot, n, eps * eps, G, t.jtile, scale,
-                                                      accumulate, phi, pos_cot, mass_cot, acc_out, s);
-        return go_vjp<double, double4, double, 2>(pm, cot, n, eps * eps, G, t.jtile, scale,
-                                                  accumulate, phi, pos_cot, mass_cot, acc_out, s);
+            return go_vjp<double, double4, double, 1>(pm, cot, n, eps * eps, G, t, scale, accumulate,
+                                                      phi, pos_cot, mass_cot, acc_out, partial, s);
+        return go_vjp<double, double4, double, 2>(pm, cot, n, eps * eps, G, t, scale, accumulate, phi,
+                                                  pos_cot, mass_cot, acc_out, partial, s);
     }
     const float e2 = (float)(eps * eps);
     if (t.tpl == 1)
-        return go_vjp<float, float4, float, 1>(pm, cot, n, e2, G, t.jtile, scale, accumulate, phi,
-                                               pos_cot, mass_cot, acc_out, s);
-    return go_vjp<float, float4, float, 2>(pm, cot, n, e2, G, t.jtile, scale, accumulate, phi,
-                                           pos_cot, mass_cot, acc_out, s);
+        return go_vjp<float, float4, float, 1>(pm, cot, n, e2, G, t, scale, accumulate, phi, pos_cot,
+                                               mass_cot, acc_out, partial, s);
+    return go_vjp<float, float4, float, 2>(pm, cot, n, e2, G, t, scale, accumulate, phi, pos_cot,
+                                           mass_cot, acc_out, partial, s);
 }
 
 hipError_t launch_vjp(int prec, const void *pm, const void *cot, int n, double G, double eps,
-                      void *pos_cot, void *mass_cot, void *acc_out, const Tune &t, hipStream_t s)
+                      void *pos_cot, void *mass_cot, void *acc_out, const Tune &t, void *partial,
+                      hipStream_t s)
 {
-    return launch_vjp_ex(prec, pm, cot, n, G, eps, true, 1.0, false, pos_cot, mass_cot, acc_out, t, s);
+    return launch_vjp_ex(prec, pm, cot, n, G, eps, true, 1.0, false, pos_cot, mass_cot, acc_out, t,
+                         partial, s);
+}
+
+hipError_t launch_reverse_step(int prec, void *x, void *vh, const void *acc, const void *xbar,
+                               void *vbar, int n, double hk, double dt, hipStream_t s)
+{
+    const dim3 grid((n + kBlock - 1) / kBlock);
+    if (prec == NBODY_F64)
+        hipLaunchKernelGGL((k_reverse<double4, double>), grid, dim3(kBlock), 0, s, (double4 *)x,
+                           (double4 *)vh, (const double4 *)acc, (const double4 *)xbar,
+                           (double4 *)vbar, n, hk, dt);
+    else
+        hipLaunchKernelGGL((k_reverse<float4, float>), grid, dim3(kBlock), 0, s, (float4 *)x,
+                           (float4 *)vh, (const float4 *)acc, (const float4 *)xbar, (float4 *)vbar,
+                           n, (float)hk, (float)dt);
+    return hipGetLastError();
 }
 
 hipError_t launch_adj_axpy(int prec, void *y, const void *x, double a, int n, hipStream_t s)

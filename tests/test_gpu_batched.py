@@ -34,13 +34,13 @@ def test_batched_equals_standalone_bitwise(orc, mode, tpl):
     nb.set_tuning(1, prec, tpl, 1, 256)
     try:
         p = to_dev(torch, pm, dtype)
-        out = nb.batched_accel(p, off, 0.01)
-        out2 = nb.batched_accel(p, off, 0.01)  # counters reset by the kernel itself
+        out = nb.batched_accel(p, off, 0.01, prec=prec)
+        out2 = nb.batched_accel(p, off, 0.01, prec=prec)  # counters reset by the kernel itself
         torch.cuda.synchronize()
         assert torch.equal(out, out2)
         for s in range(len(SIZES)):
             a, b = off[s], off[s + 1]
-            ref = nb.accel(p[a:b].contiguous(), 0.01)
+            ref = nb.accel(p[a:b].contiguous(), 0.01, prec=prec)
             torch.cuda.synchronize()
             assert torch.equal(out[a:b], ref), s
     finally:

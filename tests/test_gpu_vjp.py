@@ -71,7 +71,8 @@ def test_vjp_invariants_on_gpu():
     assert abs(lhs - rhs) <= 1e-11 * np.abs(pm[:, 3] * mc).sum()
 
 
-def test_trajectory_gradient_f64(orc):
+@pytest.mark.parametrize("scheme", ["ADJ_RECOMPUTE", "ADJ_REVERSE"])
+def test_trajectory_gradient_f64(orc, scheme):
     torch, nb = gpu()
     n, eps, dt, steps, C = 64, 0.05, 2e-3, 40, 10
     pm, v = ics.plummer(n, 66)
@@ -83,7 +84,7 @@ def test_trajectory_gradient_f64(orc):
     xb = torch.zeros_like(p)
     xb[:, :3] = 2 * (p[:, :3] - to_dev(torch, y, torch.float64))
     vb = torch.zeros_like(p)
-    pc, vc, mc = nb.trajectory_adjoint(ck, eps, dt, steps, C, xb, vb)
+    pc, vc, mc = nb.trajectory_adjoint(ck, eps, dt, steps, C, xb, vb, scheme=getattr(nb, scheme))
     torch.cuda.synchronize()
     assert abs(float(((host(p)[:, :3] - y) ** 2).sum()) - L) <= 1e-12 * L
     assert normwise(host(pc)[:, :3], gx) <= 1e-11
@@ -91,7 +92,8 @@ def test_trajectory_gradient_f64(orc):
     assert normwise(host(mc), gm) <= 1e-11
 
 
-def test_trajectory_gradient_f32_and_autograd(orc):
+@pytest.mark.parametrize("scheme", ["ADJ_RECOMPUTE", "ADJ_REVERSE"])
+def test_trajectory_gradient_f32_and_autograd(orc, scheme):
     torch, nb = gpu()
     n, eps, dt, steps, C = 1024, 0.01, 1e-3, 40, 20
     pm, v = ics.plummer(n, 68)
@@ -101,11 +103,41 @@ def test_trajectory_gradient_f32_and_autograd(orc):
     x0 = to_dev(torch, pm32[:, :3], torch.float32).requires_grad_(True)
     v0 = to_dev(torch, v32[:, :3], torch.float32).requires_grad_(True)
     m = to_dev(torch, pm32[:, 3], torch.float32).requires_grad_(True)
-    xT, vT = nb.NBodyTrajectory.apply(x0, v0, m, eps, dt, steps, C)
+    xT, vT = nb.NBodyTrajectory.apply(x0, v0, m, eps, dt, steps, C, 1.0, None, getattr(nb, scheme))
     loss = ((xT - to_dev(torch, y, torch.float32)) ** 2).sum()
     loss.backward()
     torch.cuda.synchronize()
-    print("f32 grad errors", normwise(host(x0.grad), gx), normwise(host(v0.grad), gv), normwise(host(m.grad), gm))
+    print(scheme, "f32 grad errors", normwise(host(x0.grad), gx), normwise(host(v0.grad), gv), normwise(host(m.grad), gm))
     assert normwise(host(x0.grad), gx) <= 1e-4
     assert normwise(host(v0.grad), gv) <= 1e-4
     assert normwise(host(m.grad), gm) <= 1e-4
+
+
+def test_trajectory_gradient_velocity_cotangent_and_zero_steps(orc):
+    """A cotangent on the final velocity flows through the kicks; with zero
+    steps the adjoint is the identity."""
+    torch, nb = gpu()
+    n, eps, dt, steps, C = 40, 0.05, 2e-3, 20, 5
+    pm, v = ics.plummer(n, 70)
+    p, vv = to_dev(torch, pm, torch.float64), to_dev(torch, v, torch.float64)
+    ck = nb.trajectory_forward(p, vv, eps, dt, 0, C)
+    g = ics.rng(71)
+    xb = torch.zeros_like(p); xb[:, :3] = to_dev(torch, g.standard_normal((n, 3)), torch.float64)
+    vb = torch.zeros_like(p); vb[:, :3] = to_dev(torch, g.standard_normal((n, 3)), torch.float64)
+    pc, vc, mc = nb.trajectory_adjoint(ck, eps, dt, 0, C, xb, vb)
+    torch.cuda.synchronize()
+    assert torch.equal(pc, xb) and torch.equal(vc, vb) and torch.all(mc == 0)
+    # FD of s(x0, v0) = <vb, v_T> through the oracle leapfrog
+    p, vv = to_dev(torch, pm, torch.float64), to_dev(torch, v, torch.float64)
+    ck = nb.trajectory_forward(p, vv, eps, dt, steps, C)
+    for scheme in (nb.ADJ_RECOMPUTE, nb.ADJ_REVERSE):
+        pc, vc, mc = nb.trajectory_adjoint(ck, eps, dt, steps, C, torch.zeros_like(p), vb, scheme=scheme)
+        torch.cuda.synchronize()
+        vbn = host(vb)[:, :3]
+        d = np.zeros((n, 4)); d[:, :3] = g.standard_normal((n, 3))
+        hh = 1e-6
+        fp = (orc.leapfrog(pm + hh * d, v, eps, dt, steps)["v"] * vbn).sum()
+        fm = (orc.leapfrog(pm - hh * d, v, eps, dt, steps)["v"] * vbn).sum()
+        fd = (fp - fm) / (2 * hh)
+        an = (host(pc)[:, :3] * d[:, :3]).sum()
+        assert abs(fd - an) <= 1e-6 * abs(an) + 1e-9
