@@ -68,11 +68,22 @@ hipError_t launch_permute(const void *src, void *dst, const int32_t *perm, int n
                           bool inverse, hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 
-// Reverse leapfrog step by time reversal plus vbar += dt xbar (vjp.hip).
+// Reverse leapfrog step by time reversal plus vbar += dt xbar, refreshing the
+// scaled cotangent vsc = vbar / m (vjp.hip).
 hipError_t launch_reverse_step(int prec, void *x, void *vh, const void *acc, const void *xbar,
-                               void *vbar, int n, double hk, double dt, hipStream_t s);
-// Adjoint of one leapfrog step pair, elementwise (vjp.hip).
-hipError_t launch_adj_axpy(int prec, void *y, const void *x, double a, int n, hipStream_t s);
+                               void *vbar, void *vsc, int n, double hk, double dt, hipStream_t s);
+// y += a x and ysc = y / m (m from the records pm) (vjp.hip).
+hipError_t launch_adj_axpy(int prec, void *y, const void *x, double a, const void *pm, void *ysc,
+                           int n, hipStream_t s);
+// sc = cot / m; *nonpos |= (some m <= 0).  *nonpos must be zero before.
+hipError_t launch_prescale(int prec, const void *cot, const void *pm, int n, void *sc, int *nonpos,
+                           hipStream_t s);
+// Adjoint VJP (phibar = 0, accumulate): mass-scaled form on sc unless
+// *nonpos, then the general form on raw.
+hipError_t launch_vjp_adj(int prec, const void *pm, const void *raw, const void *sc,
+                          const int *nonpos, int n, double G, double eps, double scale,
+                          void *pos_cot, void *mass_cot, void *acc_out, const Tune &t, void *partial,
+                          hipStream_t s);
 
 // ---- ORB (orb.hip) -----------------------------------------------------------
 int orb_order(const void *pm, int prec, int n, int leaf, int32_t *perm, hipStream_t s);
@@ -83,7 +94,7 @@ void set_error(const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
 // Library scratch, one growable buffer per slot and device.
 enum ScratchSlot { kSlotPartial = 0, kSlotEnergy, kSlotBatch, kSlotOrb0, kSlotOrb1, kSlotOrb2,
-                   kSlotOrb3, kSlotOrb4, kSlotAdj0, kSlotAdj1, kSlotAdj2, kSlotAdj3, kSlotTune,
+                   kSlotOrb3, kSlotOrb4, kSlotAdj0, kSlotAdj1, kSlotAdj2, kSlotAdj3, kSlotAdj4, kSlotTune,
                    kNumSlots };
 void *scratch(int slot, size_t bytes);
 

@@ -180,23 +180,21 @@ static void save_cache_locked()
     rename(tmp.c_str(), path);
 }
 
-// Heuristic shape: enough waves to cover 1024 SIMDs about four deep; the
-// source range is split only when the targets alone cannot do it.
+// Heuristic shape from measured sweeps on MI355X (force kernel, FP32 modes).
 static Tune default_tune(int kernel, int prec, int64_t n)
 {
     Tune t;
     t.jtile = 512;
-    if (kernel == 2)  // VJP: heavier pair, more registers
-        t.tpl = 1;
-    else
-        t.tpl = (prec == NBODY_F64) ? 1 : (n >= (1 << 17) ? 2 : 1);
+    // One target per lane measured fastest at every size (more waves in
+    // flight); the source range is split until about 32 waves per SIMD.
+    t.tpl = 1;
     if (kernel == 1) {
         t.jsplit = 1;
         return t;
     }
-    const int64_t waves = (n + 64 * t.tpl - 1) / (64 * t.tpl);
+    const int64_t waves = (n + 63) / 64;
     int js = 1;
-    while (js < 32 && waves * js < 4096 && n / (js * 2) >= 512) js *= 2;
+    while (js < 32 && waves * js < 32768 && n / (js * 2) >= 256) js *= 2;
     t.jsplit = js;
     return t;
 }
@@ -831,6 +829,17 @@ int nbody_trajectory_adjoint(const void *ckpt, int64_t n, int32_t prec, double G
     // 2h vbar in the interior, h vbar at the last step and at x_0.
     bool first = true;
     const char *ck = (const char *)ckpt;
+    // Scaled cotangent vbar / m for the mass-scaled VJP, and a flag that
+    // switches to the general form when some mass is not positive.
+    char *scbuf = (char *)scratch(kSlotAdj4, rb + 256);
+    if (!scbuf) {
+        set_error("cannot allocate adjoint scratch");
+        return NBODY_E_NOMEM;
+    }
+    void *vsc = scbuf;
+    int *nonpos = (int *)(scbuf + rb);  // rb is a multiple of 16
+    NB_TRY(launch_fill_zero(nonpos, 4, s), "adjoint init");
+    NB_TRY(launch_prescale(prec, vel_cot, ck, ni, vsc, nonpos, s), "adjoint init");
     if (scheme == NBODY_ADJ_REVERSE) {
         // Positions are rebuilt backwards by time reversal of the leapfrog,
         // re-anchored at every checkpoint; the fused kernel returns the force
@@ -843,17 +852,17 @@ int nbody_trajectory_adjoint(const void *ckpt, int64_t n, int32_t prec, double G
             for (int k = C - 1; k >= 0; --k) {
                 const double scale = first ? h : 2.0 * h;
                 first = false;
-                NB_TRY(launch_vjp_ex(prec, xc, vel_cot, ni, G, eps, false, scale, true, pos_cot,
-                                     mass_cot, acc, vt_tune, vpart, s),
+                NB_TRY(launch_vjp_adj(prec, xc, vel_cot, vsc, nonpos, ni, G, eps, scale, pos_cot,
+                                      mass_cot, acc, vt_tune, vpart, s),
                        "adjoint vjp");
-                NB_TRY(launch_reverse_step(prec, xc, vt, acc, pos_cot, vel_cot, ni,
+                NB_TRY(launch_reverse_step(prec, xc, vt, acc, pos_cot, vel_cot, vsc, ni,
                                            k == C - 1 ? h : 2.0 * h, dt, s),
                        "reverse step");
             }
         }
         if (nsteps > 0)
-            NB_TRY(launch_vjp_ex(prec, ck, vel_cot, ni, G, eps, false, h, true, pos_cot, mass_cot,
-                                 nullptr, vt_tune, vpart, s),
+            NB_TRY(launch_vjp_adj(prec, ck, vel_cot, vsc, nonpos, ni, G, eps, h, pos_cot, mass_cot,
+                                  nullptr, vt_tune, vpart, s),
                    "adjoint vjp");
         return NBODY_OK;
     }
@@ -873,14 +882,14 @@ int nbody_trajectory_adjoint(const void *ckpt, int64_t n, int32_t prec, double G
         for (int k = C - 1; k >= 0; --k) {
             const double scale = first ? h : 2.0 * h;
             first = false;
-            NB_TRY(launch_vjp_ex(prec, xs + (size_t)(k + 1) * rb, vel_cot, ni, G, eps, false, scale,
-                                 true, pos_cot, mass_cot, nullptr, vt_tune, vpart, s),
+            NB_TRY(launch_vjp_adj(prec, xs + (size_t)(k + 1) * rb, vel_cot, vsc, nonpos, ni, G, eps,
+                                  scale, pos_cot, mass_cot, nullptr, vt_tune, vpart, s),
                    "adjoint vjp");
-            NB_TRY(launch_adj_axpy(prec, vel_cot, pos_cot, dt, ni, s), "adjoint axpy");
+            NB_TRY(launch_adj_axpy(prec, vel_cot, pos_cot, dt, xs, vsc, ni, s), "adjoint axpy");
         }
         if (c == 0 && nsteps > 0)
-            NB_TRY(launch_vjp_ex(prec, xs, vel_cot, ni, G, eps, false, h, true, pos_cot, mass_cot,
-                                 nullptr, vt_tune, vpart, s),
+            NB_TRY(launch_vjp_adj(prec, xs, vel_cot, vsc, nonpos, ni, G, eps, h, pos_cot, mass_cot,
+                                  nullptr, vt_tune, vpart, s),
                    "adjoint vjp");
     }
     return NBODY_OK;

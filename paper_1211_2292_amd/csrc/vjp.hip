@@ -52,6 +52,10 @@ struct VTgt {
     int i[TPL];
 };
 
+// Fused multiply-add in the precision of T (no promotion of float to double).
+__device__ __forceinline__ float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <typename T>
 __device__ __forceinline__ T rsq_t(T q);
 template <>
@@ -80,35 +84,35 @@ __device__ __forceinline__ void vpair(const V p, const V c, const int j, const V
         const T d0 = p.x - K.x[t][0];
         const T d1 = p.y - K.x[t][1];
         const T d2 = p.z - K.x[t][2];
-        const T q = __builtin_fma(d2, d2, __builtin_fma(d1, d1, __builtin_fma(d0, d0, eps2)));
+        const T q = fmat(d2, d2, fmat(d1, d1, fmat(d0, d0, eps2)));
         T rho = rsq_t<T>(q);
         if (MASK) rho = (j == K.i[t]) ? T(0) : rho;
         const T r2 = rho * rho;
         const T w = rho * r2;
-        const T e0 = __builtin_fma(-p.w, K.ab[t][0], K.m[t] * c.x);
-        const T e1 = __builtin_fma(-p.w, K.ab[t][1], K.m[t] * c.y);
-        const T e2 = __builtin_fma(-p.w, K.ab[t][2], K.m[t] * c.z);
-        const T de = __builtin_fma(d2, e2, __builtin_fma(d1, e1, d0 * e0));
-        const T da = __builtin_fma(d2, c.z, __builtin_fma(d1, c.y, d0 * c.x));
+        const T e0 = fmat(-p.w, K.ab[t][0], K.m[t] * c.x);
+        const T e1 = fmat(-p.w, K.ab[t][1], K.m[t] * c.y);
+        const T e2 = fmat(-p.w, K.ab[t][2], K.m[t] * c.z);
+        const T de = fmat(d2, e2, fmat(d1, e1, d0 * e0));
+        const T da = fmat(d2, c.z, fmat(d1, c.y, d0 * c.x));
         const T uq = (w * r2) * de;
-        S.P[t][0] = __builtin_fma(w, e0, S.P[t][0]);
-        S.P[t][1] = __builtin_fma(w, e1, S.P[t][1]);
-        S.P[t][2] = __builtin_fma(w, e2, S.P[t][2]);
-        S.Q[t][0] = __builtin_fma(uq, d0, S.Q[t][0]);
-        S.Q[t][1] = __builtin_fma(uq, d1, S.Q[t][1]);
-        S.Q[t][2] = __builtin_fma(uq, d2, S.Q[t][2]);
-        S.M[t] = __builtin_fma(w, da, S.M[t]);
+        S.P[t][0] = fmat(w, e0, S.P[t][0]);
+        S.P[t][1] = fmat(w, e1, S.P[t][1]);
+        S.P[t][2] = fmat(w, e2, S.P[t][2]);
+        S.Q[t][0] = fmat(uq, d0, S.Q[t][0]);
+        S.Q[t][1] = fmat(uq, d1, S.Q[t][1]);
+        S.Q[t][2] = fmat(uq, d2, S.Q[t][2]);
+        S.M[t] = fmat(w, da, S.M[t]);
         const T mw = p.w * w;
-        S.A[t][0] = __builtin_fma(mw, d0, S.A[t][0]);
-        S.A[t][1] = __builtin_fma(mw, d1, S.A[t][1]);
-        S.A[t][2] = __builtin_fma(mw, d2, S.A[t][2]);
-        S.F[t] = __builtin_fma(p.w, rho, S.F[t]);
+        S.A[t][0] = fmat(mw, d0, S.A[t][0]);
+        S.A[t][1] = fmat(mw, d1, S.A[t][1]);
+        S.A[t][2] = fmat(mw, d2, S.A[t][2]);
+        S.F[t] = fmat(p.w, rho, S.F[t]);
         if (PHI) {
             const T pw = c.w * w;
-            S.B[t][0] = __builtin_fma(pw, d0, S.B[t][0]);
-            S.B[t][1] = __builtin_fma(pw, d1, S.B[t][1]);
-            S.B[t][2] = __builtin_fma(pw, d2, S.B[t][2]);
-            S.H[t] = __builtin_fma(c.w, rho, S.H[t]);
+            S.B[t][0] = fmat(pw, d0, S.B[t][0]);
+            S.B[t][1] = fmat(pw, d1, S.B[t][1]);
+            S.B[t][2] = fmat(pw, d2, S.B[t][2]);
+            S.H[t] = fmat(c.w, rho, S.H[t]);
         }
     }
 }
@@ -182,11 +186,11 @@ __device__ __forceinline__ void apply_out(double (&o)[8], double scale, int accu
 }
 
 template <typename T, typename V, typename MT, int TPL, bool PHI>
-__global__ __launch_bounds__(kBlock) void k_vjp(const V *__restrict__ pm, const V *__restrict__ cot,
-                                                int n, T eps2, double G, int jtile, double scale,
-                                                int accumulate, V *__restrict__ pos_cot,
-                                                MT *__restrict__ mass_cot, V *__restrict__ acc_out,
-                                                double4 *__restrict__ partial)
+__device__ __forceinline__ void vjp_general(const V *__restrict__ pm, const V *__restrict__ cot,
+                                            int n, T eps2, double G, int jtile, double scale,
+                                            int accumulate, V *__restrict__ pos_cot,
+                                            MT *__restrict__ mass_cot, V *__restrict__ acc_out,
+                                            double4 *__restrict__ partial)
 {
     constexpr int WT = 64 * TPL;
     const int lane = threadIdx.x & 63;
@@ -264,6 +268,204 @@ __global__ __launch_bounds__(kBlock) void k_vjp(const V *__restrict__ pm, const 
     }
 }
 
+template <typename T, typename V, typename MT, int TPL, bool PHI>
+__global__ __launch_bounds__(kBlock) void k_vjp(const V *__restrict__ pm, const V *__restrict__ cot,
+                                                int n, T eps2, double G, int jtile, double scale,
+                                                int accumulate, V *__restrict__ pos_cot,
+                                                MT *__restrict__ mass_cot, V *__restrict__ acc_out,
+                                                double4 *__restrict__ partial)
+{
+    vjp_general<T, V, MT, TPL, PHI>(pm, cot, n, eps2, G, jtile, scale, accumulate, pos_cot, mass_cot,
+                                    acc_out, partial);
+}
+
+// ---- mass-scaled form (all masses positive) ----------------------------------
+// With at = abar / m per body, e = at_j - at_k and s1 = m_j w:
+//   xbar_k = G m_k [sum s1 e - 3 sum (s1 rho^2)(d . e) d]
+//   mbar_k = -G [sum s1 (d . e) + at_k . sum s1 d],   a_k = G sum s1 d
+// 28 VALU per pair (no potential), against 34 for the general form.
+template <typename T, int TPL>
+struct SAcc {
+    T P[TPL][3], Q[TPL][3], M[TPL], F[TPL][3];
+    __device__ void zero()
+    {
+#pragma unroll
+        for (int t = 0; t < TPL; ++t) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) P[t][c] = Q[t][c] = F[t][c] = T(0);
+            M[t] = T(0);
+        }
+    }
+};
+
+template <typename T, typename V, int TPL, bool MASK>
+__device__ __forceinline__ void spair(const V p, const V c, const int j, const VTgt<T, TPL> &K,
+                                      const T eps2, SAcc<T, TPL> &S)
+{
+#pragma unroll
+    for (int t = 0; t < TPL; ++t) {
+        const T d0 = p.x - K.x[t][0];
+        const T d1 = p.y - K.x[t][1];
+        const T d2 = p.z - K.x[t][2];
+        const T q = fmat(d2, d2, fmat(d1, d1, fmat(d0, d0, eps2)));
+        T rho = rsq_t<T>(q);
+        if (MASK) rho = (j == K.i[t]) ? T(0) : rho;
+        const T r2 = rho * rho;
+        const T s1 = (p.w * rho) * r2;
+        const T e0 = c.x - K.ab[t][0];
+        const T e1 = c.y - K.ab[t][1];
+        const T e2 = c.z - K.ab[t][2];
+        const T de = fmat(d2, e2, fmat(d1, e1, d0 * e0));
+        const T tq = (s1 * r2) * de;
+        S.P[t][0] = fmat(s1, e0, S.P[t][0]);
+        S.P[t][1] = fmat(s1, e1, S.P[t][1]);
+        S.P[t][2] = fmat(s1, e2, S.P[t][2]);
+        S.Q[t][0] = fmat(tq, d0, S.Q[t][0]);
+        S.Q[t][1] = fmat(tq, d1, S.Q[t][1]);
+        S.Q[t][2] = fmat(tq, d2, S.Q[t][2]);
+        S.M[t] = fmat(s1, de, S.M[t]);
+        S.F[t][0] = fmat(s1, d0, S.F[t][0]);
+        S.F[t][1] = fmat(s1, d1, S.F[t][1]);
+        S.F[t][2] = fmat(s1, d2, S.F[t][2]);
+    }
+}
+
+template <typename T, typename V, int TPL, bool MASK>
+__device__ __forceinline__ void ssweep(const V *__restrict__ pm, const V *__restrict__ cot, int j0,
+                                       int j1, const VTgt<T, TPL> &K, T eps2, SAcc<T, TPL> &S)
+{
+    int j = j0;
+    for (; j + kVjpUnroll <= j1; j += kVjpUnroll) {
+        V p[kVjpUnroll], c[kVjpUnroll];
+#pragma unroll
+        for (int u = 0; u < kVjpUnroll; ++u) {
+            p[u] = pm[j + u];
+            c[u] = cot[j + u];
+        }
+#pragma unroll
+        for (int u = 0; u < kVjpUnroll; ++u) spair<T, V, TPL, MASK>(p[u], c[u], j + u, K, eps2, S);
+    }
+    for (; j < j1; ++j) spair<T, V, TPL, MASK>(pm[j], cot[j], j, K, eps2, S);
+}
+
+template <typename T, typename V, typename MT, int TPL>
+__device__ __forceinline__ void vjp_scaled(const V *__restrict__ pm, const V *__restrict__ sc,
+                                           int n, T eps2, double G, int jtile, double scale,
+                                           int accumulate, V *__restrict__ pos_cot,
+                                           MT *__restrict__ mass_cot, V *__restrict__ acc_out,
+                                           double4 *__restrict__ partial)
+{
+    constexpr int WT = 64 * TPL;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t0 = (blockIdx.x * (kBlock / 64) + wave) * WT;
+    if (t0 >= n) return;
+    const long per = ((long)n + gridDim.y - 1) / gridDim.y;
+    const int jb = (int)min((long)n, (long)blockIdx.y * per);
+    const int je = (int)min((long)n, (long)jb + per);
+    VTgt<T, TPL> K;
+#pragma unroll
+    for (int t = 0; t < TPL; ++t) {
+        const int i = t0 + t * 64 + lane;
+        K.i[t] = i;
+        const int ic = min(i, n - 1);
+        const V p = pm[ic];
+        const V c = sc[ic];
+        K.x[t][0] = p.x; K.x[t][1] = p.y; K.x[t][2] = p.z;
+        K.m[t] = p.w;
+        K.ab[t][0] = c.x; K.ab[t][1] = c.y; K.ab[t][2] = c.z;
+        K.pb[t] = T(0);
+    }
+    const int d0 = t0, d1 = t0 + WT;
+    double R[TPL][10];
+#pragma unroll
+    for (int t = 0; t < TPL; ++t)
+#pragma unroll
+        for (int c = 0; c < 10; ++c) R[t][c] = 0.0;
+    SAcc<T, TPL> S;
+    for (int jc = jb; jc < je; jc += jtile) {
+        const int ce = min(jc + jtile, je);
+        const int lo = min(max(d0, jc), ce);
+        const int hi = min(max(d1, jc), ce);
+        S.zero();
+        ssweep<T, V, TPL, false>(pm, sc, jc, lo, K, eps2, S);
+        ssweep<T, V, TPL, true>(pm, sc, lo, hi, K, eps2, S);
+        ssweep<T, V, TPL, false>(pm, sc, hi, ce, K, eps2, S);
+#pragma unroll
+        for (int t = 0; t < TPL; ++t) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                R[t][c] += (double)S.P[t][c];
+                R[t][3 + c] += (double)S.Q[t][c];
+                R[t][6 + c] += (double)S.F[t][c];
+            }
+            R[t][9] += (double)S.M[t];
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < TPL; ++t) {
+        const int i = t0 + t * 64 + lane;
+        if (i >= n) continue;
+        const double gm_k = G * (double)K.m[t];
+        double o[8];
+        o[0] = gm_k * (R[t][0] - 3.0 * R[t][3]);
+        o[1] = gm_k * (R[t][1] - 3.0 * R[t][4]);
+        o[2] = gm_k * (R[t][2] - 3.0 * R[t][5]);
+        o[3] = -G * (R[t][9] + (double)K.ab[t][0] * R[t][6] + (double)K.ab[t][1] * R[t][7] +
+                     (double)K.ab[t][2] * R[t][8]);
+        o[4] = G * R[t][6];
+        o[5] = G * R[t][7];
+        o[6] = G * R[t][8];
+        o[7] = 0.0;
+        if (gridDim.y == 1) {
+            apply_out(o, scale, accumulate, i, pos_cot, mass_cot, acc_out);
+        } else {
+            double4 *dst = partial + 2 * ((long)blockIdx.y * n + i);
+            dst[0] = make_double4(o[0], o[1], o[2], o[3]);
+            dst[1] = make_double4(o[4], o[5], o[6], o[7]);
+        }
+    }
+}
+
+// Adjoint VJP: mass-scaled form unless some mass is not positive (flag set
+// by the scaling pass), then the general form on the raw cotangent.  The
+// branch is uniform over the launch.
+template <typename T, typename V, typename MT, int TPL>
+__global__ __launch_bounds__(kBlock) void k_vjp_adj(const V *__restrict__ pm, const V *__restrict__ raw,
+                                                    const V *__restrict__ sc,
+                                                    const int *__restrict__ nonpos, int n, T eps2,
+                                                    double G, int jtile, double scale, int accumulate,
+                                                    V *__restrict__ pos_cot, MT *__restrict__ mass_cot,
+                                                    V *__restrict__ acc_out,
+                                                    double4 *__restrict__ partial)
+{
+    if (*nonpos)
+        vjp_general<T, V, MT, TPL, false>(pm, raw, n, eps2, G, jtile, scale, accumulate, pos_cot,
+                                          mass_cot, acc_out, partial);
+    else
+        vjp_scaled<T, V, MT, TPL>(pm, sc, n, eps2, G, jtile, scale, accumulate, pos_cot, mass_cot,
+                                  acc_out, partial);
+}
+
+// at = abar / m for every body; any non-positive mass sets *nonpos.
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_prescale(const V *__restrict__ cot,
+                                                     const V *__restrict__ pm, int n,
+                                                     V *__restrict__ sc, int *__restrict__ nonpos)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const V c = cot[i];
+    const V p = pm[i];
+    V o;
+    o.x = c.x / p.w;
+    o.y = c.y / p.w;
+    o.z = c.z / p.w;
+    o.w = 0;
+    sc[i] = o;
+    if (!(p.w > 0)) atomicOr(nonpos, 1);
+}
+
 // Fixed-order sum of the per-split records, then the same output step.
 template <typename V, typename MT>
 __global__ __launch_bounds__(kBlock) void k_vjp_reduce(const double4 *__restrict__ partial, int js,
@@ -284,8 +486,10 @@ __global__ __launch_bounds__(kBlock) void k_vjp_reduce(const double4 *__restrict
     apply_out(o, scale, accumulate, i, pos_cot, mass_cot, acc_out);
 }
 
+// y += a x, and ysc = y / m with m from the records pm (next scaled cotangent)
 template <typename V, typename S>
 __global__ __launch_bounds__(kBlock) void k_axpy(V *__restrict__ y, const V *__restrict__ x, S a,
+                                                 const V *__restrict__ pm, V *__restrict__ ysc,
                                                  int n)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
@@ -296,6 +500,13 @@ __global__ __launch_bounds__(kBlock) void k_axpy(V *__restrict__ y, const V *__r
     v.y = v.y + a * u.y;
     v.z = v.z + a * u.z;
     y[i] = v;
+    const S m = pm[i].w;
+    V o;
+    o.x = v.x / m;
+    o.y = v.y / m;
+    o.z = v.z / m;
+    o.w = 0;
+    ysc[i] = o;
 }
 
 // One reverse step of the leapfrog by exact time reversal (scheme used by
@@ -308,7 +519,8 @@ template <typename V, typename S>
 __global__ __launch_bounds__(kBlock) void k_reverse(V *__restrict__ x, V *__restrict__ vh,
                                                     const V *__restrict__ acc,
                                                     const V *__restrict__ xbar,
-                                                    V *__restrict__ vbar, int n, S hk, S dt)
+                                                    V *__restrict__ vbar, V *__restrict__ vsc,
+                                                    int n, S hk, S dt)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
@@ -326,6 +538,12 @@ __global__ __launch_bounds__(kBlock) void k_reverse(V *__restrict__ x, V *__rest
     x[i] = p;
     vh[i] = v;
     vbar[i] = w;
+    V o;
+    o.x = w.x / p.w;
+    o.y = w.y / p.w;
+    o.z = w.z / p.w;
+    o.w = 0;
+    vsc[i] = o;
 }
 
 template <typename T, typename V, typename MT, int TPL>
@@ -387,30 +605,82 @@ hipError_t launch_vjp(int prec, const void *pm, const void *cot, int n, double G
 }
 
 hipError_t launch_reverse_step(int prec, void *x, void *vh, const void *acc, const void *xbar,
-                               void *vbar, int n, double hk, double dt, hipStream_t s)
+                               void *vbar, void *vsc, int n, double hk, double dt, hipStream_t s)
 {
     const dim3 grid((n + kBlock - 1) / kBlock);
     if (prec == NBODY_F64)
         hipLaunchKernelGGL((k_reverse<double4, double>), grid, dim3(kBlock), 0, s, (double4 *)x,
                            (double4 *)vh, (const double4 *)acc, (const double4 *)xbar,
-                           (double4 *)vbar, n, hk, dt);
+                           (double4 *)vbar, (double4 *)vsc, n, hk, dt);
     else
         hipLaunchKernelGGL((k_reverse<float4, float>), grid, dim3(kBlock), 0, s, (float4 *)x,
                            (float4 *)vh, (const float4 *)acc, (const float4 *)xbar, (float4 *)vbar,
-                           n, (float)hk, (float)dt);
+                           (float4 *)vsc, n, (float)hk, (float)dt);
     return hipGetLastError();
 }
 
-hipError_t launch_adj_axpy(int prec, void *y, const void *x, double a, int n, hipStream_t s)
+hipError_t launch_adj_axpy(int prec, void *y, const void *x, double a, const void *pm, void *ysc,
+                           int n, hipStream_t s)
 {
     const dim3 grid((n + kBlock - 1) / kBlock);
     if (prec == NBODY_F64)
         hipLaunchKernelGGL((k_axpy<double4, double>), grid, dim3(kBlock), 0, s, (double4 *)y,
-                           (const double4 *)x, a, n);
+                           (const double4 *)x, a, (const double4 *)pm, (double4 *)ysc, n);
     else
         hipLaunchKernelGGL((k_axpy<float4, float>), grid, dim3(kBlock), 0, s, (float4 *)y,
-                           (const float4 *)x, (float)a, n);
+                           (const float4 *)x, (float)a, (const float4 *)pm, (float4 *)ysc, n);
     return hipGetLastError();
+}
+
+hipError_t launch_prescale(int prec, const void *cot, const void *pm, int n, void *sc, int *nonpos,
+                           hipStream_t s)
+{
+    const dim3 grid((n + kBlock - 1) / kBlock);
+    if (prec == NBODY_F64)
+        hipLaunchKernelGGL((k_prescale<double4>), grid, dim3(kBlock), 0, s, (const double4 *)cot,
+                           (const double4 *)pm, n, (double4 *)sc, nonpos);
+    else
+        hipLaunchKernelGGL((k_prescale<float4>), grid, dim3(kBlock), 0, s, (const float4 *)cot,
+                           (const float4 *)pm, n, (float4 *)sc, nonpos);
+    return hipGetLastError();
+}
+
+template <typename T, typename V, typename MT, int TPL>
+hipError_t go_vjp_adj(const void *pm, const void *raw, const void *sc, const int *nonpos, int n,
+                      T eps2, double G, const Tune &t, double scale, void *pos_cot, void *mass_cot,
+                      void *acc_out, void *partial, hipStream_t s)
+{
+    const int per_block = (kBlock / 64) * 64 * TPL;
+    const dim3 grid((n + per_block - 1) / per_block, t.jsplit);
+    hipLaunchKernelGGL((k_vjp_adj<T, V, MT, TPL>), grid, dim3(kBlock), 0, s, (const V *)pm,
+                       (const V *)raw, (const V *)sc, nonpos, n, eps2, G, t.jtile, scale, 1,
+                       (V *)pos_cot, (MT *)mass_cot, (V *)acc_out, (double4 *)partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || t.jsplit == 1) return e;
+    hipLaunchKernelGGL((k_vjp_reduce<V, MT>), dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                       (const double4 *)partial, t.jsplit, n, scale, 1, (V *)pos_cot,
+                       (MT *)mass_cot, (V *)acc_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_vjp_adj(int prec, const void *pm, const void *raw, const void *sc,
+                          const int *nonpos, int n, double G, double eps, double scale,
+                          void *pos_cot, void *mass_cot, void *acc_out, const Tune &t, void *partial,
+                          hipStream_t s)
+{
+    if (prec == NBODY_F64) {
+        if (t.tpl == 1)
+            return go_vjp_adj<double, double4, double, 1>(pm, raw, sc, nonpos, n, eps * eps, G, t,
+                                                          scale, pos_cot, mass_cot, acc_out, partial, s);
+        return go_vjp_adj<double, double4, double, 2>(pm, raw, sc, nonpos, n, eps * eps, G, t, scale,
+                                                      pos_cot, mass_cot, acc_out, partial, s);
+    }
+    const float e2 = (float)(eps * eps);
+    if (t.tpl == 1)
+        return go_vjp_adj<float, float4, float, 1>(pm, raw, sc, nonpos, n, e2, G, t, scale, pos_cot,
+                                                   mass_cot, acc_out, partial, s);
+    return go_vjp_adj<float, float4, float, 2>(pm, raw, sc, nonpos, n, e2, G, t, scale, pos_cot,
+                                               mass_cot, acc_out, partial, s);
 }
 
 }  // namespace nbi

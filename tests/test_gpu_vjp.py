@@ -141,3 +141,23 @@ def test_trajectory_gradient_velocity_cotangent_and_zero_steps(orc):
         fd = (fp - fm) / (2 * hh)
         an = (host(pc)[:, :3] * d[:, :3]).sum()
         assert abs(fd - an) <= 1e-6 * abs(an) + 1e-9
+
+
+@pytest.mark.parametrize("scheme", ["ADJ_RECOMPUTE", "ADJ_REVERSE"])
+def test_trajectory_gradient_with_massless_body(orc, scheme):
+    """A zero mass switches the adjoint to the general VJP form."""
+    torch, nb = gpu()
+    n, eps, dt, steps, C = 48, 0.05, 2e-3, 20, 10
+    pm, v = ics.plummer(n, 72)
+    pm[5, 3] = 0.0
+    y = ics.perturbed_snapshot(pm, 73, 0.05)
+    L, gx, gv, gm = orc.traj_grad(pm, v, y, eps, dt, steps)
+    p, vv = to_dev(torch, pm, torch.float64), to_dev(torch, v, torch.float64)
+    ck = nb.trajectory_forward(p, vv, eps, dt, steps, C)
+    xb = torch.zeros_like(p)
+    xb[:, :3] = 2 * (p[:, :3] - to_dev(torch, y, torch.float64))
+    pc, vc, mc = nb.trajectory_adjoint(ck, eps, dt, steps, C, xb, torch.zeros_like(p), scheme=getattr(nb, scheme))
+    torch.cuda.synchronize()
+    assert normwise(host(pc)[:, :3], gx) <= 1e-11
+    assert normwise(host(vc)[:, :3], gv) <= 1e-11
+    assert normwise(host(mc), gm) <= 1e-11
