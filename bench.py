@@ -146,12 +146,14 @@ def main():
         "config": {"workload": "colliding Plummer pair, N=1048576, mass ratio 1:3, eps=0.005, "
                                "dt=5e-4, leapfrog KDK, NBODY_F32_F64ACC",
                    "n": n, "eps": eps, "dt": dt, "precision": "F32_F64ACC",
-                   "kernel_shape": {"tpl": tune[0], "jsplit": tune[1], "jtile": tune[2]}},
+                   "kernel_shape": {"tpl": tune[0], "jsplit": tune[1], "jtile": tune[2],
+                                    "variant": ["scalar-load sources", "LDS sources"][tune[3]]}},
         "pct_fp32_peak": round(100 * achieved / PEAK_FP32_TFLOPS, 2),
         "wall_s_timed": round(wall, 3),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
-                     "kernel": "k_accel_f32<TPL, F64ACC>", "flop_per_pair": FLOP_PER_PAIR,
+                     "kernel": ("k_accel_lds_f32" if tune[3] else "k_accel_f32") + f"<{tune[0]}, F64ACC>",
+                     "flop_per_pair": FLOP_PER_PAIR,
                      "avg_launch_ms": round(kern_avg, 4)},
     }
 
@@ -253,7 +255,7 @@ def cpu_leg(ics, pm0_host, acc0, eps, seconds):
     done, parts_a, parts_p = 0, [], []
     t0 = time.perf_counter()
     while done < order.shape[0] and time.perf_counter() - t0 < seconds:
-        chunk = order[done:done + 512]
+        chunk = order[done:done + 4096]
         a, p = oracle.accel(pm0_host, eps, targets=chunk)
         parts_a.append(a)
         parts_p.append(p)

@@ -210,15 +210,19 @@ int nbody_trajectory_adjoint(const void *ckpt, int64_t n, int32_t prec, double G
  * synchronously, and records the fastest in the in-process table (and in the
  * JSON file named by the environment variable NBODY_TUNE_CACHE, if set).
  * nbody_set_tuning pins a shape for later calls: tpl (targets per lane:
- * 1, 2, 4), jsplit (waves sharing targets: 1, 2, 4), jtile (sources per
- * partial sum, multiple of 8); kernel and prec as above; all -1 clears it.
+ * 1, 2, 4), jsplit (independent source ranges per target, 1..32, reduced in
+ * fixed order; kernel 1 takes 1), jtile (sources per partial sum, multiple
+ * of 8), variant (0: source records through scalar loads; 1: staged in LDS,
+ * FP32 force kernel only, jtile a multiple of 256; both give identical
+ * results); kernel and prec as above; tpl = jsplit = jtile = -1 clears it.
  * nbody_get_tuning reports the shape the library would use.
  */
 int nbody_autotune(int32_t kernel, int32_t prec, int64_t n, const int64_t *offsets_host,
                    int32_t nsys, void *stream);
-int nbody_set_tuning(int32_t kernel, int32_t prec, int32_t tpl, int32_t jsplit, int32_t jtile);
+int nbody_set_tuning(int32_t kernel, int32_t prec, int32_t tpl, int32_t jsplit, int32_t jtile,
+                     int32_t variant);
 int nbody_get_tuning(int32_t kernel, int32_t prec, int64_t n, int32_t *tpl, int32_t *jsplit,
-                     int32_t *jtile);
+                     int32_t *jtile, int32_t *variant);
 
 const char *nbody_status_string(int status);
 const char *nbody_last_error(void);

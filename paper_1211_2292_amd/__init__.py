@@ -56,8 +56,8 @@ _SIGS = {
     "nbody_trajectory_adjoint": [_vp, _i64, _i32, _dbl, _dbl, _dbl, _i32, _i32, _vp, _vp, _vp,
                                  _vp, _vp, _i32, _vp],
     "nbody_autotune": [_i32, _i32, _i64, _vp, _i32, _vp],
-    "nbody_set_tuning": [_i32, _i32, _i32, _i32, _i32],
-    "nbody_get_tuning": [_i32, _i32, _i64, _vp, _vp, _vp],
+    "nbody_set_tuning": [_i32, _i32, _i32, _i32, _i32, _i32],
+    "nbody_get_tuning": [_i32, _i32, _i64, _vp, _vp, _vp, _vp],
     "nbody_status_string": [ctypes.c_int],
     "nbody_last_error": [],
     "nbody_release": [],
@@ -327,15 +327,18 @@ def autotune(kernel, prec, n, offsets=None):
     _check(lib().nbody_autotune(int(kernel), int(prec), int(n), optr, nsys, _stream()))
 
 
-def set_tuning(kernel, prec, tpl=-1, jsplit=-1, jtile=-1):
-    _check(lib().nbody_set_tuning(int(kernel), int(prec), int(tpl), int(jsplit), int(jtile)))
+def set_tuning(kernel, prec, tpl=-1, jsplit=-1, jtile=-1, variant=0):
+    """Pin (tpl, jsplit, jtile, variant) for a kernel and precision; no
+    shape arguments clears the pin."""
+    _check(lib().nbody_set_tuning(int(kernel), int(prec), int(tpl), int(jsplit), int(jtile), int(variant)))
 
 
 def get_tuning(kernel, prec, n):
-    a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    """(tpl, jsplit, jtile, variant) the library would use for size n."""
+    a, b, c, d = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     _check(lib().nbody_get_tuning(int(kernel), int(prec), int(n), ctypes.byref(a), ctypes.byref(b),
-                                  ctypes.byref(c)))
-    return a.value, b.value, c.value
+                                  ctypes.byref(c), ctypes.byref(d)))
+    return a.value, b.value, c.value, d.value
 
 
 def release():

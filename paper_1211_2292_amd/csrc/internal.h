@@ -16,10 +16,14 @@ namespace nbi {
 //          range is a separate workgroup row, reduced in fixed order after
 //   jtile  sources per partial sum (multiple of 8); the partials are folded
 //          into the running sum by the precision mode
+//   variant 0: sources through scalar loads (SGPR operands);
+//           1: sources staged in LDS (VGPR operands; FP32 force kernel only,
+//              jtile a multiple of 256).  Both give identical results.
 struct Tune {
     int tpl = 2;
     int jsplit = 1;
     int jtile = 512;
+    int variant = 0;
 };
 
 constexpr int kBlock = 256;  // threads per workgroup: four independent waves
@@ -84,6 +88,13 @@ hipError_t launch_vjp_adj(int prec, const void *pm, const void *raw, const void 
                           const int *nonpos, int n, double G, double eps, double scale,
                           void *pos_cot, void *mass_cot, void *acc_out, const Tune &t, void *partial,
                           hipStream_t s);
+// Adjoint VJP and the elementwise step after it in as few launches as the
+// shape allows (post 1: vbar += dt xbar; post 2: time reversal of x, vh).
+// Uses tpl = 1 when the source range is split.
+hipError_t launch_vjp_adj_step(int prec, int post, void *pm, void *raw, void *sc, const int *nonpos,
+                               int n, double G, double eps, double scale, void *pos_cot,
+                               void *mass_cot, void *acc, void *vh, double hk, double dt,
+                               const Tune &t, void *partial, hipStream_t s);
 
 // ---- ORB (orb.hip) -----------------------------------------------------------
 int orb_order(const void *pm, int prec, int n, int leaf, int32_t *perm, hipStream_t s);

@@ -146,15 +146,16 @@ static void load_cache_locked()
     if (!path) return;
     FILE *f = fopen(path, "r");
     if (!f) return;
-    // One entry per line: "k,p,b": [tpl, jsplit, jtile]
+    // One entry per line: "k,p,b": [tpl, jsplit, jtile, variant]
     char line[256];
     while (fgets(line, sizeof line, f)) {
-        int k, p, b, t, j, jt;
-        if (sscanf(line, " \"%d,%d,%d\" : [ %d , %d , %d ]", &k, &p, &b, &t, &j, &jt) == 6) {
+        int k, p, b, t, j, jt, v;
+        if (sscanf(line, " \"%d,%d,%d\" : [ %d , %d , %d , %d ]", &k, &p, &b, &t, &j, &jt, &v) == 7) {
             Tune tu;
             tu.tpl = t;
             tu.jsplit = j;
             tu.jtile = jt;
+            tu.variant = v;
             if (tune_valid(tu)) g_tuned[TuneKey(k, p, b)] = tu;
         }
     }
@@ -171,9 +172,9 @@ static void save_cache_locked()
     fprintf(f, "{\n");
     size_t i = 0;
     for (auto &kv : g_tuned) {
-        fprintf(f, "  \"%d,%d,%d\": [%d, %d, %d]%s\n", std::get<0>(kv.first), std::get<1>(kv.first),
-                std::get<2>(kv.first), kv.second.tpl, kv.second.jsplit, kv.second.jtile,
-                ++i < g_tuned.size() ? "," : "");
+        fprintf(f, "  \"%d,%d,%d\": [%d, %d, %d, %d]%s\n", std::get<0>(kv.first),
+                std::get<1>(kv.first), std::get<2>(kv.first), kv.second.tpl, kv.second.jsplit,
+                kv.second.jtile, kv.second.variant, ++i < g_tuned.size() ? "," : "");
     }
     fprintf(f, "}\n");
     fclose(f);
@@ -194,7 +195,7 @@ static Tune default_tune(int kernel, int prec, int64_t n)
     }
     const int64_t waves = (n + 63) / 64;
     int js = 1;
-    while (js < 32 && waves * js < 32768 && n / (js * 2) >= 256) js *= 2;
+    while (js < 32 && waves * js < 65536 && n / (js * 2) >= 256) js *= 2;
     t.jsplit = js;
     return t;
 }
@@ -310,9 +311,9 @@ static int get_plan(const int64_t *off, int32_t nsys, const Tune &t, BatchPlan *
     int cus = 256;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
-    // Persistent grid: four workgroups (16 waves) per CU, never more waves
+    // Persistent grid: eight workgroups (32 waves) per CU, never more waves
     // than units.
-    p.grid = std::max(1, std::min(cus * 4, (p.nunits + 3) / 4));
+    p.grid = std::max(1, std::min(cus * 8, (p.nunits + 3) / 4));
     auto ins = g_plans.emplace(key, p);
     *out = &ins.first->second;
     return NBODY_OK;
@@ -618,7 +619,7 @@ int nbody_leapfrog_kdk(void *pos_mass, void *vel, void *acc_pot, int64_t n,
     {
         Tune t = lookup_tune(0, prec, n), bt = lookup_tune(1, prec, n);
         key.v.insert(key.v.end(), {(uint64_t)t.tpl, (uint64_t)t.jsplit, (uint64_t)t.jtile,
-                                   (uint64_t)bt.tpl, (uint64_t)bt.jtile});
+                                   (uint64_t)t.variant, (uint64_t)bt.tpl, (uint64_t)bt.jtile});
     }
     GraphEntry *ge = nullptr;
     {
@@ -852,12 +853,10 @@ int nbody_trajectory_adjoint(const void *ckpt, int64_t n, int32_t prec, double G
             for (int k = C - 1; k >= 0; --k) {
                 const double scale = first ? h : 2.0 * h;
                 first = false;
-                NB_TRY(launch_vjp_adj(prec, xc, vel_cot, vsc, nonpos, ni, G, eps, scale, pos_cot,
-                                      mass_cot, acc, vt_tune, vpart, s),
-                       "adjoint vjp");
-                NB_TRY(launch_reverse_step(prec, xc, vt, acc, pos_cot, vel_cot, vsc, ni,
-                                           k == C - 1 ? h : 2.0 * h, dt, s),
-                       "reverse step");
+                NB_TRY(launch_vjp_adj_step(prec, 2, xc, vel_cot, vsc, nonpos, ni, G, eps, scale,
+                                           pos_cot, mass_cot, acc, vt, k == C - 1 ? h : 2.0 * h, dt,
+                                           vt_tune, vpart, s),
+                       "adjoint step");
             }
         }
         if (nsteps > 0)
@@ -882,10 +881,10 @@ int nbody_trajectory_adjoint(const void *ckpt, int64_t n, int32_t prec, double G
         for (int k = C - 1; k >= 0; --k) {
             const double scale = first ? h : 2.0 * h;
             first = false;
-            NB_TRY(launch_vjp_adj(prec, xs + (size_t)(k + 1) * rb, vel_cot, vsc, nonpos, ni, G, eps,
-                                  scale, pos_cot, mass_cot, nullptr, vt_tune, vpart, s),
-                   "adjoint vjp");
-            NB_TRY(launch_adj_axpy(prec, vel_cot, pos_cot, dt, xs, vsc, ni, s), "adjoint axpy");
+            NB_TRY(launch_vjp_adj_step(prec, 1, xs + (size_t)(k + 1) * rb, vel_cot, vsc, nonpos, ni,
+                                       G, eps, scale, pos_cot, mass_cot, acc, vt, 0.0, dt, vt_tune,
+                                       vpart, s),
+                   "adjoint step");
         }
         if (c == 0 && nsteps > 0)
             NB_TRY(launch_vjp_adj(prec, xs, vel_cot, vsc, nonpos, ni, G, eps, h, pos_cot, mass_cot,
@@ -896,7 +895,8 @@ int nbody_trajectory_adjoint(const void *ckpt, int64_t n, int32_t prec, double G
 }
 
 // ---- tuning -----------------------------------------------------------------
-int nbody_set_tuning(int32_t kernel, int32_t prec, int32_t tpl, int32_t jsplit, int32_t jtile)
+int nbody_set_tuning(int32_t kernel, int32_t prec, int32_t tpl, int32_t jsplit, int32_t jtile,
+                     int32_t variant)
 {
     if (kernel < 0 || kernel > 2 || !prec_ok(prec)) {
         set_error("bad kernel or precision");
@@ -911,9 +911,11 @@ int nbody_set_tuning(int32_t kernel, int32_t prec, int32_t tpl, int32_t jsplit, 
     t.tpl = tpl;
     t.jsplit = jsplit;
     t.jtile = jtile;
+    t.variant = variant;
     if (!tune_valid(t) || (prec == NBODY_F64 && tpl == 4) || (kernel == 1 && jsplit != 1) ||
-        (kernel == 2 && tpl == 4)) {
-        set_error("unsupported tuning (tpl %d, jsplit %d, jtile %d)", tpl, jsplit, jtile);
+        (kernel == 2 && tpl == 4) || (variant >= 1 && (kernel != 0 || prec == NBODY_F64))) {
+        set_error("unsupported tuning (tpl %d, jsplit %d, jtile %d, variant %d)", tpl, jsplit, jtile,
+                  variant);
         return NBODY_E_INVAL;
     }
     g_pinned[{kernel, prec}] = t;
@@ -921,9 +923,9 @@ int nbody_set_tuning(int32_t kernel, int32_t prec, int32_t tpl, int32_t jsplit, 
 }
 
 int nbody_get_tuning(int32_t kernel, int32_t prec, int64_t n, int32_t *tpl, int32_t *jsplit,
-                     int32_t *jtile)
+                     int32_t *jtile, int32_t *variant)
 {
-    if (kernel < 0 || kernel > 2 || !prec_ok(prec) || n < 1 || !tpl || !jsplit || !jtile) {
+    if (kernel < 0 || kernel > 2 || !prec_ok(prec) || n < 1 || !tpl || !jsplit || !jtile || !variant) {
         set_error("bad arguments");
         return NBODY_E_INVAL;
     }
@@ -931,6 +933,7 @@ int nbody_get_tuning(int32_t kernel, int32_t prec, int64_t n, int32_t *tpl, int3
     *tpl = t.tpl;
     *jsplit = t.jsplit;
     *jtile = t.jtile;
+    *variant = t.variant;
     return NBODY_OK;
 }
 
@@ -1008,11 +1011,16 @@ extern "C" int nbody_autotune(int32_t kernel, int32_t prec, int64_t n, const int
                     if (js > 1 && n / js < 512) break;
                     const int64_t waves = (n + 64 * tp - 1) / (64 * tp);
                     if (waves * js > 65536 && js > 1) break;
-                    Tune t;
-                    t.tpl = tp;
-                    t.jsplit = js;
-                    t.jtile = jt;
-                    cands.push_back(t);
+                    for (int var = 0; var < 3; ++var) {
+                        if (var >= 1 && (kernel != 0 || prec == NBODY_F64)) continue;
+                        if (var == 2 && (tp != 1 || jt % 256)) continue;
+                        Tune t;
+                        t.tpl = tp;
+                        t.jsplit = js;
+                        t.jtile = jt;
+                        t.variant = var;
+                        cands.push_back(t);
+                    }
                 }
             } else {
                 Tune t;

@@ -509,6 +509,60 @@ __global__ __launch_bounds__(kBlock) void k_axpy(V *__restrict__ y, const V *__r
     ysc[i] = o;
 }
 
+// Split reduction fused with the elementwise step that follows every adjoint
+// VJP, so that one launch finishes the step:
+//   POST 1 (segment recompute):  vbar += dt xbar,  vsc = vbar / m
+//   POST 2 (time reversal):      vh -= hk a;  x -= dt vh;  vbar += dt xbar;
+//                                vsc = vbar / m
+// The stored (rounded) xbar and a are the values used, as in the separate
+// kernels.
+template <typename V, typename MT, typename S, int POST>
+__global__ __launch_bounds__(kBlock) void k_vjp_reduce_post(
+    const double4 *__restrict__ partial, int js, int n, double scale, V *__restrict__ pos_cot,
+    MT *__restrict__ mass_cot, V *__restrict__ x, V *__restrict__ vh, V *__restrict__ vbar,
+    V *__restrict__ vsc, S hk, S dt)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double o[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int s = 0; s < js; ++s) {
+        const double4 *src = partial + 2 * ((long)s * n + i);
+        const double4 a = src[0], b = src[1];
+        o[0] += a.x; o[1] += a.y; o[2] += a.z; o[3] += a.w;
+        o[4] += b.x; o[5] += b.y; o[6] += b.z; o[7] += b.w;
+    }
+    V g = pos_cot[i];
+    g.x = (S)(o[0] * scale + (double)g.x);
+    g.y = (S)(o[1] * scale + (double)g.y);
+    g.z = (S)(o[2] * scale + (double)g.z);
+    g.w = 0;
+    pos_cot[i] = g;
+    mass_cot[i] = (MT)(o[3] * scale + (double)mass_cot[i]);
+    V p = x[i], w = vbar[i];
+    if (POST == 2) {
+        V v = vh[i];
+        const S ax = (S)o[4], ay = (S)o[5], az = (S)o[6];
+        v.x = v.x - hk * ax;
+        v.y = v.y - hk * ay;
+        v.z = v.z - hk * az;
+        p.x = p.x - dt * v.x;
+        p.y = p.y - dt * v.y;
+        p.z = p.z - dt * v.z;
+        vh[i] = v;
+        x[i] = p;
+    }
+    w.x = w.x + dt * g.x;
+    w.y = w.y + dt * g.y;
+    w.z = w.z + dt * g.z;
+    vbar[i] = w;
+    V q;
+    q.x = w.x / p.w;
+    q.y = w.y / p.w;
+    q.z = w.z / p.w;
+    q.w = 0;
+    vsc[i] = q;
+}
+
 // One reverse step of the leapfrog by exact time reversal (scheme used by
 // the reversal adjoint):  given x_{s+1}, the force a_{s+1} and either the
 // synchronised velocity v_{s+1} (first step of a segment) or v_{s+3/2},
@@ -660,6 +714,67 @@ hipError_t go_vjp_adj(const void *pm, const void *raw, const void *sc, const int
     hipLaunchKernelGGL((k_vjp_reduce<V, MT>), dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
                        (const double4 *)partial, t.jsplit, n, scale, 1, (V *)pos_cot,
                        (MT *)mass_cot, (V *)acc_out);
+    return hipGetLastError();
+}
+
+// Adjoint VJP plus its elementwise step (post = 1: vbar update, post = 2:
+// time reversal; x is the position array the VJP was evaluated at and vh
+// the half-step velocity).  With a source split the step runs inside the
+// reduction launch; otherwise as its own kernel after the VJP.
+hipError_t launch_vjp_adj_step(int prec, int post, void *pm, void *raw, void *sc, const int *nonpos,
+                               int n, double G, double eps, double scale, void *pos_cot,
+                               void *mass_cot, void *acc, void *vh, double hk, double dt,
+                               const Tune &t, void *partial, hipStream_t s)
+{
+    if (t.jsplit == 1) {
+        hipError_t e = launch_vjp_adj(prec, pm, raw, sc, nonpos, n, G, eps, scale, pos_cot, mass_cot,
+                                      post == 2 ? acc : nullptr, t, partial, s);
+        if (e != hipSuccess) return e;
+        if (post == 2) return launch_reverse_step(prec, pm, vh, acc, pos_cot, raw, sc, n, hk, dt, s);
+        return launch_adj_axpy(prec, raw, pos_cot, dt, pm, sc, n, s);
+    }
+    // the sweep alone: partial records only (the split path never writes
+    // outputs from the sweep kernel)
+    const dim3 grid((n + kBlock - 1) / kBlock, t.jsplit);
+    if (prec == NBODY_F64) {
+        const double e2 = eps * eps;
+        hipLaunchKernelGGL((k_vjp_adj<double, double4, double, 1>), grid, dim3(kBlock), 0, s,
+                           (const double4 *)pm, (const double4 *)raw, (const double4 *)sc, nonpos, n,
+                           e2, G, t.jtile, scale, 1, (double4 *)pos_cot, (double *)mass_cot,
+                           (double4 *)nullptr, (double4 *)partial);
+    } else {
+        const float e2 = (float)(eps * eps);
+        hipLaunchKernelGGL((k_vjp_adj<float, float4, float, 1>), grid, dim3(kBlock), 0, s,
+                           (const float4 *)pm, (const float4 *)raw, (const float4 *)sc, nonpos, n, e2,
+                           G, t.jtile, scale, 1, (float4 *)pos_cot, (float *)mass_cot,
+                           (float4 *)nullptr, (double4 *)partial);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 rg((n + kBlock - 1) / kBlock);
+    if (prec == NBODY_F64) {
+        if (post == 2)
+            hipLaunchKernelGGL((k_vjp_reduce_post<double4, double, double, 2>), rg, dim3(kBlock), 0, s,
+                               (const double4 *)partial, t.jsplit, n, scale, (double4 *)pos_cot,
+                               (double *)mass_cot, (double4 *)pm, (double4 *)vh, (double4 *)raw,
+                               (double4 *)sc, hk, dt);
+        else
+            hipLaunchKernelGGL((k_vjp_reduce_post<double4, double, double, 1>), rg, dim3(kBlock), 0, s,
+                               (const double4 *)partial, t.jsplit, n, scale, (double4 *)pos_cot,
+                               (double *)mass_cot, (double4 *)pm, (double4 *)vh, (double4 *)raw,
+                               (double4 *)sc, hk, dt);
+    } else {
+        if (post == 2)
+            hipLaunchKernelGGL((k_vjp_reduce_post<float4, float, float, 2>), rg, dim3(kBlock), 0, s,
+                               (const double4 *)partial, t.jsplit, n, scale, (float4 *)pos_cot,
+                               (float *)mass_cot, (float4 *)pm, (float4 *)vh, (float4 *)raw,
+                               (float4 *)sc, (float)hk, (float)dt);
+        else
+            hipLaunchKernelGGL((k_vjp_reduce_post<float4, float, float, 1>), rg, dim3(kBlock), 0, s,
+                               (const double4 *)partial, t.jsplit, n, scale, (float4 *)pos_cot,
+                               (float *)mass_cot, (float4 *)pm, (float4 *)vh, (float4 *)raw,
+                               (float4 *)sc, (float)hk, (float)dt);
+    }
     return hipGetLastError();
 }
 

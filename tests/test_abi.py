@@ -74,16 +74,19 @@ def test_other_entry_points_validate():
     assert L.nbody_orb_order(P(64), 1, 10, 0, P(1024), None) == -1
     assert L.nbody_permute(P(64), P(1024), P(4096), 10, 24, 0, None) == -1
     assert L.nbody_trajectory_forward(P(64), P(1024), 10, 1, 1.0, 0.01, 1e-3, 30, 20, P(4096), None) == -1
-    assert L.nbody_set_tuning(0, 1, 3, 1, 512) == -1
-    assert L.nbody_set_tuning(0, 1, 2, 1, 100) == -1
-    assert L.nbody_set_tuning(1, 1, 2, 4, 512) == -1
+    assert L.nbody_set_tuning(0, 1, 3, 1, 512, 0) == -1
+    assert L.nbody_set_tuning(0, 1, 2, 1, 100, 0) == -1
+    assert L.nbody_set_tuning(1, 1, 2, 4, 512, 0) == -1
+    assert L.nbody_set_tuning(0, 1, 2, 1, 320, 1) == -1   # LDS variant needs jtile % 256 == 0
+    assert L.nbody_set_tuning(0, 0, 1, 1, 512, 1) == -1   # no LDS variant in FP64
+    assert L.nbody_set_tuning(2, 1, 1, 1, 512, 1) == -1   # nor for the VJP
     assert L.nbody_energy(P(64), P(1024), P(4096), 10, 1, None, None) == -1
 
 
 def test_tuning_pin_roundtrip():
     nb, L = _lib()
-    assert L.nbody_set_tuning(0, 2, 4, 8, 1024) == 0
-    assert nb.get_tuning(0, 2, 1 << 20) == (4, 8, 1024)
-    assert L.nbody_set_tuning(0, 2, -1, -1, -1) == 0
+    assert L.nbody_set_tuning(0, 2, 4, 8, 1024, 1) == 0
+    assert nb.get_tuning(0, 2, 1 << 20) == (4, 8, 1024, 1)
+    assert L.nbody_set_tuning(0, 2, -1, -1, -1, 0) == 0
     t = nb.get_tuning(0, 2, 1 << 20)
-    assert t[0] in (1, 2, 4) and t[2] % 8 == 0
+    assert t[0] in (1, 2, 4) and t[2] % 8 == 0 and t[3] in (0, 1)
