@@ -88,10 +88,28 @@ def main():
         log("[bench] counters mode: 2 force launches, 1 GiB copy (1073741824 B read + written)")
         return
 
-    # first evaluation (step 0 forces, kept for the accuracy check)
+    # ORB body order (the paper's recursive bisection, used as an ordering):
+    # timed once, then the state is gathered into that order
+    e_a, e_b, e_c = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    torch.cuda.synchronize()
+    e_a.record()
+    perm = nb.orb_order(pm, 256)
+    e_b.record()
+    pm = nb.permute(pm, perm)
+    vel = nb.permute(vel, perm)
+    e_c.record()
+    torch.cuda.synchronize()
+    orb_ms, gather_ms = e_a.elapsed_time(e_b), e_b.elapsed_time(e_c)
+    perm_host = perm.cpu().numpy()
+    log(f"[bench] ORB order {orb_ms:.2f} ms, gather {gather_ms:.3f} ms")
+
+    # first evaluation (step 0 forces, kept for the accuracy check, returned
+    # to the input order)
     nb.accel(pm, eps, prec=prec, out=acc)
     torch.cuda.synchronize()
-    acc0 = acc.cpu().double().numpy()
+    acc0 = np.empty((n, 4))
+    acc0[perm_host] = acc.cpu().double().numpy()
+    energy0 = nb.energy(pm, vel, acc, prec=prec).cpu().numpy()
     h = 0.5 * dt
     nb.kick_drift(pm, vel, acc, h, dt, close=False, open=True, prec=prec)
 
@@ -120,6 +138,12 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     total_ms = t_start.elapsed_time(t_end)
+    # FP64 energy at the final synchronised state: the loop leaves
+    # (x_{m+1}, v_{m+1/2}); one more force and a closing half kick give v_{m+1}
+    nb.accel(pm, eps, prec=prec, out=acc)
+    nb.kick_drift(pm, vel, acc, h, dt, close=True, open=False, prec=prec)
+    energy1 = nb.energy(pm, vel, acc, prec=prec).cpu().numpy()
+    torch.cuda.synchronize()
     ms_per_step = total_ms / args.steps
     kern_ms = [a.elapsed_time(b) for a, b in ev]
     kern_avg = float(np.mean(kern_ms))
@@ -150,8 +174,13 @@ def main():
                                     "variant": ["scalar-load sources", "LDS sources"][tune[3]]}},
         "pct_fp32_peak": round(100 * achieved / PEAK_FP32_TFLOPS, 2),
         "wall_s_timed": round(wall, 3),
+        "orb": {"leaf": 256, "order_ms": round(orb_ms, 3), "gather_ms": round(gather_ms, 3)},
+        "energy_fp64": {"E0": float(energy0.sum()), "E_end": float(energy1.sum()),
+                        "rel_change": float(energy1.sum() / energy0.sum() - 1.0),
+                        "steps": args.steps + args.warmup + 1},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                     "traffic": measured_traffic(tune, n),
                      "kernel": ("k_accel_lds_f32" if tune[3] else "k_accel_f32") + f"<{tune[0]}, F64ACC>",
                      "flop_per_pair": FLOP_PER_PAIR,
                      "avg_launch_ms": round(kern_avg, 4)},
@@ -162,6 +191,21 @@ def main():
         result["batched"] = batched_leg(torch, nb, ics, dev)
         result["cpu_baseline"] = cpu_leg(ics, pm0_host, acc0, eps, args.cpu_seconds)
     print(json.dumps(result), flush=True)
+
+
+def measured_traffic(tune, n):
+    """HBM bytes per force launch from the committed rocprofv3 counter
+    summary, if it was taken on the kernel shape in use now; else None."""
+    path = os.path.join(ROOT, "profiles", "k_accel_f32_collide1m_pmc.md")
+    try:
+        for line in open(path):
+            if line.startswith("traffic_record:"):
+                rec = json.loads(line.split(":", 1)[1])
+                if rec["shape"] == list(tune) and rec["n"] == n:
+                    return rec["bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        pass
+    return None
 
 
 def adjoint_leg(torch, nb, ics, dev):
