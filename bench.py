@@ -187,6 +187,7 @@ def main():
     }
 
     if not args.no_extras:
+        result["fp64"] = fp64_leg(torch, nb, ics, dev)
         result["adjoint"] = adjoint_leg(torch, nb, ics, dev)
         result["batched"] = batched_leg(torch, nb, ics, dev)
         result["cpu_baseline"] = cpu_leg(ics, pm0_host, acc0, eps, args.cpu_seconds)
@@ -206,6 +207,30 @@ def measured_traffic(tune, n):
     except (OSError, ValueError, KeyError):
         pass
     return None
+
+
+def fp64_leg(torch, nb, ics, dev):
+    """FP64 force evaluation (FP64 pair arithmetic and sums) on a Plummer
+    sphere of 2^17 bodies."""
+    n = 1 << 17
+    pm_np, _ = ics.plummer(n, 1006)
+    p = torch.as_tensor(pm_np, dtype=torch.float64, device=dev).contiguous()
+    out = torch.empty_like(p)
+    nb.accel(p, 0.01, out=out)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(3):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        nb.accel(p, 0.01, out=out)
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    ms = float(np.median(ts))
+    g = float(n) * n / (ms * 1e-3) / 1e9
+    log(f"[bench] fp64: {ms:.2f} ms per evaluation at N={n}, {g:.1f} Gint/s")
+    return {"workload": "Plummer N=131072, NBODY_F64, eps=0.01", "ms": round(ms, 3),
+            "g_interactions_per_s": round(g, 2), "shape": list(nb.get_tuning(0, nb.F64, n))}
 
 
 def adjoint_leg(torch, nb, ics, dev):

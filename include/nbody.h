@@ -27,7 +27,11 @@
  * - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *   Every call is stream-ordered and asynchronous: it validates its
  *   arguments on the host, enqueues kernels and returns.  No call below
- *   synchronises the device except nbody_autotune().
+ *   synchronises the device except nbody_autotune(), nbody_release(), and a
+ *   call that needs more library scratch than any earlier call on the device
+ *   (growing a scratch buffer waits for the work that may still use it).
+ *   Calls that share library scratch (the same entry point on one device)
+ *   must not run concurrently on different streams.
  * - Return value: NBODY_OK (0) or a negative status.  On a validation error
  *   nothing has been enqueued.  nbody_last_error() gives a thread-local
  *   message for the last failing call.  The library never aborts or exits.
@@ -212,9 +216,11 @@ int nbody_trajectory_adjoint(const void *ckpt, int64_t n, int32_t prec, double G
  * nbody_set_tuning pins a shape for later calls: tpl (targets per lane:
  * 1, 2, 4), jsplit (independent source ranges per target, 1..32, reduced in
  * fixed order; kernel 1 takes 1), jtile (sources per partial sum, multiple
- * of 8), variant (0: source records through scalar loads; 1: staged in LDS,
- * FP32 force kernel only, jtile a multiple of 256; both give identical
- * results); kernel and prec as above; tpl = jsplit = jtile = -1 clears it.
+ * of 8), variant (FP32 force kernel only, apart from 0: 0 = source records
+ * through scalar loads; 1 = staged in LDS, jtile a multiple of 256, identical
+ * results to 0; 2 = the source contraction on the matrix cores, tpl 1, jtile
+ * a multiple of 256, accurate to about 1e-6 in ORB order); kernel and prec as
+ * above; tpl = jsplit = jtile = -1 clears it.
  * nbody_get_tuning reports the shape the library would use.
  */
 int nbody_autotune(int32_t kernel, int32_t prec, int64_t n, const int64_t *offsets_host,

@@ -696,7 +696,7 @@ __global__ __launch_bounds__(kBlock) void k_split_reduce_f32(const float4 *__res
 // bit for bit.  The wave that finishes last returns both counters to zero,
 // which keeps repeated launches and graph replays self-contained.
 template <int TPL, int MODE>
-__global__ __launch_bounds__(kBlock) void k_batched_f32(const float4 *__restrict__ pm,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_batched_f32(const float4 *__restrict__ pm,
                                                         const int64_t *__restrict__ offsets,
                                                         const int2 *__restrict__ units, int nunits,
                                                         const float *__restrict__ eps_sys,

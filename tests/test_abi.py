@@ -90,3 +90,24 @@ def test_tuning_pin_roundtrip():
     assert L.nbody_set_tuning(0, 2, -1, -1, -1, 0) == 0
     t = nb.get_tuning(0, 2, 1 << 20)
     assert t[0] in (1, 2, 4) and t[2] % 8 == 0 and t[3] in (0, 1)
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without the built library the binding raises instead of computing
+    anything elsewhere."""
+    import subprocess, sys
+    code = r"""
+import sys
+sys.path.insert(0, %r)
+import paper_1211_2292_amd as nb
+nb.LIB_PATH = %r
+try:
+    nb.lib()
+except nb.NBodyError as e:
+    print("raised:", e)
+    sys.exit(0)
+sys.exit(3)
+""" % (ROOT, str(tmp_path / "missing.so"))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "not built" in r.stdout
