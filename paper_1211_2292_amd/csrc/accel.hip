@@ -143,9 +143,10 @@ __device__ __forceinline__ void range_f32(const float4 *__restrict__ src, int j0
 // component (ax, ay, az, sum m rho) through `res`.
 template <int TPL, int MODE>
 __device__ __forceinline__ void wave_f32(const float4 *__restrict__ src, int n, int t0, int jb,
-                                         int je, int jtile, float eps2, double (&res)[TPL][4])
+                                         int je, int jtile, float eps2_in, double (&res)[TPL][4])
 {
     const int lane = threadIdx.x & 63;
+    const float eps2 = lane_copy(eps2_in);
     Targets<float, TPL> T;
 #pragma unroll
     for (int t = 0; t < TPL; ++t) {
@@ -318,10 +319,11 @@ __device__ __forceinline__ void sweep_lds(const float4 *tl, int jbase, int u0, i
 // indices as in the scalar-load sweep.
 template <int TPL, int MODE>
 __device__ __forceinline__ void block_lds_f32(const float4 *__restrict__ src, int n, int t0, int jb,
-                                              int je, int jtile, float eps2, float4 (*tile)[kLdsTile],
-                                              double (&res)[TPL][4])
+                                              int je, int jtile, float eps2_in,
+                                              float4 (*tile)[kLdsTile], double (&res)[TPL][4])
 {
     const int lane = threadIdx.x & 63;
+    const float eps2 = lane_copy(eps2_in);
     Targets<float, TPL> T;
 #pragma unroll
     for (int t = 0; t < TPL; ++t) {

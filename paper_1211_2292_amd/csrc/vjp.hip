@@ -31,6 +31,13 @@ namespace {
 
 constexpr int kVjpUnroll = 4;
 
+// eps^2 is kept in a vector register in FP32 (see lane_copy); FP64 keeps the
+// compiler's choice.
+template <typename T>
+__device__ __forceinline__ T lane_copy_t(T x) { return x; }
+template <>
+__device__ __forceinline__ float lane_copy_t<float>(float x) { return lane_copy(x); }
+
 template <typename T, int TPL, bool PHI>
 struct VAcc {
     T P[TPL][3], Q[TPL][3], M[TPL], A[TPL][3], F[TPL];
@@ -187,7 +194,7 @@ __device__ __forceinline__ void apply_out(double (&o)[8], double scale, int accu
 
 template <typename T, typename V, typename MT, int TPL, bool PHI>
 __device__ __forceinline__ void vjp_general(const V *__restrict__ pm, const V *__restrict__ cot,
-                                            int n, T eps2, double G, int jtile, double scale,
+                                            int n, T eps2_in, double G, int jtile, double scale,
                                             int accumulate, V *__restrict__ pos_cot,
                                             MT *__restrict__ mass_cot, V *__restrict__ acc_out,
                                             double4 *__restrict__ partial)
@@ -197,6 +204,7 @@ __device__ __forceinline__ void vjp_general(const V *__restrict__ pm, const V *_
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int t0 = (blockIdx.x * (kBlock / 64) + wave) * WT;
     if (t0 >= n) return;
+    const T eps2 = lane_copy_t(eps2_in);
     // source range of this split
     const long per = ((long)n + gridDim.y - 1) / gridDim.y;
     const int jb = (int)min((long)n, (long)blockIdx.y * per);
@@ -350,7 +358,7 @@ __device__ __forceinline__ void ssweep(const V *__restrict__ pm, const V *__rest
 
 template <typename T, typename V, typename MT, int TPL>
 __device__ __forceinline__ void vjp_scaled(const V *__restrict__ pm, const V *__restrict__ sc,
-                                           int n, T eps2, double G, int jtile, double scale,
+                                           int n, T eps2_in, double G, int jtile, double scale,
                                            int accumulate, V *__restrict__ pos_cot,
                                            MT *__restrict__ mass_cot, V *__restrict__ acc_out,
                                            double4 *__restrict__ partial)
@@ -360,6 +368,7 @@ __device__ __forceinline__ void vjp_scaled(const V *__restrict__ pm, const V *__
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int t0 = (blockIdx.x * (kBlock / 64) + wave) * WT;
     if (t0 >= n) return;
+    const T eps2 = lane_copy_t(eps2_in);
     const long per = ((long)n + gridDim.y - 1) / gridDim.y;
     const int jb = (int)min((long)n, (long)blockIdx.y * per);
     const int je = (int)min((long)n, (long)jb + per);
