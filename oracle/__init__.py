@@ -69,6 +69,18 @@ def _load():
         lib.oracle_traj_grad.argtypes = [ctypes.c_int64, _d, _d, _d, _d, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_double, ctypes.c_int32, _d, _d, _d]
         lib.oracle_traj_grad.restype = ctypes.c_double
+        lib.oracle_tree_nodes.argtypes = [ctypes.c_int64, ctypes.c_int32, _i64]
+        lib.oracle_tree_nodes.restype = ctypes.c_int64
+        lib.oracle_tree_moments.argtypes = [ctypes.c_int64, ctypes.c_int32, _d, _d, _d, _d, _d, _d, _d]
+        lib.oracle_tree_moments.restype = ctypes.c_int
+        lib.oracle_tree_num_groups.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]
+        lib.oracle_tree_num_groups.restype = ctypes.c_int64
+        lib.oracle_tree_lists.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _d, _d, ctypes.c_double,
+                                          _i64, _i64, _i64, _i32, ctypes.c_int64, _i32, ctypes.c_int64]
+        lib.oracle_tree_lists.restype = ctypes.c_int
+        lib.oracle_tree_accel.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _d, _d, ctypes.c_double,
+                                          ctypes.c_double, ctypes.c_double, ctypes.c_int64, _i64, _d, _d]
+        lib.oracle_tree_accel.restype = ctypes.c_int
         lib.oracle_num_threads.argtypes = []
         lib.oracle_num_threads.restype = ctypes.c_int
         _lib = lib
@@ -186,3 +198,88 @@ def traj_grad(pos_mass, vel, y, eps: float, dt: float, nsteps: int, G: float = 1
     L = lib.oracle_traj_grad(n, _ptr(x, _d), _ptr(v, _d), _ptr(m, _d), _ptr(yy, _d), float(G), float(eps),
                              float(dt), int(nsteps), _ptr(gx, _d), _ptr(gv, _d), _ptr(gm, _d))
     return float(L), gx, gv, gm
+
+
+# ---- tree code on the ORB cells (Section IV.A walk, Section IV.B cells) ----
+# All tree functions take bodies already in ORB order (``orb_order`` with the
+# same leaf, then a gather).  Groups are the maximal nodes of at most
+# ``group`` bodies, in ORB order.
+
+def tree_nodes(n: int, leaf: int) -> np.ndarray:
+    """Node table (nn, 4) = (begin, end, left, right) of the ORB recursion in
+    preorder; left = right = -1 for a leaf."""
+    lib = _load()
+    nn = int(lib.oracle_tree_nodes(int(n), int(leaf), None))
+    if nn < 1:
+        raise ValueError("oracle_tree_nodes: bad arguments")
+    nodes = np.empty((nn, 4), dtype=np.int64)
+    lib.oracle_tree_nodes(int(n), int(leaf), _ptr(nodes, _i64))
+    return nodes
+
+
+def tree_moments(pos_mass_orb, leaf: int):
+    """Monopole moments of every node: dict(mass (nn,), com (nn, 3), lo, hi
+    (nn, 3), diag2 (nn,)), FP64 in the fixed summation order of the C file."""
+    lib = _load()
+    x, m = _split(pos_mass_orb)
+    n = x.shape[0]
+    nn = tree_nodes(n, leaf).shape[0]
+    out = dict(mass=np.empty(nn), com=np.empty((nn, 3)), lo=np.empty((nn, 3)), hi=np.empty((nn, 3)),
+               diag2=np.empty(nn))
+    rc = lib.oracle_tree_moments(n, int(leaf), _ptr(x, _d), _ptr(m, _d), _ptr(out["mass"], _d),
+                                 _ptr(out["com"], _d), _ptr(out["lo"], _d), _ptr(out["hi"], _d),
+                                 _ptr(out["diag2"], _d))
+    if rc != 0:
+        raise ValueError("oracle_tree_moments failed")
+    return out
+
+
+def tree_lists(pos_mass_orb, leaf: int, group: int, theta: float):
+    """Interaction lists of every group (Section IV.A walk): dict(group_id,
+    far_cnt, near_cnt (ngroups,), far, near (concatenated node ids in walk
+    order))."""
+    lib = _load()
+    x, m = _split(pos_mass_orb)
+    n = x.shape[0]
+    ng = int(lib.oracle_tree_num_groups(n, int(leaf), int(group)))
+    if ng < 1:
+        raise ValueError("oracle_tree_num_groups: bad arguments")
+    gid = np.empty(ng, dtype=np.int64)
+    fc = np.empty(ng, dtype=np.int64)
+    nc = np.empty(ng, dtype=np.int64)
+    rc = lib.oracle_tree_lists(n, int(leaf), int(group), _ptr(x, _d), _ptr(m, _d), float(theta), _ptr(gid, _i64),
+                               _ptr(fc, _i64), _ptr(nc, _i64), None, 0, None, 0)
+    if rc != 0:
+        raise ValueError("oracle_tree_lists: bad arguments")
+    far = np.empty(max(int(fc.sum()), 1), dtype=np.int32)
+    near = np.empty(max(int(nc.sum()), 1), dtype=np.int32)
+    rc = lib.oracle_tree_lists(n, int(leaf), int(group), _ptr(x, _d), _ptr(m, _d), float(theta), _ptr(gid, _i64),
+                               _ptr(fc, _i64), _ptr(nc, _i64), _ptr(far, _i32), far.shape[0], _ptr(near, _i32),
+                               near.shape[0])
+    if rc != 0:
+        raise ValueError("oracle_tree_lists failed")
+    return dict(group_id=gid, far_cnt=fc, near_cnt=nc, far=far[:int(fc.sum())], near=near[:int(nc.sum())])
+
+
+def tree_accel(pos_mass_orb, leaf: int, group: int, theta: float, eps: float, G: float = 1.0, targets=None):
+    """Tree-code force and potential (Section IV.A) on the ORB cells: far
+    cells as monopoles, near leaves body by body.  Returns (acc (T, 3),
+    pot (T,)) for ORB positions ``targets`` (all when None)."""
+    lib = _load()
+    x, m = _split(pos_mass_orb)
+    n = x.shape[0]
+    if targets is None:
+        nt, tp = n, None
+    else:
+        tp = np.ascontiguousarray(np.asarray(targets, dtype=np.int64))
+        if tp.size and (tp.min() < 0 or tp.max() >= n):
+            raise IndexError("target index out of range")
+        nt = tp.shape[0]
+    acc = np.empty((nt, 3))
+    pot = np.empty(nt)
+    rc = lib.oracle_tree_accel(n, int(leaf), int(group), _ptr(x, _d), _ptr(m, _d), float(G), float(eps),
+                               float(theta), nt, None if tp is None else _ptr(tp, _i64), _ptr(acc, _d),
+                               _ptr(pot, _d))
+    if rc != 0:
+        raise ValueError("oracle_tree_accel failed")
+    return acc, pot

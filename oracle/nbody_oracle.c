@@ -39,6 +39,12 @@
  *                    has no derivatives).
  *   oracle_traj_grad Reverse mode through oracle_leapfrog for the loss
  *                    L = sum_i |x_i(T) - y_i|^2, storing every state.
+ *   oracle_tree_*    Section IV.A tree code (cells replaced by their total
+ *                    mass at their centre of mass when distant enough, found
+ *                    by a walk from the root) on the cells of the Section
+ *                    IV.B ORB recursion: node table, moments, interaction
+ *                    lists and the resulting force; the readings are stated
+ *                    above those functions.
  *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared (no fast-math;
  * contraction off so that every product and sum rounds as written).
@@ -394,4 +400,409 @@ double oracle_traj_grad(int64_t n, const double *x0, const double *v0, const dou
     const double out = nsum_val(&L);
     free(xs); free(v); free(a); free(abar); free(tx); free(tm);
     return out;
+}
+
+/* ---------------------------------------------------------------------------
+ * Tree code on the ORB hierarchy.
+ *
+ * Section IV.A: a distant group of bodies is replaced by one body of the
+ * group's total mass at its centre of mass; the force on a body is found by
+ * walking the tree from the root, adding a cell to the interaction list when
+ * it is distant enough and otherwise visiting its children, then summing over
+ * the list of cells and bodies.  Section IV.B: the space is divided by ORB.
+ * Here the cells are the nodes of the ORB recursion itself (the readings
+ * below are this library's, the paper fixes none of them):
+ *
+ *   nodes     node k covers ORB positions [begin, end); a node of more than
+ *             `leaf` bodies splits at begin + leaf*ceil(L/2), L =
+ *             ceil(size/leaf), exactly as in oracle_orb_order.  Nodes are
+ *             numbered in preorder (node, left subtree, right subtree).
+ *   groups    the targets are taken in groups: the maximal nodes of at
+ *             most `group` bodies (group >= leaf), in ORB order.  One walk
+ *             serves every body of a group.
+ *   moments   in FP64 from the FP32 inputs: a leaf sums m and m*x over its
+ *             positions in order starting from 0 (product rounded, then
+ *             added); an inner node adds left + right.  com = (sum m x) / M,
+ *             or the box centre 0.5*(lo + hi) when M = 0.  The box lo/hi is
+ *             the exact coordinate minimum/maximum; diag2 = sum over axes of
+ *             (hi - lo)^2, axes in order x, y, z.
+ *   opening   cell c is accepted for group g iff c and g share no body
+ *             (neither contains the other) and
+ *             diag2_c < theta^2 * D2, where D2 is the squared distance from
+ *             com_c to the box of g (per axis lo - com if com < lo, com - hi
+ *             if com > hi, else 0; summed x, y, z).  Every body of g is then
+ *             at least D = sqrt(D2) from com_c while every body of c lies
+ *             within sqrt(diag2_c) of it, so the ratio of cell size to
+ *             distance is below theta for each body of the group.
+ *   walk      visit(c): accept -> far list; else a leaf -> near list; else
+ *             visit(left), visit(right).  Starts at the root.
+ *   force     far cells act as a body of mass M at com (same softened law);
+ *             near leaves act body by body, skipping the target itself.
+ * theta = 0 never accepts a cell, so the tree force is the direct sum.
+ * Masses must be non-negative.
+ * ------------------------------------------------------------------------- */
+static int64_t tree_count_rec(int64_t size, int32_t leaf)
+{
+    if (size <= leaf)
+        return 1;
+    const int64_t L = (size + leaf - 1) / leaf;
+    int64_t k = (int64_t)leaf * ((L + 1) / 2);
+    if (k > size)
+        k = size;
+    return 1 + tree_count_rec(k, leaf) + tree_count_rec(size - k, leaf);
+}
+
+static int64_t tree_build_rec(int64_t b, int64_t size, int32_t leaf, int64_t *nodes, int64_t *next)
+{
+    const int64_t id = (*next)++;
+    nodes[4 * id] = b;
+    nodes[4 * id + 1] = b + size;
+    if (size <= leaf) {
+        nodes[4 * id + 2] = -1;
+        nodes[4 * id + 3] = -1;
+        return id;
+    }
+    const int64_t L = (size + leaf - 1) / leaf;
+    int64_t k = (int64_t)leaf * ((L + 1) / 2);
+    if (k > size)
+        k = size;
+    const int64_t l = tree_build_rec(b, k, leaf, nodes, next);
+    const int64_t r = tree_build_rec(b + k, size - k, leaf, nodes, next);
+    nodes[4 * id + 2] = l;
+    nodes[4 * id + 3] = r;
+    return id;
+}
+
+/* Returns the node count; fills nodes[nn][4] = (begin, end, left, right) when
+ * nodes is not NULL (left = right = -1 for a leaf). */
+int64_t oracle_tree_nodes(int64_t n, int32_t leaf, int64_t *nodes)
+{
+    if (n < 1 || leaf < 1)
+        return -1;
+    const int64_t nn = tree_count_rec(n, leaf);
+    if (nodes) {
+        int64_t next = 0;
+        tree_build_rec(0, n, leaf, nodes, &next);
+    }
+    return nn;
+}
+
+/* Moments of every node.  x: [n][3], m: [n] in ORB order (FP32 values widened
+ * to FP64).  mass: [nn], com: [nn][3], lo/hi: [nn][3], diag2: [nn]. */
+static void tree_moments_rec(const int64_t *nodes, int64_t id, const double *x, const double *m,
+                             double *mass, double *sx, double *lo, double *hi)
+{
+    const int64_t b = nodes[4 * id], e = nodes[4 * id + 1];
+    const int64_t l = nodes[4 * id + 2], r = nodes[4 * id + 3];
+    if (l < 0) {
+        double M = 0.0, s[3] = {0.0, 0.0, 0.0};
+        for (int k = 0; k < 3; ++k)
+            lo[3 * id + k] = hi[3 * id + k] = x[3 * b + k];
+        for (int64_t p = b; p < e; ++p) {
+            M = M + m[p];
+            for (int k = 0; k < 3; ++k) {
+                const double c = x[3 * p + k];
+                const double mc = m[p] * c;
+                s[k] = s[k] + mc;
+                if (c < lo[3 * id + k])
+                    lo[3 * id + k] = c;
+                if (c > hi[3 * id + k])
+                    hi[3 * id + k] = c;
+            }
+        }
+        mass[id] = M;
+        for (int k = 0; k < 3; ++k)
+            sx[3 * id + k] = s[k];
+        return;
+    }
+    tree_moments_rec(nodes, l, x, m, mass, sx, lo, hi);
+    tree_moments_rec(nodes, r, x, m, mass, sx, lo, hi);
+    mass[id] = mass[l] + mass[r];
+    for (int k = 0; k < 3; ++k) {
+        sx[3 * id + k] = sx[3 * l + k] + sx[3 * r + k];
+        lo[3 * id + k] = lo[3 * l + k] < lo[3 * r + k] ? lo[3 * l + k] : lo[3 * r + k];
+        hi[3 * id + k] = hi[3 * l + k] > hi[3 * r + k] ? hi[3 * l + k] : hi[3 * r + k];
+    }
+}
+
+int oracle_tree_moments(int64_t n, int32_t leaf, const double *x, const double *m, double *mass,
+                        double *com, double *lo, double *hi, double *diag2)
+{
+    const int64_t nn = oracle_tree_nodes(n, leaf, NULL);
+    if (nn < 1)
+        return -1;
+    int64_t *nodes = (int64_t *)malloc((size_t)nn * 4 * sizeof(int64_t));
+    double *sx = (double *)malloc((size_t)nn * 3 * sizeof(double));
+    if (!nodes || !sx) {
+        free(nodes);
+        free(sx);
+        return -1;
+    }
+    oracle_tree_nodes(n, leaf, nodes);
+    tree_moments_rec(nodes, 0, x, m, mass, sx, lo, hi);
+    for (int64_t id = 0; id < nn; ++id) {
+        for (int k = 0; k < 3; ++k) {
+            if (mass[id] > 0.0)
+                com[3 * id + k] = sx[3 * id + k] / mass[id];
+            else
+                com[3 * id + k] = 0.5 * (lo[3 * id + k] + hi[3 * id + k]);
+        }
+        double d2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const double ext = hi[3 * id + k] - lo[3 * id + k];
+            d2 = d2 + ext * ext;
+        }
+        diag2[id] = d2;
+    }
+    free(nodes);
+    free(sx);
+    return 0;
+}
+
+typedef struct {
+    const int64_t *nodes;
+    const double *com, *lo, *hi, *diag2;
+    double theta2;
+} tree_ctx;
+
+static int tree_accept(const tree_ctx *t, int64_t c, int64_t g)
+{
+    const int64_t *nc = t->nodes + 4 * c, *ng = t->nodes + 4 * g;
+    if (nc[0] < ng[1] && ng[0] < nc[1])
+        return 0; /* c and the group overlap: c contains it or lies inside it */
+    double d[3];
+    for (int k = 0; k < 3; ++k) {
+        const double p = t->com[3 * c + k];
+        const double a = t->lo[3 * g + k], b = t->hi[3 * g + k];
+        d[k] = p < a ? a - p : (p > b ? p - b : 0.0);
+    }
+    const double D2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+    return t->diag2[c] < t->theta2 * D2;
+}
+
+/* Walk for group node g; appends to far/near (either may be NULL to count). */
+static void tree_walk_rec(const tree_ctx *t, int64_t c, int64_t g, int32_t *far, int64_t *nf,
+                          int32_t *near, int64_t *nnr)
+{
+    if (tree_accept(t, c, g)) {
+        if (far)
+            far[*nf] = (int32_t)c;
+        ++*nf;
+        return;
+    }
+    const int64_t l = t->nodes[4 * c + 2], r = t->nodes[4 * c + 3];
+    if (l < 0) {
+        if (near)
+            near[*nnr] = (int32_t)c;
+        ++*nnr;
+        return;
+    }
+    tree_walk_rec(t, l, g, far, nf, near, nnr);
+    tree_walk_rec(t, r, g, far, nf, near, nnr);
+}
+
+typedef struct {
+    int64_t nn, ngroups;
+    int64_t *nodes, *group_node;
+    double *mass, *com, *lo, *hi, *diag2;
+} tree_data;
+
+/* Collects the groups under node id in preorder. */
+static void tree_groups_rec(const int64_t *nodes, int64_t id, int64_t group, int64_t *out, int64_t *cnt)
+{
+    const int64_t size = nodes[4 * id + 1] - nodes[4 * id];
+    if (size <= group || nodes[4 * id + 2] < 0) {
+        if (out)
+            out[*cnt] = id;
+        ++*cnt;
+        return;
+    }
+    tree_groups_rec(nodes, nodes[4 * id + 2], group, out, cnt);
+    tree_groups_rec(nodes, nodes[4 * id + 3], group, out, cnt);
+}
+
+static void tree_free(tree_data *d)
+{
+    free(d->nodes);
+    free(d->group_node);
+    free(d->mass);
+    free(d->com);
+    free(d->lo);
+    free(d->hi);
+    free(d->diag2);
+}
+
+static int tree_setup(int64_t n, int32_t leaf, int32_t group, const double *x, const double *m,
+                      tree_data *d)
+{
+    memset(d, 0, sizeof *d);
+    if (group < leaf)
+        return -1;
+    d->nn = oracle_tree_nodes(n, leaf, NULL);
+    if (d->nn < 1)
+        return -1;
+    d->nodes = (int64_t *)malloc((size_t)d->nn * 4 * sizeof(int64_t));
+    d->group_node = (int64_t *)malloc((size_t)d->nn * sizeof(int64_t));
+    d->mass = (double *)malloc((size_t)d->nn * sizeof(double));
+    d->com = (double *)malloc((size_t)d->nn * 3 * sizeof(double));
+    d->lo = (double *)malloc((size_t)d->nn * 3 * sizeof(double));
+    d->hi = (double *)malloc((size_t)d->nn * 3 * sizeof(double));
+    d->diag2 = (double *)malloc((size_t)d->nn * sizeof(double));
+    if (!d->nodes || !d->group_node || !d->mass || !d->com || !d->lo || !d->hi || !d->diag2) {
+        tree_free(d);
+        return -1;
+    }
+    oracle_tree_nodes(n, leaf, d->nodes);
+    d->ngroups = 0;
+    tree_groups_rec(d->nodes, 0, group, d->group_node, &d->ngroups);
+    return oracle_tree_moments(n, leaf, x, m, d->mass, d->com, d->lo, d->hi, d->diag2);
+}
+
+/* Number of groups (see above), or -1 on bad arguments. */
+int64_t oracle_tree_num_groups(int64_t n, int32_t leaf, int32_t group)
+{
+    if (n < 1 || leaf < 1 || group < leaf)
+        return -1;
+    const int64_t nn = oracle_tree_nodes(n, leaf, NULL);
+    int64_t *nodes = (int64_t *)malloc((size_t)nn * 4 * sizeof(int64_t));
+    if (!nodes)
+        return -1;
+    oracle_tree_nodes(n, leaf, nodes);
+    int64_t cnt = 0;
+    tree_groups_rec(nodes, 0, group, NULL, &cnt);
+    free(nodes);
+    return cnt;
+}
+
+/* Interaction lists of every group, in walk order.  group_id: [ngroups] node
+ * id of each group (may be NULL).  far_cnt/near_cnt: [ngroups].  far/near: concatenated lists in group order (NULL to count
+ * only; capacities far_cap/near_cap).  Returns 0, or -1 on bad arguments or a
+ * list longer than its capacity. */
+int oracle_tree_lists(int64_t n, int32_t leaf, int32_t group, const double *x, const double *m,
+                      double theta, int64_t *group_id, int64_t *far_cnt, int64_t *near_cnt, int32_t *far,
+                      int64_t far_cap, int32_t *near, int64_t near_cap)
+{
+    if (!(theta >= 0.0) || !far_cnt || !near_cnt)
+        return -1;
+    tree_data d;
+    if (tree_setup(n, leaf, group, x, m, &d) != 0)
+        return -1;
+    if (group_id)
+        memcpy(group_id, d.group_node, (size_t)d.ngroups * sizeof(int64_t));
+    tree_ctx t = {d.nodes, d.com, d.lo, d.hi, d.diag2, theta * theta};
+    int64_t of = 0, on = 0;
+    int rc = 0;
+    for (int64_t g = 0; g < d.ngroups; ++g) {
+        int64_t nf = 0, nnr = 0;
+        tree_walk_rec(&t, 0, d.group_node[g], NULL, &nf, NULL, &nnr);
+        far_cnt[g] = nf;
+        near_cnt[g] = nnr;
+        if (far || near) {
+            if (of + nf > far_cap || on + nnr > near_cap) {
+                rc = -1;
+                break;
+            }
+            int64_t a = 0, b = 0;
+            tree_walk_rec(&t, 0, d.group_node[g], far ? far + of : NULL, &a, near ? near + on : NULL, &b);
+        }
+        of += nf;
+        on += nnr;
+    }
+    tree_free(&d);
+    return rc;
+}
+
+/* Tree force and potential on targets (ORB positions; NULL = all n).
+ * acc: [ntarg][3], pot: [ntarg].  Neumaier-compensated FP64 sums over the
+ * far cells in list order, then the near bodies in list order. */
+int oracle_tree_accel(int64_t n, int32_t leaf, int32_t group, const double *x, const double *m, double G,
+                      double eps, double theta, int64_t ntarg, const int64_t *targets, double *acc,
+                      double *pot)
+{
+    if (!(theta >= 0.0))
+        return -1;
+    tree_data d;
+    if (tree_setup(n, leaf, group, x, m, &d) != 0)
+        return -1;
+    tree_ctx tc = {d.nodes, d.com, d.lo, d.hi, d.diag2, theta * theta};
+    /* group of every position */
+    int64_t *gof = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    if (!gof) {
+        tree_free(&d);
+        return -1;
+    }
+    for (int64_t q = 0; q < d.ngroups; ++q)
+        for (int64_t p = d.nodes[4 * d.group_node[q]]; p < d.nodes[4 * d.group_node[q] + 1]; ++p)
+            gof[p] = d.group_node[q];
+    const double eps2 = eps * eps;
+    int bad = 0;
+    int64_t t;
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : bad)
+    for (t = 0; t < ntarg; ++t) {
+        const int64_t i = targets ? targets[t] : t;
+        const int64_t g = gof[i];
+        int64_t nf = 0, nnr = 0;
+        tree_walk_rec(&tc, 0, g, NULL, &nf, NULL, &nnr);
+        int32_t *far = (int32_t *)malloc((size_t)(nf + 1) * sizeof(int32_t));
+        int32_t *near = (int32_t *)malloc((size_t)(nnr + 1) * sizeof(int32_t));
+        if (!far || !near) {
+            free(far);
+            free(near);
+            bad = 1;
+            continue;
+        }
+        int64_t a = 0, b = 0;
+        tree_walk_rec(&tc, 0, g, far, &a, near, &b);
+        const double xi = x[3 * i], yi = x[3 * i + 1], zi = x[3 * i + 2];
+        nsum ax = {0, 0}, ay = {0, 0}, az = {0, 0}, ph = {0, 0};
+        for (int64_t q = 0; q < nf + nnr; ++q) {
+            int64_t jb, je;
+            const double *src;
+            const double *ms;
+            double cm;
+            if (q < nf) {
+                const int64_t c = far[q];
+                src = d.com + 3 * c;
+                cm = d.mass[c];
+                ms = &cm;
+                jb = 0;
+                je = 1;
+            } else {
+                const int64_t c = near[q - nf];
+                src = x;
+                ms = m;
+                jb = d.nodes[4 * c];
+                je = d.nodes[4 * c + 1];
+            }
+            for (int64_t j = jb; j < je; ++j) {
+                if (q >= nf && j == i)
+                    continue;
+                const double *xj = q < nf ? src : src + 3 * j;
+                const double mj = q < nf ? ms[0] : ms[j];
+                const double dx = xj[0] - xi;
+                const double dy = xj[1] - yi;
+                const double dz = xj[2] - zi;
+                const double r2 = ((dx * dx + dy * dy) + dz * dz) + eps2;
+                const double r = sqrt(r2);
+                const double w = 1.0 / (r2 * r);
+                const double mw = mj * w;
+                nsum_add(&ax, mw * dx);
+                nsum_add(&ay, mw * dy);
+                nsum_add(&az, mw * dz);
+                nsum_add(&ph, mj / r);
+            }
+        }
+        free(far);
+        free(near);
+        if (acc) {
+            acc[3 * t] = G * nsum_val(&ax);
+            acc[3 * t + 1] = G * nsum_val(&ay);
+            acc[3 * t + 2] = G * nsum_val(&az);
+        }
+        if (pot)
+            pot[t] = -G * nsum_val(&ph);
+    }
+    free(gof);
+    tree_free(&d);
+    return bad ? -1 : 0;
 }
