@@ -208,6 +208,67 @@ int nbody_trajectory_adjoint(const void *ckpt, int64_t n, int32_t prec, double G
                              void *vel_cot, void *mass_cot, int32_t scheme, void *stream);
 
 /*
+ * Tree code on the ORB cells (Section IV.A: a distant group of bodies acts as
+ * one body of its total mass at its centre of mass; the distant cells are
+ * found by a walk from the root, the force sums over them and the remaining
+ * nearby bodies.  The cells are the nodes of the Section IV.B ORB recursion).
+ *
+ * Input: pos_mass, n float4 records (x, y, z, m), m >= 0, ALREADY IN ORB
+ * ORDER for the same `leaf` (nbody_orb_order, then a gather such as
+ * nbody_permute).  Node k of the tree is then the range of positions
+ * [begin, end); a node of more than `leaf` bodies has the children
+ * [begin, begin + k) and [begin + k, end), k = leaf * ceil(ceil(size/leaf)/2).
+ * Nodes are numbered in preorder (node, left subtree, right subtree).
+ * Targets are taken in groups, the maximal nodes of at most
+ * NBODY_TREE_GROUP bodies, in ORB order.
+ * Moments, in FP64 from the FP32 records: a leaf sums m and m*x over its
+ * bodies in position order from 0 (each product rounded, then added), an inner
+ * node adds left + right; com = S / M, or the box centre 0.5 (lo + hi) if
+ * M = 0; lo/hi are the exact coordinate minima/maxima; diag2 = sum over
+ * x, y, z of (hi - lo)^2.  Opening: cell c is accepted for group g iff c and
+ * g share no body and diag2_c < theta^2 * D2, D2 the squared distance from
+ * com_c to the box of g (per axis lo - com if com < lo, com - hi if com > hi,
+ * else 0, summed x, y, z; all in FP64): the cell's size over its distance is
+ * then below theta for every target of the group.  An accepted cell acts as
+ * one body (com and M rounded to FP32) under the same softened law; a leaf
+ * that is not accepted acts body by body; the group's own bodies act body by
+ * body without the self pair.  theta = 0 accepts nothing: the exact direct
+ * sum.  Decisions are bit-exact against an FP64 implementation of these
+ * definitions.
+ * 1 <= leaf <= NBODY_TREE_GROUP.  The first call for a new (n, leaf)
+ * uploads the node table and synchronizes the stream; later calls are
+ * asynchronous.  The tree tables are library scratch (about 120 bytes per
+ * node) shared by all tree calls on a device: overlapping calls race.
+ *
+ * nbody_tree_shape (host only): node and group counts; nodes_out, if not
+ *   NULL, receives int32[num_nodes][4] = (begin, end, left, right), -1
+ *   children for a leaf.
+ * nbody_tree_accel: acc_pot_out = n float4 (ax, ay, az, phi) in ORB order.
+ *   prec: NBODY_F32, NBODY_F32_KAHAN or NBODY_F32_F64ACC (how the partial
+ *   sums of each batch of cells or ranges are folded); NBODY_F64 is
+ *   unsupported.  eps >= 0, theta >= 0 finite.
+ * nbody_tree_moments (inspection): moments_out double[num_nodes][5] =
+ *   (M, com_x, com_y, com_z, diag2), box_out float[num_nodes][6] =
+ *   (lo_x, lo_y, lo_z, hi_x, hi_y, hi_z); either may be NULL.
+ * nbody_tree_lists (inspection): for every group, the number of accepted
+ *   cells (far_count[g]) and of rejected leaves outside the group
+ *   (near_count[g]), and their node ids, in walk order, in
+ *   far_ids[g * max_far + ...] and near_ids[g * max_near + ...] (NULL for
+ *   counts only; lists longer than the maximum are cut, the counts are not).
+ * Device pointers for all arrays except nodes_out.
+ */
+#define NBODY_TREE_GROUP 64
+int nbody_tree_shape(int64_t n, int32_t leaf, int64_t *num_nodes, int64_t *num_groups,
+                     int32_t *nodes_out);
+int nbody_tree_accel(const void *pos_mass, int64_t n, int32_t prec, double G, double eps,
+                     double theta, int32_t leaf, void *acc_pot_out, void *stream);
+int nbody_tree_moments(const void *pos_mass, int64_t n, int32_t leaf, double *moments_out,
+                       float *box_out, void *stream);
+int nbody_tree_lists(const void *pos_mass, int64_t n, int32_t leaf, double theta,
+                     int32_t max_far, int32_t max_near, int32_t *far_count, int32_t *near_count,
+                     int32_t *far_ids, int32_t *near_ids, void *stream);
+
+/*
  * Tuning.  nbody_autotune times the candidate kernel shapes for one problem
  * (kernel 0 = nbody_accel at size n, 1 = nbody_batched_accel for the given
  * offsets, 2 = nbody_accel_vjp) on library-owned synthetic inputs,

@@ -24,13 +24,15 @@ __all__ = [
     "ADJ_REVERSE",
     "lib", "accel", "accel_vjp", "leapfrog_kdk", "kick_drift", "batched_accel", "energy", "orb_order",
     "permute", "trajectory_forward", "trajectory_adjoint", "NBodyTrajectory", "autotune",
-    "set_tuning", "get_tuning", "release", "NBodyError",
+    "set_tuning", "get_tuning", "release", "NBodyError", "TREE_GROUP", "tree_shape", "tree_accel",
+    "tree_moments", "tree_lists",
 ]
 
 F64, F32, F32_KAHAN, F32_F64ACC = 0, 1, 2, 3
 ADJ_RECOMPUTE, ADJ_REVERSE = 0, 1
 ACC_VALID, GRAPH, ENERGY = 0x1, 0x2, 0x4
 KERNEL_ACCEL, KERNEL_BATCHED, KERNEL_VJP = 0, 1, 2
+TREE_GROUP = 64
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libnbody.so")
@@ -55,6 +57,10 @@ _SIGS = {
     "nbody_trajectory_forward": [_vp, _vp, _i64, _i32, _dbl, _dbl, _dbl, _i32, _i32, _vp, _vp],
     "nbody_trajectory_adjoint": [_vp, _i64, _i32, _dbl, _dbl, _dbl, _i32, _i32, _vp, _vp, _vp,
                                  _vp, _vp, _i32, _vp],
+    "nbody_tree_shape": [_i64, _i32, _vp, _vp, _vp],
+    "nbody_tree_accel": [_vp, _i64, _i32, _dbl, _dbl, _dbl, _i32, _vp, _vp],
+    "nbody_tree_moments": [_vp, _i64, _i32, _vp, _vp, _vp],
+    "nbody_tree_lists": [_vp, _i64, _i32, _dbl, _i32, _i32, _vp, _vp, _vp, _vp, _vp],
     "nbody_autotune": [_i32, _i32, _i64, _vp, _i32, _vp],
     "nbody_set_tuning": [_i32, _i32, _i32, _i32, _i32, _i32],
     "nbody_get_tuning": [_i32, _i32, _i64, _vp, _vp, _vp, _vp],
@@ -250,6 +256,67 @@ def permute(src, perm, inverse=False, out=None):
     _check(lib().nbody_permute(_ptr(s), _ptr(out), _ptr(perm), s.shape[0], s.element_size() * 4,
                                1 if inverse else 0, _stream()))
     return out
+
+
+# ---- tree code on the ORB cells ------------------------------------------------
+# Inputs are float32 (N, 4) records already in ORB order for the same leaf
+# (orb_order, then permute); results are in that order too.
+
+def tree_shape(n, leaf, nodes=False):
+    """(num_nodes, num_groups[, nodes int32 (num_nodes, 4) = begin, end,
+    left, right]) of the ORB tree for n bodies and this leaf size."""
+    nn, ng = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib().nbody_tree_shape(int(n), int(leaf), ctypes.byref(nn), ctypes.byref(ng), None))
+    if not nodes:
+        return nn.value, ng.value
+    import numpy as np
+    tab = np.empty((nn.value, 4), dtype=np.int32)
+    _check(lib().nbody_tree_shape(int(n), int(leaf), ctypes.byref(nn), ctypes.byref(ng),
+                                  tab.ctypes.data_as(ctypes.c_void_p)))
+    return nn.value, ng.value, tab
+
+
+def tree_accel(pos_mass, eps, theta, leaf=8, G=1.0, prec=None, out=None):
+    """Tree-code force and potential (ax, ay, az, phi) per body, ORB order."""
+    pm = _rec(pos_mass, "pos_mass", torch.float32)
+    p = _prec(pm, prec)
+    if out is None:
+        out = torch.empty_like(pm)
+    else:
+        _rec(out, "out", torch.float32)
+        if out.shape != pm.shape:
+            raise ValueError("out must match pos_mass")
+    _check(lib().nbody_tree_accel(_ptr(pm), pm.shape[0], p, float(G), float(eps), float(theta), int(leaf),
+                                  _ptr(out), _stream()))
+    return out
+
+
+def tree_moments(pos_mass, leaf=8):
+    """Node moments (num_nodes, 5) float64 = (M, com_x, com_y, com_z, diag2)
+    and boxes (num_nodes, 6) float32 = (lo, hi)."""
+    pm = _rec(pos_mass, "pos_mass", torch.float32)
+    nn, _ = tree_shape(pm.shape[0], leaf)
+    mom = torch.empty((nn, 5), dtype=torch.float64, device=pm.device)
+    box = torch.empty((nn, 6), dtype=torch.float32, device=pm.device)
+    _check(lib().nbody_tree_moments(_ptr(pm), pm.shape[0], int(leaf), _ptr(mom), _ptr(box), _stream()))
+    return mom, box
+
+
+def tree_lists(pos_mass, theta, leaf=8, max_far=None, max_near=None):
+    """Per-group interaction lists: (far_count, near_count) int32 (groups,)
+    and, when the maxima are given, far_ids (groups, max_far) and near_ids
+    (groups, max_near) node ids in walk order (entries past the counts are
+    undefined)."""
+    pm = _rec(pos_mass, "pos_mass", torch.float32)
+    _, ng = tree_shape(pm.shape[0], leaf)
+    fc = torch.empty(ng, dtype=torch.int32, device=pm.device)
+    nc = torch.empty(ng, dtype=torch.int32, device=pm.device)
+    fi = None if not max_far else torch.empty((ng, int(max_far)), dtype=torch.int32, device=pm.device)
+    ni = None if not max_near else torch.empty((ng, int(max_near)), dtype=torch.int32, device=pm.device)
+    _check(lib().nbody_tree_lists(_ptr(pm), pm.shape[0], int(leaf), float(theta), int(max_far or 0),
+                                  int(max_near or 0), _ptr(fc), _ptr(nc), None if fi is None else _ptr(fi),
+                                  None if ni is None else _ptr(ni), _stream()))
+    return fc, nc, fi, ni
 
 
 def trajectory_forward(pos_mass, vel, eps, dt, nsteps, ckpt_every, G=1.0, prec=None):

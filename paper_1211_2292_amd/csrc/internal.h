@@ -111,6 +111,15 @@ hipError_t launch_vjp_adj_step(int prec, int post, void *pm, void *raw, void *sc
 int orb_order(const void *pm, int prec, int n, int leaf, int32_t *perm, hipStream_t s);
 void orb_release();
 
+// ---- tree code (tree.hip) ----------------------------------------------------
+int tree_shape(int n, int leaf, int64_t *num_nodes, int64_t *num_groups, int32_t *nodes_out);
+int tree_moments(const void *pm, int n, int leaf, double *mom, float *box, hipStream_t s);
+int tree_lists(const void *pm, int n, int leaf, double theta, int max_far, int max_near, int32_t *far_cnt,
+               int32_t *near_cnt, int32_t *far_ids, int32_t *near_ids, hipStream_t s);
+int tree_accel(const void *pm, int n, int prec, double G, double eps, double theta, int leaf, void *out,
+               hipStream_t s);
+void tree_release();
+
 // ---- runtime helpers (runtime.hip) -----------------------------------------
 void set_error(const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);

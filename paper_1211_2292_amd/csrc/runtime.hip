@@ -739,6 +739,79 @@ int nbody_orb_order(const void *pos_mass, int32_t prec, int64_t n, int32_t leaf,
     return orb_order(pos_mass, prec, (int)n, leaf, perm_out, (hipStream_t)stream);
 }
 
+// ---- tree code -----------------------------------------------------------------
+static int check_tree(int64_t n, int32_t leaf)
+{
+    NB_CHECK(check_n(n));
+    if (leaf < 1 || leaf > NBODY_TREE_GROUP) {
+        set_error("leaf = %d out of range [1, %d]", leaf, NBODY_TREE_GROUP);
+        return NBODY_E_INVAL;
+    }
+    return NBODY_OK;
+}
+
+static int check_theta(double theta)
+{
+    if (!std::isfinite(theta) || theta < 0.0) {
+        set_error("theta must be finite and >= 0");
+        return NBODY_E_INVAL;
+    }
+    return NBODY_OK;
+}
+
+int nbody_tree_shape(int64_t n, int32_t leaf, int64_t *num_nodes, int64_t *num_groups, int32_t *nodes_out)
+{
+    NB_CHECK(check_tree(n, leaf));
+    return tree_shape((int)n, leaf, num_nodes, num_groups, nodes_out);
+}
+
+int nbody_tree_accel(const void *pos_mass, int64_t n, int32_t prec, double G, double eps, double theta,
+                     int32_t leaf, void *acc_pot_out, void *stream)
+{
+    NB_CHECK(check_tree(n, leaf));
+    if (!prec_ok(prec)) {
+        set_error("bad precision %d", prec);
+        return NBODY_E_INVAL;
+    }
+    if (prec == NBODY_F64) {
+        set_error("the tree code runs the FP32 modes only");
+        return NBODY_E_UNSUPPORTED;
+    }
+    NB_CHECK(check_scalars(G, eps, 0.0));
+    NB_CHECK(check_theta(theta));
+    NB_CHECK(check_vec(pos_mass, prec, "pos_mass"));
+    NB_CHECK(check_vec(acc_pot_out, prec, "acc_pot_out"));
+    return tree_accel(pos_mass, (int)n, prec, G, eps, theta, leaf, acc_pot_out, (hipStream_t)stream);
+}
+
+int nbody_tree_moments(const void *pos_mass, int64_t n, int32_t leaf, double *moments_out, float *box_out,
+                       void *stream)
+{
+    NB_CHECK(check_tree(n, leaf));
+    NB_CHECK(check_vec(pos_mass, NBODY_F32, "pos_mass"));
+    if (((uintptr_t)moments_out % 8) || ((uintptr_t)box_out % 4)) {
+        set_error("moments_out or box_out misaligned");
+        return NBODY_E_ALIGN;
+    }
+    return tree_moments(pos_mass, (int)n, leaf, moments_out, box_out, (hipStream_t)stream);
+}
+
+int nbody_tree_lists(const void *pos_mass, int64_t n, int32_t leaf, double theta, int32_t max_far,
+                     int32_t max_near, int32_t *far_count, int32_t *near_count, int32_t *far_ids,
+                     int32_t *near_ids, void *stream)
+{
+    NB_CHECK(check_tree(n, leaf));
+    NB_CHECK(check_theta(theta));
+    NB_CHECK(check_vec(pos_mass, NBODY_F32, "pos_mass"));
+    if (!far_count || !near_count || max_far < 0 || max_near < 0 || (far_ids && !max_far) ||
+        (near_ids && !max_near)) {
+        set_error("bad list arguments");
+        return NBODY_E_INVAL;
+    }
+    return tree_lists(pos_mass, (int)n, leaf, theta, max_far, max_near, far_count, near_count, far_ids,
+                      near_ids, (hipStream_t)stream);
+}
+
 // ---- trajectory + adjoint ---------------------------------------------------
 int nbody_trajectory_forward(void *pos_mass, void *vel, int64_t n, int32_t prec, double G,
                              double eps, double dt, int32_t nsteps, int32_t ckpt_every, void *ckpt,
@@ -1103,4 +1176,5 @@ extern "C" void nbody_release(void)
             if (kv.second.ptr[k]) (void)hipFree(kv.second.ptr[k]);
     g_scratch.clear();
     orb_release();
+    tree_release();
 }

@@ -1,0 +1,591 @@
+// Tree-code force on the ORB cells (gfx950).
+//
+// The paper's force calculation (Section IV.A): a distant group of bodies acts
+// as one body of the group's total mass at its centre of mass; the cells that
+// are distant enough are found by walking the tree from the root, and the
+// force sums over the accepted cells and the remaining nearby bodies.  The
+// cells here are the nodes of the ORB recursion of Section IV.B, so they need
+// no separate tree build: with the bodies in ORB order (same leaf size) node k
+// is the contiguous range [begin, end), and the node table depends only on
+// (n, leaf).
+//
+// Definitions shared with the FP64 oracle (bit-exact decisions):
+// * moments in FP64: a leaf sums m and m*x over its bodies in order (product
+//   rounded, then added); an inner node adds left + right.  com = S / M, or the
+//   box centre when M = 0.  Boxes are exact FP32 minima/maxima, and
+//   diag2 = sum over x, y, z of (hi - lo)^2 in FP64.
+// * groups: the targets are taken in groups, the maximal nodes of at most 64
+//   bodies (one wave each).
+// * opening: cell c is accepted for group g iff c and g share no body and
+//   diag2_c < theta^2 * D2, D2 the squared distance from com_c to the box of g
+//   (per axis lo - com, com - hi or 0; summed x, y, z).  Every body of c lies
+//   within sqrt(diag2_c) of com_c and every body of g at least sqrt(D2) from
+//   it, so the size-to-distance ratio is below theta for every target.
+//
+// Kernels:
+// * k_tree_moments: one thread per leaf computes the leaf, then climbs; at
+//   each parent an agent-scope counter tells the second child to arrive, which
+//   combines left + right.  Nothing waits, and the counter is reset by the
+//   thread that consumed it, so the launch leaves it zero for the next.
+// * k_tree_walk: one wave per group.  The walk starts from the siblings of
+//   the group's ancestors (every cell disjoint from the group) and pops up to
+//   64 cells per step from a stack in LDS, one cell per lane: the acceptance
+//   test is per cell, so the control flow of the wave stays uniform.
+//   Accepted cells go to an LDS batch of pseudo-body records that every lane
+//   sweeps with the same FP32 pair code as the direct sum (broadcast LDS
+//   reads); rejected leaves go to a batch of contiguous source ranges swept
+//   with scalar loads; the group's own bodies are one masked range.  A cell
+//   whose children would overflow the stack is summed body by body instead,
+//   which is exact.  In inspection mode the same walk writes the node ids of
+//   the accepted cells and of the rejected leaves instead of summing.
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "internal.h"
+#include "pair.h"
+
+namespace nbi {
+namespace {
+
+constexpr int kGroup = 64;     // targets per group: one per lane
+constexpr int kStack = 1024;   // LDS stack entries per wave
+constexpr int kBuf = 128;      // LDS batch entries (cells, near ranges)
+
+struct TreeDev {
+    const int4 *node;    // begin, end, left, right (-1 for a leaf)
+    const int *parent;   // -1 for the root
+    const int *leaves;   // leaf node ids in ORB order
+    const int *groups;   // group node ids in ORB order
+    double4 *sums;       // M, Sx, Sy, Sz
+    double4 *comd;       // com (FP64), diag2
+    float4 *rec;         // com (FP32), M (FP32): the pseudo-body record
+    float4 *lo, *hi;     // box
+    unsigned *cnt;       // children arrived, per node
+};
+
+__device__ __forceinline__ void finish_node(const TreeDev &T, int c, double M, double sx, double sy,
+                                            double sz, float4 lo, float4 hi)
+{
+    double cx, cy, cz;
+    if (M > 0.0) {
+        cx = sx / M;
+        cy = sy / M;
+        cz = sz / M;
+    } else {
+        cx = 0.5 * ((double)lo.x + (double)hi.x);
+        cy = 0.5 * ((double)lo.y + (double)hi.y);
+        cz = 0.5 * ((double)lo.z + (double)hi.z);
+    }
+    const double ex = (double)hi.x - (double)lo.x;
+    const double ey = (double)hi.y - (double)lo.y;
+    const double ez = (double)hi.z - (double)lo.z;
+    double d2 = 0.0;
+    d2 = d2 + ex * ex;
+    d2 = d2 + ey * ey;
+    d2 = d2 + ez * ez;
+    T.sums[c] = make_double4(M, sx, sy, sz);
+    T.comd[c] = make_double4(cx, cy, cz, d2);
+    T.rec[c] = make_float4((float)cx, (float)cy, (float)cz, (float)M);
+    T.lo[c] = lo;
+    T.hi[c] = hi;
+}
+
+__global__ __launch_bounds__(256) void k_tree_moments(const float4 *__restrict__ pm, TreeDev T,
+                                                      int nleaves)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nleaves) return;
+    int c = T.leaves[t];
+    {
+        const int4 nd = T.node[c];
+        const float4 p0 = pm[nd.x];
+        float4 lo = make_float4(p0.x, p0.y, p0.z, 0.0f), hi = lo;
+        double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+        for (int p = nd.x; p < nd.y; ++p) {
+            const float4 b = pm[p];
+            const double m = b.w;
+            M = M + m;
+            const double mx = m * (double)b.x, my = m * (double)b.y, mz = m * (double)b.z;
+            sx = sx + mx;
+            sy = sy + my;
+            sz = sz + mz;
+            if (b.x < lo.x) lo.x = b.x;
+            if (b.x > hi.x) hi.x = b.x;
+            if (b.y < lo.y) lo.y = b.y;
+            if (b.y > hi.y) hi.y = b.y;
+            if (b.z < lo.z) lo.z = b.z;
+            if (b.z > hi.z) hi.z = b.z;
+        }
+        finish_node(T, c, M, sx, sy, sz, lo, hi);
+    }
+    for (;;) {
+        const int par = T.parent[c];
+        if (par < 0) return;
+        __threadfence();  // release this subtree's moments
+        const unsigned old = atomicAdd(&T.cnt[par], 1u);
+        if (old == 0u) return;  // the sibling finishes later and combines
+        __threadfence();  // acquire the sibling's moments
+        T.cnt[par] = 0u;
+        const int4 nd = T.node[par];
+        const double4 a = T.sums[nd.z], b = T.sums[nd.w];
+        const float4 la = T.lo[nd.z], lb = T.lo[nd.w], ha = T.hi[nd.z], hb = T.hi[nd.w];
+        const float4 lo = make_float4(la.x < lb.x ? la.x : lb.x, la.y < lb.y ? la.y : lb.y,
+                                      la.z < lb.z ? la.z : lb.z, 0.0f);
+        const float4 hi = make_float4(ha.x > hb.x ? ha.x : hb.x, ha.y > hb.y ? ha.y : hb.y,
+                                      ha.z > hb.z ? ha.z : hb.z, 0.0f);
+        finish_node(T, par, a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w, lo, hi);
+        c = par;
+    }
+}
+
+__device__ __forceinline__ double box_gap(double p, double a, double b)
+{
+    return p < a ? a - p : (p > b ? p - b : 0.0);
+}
+
+__device__ __forceinline__ unsigned lane_rank(unsigned long long mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+struct WalkOut {
+    float4 *acc_pot;   // force mode: ORB-ordered output records
+    int *far_cnt, *near_cnt, *far_ids, *near_ids;  // inspection mode
+    int max_far, max_near;
+};
+
+// Sweeps the batched pseudo-body records in LDS (broadcast reads).
+__device__ __forceinline__ void sweep_cells(const float4 *cb, int cnt, const Targets<float, 1> &T,
+                                            float eps2, Sums<float, 1> &S)
+{
+    int j = 0;
+    for (; j + kUnroll <= cnt; j += kUnroll) {
+        float4 b[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) b[u] = cb[j + u];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) pair_f32<1, false>(b[u], j + u, T, eps2, S);
+    }
+    for (; j < cnt; ++j) pair_f32<1, false>(cb[j], j, T, eps2, S);
+}
+
+template <int MODE, bool INSPECT>
+__global__ __launch_bounds__(64) void k_tree_walk(const float4 *__restrict__ src, int n, TreeDev T,
+                                                  float eps2_in, double G, double theta2, WalkOut O)
+{
+    __shared__ int stk[kStack];
+    __shared__ float4 cbuf[kBuf];
+    __shared__ int2 nbuf[kBuf];
+    const int lane = threadIdx.x;
+    const int g = blockIdx.x;
+    const int gnode = T.groups[g];
+    const int4 gn = T.node[gnode];
+    const float4 glo = T.lo[gnode], ghi = T.hi[gnode];
+    const double ax = glo.x, ay = glo.y, az = glo.z, bx = ghi.x, by = ghi.y, bz = ghi.z;
+    const float eps2 = lane_copy(eps2_in);
+
+    Targets<float, 1> TT;
+    const int i = gn.x + lane;
+    {
+        const float4 p = src[min(i, gn.y - 1)];
+        TT.x[0] = p.x;
+        TT.y[0] = p.y;
+        TT.z[0] = p.z;
+        TT.i[0] = i;
+    }
+    Run<MODE> R[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) R[c].zero();
+    Sums<float, 1> S;
+
+    // siblings of the ancestors, root first (the deepest ends on top)
+    int top = 0;
+    for (int c = 0, depth = 0; c != gnode && c >= 0 && depth < 64; ++depth) {
+        const int4 nd = T.node[c];
+        const int4 ln = T.node[nd.z];
+        const bool left = gn.x < ln.y;
+        if (lane == 0) stk[top] = left ? nd.w : nd.z;
+        ++top;
+        c = left ? nd.z : nd.w;
+    }
+    int nf = 0, nr = 0, tf = 0, tn = 0;
+
+    auto flush_cells = [&]() {
+        if constexpr (!INSPECT) {
+            S.zero();
+            sweep_cells(cbuf, nf, TT, eps2, S);
+            R[0].fold(S.ax[0]);
+            R[1].fold(S.ay[0]);
+            R[2].fold(S.az[0]);
+            R[3].fold(S.ph[0]);
+        }
+        nf = 0;
+    };
+    auto flush_near = [&]() {
+        if constexpr (!INSPECT) {
+            S.zero();
+            for (int r = 0; r < nr;) {
+                const int2 a = nbuf[r];
+                int b = __builtin_amdgcn_readfirstlane(a.x);
+                int e = __builtin_amdgcn_readfirstlane(a.y);
+                ++r;
+                while (r < nr) {  // merge ranges that continue each other
+                    const int2 c2 = nbuf[r];
+                    const int nb = __builtin_amdgcn_readfirstlane(c2.x);
+                    if (nb != e) break;
+                    e = __builtin_amdgcn_readfirstlane(c2.y);
+                    ++r;
+                }
+                sweep_f32<1, false>(src, b, e, TT, eps2, S);
+            }
+            R[0].fold(S.ax[0]);
+            R[1].fold(S.ay[0]);
+            R[2].fold(S.az[0]);
+            R[3].fold(S.ph[0]);
+        }
+        nr = 0;
+    };
+
+    while (top > 0) {
+        const int k = min(kGroup, top);
+        top -= k;
+        __syncthreads();
+        const bool act = lane < k;
+        const int c = act ? stk[top + lane] : 0;
+        __syncthreads();
+        bool acc = false, nearr = false, open = false;
+        int4 nd = make_int4(0, 0, -1, -1);
+        if (act) {
+            nd = T.node[c];
+            const double4 cd = T.comd[c];
+            const double dx = box_gap(cd.x, ax, bx);
+            const double dy = box_gap(cd.y, ay, by);
+            const double dz = box_gap(cd.z, az, bz);
+            const double D2 = (dx * dx + dy * dy) + dz * dz;
+            acc = cd.w < theta2 * D2;
+            if (!acc) {
+                if (nd.z < 0)
+                    nearr = true;
+                else
+                    open = true;
+            }
+        }
+        // children that would not fit on the stack are summed body by body
+        const unsigned long long mo0 = __ballot(open);
+        if (open && top + 2 * (int)(lane_rank(mo0) + 1) > kStack) {
+            open = false;
+            nearr = true;
+        }
+        const unsigned long long ma = __ballot(acc), mn = __ballot(nearr), mo = __ballot(open);
+        const int ca = __popcll(ma), cn = __popcll(mn), co = __popcll(mo);
+        if constexpr (INSPECT) {
+            if (acc) {
+                const int q = tf + (int)lane_rank(ma);
+                if (q < O.max_far) O.far_ids[(long)g * O.max_far + q] = c;
+            }
+            if (nearr) {
+                const int q = tn + (int)lane_rank(mn);
+                if (q < O.max_near) O.near_ids[(long)g * O.max_near + q] = c;
+            }
+        } else {
+            if (acc) cbuf[nf + (int)lane_rank(ma)] = T.rec[c];
+            if (nearr) nbuf[nr + (int)lane_rank(mn)] = make_int2(nd.x, nd.y);
+        }
+        if (open) {
+            const int q = top + 2 * (int)lane_rank(mo);
+            stk[q] = nd.w;
+            stk[q + 1] = nd.z;
+        }
+        tf += ca;
+        tn += cn;
+        nf += ca;
+        nr += cn;
+        top += 2 * co;
+        __syncthreads();
+        if (nf >= kGroup) flush_cells();
+        if (nr >= kGroup) flush_near();
+    }
+    if (nf > 0) flush_cells();
+    if (nr > 0) flush_near();
+
+    if constexpr (INSPECT) {
+        if (lane == 0) {
+            O.far_cnt[g] = tf;
+            O.near_cnt[g] = tn;
+        }
+    } else {
+        // the group's own bodies, without the self pair
+        S.zero();
+        range_f32<1>(src, gn.x, gn.y, gn.x, gn.x + kGroup, TT, eps2, S);
+        R[0].fold(S.ax[0]);
+        R[1].fold(S.ay[0]);
+        R[2].fold(S.az[0]);
+        R[3].fold(S.ph[0]);
+        if (i < gn.y) {
+            double r[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) r[c] = R[c].get();
+            if constexpr (MODE == M_F32)
+                put_f32(O.acc_pot, i, r, (float)G);
+            else
+                put(O.acc_pot, i, r, G);
+        }
+    }
+}
+
+__global__ void k_tree_export(TreeDev T, int nn, double *__restrict__ mom, float *__restrict__ box)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nn) return;
+    const double4 s = T.sums[c], d = T.comd[c];
+    const float4 lo = T.lo[c], hi = T.hi[c];
+    if (mom) {
+        mom[5L * c + 0] = s.x;
+        mom[5L * c + 1] = d.x;
+        mom[5L * c + 2] = d.y;
+        mom[5L * c + 3] = d.z;
+        mom[5L * c + 4] = d.w;
+    }
+    if (box) {
+        box[6L * c + 0] = lo.x;
+        box[6L * c + 1] = lo.y;
+        box[6L * c + 2] = lo.z;
+        box[6L * c + 3] = hi.x;
+        box[6L * c + 4] = hi.y;
+        box[6L * c + 5] = hi.z;
+    }
+}
+
+// ---- host plan ------------------------------------------------------------------
+struct HostTree {
+    std::vector<int4> node;
+    std::vector<int> parent, leaves, groups;
+};
+
+int build_rec(HostTree &h, int b, int size, int leaf, int par)
+{
+    const int id = (int)h.node.size();
+    h.node.push_back(make_int4(b, b + size, -1, -1));
+    h.parent.push_back(par);
+    if (size <= leaf) {
+        h.leaves.push_back(id);
+        return id;
+    }
+    const int L = (size + leaf - 1) / leaf;
+    const int k = std::min(size, leaf * ((L + 1) / 2));
+    const int l = build_rec(h, b, k, leaf, id);
+    const int r = build_rec(h, b + k, size - k, leaf, id);
+    h.node[id].z = l;
+    h.node[id].w = r;
+    return id;
+}
+
+void groups_rec(HostTree &h, int id)
+{
+    const int4 nd = h.node[id];
+    if (nd.y - nd.x <= kGroup || nd.z < 0) {
+        h.groups.push_back(id);
+        return;
+    }
+    groups_rec(h, nd.z);
+    groups_rec(h, nd.w);
+}
+
+void plan(HostTree &h, int n, int leaf)
+{
+    h.node.clear();
+    h.parent.clear();
+    h.leaves.clear();
+    h.groups.clear();
+    const size_t nl = (size_t)((n + (int64_t)leaf - 1) / leaf);
+    h.node.reserve(2 * nl);
+    h.parent.reserve(2 * nl);
+    h.leaves.reserve(nl);
+    build_rec(h, 0, n, leaf, -1);
+    groups_rec(h, 0);
+}
+
+struct TreeCache {
+    int n = 0, leaf = 0, dev = -1;
+    HostTree host;
+    void *mem = nullptr;
+    size_t bytes = 0;
+    TreeDev d{};
+};
+std::mutex g_tree_mu;
+TreeCache g_tree;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Makes the device tables and node arrays for (n, leaf) current; returns the
+// device view.  Called with g_tree_mu held.
+int tree_prepare(int n, int leaf, hipStream_t s, TreeDev &out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        set_error("hipGetDevice failed");
+        return NBODY_E_HIP;
+    }
+    TreeCache &C = g_tree;
+    if (C.mem && C.n == n && C.leaf == leaf && C.dev == dev) {
+        out = C.d;
+        return NBODY_OK;
+    }
+    HostTree h;
+    plan(h, n, leaf);
+    const size_t nn = h.node.size(), nl = h.leaves.size(), ng = h.groups.size();
+    const size_t o_node = 0;
+    const size_t o_par = o_node + align256(nn * sizeof(int4));
+    const size_t o_leaf = o_par + align256(nn * sizeof(int));
+    const size_t o_grp = o_leaf + align256(nl * sizeof(int));
+    const size_t o_sums = o_grp + align256(ng * sizeof(int));
+    const size_t o_comd = o_sums + align256(nn * sizeof(double4));
+    const size_t o_rec = o_comd + align256(nn * sizeof(double4));
+    const size_t o_lo = o_rec + align256(nn * sizeof(float4));
+    const size_t o_hi = o_lo + align256(nn * sizeof(float4));
+    const size_t o_cnt = o_hi + align256(nn * sizeof(float4));
+    const size_t total = o_cnt + align256(nn * sizeof(unsigned));
+    if (C.mem) {
+        // work already enqueued may still read the old tables
+        (void)hipDeviceSynchronize();
+        (void)hipFree(C.mem);
+        C.mem = nullptr;
+        C.bytes = 0;
+    }
+    void *mem = nullptr;
+    if (hipMalloc(&mem, total) != hipSuccess) {
+        set_error("cannot allocate %zu bytes of tree tables", total);
+        return NBODY_E_NOMEM;
+    }
+    char *base = (char *)mem;
+    TreeDev d;
+    d.node = (const int4 *)(base + o_node);
+    d.parent = (const int *)(base + o_par);
+    d.leaves = (const int *)(base + o_leaf);
+    d.groups = (const int *)(base + o_grp);
+    d.sums = (double4 *)(base + o_sums);
+    d.comd = (double4 *)(base + o_comd);
+    d.rec = (float4 *)(base + o_rec);
+    d.lo = (float4 *)(base + o_lo);
+    d.hi = (float4 *)(base + o_hi);
+    d.cnt = (unsigned *)(base + o_cnt);
+    // pageable copies complete on the host side before returning; the vectors
+    // stay alive in the cache in any case
+    C.host = std::move(h);
+    hipError_t e = hipMemcpyAsync(base + o_node, C.host.node.data(), nn * sizeof(int4), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(base + o_par, C.host.parent.data(), nn * sizeof(int), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(base + o_leaf, C.host.leaves.data(), nl * sizeof(int), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(base + o_grp, C.host.groups.data(), ng * sizeof(int), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_fill_zero(d.cnt, nn * sizeof(unsigned), s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipFree(mem);
+        return hip_fail(e, "tree table upload");
+    }
+    C.mem = mem;
+    C.bytes = total;
+    C.n = n;
+    C.leaf = leaf;
+    C.dev = dev;
+    C.d = d;
+    out = d;
+    return NBODY_OK;
+}
+
+hipError_t launch_moments(const float4 *pm, const TreeDev &d, int nleaves, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_tree_moments, dim3((nleaves + 255) / 256), dim3(256), 0, s, pm, d, nleaves);
+    return hipGetLastError();
+}
+
+template <int MODE, bool INSPECT>
+hipError_t launch_walk(const float4 *pm, int n, const TreeDev &d, int ngroups, float eps2, double G,
+                       double theta2, const WalkOut &o, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_tree_walk<MODE, INSPECT>), dim3(ngroups), dim3(64), 0, s, pm, n, d, eps2, G, theta2, o);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int tree_shape(int n, int leaf, int64_t *num_nodes, int64_t *num_groups, int32_t *nodes_out)
+{
+    HostTree h;
+    plan(h, n, leaf);
+    if (num_nodes) *num_nodes = (int64_t)h.node.size();
+    if (num_groups) *num_groups = (int64_t)h.groups.size();
+    if (nodes_out) std::memcpy(nodes_out, h.node.data(), h.node.size() * sizeof(int4));
+    return NBODY_OK;
+}
+
+int tree_moments(const void *pm, int n, int leaf, double *mom, float *box, hipStream_t s)
+{
+    std::lock_guard<std::mutex> lk(g_tree_mu);
+    TreeDev d;
+    int rc = tree_prepare(n, leaf, s, d);
+    if (rc != NBODY_OK) return rc;
+    const int nn = (int)g_tree.host.node.size();
+    hipError_t e = launch_moments((const float4 *)pm, d, (int)g_tree.host.leaves.size(), s);
+    if (e == hipSuccess && (mom || box)) {
+        hipLaunchKernelGGL(k_tree_export, dim3((nn + 255) / 256), dim3(256), 0, s, d, nn, mom, box);
+        e = hipGetLastError();
+    }
+    return e == hipSuccess ? NBODY_OK : hip_fail(e, "tree moments");
+}
+
+int tree_lists(const void *pm, int n, int leaf, double theta, int max_far, int max_near, int32_t *far_cnt,
+               int32_t *near_cnt, int32_t *far_ids, int32_t *near_ids, hipStream_t s)
+{
+    std::lock_guard<std::mutex> lk(g_tree_mu);
+    TreeDev d;
+    int rc = tree_prepare(n, leaf, s, d);
+    if (rc != NBODY_OK) return rc;
+    hipError_t e = launch_moments((const float4 *)pm, d, (int)g_tree.host.leaves.size(), s);
+    WalkOut o{};
+    o.far_cnt = far_cnt;
+    o.near_cnt = near_cnt;
+    o.far_ids = far_ids;
+    o.near_ids = near_ids;
+    o.max_far = far_ids ? max_far : 0;
+    o.max_near = near_ids ? max_near : 0;
+    if (e == hipSuccess)
+        e = launch_walk<M_F32, true>((const float4 *)pm, n, d, (int)g_tree.host.groups.size(), 0.0f, 1.0,
+                                     theta * theta, o, s);
+    return e == hipSuccess ? NBODY_OK : hip_fail(e, "tree lists");
+}
+
+int tree_accel(const void *pm, int n, int prec, double G, double eps, double theta, int leaf, void *out,
+               hipStream_t s)
+{
+    std::lock_guard<std::mutex> lk(g_tree_mu);
+    TreeDev d;
+    int rc = tree_prepare(n, leaf, s, d);
+    if (rc != NBODY_OK) return rc;
+    hipError_t e = launch_moments((const float4 *)pm, d, (int)g_tree.host.leaves.size(), s);
+    WalkOut o{};
+    o.acc_pot = (float4 *)out;
+    const int ng = (int)g_tree.host.groups.size();
+    const float eps2 = (float)(eps * eps);
+    const double th2 = theta * theta;
+    if (e == hipSuccess) {
+        switch (prec) {
+        case NBODY_F32: e = launch_walk<M_F32, false>((const float4 *)pm, n, d, ng, eps2, G, th2, o, s); break;
+        case NBODY_F32_KAHAN: e = launch_walk<M_KAHAN, false>((const float4 *)pm, n, d, ng, eps2, G, th2, o, s); break;
+        default: e = launch_walk<M_F64ACC, false>((const float4 *)pm, n, d, ng, eps2, G, th2, o, s); break;
+        }
+    }
+    return e == hipSuccess ? NBODY_OK : hip_fail(e, "tree force");
+}
+
+void tree_release()
+{
+    std::lock_guard<std::mutex> lk(g_tree_mu);
+    if (g_tree.mem) (void)hipFree(g_tree.mem);
+    g_tree = TreeCache();
+}
+
+}  // namespace nbi

@@ -2,6 +2,8 @@
 declares, and rejects bad arguments before enqueueing anything (these calls
 return on the host without touching a GPU)."""
 import ctypes
+
+import numpy as np
 import os
 import re
 
@@ -81,6 +83,28 @@ def test_other_entry_points_validate():
     assert L.nbody_set_tuning(0, 0, 1, 1, 512, 1) == -1   # no LDS variant in FP64
     assert L.nbody_set_tuning(2, 1, 1, 1, 512, 1) == -1   # nor for the VJP
     assert L.nbody_energy(P(64), P(1024), P(4096), 10, 1, None, None) == -1
+    # tree code: leaf range, precision, theta, list arguments
+    assert L.nbody_tree_shape(100, 0, None, None, None) == -1
+    assert L.nbody_tree_shape(100, 65, None, None, None) == -1
+    assert L.nbody_tree_accel(P(64), 100, 1, 1.0, 0.01, 0.5, 0, P(4096), None) == -1
+    assert L.nbody_tree_accel(P(64), 100, 0, 1.0, 0.01, 0.5, 8, P(4096), None) == -5   # FP64 unsupported
+    assert L.nbody_tree_accel(P(64), 100, 1, 1.0, 0.01, -0.1, 8, P(4096), None) == -1
+    assert L.nbody_tree_accel(P(64), 100, 1, 1.0, 0.01, float("inf"), 8, P(4096), None) == -1
+    assert L.nbody_tree_accel(P(72), 100, 1, 1.0, 0.01, 0.5, 8, P(4096), None) == -2
+    assert L.nbody_tree_lists(P(64), 100, 8, 0.5, 4, 4, None, P(256), None, None, None) == -1
+    assert L.nbody_tree_lists(P(64), 100, 8, 0.5, 0, 4, P(256), P(512), P(1024), None, None) == -1
+    assert L.nbody_tree_moments(P(64), 100, 8, P(12), None, None) == -2
+
+
+@pytest.mark.parametrize("n,leaf", [(1, 1), (9, 8), (100, 8), (1000, 3), (4096, 16), (70001, 8), (777, 64)])
+def test_tree_node_table_matches_oracle(orc, n, leaf):
+    """The library's tree plan (host code) numbers and splits the nodes
+    exactly as the oracle's ORB recursion."""
+    nb, L = _lib()
+    nn, ng, tab = nb.tree_shape(n, leaf, nodes=True)
+    want = orc.tree_nodes(n, leaf)
+    assert np.array_equal(tab.astype(np.int64), want)
+    assert ng == orc._load().oracle_tree_num_groups(n, leaf, nb.TREE_GROUP)
 
 
 def test_tuning_pin_roundtrip():
