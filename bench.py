@@ -190,6 +190,7 @@ def main():
         result["fp64"] = fp64_leg(torch, nb, ics, dev)
         result["adjoint"] = adjoint_leg(torch, nb, ics, dev)
         result["batched"] = batched_leg(torch, nb, ics, dev)
+        result["tree"] = tree_leg(torch, nb, pm_np, eps, kern_avg)
         result["cpu_baseline"] = cpu_leg(ics, pm0_host, acc0, eps, args.cpu_seconds)
     print(json.dumps(result), flush=True)
 
@@ -310,6 +311,99 @@ def batched_leg(torch, nb, ics, dev):
     log(f"[bench] batched: {ms:.1f} ms for {steps} steps, {gint:.1f} Gint/s")
     return {"workload": "512 Plummer systems, N_s log-uniform [256, 32768], F32_KAHAN, 50 steps in one graph",
             "bodies": int(off[-1]), "ms": round(ms, 3), "g_interactions_per_s": round(gint, 2)}
+
+
+def _tree_groups(nodes, group):
+    """(begin, end) of the groups: the maximal nodes of at most `group`
+    bodies, in ORB order (node table rows: begin, end, left, right)."""
+    out, stack = [], [0]
+    while stack:
+        k = stack.pop()
+        b, e, l, r = nodes[k]
+        if e - b <= group or l < 0:
+            out.append((b, e))
+        else:
+            stack.extend((r, l))
+    return out
+
+
+def tree_leg(torch, nb, pm_np, eps, direct_ms):
+    """Tree code on the ORB cells (leaf 8, groups of 64) for the same
+    colliding pair at step 0, FP32 pairs with FP64 batch sums: time per
+    evaluation, interactions per body, and the error against the exact direct
+    sum computed by the direct kernel on the same ordered input."""
+    import ctypes
+    leaf = 8
+    dev = torch.device("cuda:0")
+    n = pm_np.shape[0]
+    p = torch.as_tensor(pm_np, dtype=torch.float32, device=dev).contiguous()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    perm = nb.orb_order(p, leaf)
+    q = nb.permute(p, perm)
+    e1.record()
+    torch.cuda.synchronize()
+    orb_ms = e0.elapsed_time(e1)
+    direct = nb.accel(q, eps, prec=nb.F32_F64ACC)
+    torch.cuda.synchronize()
+    d_host = direct.cpu().double().numpy()
+    _, _, nodes = nb.tree_shape(n, leaf, nodes=True)
+    nodes = nodes.astype(np.int64)
+    groups = _tree_groups(nodes, nb.TREE_GROUP)
+    gsz = np.array([e - b for b, e in groups], dtype=np.float64)
+    L = nb.lib()
+    out = torch.empty_like(q)
+    res = {"workload": "colliding Plummer pair, N=1048576, eps=0.005, step 0, ORB leaf 8, groups of 64, "
+                       "F32_F64ACC", "leaf": leaf, "orb_plus_gather_ms": round(orb_ms, 3), "theta": {}}
+    reps = 10
+    for theta in (0.5, 0.7, 1.0):
+        fc, ncnt, _, _ = nb.tree_lists(q, theta, leaf)
+        mn = int(ncnt.max().item())
+        fc, ncnt, _, ni = nb.tree_lists(q, theta, leaf, None, max(mn, 1))
+        torch.cuda.synchronize()
+        fc, ncnt, ni = fc.cpu().numpy(), ncnt.cpu().numpy(), ni.cpu().numpy()
+        sizes = nodes[:, 1] - nodes[:, 0]
+        near_bodies = np.array([sizes[ni[g, :ncnt[g]]].sum() for g in range(len(groups))], dtype=np.float64)
+        pairs = float((gsz * (fc + near_bodies) + gsz * (gsz - 1)).sum())
+        nb.tree_accel(q, eps, theta, leaf, prec=nb.F32_F64ACC, out=out)
+        torch.cuda.synchronize()
+        ts, tm = [], []
+        for _ in range(reps):
+            e0.record()
+            nb.tree_accel(q, eps, theta, leaf, prec=nb.F32_F64ACC, out=out)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+            e0.record()
+            rc = L.nbody_tree_moments(ctypes.c_void_p(q.data_ptr()), n, leaf, None, None,
+                                      ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+            e1.record()
+            torch.cuda.synchronize()
+            if rc != 0:
+                raise RuntimeError("nbody_tree_moments failed")
+            tm.append(e0.elapsed_time(e1))
+        t, t_mom = float(np.mean(ts)), float(np.mean(tm))
+        t_walk = t - t_mom
+        got = out.cpu().double().numpy()
+        rel = np.linalg.norm(got[:, :3] - d_host[:, :3], axis=1) / np.linalg.norm(d_host[:, :3], axis=1)
+        walk_tflops = FLOP_PER_PAIR * pairs / (t_walk * 1e-3) / 1e12
+        r = {"ms": round(t, 4), "ms_std": round(float(np.std(ts)), 4), "moments_ms": round(t_mom, 4),
+             "walk_force_ms": round(t_walk, 4), "interactions_per_body": round(pairs / n, 1),
+             "far_cells_per_group": round(float(fc.mean()), 1),
+             "pairs_per_s": round(pairs / (t_walk * 1e-3), 1),
+             "direct_equivalent_g_interactions_per_s": round(float(n) * n / (t * 1e-3) / 1e9, 1),
+             "speedup_vs_direct_kernel": round(direct_ms / t, 2),
+             "rms_rel_err_vs_direct": float(np.sqrt(np.mean(rel ** 2))),
+             "max_rel_err_vs_direct": float(rel.max()),
+             "walk_roofline": {"bound": "alu", "achieved": round(walk_tflops, 3), "peak": PEAK_FP32_TFLOPS,
+                               "unit": "TFLOP/s", "frac": round(walk_tflops / PEAK_FP32_TFLOPS, 4),
+                               "kernel": "k_tree_walk<F64ACC>", "flop_per_pair": FLOP_PER_PAIR}}
+        res["theta"][str(theta)] = r
+        log(f"[bench] tree theta {theta}: {t:.3f} ms ({t_mom:.3f} moments), {pairs / n:.0f} interactions/body, "
+            f"{walk_tflops:.1f} TFLOP/s in the walk, x{direct_ms / t:.1f} vs direct, "
+            f"rms err {r['rms_rel_err_vs_direct']:.2e}")
+    return res
 
 
 def cpu_leg(ics, pm0_host, acc0, eps, seconds):

@@ -294,6 +294,95 @@ __device__ __forceinline__ uint32_t block_reduce_u32(uint32_t v, bool is_min, ui
     return r;
 }
 
+// Finishes the recursion of a node of at most 64 bodies (positions
+// [lo, lo + m) of idx) with one wave, one position per lane, every node of a
+// level split at once.  keys: per-wave LDS of 3 x 64 total-order keys.  The
+// k smallest keys of a node are found by ranking (keys and indices are
+// distinct), then each leaf is ordered by original index.
+constexpr int kWaveSeg = 64;
+
+__device__ void orb_wave(int32_t *idx, uint32_t (*keys)[kWaveSeg], int lo, int m, int leaf,
+                         const float *__restrict__ xyz, int n, int lane)
+{
+    int b = lane < m ? idx[lo + lane] : -1;
+    uint32_t kx = 0, ky = 0, kz = 0;
+    if (lane < m) {
+        kx = tkey(xyz[b]);
+        ky = tkey(xyz[(size_t)n + b]);
+        kz = tkey(xyz[2 * (size_t)n + b]);
+    }
+    int slo = 0, sm = m;  // the node holding this lane's position (relative to lo)
+    for (;;) {
+        const bool split = lane < m && sm > leaf;
+        if (!__any(split)) break;
+        if (lane < m) {
+            keys[0][lane] = kx;
+            keys[1][lane] = ky;
+            keys[2][lane] = kz;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        int pos = lane;
+        int k = sm;
+        if (split) {
+            uint32_t bb[6] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0u, 0u};
+            for (int f = slo; f < slo + sm; ++f)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const uint32_t v = keys[a][f];
+                    bb[a] = min(bb[a], v);
+                    bb[3 + a] = max(bb[3 + a], v);
+                }
+            const int axis = pick_axis(bb);
+            const uint32_t mine = axis == 0 ? kx : (axis == 1 ? ky : kz);
+            int r = 0;
+            for (int f = slo; f < slo + sm; ++f) {
+                const uint32_t v = keys[axis][f];
+                const int bf = idx[lo + f];
+                r += (v < mine) || (v == mine && bf < b);
+            }
+            pos = slo + r;
+            const int L = (sm + leaf - 1) / leaf;
+            k = min(sm, leaf * ((L + 1) / 2));
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane < m) {
+            idx[lo + pos] = b;
+            keys[0][pos] = kx;
+            keys[1][pos] = ky;
+            keys[2][pos] = kz;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane < m) {
+            b = idx[lo + lane];
+            kx = keys[0][lane];
+            ky = keys[1][lane];
+            kz = keys[2][lane];
+            if (split) {
+                if (lane - slo < k) {
+                    sm = k;
+                } else {
+                    slo += k;
+                    sm -= k;
+                }
+            }
+        }
+    }
+    // leaves: ascending original index
+    int r = 0;
+    if (lane < m)
+        for (int f = slo; f < slo + sm; ++f) r += idx[lo + f] < b;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < m) idx[lo + slo + r] = b;
+}
+
 __global__ __launch_bounds__(kOrbBlock) void k_orb_block(const int2 *__restrict__ segs,
                                                          const float *__restrict__ xyz, int n,
                                                          const int32_t *__restrict__ cur, int leaf,
@@ -306,10 +395,14 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_block(const int2 *__restrict_
     __shared__ uint32_t cnt[2];
     __shared__ uint64_t kth_s;
     __shared__ uint32_t krem_s;
+    constexpr int kMaxTask = kMaxBlockSeg / kWaveSeg * 2 + 2;
+    __shared__ int2 task[kMaxTask];
+    __shared__ uint32_t wkeys[kOrbBlock / 64][3][kWaveSeg];
     const int2 sg = segs[blockIdx.x];
     const int start = sg.x, size = sg.y;
     for (int e = threadIdx.x; e < size; e += kOrbBlock) idx[e] = cur[start + e];
     __syncthreads();
+    int ntask = 0;  // same value in every thread: the loop below is uniform
     int stk_lo[24], stk_m[24], sp = 0;
     stk_lo[0] = 0;
     stk_m[0] = size;
@@ -317,6 +410,13 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_block(const int2 *__restrict_
     while (sp > 0) {
         --sp;
         const int lo = stk_lo[sp], m = stk_m[sp];
+        if (m <= kWaveSeg && ntask < kMaxTask) {
+            // finished by one wave below, all small nodes in parallel (past
+            // the list's capacity the block-wide path below takes them)
+            if (threadIdx.x == 0) task[ntask] = make_int2(lo, m);
+            ++ntask;
+            continue;
+        }
         if (m <= leaf) {
             // leaf: ascending original index (rank of each element; distinct)
             for (int e = threadIdx.x; e < m; e += kOrbBlock) {
@@ -400,6 +500,15 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_block(const int2 *__restrict_
         stk_m[sp] = k;
         ++sp;
     }
+    __syncthreads();
+    {
+        const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        for (int t = w; t < ntask; t += kOrbBlock / 64) {
+            const int2 tk = task[t];
+            orb_wave(idx, wkeys[w], tk.x, tk.y, leaf, xyz, n, lane);
+        }
+    }
+    __syncthreads();
     for (int e = threadIdx.x; e < size; e += kOrbBlock) perm[start + e] = idx[e];
 }
 

@@ -23,13 +23,12 @@
 //   it, so the size-to-distance ratio is below theta for every target.
 //
 // Kernels:
-// * k_tree_moments: one thread per leaf computes the leaf, then climbs; at
-//   each parent an agent-scope counter tells the second child to arrive, which
-//   combines left + right.  Nothing waits, and the counter is reset by the
-//   thread that consumed it, so the launch leaves it zero for the next.
+// * k_tree_leaves, then k_tree_inner once per node height (children are
+//   always lower than their parent): one thread per node, left + right.  The
+//   kernel boundaries order the levels, so no fences or counters are needed.
 // * k_tree_walk: one wave per group.  The walk starts from the siblings of
 //   the group's ancestors (every cell disjoint from the group) and pops up to
-//   64 cells per step from a stack in LDS, one cell per lane: the acceptance
+//   64 cells per step from a 512-entry stack in LDS, one cell per lane: the acceptance
 //   test is per cell, so the control flow of the wave stays uniform.
 //   Accepted cells go to an LDS batch of pseudo-body records that every lane
 //   sweeps with the same FP32 pair code as the direct sum (broadcast LDS
@@ -49,19 +48,17 @@ namespace nbi {
 namespace {
 
 constexpr int kGroup = 64;     // targets per group: one per lane
-constexpr int kStack = 1024;   // LDS stack entries per wave
+constexpr int kStack = 512;    // LDS stack entries per wave
 constexpr int kBuf = 128;      // LDS batch entries (cells, near ranges)
 
 struct TreeDev {
     const int4 *node;    // begin, end, left, right (-1 for a leaf)
-    const int *parent;   // -1 for the root
-    const int *leaves;   // leaf node ids in ORB order
-    const int *groups;   // group node ids in ORB order
+    const int *by_height;  // node ids by height (0 = leaves, in ORB order), ascending
+    const int *groups;     // group node ids in ORB order
     double4 *sums;       // M, Sx, Sy, Sz
     double4 *comd;       // com (FP64), diag2
     float4 *rec;         // com (FP32), M (FP32): the pseudo-body record
     float4 *lo, *hi;     // box
-    unsigned *cnt;       // children arrived, per node
 };
 
 __device__ __forceinline__ void finish_node(const TreeDev &T, int c, double M, double sx, double sy,
@@ -91,52 +88,49 @@ __device__ __forceinline__ void finish_node(const TreeDev &T, int c, double M, d
     T.hi[c] = hi;
 }
 
-__global__ __launch_bounds__(256) void k_tree_moments(const float4 *__restrict__ pm, TreeDev T,
-                                                      int nleaves)
+// Leaves: one thread per leaf sums its bodies in position order.
+__global__ __launch_bounds__(256) void k_tree_leaves(const float4 *__restrict__ pm, TreeDev T, int nleaves)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nleaves) return;
-    int c = T.leaves[t];
-    {
-        const int4 nd = T.node[c];
-        const float4 p0 = pm[nd.x];
-        float4 lo = make_float4(p0.x, p0.y, p0.z, 0.0f), hi = lo;
-        double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
-        for (int p = nd.x; p < nd.y; ++p) {
-            const float4 b = pm[p];
-            const double m = b.w;
-            M = M + m;
-            const double mx = m * (double)b.x, my = m * (double)b.y, mz = m * (double)b.z;
-            sx = sx + mx;
-            sy = sy + my;
-            sz = sz + mz;
-            if (b.x < lo.x) lo.x = b.x;
-            if (b.x > hi.x) hi.x = b.x;
-            if (b.y < lo.y) lo.y = b.y;
-            if (b.y > hi.y) hi.y = b.y;
-            if (b.z < lo.z) lo.z = b.z;
-            if (b.z > hi.z) hi.z = b.z;
-        }
-        finish_node(T, c, M, sx, sy, sz, lo, hi);
+    const int c = T.by_height[t];
+    const int4 nd = T.node[c];
+    const float4 p0 = pm[nd.x];
+    float4 lo = make_float4(p0.x, p0.y, p0.z, 0.0f), hi = lo;
+    double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+    for (int p = nd.x; p < nd.y; ++p) {
+        const float4 b = pm[p];
+        const double m = b.w;
+        M = M + m;
+        const double mx = m * (double)b.x, my = m * (double)b.y, mz = m * (double)b.z;
+        sx = sx + mx;
+        sy = sy + my;
+        sz = sz + mz;
+        if (b.x < lo.x) lo.x = b.x;
+        if (b.x > hi.x) hi.x = b.x;
+        if (b.y < lo.y) lo.y = b.y;
+        if (b.y > hi.y) hi.y = b.y;
+        if (b.z < lo.z) lo.z = b.z;
+        if (b.z > hi.z) hi.z = b.z;
     }
-    for (;;) {
-        const int par = T.parent[c];
-        if (par < 0) return;
-        __threadfence();  // release this subtree's moments
-        const unsigned old = atomicAdd(&T.cnt[par], 1u);
-        if (old == 0u) return;  // the sibling finishes later and combines
-        __threadfence();  // acquire the sibling's moments
-        T.cnt[par] = 0u;
-        const int4 nd = T.node[par];
-        const double4 a = T.sums[nd.z], b = T.sums[nd.w];
-        const float4 la = T.lo[nd.z], lb = T.lo[nd.w], ha = T.hi[nd.z], hb = T.hi[nd.w];
-        const float4 lo = make_float4(la.x < lb.x ? la.x : lb.x, la.y < lb.y ? la.y : lb.y,
-                                      la.z < lb.z ? la.z : lb.z, 0.0f);
-        const float4 hi = make_float4(ha.x > hb.x ? ha.x : hb.x, ha.y > hb.y ? ha.y : hb.y,
-                                      ha.z > hb.z ? ha.z : hb.z, 0.0f);
-        finish_node(T, par, a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w, lo, hi);
-        c = par;
-    }
+    finish_node(T, c, M, sx, sy, sz, lo, hi);
+}
+
+// Inner nodes of one height (their children are all lower, so finished by
+// the previous launches): left + right.
+__global__ __launch_bounds__(256) void k_tree_inner(TreeDev T, int first, int count)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    const int c = T.by_height[first + t];
+    const int4 nd = T.node[c];
+    const double4 a = T.sums[nd.z], b = T.sums[nd.w];
+    const float4 la = T.lo[nd.z], lb = T.lo[nd.w], ha = T.hi[nd.z], hb = T.hi[nd.w];
+    const float4 lo = make_float4(la.x < lb.x ? la.x : lb.x, la.y < lb.y ? la.y : lb.y,
+                                  la.z < lb.z ? la.z : lb.z, 0.0f);
+    const float4 hi = make_float4(ha.x > hb.x ? ha.x : hb.x, ha.y > hb.y ? ha.y : hb.y,
+                                  ha.z > hb.z ? ha.z : hb.z, 0.0f);
+    finish_node(T, c, a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w, lo, hi);
 }
 
 __device__ __forceinline__ double box_gap(double p, double a, double b)
@@ -171,7 +165,9 @@ __device__ __forceinline__ void sweep_cells(const float4 *cb, int cnt, const Tar
 }
 
 template <int MODE, bool INSPECT>
-__global__ __launch_bounds__(64) void k_tree_walk(const float4 *__restrict__ src, int n, TreeDev T,
+// 7 waves per SIMD: 5 KB of LDS per wave and at most 72 VGPRs (measured
+// faster than 6 waves, and than 8 waves with register spills).
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void k_tree_walk(const float4 *__restrict__ src, int n, TreeDev T,
                                                   float eps2_in, double G, double theta2, WalkOut O)
 {
     __shared__ int stk[kStack];
@@ -360,24 +356,27 @@ __global__ void k_tree_export(TreeDev T, int nn, double *__restrict__ mom, float
 // ---- host plan ------------------------------------------------------------------
 struct HostTree {
     std::vector<int4> node;
-    std::vector<int> parent, leaves, groups;
+    std::vector<int> leaves, groups, height;
+    std::vector<int> by_height;    // node ids ordered by height, leaves first in ORB order
+    std::vector<int> height_off;   // start of each height in by_height, plus the end
 };
 
-int build_rec(HostTree &h, int b, int size, int leaf, int par)
+int build_rec(HostTree &h, int b, int size, int leaf)
 {
     const int id = (int)h.node.size();
     h.node.push_back(make_int4(b, b + size, -1, -1));
-    h.parent.push_back(par);
+    h.height.push_back(0);
     if (size <= leaf) {
         h.leaves.push_back(id);
         return id;
     }
     const int L = (size + leaf - 1) / leaf;
     const int k = std::min(size, leaf * ((L + 1) / 2));
-    const int l = build_rec(h, b, k, leaf, id);
-    const int r = build_rec(h, b + k, size - k, leaf, id);
+    const int l = build_rec(h, b, k, leaf);
+    const int r = build_rec(h, b + k, size - k, leaf);
     h.node[id].z = l;
     h.node[id].w = r;
+    h.height[id] = 1 + std::max(h.height[l], h.height[r]);
     return id;
 }
 
@@ -394,16 +393,25 @@ void groups_rec(HostTree &h, int id)
 
 void plan(HostTree &h, int n, int leaf)
 {
-    h.node.clear();
-    h.parent.clear();
-    h.leaves.clear();
-    h.groups.clear();
+    h = HostTree();
     const size_t nl = (size_t)((n + (int64_t)leaf - 1) / leaf);
     h.node.reserve(2 * nl);
-    h.parent.reserve(2 * nl);
+    h.height.reserve(2 * nl);
     h.leaves.reserve(nl);
-    build_rec(h, 0, n, leaf, -1);
+    build_rec(h, 0, n, leaf);
     groups_rec(h, 0);
+    // bucket the nodes by height (counting sort; leaves keep ORB order)
+    const int H = h.height[0];
+    h.height_off.assign(H + 2, 0);
+    for (int v : h.height) ++h.height_off[v + 1];
+    for (int k = 0; k <= H; ++k) h.height_off[k + 1] += h.height_off[k];
+    h.by_height.assign(h.node.size(), 0);
+    std::vector<int> pos(h.height_off.begin(), h.height_off.end() - 1);
+    for (size_t id = 0; id < h.node.size(); ++id) {
+        if (h.height[id] == 0) continue;
+        h.by_height[pos[h.height[id]]++] = (int)id;
+    }
+    for (size_t k = 0; k < h.leaves.size(); ++k) h.by_height[k] = h.leaves[k];
 }
 
 struct TreeCache {
@@ -434,18 +442,16 @@ int tree_prepare(int n, int leaf, hipStream_t s, TreeDev &out)
     }
     HostTree h;
     plan(h, n, leaf);
-    const size_t nn = h.node.size(), nl = h.leaves.size(), ng = h.groups.size();
+    const size_t nn = h.node.size(), ng = h.groups.size();
     const size_t o_node = 0;
-    const size_t o_par = o_node + align256(nn * sizeof(int4));
-    const size_t o_leaf = o_par + align256(nn * sizeof(int));
-    const size_t o_grp = o_leaf + align256(nl * sizeof(int));
+    const size_t o_byh = o_node + align256(nn * sizeof(int4));
+    const size_t o_grp = o_byh + align256(nn * sizeof(int));
     const size_t o_sums = o_grp + align256(ng * sizeof(int));
     const size_t o_comd = o_sums + align256(nn * sizeof(double4));
     const size_t o_rec = o_comd + align256(nn * sizeof(double4));
     const size_t o_lo = o_rec + align256(nn * sizeof(float4));
     const size_t o_hi = o_lo + align256(nn * sizeof(float4));
-    const size_t o_cnt = o_hi + align256(nn * sizeof(float4));
-    const size_t total = o_cnt + align256(nn * sizeof(unsigned));
+    const size_t total = o_hi + align256(nn * sizeof(float4));
     if (C.mem) {
         // work already enqueued may still read the old tables
         (void)hipDeviceSynchronize();
@@ -461,26 +467,21 @@ int tree_prepare(int n, int leaf, hipStream_t s, TreeDev &out)
     char *base = (char *)mem;
     TreeDev d;
     d.node = (const int4 *)(base + o_node);
-    d.parent = (const int *)(base + o_par);
-    d.leaves = (const int *)(base + o_leaf);
+    d.by_height = (const int *)(base + o_byh);
     d.groups = (const int *)(base + o_grp);
     d.sums = (double4 *)(base + o_sums);
     d.comd = (double4 *)(base + o_comd);
     d.rec = (float4 *)(base + o_rec);
     d.lo = (float4 *)(base + o_lo);
     d.hi = (float4 *)(base + o_hi);
-    d.cnt = (unsigned *)(base + o_cnt);
     // pageable copies complete on the host side before returning; the vectors
     // stay alive in the cache in any case
     C.host = std::move(h);
     hipError_t e = hipMemcpyAsync(base + o_node, C.host.node.data(), nn * sizeof(int4), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(base + o_par, C.host.parent.data(), nn * sizeof(int), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(base + o_leaf, C.host.leaves.data(), nl * sizeof(int), hipMemcpyHostToDevice, s);
+        e = hipMemcpyAsync(base + o_byh, C.host.by_height.data(), nn * sizeof(int), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(base + o_grp, C.host.groups.data(), ng * sizeof(int), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = launch_fill_zero(d.cnt, nn * sizeof(unsigned), s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         (void)hipFree(mem);
@@ -496,10 +497,17 @@ int tree_prepare(int n, int leaf, hipStream_t s, TreeDev &out)
     return NBODY_OK;
 }
 
-hipError_t launch_moments(const float4 *pm, const TreeDev &d, int nleaves, hipStream_t s)
+hipError_t launch_moments(const float4 *pm, const TreeDev &d, const HostTree &h, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_tree_moments, dim3((nleaves + 255) / 256), dim3(256), 0, s, pm, d, nleaves);
-    return hipGetLastError();
+    const int nl = (int)h.leaves.size();
+    hipLaunchKernelGGL(k_tree_leaves, dim3((nl + 255) / 256), dim3(256), 0, s, pm, d, nl);
+    hipError_t e = hipGetLastError();
+    for (size_t k = 1; e == hipSuccess && k + 1 < h.height_off.size(); ++k) {
+        const int first = h.height_off[k], count = h.height_off[k + 1] - first;
+        hipLaunchKernelGGL(k_tree_inner, dim3((count + 255) / 256), dim3(256), 0, s, d, first, count);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 template <int MODE, bool INSPECT>
@@ -529,7 +537,7 @@ int tree_moments(const void *pm, int n, int leaf, double *mom, float *box, hipSt
     int rc = tree_prepare(n, leaf, s, d);
     if (rc != NBODY_OK) return rc;
     const int nn = (int)g_tree.host.node.size();
-    hipError_t e = launch_moments((const float4 *)pm, d, (int)g_tree.host.leaves.size(), s);
+    hipError_t e = launch_moments((const float4 *)pm, d, g_tree.host, s);
     if (e == hipSuccess && (mom || box)) {
         hipLaunchKernelGGL(k_tree_export, dim3((nn + 255) / 256), dim3(256), 0, s, d, nn, mom, box);
         e = hipGetLastError();
@@ -544,7 +552,7 @@ int tree_lists(const void *pm, int n, int leaf, double theta, int max_far, int m
     TreeDev d;
     int rc = tree_prepare(n, leaf, s, d);
     if (rc != NBODY_OK) return rc;
-    hipError_t e = launch_moments((const float4 *)pm, d, (int)g_tree.host.leaves.size(), s);
+    hipError_t e = launch_moments((const float4 *)pm, d, g_tree.host, s);
     WalkOut o{};
     o.far_cnt = far_cnt;
     o.near_cnt = near_cnt;
@@ -565,7 +573,7 @@ int tree_accel(const void *pm, int n, int prec, double G, double eps, double the
     TreeDev d;
     int rc = tree_prepare(n, leaf, s, d);
     if (rc != NBODY_OK) return rc;
-    hipError_t e = launch_moments((const float4 *)pm, d, (int)g_tree.host.leaves.size(), s);
+    hipError_t e = launch_moments((const float4 *)pm, d, g_tree.host, s);
     WalkOut o{};
     o.acc_pot = (float4 *)out;
     const int ng = (int)g_tree.host.groups.size();
