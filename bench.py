@@ -195,15 +195,27 @@ def main():
     print(json.dumps(result), flush=True)
 
 
+def force_source_sha1():
+    """SHA-1 of the sources the force kernel is compiled from."""
+    import hashlib
+    h = hashlib.sha1()
+    for f in ("accel.hip", "pair.h", "internal.h"):
+        with open(os.path.join(ROOT, "paper_1211_2292_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def measured_traffic(tune, n):
     """HBM bytes per force launch from the committed rocprofv3 counter
-    summary, if it was taken on the kernel shape in use now; else None."""
+    summary, if it was taken on the kernel shape in use now and on the same
+    kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "k_accel_f32_collide1m_pmc.md")
     try:
+        sha = force_source_sha1()
         for line in open(path):
             if line.startswith("traffic_record:"):
                 rec = json.loads(line.split(":", 1)[1])
-                if rec["shape"] == list(tune) and rec["n"] == n:
+                if rec["shape"] == list(tune) and rec["n"] == n and rec.get("src_sha1") == sha:
                     return rec["bytes_per_launch"]
     except (OSError, ValueError, KeyError):
         pass
