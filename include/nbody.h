@@ -257,6 +257,18 @@ int nbody_trajectory_adjoint(const void *ckpt, int64_t n, int32_t prec, double G
  *   counts only; lists longer than the maximum are cut, the counts are not).
  * Device pointers for all arrays except nodes_out.
  */
+/*
+ * nbody_tree_leapfrog: nsteps kick-drift-kick steps (as nbody_leapfrog_kdk)
+ * with tree forces.  pos_mass, vel, acc_pot: n float4 records in the ORB
+ * order of `leaf`.  reorder_every = K > 0 puts the state into the ORB order
+ * of its current positions at entry and again before the force evaluation of
+ * every K-th step (x, v and a move with their bodies), and composes
+ * order[p] (int32[n], device, caller-initialized, e.g. to the identity) so
+ * that it keeps naming the caller's index of the body at position p;
+ * K = 0 never re-orders (order may be NULL).  flags: NBODY_ACC_VALID,
+ * NBODY_ENERGY (energy_out as for nbody_leapfrog_kdk, with the tree
+ * potential).  Re-ordering uses library scratch of about 24 bytes per body.
+ */
 #define NBODY_TREE_GROUP 64
 int nbody_tree_shape(int64_t n, int32_t leaf, int64_t *num_nodes, int64_t *num_groups,
                      int32_t *nodes_out);
@@ -267,6 +279,10 @@ int nbody_tree_moments(const void *pos_mass, int64_t n, int32_t leaf, double *mo
 int nbody_tree_lists(const void *pos_mass, int64_t n, int32_t leaf, double theta,
                      int32_t max_far, int32_t max_near, int32_t *far_count, int32_t *near_count,
                      int32_t *far_ids, int32_t *near_ids, void *stream);
+int nbody_tree_leapfrog(void *pos_mass, void *vel, void *acc_pot, int32_t *order, int64_t n,
+                        int32_t prec, double G, double eps, double theta, int32_t leaf, double dt,
+                        int32_t nsteps, int32_t reorder_every, uint32_t flags,
+                        double *energy_out, void *stream);
 
 /*
  * Tuning.  nbody_autotune times the candidate kernel shapes for one problem

@@ -25,7 +25,7 @@ __all__ = [
     "lib", "accel", "accel_vjp", "leapfrog_kdk", "kick_drift", "batched_accel", "energy", "orb_order",
     "permute", "trajectory_forward", "trajectory_adjoint", "NBodyTrajectory", "autotune",
     "set_tuning", "get_tuning", "release", "NBodyError", "TREE_GROUP", "tree_shape", "tree_accel",
-    "tree_moments", "tree_lists",
+    "tree_moments", "tree_lists", "tree_leapfrog",
 ]
 
 F64, F32, F32_KAHAN, F32_F64ACC = 0, 1, 2, 3
@@ -61,6 +61,8 @@ _SIGS = {
     "nbody_tree_accel": [_vp, _i64, _i32, _dbl, _dbl, _dbl, _i32, _vp, _vp],
     "nbody_tree_moments": [_vp, _i64, _i32, _vp, _vp, _vp],
     "nbody_tree_lists": [_vp, _i64, _i32, _dbl, _i32, _i32, _vp, _vp, _vp, _vp, _vp],
+    "nbody_tree_leapfrog": [_vp, _vp, _vp, _vp, _i64, _i32, _dbl, _dbl, _dbl, _i32, _dbl, _i32, _i32,
+                            ctypes.c_uint32, _vp, _vp],
     "nbody_autotune": [_i32, _i32, _i64, _vp, _i32, _vp],
     "nbody_set_tuning": [_i32, _i32, _i32, _i32, _i32, _i32],
     "nbody_get_tuning": [_i32, _i32, _i64, _vp, _vp, _vp, _vp],
@@ -317,6 +319,29 @@ def tree_lists(pos_mass, theta, leaf=8, max_far=None, max_near=None):
                                   int(max_near or 0), _ptr(fc), _ptr(nc), None if fi is None else _ptr(fi),
                                   None if ni is None else _ptr(ni), _stream()))
     return fc, nc, fi, ni
+
+
+def tree_leapfrog(pos_mass, vel, acc, eps, theta, dt, nsteps, leaf=8, reorder_every=0, order=None,
+                  acc_valid=False, energy=False, G=1.0, prec=None):
+    """Kick-drift-kick steps with tree forces, in place on ORB-ordered
+    float32 records.  reorder_every = K > 0 re-orders the state by ORB at
+    entry and every K steps and composes ``order`` (int32 (N,), created as
+    the identity when None); returns (order, energies (nsteps+1, 2) or None)."""
+    pm = _rec(pos_mass, "pos_mass", torch.float32)
+    v = _rec(vel, "vel", torch.float32)
+    a = _rec(acc, "acc", torch.float32)
+    p = _prec(pm, prec)
+    n = pm.shape[0]
+    if reorder_every and order is None:
+        order = torch.arange(n, dtype=torch.int32, device=pm.device)
+    if order is not None and (order.dtype != torch.int32 or order.numel() != n or not order.is_contiguous()):
+        raise ValueError("order must be a contiguous int32 tensor of N entries")
+    en = torch.empty((nsteps + 1, 2), dtype=torch.float64, device=pm.device) if energy else None
+    flags = (ACC_VALID if acc_valid else 0) | (ENERGY if energy else 0)
+    _check(lib().nbody_tree_leapfrog(_ptr(pm), _ptr(v), _ptr(a), None if order is None else _ptr(order), n, p,
+                                     float(G), float(eps), float(theta), int(leaf), float(dt), int(nsteps),
+                                     int(reorder_every), flags, None if en is None else _ptr(en), _stream()))
+    return order, en
 
 
 def trajectory_forward(pos_mass, vel, eps, dt, nsteps, ckpt_every, G=1.0, prec=None):

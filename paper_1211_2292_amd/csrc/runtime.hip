@@ -812,6 +812,41 @@ int nbody_tree_lists(const void *pos_mass, int64_t n, int32_t leaf, double theta
                       near_ids, (hipStream_t)stream);
 }
 
+int nbody_tree_leapfrog(void *pos_mass, void *vel, void *acc_pot, int32_t *order, int64_t n, int32_t prec,
+                        double G, double eps, double theta, int32_t leaf, double dt, int32_t nsteps,
+                        int32_t reorder_every, uint32_t flags, double *energy_out, void *stream)
+{
+    NB_CHECK(check_tree(n, leaf));
+    if (!prec_ok(prec) || nsteps < 0 || reorder_every < 0) {
+        set_error("bad precision, nsteps or reorder_every");
+        return NBODY_E_INVAL;
+    }
+    if (prec == NBODY_F64) {
+        set_error("the tree code runs the FP32 modes only");
+        return NBODY_E_UNSUPPORTED;
+    }
+    if (flags & ~(NBODY_ACC_VALID | NBODY_ENERGY)) {
+        set_error("unsupported flags 0x%x (NBODY_ACC_VALID and NBODY_ENERGY only)", flags);
+        return NBODY_E_INVAL;
+    }
+    NB_CHECK(check_scalars(G, eps, dt));
+    NB_CHECK(check_theta(theta));
+    NB_CHECK(check_vec(pos_mass, prec, "pos_mass"));
+    NB_CHECK(check_vec(vel, prec, "vel"));
+    NB_CHECK(check_vec(acc_pot, prec, "acc_pot"));
+    if (reorder_every > 0 && (!order || (uintptr_t)order % 4)) {
+        set_error("order must be a 4-byte aligned int32 array when reorder_every > 0");
+        return NBODY_E_INVAL;
+    }
+    if ((flags & NBODY_ENERGY) && (!energy_out || (uintptr_t)energy_out % 8)) {
+        set_error("energy_out NULL or misaligned");
+        return NBODY_E_INVAL;
+    }
+    return tree_leapfrog(pos_mass, vel, acc_pot, order, (int)n, prec, G, eps, theta, leaf, dt, nsteps,
+                         reorder_every, flags, (flags & NBODY_ENERGY) ? energy_out : nullptr,
+                         (hipStream_t)stream);
+}
+
 // ---- trajectory + adjoint ---------------------------------------------------
 int nbody_trajectory_forward(void *pos_mass, void *vel, int64_t n, int32_t prec, double G,
                              double eps, double dt, int32_t nsteps, int32_t ckpt_every, void *ckpt,

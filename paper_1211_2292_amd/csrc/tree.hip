@@ -420,6 +420,10 @@ struct TreeCache {
     void *mem = nullptr;
     size_t bytes = 0;
     TreeDev d{};
+    // re-ordering scratch of the tree leapfrog: one record array, the new
+    // permutation and the composed order (allocated on first use)
+    void *reo = nullptr;
+    size_t reo_bytes = 0;
 };
 std::mutex g_tree_mu;
 TreeCache g_tree;
@@ -589,10 +593,108 @@ int tree_accel(const void *pm, int n, int prec, double G, double eps, double the
     return e == hipSuccess ? NBODY_OK : hip_fail(e, "tree force");
 }
 
+// ---- tree leapfrog ---------------------------------------------------------------
+namespace {
+
+__global__ __launch_bounds__(kBlock) void k_compose(const int32_t *__restrict__ order,
+                                                    const int32_t *__restrict__ perm, int n,
+                                                    int32_t *__restrict__ out)
+{
+    const int p = blockIdx.x * kBlock + threadIdx.x;
+    if (p < n) out[p] = order[perm[p]];
+}
+
+// Puts the state into the ORB order of its current positions: x, v and a
+// move with their bodies, and order[p] keeps naming the caller's index of
+// the body at position p.
+int reorder(void *pm, void *vel, void *acc, int32_t *order, int n, int leaf, hipStream_t s)
+{
+    const size_t rb = (size_t)n * 16, ib = (size_t)n * 4;
+    const size_t need = rb + 2 * ((ib + 255) & ~size_t(255)) + 256;
+    {
+        std::lock_guard<std::mutex> lk(g_tree_mu);
+        if (g_tree.reo_bytes < need) {
+            if (g_tree.reo) {
+                (void)hipDeviceSynchronize();
+                (void)hipFree(g_tree.reo);
+                g_tree.reo = nullptr;
+                g_tree.reo_bytes = 0;
+            }
+            if (hipMalloc(&g_tree.reo, need) != hipSuccess) {
+                set_error("cannot allocate %zu bytes of re-ordering scratch", need);
+                return NBODY_E_NOMEM;
+            }
+            g_tree.reo_bytes = need;
+        }
+    }
+    char *base = (char *)g_tree.reo;
+    void *tmp = base;
+    int32_t *perm = (int32_t *)(base + ((rb + 255) & ~size_t(255)));
+    int32_t *ord = (int32_t *)((char *)perm + ((ib + 255) & ~size_t(255)));
+    int rc = orb_order(pm, NBODY_F32, n, leaf, perm, s);
+    if (rc != NBODY_OK) return rc;
+    void *arr[3] = {pm, vel, acc};
+    for (void *a : arr) {
+        hipError_t e = launch_permute(a, tmp, perm, n, 16, false, s);
+        if (e == hipSuccess) e = launch_copy(a, tmp, rb, s);
+        if (e != hipSuccess) return hip_fail(e, "tree re-ordering");
+    }
+    if (order) {
+        hipLaunchKernelGGL(k_compose, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, order, perm, n, ord);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(order, ord, ib, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "tree re-ordering");
+    }
+    return NBODY_OK;
+}
+
+}  // namespace
+
+int tree_leapfrog(void *pm, void *vel, void *acc, int32_t *order, int n, int prec, double G, double eps,
+                  double theta, int leaf, double dt, int nsteps, int reorder_every, unsigned flags,
+                  double *energy, hipStream_t s)
+{
+    const double h = 0.5 * dt;
+    double *ep = nullptr;
+    if (energy) {
+        ep = (double *)scratch(kSlotEnergy, sizeof(double) * 2 * step_blocks(n));
+        if (!ep) {
+            set_error("cannot allocate energy scratch");
+            return NBODY_E_NOMEM;
+        }
+    }
+    int eb = 0;
+    if (reorder_every > 0) {
+        const int rc = reorder(pm, vel, acc, order, n, leaf, s);
+        if (rc != NBODY_OK) return rc;
+    }
+    if (!(flags & NBODY_ACC_VALID)) {
+        const int rc = tree_accel(pm, n, prec, G, eps, theta, leaf, acc, s);
+        if (rc != NBODY_OK) return rc;
+    }
+    hipError_t e = launch_step(prec, pm, vel, acc, n, h, dt, false, nsteps > 0, ep, &eb, s);
+    if (e == hipSuccess && energy) e = launch_energy_final(ep, eb, energy, s);
+    if (e != hipSuccess) return hip_fail(e, "tree leapfrog step");
+    for (int k = 0; k < nsteps; ++k) {
+        if (reorder_every > 0 && (k + 1) % reorder_every == 0) {
+            const int rc = reorder(pm, vel, acc, order, n, leaf, s);
+            if (rc != NBODY_OK) return rc;
+        }
+        const int rc = tree_accel(pm, n, prec, G, eps, theta, leaf, acc, s);
+        if (rc != NBODY_OK) return rc;
+        const bool last = (k == nsteps - 1);
+        e = launch_step(prec, pm, vel, acc, n, h, dt, true, !last, ep, &eb, s);
+        if (e == hipSuccess && energy) e = launch_energy_final(ep, eb, energy + 2 * (k + 1), s);
+        if (e != hipSuccess) return hip_fail(e, "tree leapfrog step");
+    }
+    return NBODY_OK;
+}
+
 void tree_release()
 {
     std::lock_guard<std::mutex> lk(g_tree_mu);
     if (g_tree.mem) (void)hipFree(g_tree.mem);
+    if (g_tree.reo) (void)hipFree(g_tree.reo);
     g_tree = TreeCache();
 }
 

@@ -195,3 +195,102 @@ def test_repeat_and_shape_change_same_bits():
     _ = host(nb.tree_accel(q2, 0.01, 0.7, 16))
     r2 = host(nb.tree_accel(q, 0.01, 0.7, 8))
     assert np.array_equal(r1, r2)
+
+
+# ---- tree leapfrog -----------------------------------------------------------------
+
+def _kdk_oracle(orc, q, v, eps, dt, steps, accel):
+    """FP64 kick-drift-kick (one force evaluation per step) with the given
+    oracle force on the fixed ORB order."""
+    x = widen32(q).copy()
+    vv = np.asarray(v, dtype=np.float64)[:, :3].copy()
+    a, _ = accel(x)
+    for _ in range(steps):
+        vv += 0.5 * dt * a
+        x[:, :3] += dt * vv
+        a, _ = accel(x)
+        vv += 0.5 * dt * a
+    return x, vv
+
+
+def test_tree_leapfrog_is_kdk_with_tree_forces(orc):
+    """Ten steps taken one call at a time: every force the integrator used
+    is the oracle's tree force at the integrator's own positions (FP32
+    tolerance), every step satisfies the kick-drift-kick recurrence, and one
+    ten-step call reproduces the ten single steps.  The trajectory as a whole
+    stays closer to the oracle's tree-force integration than to the direct
+    sum (the tree decisions depend on the last bits of the positions, so the
+    two FP64/FP32 trajectories are compared only this way)."""
+    torch, nb = gpu()
+    n, leaf, theta, eps, dt, steps = 3000, 8, 0.6, 0.01, 1e-3, 10
+    pm, v0 = ics.plummer(n, 380)
+    p = to_dev(torch, np.asarray(pm, dtype=np.float32), torch.float32)
+    perm = nb.orb_order(p, leaf)
+    q = nb.permute(p, perm)
+    v = nb.permute(to_dev(torch, np.c_[v0[:, :3], np.zeros(n)].astype(np.float32), torch.float32), perm)
+    q1, v1 = q.clone(), v.clone()
+    qh, vh = q.cpu().numpy(), v.cpu().numpy()
+    a = nb.tree_accel(q, eps, theta, leaf, prec=nb.F32_F64ACC)
+    h = 0.5 * dt
+    for _ in range(steps):
+        xk, vk, ak = host(q), host(v), host(a)
+        at, _ = orc.tree_accel(xk, leaf, 64, theta, eps)
+        assert rms_rel(ak[:, :3], at) < 1e-6
+        nb.tree_leapfrog(q, v, a, eps, theta, dt, 1, leaf, acc_valid=True, prec=nb.F32_F64ACC)
+        x1, v1_, a1 = host(q), host(v), host(a)
+        np.testing.assert_allclose(x1[:, :3], xk[:, :3] + dt * (vk[:, :3] + h * ak[:, :3]), rtol=0, atol=1e-6)
+        np.testing.assert_allclose(v1_[:, :3], vk[:, :3] + h * (ak[:, :3] + a1[:, :3]), rtol=0, atol=1e-6)
+    a1 = torch.empty_like(q1)
+    nb.tree_leapfrog(q1, v1, a1, eps, theta, dt, steps, leaf, prec=nb.F32_F64ACC)
+    assert rms_rel(host(q1)[:, :3], host(q)[:, :3]) < 1e-7
+    assert rms_rel(host(v1)[:, :3] - vh[:, :3], host(v)[:, :3] - vh[:, :3]) < 1e-6
+    dv = host(v)[:, :3] - vh[:, :3].astype(np.float64)
+    base = vh[:, :3].astype(np.float64)
+    _, vt = _kdk_oracle(orc, qh, vh, eps, dt, steps, lambda x: orc.tree_accel(x, leaf, 64, theta, eps))
+    _, vd = _kdk_oracle(orc, qh, vh, eps, dt, steps, lambda x: orc.accel(x, eps))
+    e_tree, e_direct = rms_rel(dv, vt - base), rms_rel(dv, vd - base)
+    print(f"tree leapfrog: dv against tree oracle {e_tree:.2e}, against direct sum {e_direct:.2e}")
+    assert e_tree < 0.5 * e_direct
+
+
+def test_tree_leapfrog_theta_zero_and_reordering_match_direct(orc):
+    """theta = 0 is the exact sum, so the tree leapfrog with re-ordering every
+    3 steps, mapped back through `order`, equals the direct leapfrog on the
+    caller's order up to FP32 rounding; `order` stays a permutation."""
+    torch, nb = gpu()
+    n, leaf, eps, dt, steps = 2500, 8, 0.02, 2e-3, 10
+    pm, v0 = ics.plummer(n, 390)
+    p = to_dev(torch, np.asarray(pm, dtype=np.float32), torch.float32)
+    v = to_dev(torch, np.c_[v0[:, :3], np.zeros(n)].astype(np.float32), torch.float32)
+    a = torch.empty_like(p)
+    pd, vd, ad = p.clone(), v.clone(), torch.empty_like(p)
+    order, _ = nb.tree_leapfrog(p, v, a, eps, 0.0, dt, steps, leaf, reorder_every=3, prec=nb.F32_F64ACC)
+    nb.leapfrog_kdk(pd, vd, ad, eps, dt, steps, prec=nb.F32_F64ACC)
+    o = order.cpu().numpy()
+    assert np.array_equal(np.sort(o), np.arange(n))
+    back_x = np.empty((n, 4)); back_v = np.empty((n, 4))
+    back_x[o] = host(p); back_v[o] = host(v)
+    assert rms_rel(back_x[:, :3], host(pd)[:, :3]) < 1e-6
+    assert rms_rel(back_v[:, :3] - v0[:, :3], host(vd)[:, :3] - v0[:, :3]) < 1e-5
+    assert np.array_equal(back_x[:, 3], host(pd)[:, 3])
+
+
+def test_tree_leapfrog_energy():
+    """Energy output of the tree leapfrog (tree potential) over 200 steps of
+    a Plummer sphere, re-ordered every 20 steps: the FP64 energies are
+    reported per step and the drift stays small."""
+    torch, nb = gpu()
+    n, leaf, theta, eps, dt, steps = 16384, 8, 0.5, 0.01, 1e-3, 200
+    pm, v0 = ics.plummer(n, 400)
+    p = to_dev(torch, np.asarray(pm, dtype=np.float32), torch.float32)
+    v = to_dev(torch, np.c_[v0[:, :3], np.zeros(n)].astype(np.float32), torch.float32)
+    a = torch.empty_like(p)
+    _, en = nb.tree_leapfrog(p, v, a, eps, theta, dt, steps, leaf, reorder_every=20, energy=True,
+                             prec=nb.F32_F64ACC)
+    e = en.cpu().numpy().sum(1)
+    drift = np.abs(e / e[0] - 1.0).max()
+    print(f"tree leapfrog energy: max |dE/E| over {steps} steps {drift:.2e}")
+    assert np.isfinite(e).all()
+    assert drift < 1e-3
+    k_end, u_end = nb.energy(p, v, a).cpu().numpy()
+    assert abs((k_end + u_end) / e[-1] - 1.0) < 1e-12
