@@ -50,6 +50,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-extras", action="store_true", help="skip adjoint, batched and CPU legs")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--tree-counters", action="store_true",
+                    help="two tree evaluations (theta 0.7, leaf 8) of the workload for counter runs")
     ap.add_argument("--counters", action="store_true",
                     help="counter-collection mode: two force launches of the headline workload "
                          "and one 1 GiB device copy (the copy calibrates byte counters); no JSON")
@@ -86,6 +88,15 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         log("[bench] counters mode: 2 force launches, 1 GiB copy (1073741824 B read + written)")
+        return
+
+    if args.tree_counters:
+        q = nb.permute(pm, nb.orb_order(pm, 8))
+        out = torch.empty_like(q)
+        for _ in range(2):
+            nb.tree_accel(q, eps, 0.7, 8, prec=prec, out=out)
+        torch.cuda.synchronize()
+        log("[bench] tree counters mode: 2 tree evaluations, theta 0.7, leaf 8, F32_F64ACC")
         return
 
     # ORB body order (the paper's recursive bisection, used as an ordering):
