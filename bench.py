@@ -194,7 +194,9 @@ def main():
                      "traffic": measured_traffic(tune, n),
                      "kernel": ("k_accel_lds_f32" if tune[3] else "k_accel_f32") + f"<{tune[0]}, F64ACC>",
                      "flop_per_pair": FLOP_PER_PAIR,
-                     "avg_launch_ms": round(kern_avg, 4)},
+                     "avg_launch_ms": round(kern_avg, 4),
+                     "launch_ms_std": round(float(np.std(kern_ms)), 4),
+                     "launch_ms_min_max": [round(float(np.min(kern_ms)), 4), round(float(np.max(kern_ms)), 4)]},
     }
 
     if not args.no_extras:
@@ -202,6 +204,7 @@ def main():
         result["adjoint"] = adjoint_leg(torch, nb, ics, dev)
         result["batched"] = batched_leg(torch, nb, ics, dev)
         result["tree"] = tree_leg(torch, nb, pm_np, eps, kern_avg)
+        result["shard"] = shard_leg(torch, nb, pm, eps, prec)
         result["cpu_baseline"] = cpu_leg(ics, pm0_host, acc0, eps, args.cpu_seconds)
     print(json.dumps(result), flush=True)
 
@@ -331,9 +334,65 @@ def batched_leg(torch, nb, ics, dev):
     sizes = np.diff(off).astype(np.float64)
     pairs = float((sizes ** 2).sum()) * steps
     gint = pairs / (ms * 1e-3) / 1e9
-    log(f"[bench] batched: {ms:.1f} ms for {steps} steps, {gint:.1f} Gint/s")
+    # (ii) the same 50 steps launched eagerly, without the graph
+    e0.record()
+    nb.leapfrog_kdk(p, v, a, w["eps"], w["dt"], steps, offsets=off, graph=False, acc_valid=True)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_eager = e0.elapsed_time(e1)
+    # (i) one force evaluation as a loop of one launch per system (forces only,
+    # the batched launch timed the same way for the comparison)
+    sl = [(int(off[k]), int(off[k + 1])) for k in range(len(off) - 1)]
+    views = [(p[b:e], a[b:e]) for b, e in sl]
+    for pv, av in views[:4]:
+        nb.accel(pv, w["eps"], prec=nb.F32_KAHAN, out=av)
+    torch.cuda.synchronize()
+    e0.record()
+    for pv, av in views:
+        nb.accel(pv, w["eps"], prec=nb.F32_KAHAN, out=av)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_loop = e0.elapsed_time(e1)
+    nb.batched_accel(p, off, w["eps"], prec=nb.F32_KAHAN, out=a)
+    torch.cuda.synchronize()
+    e0.record()
+    nb.batched_accel(p, off, w["eps"], prec=nb.F32_KAHAN, out=a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_one = e0.elapsed_time(e1)
+    log(f"[bench] batched: {ms:.1f} ms for {steps} steps in one graph ({gint:.1f} Gint/s), eager {ms_eager:.1f} ms; "
+        f"one evaluation: batched launch {ms_one:.2f} ms, loop of {len(sl)} launches {ms_loop:.2f} ms")
     return {"workload": "512 Plummer systems, N_s log-uniform [256, 32768], F32_KAHAN, 50 steps in one graph",
-            "bodies": int(off[-1]), "ms": round(ms, 3), "g_interactions_per_s": round(gint, 2)}
+            "bodies": int(off[-1]), "ms": round(ms, 3), "g_interactions_per_s": round(gint, 2),
+            "eager_50_steps_ms": round(ms_eager, 3),
+            "one_evaluation_batched_ms": round(ms_one, 3),
+            "one_evaluation_loop_of_launches_ms": round(ms_loop, 3)}
+
+
+def shard_leg(torch, nb, pm, eps, prec):
+    """One GPU's share of an 8-way target split of the same workload: 131072
+    targets (the middle eighth of the ORB order) against all 2^20 sources,
+    the call a multi-GPU run would make on each rank."""
+    n = pm.shape[0]
+    cnt = n // 8
+    beg = 3 * cnt
+    out = torch.empty((cnt, 4), dtype=pm.dtype, device=pm.device)
+    nb.accel(pm, eps, prec=prec, out=out, target_begin=beg, target_count=cnt)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        nb.accel(pm, eps, prec=prec, out=out, target_begin=beg, target_count=cnt)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    t = float(np.mean(ts))
+    gint = float(cnt) * n / (t * 1e-3) / 1e9
+    log(f"[bench] shard: {cnt} x {n} in {t:.2f} ms, {gint:.1f} Gint/s")
+    return {"workload": f"{cnt} targets x {n} sources (one of 8 target shards), F32_F64ACC",
+            "ms": round(t, 3), "g_interactions_per_s": round(gint, 2),
+            "tune_jsplit_rule": "source splits sized by the target count (32 here)"}
 
 
 def _tree_groups(nodes, group):
