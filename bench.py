@@ -409,13 +409,12 @@ def _tree_groups(nodes, group):
     return out
 
 
-def tree_leg(torch, nb, pm_np, eps, direct_ms):
-    """Tree code on the ORB cells (leaf 8, groups of 64) for the same
+def tree_leg(torch, nb, pm_np, eps, direct_ms, leaf=4):
+    """Tree code on the ORB cells (leaf 4, groups of 64) for the same
     colliding pair at step 0, FP32 pairs with FP64 batch sums: time per
     evaluation, interactions per body, and the error against the exact direct
     sum computed by the direct kernel on the same ordered input."""
     import ctypes
-    leaf = 8
     dev = torch.device("cuda:0")
     n = pm_np.shape[0]
     p = torch.as_tensor(pm_np, dtype=torch.float32, device=dev).contiguous()
@@ -436,7 +435,7 @@ def tree_leg(torch, nb, pm_np, eps, direct_ms):
     gsz = np.array([e - b for b, e in groups], dtype=np.float64)
     L = nb.lib()
     out = torch.empty_like(q)
-    res = {"workload": "colliding Plummer pair, N=1048576, eps=0.005, step 0, ORB leaf 8, groups of 64, "
+    res = {"workload": f"colliding Plummer pair, N=1048576, eps=0.005, step 0, ORB leaf {leaf}, groups of 64, "
                        "F32_F64ACC", "leaf": leaf, "orb_plus_gather_ms": round(orb_ms, 3), "theta": {}}
     reps = 10
     for theta in (0.5, 0.7, 1.0):

@@ -262,7 +262,9 @@ def permute(src, perm, inverse=False, out=None):
 
 # ---- tree code on the ORB cells ------------------------------------------------
 # Inputs are float32 (N, 4) records already in ORB order for the same leaf
-# (orb_order, then permute); results are in that order too.
+# (orb_order, then permute); results are in that order too.  The default leaf
+# of 4 bodies measured fastest at 2^20 (leaf 2, 4, 8, 16: 2.44, 2.38, 2.50,
+# 3.81 ms at theta 0.7) with the same accuracy as 8.
 
 def tree_shape(n, leaf, nodes=False):
     """(num_nodes, num_groups[, nodes int32 (num_nodes, 4) = begin, end,
@@ -278,7 +280,7 @@ def tree_shape(n, leaf, nodes=False):
     return nn.value, ng.value, tab
 
 
-def tree_accel(pos_mass, eps, theta, leaf=8, G=1.0, prec=None, out=None):
+def tree_accel(pos_mass, eps, theta, leaf=4, G=1.0, prec=None, out=None):
     """Tree-code force and potential (ax, ay, az, phi) per body, ORB order."""
     pm = _rec(pos_mass, "pos_mass", torch.float32)
     p = _prec(pm, prec)
@@ -293,7 +295,7 @@ def tree_accel(pos_mass, eps, theta, leaf=8, G=1.0, prec=None, out=None):
     return out
 
 
-def tree_moments(pos_mass, leaf=8):
+def tree_moments(pos_mass, leaf=4):
     """Node moments (num_nodes, 5) float64 = (M, com_x, com_y, com_z, diag2)
     and boxes (num_nodes, 6) float32 = (lo, hi)."""
     pm = _rec(pos_mass, "pos_mass", torch.float32)
@@ -304,7 +306,7 @@ def tree_moments(pos_mass, leaf=8):
     return mom, box
 
 
-def tree_lists(pos_mass, theta, leaf=8, max_far=None, max_near=None):
+def tree_lists(pos_mass, theta, leaf=4, max_far=None, max_near=None):
     """Per-group interaction lists: (far_count, near_count) int32 (groups,)
     and, when the maxima are given, far_ids (groups, max_far) and near_ids
     (groups, max_near) node ids in walk order (entries past the counts are
@@ -321,7 +323,7 @@ def tree_lists(pos_mass, theta, leaf=8, max_far=None, max_near=None):
     return fc, nc, fi, ni
 
 
-def tree_leapfrog(pos_mass, vel, acc, eps, theta, dt, nsteps, leaf=8, reorder_every=0, order=None,
+def tree_leapfrog(pos_mass, vel, acc, eps, theta, dt, nsteps, leaf=4, reorder_every=0, order=None,
                   acc_valid=False, energy=False, G=1.0, prec=None):
     """Kick-drift-kick steps with tree forces, in place on ORB-ordered
     float32 records.  reorder_every = K > 0 re-orders the state by ORB at
