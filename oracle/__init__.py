@@ -69,6 +69,9 @@ def _load():
         lib.oracle_traj_grad.argtypes = [ctypes.c_int64, _d, _d, _d, _d, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_double, ctypes.c_int32, _d, _d, _d]
         lib.oracle_traj_grad.restype = ctypes.c_double
+        lib.oracle_traj_grad_cot.argtypes = [ctypes.c_int64, _d, _d, _d, ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_double, ctypes.c_int32, _d, _d, _d, _d, _d, _d]
+        lib.oracle_traj_grad_cot.restype = ctypes.c_int
         lib.oracle_tree_nodes.argtypes = [ctypes.c_int64, ctypes.c_int32, _i64]
         lib.oracle_tree_nodes.restype = ctypes.c_int64
         lib.oracle_tree_moments.argtypes = [ctypes.c_int64, ctypes.c_int32, _d, _d, _d, _d, _d, _d, _d]
@@ -198,6 +201,30 @@ def traj_grad(pos_mass, vel, y, eps: float, dt: float, nsteps: int, G: float = 1
     L = lib.oracle_traj_grad(n, _ptr(x, _d), _ptr(v, _d), _ptr(m, _d), _ptr(yy, _d), float(G), float(eps),
                              float(dt), int(nsteps), _ptr(gx, _d), _ptr(gv, _d), _ptr(gm, _d))
     return float(L), gx, gv, gm
+
+
+def traj_grad_cot(pos_mass, vel, eps: float, dt: float, nsteps: int, xbar_T, vbar_T, phibar_T=None,
+                  G: float = 1.0):
+    """Reverse mode through the leapfrog for cotangents of the final state
+    (xbar_T, vbar_T (N, 3), phibar_T (N,) on the final potential, optional).
+    Returns (dL/dx0 (N, 3), dL/dv0 (N, 3), dL/dm (N,)) through the
+    trajectory."""
+    lib = _load()
+    x, m = _split(pos_mass)
+    n = x.shape[0]
+    v = np.ascontiguousarray(np.asarray(vel)[:, :3], dtype=np.float64)
+    xb = np.ascontiguousarray(np.asarray(xbar_T)[:, :3], dtype=np.float64)
+    vb = np.ascontiguousarray(np.asarray(vbar_T)[:, :3], dtype=np.float64)
+    pb = None if phibar_T is None else np.ascontiguousarray(phibar_T, dtype=np.float64)
+    gx = np.empty((n, 3))
+    gv = np.empty((n, 3))
+    gm = np.empty(n)
+    rc = lib.oracle_traj_grad_cot(n, _ptr(x, _d), _ptr(v, _d), _ptr(m, _d), float(G), float(eps), float(dt),
+                                  int(nsteps), _ptr(xb, _d), _ptr(vb, _d), None if pb is None else _ptr(pb, _d),
+                                  _ptr(gx, _d), _ptr(gv, _d), _ptr(gm, _d))
+    if rc != 0:
+        raise MemoryError("oracle_traj_grad_cot failed")
+    return gx, gv, gm
 
 
 # ---- tree code on the ORB cells (Section IV.A walk, Section IV.B cells) ----

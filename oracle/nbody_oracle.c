@@ -38,7 +38,9 @@
  *                    written from the derivative of the pair law (the paper
  *                    has no derivatives).
  *   oracle_traj_grad Reverse mode through oracle_leapfrog for the loss
- *                    L = sum_i |x_i(T) - y_i|^2, storing every state.
+ *                    L = sum_i |x_i(T) - y_i|^2, storing every state;
+ *                    oracle_traj_grad_cot takes any cotangents of the final
+ *                    state, including one of the final potential.
  *   oracle_tree_*    Section IV.A tree code (cells replaced by their total
  *                    mass at their centre of mass when distant enough, found
  *                    by a walk from the root) on the cells of the Section
@@ -327,6 +329,86 @@ void oracle_vjp(int64_t n, const double *x, const double *m, double G, double ep
  * the opposite order (closing kick, force, drift, opening kick) and ends with
  * the force at x_0.  Returns L.  y, gx, gv: [n][3]; gm: [n].
  * ------------------------------------------------------------------------- */
+/* ---------------------------------------------------------------------------
+ * Reverse mode through oracle_leapfrog for given cotangents of the final
+ * state: xbar_T, vbar_T ([n][3]) and phibar_T ([n], the cotangent of the
+ * potential phi(x_T), may be NULL).  Returns dL/dx0, dL/dv0, dL/dm through
+ * the trajectory (the explicit dependence of the loss on m is the caller's).
+ * The phibar path: phi(x_T) is one more evaluation of the pair law at x_T, so
+ * its cotangent enters through one VJP with abar = 0 before the reverse loop.
+ * ------------------------------------------------------------------------- */
+int oracle_traj_grad_cot(int64_t n, const double *x0, const double *v0, const double *m, double G,
+                         double eps, double dt, int32_t nsteps, const double *xbar_T,
+                         const double *vbar_T, const double *phibar_T, double *gx, double *gv,
+                         double *gm)
+{
+    const double h = 0.5 * dt;
+    const size_t n3 = (size_t)(3 * n);
+    double *xs = (double *)malloc((size_t)(nsteps + 1) * n3 * sizeof(double));
+    double *v = (double *)malloc(n3 * sizeof(double));
+    double *a = (double *)malloc(n3 * sizeof(double));
+    double *abar = (double *)malloc(n3 * sizeof(double));
+    double *tx = (double *)malloc(n3 * sizeof(double));
+    double *tm = (double *)malloc((size_t)n * sizeof(double));
+    if (!xs || !v || !a || !abar || !tx || !tm) {
+        free(xs); free(v); free(a); free(abar); free(tx); free(tm);
+        return -1;
+    }
+    memcpy(xs, x0, n3 * sizeof(double));
+    memcpy(v, v0, n3 * sizeof(double));
+    oracle_accel(n, xs, m, G, eps, n, NULL, a, NULL);
+    for (int32_t s = 0; s < nsteps; ++s) {
+        const double *xc = xs + (size_t)s * n3;
+        double *xn = xs + (size_t)(s + 1) * n3;
+        for (size_t k = 0; k < n3; ++k)
+            v[k] = v[k] + h * a[k];
+        for (size_t k = 0; k < n3; ++k)
+            xn[k] = xc[k] + dt * v[k];
+        oracle_accel(n, xn, m, G, eps, n, NULL, a, NULL);
+        for (size_t k = 0; k < n3; ++k)
+            v[k] = v[k] + h * a[k];
+    }
+    for (size_t k = 0; k < n3; ++k) {
+        gx[k] = xbar_T[k];
+        gv[k] = vbar_T[k];
+    }
+    for (int64_t k = 0; k < n; ++k)
+        gm[k] = 0.0;
+    if (phibar_T) {
+        for (size_t k = 0; k < n3; ++k)
+            abar[k] = 0.0;
+        oracle_vjp(n, xs + (size_t)nsteps * n3, m, G, eps, abar, phibar_T, tx, tm);
+        for (size_t k = 0; k < n3; ++k)
+            gx[k] += tx[k];
+        for (int64_t k = 0; k < n; ++k)
+            gm[k] += tm[k];
+    }
+    double *carry = a;
+    for (size_t k = 0; k < n3; ++k)
+        carry[k] = 0.0;
+    for (int32_t s = nsteps - 1; s >= 0; --s) {
+        const double *xn = xs + (size_t)(s + 1) * n3;
+        for (size_t k = 0; k < n3; ++k)
+            abar[k] = h * gv[k] + carry[k];
+        oracle_vjp(n, xn, m, G, eps, abar, NULL, tx, tm);
+        for (size_t k = 0; k < n3; ++k)
+            gx[k] += tx[k];
+        for (int64_t k = 0; k < n; ++k)
+            gm[k] += tm[k];
+        for (size_t k = 0; k < n3; ++k)
+            gv[k] += dt * gx[k];
+        for (size_t k = 0; k < n3; ++k)
+            carry[k] = h * gv[k];
+    }
+    oracle_vjp(n, xs, m, G, eps, carry, NULL, tx, tm);
+    for (size_t k = 0; k < n3; ++k)
+        gx[k] += tx[k];
+    for (int64_t k = 0; k < n; ++k)
+        gm[k] += tm[k];
+    free(xs); free(v); free(a); free(abar); free(tx); free(tm);
+    return 0;
+}
+
 double oracle_traj_grad(int64_t n, const double *x0, const double *v0, const double *m,
                         const double *y, double G, double eps, double dt, int32_t nsteps,
                         double *gx, double *gv, double *gm)

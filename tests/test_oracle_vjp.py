@@ -119,3 +119,48 @@ def test_traj_grad_closed_forms(orc):
     np.testing.assert_allclose(gx, 2 * (xT - y), rtol=1e-13, atol=1e-13)
     np.testing.assert_allclose(gv, 2 * T * (xT - y), rtol=1e-13, atol=1e-13)
     assert np.all(gm == 0)
+
+
+def _energy_T(orc, pm, vv, eps, dt, steps):
+    """Total energy K + U of the final state of the FP64 leapfrog."""
+    r = orc.leapfrog(pm, vv, eps, dt, steps)
+    m = np.asarray(pm)[:, 3]
+    return 0.5 * float((m * (r["v"] ** 2).sum(1)).sum()) + 0.5 * float((m * r["pot"]).sum()), r
+
+
+def test_energy_gradient_vs_fd(orc):
+    """Gradient of the final total energy E(T) = 1/2 sum m v^2 + 1/2 sum m phi
+    through the leapfrog: cotangents vbar_T = m v_T and phibar_T = m / 2 on the
+    final potential (the potential path of the reverse mode), plus the
+    explicit mass terms 1/2 v^2 + 1/2 phi; checked against central finite
+    differences of E(T)."""
+    n, eps, dt, steps = 10, 0.1, 0.02, 12
+    p, v = ics.plummer(n, 61)
+    p[:, 3] *= np.linspace(0.5, 1.5, n)
+    E, r = _energy_T(orc, p, v, eps, dt, steps)
+    m = p[:, 3]
+    gx, gv, gm = orc.traj_grad_cot(p, v, eps, dt, steps, np.zeros((n, 3)), m[:, None] * r["v"], 0.5 * m)
+    gm = gm + 0.5 * (r["v"] ** 2).sum(1) + 0.5 * r["pot"]
+    g = ics.rng(62)
+    for k in range(5):
+        dx = np.zeros((n, 4)); dx[:, :3] = g.standard_normal((n, 3))
+        dv = np.zeros((n, 4)); dv[:, :3] = g.standard_normal((n, 3))
+        dm = np.zeros((n, 4)); dm[:, 3] = g.standard_normal(n)
+        h = 1e-6
+        fdx = (_energy_T(orc, p + h * dx, v, eps, dt, steps)[0] - _energy_T(orc, p - h * dx, v, eps, dt, steps)[0]) / (2 * h)
+        fdv = (_energy_T(orc, p, v + h * dv, eps, dt, steps)[0] - _energy_T(orc, p, v - h * dv, eps, dt, steps)[0]) / (2 * h)
+        fdm = (_energy_T(orc, p + h * dm, v, eps, dt, steps)[0] - _energy_T(orc, p - h * dm, v, eps, dt, steps)[0]) / (2 * h)
+        for fd, an in [(fdx, (gx * dx[:, :3]).sum()), (fdv, (gv * dv[:, :3]).sum()), (fdm, (gm * dm[:, 3]).sum())]:
+            assert abs(fd - an) <= 1e-6 * abs(an) + 1e-9, (fd, an)
+
+
+def test_traj_grad_cot_reduces_to_position_loss(orc):
+    """With xbar_T = 2 (x_T - y) and no other cotangent the general reverse
+    mode gives the position-loss gradient bit for bit."""
+    n, eps, dt, steps = 9, 0.1, 0.02, 7
+    p, v = ics.plummer(n, 63)
+    y = ics.perturbed_snapshot(p, 64, 0.1)
+    L, gx, gv, gm = orc.traj_grad(p, v, y, eps, dt, steps)
+    xT = orc.leapfrog(p, v, eps, dt, steps)["x"]
+    hx, hv, hm = orc.traj_grad_cot(p, v, eps, dt, steps, 2.0 * (xT - y), np.zeros((n, 3)))
+    assert np.array_equal(gx, hx) and np.array_equal(gv, hv) and np.array_equal(gm, hm)
