@@ -182,7 +182,8 @@ int nbody_energy(const void *pos_mass, const void *vel, const void *acc_pot, int
  * c = 0..nsteps/ckpt_every: slot size 2 records per body.  nsteps must be a
  * multiple of ckpt_every.
  * nbody_trajectory_adjoint takes the cotangents (xbar_T, vbar_T) of the
- * final positions and velocities (records, w unused) and returns the
+ * final positions and velocities (records; w unused unless scheme includes
+ * NBODY_ADJ_PHI, see below) and returns the
  * gradients with respect to the initial positions (pos_cot, record x,y,z),
  * velocities (vel_cot) and masses (mass_cot, float/double[n]), applying one
  * force VJP per position x_n with cotangent h vbar (first and last) or
@@ -202,6 +203,10 @@ int nbody_trajectory_forward(void *pos_mass, void *vel, int64_t n, int32_t prec,
                              void *ckpt, void *stream);
 #define NBODY_ADJ_RECOMPUTE 0
 #define NBODY_ADJ_REVERSE 1
+/* OR-ed into scheme: the w components of xbar_T hold phibar_T, the cotangent
+ * of the final potential phi(x_T) of the same softened law (one more
+ * general-form VJP at x_T).  Without it the w components are ignored. */
+#define NBODY_ADJ_PHI 0x10
 int nbody_trajectory_adjoint(const void *ckpt, int64_t n, int32_t prec, double G, double eps,
                              double dt, int32_t nsteps, int32_t ckpt_every,
                              const void *xbar_T, const void *vbar_T, void *pos_cot,

@@ -21,7 +21,7 @@ import torch
 
 __all__ = [
     "F64", "F32", "F32_KAHAN", "F32_F64ACC", "ACC_VALID", "GRAPH", "ENERGY", "ADJ_RECOMPUTE",
-    "ADJ_REVERSE",
+    "ADJ_REVERSE", "ADJ_PHI",
     "lib", "accel", "accel_vjp", "leapfrog_kdk", "kick_drift", "batched_accel", "energy", "orb_order",
     "permute", "trajectory_forward", "trajectory_adjoint", "NBodyTrajectory", "autotune",
     "set_tuning", "get_tuning", "release", "NBodyError", "TREE_GROUP", "tree_shape", "tree_accel",
@@ -29,7 +29,7 @@ __all__ = [
 ]
 
 F64, F32, F32_KAHAN, F32_F64ACC = 0, 1, 2, 3
-ADJ_RECOMPUTE, ADJ_REVERSE = 0, 1
+ADJ_RECOMPUTE, ADJ_REVERSE, ADJ_PHI = 0, 1, 0x10
 ACC_VALID, GRAPH, ENERGY = 0x1, 0x2, 0x4
 KERNEL_ACCEL, KERNEL_BATCHED, KERNEL_VJP = 0, 1, 2
 TREE_GROUP = 64
@@ -360,13 +360,20 @@ def trajectory_forward(pos_mass, vel, eps, dt, nsteps, ckpt_every, G=1.0, prec=N
 
 
 def trajectory_adjoint(ckpt, eps, dt, nsteps, ckpt_every, xbar_T, vbar_T, G=1.0, prec=None,
-                       scheme=ADJ_REVERSE):
+                       scheme=ADJ_REVERSE, phibar_T=None):
     """(pos_cot (N,4), vel_cot (N,4), mass_cot (N,)) = gradients at the
-    initial state for final-state cotangents (xbar_T, vbar_T).  scheme:
-    ADJ_RECOMPUTE (segments re-run from checkpoints) or ADJ_REVERSE
-    (time reversal from each checkpoint, no extra force evaluations)."""
+    initial state for final-state cotangents (xbar_T, vbar_T) and, if given,
+    phibar_T (N,) on the final potential phi(x_T).  scheme: ADJ_RECOMPUTE
+    (segments re-run from checkpoints) or ADJ_REVERSE (time reversal from each
+    checkpoint, no extra force evaluations)."""
     xb = _rec(xbar_T, "xbar_T")
     vb = _rec(vbar_T, "vbar_T", xb.dtype)
+    if phibar_T is not None:
+        xb = xb.clone()
+        xb[:, 3] = phibar_T.to(xb.dtype)
+        scheme = int(scheme) | ADJ_PHI
+    else:
+        scheme = int(scheme) & ~ADJ_PHI
     if ckpt.dtype != xb.dtype or not ckpt.is_contiguous() or ckpt.device != xb.device:
         raise ValueError("ckpt must be a contiguous tensor of the same dtype and device")
     p = _prec(xb, prec)
@@ -385,11 +392,13 @@ class NBodyTrajectory(torch.autograd.Function):
 
     forward: checkpointed trajectory (nbody_trajectory_forward); backward:
     checkpointed adjoint (nbody_trajectory_adjoint).  x0, v0: (N, 3); m: (N,).
-    Returns (x_T (N, 3), v_T (N, 3))."""
+    Returns (x_T (N, 3), v_T (N, 3)), and with with_potential=True also the
+    final potential phi(x_T) (N,), whose gradient takes the potential path of
+    the adjoint (losses on the final energy)."""
 
     @staticmethod
     def forward(ctx, x0, v0, m, eps, dt, nsteps, ckpt_every=20, G=1.0, prec=None,
-                scheme=ADJ_REVERSE):
+                scheme=ADJ_REVERSE, with_potential=False):
         n = x0.shape[0]
         pm = torch.empty((n, 4), dtype=x0.dtype, device=x0.device)
         pm[:, :3] = x0.detach()
@@ -398,13 +407,16 @@ class NBodyTrajectory(torch.autograd.Function):
         vel[:, :3] = v0.detach()
         ck = trajectory_forward(pm, vel, eps, dt, nsteps, ckpt_every, G, prec)
         ctx.save_for_backward(ck)
-        ctx.args = (eps, dt, nsteps, ckpt_every, G, prec, scheme)
-        return pm[:, :3].clone(), vel[:, :3].clone()
+        ctx.args = (eps, dt, nsteps, ckpt_every, G, prec, scheme, with_potential)
+        if not with_potential:
+            return pm[:, :3].clone(), vel[:, :3].clone()
+        phi = accel(pm, eps, G, prec)[:, 3].clone()
+        return pm[:, :3].clone(), vel[:, :3].clone(), phi
 
     @staticmethod
-    def backward(ctx, gx, gv):
+    def backward(ctx, gx, gv, gphi=None):
         (ck,) = ctx.saved_tensors
-        eps, dt, nsteps, ckpt_every, G, prec, scheme = ctx.args
+        eps, dt, nsteps, ckpt_every, G, prec, scheme, with_potential = ctx.args
         n = ck.shape[2]
         xb = torch.zeros((n, 4), dtype=ck.dtype, device=ck.device)
         vb = torch.zeros((n, 4), dtype=ck.dtype, device=ck.device)
@@ -412,8 +424,9 @@ class NBodyTrajectory(torch.autograd.Function):
             xb[:, :3] = gx
         if gv is not None:
             vb[:, :3] = gv
-        pc, vc, mc = trajectory_adjoint(ck, eps, dt, nsteps, ckpt_every, xb, vb, G, prec, scheme)
-        return pc[:, :3], vc[:, :3], mc, None, None, None, None, None, None, None
+        pc, vc, mc = trajectory_adjoint(ck, eps, dt, nsteps, ckpt_every, xb, vb, G, prec, scheme,
+                                        phibar_T=gphi if with_potential else None)
+        return pc[:, :3], vc[:, :3], mc, None, None, None, None, None, None, None, None
 
 
 def autotune(kernel, prec, n, offsets=None):

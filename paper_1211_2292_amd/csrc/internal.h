@@ -91,6 +91,8 @@ hipError_t launch_reverse_step(int prec, void *x, void *vh, const void *acc, con
 hipError_t launch_adj_axpy(int prec, void *y, const void *x, double a, const void *pm, void *ysc,
                            int n, hipStream_t s);
 // sc = cot / m; *nonpos |= (some m <= 0).  *nonpos must be zero before.
+// dst = (0, 0, 0, src.w) per record (the potential part of a cotangent).
+hipError_t launch_phibar_only(int prec, const void *src, int n, void *dst, hipStream_t s);
 hipError_t launch_prescale(int prec, const void *cot, const void *pm, int n, void *sc, int *nonpos,
                            hipStream_t s);
 // Adjoint VJP (phibar = 0, accumulate): mass-scaled form on sc unless

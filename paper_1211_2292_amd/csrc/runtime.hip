@@ -892,6 +892,8 @@ int nbody_trajectory_adjoint(const void *ckpt, int64_t n, int32_t prec, double G
                              const void *vbar_T, void *pos_cot, void *vel_cot, void *mass_cot,
                              int32_t scheme, void *stream)
 {
+    const bool with_phi = (scheme & NBODY_ADJ_PHI) != 0;
+    scheme &= ~NBODY_ADJ_PHI;
     if (scheme != NBODY_ADJ_RECOMPUTE && scheme != NBODY_ADJ_REVERSE) {
         set_error("bad adjoint scheme %d", scheme);
         return NBODY_E_INVAL;
@@ -937,6 +939,16 @@ int nbody_trajectory_adjoint(const void *ckpt, int64_t n, int32_t prec, double G
     NB_TRY(launch_copy(pos_cot, xbar_T, rb, s), "adjoint init");
     NB_TRY(launch_copy(vel_cot, vbar_T, rb, s), "adjoint init");
     NB_TRY(launch_fill_zero(mass_cot, mb * (size_t)n, s), "adjoint init");
+    if (with_phi) {
+        // the final potential phi(x_T) is one more evaluation of the pair law
+        // at x_T: its cotangent (the w components of xbar_T) enters through
+        // one general-form VJP with a zero acceleration cotangent
+        const char *xT = (const char *)ckpt + (size_t)nseg * 2 * rb;
+        NB_TRY(launch_phibar_only(prec, xbar_T, ni, acc, s), "adjoint potential cotangent");
+        NB_TRY(launch_vjp_ex(prec, xT, acc, ni, G, eps, true, 1.0, true, pos_cot, mass_cot, nullptr, vt_tune,
+                             vpart, s),
+               "adjoint potential cotangent");
+    }
     // The force at x_{s+1} receives h vbar from the closing kick of step s and
     // h vbar from the opening kick of step s+1 (vbar unchanged in between):
     // 2h vbar in the interior, h vbar at the last step and at x_0.

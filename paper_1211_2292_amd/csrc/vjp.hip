@@ -695,6 +695,32 @@ hipError_t launch_adj_axpy(int prec, void *y, const void *x, double a, const voi
     return hipGetLastError();
 }
 
+// (0, 0, 0, w) of every record: the potential cotangent alone.
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_phibar_only(const V *__restrict__ src, int n, V *__restrict__ dst)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    V o;
+    o.x = 0;
+    o.y = 0;
+    o.z = 0;
+    o.w = src[i].w;
+    dst[i] = o;
+}
+
+hipError_t launch_phibar_only(int prec, const void *src, int n, void *dst, hipStream_t s)
+{
+    const dim3 grid((n + kBlock - 1) / kBlock);
+    if (prec == NBODY_F64)
+        hipLaunchKernelGGL((k_phibar_only<double4>), grid, dim3(kBlock), 0, s, (const double4 *)src, n,
+                           (double4 *)dst);
+    else
+        hipLaunchKernelGGL((k_phibar_only<float4>), grid, dim3(kBlock), 0, s, (const float4 *)src, n,
+                           (float4 *)dst);
+    return hipGetLastError();
+}
+
 hipError_t launch_prescale(int prec, const void *cot, const void *pm, int n, void *sc, int *nonpos,
                            hipStream_t s)
 {

@@ -161,3 +161,55 @@ def test_trajectory_gradient_with_massless_body(orc, scheme):
     assert normwise(host(pc)[:, :3], gx) <= 1e-11
     assert normwise(host(vc)[:, :3], gv) <= 1e-11
     assert normwise(host(mc), gm) <= 1e-11
+
+
+@pytest.mark.parametrize("scheme", ["ADJ_RECOMPUTE", "ADJ_REVERSE"])
+def test_energy_gradient_potential_path_f64(orc, scheme):
+    """Cotangents of the final total energy: vbar_T = m v_T and phibar_T = m/2
+    on the final potential (the adjoint's potential path) against the
+    oracle's reverse mode with the same cotangents."""
+    torch, nb = gpu()
+    n, eps, dt, steps, C = 64, 0.05, 2e-3, 40, 10
+    pm, v = ics.plummer(n, 70)
+    pm[:, 3] *= np.linspace(0.5, 1.5, n)
+    r = orc.leapfrog(pm, v, eps, dt, steps)
+    m = pm[:, 3]
+    gx, gv, gm = orc.traj_grad_cot(pm, v, eps, dt, steps, np.zeros((n, 3)), m[:, None] * r["v"], 0.5 * m)
+    p, vv = to_dev(torch, pm, torch.float64), to_dev(torch, v, torch.float64)
+    ck = nb.trajectory_forward(p, vv, eps, dt, steps, C)
+    xb = torch.zeros_like(p)
+    vb = torch.zeros_like(p)
+    vb[:, :3] = vv[:, :3] * p[:, 3:4]
+    pc, vc, mc = nb.trajectory_adjoint(ck, eps, dt, steps, C, xb, vb, scheme=getattr(nb, scheme),
+                                       phibar_T=0.5 * p[:, 3])
+    torch.cuda.synchronize()
+    assert normwise(host(pc)[:, :3], gx) <= 1e-11
+    assert normwise(host(vc)[:, :3], gv) <= 1e-11
+    assert normwise(host(mc), gm) <= 1e-11
+
+
+def test_energy_loss_autograd_f32(orc):
+    """d E(T) / d(x0, v0, m) through NBodyTrajectory(with_potential=True),
+    with the energy written in torch (autograd supplies the explicit mass
+    terms), against the oracle."""
+    torch, nb = gpu()
+    n, eps, dt, steps, C = 1024, 0.01, 1e-3, 40, 20
+    pm, v = ics.plummer(n, 71)
+    pm32, v32 = widen32(pm), widen32(v)
+    r = orc.leapfrog(pm32, v32, eps, dt, steps)
+    m = pm32[:, 3]
+    gx, gv, gm = orc.traj_grad_cot(pm32, v32, eps, dt, steps, np.zeros((n, 3)), m[:, None] * r["v"], 0.5 * m)
+    gm = gm + 0.5 * (r["v"] ** 2).sum(1) + 0.5 * r["pot"]
+    x0 = to_dev(torch, pm32[:, :3], torch.float32).requires_grad_(True)
+    v0 = to_dev(torch, v32[:, :3], torch.float32).requires_grad_(True)
+    mm = to_dev(torch, m, torch.float32).requires_grad_(True)
+    xT, vT, phiT = nb.NBodyTrajectory.apply(x0, v0, mm, eps, dt, steps, C, 1.0, None, nb.ADJ_REVERSE, True)
+    E = 0.5 * (mm * (vT ** 2).sum(1)).sum() + 0.5 * (mm * phiT).sum()
+    E.backward()
+    torch.cuda.synchronize()
+    e_ref = 0.5 * float((m * (r["v"] ** 2).sum(1)).sum()) + 0.5 * float((m * r["pot"]).sum())
+    assert abs(float(E.detach()) / e_ref - 1.0) < 1e-5
+    print("energy grad errors", normwise(host(x0.grad), gx), normwise(host(v0.grad), gv), normwise(host(mm.grad), gm))
+    assert normwise(host(x0.grad), gx) <= 1e-4
+    assert normwise(host(v0.grad), gv) <= 1e-4
+    assert normwise(host(mm.grad), gm) <= 1e-4
