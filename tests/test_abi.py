@@ -94,6 +94,17 @@ def test_other_entry_points_validate():
     assert L.nbody_tree_lists(P(64), 100, 8, 0.5, 4, 4, None, P(256), None, None, None) == -1
     assert L.nbody_tree_lists(P(64), 100, 8, 0.5, 0, 4, P(256), P(512), P(1024), None, None) == -1
     assert L.nbody_tree_moments(P(64), 100, 8, P(12), None, None) == -2
+    # tree leapfrog: precision, flags, order map, energy output
+    lf = lambda *a: L.nbody_tree_leapfrog(*a)
+    assert lf(P(64), P(1024), P(4096), None, 100, 0, 1.0, 0.01, 0.5, 8, 1e-3, 4, 0, 0, None, None) == -5
+    assert lf(P(64), P(1024), P(4096), None, 100, 1, 1.0, 0.01, 0.5, 8, 1e-3, 4, 0, 0x2, None, None) == -1
+    assert lf(P(64), P(1024), P(4096), None, 100, 1, 1.0, 0.01, 0.5, 8, 1e-3, 4, 2, 0, None, None) == -1
+    assert lf(P(64), P(1024), P(4096), None, 100, 1, 1.0, 0.01, 0.5, 8, 1e-3, 4, 0, 0x4, None, None) == -1
+    assert lf(P(64), P(1024), P(4096), None, 100, 1, 1.0, 0.01, 0.5, 8, 1e-3, -1, 0, 0, None, None) == -1
+    assert lf(P(64), P(1024), P(4096), None, 100, 1, 1.0, 0.01, 0.5, 0, 1e-3, 4, 0, 0, None, None) == -1
+    # adjoint: an unknown scheme stays invalid with the potential flag set
+    assert L.nbody_trajectory_adjoint(P(64), 10, 1, 1.0, 0.01, 1e-3, 20, 20, P(1024), P(2048), P(4096),
+                                      P(8192), P(16384), 0x10 | 5, None) == -1
 
 
 @pytest.mark.parametrize("n,leaf", [(1, 1), (9, 8), (100, 8), (1000, 3), (4096, 16), (70001, 8), (777, 64)])

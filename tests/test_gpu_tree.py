@@ -294,3 +294,32 @@ def test_tree_leapfrog_energy():
     assert drift < 1e-3
     k_end, u_end = nb.energy(p, v, a).cpu().numpy()
     assert abs((k_end + u_end) / e[-1] - 1.0) < 1e-12
+
+
+def test_tree_force_replays_in_a_captured_graph():
+    """After the first call for a shape (which uploads the node table), the
+    tree force is kernel launches only: captured in a HIP graph it replays
+    bit for bit like eager calls, with eager work in between."""
+    torch, nb = gpu()
+    pm, _ = ics.plummer(20000, 410)
+    q, _ = _orb_input(torch, nb, pm, 4)
+    out_e = nb.tree_accel(q, 0.01, 0.6, 4, prec=nb.F32_F64ACC)
+    out_g = torch.empty_like(q)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        nb.tree_accel(q, 0.01, 0.6, 4, prec=nb.F32_F64ACC, out=out_g)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        nb.tree_accel(q, 0.01, 0.6, 4, prec=nb.F32_F64ACC, out=out_g)
+    for rep in range(3):
+        out_g.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        junk = torch.randn(1000, device="cuda").sum()
+        ref = nb.tree_accel(q, 0.01, 0.6, 4, prec=nb.F32_F64ACC)
+        torch.cuda.synchronize()
+        assert torch.equal(out_g, ref) and torch.equal(ref, out_e), rep
+        del junk
