@@ -72,6 +72,10 @@ def _load():
         lib.oracle_traj_grad_cot.argtypes = [ctypes.c_int64, _d, _d, _d, ctypes.c_double, ctypes.c_double,
                                              ctypes.c_double, ctypes.c_int32, _d, _d, _d, _d, _d, _d]
         lib.oracle_traj_grad_cot.restype = ctypes.c_int
+        lib.oracle_janus_run.argtypes = [ctypes.c_int64, _i64, _d, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int32]
+        lib.oracle_janus_run.restype = ctypes.c_int
         lib.oracle_tree_nodes.argtypes = [ctypes.c_int64, ctypes.c_int32, _i64]
         lib.oracle_tree_nodes.restype = ctypes.c_int64
         lib.oracle_tree_moments.argtypes = [ctypes.c_int64, ctypes.c_int32, _d, _d, _d, _d, _d, _d, _d]
@@ -225,6 +229,31 @@ def traj_grad_cot(pos_mass, vel, eps: float, dt: float, nsteps: int, xbar_T, vba
     if rc != 0:
         raise MemoryError("oracle_traj_grad_cot failed")
     return gx, gv, gm
+
+
+def janus_encode(pos, vel, sx: int = 40, sv: int = 40) -> np.ndarray:
+    """Fixed-point state int64 (N, 8) = (X, Y, Z, 0, VX, VY, VZ, 0) from
+    positions and velocities (rounded to nearest, half to even)."""
+    n = np.asarray(pos).shape[0]
+    st = np.zeros((n, 8), dtype=np.int64)
+    st[:, :3] = np.rint(np.ldexp(np.asarray(pos, dtype=np.float64)[:, :3], sx)).astype(np.int64)
+    st[:, 4:7] = np.rint(np.ldexp(np.asarray(vel, dtype=np.float64)[:, :3], sv)).astype(np.int64)
+    return st
+
+
+def janus_run(state, masses, eps: float, dt: float, nsteps: int, sx: int = 40, sv: int = 40, G: float = 1.0,
+              direction: int = 1) -> np.ndarray:
+    """Bit-reversible fixed-point kick-drift-kick (FP64 forces): nsteps
+    forward (direction 1) or backward (-1) from ``state``; returns the new
+    state."""
+    lib = _load()
+    st = np.ascontiguousarray(np.array(state, dtype=np.int64))
+    m = np.ascontiguousarray(masses, dtype=np.float64)
+    rc = lib.oracle_janus_run(st.shape[0], _ptr(st, _i64), _ptr(m, _d), float(G), float(eps), float(dt),
+                              int(nsteps), int(sx), int(sv), int(direction))
+    if rc != 0:
+        raise ValueError("oracle_janus_run: bad arguments")
+    return st
 
 
 # ---- tree code on the ORB cells (Section IV.A walk, Section IV.B cells) ----

@@ -41,6 +41,9 @@
  *                    L = sum_i |x_i(T) - y_i|^2, storing every state;
  *                    oracle_traj_grad_cot takes any cotangents of the final
  *                    state, including one of the final potential.
+ *   oracle_janus_run Bit-reversible fixed-point form of the same
+ *                    kick-drift-kick (integer state, increments rounded once),
+ *                    forward or backward.
  *   oracle_tree_*    Section IV.A tree code (cells replaced by their total
  *                    mass at their centre of mass when distant enough, found
  *                    by a walk from the root) on the cells of the Section
@@ -887,4 +890,77 @@ int oracle_tree_accel(int64_t n, int32_t leaf, int32_t group, const double *x, c
     free(gof);
     tree_free(&d);
     return bad ? -1 : 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Bit-reversible kick-drift-kick with fixed-point state (the integer-state
+ * idea of Rein and Tamayo's JANUS integrator, 2018, applied to the leapfrog
+ * of Section IV.B's Move_bodies).  Positions and velocities are integers in
+ * units of 2^-sx and 2^-sv.  With the force a(x) of the decoded positions
+ * (decode: x = X * 2^-sx, exact in FP64 for |X| < 2^53):
+ *   kick:  V += round(kick_scale * a),  kick_scale = h G 2^sv
+ *   drift: X += round((double)V * drift_scale),  drift_scale = dt 2^(sx-sv)
+ * round() is round-half-to-even of the FP64 product.  Every increment depends
+ * only on the state it does not change, so subtracting the same integers
+ * undoes a step exactly.  One force evaluation per step; the oracle uses its
+ * FP64 force (G = 1 in the evaluation, G in kick_scale).
+ * state: int64 [n][8] = (X, Y, Z, 0, VX, VY, VZ, 0).
+ * ------------------------------------------------------------------------- */
+static void janus_decode(int64_t n, const int64_t *st, double inv_sx, double *x)
+{
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < 3; ++k)
+            x[3 * i + k] = (double)st[8 * i + k] * inv_sx;
+}
+
+static void janus_kick(int64_t n, int64_t *st, const double *a, double kick_scale, int64_t sign)
+{
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < 3; ++k)
+            st[8 * i + 4 + k] += sign * (int64_t)nearbyint(kick_scale * a[3 * i + k]);
+}
+
+static void janus_drift(int64_t n, int64_t *st, double drift_scale, int64_t sign)
+{
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < 3; ++k)
+            st[8 * i + k] += sign * (int64_t)nearbyint((double)st[8 * i + 4 + k] * drift_scale);
+}
+
+/* direction +1: nsteps forward; -1: nsteps backward (exact inverse). */
+int oracle_janus_run(int64_t n, int64_t *state, const double *m, double G, double eps, double dt,
+                     int32_t nsteps, int32_t sx, int32_t sv, int32_t direction)
+{
+    if (n < 1 || nsteps < 0 || (direction != 1 && direction != -1))
+        return -1;
+    double *x = (double *)malloc((size_t)n * 3 * sizeof(double));
+    double *a = (double *)malloc((size_t)n * 3 * sizeof(double));
+    if (!x || !a) {
+        free(x);
+        free(a);
+        return -1;
+    }
+    const double inv_sx = ldexp(1.0, -sx);
+    const double kick_scale = 0.5 * dt * G * ldexp(1.0, sv);
+    const double drift_scale = dt * ldexp(1.0, sx - sv);
+    janus_decode(n, state, inv_sx, x);
+    oracle_accel(n, x, m, 1.0, eps, n, NULL, a, NULL);
+    for (int32_t s = 0; s < nsteps; ++s) {
+        if (direction > 0) {
+            janus_kick(n, state, a, kick_scale, 1);
+            janus_drift(n, state, drift_scale, 1);
+            janus_decode(n, state, inv_sx, x);
+            oracle_accel(n, x, m, 1.0, eps, n, NULL, a, NULL);
+            janus_kick(n, state, a, kick_scale, 1);
+        } else {
+            janus_kick(n, state, a, kick_scale, -1);
+            janus_drift(n, state, drift_scale, -1);
+            janus_decode(n, state, inv_sx, x);
+            oracle_accel(n, x, m, 1.0, eps, n, NULL, a, NULL);
+            janus_kick(n, state, a, kick_scale, -1);
+        }
+    }
+    free(x);
+    free(a);
+    return 0;
 }
