@@ -301,16 +301,41 @@ def adjoint_leg(torch, nb, ics, dev):
             ts.append(a.elapsed_time(b))
         return float(np.median(ts))
 
+    # the fixed-point, bit-reversible leapfrog sums in FP32 + FP64 partials:
+    # its ratio is taken against the plain leapfrog in that mode
+    def plain64():
+        p, v = p0.clone(), v0.clone()
+        a = torch.empty_like(p)
+        nb.leapfrog_kdk(p, v, a, eps, dt, steps, prec=nb.F32_F64ACC)
+        return p
+
+    def janus_fwd():
+        return nb.janus_forward(p0, v0, eps, dt, steps)
+
+    def janus_fwd_adj():
+        st, pT, _ = nb.janus_forward(p0, v0, eps, dt, steps)
+        xb = torch.zeros_like(pT)
+        xb[:, :3] = 2 * (pT[:, :3] - y)
+        return nb.janus_adjoint(st, p0, eps, dt, steps, xb, torch.zeros_like(pT))
+
     t_plain = timed(plain)
     t_rev = timed(fwd_adj(nb.ADJ_REVERSE))
     t_rec = timed(fwd_adj(nb.ADJ_RECOMPUTE))
+    t_plain64 = timed(plain64)
+    t_jf = timed(janus_fwd)
+    t_ja = timed(janus_fwd_adj)
     log(f"[bench] adjoint: plain {t_plain:.1f} ms, fwd+adj reversal {t_rev:.1f} ms "
         f"(ratio {t_rev / t_plain:.2f}), recompute {t_rec:.1f} ms (ratio {t_rec / t_plain:.2f})")
+    log(f"[bench] fixed-point: plain F32_F64ACC {t_plain64:.1f} ms, forward {t_jf:.1f} ms, "
+        f"fwd+adj {t_ja:.1f} ms (ratio {t_ja / t_plain64:.2f})")
     return {"workload": "Plummer N=16384, F32_KAHAN, 200 steps dt=1e-3, checkpoints every 20",
             "plain_forward_ms": round(t_plain, 3),
             "fwd_plus_adjoint_ms": round(t_rev, 3), "ratio": round(t_rev / t_plain, 3),
             "scheme": "time reversal re-anchored at checkpoints (fused force+VJP)",
-            "recompute_scheme_ms": round(t_rec, 3), "recompute_scheme_ratio": round(t_rec / t_plain, 3)}
+            "recompute_scheme_ms": round(t_rec, 3), "recompute_scheme_ratio": round(t_rec / t_plain, 3),
+            "fixed_point": {"prec": "F32_F64ACC", "plain_forward_ms": round(t_plain64, 3),
+                            "forward_ms": round(t_jf, 3), "fwd_plus_adjoint_ms": round(t_ja, 3),
+                            "ratio": round(t_ja / t_plain64, 3), "checkpoints": 0}}
 
 
 def batched_leg(torch, nb, ics, dev):

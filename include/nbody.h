@@ -290,6 +290,36 @@ int nbody_tree_leapfrog(void *pos_mass, void *vel, void *acc_pot, int32_t *order
                         double *energy_out, void *stream);
 
 /*
+ * Bit-reversible kick-drift-kick and its checkpoint-free adjoint (the
+ * integer-state reading of the leapfrog of Section IV.B, after Rein and
+ * Tamayo's JANUS integrator).  Positions and velocities are int64 fixed point
+ * in units of 2^-shift_x and 2^-shift_v: kick V += round(h G 2^shift_v a),
+ * drift X += round(V dt 2^(shift_x - shift_v)), rounded to nearest even in
+ * FP64, forces of the positions decoded to FP32 (NBODY_F32_F64ACC sums).
+ * Subtracting the same integers undoes a step exactly, so the adjoint rebuilds
+ * every position bit for bit from the final state and stores nothing per step.
+ * state: int64 [2n][4], rows [0, n) = (X, Y, Z, 0), rows [n, 2n) =
+ * (VX, VY, VZ, 0); 32-byte aligned device memory.  |X|, |V| < 2^53.
+ * nbody_janus_forward: encodes pos_mass/vel (float4, masses in w), runs
+ *   nsteps, writes the final state, the decoded positions with the masses
+ *   (pos_mass_out) and, if not NULL, the decoded velocities (vel_out).
+ * nbody_janus_adjoint: gradients (pos_cot, vel_cot, mass_cot as for
+ *   nbody_trajectory_adjoint) of a loss with cotangents xbar_T, vbar_T of
+ *   the final decoded state, reversing `state` IN PLACE to the initial state
+ *   (bit-exact); pos_mass supplies the masses (w).  Every mass must be
+ *   positive (checked once, synchronizing the stream; else
+ *   NBODY_E_UNSUPPORTED).  Rounding is treated as the identity in the
+ *   derivative.
+ */
+int nbody_janus_forward(const void *pos_mass, const void *vel, int64_t n, double G, double eps,
+                        double dt, int32_t nsteps, int32_t shift_x, int32_t shift_v,
+                        void *state_out, void *pos_mass_out, void *vel_out, void *stream);
+int nbody_janus_adjoint(void *state, const void *pos_mass, int64_t n, double G, double eps,
+                        double dt, int32_t nsteps, int32_t shift_x, int32_t shift_v,
+                        const void *xbar_T, const void *vbar_T, void *pos_cot, void *vel_cot,
+                        void *mass_cot, void *stream);
+
+/*
  * Tuning.  nbody_autotune times the candidate kernel shapes for one problem
  * (kernel 0 = nbody_accel at size n, 1 = nbody_batched_accel for the given
  * offsets, 2 = nbody_accel_vjp) on library-owned synthetic inputs,

@@ -25,7 +25,7 @@ __all__ = [
     "lib", "accel", "accel_vjp", "leapfrog_kdk", "kick_drift", "batched_accel", "energy", "orb_order",
     "permute", "trajectory_forward", "trajectory_adjoint", "NBodyTrajectory", "autotune",
     "set_tuning", "get_tuning", "release", "NBodyError", "TREE_GROUP", "tree_shape", "tree_accel",
-    "tree_moments", "tree_lists", "tree_leapfrog",
+    "tree_moments", "tree_lists", "tree_leapfrog", "janus_forward", "janus_adjoint",
 ]
 
 F64, F32, F32_KAHAN, F32_F64ACC = 0, 1, 2, 3
@@ -63,6 +63,8 @@ _SIGS = {
     "nbody_tree_lists": [_vp, _i64, _i32, _dbl, _i32, _i32, _vp, _vp, _vp, _vp, _vp],
     "nbody_tree_leapfrog": [_vp, _vp, _vp, _vp, _i64, _i32, _dbl, _dbl, _dbl, _i32, _dbl, _i32, _i32,
                             ctypes.c_uint32, _vp, _vp],
+    "nbody_janus_forward": [_vp, _vp, _i64, _dbl, _dbl, _dbl, _i32, _i32, _i32, _vp, _vp, _vp, _vp],
+    "nbody_janus_adjoint": [_vp, _vp, _i64, _dbl, _dbl, _dbl, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp],
     "nbody_autotune": [_i32, _i32, _i64, _vp, _i32, _vp],
     "nbody_set_tuning": [_i32, _i32, _i32, _i32, _i32, _i32],
     "nbody_get_tuning": [_i32, _i32, _i64, _vp, _vp, _vp, _vp],
@@ -384,6 +386,41 @@ def trajectory_adjoint(ckpt, eps, dt, nsteps, ckpt_every, xbar_T, vbar_T, G=1.0,
     _check(lib().nbody_trajectory_adjoint(_ptr(ckpt), n, p, float(G), float(eps), float(dt), int(nsteps),
                                           int(ckpt_every), _ptr(xb), _ptr(vb), _ptr(pc), _ptr(vc),
                                           _ptr(mc), int(scheme), _stream()))
+    return pc, vc, mc
+
+
+def janus_forward(pos_mass, vel, eps, dt, nsteps, shift_x=40, shift_v=40, G=1.0):
+    """Bit-reversible fixed-point kick-drift-kick from float32 records.
+    Returns (state int64 (2N, 4), final positions with masses (N, 4),
+    final velocities (N, 4))."""
+    pm = _rec(pos_mass, "pos_mass", torch.float32)
+    v = _rec(vel, "vel", torch.float32)
+    n = pm.shape[0]
+    state = torch.empty((2 * n, 4), dtype=torch.int64, device=pm.device)
+    pm_out = torch.empty_like(pm)
+    v_out = torch.empty_like(pm)
+    _check(lib().nbody_janus_forward(_ptr(pm), _ptr(v), n, float(G), float(eps), float(dt), int(nsteps),
+                                     int(shift_x), int(shift_v), _ptr(state), _ptr(pm_out), _ptr(v_out),
+                                     _stream()))
+    return state, pm_out, v_out
+
+
+def janus_adjoint(state, pos_mass, eps, dt, nsteps, xbar_T, vbar_T, shift_x=40, shift_v=40, G=1.0):
+    """Gradients (pos_cot, vel_cot (N, 4), mass_cot (N,)) for cotangents of the
+    final state, rebuilding the trajectory backwards from ``state`` alone;
+    ``state`` is rewound in place to the initial state (bit-exact)."""
+    pm = _rec(pos_mass, "pos_mass", torch.float32)
+    xb = _rec(xbar_T, "xbar_T", torch.float32)
+    vb = _rec(vbar_T, "vbar_T", torch.float32)
+    n = pm.shape[0]
+    if state.dtype != torch.int64 or tuple(state.shape) != (2 * n, 4) or not state.is_contiguous():
+        raise ValueError("state must be a contiguous int64 tensor of shape (2N, 4)")
+    pc = torch.empty_like(xb)
+    vc = torch.empty_like(xb)
+    mc = torch.empty(n, dtype=torch.float32, device=pm.device)
+    _check(lib().nbody_janus_adjoint(_ptr(state), _ptr(pm), n, float(G), float(eps), float(dt), int(nsteps),
+                                     int(shift_x), int(shift_v), _ptr(xb), _ptr(vb), _ptr(pc), _ptr(vc), _ptr(mc),
+                                     _stream()))
     return pc, vc, mc
 
 

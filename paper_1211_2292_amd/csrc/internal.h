@@ -102,8 +102,9 @@ hipError_t launch_vjp_adj(int prec, const void *pm, const void *raw, const void 
                           void *pos_cot, void *mass_cot, void *acc_out, const Tune &t, void *partial,
                           hipStream_t s);
 // Adjoint VJP and the elementwise step after it in as few launches as the
-// shape allows (post 1: vbar += dt xbar; post 2: time reversal of x, vh).
-// Uses tpl = 1 when the source range is split.
+// shape allows (post 1: vbar += dt xbar; post 2: time reversal of x, vh;
+// post 3: as post 1, and the force to acc).  Uses tpl = 1 when the source
+// range is split.
 hipError_t launch_vjp_adj_step(int prec, int post, void *pm, void *raw, void *sc, const int *nonpos,
                                int n, double G, double eps, double scale, void *pos_cot,
                                void *mass_cot, void *acc, void *vh, double hk, double dt,
@@ -124,6 +125,17 @@ int tree_leapfrog(void *pm, void *vel, void *acc, int32_t *order, int n, int pre
                   double theta, int leaf, double dt, int nsteps, int reorder_every, unsigned flags,
                   double *energy, hipStream_t s);
 void tree_release();
+
+// ---- bit-reversible fixed-point leapfrog (janus.hip) ---------------------------
+// state: 2n longlong4 (X then V); the force kernel and the fused VJP run with
+// G = 1 and the shape of janus_tune so their forces agree bit for bit.
+Tune janus_tune(const Tune &vjp_default);
+int janus_forward(const void *pm, const void *vel, int n, double G, double eps, double dt, int nsteps, int sx,
+                  int sv, const Tune &t, void *state, void *pm_out, void *vel_out, void *acc, void *partial,
+                  hipStream_t s);
+int janus_decode(const void *state, const void *pm, int n, int sx, void *dec, hipStream_t s);
+int janus_unstep(void *state, const void *acc, int n, double G, double dt, int sx, int sv, int kicks, int drift,
+                 void *dec, hipStream_t s);
 
 // ---- runtime helpers (runtime.hip) -----------------------------------------
 void set_error(const char *fmt, ...);

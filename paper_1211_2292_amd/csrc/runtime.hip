@@ -851,6 +851,117 @@ int nbody_tree_leapfrog(void *pos_mass, void *vel, void *acc_pot, int32_t *order
                          (hipStream_t)stream);
 }
 
+// ---- bit-reversible fixed-point leapfrog and its checkpoint-free adjoint ---------
+static int check_shifts(int32_t sx, int32_t sv)
+{
+    if (sx < 0 || sx > 60 || sv < 0 || sv > 60) {
+        set_error("fixed-point shifts must be in [0, 60]");
+        return NBODY_E_INVAL;
+    }
+    return NBODY_OK;
+}
+
+int nbody_janus_forward(const void *pos_mass, const void *vel, int64_t n, double G, double eps, double dt,
+                        int32_t nsteps, int32_t shift_x, int32_t shift_v, void *state_out, void *pos_mass_out,
+                        void *vel_out, void *stream)
+{
+    NB_CHECK(check_n(n));
+    if (nsteps < 0) {
+        set_error("nsteps < 0");
+        return NBODY_E_INVAL;
+    }
+    NB_CHECK(check_scalars(G, eps, dt));
+    NB_CHECK(check_shifts(shift_x, shift_v));
+    NB_CHECK(check_vec(pos_mass, NBODY_F32, "pos_mass"));
+    NB_CHECK(check_vec(vel, NBODY_F32, "vel"));
+    NB_CHECK(check_vec(pos_mass_out, NBODY_F32, "pos_mass_out"));
+    NB_CHECK(check_vec(vel_out, NBODY_F32, "vel_out", true));
+    if (!state_out || (uintptr_t)state_out % 32) {
+        set_error("state_out NULL or not 32-byte aligned");
+        return NBODY_E_ALIGN;
+    }
+    const int ni = (int)n;
+    const Tune t = janus_tune(lookup_tune(2, NBODY_F32_F64ACC, n));
+    void *acc = scratch(kSlotAdj0, (size_t)n * 16);
+    void *partial = nullptr;
+    if (const size_t pb = accel_partial_bytes(NBODY_F32_F64ACC, ni, t)) partial = scratch(kSlotPartial, pb);
+    if (!acc || (accel_partial_bytes(NBODY_F32_F64ACC, ni, t) && !partial)) {
+        set_error("cannot allocate fixed-point leapfrog scratch");
+        return NBODY_E_NOMEM;
+    }
+    return janus_forward(pos_mass, vel, ni, G, eps, dt, nsteps, shift_x, shift_v, t, state_out, pos_mass_out,
+                         vel_out, acc, partial, (hipStream_t)stream);
+}
+
+int nbody_janus_adjoint(void *state, const void *pos_mass, int64_t n, double G, double eps, double dt,
+                        int32_t nsteps, int32_t shift_x, int32_t shift_v, const void *xbar_T, const void *vbar_T,
+                        void *pos_cot, void *vel_cot, void *mass_cot, void *stream)
+{
+    NB_CHECK(check_n(n));
+    if (nsteps < 0) {
+        set_error("nsteps < 0");
+        return NBODY_E_INVAL;
+    }
+    NB_CHECK(check_scalars(G, eps, dt));
+    NB_CHECK(check_shifts(shift_x, shift_v));
+    NB_CHECK(check_vec(pos_mass, NBODY_F32, "pos_mass"));
+    NB_CHECK(check_vec(xbar_T, NBODY_F32, "xbar_T"));
+    NB_CHECK(check_vec(vbar_T, NBODY_F32, "vbar_T"));
+    NB_CHECK(check_vec(pos_cot, NBODY_F32, "pos_cot"));
+    NB_CHECK(check_vec(vel_cot, NBODY_F32, "vel_cot"));
+    if (!state || (uintptr_t)state % 32 || !mass_cot || (uintptr_t)mass_cot % 4) {
+        set_error("state (32-byte aligned) or mass_cot NULL or misaligned");
+        return NBODY_E_ALIGN;
+    }
+    const int prec = NBODY_F32_F64ACC;
+    const int ni = (int)n;
+    const size_t rb = (size_t)n * 16;
+    const double h = 0.5 * dt;
+    hipStream_t s = (hipStream_t)stream;
+    const Tune t = janus_tune(lookup_tune(2, prec, n));
+    void *acc = scratch(kSlotAdj0, rb);
+    void *dec = scratch(kSlotAdj1, rb);
+    char *scbuf = (char *)scratch(kSlotAdj4, rb + 256);
+    void *vpart = nullptr;
+    if (const size_t pb = vjp_partial_bytes(ni, t)) vpart = scratch(kSlotAdj3, pb);
+    if (!acc || !dec || !scbuf || (vjp_partial_bytes(ni, t) && !vpart)) {
+        set_error("cannot allocate adjoint scratch");
+        return NBODY_E_NOMEM;
+    }
+    void *vsc = scbuf;
+    int *nonpos = (int *)(scbuf + rb);
+    NB_TRY(launch_copy(pos_cot, xbar_T, rb, s), "adjoint init");
+    NB_TRY(launch_copy(vel_cot, vbar_T, rb, s), "adjoint init");
+    NB_TRY(launch_fill_zero(mass_cot, 4 * (size_t)n, s), "adjoint init");
+    NB_TRY(launch_fill_zero(nonpos, 4, s), "adjoint init");
+    NB_CHECK(janus_decode(state, pos_mass, ni, shift_x, dec, s));
+    NB_TRY(launch_prescale(prec, vel_cot, dec, ni, vsc, nonpos, s), "adjoint init");
+    // the exact reversal needs the mass-scaled VJP (its force equals the
+    // force kernel's bit for bit): check the masses once
+    int host_nonpos = 0;
+    NB_TRY(hipMemcpyAsync(&host_nonpos, nonpos, 4, hipMemcpyDeviceToHost, s), "adjoint mass check");
+    NB_TRY(hipStreamSynchronize(s), "adjoint mass check");
+    if (host_nonpos) {
+        set_error("the bit-reversible adjoint needs every mass positive");
+        return NBODY_E_UNSUPPORTED;
+    }
+    // the kernels run with G = 1; G scales the cotangents and the kicks
+    for (int k = nsteps - 1; k >= 0; --k) {
+        const double scale = (k == nsteps - 1 ? h : 2.0 * h) * G;
+        NB_TRY(launch_vjp_adj_step(prec, 3, dec, vel_cot, vsc, nonpos, ni, 1.0, eps, scale, pos_cot, mass_cot,
+                                   acc, nullptr, 0.0, dt, t, vpart, s),
+               "adjoint step");
+        NB_CHECK(janus_unstep(state, acc, ni, G, dt, shift_x, shift_v, k == nsteps - 1 ? 1 : 2, 1, dec, s));
+    }
+    if (nsteps > 0) {
+        NB_TRY(launch_vjp_adj(prec, dec, vel_cot, vsc, nonpos, ni, 1.0, eps, h * G, pos_cot, mass_cot, acc, t,
+                              vpart, s),
+               "adjoint vjp");
+        NB_CHECK(janus_unstep(state, acc, ni, G, dt, shift_x, shift_v, 1, 0, dec, s));
+    }
+    return NBODY_OK;
+}
+
 // ---- trajectory + adjoint ---------------------------------------------------
 int nbody_trajectory_forward(void *pos_mass, void *vel, int64_t n, int32_t prec, double G,
                              double eps, double dt, int32_t nsteps, int32_t ckpt_every, void *ckpt,

@@ -521,6 +521,7 @@ __global__ __launch_bounds__(kBlock) void k_axpy(V *__restrict__ y, const V *__r
 // Split reduction fused with the elementwise step that follows every adjoint
 // VJP, so that one launch finishes the step:
 //   POST 1 (segment recompute):  vbar += dt xbar,  vsc = vbar / m
+//   POST 3 (integer reversal):    as POST 1, and the force is written to vh
 //   POST 2 (time reversal):      vh -= hk a;  x -= dt vh;  vbar += dt xbar;
 //                                vsc = vbar / m
 // The stored (rounded) xbar and a are the values used, as in the separate
@@ -559,6 +560,14 @@ __global__ __launch_bounds__(kBlock) void k_vjp_reduce_post(
         p.z = p.z - dt * v.z;
         vh[i] = v;
         x[i] = p;
+    }
+    if (POST == 3) {  // the force alone, for a reversal done elsewhere (vh receives it)
+        V f;
+        f.x = (S)o[4];
+        f.y = (S)o[5];
+        f.z = (S)o[6];
+        f.w = 0;
+        vh[i] = f;
     }
     w.x = w.x + dt * g.x;
     w.y = w.y + dt * g.y;
@@ -763,7 +772,7 @@ hipError_t launch_vjp_adj_step(int prec, int post, void *pm, void *raw, void *sc
 {
     if (t.jsplit == 1) {
         hipError_t e = launch_vjp_adj(prec, pm, raw, sc, nonpos, n, G, eps, scale, pos_cot, mass_cot,
-                                      post == 2 ? acc : nullptr, t, partial, s);
+                                      post >= 2 ? acc : nullptr, t, partial, s);
         if (e != hipSuccess) return e;
         if (post == 2) return launch_reverse_step(prec, pm, vh, acc, pos_cot, raw, sc, n, hk, dt, s);
         return launch_adj_axpy(prec, raw, pos_cot, dt, pm, sc, n, s);
@@ -793,6 +802,11 @@ hipError_t launch_vjp_adj_step(int prec, int post, void *pm, void *raw, void *sc
                                (const double4 *)partial, t.jsplit, n, scale, (double4 *)pos_cot,
                                (double *)mass_cot, (double4 *)pm, (double4 *)vh, (double4 *)raw,
                                (double4 *)sc, hk, dt);
+        else if (post == 3)
+            hipLaunchKernelGGL((k_vjp_reduce_post<double4, double, double, 3>), rg, dim3(kBlock), 0, s,
+                               (const double4 *)partial, t.jsplit, n, scale, (double4 *)pos_cot,
+                               (double *)mass_cot, (double4 *)pm, (double4 *)acc, (double4 *)raw,
+                               (double4 *)sc, hk, dt);
         else
             hipLaunchKernelGGL((k_vjp_reduce_post<double4, double, double, 1>), rg, dim3(kBlock), 0, s,
                                (const double4 *)partial, t.jsplit, n, scale, (double4 *)pos_cot,
@@ -803,6 +817,11 @@ hipError_t launch_vjp_adj_step(int prec, int post, void *pm, void *raw, void *sc
             hipLaunchKernelGGL((k_vjp_reduce_post<float4, float, float, 2>), rg, dim3(kBlock), 0, s,
                                (const double4 *)partial, t.jsplit, n, scale, (float4 *)pos_cot,
                                (float *)mass_cot, (float4 *)pm, (float4 *)vh, (float4 *)raw,
+                               (float4 *)sc, (float)hk, (float)dt);
+        else if (post == 3)
+            hipLaunchKernelGGL((k_vjp_reduce_post<float4, float, float, 3>), rg, dim3(kBlock), 0, s,
+                               (const double4 *)partial, t.jsplit, n, scale, (float4 *)pos_cot,
+                               (float *)mass_cot, (float4 *)pm, (float4 *)acc, (float4 *)raw,
                                (float4 *)sc, (float)hk, (float)dt);
         else
             hipLaunchKernelGGL((k_vjp_reduce_post<float4, float, float, 1>), rg, dim3(kBlock), 0, s,

@@ -105,6 +105,21 @@ def test_other_entry_points_validate():
     # adjoint: an unknown scheme stays invalid with the potential flag set
     assert L.nbody_trajectory_adjoint(P(64), 10, 1, 1.0, 0.01, 1e-3, 20, 20, P(1024), P(2048), P(4096),
                                       P(8192), P(16384), 0x10 | 5, None) == -1
+    # fixed-point leapfrog: step count, shifts, state pointer and alignment
+    jf = lambda *a: L.nbody_janus_forward(*a)
+    assert jf(P(64), P(1024), 10, 1.0, 0.01, 1e-3, -1, 40, 40, P(4096), P(8192), None, None) == -1
+    assert jf(P(64), P(1024), 10, 1.0, 0.01, 1e-3, 4, 61, 40, P(4096), P(8192), None, None) == -1
+    assert jf(P(64), P(1024), 10, 1.0, 0.01, 1e-3, 4, 40, -1, P(4096), P(8192), None, None) == -1
+    assert jf(P(64), P(1024), 10, 1.0, 0.01, 1e-3, 4, 40, 40, None, P(8192), None, None) == -2
+    assert jf(P(64), P(1024), 10, 1.0, 0.01, 1e-3, 4, 40, 40, P(4112), P(8192), None, None) == -2
+    assert jf(P(64), P(1024), 10, 1.0, 0.01, float("nan"), 4, 40, 40, P(4096), P(8192), None, None) == -1
+    ja = lambda *a: L.nbody_janus_adjoint(*a)
+    assert ja(P(4096), P(64), 10, 1.0, 0.01, 1e-3, -2, 40, 40, P(1024), P(2048), P(8192), P(16384), P(32768),
+              None) == -1
+    assert ja(P(4112), P(64), 10, 1.0, 0.01, 1e-3, 2, 40, 40, P(1024), P(2048), P(8192), P(16384), P(32768),
+              None) == -2
+    assert ja(P(4096), P(64), 10, 1.0, 0.01, 1e-3, 2, 40, 40, P(1024), P(2048), P(8192), P(16384), None,
+              None) == -2
 
 
 @pytest.mark.parametrize("n,leaf", [(1, 1), (9, 8), (100, 8), (1000, 3), (4096, 16), (70001, 8), (777, 64)])
