@@ -88,6 +88,14 @@ def _load():
         lib.oracle_tree_accel.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _d, _d, ctypes.c_double,
                                           ctypes.c_double, ctypes.c_double, ctypes.c_int64, _i64, _d, _d]
         lib.oracle_tree_accel.restype = ctypes.c_int
+        lib.oracle_tree_accel_order.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _d, _d,
+                                                ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                                ctypes.c_int32, ctypes.c_int64, _i64, _d, _d]
+        lib.oracle_tree_accel_order.restype = ctypes.c_int
+        lib.oracle_tree_pseudo.argtypes = [ctypes.c_int64, ctypes.c_int32, _d, _d, _d]
+        lib.oracle_tree_pseudo.restype = ctypes.c_int
+        lib.oracle_pseudo_dirs.argtypes = [_d]
+        lib.oracle_pseudo_dirs.restype = None
         lib.oracle_num_threads.argtypes = []
         lib.oracle_num_threads.restype = ctypes.c_int
         _lib = lib
@@ -317,10 +325,13 @@ def tree_lists(pos_mass_orb, leaf: int, group: int, theta: float):
     return dict(group_id=gid, far_cnt=fc, near_cnt=nc, far=far[:int(fc.sum())], near=near[:int(nc.sum())])
 
 
-def tree_accel(pos_mass_orb, leaf: int, group: int, theta: float, eps: float, G: float = 1.0, targets=None):
+def tree_accel(pos_mass_orb, leaf: int, group: int, theta: float, eps: float, G: float = 1.0, targets=None,
+               order: int = 0):
     """Tree-code force and potential (Section IV.A) on the ORB cells: far
-    cells as monopoles, near leaves body by body.  Returns (acc (T, 3),
-    pot (T,)) for ORB positions ``targets`` (all when None)."""
+    cells as monopoles (order 0) or as their 12 pseudo-particles (order 2,
+    the pseudo-particle multipole method of the paper's reference [20]), near
+    leaves body by body.  Returns (acc (T, 3), pot (T,)) for ORB positions
+    ``targets`` (all when None)."""
     lib = _load()
     x, m = _split(pos_mass_orb)
     n = x.shape[0]
@@ -333,9 +344,31 @@ def tree_accel(pos_mass_orb, leaf: int, group: int, theta: float, eps: float, G:
         nt = tp.shape[0]
     acc = np.empty((nt, 3))
     pot = np.empty(nt)
-    rc = lib.oracle_tree_accel(n, int(leaf), int(group), _ptr(x, _d), _ptr(m, _d), float(G), float(eps),
-                               float(theta), nt, None if tp is None else _ptr(tp, _i64), _ptr(acc, _d),
-                               _ptr(pot, _d))
+    rc = lib.oracle_tree_accel_order(n, int(leaf), int(group), _ptr(x, _d), _ptr(m, _d), float(G), float(eps),
+                                     float(theta), int(order), nt, None if tp is None else _ptr(tp, _i64),
+                                     _ptr(acc, _d), _ptr(pot, _d))
     if rc != 0:
-        raise ValueError("oracle_tree_accel failed")
+        raise ValueError("oracle_tree_accel_order failed")
     return acc, pot
+
+
+def pseudo_dirs() -> np.ndarray:
+    """The 12 unit directions (icosahedron vertices) of the pseudo-particles."""
+    out = np.empty((12, 3))
+    _load().oracle_pseudo_dirs(_ptr(out, _d))
+    return out
+
+
+def tree_pseudo(pos_mass_orb, leaf: int) -> np.ndarray:
+    """Pseudo-particles (x, y, z, q) of every node, (nn, 12, 4): the order-2
+    expansion of each cell about its centre of mass carried by 12 point
+    masses on a sphere of half the box diagonal (Makino's formula, summed
+    over the cell's bodies)."""
+    lib = _load()
+    x, m = _split(pos_mass_orb)
+    n = x.shape[0]
+    nn = tree_nodes(n, leaf).shape[0]
+    out = np.empty((nn, 12, 4))
+    if lib.oracle_tree_pseudo(n, int(leaf), _ptr(x, _d), _ptr(m, _d), _ptr(out, _d)) != 0:
+        raise ValueError("oracle_tree_pseudo: bad arguments")
+    return out

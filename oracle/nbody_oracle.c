@@ -50,6 +50,13 @@
  *                    IV.B ORB recursion: node table, moments, interaction
  *                    lists and the resulting force; the readings are stated
  *                    above those functions.
+ *   oracle_tree_pseudo, oracle_tree_accel_order
+ *                    Higher-order cells by the pseudo-particle multipole
+ *                    method of Makino (1999), the paper's reference [20],
+ *                    which Section VI names as the way past monopole cells:
+ *                    each cell's expansion to quadrupole order is carried by
+ *                    12 point masses, computed from the cell's bodies by
+ *                    that method's formula.
  *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared (no fast-math;
  * contraction off so that every product and sum rounds as written).
@@ -797,22 +804,138 @@ int oracle_tree_lists(int64_t n, int32_t leaf, int32_t group, const double *x, c
     return rc;
 }
 
-/* Tree force and potential on targets (ORB positions; NULL = all n).
- * acc: [ntarg][3], pot: [ntarg].  Neumaier-compensated FP64 sums over the
- * far cells in list order, then the near bodies in list order. */
-int oracle_tree_accel(int64_t n, int32_t leaf, int32_t group, const double *x, const double *m, double G,
-                      double eps, double theta, int64_t ntarg, const int64_t *targets, double *acc,
-                      double *pot)
+/* ---------------------------------------------------------------------------
+ * Pseudo-particle multipoles (Makino 1999, the paper's reference [20]).
+ *
+ * Outside a cell the potential of its bodies is the multipole series
+ *   phi(R) = -G sum_i m_i sum_l |r_i|^l / |R|^(l+1) P_l(cos angle(r_i, R)),
+ * r_i = x_i - com, R measured from com.  The method replaces the bodies by K
+ * point masses q_j at com + a s_j (unit vectors s_j, radius a) whose series
+ * is the same for l = 0..p:
+ *   q_j = sum_i m_i sum_{l=0..p} (2l+1)/K (|r_i|/a)^l P_l(cos angle(r_i, s_j)).
+ * By the addition theorem of the Legendre polynomials this holds whenever
+ * the mean of every polynomial of degree <= 2p over the K directions equals
+ * its mean over the unit sphere.  Order p = 2 here, with K = 12 directions,
+ * the vertices of the icosahedron (a spherical 5-design).  With
+ * c_j = s_j . r_i the terms are written without dividing by |r_i|:
+ *   l = 0: 1,   l = 1: c_j / a,   l = 2: (3 c_j^2 - |r_i|^2) / (2 a^2).
+ * Readings of this library (the paper fixes none of them):
+ *   directions  (0, +-1, +-g), (+-1, +-g, 0), (+-g, 0, +-1) divided by
+ *               sqrt(1 + g^2), g = (1 + sqrt 5) / 2; j = 0..11 in that order,
+ *               the sign pairs of each triple in the order (+,+), (+,-),
+ *               (-,+), (-,-).
+ *   centre      the cell's FP64 centre of mass (tree moments above).
+ *   radius      a = sqrt(diag2) / 2, half the cell's box diagonal; when a = 0
+ *               the l >= 1 terms are dropped (q_j = M / 12).
+ *   sums        over the cell's bodies in position order, Neumaier-compensated.
+ *   force       an accepted cell acts as its 12 pseudo-particles, j = 0..11,
+ *               with the softened pair law of the bodies.
+ * ------------------------------------------------------------------------- */
+#define PSEUDO_K 12
+
+static void pseudo_dirs(double s[PSEUDO_K][3])
 {
-    if (!(theta >= 0.0))
+    const double g = 0.5 * (1.0 + sqrt(5.0));
+    const double inv = 1.0 / sqrt(1.0 + g * g);
+    static const double sg[4][2] = {{1, 1}, {1, -1}, {-1, 1}, {-1, -1}};
+    for (int k = 0; k < 4; ++k) {
+        const double u = sg[k][0], v = sg[k][1];
+        /* (0, +-1, +-g) */
+        s[k][0] = 0.0;
+        s[k][1] = u * inv;
+        s[k][2] = v * g * inv;
+        /* (+-1, +-g, 0) */
+        s[4 + k][0] = u * inv;
+        s[4 + k][1] = v * g * inv;
+        s[4 + k][2] = 0.0;
+        /* (+-g, 0, +-1) */
+        s[8 + k][0] = u * g * inv;
+        s[8 + k][1] = 0.0;
+        s[8 + k][2] = v * inv;
+    }
+}
+
+/* The 12 unit directions, [12][3]. */
+void oracle_pseudo_dirs(double *out)
+{
+    double s[PSEUDO_K][3];
+    pseudo_dirs(s);
+    memcpy(out, s, sizeof(s));
+}
+
+/* Pseudo-particles of every node from its bodies: out [nn][12][4] =
+ * (x, y, z, q).  d holds the node table and the monopole moments. */
+static void tree_pseudo_fill(const tree_data *d, const double *x, const double *m, double *out)
+{
+    double s[PSEUDO_K][3];
+    pseudo_dirs(s);
+    int64_t c;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (c = 0; c < d->nn; ++c) {
+        const double *cm = d->com + 3 * c;
+        const double a = 0.5 * sqrt(d->diag2[c]);
+        for (int j = 0; j < PSEUDO_K; ++j) {
+            nsum q = {0, 0};
+            for (int64_t i = d->nodes[4 * c]; i < d->nodes[4 * c + 1]; ++i) {
+                const double rx = x[3 * i] - cm[0], ry = x[3 * i + 1] - cm[1], rz = x[3 * i + 2] - cm[2];
+                double t = 1.0 / PSEUDO_K;
+                if (a > 0.0) {
+                    const double cj = (s[j][0] * rx + s[j][1] * ry) + s[j][2] * rz;
+                    const double r2 = (rx * rx + ry * ry) + rz * rz;
+                    t = t + 3.0 / PSEUDO_K * (cj / a);
+                    t = t + 5.0 / PSEUDO_K * ((3.0 * cj * cj - r2) / (2.0 * a * a));
+                }
+                nsum_add(&q, m[i] * t);
+            }
+            double *o = out + 4 * (PSEUDO_K * c + j);
+            o[0] = cm[0] + a * s[j][0];
+            o[1] = cm[1] + a * s[j][1];
+            o[2] = cm[2] + a * s[j][2];
+            o[3] = nsum_val(&q);
+        }
+    }
+}
+
+/* Pseudo-particles of every node (ORB positions): out [nn][12][4] =
+ * (x, y, z, q).  Returns 0, or -1 on bad arguments. */
+int oracle_tree_pseudo(int64_t n, int32_t leaf, const double *x, const double *m, double *out)
+{
+    tree_data d;
+    if (tree_setup(n, leaf, leaf, x, m, &d) != 0)
+        return -1;
+    tree_pseudo_fill(&d, x, m, out);
+    tree_free(&d);
+    return 0;
+}
+
+/* Tree force and potential on targets (ORB positions; NULL = all n).
+ * acc: [ntarg][3], pot: [ntarg].  order 0: an accepted cell acts as one body
+ * (M at com); order 2: as its 12 pseudo-particles.  Neumaier-compensated
+ * FP64 sums over the far cells in list order (pseudo-particles j = 0..11
+ * within a cell), then the near bodies in list order. */
+int oracle_tree_accel_order(int64_t n, int32_t leaf, int32_t group, const double *x, const double *m,
+                            double G, double eps, double theta, int32_t order, int64_t ntarg,
+                            const int64_t *targets, double *acc, double *pot)
+{
+    if (!(theta >= 0.0) || (order != 0 && order != 2))
         return -1;
     tree_data d;
     if (tree_setup(n, leaf, group, x, m, &d) != 0)
         return -1;
+    double *pp = NULL;
+    if (order == 2) {
+        pp = (double *)malloc((size_t)d.nn * PSEUDO_K * 4 * sizeof(double));
+        if (!pp) {
+            tree_free(&d);
+            return -1;
+        }
+        tree_pseudo_fill(&d, x, m, pp);
+    }
     tree_ctx tc = {d.nodes, d.com, d.lo, d.hi, d.diag2, theta * theta};
     /* group of every position */
     int64_t *gof = (int64_t *)malloc((size_t)n * sizeof(int64_t));
     if (!gof) {
+        free(pp);
         tree_free(&d);
         return -1;
     }
@@ -841,29 +964,30 @@ int oracle_tree_accel(int64_t n, int32_t leaf, int32_t group, const double *x, c
         const double xi = x[3 * i], yi = x[3 * i + 1], zi = x[3 * i + 2];
         nsum ax = {0, 0}, ay = {0, 0}, az = {0, 0}, ph = {0, 0};
         for (int64_t q = 0; q < nf + nnr; ++q) {
+            const int64_t c = q < nf ? far[q] : near[q - nf];
             int64_t jb, je;
-            const double *src;
-            const double *ms;
-            double cm;
             if (q < nf) {
-                const int64_t c = far[q];
-                src = d.com + 3 * c;
-                cm = d.mass[c];
-                ms = &cm;
                 jb = 0;
-                je = 1;
+                je = order == 0 ? 1 : PSEUDO_K;
             } else {
-                const int64_t c = near[q - nf];
-                src = x;
-                ms = m;
                 jb = d.nodes[4 * c];
                 je = d.nodes[4 * c + 1];
             }
             for (int64_t j = jb; j < je; ++j) {
-                if (q >= nf && j == i)
-                    continue;
-                const double *xj = q < nf ? src : src + 3 * j;
-                const double mj = q < nf ? ms[0] : ms[j];
+                const double *xj;
+                double mj;
+                if (q >= nf) {
+                    if (j == i)
+                        continue;
+                    xj = x + 3 * j;
+                    mj = m[j];
+                } else if (order == 0) {
+                    xj = d.com + 3 * c;
+                    mj = d.mass[c];
+                } else {
+                    xj = pp + 4 * (PSEUDO_K * c + j);
+                    mj = xj[3];
+                }
                 const double dx = xj[0] - xi;
                 const double dy = xj[1] - yi;
                 const double dz = xj[2] - zi;
@@ -888,8 +1012,17 @@ int oracle_tree_accel(int64_t n, int32_t leaf, int32_t group, const double *x, c
             pot[t] = -G * nsum_val(&ph);
     }
     free(gof);
+    free(pp);
     tree_free(&d);
     return bad ? -1 : 0;
+}
+
+/* The monopole tree force (order 0 of the above). */
+int oracle_tree_accel(int64_t n, int32_t leaf, int32_t group, const double *x, const double *m, double G,
+                      double eps, double theta, int64_t ntarg, const int64_t *targets, double *acc,
+                      double *pot)
+{
+    return oracle_tree_accel_order(n, leaf, group, x, m, G, eps, theta, 0, ntarg, targets, acc, pot);
 }
 
 /* ---------------------------------------------------------------------------
