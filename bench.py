@@ -18,9 +18,14 @@ Also reported on the same JSON line:
 * cpu_baseline: the FP64 oracle on a bounded sample of targets of the same
   workload, on the host cores, and the GPU's error against it;
 * adjoint: forward+adjoint time / plain forward time for the differentiation
-  workload (Plummer N = 16384, 200 steps, checkpoints every 20);
+  workload (Plummer N = 16384, 200 steps, checkpoints every 20), and the same
+  ratio for the bit-reversible fixed-point leapfrog (no checkpoints);
 * batched: aggregate G-interactions/s for 512 ragged Plummer systems, 50
-  steps captured in one HIP graph.
+  steps captured in one HIP graph;
+* tree: the tree code on the ORB cells of the same colliding pair, monopole
+  and order-2 (pseudo-particle) cells at theta 0.5, 0.7, 1.0: time, work and
+  error against the exact sum;
+* shard: one GPU's share of an 8-way target split (131072 x 1048576).
 """
 from __future__ import annotations
 
@@ -463,6 +468,19 @@ def tree_leg(torch, nb, pm_np, eps, direct_ms, leaf=4):
     res = {"workload": f"colliding Plummer pair, N=1048576, eps=0.005, step 0, ORB leaf {leaf}, groups of 64, "
                        "F32_F64ACC", "leaf": leaf, "orb_plus_gather_ms": round(orb_ms, 3), "theta": {}}
     reps = 10
+    nn = nodes.shape[0]
+    pseudo = torch.empty((nn, nb.TREE_PSEUDO, 4), dtype=torch.float32, device=dev)
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    res["order2"] = {}
+
+    def moments_only(order):
+        # order 0: monopole moments; order 2: also second moments and
+        # pseudo-particles (plus their export copy, ~0.02 ms at 2^20)
+        if order == 0:
+            return L.nbody_tree_moments(ctypes.c_void_p(q.data_ptr()), n, leaf, None, None, stream)
+        return L.nbody_tree_pseudo(ctypes.c_void_p(q.data_ptr()), n, leaf, ctypes.c_void_p(pseudo.data_ptr()),
+                                   stream)
+
     for theta in (0.5, 0.7, 1.0):
         fc, ncnt, _, _ = nb.tree_lists(q, theta, leaf)
         mn = int(ncnt.max().item())
@@ -471,44 +489,46 @@ def tree_leg(torch, nb, pm_np, eps, direct_ms, leaf=4):
         fc, ncnt, ni = fc.cpu().numpy(), ncnt.cpu().numpy(), ni.cpu().numpy()
         sizes = nodes[:, 1] - nodes[:, 0]
         near_bodies = np.array([sizes[ni[g, :ncnt[g]]].sum() for g in range(len(groups))], dtype=np.float64)
-        pairs = float((gsz * (fc + near_bodies) + gsz * (gsz - 1)).sum())
-        nb.tree_accel(q, eps, theta, leaf, prec=nb.F32_F64ACC, out=out)
-        torch.cuda.synchronize()
-        ts, tm = [], []
-        for _ in range(reps):
-            e0.record()
-            nb.tree_accel(q, eps, theta, leaf, prec=nb.F32_F64ACC, out=out)
-            e1.record()
+        for order in (0, 2):
+            per_cell = 1 if order == 0 else nb.TREE_PSEUDO
+            pairs = float((gsz * (per_cell * fc + near_bodies) + gsz * (gsz - 1)).sum())
+            nb.tree_accel(q, eps, theta, leaf, prec=nb.F32_F64ACC, out=out, cell_order=order)
             torch.cuda.synchronize()
-            ts.append(e0.elapsed_time(e1))
-            e0.record()
-            rc = L.nbody_tree_moments(ctypes.c_void_p(q.data_ptr()), n, leaf, None, None,
-                                      ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
-            e1.record()
-            torch.cuda.synchronize()
-            if rc != 0:
-                raise RuntimeError("nbody_tree_moments failed")
-            tm.append(e0.elapsed_time(e1))
-        t, t_mom = float(np.mean(ts)), float(np.mean(tm))
-        t_walk = t - t_mom
-        got = out.cpu().double().numpy()
-        rel = np.linalg.norm(got[:, :3] - d_host[:, :3], axis=1) / np.linalg.norm(d_host[:, :3], axis=1)
-        walk_tflops = FLOP_PER_PAIR * pairs / (t_walk * 1e-3) / 1e12
-        r = {"ms": round(t, 4), "ms_std": round(float(np.std(ts)), 4), "moments_ms": round(t_mom, 4),
-             "walk_force_ms": round(t_walk, 4), "interactions_per_body": round(pairs / n, 1),
-             "far_cells_per_group": round(float(fc.mean()), 1),
-             "pairs_per_s": round(pairs / (t_walk * 1e-3), 1),
-             "direct_equivalent_g_interactions_per_s": round(float(n) * n / (t * 1e-3) / 1e9, 1),
-             "speedup_vs_direct_kernel": round(direct_ms / t, 2),
-             "rms_rel_err_vs_direct": float(np.sqrt(np.mean(rel ** 2))),
-             "max_rel_err_vs_direct": float(rel.max()),
-             "walk_roofline": {"bound": "alu", "achieved": round(walk_tflops, 3), "peak": PEAK_FP32_TFLOPS,
-                               "unit": "TFLOP/s", "frac": round(walk_tflops / PEAK_FP32_TFLOPS, 4),
-                               "kernel": "k_tree_walk<F64ACC>", "flop_per_pair": FLOP_PER_PAIR}}
-        res["theta"][str(theta)] = r
-        log(f"[bench] tree theta {theta}: {t:.3f} ms ({t_mom:.3f} moments), {pairs / n:.0f} interactions/body, "
-            f"{walk_tflops:.1f} TFLOP/s in the walk, x{direct_ms / t:.1f} vs direct, "
-            f"rms err {r['rms_rel_err_vs_direct']:.2e}")
+            ts, tm = [], []
+            for _ in range(reps):
+                e0.record()
+                nb.tree_accel(q, eps, theta, leaf, prec=nb.F32_F64ACC, out=out, cell_order=order)
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+                e0.record()
+                rc = moments_only(order)
+                e1.record()
+                torch.cuda.synchronize()
+                if rc != 0:
+                    raise RuntimeError("tree moments failed")
+                tm.append(e0.elapsed_time(e1))
+            t, t_mom = float(np.mean(ts)), float(np.mean(tm))
+            t_walk = t - t_mom
+            got = out.cpu().double().numpy()
+            rel = np.linalg.norm(got[:, :3] - d_host[:, :3], axis=1) / np.linalg.norm(d_host[:, :3], axis=1)
+            walk_tflops = FLOP_PER_PAIR * pairs / (t_walk * 1e-3) / 1e12
+            kern = "k_tree_walk<F64ACC>" if order == 0 else "k_tree_walk<F64ACC, pseudo-particles>"
+            r = {"ms": round(t, 4), "ms_std": round(float(np.std(ts)), 4), "moments_ms": round(t_mom, 4),
+                 "walk_force_ms": round(t_walk, 4), "interactions_per_body": round(pairs / n, 1),
+                 "far_cells_per_group": round(float(fc.mean()), 1),
+                 "pairs_per_s": round(pairs / (t_walk * 1e-3), 1),
+                 "direct_equivalent_g_interactions_per_s": round(float(n) * n / (t * 1e-3) / 1e9, 1),
+                 "speedup_vs_direct_kernel": round(direct_ms / t, 2),
+                 "rms_rel_err_vs_direct": float(np.sqrt(np.mean(rel ** 2))),
+                 "max_rel_err_vs_direct": float(rel.max()),
+                 "walk_roofline": {"bound": "alu", "achieved": round(walk_tflops, 3), "peak": PEAK_FP32_TFLOPS,
+                                   "unit": "TFLOP/s", "frac": round(walk_tflops / PEAK_FP32_TFLOPS, 4),
+                                   "kernel": kern, "flop_per_pair": FLOP_PER_PAIR}}
+            (res["theta"] if order == 0 else res["order2"])[str(theta)] = r
+            log(f"[bench] tree order {order} theta {theta}: {t:.3f} ms ({t_mom:.3f} moments), "
+                f"{pairs / n:.0f} interactions/body, {walk_tflops:.1f} TFLOP/s in the walk, "
+                f"x{direct_ms / t:.1f} vs direct, rms err {r['rms_rel_err_vs_direct']:.2e}")
     return res
 
 

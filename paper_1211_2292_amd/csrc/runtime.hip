@@ -772,7 +772,17 @@ int nbody_tree_shape(int64_t n, int32_t leaf, int64_t *num_nodes, int64_t *num_g
 int nbody_tree_accel(const void *pos_mass, int64_t n, int32_t prec, double G, double eps, double theta,
                      int32_t leaf, void *acc_pot_out, void *stream)
 {
+    return nbody_tree_accel_order(pos_mass, n, prec, G, eps, theta, leaf, 0, acc_pot_out, stream);
+}
+
+int nbody_tree_accel_order(const void *pos_mass, int64_t n, int32_t prec, double G, double eps, double theta,
+                           int32_t leaf, int32_t order, void *acc_pot_out, void *stream)
+{
     NB_CHECK(check_tree(n, leaf));
+    if (order != 0 && order != 2) {
+        set_error("cell order %d (0 or 2)", order);
+        return NBODY_E_INVAL;
+    }
     if (!prec_ok(prec)) {
         set_error("bad precision %d", prec);
         return NBODY_E_INVAL;
@@ -785,7 +795,15 @@ int nbody_tree_accel(const void *pos_mass, int64_t n, int32_t prec, double G, do
     NB_CHECK(check_theta(theta));
     NB_CHECK(check_vec(pos_mass, prec, "pos_mass"));
     NB_CHECK(check_vec(acc_pot_out, prec, "acc_pot_out"));
-    return tree_accel(pos_mass, (int)n, prec, G, eps, theta, leaf, acc_pot_out, (hipStream_t)stream);
+    return tree_accel(pos_mass, (int)n, prec, G, eps, theta, leaf, order, acc_pot_out, (hipStream_t)stream);
+}
+
+int nbody_tree_pseudo(const void *pos_mass, int64_t n, int32_t leaf, void *pseudo_out, void *stream)
+{
+    NB_CHECK(check_tree(n, leaf));
+    NB_CHECK(check_vec(pos_mass, NBODY_F32, "pos_mass"));
+    NB_CHECK(check_vec(pseudo_out, NBODY_F32, "pseudo_out"));
+    return tree_pseudo(pos_mass, (int)n, leaf, pseudo_out, (hipStream_t)stream);
 }
 
 int nbody_tree_moments(const void *pos_mass, int64_t n, int32_t leaf, double *moments_out, float *box_out,
@@ -829,8 +847,8 @@ int nbody_tree_leapfrog(void *pos_mass, void *vel, void *acc_pot, int32_t *order
         set_error("the tree code runs the FP32 modes only");
         return NBODY_E_UNSUPPORTED;
     }
-    if (flags & ~(NBODY_ACC_VALID | NBODY_ENERGY)) {
-        set_error("unsupported flags 0x%x (NBODY_ACC_VALID and NBODY_ENERGY only)", flags);
+    if (flags & ~(NBODY_ACC_VALID | NBODY_ENERGY | NBODY_TREE_ORDER2)) {
+        set_error("unsupported flags 0x%x (NBODY_ACC_VALID, NBODY_ENERGY, NBODY_TREE_ORDER2 only)", flags);
         return NBODY_E_INVAL;
     }
     NB_CHECK(check_scalars(G, eps, dt));

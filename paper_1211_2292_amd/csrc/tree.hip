@@ -37,6 +37,20 @@
 //   whose children would overflow the stack is summed body by body instead,
 //   which is exact.  In inspection mode the same walk writes the node ids of
 //   the accepted cells and of the rejected leaves instead of summing.
+//
+// Order 2 (pseudo-particle multipoles, Makino 1999, the paper's reference
+// [20], named in Section VI as the next step past monopole cells): an
+// accepted cell acts as 12 point masses q_j at com + a s_j, s_j the unit
+// vertices of the icosahedron, a = half the box diagonal, whose expansion
+// about com equals the cell's through the quadrupole term.  With S the
+// cell's second moment about com (FP64, bottom-up by the parallel-axis rule:
+// a leaf sums m r r^T over its bodies, a parent adds each child's S plus
+// m_c d_c d_c^T, d_c = com_c - com), the method's mass formula reduces to
+//   q_j = M / 12 + 5 / (24 a^2) (3 s_j.S.s_j - trace S)
+// (the dipole term vanishes about com); a = 0 leaves q_j = M / 12.  The walk
+// and its acceptance test are unchanged; accepted cell ids are batched in
+// LDS and each cell's 12 records are read with scalar loads.
+#include <cstdint>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -50,6 +64,7 @@ namespace {
 constexpr int kGroup = 64;     // targets per group: one per lane
 constexpr int kStack = 512;    // LDS stack entries per wave
 constexpr int kBuf = 128;      // LDS batch entries (cells, near ranges)
+constexpr int kPseudo = 12;    // pseudo-particles per cell at order 2
 
 struct TreeDev {
     const int4 *node;    // begin, end, left, right (-1 for a leaf)
@@ -59,12 +74,14 @@ struct TreeDev {
     double4 *comd;       // com (FP64), diag2
     float4 *rec;         // com (FP32), M (FP32): the pseudo-body record
     float4 *lo, *hi;     // box
+    double4 *s2a, *s2b;  // second moment about com: (xx, yy, zz, xy), (xz, yz, -, -)
+    float4 *pp;          // order 2: kPseudo records (x, y, z, q) per node
 };
 
 __device__ __forceinline__ void finish_node(const TreeDev &T, int c, double M, double sx, double sy,
-                                            double sz, float4 lo, float4 hi)
+                                            double sz, float4 lo, float4 hi, double &cx, double &cy,
+                                            double &cz)
 {
-    double cx, cy, cz;
     if (M > 0.0) {
         cx = sx / M;
         cy = sy / M;
@@ -88,7 +105,9 @@ __device__ __forceinline__ void finish_node(const TreeDev &T, int c, double M, d
     T.hi[c] = hi;
 }
 
-// Leaves: one thread per leaf sums its bodies in position order.
+// Leaves: one thread per leaf sums its bodies in position order (Q2: then
+// the second moment about the centre of mass).
+template <bool Q2>
 __global__ __launch_bounds__(256) void k_tree_leaves(const float4 *__restrict__ pm, TreeDev T, int nleaves)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -113,11 +132,31 @@ __global__ __launch_bounds__(256) void k_tree_leaves(const float4 *__restrict__ 
         if (b.z < lo.z) lo.z = b.z;
         if (b.z > hi.z) hi.z = b.z;
     }
-    finish_node(T, c, M, sx, sy, sz, lo, hi);
+    double cx, cy, cz;
+    finish_node(T, c, M, sx, sy, sz, lo, hi, cx, cy, cz);
+    if constexpr (Q2) {
+        double xx = 0.0, yy = 0.0, zz = 0.0, xy = 0.0, xz = 0.0, yz = 0.0;
+        for (int p = nd.x; p < nd.y; ++p) {
+            const float4 b = pm[p];
+            const double m = b.w;
+            const double dx = (double)b.x - cx, dy = (double)b.y - cy, dz = (double)b.z - cz;
+            const double mx = m * dx, my = m * dy, mz = m * dz;
+            xx = xx + mx * dx;
+            yy = yy + my * dy;
+            zz = zz + mz * dz;
+            xy = xy + mx * dy;
+            xz = xz + mx * dz;
+            yz = yz + my * dz;
+        }
+        T.s2a[c] = make_double4(xx, yy, zz, xy);
+        T.s2b[c] = make_double4(xz, yz, 0.0, 0.0);
+    }
 }
 
 // Inner nodes of one height (their children are all lower, so finished by
-// the previous launches): left + right.
+// the previous launches): left + right (Q2: second moments moved to the
+// parent's centre of mass).
+template <bool Q2>
 __global__ __launch_bounds__(256) void k_tree_inner(TreeDev T, int first, int count)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -130,7 +169,63 @@ __global__ __launch_bounds__(256) void k_tree_inner(TreeDev T, int first, int co
                                   la.z < lb.z ? la.z : lb.z, 0.0f);
     const float4 hi = make_float4(ha.x > hb.x ? ha.x : hb.x, ha.y > hb.y ? ha.y : hb.y,
                                   ha.z > hb.z ? ha.z : hb.z, 0.0f);
-    finish_node(T, c, a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w, lo, hi);
+    double cx, cy, cz;
+    finish_node(T, c, a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w, lo, hi, cx, cy, cz);
+    if constexpr (Q2) {
+        const double4 ca = T.comd[nd.z], cb = T.comd[nd.w];
+        const double4 pa = T.s2a[nd.z], pb = T.s2a[nd.w], qa = T.s2b[nd.z], qb = T.s2b[nd.w];
+        const double ax = ca.x - cx, ay = ca.y - cy, az = ca.z - cz;
+        const double bx = cb.x - cx, by = cb.y - cy, bz = cb.z - cz;
+        const double ma = a.x, mb = b.x;
+        const double xx = (pa.x + ma * ax * ax) + (pb.x + mb * bx * bx);
+        const double yy = (pa.y + ma * ay * ay) + (pb.y + mb * by * by);
+        const double zz = (pa.z + ma * az * az) + (pb.z + mb * bz * bz);
+        const double xy = (pa.w + ma * ax * ay) + (pb.w + mb * bx * by);
+        const double xz = (qa.x + ma * ax * az) + (qb.x + mb * bx * bz);
+        const double yz = (qa.y + ma * ay * az) + (qb.y + mb * by * bz);
+        T.s2a[c] = make_double4(xx, yy, zz, xy);
+        T.s2b[c] = make_double4(xz, yz, 0.0, 0.0);
+    }
+}
+
+// Order-2 pseudo-particles, one thread per (node, direction).  Direction j:
+// family j / 4 = (0, u, v g), (u, v g, 0), (u g, 0, v), divided by
+// sqrt(1 + g^2), g the golden ratio, with (u, v) = (+,+), (+,-), (-,+), (-,-)
+// for j % 4 = 0..3.
+__global__ __launch_bounds__(256) void k_tree_pseudo(TreeDev T, int nn)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nn * kPseudo) return;
+    const int c = t / kPseudo, j = t - c * kPseudo;
+    const double g = 0.5 * (1.0 + sqrt(5.0));
+    const double inv = 1.0 / sqrt(1.0 + g * g);
+    const double u = (j & 2) ? -1.0 : 1.0, v = (j & 1) ? -1.0 : 1.0;
+    double s0, s1, s2;
+    if (j < 4) {
+        s0 = 0.0;
+        s1 = u * inv;
+        s2 = v * g * inv;
+    } else if (j < 8) {
+        s0 = u * inv;
+        s1 = v * g * inv;
+        s2 = 0.0;
+    } else {
+        s0 = u * g * inv;
+        s1 = 0.0;
+        s2 = v * inv;
+    }
+    const double4 cd = T.comd[c];
+    const double M = T.sums[c].x;
+    const double a = 0.5 * sqrt(cd.w);
+    double q = M / kPseudo;
+    if (a > 0.0) {
+        const double4 A = T.s2a[c], B = T.s2b[c];
+        const double sSs = (s0 * s0 * A.x + s1 * s1 * A.y + s2 * s2 * A.z) +
+                           2.0 * (s0 * s1 * A.w + s0 * s2 * B.x + s1 * s2 * B.y);
+        const double tr = (A.x + A.y) + A.z;
+        q = q + 5.0 / (2.0 * kPseudo * a * a) * (3.0 * sSs - tr);
+    }
+    T.pp[t] = make_float4((float)(cd.x + a * s0), (float)(cd.y + a * s1), (float)(cd.z + a * s2), (float)q);
 }
 
 __device__ __forceinline__ double box_gap(double p, double a, double b)
@@ -164,14 +259,32 @@ __device__ __forceinline__ void sweep_cells(const float4 *cb, int cnt, const Tar
     for (; j < cnt; ++j) pair_f32<1, false>(cb[j], j, T, eps2, S);
 }
 
-template <int MODE, bool INSPECT>
+// Sweeps the pseudo-particles of the batched cell ids (scalar loads of each
+// cell's 12 contiguous records).
+__device__ __forceinline__ void sweep_pseudo(const float4 *__restrict__ pp, const int *ids, int cnt,
+                                             const Targets<float, 1> &T, float eps2, Sums<float, 1> &S)
+{
+    for (int r = 0; r < cnt; ++r) {
+        const int c = __builtin_amdgcn_readfirstlane(ids[r]);
+        const float4 *q = pp + (long)kPseudo * c;
+        float4 b[kPseudo];
+#pragma unroll
+        for (int u = 0; u < kPseudo; ++u) b[u] = q[u];
+#pragma unroll
+        for (int u = 0; u < kPseudo; ++u) pair_f32<1, false>(b[u], u, T, eps2, S);
+    }
+}
+
+template <int MODE, bool INSPECT, bool PP>
 // 7 waves per SIMD: 5 KB of LDS per wave and at most 72 VGPRs (measured
 // faster than 6 waves, and than 8 waves with register spills).
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void k_tree_walk(const float4 *__restrict__ src, int n, TreeDev T,
-                                                  float eps2_in, double G, double theta2, WalkOut O)
+                                                  const float4 *__restrict__ pp, float eps2_in, double G,
+                                                  double theta2, WalkOut O)
 {
     __shared__ int stk[kStack];
-    __shared__ float4 cbuf[kBuf];
+    __shared__ float4 cbuf[PP ? 1 : kBuf];  // order 0: the accepted cells' records
+    __shared__ int cid[PP ? kBuf : 1];      // order 2: the accepted cells' ids
     __shared__ int2 nbuf[kBuf];
     const int lane = threadIdx.x;
     const int g = blockIdx.x;
@@ -210,7 +323,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void k_
     auto flush_cells = [&]() {
         if constexpr (!INSPECT) {
             S.zero();
-            sweep_cells(cbuf, nf, TT, eps2, S);
+            if constexpr (PP)
+                sweep_pseudo(pp, cid, nf, TT, eps2, S);
+            else
+                sweep_cells(cbuf, nf, TT, eps2, S);
             R[0].fold(S.ax[0]);
             R[1].fold(S.ay[0]);
             R[2].fold(S.az[0]);
@@ -285,7 +401,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void k_
                 if (q < O.max_near) O.near_ids[(long)g * O.max_near + q] = c;
             }
         } else {
-            if (acc) cbuf[nf + (int)lane_rank(ma)] = T.rec[c];
+            if (acc) {
+                if constexpr (PP)
+                    cid[nf + (int)lane_rank(ma)] = c;
+                else
+                    cbuf[nf + (int)lane_rank(ma)] = T.rec[c];
+            }
             if (nearr) nbuf[nr + (int)lane_rank(mn)] = make_int2(nd.x, nd.y);
         }
         if (open) {
@@ -455,7 +576,10 @@ int tree_prepare(int n, int leaf, hipStream_t s, TreeDev &out)
     const size_t o_rec = o_comd + align256(nn * sizeof(double4));
     const size_t o_lo = o_rec + align256(nn * sizeof(float4));
     const size_t o_hi = o_lo + align256(nn * sizeof(float4));
-    const size_t total = o_hi + align256(nn * sizeof(float4));
+    const size_t o_s2a = o_hi + align256(nn * sizeof(float4));
+    const size_t o_s2b = o_s2a + align256(nn * sizeof(double4));
+    const size_t o_pp = o_s2b + align256(nn * sizeof(double4));
+    const size_t total = o_pp + align256(nn * kPseudo * sizeof(float4));
     if (C.mem) {
         // work already enqueued may still read the old tables
         (void)hipDeviceSynchronize();
@@ -478,6 +602,9 @@ int tree_prepare(int n, int leaf, hipStream_t s, TreeDev &out)
     d.rec = (float4 *)(base + o_rec);
     d.lo = (float4 *)(base + o_lo);
     d.hi = (float4 *)(base + o_hi);
+    d.s2a = (double4 *)(base + o_s2a);
+    d.s2b = (double4 *)(base + o_s2b);
+    d.pp = (float4 *)(base + o_pp);
     // pageable copies complete on the host side before returning; the vectors
     // stay alive in the cache in any case
     C.host = std::move(h);
@@ -501,24 +628,46 @@ int tree_prepare(int n, int leaf, hipStream_t s, TreeDev &out)
     return NBODY_OK;
 }
 
-hipError_t launch_moments(const float4 *pm, const TreeDev &d, const HostTree &h, hipStream_t s)
+template <bool Q2>
+hipError_t launch_moments_t(const float4 *pm, const TreeDev &d, const HostTree &h, hipStream_t s)
 {
     const int nl = (int)h.leaves.size();
-    hipLaunchKernelGGL(k_tree_leaves, dim3((nl + 255) / 256), dim3(256), 0, s, pm, d, nl);
+    hipLaunchKernelGGL(k_tree_leaves<Q2>, dim3((nl + 255) / 256), dim3(256), 0, s, pm, d, nl);
     hipError_t e = hipGetLastError();
     for (size_t k = 1; e == hipSuccess && k + 1 < h.height_off.size(); ++k) {
         const int first = h.height_off[k], count = h.height_off[k + 1] - first;
-        hipLaunchKernelGGL(k_tree_inner, dim3((count + 255) / 256), dim3(256), 0, s, d, first, count);
+        hipLaunchKernelGGL(k_tree_inner<Q2>, dim3((count + 255) / 256), dim3(256), 0, s, d, first, count);
+        e = hipGetLastError();
+    }
+    if (Q2 && e == hipSuccess) {
+        const int nn = (int)h.node.size();
+        hipLaunchKernelGGL(k_tree_pseudo, dim3((nn * kPseudo + 255) / 256), dim3(256), 0, s, d, nn);
         e = hipGetLastError();
     }
     return e;
 }
 
-template <int MODE, bool INSPECT>
+// The pseudo-particle kernel indexes (node, direction) pairs with an int.
+bool pseudo_fits(const HostTree &h)
+{
+    if (h.node.size() * (size_t)kPseudo <= (size_t)INT32_MAX) return true;
+    set_error("%zu tree nodes are too many for order-2 cells", h.node.size());
+    return false;
+}
+
+// Monopole moments and boxes; with order 2 also the second moments and the
+// pseudo-particles.
+hipError_t launch_moments(const float4 *pm, const TreeDev &d, const HostTree &h, int order, hipStream_t s)
+{
+    return order == 2 ? launch_moments_t<true>(pm, d, h, s) : launch_moments_t<false>(pm, d, h, s);
+}
+
+template <int MODE, bool INSPECT, bool PP>
 hipError_t launch_walk(const float4 *pm, int n, const TreeDev &d, int ngroups, float eps2, double G,
                        double theta2, const WalkOut &o, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_tree_walk<MODE, INSPECT>), dim3(ngroups), dim3(64), 0, s, pm, n, d, eps2, G, theta2, o);
+    hipLaunchKernelGGL((k_tree_walk<MODE, INSPECT, PP>), dim3(ngroups), dim3(64), 0, s, pm, n, d,
+                       (const float4 *)d.pp, eps2, G, theta2, o);
     return hipGetLastError();
 }
 
@@ -541,7 +690,7 @@ int tree_moments(const void *pm, int n, int leaf, double *mom, float *box, hipSt
     int rc = tree_prepare(n, leaf, s, d);
     if (rc != NBODY_OK) return rc;
     const int nn = (int)g_tree.host.node.size();
-    hipError_t e = launch_moments((const float4 *)pm, d, g_tree.host, s);
+    hipError_t e = launch_moments((const float4 *)pm, d, g_tree.host, 0, s);
     if (e == hipSuccess && (mom || box)) {
         hipLaunchKernelGGL(k_tree_export, dim3((nn + 255) / 256), dim3(256), 0, s, d, nn, mom, box);
         e = hipGetLastError();
@@ -556,7 +705,7 @@ int tree_lists(const void *pm, int n, int leaf, double theta, int max_far, int m
     TreeDev d;
     int rc = tree_prepare(n, leaf, s, d);
     if (rc != NBODY_OK) return rc;
-    hipError_t e = launch_moments((const float4 *)pm, d, g_tree.host, s);
+    hipError_t e = launch_moments((const float4 *)pm, d, g_tree.host, 0, s);
     WalkOut o{};
     o.far_cnt = far_cnt;
     o.near_cnt = near_cnt;
@@ -565,32 +714,58 @@ int tree_lists(const void *pm, int n, int leaf, double theta, int max_far, int m
     o.max_far = far_ids ? max_far : 0;
     o.max_near = near_ids ? max_near : 0;
     if (e == hipSuccess)
-        e = launch_walk<M_F32, true>((const float4 *)pm, n, d, (int)g_tree.host.groups.size(), 0.0f, 1.0,
-                                     theta * theta, o, s);
+        e = launch_walk<M_F32, true, false>((const float4 *)pm, n, d, (int)g_tree.host.groups.size(), 0.0f,
+                                            1.0, theta * theta, o, s);
     return e == hipSuccess ? NBODY_OK : hip_fail(e, "tree lists");
 }
 
-int tree_accel(const void *pm, int n, int prec, double G, double eps, double theta, int leaf, void *out,
-               hipStream_t s)
+namespace {
+template <bool PP>
+hipError_t walk_prec(int prec, const float4 *pm, int n, const TreeDev &d, int ng, float eps2, double G, double th2,
+                     const WalkOut &o, hipStream_t s)
+{
+    switch (prec) {
+    case NBODY_F32: return launch_walk<M_F32, false, PP>(pm, n, d, ng, eps2, G, th2, o, s);
+    case NBODY_F32_KAHAN: return launch_walk<M_KAHAN, false, PP>(pm, n, d, ng, eps2, G, th2, o, s);
+    default: return launch_walk<M_F64ACC, false, PP>(pm, n, d, ng, eps2, G, th2, o, s);
+    }
+}
+}  // namespace
+
+int tree_accel(const void *pm, int n, int prec, double G, double eps, double theta, int leaf, int order,
+               void *out, hipStream_t s)
 {
     std::lock_guard<std::mutex> lk(g_tree_mu);
     TreeDev d;
     int rc = tree_prepare(n, leaf, s, d);
     if (rc != NBODY_OK) return rc;
-    hipError_t e = launch_moments((const float4 *)pm, d, g_tree.host, s);
+    if (order == 2 && !pseudo_fits(g_tree.host)) return NBODY_E_INVAL;
+    hipError_t e = launch_moments((const float4 *)pm, d, g_tree.host, order, s);
     WalkOut o{};
     o.acc_pot = (float4 *)out;
     const int ng = (int)g_tree.host.groups.size();
     const float eps2 = (float)(eps * eps);
     const double th2 = theta * theta;
     if (e == hipSuccess) {
-        switch (prec) {
-        case NBODY_F32: e = launch_walk<M_F32, false>((const float4 *)pm, n, d, ng, eps2, G, th2, o, s); break;
-        case NBODY_F32_KAHAN: e = launch_walk<M_KAHAN, false>((const float4 *)pm, n, d, ng, eps2, G, th2, o, s); break;
-        default: e = launch_walk<M_F64ACC, false>((const float4 *)pm, n, d, ng, eps2, G, th2, o, s); break;
-        }
+        if (order == 2)
+            e = walk_prec<true>(prec, (const float4 *)pm, n, d, ng, eps2, G, th2, o, s);
+        else
+            e = walk_prec<false>(prec, (const float4 *)pm, n, d, ng, eps2, G, th2, o, s);
     }
     return e == hipSuccess ? NBODY_OK : hip_fail(e, "tree force");
+}
+
+int tree_pseudo(const void *pm, int n, int leaf, void *out, hipStream_t s)
+{
+    std::lock_guard<std::mutex> lk(g_tree_mu);
+    TreeDev d;
+    int rc = tree_prepare(n, leaf, s, d);
+    if (rc != NBODY_OK) return rc;
+    if (!pseudo_fits(g_tree.host)) return NBODY_E_INVAL;
+    const size_t bytes = g_tree.host.node.size() * kPseudo * sizeof(float4);
+    hipError_t e = launch_moments((const float4 *)pm, d, g_tree.host, 2, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, d.pp, bytes, hipMemcpyDeviceToDevice, s);
+    return e == hipSuccess ? NBODY_OK : hip_fail(e, "tree pseudo-particles");
 }
 
 // ---- tree leapfrog ---------------------------------------------------------------
@@ -668,8 +843,9 @@ int tree_leapfrog(void *pm, void *vel, void *acc, int32_t *order, int n, int pre
         const int rc = reorder(pm, vel, acc, order, n, leaf, s);
         if (rc != NBODY_OK) return rc;
     }
+    const int cell_order = (flags & NBODY_TREE_ORDER2) ? 2 : 0;
     if (!(flags & NBODY_ACC_VALID)) {
-        const int rc = tree_accel(pm, n, prec, G, eps, theta, leaf, acc, s);
+        const int rc = tree_accel(pm, n, prec, G, eps, theta, leaf, cell_order, acc, s);
         if (rc != NBODY_OK) return rc;
     }
     hipError_t e = launch_step(prec, pm, vel, acc, n, h, dt, false, nsteps > 0, ep, &eb, s);
@@ -680,7 +856,7 @@ int tree_leapfrog(void *pm, void *vel, void *acc, int32_t *order, int n, int pre
             const int rc = reorder(pm, vel, acc, order, n, leaf, s);
             if (rc != NBODY_OK) return rc;
         }
-        const int rc = tree_accel(pm, n, prec, G, eps, theta, leaf, acc, s);
+        const int rc = tree_accel(pm, n, prec, G, eps, theta, leaf, cell_order, acc, s);
         if (rc != NBODY_OK) return rc;
         const bool last = (k == nsteps - 1);
         e = launch_step(prec, pm, vel, acc, n, h, dt, true, !last, ep, &eb, s);
