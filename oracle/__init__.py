@@ -88,10 +88,12 @@ def _load():
         lib.oracle_tree_accel.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _d, _d, ctypes.c_double,
                                           ctypes.c_double, ctypes.c_double, ctypes.c_int64, _i64, _d, _d]
         lib.oracle_tree_accel.restype = ctypes.c_int
-        lib.oracle_tree_accel_order.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _d, _d,
+        lib.oracle_tree_accel_cells.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _d, _d,
                                                 ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                                 ctypes.c_int32, ctypes.c_int64, _i64, _d, _d]
-        lib.oracle_tree_accel_order.restype = ctypes.c_int
+        lib.oracle_tree_accel_cells.restype = ctypes.c_int
+        lib.oracle_tree_quad.argtypes = [ctypes.c_int64, ctypes.c_int32, _d, _d, _d]
+        lib.oracle_tree_quad.restype = ctypes.c_int
         lib.oracle_tree_pseudo.argtypes = [ctypes.c_int64, ctypes.c_int32, _d, _d, _d]
         lib.oracle_tree_pseudo.restype = ctypes.c_int
         lib.oracle_pseudo_dirs.argtypes = [_d]
@@ -326,12 +328,12 @@ def tree_lists(pos_mass_orb, leaf: int, group: int, theta: float):
 
 
 def tree_accel(pos_mass_orb, leaf: int, group: int, theta: float, eps: float, G: float = 1.0, targets=None,
-               order: int = 0):
+               cells: int = 0):
     """Tree-code force and potential (Section IV.A) on the ORB cells: far
-    cells as monopoles (order 0) or as their 12 pseudo-particles (order 2,
-    the pseudo-particle multipole method of the paper's reference [20]), near
-    leaves body by body.  Returns (acc (T, 3), pot (T,)) for ORB positions
-    ``targets`` (all when None)."""
+    cells as monopoles (cells 0), as their 12 pseudo-particles (2, the
+    pseudo-particle multipole method of the paper's reference [20]) or through
+    their quadrupole expansion (3); near leaves body by body.  Returns
+    (acc (T, 3), pot (T,)) for ORB positions ``targets`` (all when None)."""
     lib = _load()
     x, m = _split(pos_mass_orb)
     n = x.shape[0]
@@ -344,11 +346,11 @@ def tree_accel(pos_mass_orb, leaf: int, group: int, theta: float, eps: float, G:
         nt = tp.shape[0]
     acc = np.empty((nt, 3))
     pot = np.empty(nt)
-    rc = lib.oracle_tree_accel_order(n, int(leaf), int(group), _ptr(x, _d), _ptr(m, _d), float(G), float(eps),
-                                     float(theta), int(order), nt, None if tp is None else _ptr(tp, _i64),
+    rc = lib.oracle_tree_accel_cells(n, int(leaf), int(group), _ptr(x, _d), _ptr(m, _d), float(G), float(eps),
+                                     float(theta), int(cells), nt, None if tp is None else _ptr(tp, _i64),
                                      _ptr(acc, _d), _ptr(pot, _d))
     if rc != 0:
-        raise ValueError("oracle_tree_accel_order failed")
+        raise ValueError("oracle_tree_accel_cells failed")
     return acc, pot
 
 
@@ -371,4 +373,17 @@ def tree_pseudo(pos_mass_orb, leaf: int) -> np.ndarray:
     out = np.empty((nn, 12, 4))
     if lib.oracle_tree_pseudo(n, int(leaf), _ptr(x, _d), _ptr(m, _d), _ptr(out, _d)) != 0:
         raise ValueError("oracle_tree_pseudo: bad arguments")
+    return out
+
+
+def tree_quad(pos_mass_orb, leaf: int) -> np.ndarray:
+    """Traceless quadrupole (Qxx, Qyy, Qzz, Qxy, Qxz, Qyz) of every node about
+    its centre of mass, (nn, 6), summed over the cell's bodies."""
+    lib = _load()
+    x, m = _split(pos_mass_orb)
+    n = x.shape[0]
+    nn = tree_nodes(n, leaf).shape[0]
+    out = np.empty((nn, 6))
+    if lib.oracle_tree_quad(n, int(leaf), _ptr(x, _d), _ptr(m, _d), _ptr(out, _d)) != 0:
+        raise ValueError("oracle_tree_quad: bad arguments")
     return out

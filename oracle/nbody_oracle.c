@@ -50,13 +50,14 @@
  *                    IV.B ORB recursion: node table, moments, interaction
  *                    lists and the resulting force; the readings are stated
  *                    above those functions.
- *   oracle_tree_pseudo, oracle_tree_accel_order
- *                    Higher-order cells by the pseudo-particle multipole
+ *   oracle_tree_pseudo, oracle_tree_quad, oracle_tree_accel_cells
+ *                    Higher-order cells, after the pseudo-particle multipole
  *                    method of Makino (1999), the paper's reference [20],
  *                    which Section VI names as the way past monopole cells:
- *                    each cell's expansion to quadrupole order is carried by
- *                    12 point masses, computed from the cell's bodies by
- *                    that method's formula.
+ *                    each cell's expansion to quadrupole order is carried
+ *                    either by 12 point masses from that method's formula,
+ *                    or by the cell's traceless quadrupole tensor with the
+ *                    expansion evaluated directly.
  *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared (no fast-math;
  * contraction off so that every product and sum rounds as written).
@@ -908,28 +909,80 @@ int oracle_tree_pseudo(int64_t n, int32_t leaf, const double *x, const double *m
     return 0;
 }
 
+/* ---------------------------------------------------------------------------
+ * Quadrupole cells evaluated directly.  The same expansion through l = 2,
+ * written with the traceless quadrupole tensor of the cell about its centre
+ * of mass,
+ *   Q = sum_i m_i (3 r_i r_i^T - |r_i|^2 I),   r_i = x_i - com,
+ * is, at a target at offset d = x - com,
+ *   phi = -G (M / s + d.Q.d / (2 s^5)),
+ *   a   =  G (-M d / s^3 + Q d / s^5 - 5 (d.Q.d) d / (2 s^7)),
+ * a = -grad phi, with the softened distance s^2 = |d|^2 + eps^2 in place of
+ * |d| (this library's reading: the expansion of the softened monopole law,
+ * differentiated as written).  Q is summed over the cell's bodies in position
+ * order, Neumaier-compensated.
+ * ------------------------------------------------------------------------- */
+static void tree_quad_fill(const tree_data *d, const double *x, const double *m, double *out)
+{
+    int64_t c;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (c = 0; c < d->nn; ++c) {
+        const double *cm = d->com + 3 * c;
+        nsum q[6] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}, {0, 0}, {0, 0}};
+        for (int64_t i = d->nodes[4 * c]; i < d->nodes[4 * c + 1]; ++i) {
+            const double r[3] = {x[3 * i] - cm[0], x[3 * i + 1] - cm[1], x[3 * i + 2] - cm[2]};
+            const double r2 = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2];
+            nsum_add(&q[0], m[i] * (3.0 * r[0] * r[0] - r2));
+            nsum_add(&q[1], m[i] * (3.0 * r[1] * r[1] - r2));
+            nsum_add(&q[2], m[i] * (3.0 * r[2] * r[2] - r2));
+            nsum_add(&q[3], m[i] * (3.0 * r[0] * r[1]));
+            nsum_add(&q[4], m[i] * (3.0 * r[0] * r[2]));
+            nsum_add(&q[5], m[i] * (3.0 * r[1] * r[2]));
+        }
+        for (int k = 0; k < 6; ++k)
+            out[6 * c + k] = nsum_val(&q[k]);
+    }
+}
+
+/* Traceless quadrupole of every node (ORB positions): out [nn][6] =
+ * (Qxx, Qyy, Qzz, Qxy, Qxz, Qyz).  Returns 0, or -1 on bad arguments. */
+int oracle_tree_quad(int64_t n, int32_t leaf, const double *x, const double *m, double *out)
+{
+    tree_data d;
+    if (tree_setup(n, leaf, leaf, x, m, &d) != 0)
+        return -1;
+    tree_quad_fill(&d, x, m, out);
+    tree_free(&d);
+    return 0;
+}
+
 /* Tree force and potential on targets (ORB positions; NULL = all n).
- * acc: [ntarg][3], pot: [ntarg].  order 0: an accepted cell acts as one body
- * (M at com); order 2: as its 12 pseudo-particles.  Neumaier-compensated
- * FP64 sums over the far cells in list order (pseudo-particles j = 0..11
- * within a cell), then the near bodies in list order. */
-int oracle_tree_accel_order(int64_t n, int32_t leaf, int32_t group, const double *x, const double *m,
-                            double G, double eps, double theta, int32_t order, int64_t ntarg,
+ * acc: [ntarg][3], pot: [ntarg].  cells 0: an accepted cell acts as one body
+ * (M at com); 2: as its 12 pseudo-particles; 3: through its quadrupole
+ * expansion (above).  Neumaier-compensated FP64 sums over the far cells in
+ * list order (pseudo-particles j = 0..11 within a cell), then the near
+ * bodies in list order. */
+int oracle_tree_accel_cells(int64_t n, int32_t leaf, int32_t group, const double *x, const double *m,
+                            double G, double eps, double theta, int32_t cells, int64_t ntarg,
                             const int64_t *targets, double *acc, double *pot)
 {
-    if (!(theta >= 0.0) || (order != 0 && order != 2))
+    if (!(theta >= 0.0) || (cells != 0 && cells != 2 && cells != 3))
         return -1;
     tree_data d;
     if (tree_setup(n, leaf, group, x, m, &d) != 0)
         return -1;
     double *pp = NULL;
-    if (order == 2) {
-        pp = (double *)malloc((size_t)d.nn * PSEUDO_K * 4 * sizeof(double));
+    if (cells == 2 || cells == 3) {
+        const size_t per = cells == 2 ? PSEUDO_K * 4 : 6;
+        pp = (double *)malloc((size_t)d.nn * per * sizeof(double));
         if (!pp) {
             tree_free(&d);
             return -1;
         }
-        tree_pseudo_fill(&d, x, m, pp);
+        if (cells == 2)
+            tree_pseudo_fill(&d, x, m, pp);
+        else
+            tree_quad_fill(&d, x, m, pp);
     }
     tree_ctx tc = {d.nodes, d.com, d.lo, d.hi, d.diag2, theta * theta};
     /* group of every position */
@@ -965,10 +1018,32 @@ int oracle_tree_accel_order(int64_t n, int32_t leaf, int32_t group, const double
         nsum ax = {0, 0}, ay = {0, 0}, az = {0, 0}, ph = {0, 0};
         for (int64_t q = 0; q < nf + nnr; ++q) {
             const int64_t c = q < nf ? far[q] : near[q - nf];
+            if (q < nf && cells == 3) {
+                /* quadrupole cell, d = x - com */
+                const double *cm = d.com + 3 * c, *Q = pp + 6 * c;
+                const double M = d.mass[c];
+                const double dv[3] = {xi - cm[0], yi - cm[1], zi - cm[2]};
+                const double s2 = ((dv[0] * dv[0] + dv[1] * dv[1]) + dv[2] * dv[2]) + eps2;
+                const double s = sqrt(s2);
+                const double qd[3] = {(Q[0] * dv[0] + Q[3] * dv[1]) + Q[4] * dv[2],
+                                      (Q[3] * dv[0] + Q[1] * dv[1]) + Q[5] * dv[2],
+                                      (Q[4] * dv[0] + Q[5] * dv[1]) + Q[2] * dv[2]};
+                const double dqd = (dv[0] * qd[0] + dv[1] * qd[1]) + dv[2] * qd[2];
+                const double s3 = s2 * s, s5 = s3 * s2, s7 = s5 * s2;
+                for (int k = 0; k < 3; ++k) {
+                    nsum *ak = k == 0 ? &ax : (k == 1 ? &ay : &az);
+                    nsum_add(ak, -M * dv[k] / s3);
+                    nsum_add(ak, qd[k] / s5);
+                    nsum_add(ak, -2.5 * dqd * dv[k] / s7);
+                }
+                nsum_add(&ph, M / s);
+                nsum_add(&ph, 0.5 * dqd / s5);
+                continue;
+            }
             int64_t jb, je;
             if (q < nf) {
                 jb = 0;
-                je = order == 0 ? 1 : PSEUDO_K;
+                je = cells == 0 ? 1 : PSEUDO_K;
             } else {
                 jb = d.nodes[4 * c];
                 je = d.nodes[4 * c + 1];
@@ -981,7 +1056,7 @@ int oracle_tree_accel_order(int64_t n, int32_t leaf, int32_t group, const double
                         continue;
                     xj = x + 3 * j;
                     mj = m[j];
-                } else if (order == 0) {
+                } else if (cells == 0) {
                     xj = d.com + 3 * c;
                     mj = d.mass[c];
                 } else {
@@ -1017,12 +1092,12 @@ int oracle_tree_accel_order(int64_t n, int32_t leaf, int32_t group, const double
     return bad ? -1 : 0;
 }
 
-/* The monopole tree force (order 0 of the above). */
+/* The monopole tree force (cells 0 of the above). */
 int oracle_tree_accel(int64_t n, int32_t leaf, int32_t group, const double *x, const double *m, double G,
                       double eps, double theta, int64_t ntarg, const int64_t *targets, double *acc,
                       double *pot)
 {
-    return oracle_tree_accel_order(n, leaf, group, x, m, G, eps, theta, 0, ntarg, targets, acc, pot);
+    return oracle_tree_accel_cells(n, leaf, group, x, m, G, eps, theta, 0, ntarg, targets, acc, pot);
 }
 
 /* ---------------------------------------------------------------------------

@@ -136,7 +136,7 @@ def test_far_field_error_orders(orc):
 def test_theta_zero_is_the_direct_sum(orc):
     pm, _ = ics.plummer(700, 42)
     q = _orb(orc, pm, 4).astype(np.float64)
-    a, p = orc.tree_accel(q, 4, 64, 0.0, 0.01, order=2)
+    a, p = orc.tree_accel(q, 4, 64, 0.0, 0.01, cells=2)
     ra, rp = orc.accel(q, 0.01)
     np.testing.assert_allclose(a, ra, rtol=1e-12, atol=1e-12 * np.abs(ra).max())
     np.testing.assert_allclose(p, rp, rtol=1e-12)
@@ -154,7 +154,7 @@ def test_tree_force_beats_the_monopole_tree(orc):
     for theta in (0.5, 0.7, 1.0):
         err = {}
         for order in (0, 2):
-            a, p = orc.tree_accel(q, 4, 64, theta, 0.01, order=order)
+            a, p = orc.tree_accel(q, 4, 64, theta, 0.01, cells=order)
             err[order] = np.sqrt(np.mean((np.linalg.norm(a - ra, axis=1) / np.linalg.norm(ra, axis=1)) ** 2))
         print("theta", theta, "rms force error monopole", err[0], "pseudo-particles", err[2])
         assert err[2] < err[0] / 2
@@ -188,4 +188,4 @@ def test_massless_and_point_cells(orc):
 def test_order_is_validated(orc):
     pm, _ = ics.plummer(100, 44)
     with pytest.raises(ValueError):
-        orc.tree_accel(_orb(orc, pm, 4), 4, 64, 0.5, 0.01, order=1)
+        orc.tree_accel(_orb(orc, pm, 4), 4, 64, 0.5, 0.01, cells=1)
