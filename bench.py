@@ -42,6 +42,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (AMD), packed FP32 counted
 FLOP_PER_PAIR = 20
+FLOP_PER_QUAD_CELL = 54   # one quadrupole cell against one target, counted like the pair's 20
 
 
 def log(msg):
@@ -471,15 +472,18 @@ def tree_leg(torch, nb, pm_np, eps, direct_ms, leaf=4):
     nn = nodes.shape[0]
     pseudo = torch.empty((nn, nb.TREE_PSEUDO, 4), dtype=torch.float32, device=dev)
     stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
-    res["order2"] = {}
+    quad = torch.empty((nn, 3, 4), dtype=torch.float32, device=dev)
+    res["pseudo_cells"], res["quadrupole_cells"] = {}, {}
 
-    def moments_only(order):
-        # order 0: monopole moments; order 2: also second moments and
-        # pseudo-particles (plus their export copy, ~0.02 ms at 2^20)
-        if order == 0:
+    def moments_only(cells):
+        # monopole moments; for the other models also the second moments and
+        # the cells' records (plus their export copy, <= 0.02 ms at 2^20)
+        if cells == nb.CELLS_MONOPOLE:
             return L.nbody_tree_moments(ctypes.c_void_p(q.data_ptr()), n, leaf, None, None, stream)
-        return L.nbody_tree_pseudo(ctypes.c_void_p(q.data_ptr()), n, leaf, ctypes.c_void_p(pseudo.data_ptr()),
-                                   stream)
+        if cells == nb.CELLS_PSEUDO:
+            return L.nbody_tree_pseudo(ctypes.c_void_p(q.data_ptr()), n, leaf,
+                                       ctypes.c_void_p(pseudo.data_ptr()), stream)
+        return L.nbody_tree_quad(ctypes.c_void_p(q.data_ptr()), n, leaf, ctypes.c_void_p(quad.data_ptr()), stream)
 
     for theta in (0.5, 0.7, 1.0):
         fc, ncnt, _, _ = nb.tree_lists(q, theta, leaf)
@@ -489,15 +493,19 @@ def tree_leg(torch, nb, pm_np, eps, direct_ms, leaf=4):
         fc, ncnt, ni = fc.cpu().numpy(), ncnt.cpu().numpy(), ni.cpu().numpy()
         sizes = nodes[:, 1] - nodes[:, 0]
         near_bodies = np.array([sizes[ni[g, :ncnt[g]]].sum() for g in range(len(groups))], dtype=np.float64)
-        for order in (0, 2):
-            per_cell = 1 if order == 0 else nb.TREE_PSEUDO
+        for order in (nb.CELLS_MONOPOLE, nb.CELLS_PSEUDO, nb.CELLS_QUADRUPOLE):
+            per_cell = nb.TREE_PSEUDO if order == nb.CELLS_PSEUDO else 1
             pairs = float((gsz * (per_cell * fc + near_bodies) + gsz * (gsz - 1)).sum())
-            nb.tree_accel(q, eps, theta, leaf, prec=nb.F32_F64ACC, out=out, cell_order=order)
+            # walk flops: 20 per body or pseudo-body pair, 54 per quadrupole cell
+            flops = FLOP_PER_PAIR * pairs
+            if order == nb.CELLS_QUADRUPOLE:
+                flops += (FLOP_PER_QUAD_CELL - FLOP_PER_PAIR) * float((gsz * fc).sum())
+            nb.tree_accel(q, eps, theta, leaf, prec=nb.F32_F64ACC, out=out, cells=order)
             torch.cuda.synchronize()
             ts, tm = [], []
             for _ in range(reps):
                 e0.record()
-                nb.tree_accel(q, eps, theta, leaf, prec=nb.F32_F64ACC, out=out, cell_order=order)
+                nb.tree_accel(q, eps, theta, leaf, prec=nb.F32_F64ACC, out=out, cells=order)
                 e1.record()
                 torch.cuda.synchronize()
                 ts.append(e0.elapsed_time(e1))
@@ -512,8 +520,9 @@ def tree_leg(torch, nb, pm_np, eps, direct_ms, leaf=4):
             t_walk = t - t_mom
             got = out.cpu().double().numpy()
             rel = np.linalg.norm(got[:, :3] - d_host[:, :3], axis=1) / np.linalg.norm(d_host[:, :3], axis=1)
-            walk_tflops = FLOP_PER_PAIR * pairs / (t_walk * 1e-3) / 1e12
-            kern = "k_tree_walk<F64ACC>" if order == 0 else "k_tree_walk<F64ACC, pseudo-particles>"
+            walk_tflops = flops / (t_walk * 1e-3) / 1e12
+            kern = {0: "k_tree_walk<F64ACC>", 2: "k_tree_walk<F64ACC, pseudo-particle cells>",
+                    3: "k_tree_walk<F64ACC, quadrupole cells>"}[order]
             r = {"ms": round(t, 4), "ms_std": round(float(np.std(ts)), 4), "moments_ms": round(t_mom, 4),
                  "walk_force_ms": round(t_walk, 4), "interactions_per_body": round(pairs / n, 1),
                  "far_cells_per_group": round(float(fc.mean()), 1),
@@ -524,9 +533,10 @@ def tree_leg(torch, nb, pm_np, eps, direct_ms, leaf=4):
                  "max_rel_err_vs_direct": float(rel.max()),
                  "walk_roofline": {"bound": "alu", "achieved": round(walk_tflops, 3), "peak": PEAK_FP32_TFLOPS,
                                    "unit": "TFLOP/s", "frac": round(walk_tflops / PEAK_FP32_TFLOPS, 4),
-                                   "kernel": kern, "flop_per_pair": FLOP_PER_PAIR}}
-            (res["theta"] if order == 0 else res["order2"])[str(theta)] = r
-            log(f"[bench] tree order {order} theta {theta}: {t:.3f} ms ({t_mom:.3f} moments), "
+                                   "kernel": kern, "flop_per_pair": FLOP_PER_PAIR,
+                                   "flop_per_quadrupole_cell": FLOP_PER_QUAD_CELL}}
+            {0: res["theta"], 2: res["pseudo_cells"], 3: res["quadrupole_cells"]}[order][str(theta)] = r
+            log(f"[bench] tree cells {order} theta {theta}: {t:.3f} ms ({t_mom:.3f} moments), "
                 f"{pairs / n:.0f} interactions/body, {walk_tflops:.1f} TFLOP/s in the walk, "
                 f"x{direct_ms / t:.1f} vs direct, rms err {r['rms_rel_err_vs_direct']:.2e}")
     return res

@@ -242,19 +242,27 @@ int nbody_trajectory_adjoint(const void *ckpt, int64_t n, int32_t prec, double G
  * definitions.
  * 1 <= leaf <= NBODY_TREE_GROUP.  The first call for a new (n, leaf)
  * uploads the node table and synchronizes the stream; later calls are
- * asynchronous.  The tree tables are library scratch (about 380 bytes per
+ * asynchronous.  The tree tables are library scratch (about 430 bytes per
  * node) shared by all tree calls on a device: overlapping calls race.
  *
- * Order 2 (pseudo-particle multipoles: Makino 1999, the paper's reference
- * [20], named in Section VI as the step past monopole cells): an accepted
- * cell acts instead as NBODY_TREE_PSEUDO point masses q_j at com + a s_j,
- * whose multipole expansion about com equals the cell's through the
- * quadrupole term.  s_j: the unit vertices of the icosahedron, (0, u, v g),
- * (u, v g, 0), (u g, 0, v) over sqrt(1 + g^2), g the golden ratio, (u, v) =
- * (+,+), (+,-), (-,+), (-,-), j = 0..11 in that order; a = sqrt(diag2) / 2;
- * q_j = M/12 + 5/(24 a^2) (3 s_j.S.s_j - trace S), S = sum m r r^T over the
- * cell's bodies, r = x - com, in FP64 (q_j = M/12 when a = 0).  The
- * acceptance test and the interaction lists are those of order 0.
+ * Cell models (the acceptance test and the interaction lists are the same
+ * for all three):
+ * NBODY_CELLS_MONOPOLE: an accepted cell acts as one body (above).
+ * NBODY_CELLS_PSEUDO (order 2 by pseudo-particle multipoles: Makino 1999,
+ *   the paper's reference [20], named in Section VI as the step past
+ *   monopole cells): the cell acts as NBODY_TREE_PSEUDO point masses q_j at
+ *   com + a s_j whose multipole expansion about com equals the cell's
+ *   through the quadrupole term.  s_j: the unit vertices of the icosahedron,
+ *   (0, u, v g), (u, v g, 0), (u g, 0, v) over sqrt(1 + g^2), g the golden
+ *   ratio, (u, v) = (+,+), (+,-), (-,+), (-,-), j = 0..11 in that order;
+ *   a = sqrt(diag2) / 2; q_j = M/12 + 5/(24 a^2) (3 s_j.S.s_j - trace S),
+ *   S = sum m r r^T over the cell's bodies, r = x - com, in FP64
+ *   (q_j = M/12 when a = 0).
+ * NBODY_CELLS_QUADRUPOLE: the same expansion through l = 2 evaluated
+ *   directly: with Q = 3 S - trace(S) I (FP64, rounded to FP32), d = x - com
+ *   and s^2 = |d|^2 + eps^2, phi = -G (M/s + d.Q.d / (2 s^5)) and
+ *   a = G (-M d/s^3 + Q d/s^5 - 5 (d.Q.d) d / (2 s^7)).  The same accuracy
+ *   as the pseudo-particles for a fraction of the work.
  *
  * nbody_tree_shape (host only): node and group counts; nodes_out, if not
  *   NULL, receives int32[num_nodes][4] = (begin, end, left, right), -1
@@ -263,12 +271,13 @@ int nbody_trajectory_adjoint(const void *ckpt, int64_t n, int32_t prec, double G
  *   prec: NBODY_F32, NBODY_F32_KAHAN or NBODY_F32_F64ACC (how the partial
  *   sums of each batch of cells or ranges are folded); NBODY_F64 is
  *   unsupported.  eps >= 0, theta >= 0 finite.
- * nbody_tree_accel_order: the same with the cell order, 0 (monopole, as
- *   nbody_tree_accel) or 2 (pseudo-particles); other orders are
- *   NBODY_E_INVAL.
+ * nbody_tree_accel_cells: the same with a cell model, NBODY_CELLS_*; other
+ *   values are NBODY_E_INVAL.
  * nbody_tree_pseudo (inspection): pseudo_out = float4[num_nodes][12] =
  *   (x, y, z, q) of every node's pseudo-particles (positions and masses
  *   rounded to FP32).
+ * nbody_tree_quad (inspection): quad_out = float4[num_nodes][3] =
+ *   (com, M), (Qxx, Qyy, Qzz, Qxy), (Qxz, Qyz, 0, 0) in FP32.
  * nbody_tree_moments (inspection): moments_out double[num_nodes][5] =
  *   (M, com_x, com_y, com_z, diag2), box_out float[num_nodes][6] =
  *   (lo_x, lo_y, lo_z, hi_x, hi_y, hi_z); either may be NULL.
@@ -289,21 +298,27 @@ int nbody_trajectory_adjoint(const void *ckpt, int64_t n, int32_t prec, double G
  * that it keeps naming the caller's index of the body at position p;
  * K = 0 never re-orders (order may be NULL).  flags: NBODY_ACC_VALID,
  * NBODY_ENERGY (energy_out as for nbody_leapfrog_kdk, with the tree
- * potential), NBODY_TREE_ORDER2 (order-2 cells).  Re-ordering uses library
- * scratch of about 24 bytes per body.
+ * potential), NBODY_TREE_PSEUDO_CELLS or NBODY_TREE_QUAD_CELLS (the cell
+ * model; monopole without either, both together are NBODY_E_INVAL).
+ * Re-ordering uses library scratch of about 24 bytes per body.
  */
 #define NBODY_TREE_GROUP 64
 #define NBODY_TREE_PSEUDO 12
-#define NBODY_TREE_ORDER2 0x8u /* nbody_tree_leapfrog: pseudo-particle cells */
+#define NBODY_CELLS_MONOPOLE 0
+#define NBODY_CELLS_PSEUDO 2
+#define NBODY_CELLS_QUADRUPOLE 3
+#define NBODY_TREE_PSEUDO_CELLS 0x8u /* nbody_tree_leapfrog flags */
+#define NBODY_TREE_QUAD_CELLS 0x20u
 int nbody_tree_shape(int64_t n, int32_t leaf, int64_t *num_nodes, int64_t *num_groups,
                      int32_t *nodes_out);
 int nbody_tree_accel(const void *pos_mass, int64_t n, int32_t prec, double G, double eps,
                      double theta, int32_t leaf, void *acc_pot_out, void *stream);
-int nbody_tree_accel_order(const void *pos_mass, int64_t n, int32_t prec, double G, double eps,
-                           double theta, int32_t leaf, int32_t order, void *acc_pot_out,
+int nbody_tree_accel_cells(const void *pos_mass, int64_t n, int32_t prec, double G, double eps,
+                           double theta, int32_t leaf, int32_t cells, void *acc_pot_out,
                            void *stream);
 int nbody_tree_pseudo(const void *pos_mass, int64_t n, int32_t leaf, void *pseudo_out,
                       void *stream);
+int nbody_tree_quad(const void *pos_mass, int64_t n, int32_t leaf, void *quad_out, void *stream);
 int nbody_tree_moments(const void *pos_mass, int64_t n, int32_t leaf, double *moments_out,
                        float *box_out, void *stream);
 int nbody_tree_lists(const void *pos_mass, int64_t n, int32_t leaf, double theta,

@@ -25,8 +25,8 @@ __all__ = [
     "lib", "accel", "accel_vjp", "leapfrog_kdk", "kick_drift", "batched_accel", "energy", "orb_order",
     "permute", "trajectory_forward", "trajectory_adjoint", "NBodyTrajectory", "autotune",
     "set_tuning", "get_tuning", "release", "NBodyError", "TREE_GROUP", "tree_shape", "tree_accel",
-    "tree_moments", "tree_lists", "tree_leapfrog", "tree_pseudo", "TREE_PSEUDO", "TREE_ORDER2",
-    "janus_forward", "janus_adjoint",
+    "tree_moments", "tree_lists", "tree_leapfrog", "tree_pseudo", "tree_quad", "TREE_PSEUDO",
+    "CELLS_MONOPOLE", "CELLS_PSEUDO", "CELLS_QUADRUPOLE", "janus_forward", "janus_adjoint",
 ]
 
 F64, F32, F32_KAHAN, F32_F64ACC = 0, 1, 2, 3
@@ -34,8 +34,9 @@ ADJ_RECOMPUTE, ADJ_REVERSE, ADJ_PHI = 0, 1, 0x10
 ACC_VALID, GRAPH, ENERGY = 0x1, 0x2, 0x4
 KERNEL_ACCEL, KERNEL_BATCHED, KERNEL_VJP = 0, 1, 2
 TREE_GROUP = 64
-TREE_PSEUDO = 12      # pseudo-particles per cell at order 2
-TREE_ORDER2 = 0x8     # tree leapfrog flag: order-2 cells
+TREE_PSEUDO = 12      # pseudo-particles per cell (CELLS_PSEUDO)
+CELLS_MONOPOLE, CELLS_PSEUDO, CELLS_QUADRUPOLE = 0, 2, 3   # tree cell models
+_TREE_CELL_FLAGS = {CELLS_MONOPOLE: 0, CELLS_PSEUDO: 0x8, CELLS_QUADRUPOLE: 0x20}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libnbody.so")
@@ -62,8 +63,9 @@ _SIGS = {
                                  _vp, _vp, _i32, _vp],
     "nbody_tree_shape": [_i64, _i32, _vp, _vp, _vp],
     "nbody_tree_accel": [_vp, _i64, _i32, _dbl, _dbl, _dbl, _i32, _vp, _vp],
-    "nbody_tree_accel_order": [_vp, _i64, _i32, _dbl, _dbl, _dbl, _i32, _i32, _vp, _vp],
+    "nbody_tree_accel_cells": [_vp, _i64, _i32, _dbl, _dbl, _dbl, _i32, _i32, _vp, _vp],
     "nbody_tree_pseudo": [_vp, _i64, _i32, _vp, _vp],
+    "nbody_tree_quad": [_vp, _i64, _i32, _vp, _vp],
     "nbody_tree_moments": [_vp, _i64, _i32, _vp, _vp, _vp],
     "nbody_tree_lists": [_vp, _i64, _i32, _dbl, _i32, _i32, _vp, _vp, _vp, _vp, _vp],
     "nbody_tree_leapfrog": [_vp, _vp, _vp, _vp, _i64, _i32, _dbl, _dbl, _dbl, _i32, _dbl, _i32, _i32,
@@ -287,10 +289,10 @@ def tree_shape(n, leaf, nodes=False):
     return nn.value, ng.value, tab
 
 
-def tree_accel(pos_mass, eps, theta, leaf=4, G=1.0, prec=None, out=None, cell_order=0):
+def tree_accel(pos_mass, eps, theta, leaf=4, G=1.0, prec=None, out=None, cells=CELLS_MONOPOLE):
     """Tree-code force and potential (ax, ay, az, phi) per body, ORB order.
-    cell_order 0: accepted cells as monopoles; 2: as their 12
-    pseudo-particles (quadrupole order)."""
+    cells: CELLS_MONOPOLE (accepted cells as one body), CELLS_PSEUDO (as their
+    12 pseudo-particles) or CELLS_QUADRUPOLE (their quadrupole expansion)."""
     pm = _rec(pos_mass, "pos_mass", torch.float32)
     p = _prec(pm, prec)
     if out is None:
@@ -299,8 +301,8 @@ def tree_accel(pos_mass, eps, theta, leaf=4, G=1.0, prec=None, out=None, cell_or
         _rec(out, "out", torch.float32)
         if out.shape != pm.shape:
             raise ValueError("out must match pos_mass")
-    _check(lib().nbody_tree_accel_order(_ptr(pm), pm.shape[0], p, float(G), float(eps), float(theta),
-                                        int(leaf), int(cell_order), _ptr(out), _stream()))
+    _check(lib().nbody_tree_accel_cells(_ptr(pm), pm.shape[0], p, float(G), float(eps), float(theta),
+                                        int(leaf), int(cells), _ptr(out), _stream()))
     return out
 
 
@@ -311,6 +313,16 @@ def tree_pseudo(pos_mass, leaf=4):
     nn, _ = tree_shape(pm.shape[0], leaf)
     out = torch.empty((nn, TREE_PSEUDO, 4), dtype=torch.float32, device=pm.device)
     _check(lib().nbody_tree_pseudo(_ptr(pm), pm.shape[0], int(leaf), _ptr(out), _stream()))
+    return out
+
+
+def tree_quad(pos_mass, leaf=4):
+    """Quadrupole records of every node, (num_nodes, 3, 4) float32 =
+    (com, M), (Qxx, Qyy, Qzz, Qxy), (Qxz, Qyz, 0, 0), for ORB-ordered records."""
+    pm = _rec(pos_mass, "pos_mass", torch.float32)
+    nn, _ = tree_shape(pm.shape[0], leaf)
+    out = torch.empty((nn, 3, 4), dtype=torch.float32, device=pm.device)
+    _check(lib().nbody_tree_quad(_ptr(pm), pm.shape[0], int(leaf), _ptr(out), _stream()))
     return out
 
 
@@ -343,11 +355,11 @@ def tree_lists(pos_mass, theta, leaf=4, max_far=None, max_near=None):
 
 
 def tree_leapfrog(pos_mass, vel, acc, eps, theta, dt, nsteps, leaf=4, reorder_every=0, order=None,
-                  acc_valid=False, energy=False, G=1.0, prec=None, cell_order=0):
+                  acc_valid=False, energy=False, G=1.0, prec=None, cells=CELLS_MONOPOLE):
     """Kick-drift-kick steps with tree forces, in place on ORB-ordered
     float32 records.  reorder_every = K > 0 re-orders the state by ORB at
     entry and every K steps and composes ``order`` (int32 (N,), created as
-    the identity when None); cell_order as for tree_accel; returns (order,
+    the identity when None); cells as for tree_accel; returns (order,
     energies (nsteps+1, 2) or None)."""
     pm = _rec(pos_mass, "pos_mass", torch.float32)
     v = _rec(vel, "vel", torch.float32)
@@ -359,9 +371,9 @@ def tree_leapfrog(pos_mass, vel, acc, eps, theta, dt, nsteps, leaf=4, reorder_ev
     if order is not None and (order.dtype != torch.int32 or order.numel() != n or not order.is_contiguous()):
         raise ValueError("order must be a contiguous int32 tensor of N entries")
     en = torch.empty((nsteps + 1, 2), dtype=torch.float64, device=pm.device) if energy else None
-    if cell_order not in (0, 2):
-        raise ValueError("cell_order must be 0 or 2")
-    flags = (ACC_VALID if acc_valid else 0) | (ENERGY if energy else 0) | (TREE_ORDER2 if cell_order == 2 else 0)
+    if cells not in _TREE_CELL_FLAGS:
+        raise ValueError("cells must be CELLS_MONOPOLE, CELLS_PSEUDO or CELLS_QUADRUPOLE")
+    flags = (ACC_VALID if acc_valid else 0) | (ENERGY if energy else 0) | _TREE_CELL_FLAGS[cells]
     _check(lib().nbody_tree_leapfrog(_ptr(pm), _ptr(v), _ptr(a), None if order is None else _ptr(order), n, p,
                                      float(G), float(eps), float(theta), int(leaf), float(dt), int(nsteps),
                                      int(reorder_every), flags, None if en is None else _ptr(en), _stream()))

@@ -119,9 +119,10 @@ int tree_shape(int n, int leaf, int64_t *num_nodes, int64_t *num_groups, int32_t
 int tree_moments(const void *pm, int n, int leaf, double *mom, float *box, hipStream_t s);
 int tree_lists(const void *pm, int n, int leaf, double theta, int max_far, int max_near, int32_t *far_cnt,
                int32_t *near_cnt, int32_t *far_ids, int32_t *near_ids, hipStream_t s);
-int tree_accel(const void *pm, int n, int prec, double G, double eps, double theta, int leaf, int order,
+int tree_accel(const void *pm, int n, int prec, double G, double eps, double theta, int leaf, int cells,
                void *out, hipStream_t s);
 int tree_pseudo(const void *pm, int n, int leaf, void *out, hipStream_t s);
+int tree_quad(const void *pm, int n, int leaf, void *out, hipStream_t s);
 int tree_leapfrog(void *pm, void *vel, void *acc, int32_t *order, int n, int prec, double G, double eps,
                   double theta, int leaf, double dt, int nsteps, int reorder_every, unsigned flags,
                   double *energy, hipStream_t s);

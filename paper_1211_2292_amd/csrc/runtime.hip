@@ -772,15 +772,16 @@ int nbody_tree_shape(int64_t n, int32_t leaf, int64_t *num_nodes, int64_t *num_g
 int nbody_tree_accel(const void *pos_mass, int64_t n, int32_t prec, double G, double eps, double theta,
                      int32_t leaf, void *acc_pot_out, void *stream)
 {
-    return nbody_tree_accel_order(pos_mass, n, prec, G, eps, theta, leaf, 0, acc_pot_out, stream);
+    return nbody_tree_accel_cells(pos_mass, n, prec, G, eps, theta, leaf, NBODY_CELLS_MONOPOLE, acc_pot_out,
+                                  stream);
 }
 
-int nbody_tree_accel_order(const void *pos_mass, int64_t n, int32_t prec, double G, double eps, double theta,
-                           int32_t leaf, int32_t order, void *acc_pot_out, void *stream)
+int nbody_tree_accel_cells(const void *pos_mass, int64_t n, int32_t prec, double G, double eps, double theta,
+                           int32_t leaf, int32_t cells, void *acc_pot_out, void *stream)
 {
     NB_CHECK(check_tree(n, leaf));
-    if (order != 0 && order != 2) {
-        set_error("cell order %d (0 or 2)", order);
+    if (cells != NBODY_CELLS_MONOPOLE && cells != NBODY_CELLS_PSEUDO && cells != NBODY_CELLS_QUADRUPOLE) {
+        set_error("cell model %d (NBODY_CELLS_MONOPOLE, _PSEUDO or _QUADRUPOLE)", cells);
         return NBODY_E_INVAL;
     }
     if (!prec_ok(prec)) {
@@ -795,7 +796,7 @@ int nbody_tree_accel_order(const void *pos_mass, int64_t n, int32_t prec, double
     NB_CHECK(check_theta(theta));
     NB_CHECK(check_vec(pos_mass, prec, "pos_mass"));
     NB_CHECK(check_vec(acc_pot_out, prec, "acc_pot_out"));
-    return tree_accel(pos_mass, (int)n, prec, G, eps, theta, leaf, order, acc_pot_out, (hipStream_t)stream);
+    return tree_accel(pos_mass, (int)n, prec, G, eps, theta, leaf, cells, acc_pot_out, (hipStream_t)stream);
 }
 
 int nbody_tree_pseudo(const void *pos_mass, int64_t n, int32_t leaf, void *pseudo_out, void *stream)
@@ -804,6 +805,14 @@ int nbody_tree_pseudo(const void *pos_mass, int64_t n, int32_t leaf, void *pseud
     NB_CHECK(check_vec(pos_mass, NBODY_F32, "pos_mass"));
     NB_CHECK(check_vec(pseudo_out, NBODY_F32, "pseudo_out"));
     return tree_pseudo(pos_mass, (int)n, leaf, pseudo_out, (hipStream_t)stream);
+}
+
+int nbody_tree_quad(const void *pos_mass, int64_t n, int32_t leaf, void *quad_out, void *stream)
+{
+    NB_CHECK(check_tree(n, leaf));
+    NB_CHECK(check_vec(pos_mass, NBODY_F32, "pos_mass"));
+    NB_CHECK(check_vec(quad_out, NBODY_F32, "quad_out"));
+    return tree_quad(pos_mass, (int)n, leaf, quad_out, (hipStream_t)stream);
 }
 
 int nbody_tree_moments(const void *pos_mass, int64_t n, int32_t leaf, double *moments_out, float *box_out,
@@ -847,8 +856,9 @@ int nbody_tree_leapfrog(void *pos_mass, void *vel, void *acc_pot, int32_t *order
         set_error("the tree code runs the FP32 modes only");
         return NBODY_E_UNSUPPORTED;
     }
-    if (flags & ~(NBODY_ACC_VALID | NBODY_ENERGY | NBODY_TREE_ORDER2)) {
-        set_error("unsupported flags 0x%x (NBODY_ACC_VALID, NBODY_ENERGY, NBODY_TREE_ORDER2 only)", flags);
+    if ((flags & ~(NBODY_ACC_VALID | NBODY_ENERGY | NBODY_TREE_PSEUDO_CELLS | NBODY_TREE_QUAD_CELLS)) ||
+        ((flags & NBODY_TREE_PSEUDO_CELLS) && (flags & NBODY_TREE_QUAD_CELLS))) {
+        set_error("unsupported flags 0x%x (NBODY_ACC_VALID, NBODY_ENERGY and one cell-model flag only)", flags);
         return NBODY_E_INVAL;
     }
     NB_CHECK(check_scalars(G, eps, dt));

@@ -50,6 +50,13 @@
 // (the dipole term vanishes about com); a = 0 leaves q_j = M / 12.  The walk
 // and its acceptance test are unchanged; accepted cell ids are batched in
 // LDS and each cell's 12 records are read with scalar loads.
+//
+// Quadrupole cells: the same expansion through l = 2 evaluated directly from
+// the traceless tensor Q = 3 S - trace(S) I, at offset d = com - x and
+// softened distance s^2 = |d|^2 + eps^2:
+//   potential sum  M / s + d.Q.d / (2 s^5)
+//   acceleration   d (M / s^3 + 5 d.Q.d / (2 s^7)) - Q d / s^5
+// about 35 VALU per cell and target instead of 12 pair evaluations.
 #include <cstdint>
 #include <cstring>
 #include <mutex>
@@ -64,7 +71,9 @@ namespace {
 constexpr int kGroup = 64;     // targets per group: one per lane
 constexpr int kStack = 512;    // LDS stack entries per wave
 constexpr int kBuf = 128;      // LDS batch entries (cells, near ranges)
-constexpr int kPseudo = 12;    // pseudo-particles per cell at order 2
+constexpr int kPseudo = 12;    // pseudo-particles per cell (pseudo-particle cells)
+constexpr int kQuadRec = 3;    // float4 records per cell (quadrupole cells)
+constexpr int kCellsMono = 0, kCellsPseudo = 2, kCellsQuad = 3;
 
 struct TreeDev {
     const int4 *node;    // begin, end, left, right (-1 for a leaf)
@@ -75,7 +84,8 @@ struct TreeDev {
     float4 *rec;         // com (FP32), M (FP32): the pseudo-body record
     float4 *lo, *hi;     // box
     double4 *s2a, *s2b;  // second moment about com: (xx, yy, zz, xy), (xz, yz, -, -)
-    float4 *pp;          // order 2: kPseudo records (x, y, z, q) per node
+    float4 *pp;          // pseudo-particle cells: kPseudo records (x, y, z, q) per node
+    float4 *qr;          // quadrupole cells: (com, M), (Qxx, Qyy, Qzz, Qxy), (Qxz, Qyz, 0, 0)
 };
 
 __device__ __forceinline__ void finish_node(const TreeDev &T, int c, double M, double sx, double sy,
@@ -228,6 +238,21 @@ __global__ __launch_bounds__(256) void k_tree_pseudo(TreeDev T, int nn)
     T.pp[t] = make_float4((float)(cd.x + a * s0), (float)(cd.y + a * s1), (float)(cd.z + a * s2), (float)q);
 }
 
+// Quadrupole records, one thread per node: Q = 3 S - trace(S) I in FP64,
+// rounded to FP32.
+__global__ __launch_bounds__(256) void k_tree_quad(TreeDev T, int nn)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nn) return;
+    const double4 A = T.s2a[c], B = T.s2b[c];
+    const double tr = (A.x + A.y) + A.z;
+    float4 *o = T.qr + (long)kQuadRec * c;
+    o[0] = T.rec[c];
+    o[1] = make_float4((float)(3.0 * A.x - tr), (float)(3.0 * A.y - tr), (float)(3.0 * A.z - tr),
+                       (float)(3.0 * A.w));
+    o[2] = make_float4((float)(3.0 * B.x), (float)(3.0 * B.y), 0.0f, 0.0f);
+}
+
 __device__ __forceinline__ double box_gap(double p, double a, double b)
 {
     return p < a ? a - p : (p > b ? p - b : 0.0);
@@ -275,16 +300,55 @@ __device__ __forceinline__ void sweep_pseudo(const float4 *__restrict__ pp, cons
     }
 }
 
-template <int MODE, bool INSPECT, bool PP>
+// One quadrupole cell against the lane's target: c = (com, M),
+// q1 = (Qxx, Qyy, Qzz, Qxy), q2 = (Qxz, Qyz, -, -).
+__device__ __forceinline__ void quad_f32(const float4 c, const float4 q1, const float4 q2,
+                                         const Targets<float, 1> &T, float eps2, Sums<float, 1> &S)
+{
+    const float dx = c.x - T.x[0];
+    const float dy = c.y - T.y[0];
+    const float dz = c.z - T.z[0];
+    const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    const float ri2 = ri * ri;
+    const float ri3 = ri2 * ri;
+    const float ri5 = ri3 * ri2;
+    const float qx = __builtin_fmaf(q1.x, dx, __builtin_fmaf(q1.w, dy, q2.x * dz));
+    const float qy = __builtin_fmaf(q1.w, dx, __builtin_fmaf(q1.y, dy, q2.y * dz));
+    const float qz = __builtin_fmaf(q2.x, dx, __builtin_fmaf(q2.y, dy, q1.z * dz));
+    const float dqd = __builtin_fmaf(dx, qx, __builtin_fmaf(dy, qy, dz * qz));
+    const float t5 = dqd * ri5;
+    S.ph[0] = __builtin_fmaf(0.5f, t5, __builtin_fmaf(c.w, ri, S.ph[0]));
+    const float k = __builtin_fmaf(2.5f * t5, ri2, c.w * ri3);
+    S.ax[0] = __builtin_fmaf(-qx, ri5, __builtin_fmaf(k, dx, S.ax[0]));
+    S.ay[0] = __builtin_fmaf(-qy, ri5, __builtin_fmaf(k, dy, S.ay[0]));
+    S.az[0] = __builtin_fmaf(-qz, ri5, __builtin_fmaf(k, dz, S.az[0]));
+}
+
+// Sweeps the quadrupole cells of the batched ids (one 48-byte scalar load
+// per cell).
+__device__ __forceinline__ void sweep_quad(const float4 *__restrict__ qr, const int *ids, int cnt,
+                                           const Targets<float, 1> &T, float eps2, Sums<float, 1> &S)
+{
+    for (int r = 0; r < cnt; ++r) {
+        const int c = __builtin_amdgcn_readfirstlane(ids[r]);
+        const float4 *q = qr + (long)kQuadRec * c;
+        const float4 a = q[0], b = q[1], d = q[2];
+        quad_f32(a, b, d, T, eps2, S);
+    }
+}
+
+template <int MODE, bool INSPECT, int CELLS>
 // 7 waves per SIMD: 5 KB of LDS per wave and at most 72 VGPRs (measured
 // faster than 6 waves, and than 8 waves with register spills).
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void k_tree_walk(const float4 *__restrict__ src, int n, TreeDev T,
-                                                  const float4 *__restrict__ pp, float eps2_in, double G,
+                                                  const float4 *__restrict__ cells, float eps2_in, double G,
                                                   double theta2, WalkOut O)
 {
+    constexpr bool kIds = CELLS != kCellsMono;
     __shared__ int stk[kStack];
-    __shared__ float4 cbuf[PP ? 1 : kBuf];  // order 0: the accepted cells' records
-    __shared__ int cid[PP ? kBuf : 1];      // order 2: the accepted cells' ids
+    __shared__ float4 cbuf[kIds ? 1 : kBuf];  // monopole cells: the accepted cells' records
+    __shared__ int cid[kIds ? kBuf : 1];      // other cells: the accepted cells' ids
     __shared__ int2 nbuf[kBuf];
     const int lane = threadIdx.x;
     const int g = blockIdx.x;
@@ -323,8 +387,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void k_
     auto flush_cells = [&]() {
         if constexpr (!INSPECT) {
             S.zero();
-            if constexpr (PP)
-                sweep_pseudo(pp, cid, nf, TT, eps2, S);
+            if constexpr (CELLS == kCellsPseudo)
+                sweep_pseudo(cells, cid, nf, TT, eps2, S);
+            else if constexpr (CELLS == kCellsQuad)
+                sweep_quad(cells, cid, nf, TT, eps2, S);
             else
                 sweep_cells(cbuf, nf, TT, eps2, S);
             R[0].fold(S.ax[0]);
@@ -402,7 +468,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void k_
             }
         } else {
             if (acc) {
-                if constexpr (PP)
+                if constexpr (kIds)
                     cid[nf + (int)lane_rank(ma)] = c;
                 else
                     cbuf[nf + (int)lane_rank(ma)] = T.rec[c];
@@ -579,7 +645,8 @@ int tree_prepare(int n, int leaf, hipStream_t s, TreeDev &out)
     const size_t o_s2a = o_hi + align256(nn * sizeof(float4));
     const size_t o_s2b = o_s2a + align256(nn * sizeof(double4));
     const size_t o_pp = o_s2b + align256(nn * sizeof(double4));
-    const size_t total = o_pp + align256(nn * kPseudo * sizeof(float4));
+    const size_t o_qr = o_pp + align256(nn * kPseudo * sizeof(float4));
+    const size_t total = o_qr + align256(nn * kQuadRec * sizeof(float4));
     if (C.mem) {
         // work already enqueued may still read the old tables
         (void)hipDeviceSynchronize();
@@ -605,6 +672,7 @@ int tree_prepare(int n, int leaf, hipStream_t s, TreeDev &out)
     d.s2a = (double4 *)(base + o_s2a);
     d.s2b = (double4 *)(base + o_s2b);
     d.pp = (float4 *)(base + o_pp);
+    d.qr = (float4 *)(base + o_qr);
     // pageable copies complete on the host side before returning; the vectors
     // stay alive in the cache in any case
     C.host = std::move(h);
@@ -629,7 +697,7 @@ int tree_prepare(int n, int leaf, hipStream_t s, TreeDev &out)
 }
 
 template <bool Q2>
-hipError_t launch_moments_t(const float4 *pm, const TreeDev &d, const HostTree &h, hipStream_t s)
+hipError_t launch_moments_t(const float4 *pm, const TreeDev &d, const HostTree &h, int cells, hipStream_t s)
 {
     const int nl = (int)h.leaves.size();
     hipLaunchKernelGGL(k_tree_leaves<Q2>, dim3((nl + 255) / 256), dim3(256), 0, s, pm, d, nl);
@@ -639,9 +707,13 @@ hipError_t launch_moments_t(const float4 *pm, const TreeDev &d, const HostTree &
         hipLaunchKernelGGL(k_tree_inner<Q2>, dim3((count + 255) / 256), dim3(256), 0, s, d, first, count);
         e = hipGetLastError();
     }
-    if (Q2 && e == hipSuccess) {
-        const int nn = (int)h.node.size();
+    const int nn = (int)h.node.size();
+    if (Q2 && e == hipSuccess && cells == kCellsPseudo) {
         hipLaunchKernelGGL(k_tree_pseudo, dim3((nn * kPseudo + 255) / 256), dim3(256), 0, s, d, nn);
+        e = hipGetLastError();
+    }
+    if (Q2 && e == hipSuccess && cells == kCellsQuad) {
+        hipLaunchKernelGGL(k_tree_quad, dim3((nn + 255) / 256), dim3(256), 0, s, d, nn);
         e = hipGetLastError();
     }
     return e;
@@ -655,19 +727,21 @@ bool pseudo_fits(const HostTree &h)
     return false;
 }
 
-// Monopole moments and boxes; with order 2 also the second moments and the
-// pseudo-particles.
-hipError_t launch_moments(const float4 *pm, const TreeDev &d, const HostTree &h, int order, hipStream_t s)
+// Monopole moments and boxes; for the other cell models also the second
+// moments and the cells' records.
+hipError_t launch_moments(const float4 *pm, const TreeDev &d, const HostTree &h, int cells, hipStream_t s)
 {
-    return order == 2 ? launch_moments_t<true>(pm, d, h, s) : launch_moments_t<false>(pm, d, h, s);
+    return cells != kCellsMono ? launch_moments_t<true>(pm, d, h, cells, s)
+                               : launch_moments_t<false>(pm, d, h, cells, s);
 }
 
-template <int MODE, bool INSPECT, bool PP>
+template <int MODE, bool INSPECT, int CELLS>
 hipError_t launch_walk(const float4 *pm, int n, const TreeDev &d, int ngroups, float eps2, double G,
                        double theta2, const WalkOut &o, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_tree_walk<MODE, INSPECT, PP>), dim3(ngroups), dim3(64), 0, s, pm, n, d,
-                       (const float4 *)d.pp, eps2, G, theta2, o);
+    const float4 *recs = CELLS == kCellsPseudo ? d.pp : (CELLS == kCellsQuad ? d.qr : d.rec);
+    hipLaunchKernelGGL((k_tree_walk<MODE, INSPECT, CELLS>), dim3(ngroups), dim3(64), 0, s, pm, n, d, recs, eps2,
+                       G, theta2, o);
     return hipGetLastError();
 }
 
@@ -714,43 +788,45 @@ int tree_lists(const void *pm, int n, int leaf, double theta, int max_far, int m
     o.max_far = far_ids ? max_far : 0;
     o.max_near = near_ids ? max_near : 0;
     if (e == hipSuccess)
-        e = launch_walk<M_F32, true, false>((const float4 *)pm, n, d, (int)g_tree.host.groups.size(), 0.0f,
-                                            1.0, theta * theta, o, s);
+        e = launch_walk<M_F32, true, kCellsMono>((const float4 *)pm, n, d, (int)g_tree.host.groups.size(),
+                                                 0.0f, 1.0, theta * theta, o, s);
     return e == hipSuccess ? NBODY_OK : hip_fail(e, "tree lists");
 }
 
 namespace {
-template <bool PP>
+template <int CELLS>
 hipError_t walk_prec(int prec, const float4 *pm, int n, const TreeDev &d, int ng, float eps2, double G, double th2,
                      const WalkOut &o, hipStream_t s)
 {
     switch (prec) {
-    case NBODY_F32: return launch_walk<M_F32, false, PP>(pm, n, d, ng, eps2, G, th2, o, s);
-    case NBODY_F32_KAHAN: return launch_walk<M_KAHAN, false, PP>(pm, n, d, ng, eps2, G, th2, o, s);
-    default: return launch_walk<M_F64ACC, false, PP>(pm, n, d, ng, eps2, G, th2, o, s);
+    case NBODY_F32: return launch_walk<M_F32, false, CELLS>(pm, n, d, ng, eps2, G, th2, o, s);
+    case NBODY_F32_KAHAN: return launch_walk<M_KAHAN, false, CELLS>(pm, n, d, ng, eps2, G, th2, o, s);
+    default: return launch_walk<M_F64ACC, false, CELLS>(pm, n, d, ng, eps2, G, th2, o, s);
     }
 }
 }  // namespace
 
-int tree_accel(const void *pm, int n, int prec, double G, double eps, double theta, int leaf, int order,
+int tree_accel(const void *pm, int n, int prec, double G, double eps, double theta, int leaf, int cells,
                void *out, hipStream_t s)
 {
     std::lock_guard<std::mutex> lk(g_tree_mu);
     TreeDev d;
     int rc = tree_prepare(n, leaf, s, d);
     if (rc != NBODY_OK) return rc;
-    if (order == 2 && !pseudo_fits(g_tree.host)) return NBODY_E_INVAL;
-    hipError_t e = launch_moments((const float4 *)pm, d, g_tree.host, order, s);
+    if (cells == kCellsPseudo && !pseudo_fits(g_tree.host)) return NBODY_E_INVAL;
+    hipError_t e = launch_moments((const float4 *)pm, d, g_tree.host, cells, s);
     WalkOut o{};
     o.acc_pot = (float4 *)out;
     const int ng = (int)g_tree.host.groups.size();
     const float eps2 = (float)(eps * eps);
     const double th2 = theta * theta;
     if (e == hipSuccess) {
-        if (order == 2)
-            e = walk_prec<true>(prec, (const float4 *)pm, n, d, ng, eps2, G, th2, o, s);
+        if (cells == kCellsPseudo)
+            e = walk_prec<kCellsPseudo>(prec, (const float4 *)pm, n, d, ng, eps2, G, th2, o, s);
+        else if (cells == kCellsQuad)
+            e = walk_prec<kCellsQuad>(prec, (const float4 *)pm, n, d, ng, eps2, G, th2, o, s);
         else
-            e = walk_prec<false>(prec, (const float4 *)pm, n, d, ng, eps2, G, th2, o, s);
+            e = walk_prec<kCellsMono>(prec, (const float4 *)pm, n, d, ng, eps2, G, th2, o, s);
     }
     return e == hipSuccess ? NBODY_OK : hip_fail(e, "tree force");
 }
@@ -763,9 +839,21 @@ int tree_pseudo(const void *pm, int n, int leaf, void *out, hipStream_t s)
     if (rc != NBODY_OK) return rc;
     if (!pseudo_fits(g_tree.host)) return NBODY_E_INVAL;
     const size_t bytes = g_tree.host.node.size() * kPseudo * sizeof(float4);
-    hipError_t e = launch_moments((const float4 *)pm, d, g_tree.host, 2, s);
+    hipError_t e = launch_moments((const float4 *)pm, d, g_tree.host, kCellsPseudo, s);
     if (e == hipSuccess) e = hipMemcpyAsync(out, d.pp, bytes, hipMemcpyDeviceToDevice, s);
     return e == hipSuccess ? NBODY_OK : hip_fail(e, "tree pseudo-particles");
+}
+
+int tree_quad(const void *pm, int n, int leaf, void *out, hipStream_t s)
+{
+    std::lock_guard<std::mutex> lk(g_tree_mu);
+    TreeDev d;
+    int rc = tree_prepare(n, leaf, s, d);
+    if (rc != NBODY_OK) return rc;
+    const size_t bytes = g_tree.host.node.size() * kQuadRec * sizeof(float4);
+    hipError_t e = launch_moments((const float4 *)pm, d, g_tree.host, kCellsQuad, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, d.qr, bytes, hipMemcpyDeviceToDevice, s);
+    return e == hipSuccess ? NBODY_OK : hip_fail(e, "tree quadrupoles");
 }
 
 // ---- tree leapfrog ---------------------------------------------------------------
@@ -843,9 +931,9 @@ int tree_leapfrog(void *pm, void *vel, void *acc, int32_t *order, int n, int pre
         const int rc = reorder(pm, vel, acc, order, n, leaf, s);
         if (rc != NBODY_OK) return rc;
     }
-    const int cell_order = (flags & NBODY_TREE_ORDER2) ? 2 : 0;
+    const int cells = (flags & NBODY_TREE_QUAD_CELLS) ? kCellsQuad : ((flags & NBODY_TREE_PSEUDO_CELLS) ? kCellsPseudo : kCellsMono);
     if (!(flags & NBODY_ACC_VALID)) {
-        const int rc = tree_accel(pm, n, prec, G, eps, theta, leaf, cell_order, acc, s);
+        const int rc = tree_accel(pm, n, prec, G, eps, theta, leaf, cells, acc, s);
         if (rc != NBODY_OK) return rc;
     }
     hipError_t e = launch_step(prec, pm, vel, acc, n, h, dt, false, nsteps > 0, ep, &eb, s);
@@ -856,7 +944,7 @@ int tree_leapfrog(void *pm, void *vel, void *acc, int32_t *order, int n, int pre
             const int rc = reorder(pm, vel, acc, order, n, leaf, s);
             if (rc != NBODY_OK) return rc;
         }
-        const int rc = tree_accel(pm, n, prec, G, eps, theta, leaf, cell_order, acc, s);
+        const int rc = tree_accel(pm, n, prec, G, eps, theta, leaf, cells, acc, s);
         if (rc != NBODY_OK) return rc;
         const bool last = (k == nsteps - 1);
         e = launch_step(prec, pm, vel, acc, n, h, dt, true, !last, ep, &eb, s);

@@ -58,8 +58,8 @@ def test_force_matches_oracle(orc, prec, tol_rms, tol_max, theta):
     n, leaf, eps = 12000, 4, 0.01
     pm, _ = ics.plummer(n, 410)
     q, qh = _orb_input(torch, nb, pm, leaf)
-    got = host(nb.tree_accel(q, eps, theta, leaf, prec=getattr(nb, prec), cell_order=2))
-    a, p = orc.tree_accel(widen32(qh), leaf, 64, theta, eps, order=2)
+    got = host(nb.tree_accel(q, eps, theta, leaf, prec=getattr(nb, prec), cells=nb.CELLS_PSEUDO))
+    a, p = orc.tree_accel(widen32(qh), leaf, 64, theta, eps, cells=2)
     assert rms_rel(got[:, :3], a) < tol_rms
     assert max_rel(got[:, :3], a) < tol_max
     assert rms_rel(got[:, 3], p) < tol_rms
@@ -71,12 +71,12 @@ def test_theta_zero_equals_direct_and_order_two_beats_monopole(orc):
     pm, _ = ics.colliding_pair(n, 420)
     q, qh = _orb_input(torch, nb, pm, leaf)
     ad, pd = orc.accel(widen32(qh), eps)
-    t0 = host(nb.tree_accel(q, eps, 0.0, leaf, prec=nb.F32_F64ACC, cell_order=2))
+    t0 = host(nb.tree_accel(q, eps, 0.0, leaf, prec=nb.F32_F64ACC, cells=nb.CELLS_PSEUDO))
     assert rms_rel(t0[:, :3], ad) < 1e-6 and rms_rel(t0[:, 3], pd) < 1e-6
     for theta in (0.5, 0.7, 1.0):
         e = {}
         for order in (0, 2):
-            t = host(nb.tree_accel(q, eps, theta, leaf, prec=nb.F32_F64ACC, cell_order=order))
+            t = host(nb.tree_accel(q, eps, theta, leaf, prec=nb.F32_F64ACC, cells=order))
             e[order] = rms_rel(t[:, :3], ad)
         print(f"theta {theta}: rms error against the direct sum, monopole {e[0]:.3e}, order 2 {e[2]:.3e}")
         assert e[2] < e[0] / 2
@@ -89,11 +89,11 @@ def test_small_and_ragged(orc, n):
     pm = pm[:n].copy()
     pm[:, 3] = 1.0 / n
     q, qh = _orb_input(torch, nb, pm, 4)
-    got = host(nb.tree_accel(q, 0.05, 0.8, 4, prec=nb.F32_F64ACC, cell_order=2))
+    got = host(nb.tree_accel(q, 0.05, 0.8, 4, prec=nb.F32_F64ACC, cells=nb.CELLS_PSEUDO))
     if n == 1:
         assert np.all(got == 0.0)
         return
-    a, p = orc.tree_accel(widen32(qh), 4, 64, 0.8, 0.05, order=2)
+    a, p = orc.tree_accel(widen32(qh), 4, 64, 0.8, 0.05, cells=2)
     assert rms_rel(got[:, :3], a) < 1e-6
     assert rms_rel(got[:, 3], p) < 1e-6
 
@@ -106,8 +106,8 @@ def test_massless_bodies_and_eps_zero(orc):
     pm[::4, 3] = 0.0
     pm[pm[:, 0] < -0.5, 3] = 0.0  # whole cells without mass
     q, qh = _orb_input(torch, nb, pm, 4)
-    got = host(nb.tree_accel(q, 0.0, 0.6, 4, prec=nb.F32_F64ACC, cell_order=2))
-    a, p = orc.tree_accel(widen32(qh), 4, 64, 0.6, 0.0, order=2)
+    got = host(nb.tree_accel(q, 0.0, 0.6, 4, prec=nb.F32_F64ACC, cells=nb.CELLS_PSEUDO))
+    a, p = orc.tree_accel(widen32(qh), 4, 64, 0.6, 0.0, cells=2)
     assert np.isfinite(got).all()
     assert rms_rel(got[:, :3], a) < 1e-6
 
@@ -121,9 +121,9 @@ def test_large_sampled(orc):
     n, eps, leaf, theta = w["n"], w["eps"], 4, 0.7
     pm, _ = ics.colliding_pair(n, w["seed"])
     q, qh = _orb_input(torch, nb, pm, leaf)
-    got = host(nb.tree_accel(q, eps, theta, leaf, prec=nb.F32_F64ACC, cell_order=2))
+    got = host(nb.tree_accel(q, eps, theta, leaf, prec=nb.F32_F64ACC, cells=nb.CELLS_PSEUDO))
     tg = np.random.default_rng(8).choice(n, 256, replace=False)
-    a, p = orc.tree_accel(widen32(qh), leaf, 64, theta, eps, targets=tg, order=2)
+    a, p = orc.tree_accel(widen32(qh), leaf, 64, theta, eps, targets=tg, cells=2)
     assert rms_rel(got[tg, :3], a) < 1e-6
     assert rms_rel(got[tg, 3], p) < 1e-6
     ad, _ = orc.accel(widen32(qh), eps, targets=tg)
@@ -138,10 +138,10 @@ def test_order_switch_and_repeat_same_bits():
     torch, nb = gpu()
     pm, _ = ics.plummer(5000, 450)
     q, _ = _orb_input(torch, nb, pm, 4)
-    r2 = host(nb.tree_accel(q, 0.01, 0.7, 4, cell_order=2))
-    r0 = host(nb.tree_accel(q, 0.01, 0.7, 4, cell_order=0))
-    assert np.array_equal(r2, host(nb.tree_accel(q, 0.01, 0.7, 4, cell_order=2)))
-    assert np.array_equal(r0, host(nb.tree_accel(q, 0.01, 0.7, 4, cell_order=0)))
+    r2 = host(nb.tree_accel(q, 0.01, 0.7, 4, cells=nb.CELLS_PSEUDO))
+    r0 = host(nb.tree_accel(q, 0.01, 0.7, 4, cells=0))
+    assert np.array_equal(r2, host(nb.tree_accel(q, 0.01, 0.7, 4, cells=nb.CELLS_PSEUDO)))
+    assert np.array_equal(r0, host(nb.tree_accel(q, 0.01, 0.7, 4, cells=0)))
     assert not np.array_equal(r0, r2)
 
 
@@ -155,13 +155,13 @@ def test_tree_leapfrog_order_two(orc):
     perm = nb.orb_order(p, leaf)
     q = nb.permute(p, perm)
     v = nb.permute(to_dev(torch, np.c_[v0[:, :3], np.zeros(n)].astype(np.float32), torch.float32), perm)
-    a = nb.tree_accel(q, eps, theta, leaf, prec=nb.F32_F64ACC, cell_order=2)
+    a = nb.tree_accel(q, eps, theta, leaf, prec=nb.F32_F64ACC, cells=2)
     h = 0.5 * dt
     for _ in range(3):
         xk, vk, ak = host(q), host(v), host(a)
-        at, _ = orc.tree_accel(xk, leaf, 64, theta, eps, order=2)
+        at, _ = orc.tree_accel(xk, leaf, 64, theta, eps, cells=2)
         assert rms_rel(ak[:, :3], at) < 1e-6
-        nb.tree_leapfrog(q, v, a, eps, theta, dt, 1, leaf, acc_valid=True, prec=nb.F32_F64ACC, cell_order=2)
+        nb.tree_leapfrog(q, v, a, eps, theta, dt, 1, leaf, acc_valid=True, prec=nb.F32_F64ACC, cells=2)
         x1, v1, a1 = host(q), host(v), host(a)
         np.testing.assert_allclose(x1[:, :3], xk[:, :3] + dt * (vk[:, :3] + h * ak[:, :3]), rtol=0, atol=1e-6)
         np.testing.assert_allclose(v1[:, :3], vk[:, :3] + h * (ak[:, :3] + a1[:, :3]), rtol=0, atol=1e-6)
