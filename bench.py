@@ -58,6 +58,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--tree-counters", action="store_true",
                     help="two tree evaluations (theta 0.7, leaf 8) of the workload for counter runs")
+    ap.add_argument("--tree-cells", action="store_true",
+                    help="two tree evaluations (theta 0.7, leaf 4) per cell model for trace and counter runs")
     ap.add_argument("--counters", action="store_true",
                     help="counter-collection mode: two force launches of the headline workload "
                          "and one 1 GiB device copy (the copy calibrates byte counters); no JSON")
@@ -103,6 +105,16 @@ def main():
             nb.tree_accel(q, eps, 0.7, 8, prec=prec, out=out)
         torch.cuda.synchronize()
         log("[bench] tree counters mode: 2 tree evaluations, theta 0.7, leaf 8, F32_F64ACC")
+        return
+
+    if args.tree_cells:
+        q = nb.permute(pm, nb.orb_order(pm, 4))
+        out = torch.empty_like(q)
+        for cells in (nb.CELLS_MONOPOLE, nb.CELLS_PSEUDO, nb.CELLS_QUADRUPOLE):
+            for _ in range(2):
+                nb.tree_accel(q, eps, 0.7, 4, prec=prec, out=out, cells=cells)
+        torch.cuda.synchronize()
+        log("[bench] tree cells mode: 2 evaluations per cell model (0, 2, 3), theta 0.7, leaf 4, F32_F64ACC")
         return
 
     # ORB body order (the paper's recursive bisection, used as an ordering):

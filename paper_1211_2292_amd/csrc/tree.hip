@@ -56,7 +56,10 @@
 // softened distance s^2 = |d|^2 + eps^2:
 //   potential sum  M / s + d.Q.d / (2 s^5)
 //   acceleration   d (M / s^3 + 5 d.Q.d / (2 s^7)) - Q d / s^5
-// about 35 VALU per cell and target instead of 12 pair evaluations.
+// about 35 VALU per cell and target instead of 12 pair evaluations.  The
+// accepted cells' 3 records are staged in LDS and swept after every walk
+// step, so the cell values reach the arithmetic as vector operands (read
+// from scalar registers they issue at about two thirds of the rate).
 #include <cstdint>
 #include <cstring>
 #include <mutex>
@@ -325,15 +328,13 @@ __device__ __forceinline__ void quad_f32(const float4 c, const float4 q1, const 
     S.az[0] = __builtin_fmaf(-qz, ri5, __builtin_fmaf(k, dz, S.az[0]));
 }
 
-// Sweeps the quadrupole cells of the batched ids (one 48-byte scalar load
-// per cell).
-__device__ __forceinline__ void sweep_quad(const float4 *__restrict__ qr, const int *ids, int cnt,
-                                           const Targets<float, 1> &T, float eps2, Sums<float, 1> &S)
+// Sweeps the quadrupole records batched in LDS (broadcast reads into vector
+// registers: the cell values then enter the arithmetic as vector operands).
+__device__ __forceinline__ void sweep_quad(const float4 *qb, int cnt, const Targets<float, 1> &T, float eps2,
+                                           Sums<float, 1> &S)
 {
     for (int r = 0; r < cnt; ++r) {
-        const int c = __builtin_amdgcn_readfirstlane(ids[r]);
-        const float4 *q = qr + (long)kQuadRec * c;
-        const float4 a = q[0], b = q[1], d = q[2];
+        const float4 a = qb[kQuadRec * r], b = qb[kQuadRec * r + 1], d = qb[kQuadRec * r + 2];
         quad_f32(a, b, d, T, eps2, S);
     }
 }
@@ -345,10 +346,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void k_
                                                   const float4 *__restrict__ cells, float eps2_in, double G,
                                                   double theta2, WalkOut O)
 {
-    constexpr bool kIds = CELLS != kCellsMono;
     __shared__ int stk[kStack];
-    __shared__ float4 cbuf[kIds ? 1 : kBuf];  // monopole cells: the accepted cells' records
-    __shared__ int cid[kIds ? kBuf : 1];      // other cells: the accepted cells' ids
+    __shared__ float4 cbuf[CELLS == kCellsMono ? kBuf : 1];    // monopole cells: the accepted records
+    __shared__ int cid[CELLS == kCellsPseudo ? kBuf : 1];      // pseudo-particle cells: the accepted ids
+    // quadrupole cells: the records of one step's accepted cells (swept every step)
+    __shared__ float4 qbuf[CELLS == kCellsQuad ? kQuadRec * kGroup : 1];
     __shared__ int2 nbuf[kBuf];
     const int lane = threadIdx.x;
     const int g = blockIdx.x;
@@ -390,7 +392,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void k_
             if constexpr (CELLS == kCellsPseudo)
                 sweep_pseudo(cells, cid, nf, TT, eps2, S);
             else if constexpr (CELLS == kCellsQuad)
-                sweep_quad(cells, cid, nf, TT, eps2, S);
+                sweep_quad(qbuf, nf, TT, eps2, S);
             else
                 sweep_cells(cbuf, nf, TT, eps2, S);
             R[0].fold(S.ax[0]);
@@ -468,7 +470,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void k_
             }
         } else {
             if (acc) {
-                if constexpr (kIds)
+                if constexpr (CELLS == kCellsQuad) {
+                    const int slot = nf + (int)lane_rank(ma);
+                    const float4 *r = cells + (long)kQuadRec * c;
+                    qbuf[kQuadRec * slot] = r[0];
+                    qbuf[kQuadRec * slot + 1] = r[1];
+                    qbuf[kQuadRec * slot + 2] = r[2];
+                } else if constexpr (CELLS == kCellsPseudo)
                     cid[nf + (int)lane_rank(ma)] = c;
                 else
                     cbuf[nf + (int)lane_rank(ma)] = T.rec[c];
@@ -486,7 +494,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void k_
         nr += cn;
         top += 2 * co;
         __syncthreads();
-        if (nf >= kGroup) flush_cells();
+        if (CELLS == kCellsQuad ? nf > 0 : nf >= kGroup) flush_cells();
         if (nr >= kGroup) flush_near();
     }
     if (nf > 0) flush_cells();
