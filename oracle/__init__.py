@@ -94,6 +94,9 @@ def _load():
         lib.oracle_tree_accel_cells.restype = ctypes.c_int
         lib.oracle_tree_quad.argtypes = [ctypes.c_int64, ctypes.c_int32, _d, _d, _d]
         lib.oracle_tree_quad.restype = ctypes.c_int
+        lib.oracle_tree_local_counts.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _d, _d,
+                                                 ctypes.c_double, _i64, _i64, _i64]
+        lib.oracle_tree_local_counts.restype = ctypes.c_int
         lib.oracle_tree_pseudo.argtypes = [ctypes.c_int64, ctypes.c_int32, _d, _d, _d]
         lib.oracle_tree_pseudo.restype = ctypes.c_int
         lib.oracle_pseudo_dirs.argtypes = [_d]
@@ -386,4 +389,23 @@ def tree_quad(pos_mass_orb, leaf: int) -> np.ndarray:
     out = np.empty((nn, 6))
     if lib.oracle_tree_quad(n, int(leaf), _ptr(x, _d), _ptr(m, _d), _ptr(out, _d)) != 0:
         raise ValueError("oracle_tree_quad: bad arguments")
+    return out
+
+
+def tree_local_counts(pos_mass_orb, leaf: int, group: int, theta: float):
+    """Per-group sizes of the local-expansion walk: dict(loc_cnt, far_cnt,
+    near_cnt), each (ngroups,) int64, groups in ORB order."""
+    lib = _load()
+    x, m = _split(pos_mass_orb)
+    n = x.shape[0]
+    ng = int(lib.oracle_tree_num_groups(n, int(leaf), int(group)))
+    if ng < 1:
+        raise ValueError("oracle_tree_num_groups: bad arguments")
+    out = dict(loc_cnt=np.empty(ng, dtype=np.int64), far_cnt=np.empty(ng, dtype=np.int64),
+               near_cnt=np.empty(ng, dtype=np.int64))
+    rc = lib.oracle_tree_local_counts(n, int(leaf), int(group), _ptr(x, _d), _ptr(m, _d), float(theta),
+                                      _ptr(out["loc_cnt"], _i64), _ptr(out["far_cnt"], _i64),
+                                      _ptr(out["near_cnt"], _i64))
+    if rc != 0:
+        raise ValueError("oracle_tree_local_counts failed")
     return out

@@ -57,7 +57,10 @@
  *                    each cell's expansion to quadrupole order is carried
  *                    either by 12 point masses from that method's formula,
  *                    or by the cell's traceless quadrupole tensor with the
- *                    expansion evaluated directly.
+ *                    expansion evaluated directly; and the fast multipole
+ *                    method's local expansions at the level of the target
+ *                    groups (cells far from a whole group enter one Taylor
+ *                    expansion about the group's centre).
  *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared (no fast-math;
  * contraction off so that every product and sum rounds as written).
@@ -694,6 +697,81 @@ static void tree_walk_rec(const tree_ctx *t, int64_t c, int64_t g, int32_t *far,
     tree_walk_rec(t, r, g, far, nf, near, nnr);
 }
 
+/* ---------------------------------------------------------------------------
+ * Group local expansions (the M2L and L2P steps of the fast multipole method
+ * the paper's Section VI points to through its reference [20], taken at the
+ * level of the target groups; cells carry their quadrupole expansion).
+ * Readings of this library:
+ *   centre   z_g = the group node's FP64 centre of mass.
+ *   MAC_L    cell c may enter group g's local expansion iff c and g share no
+ *            body and diag2_c + diag2_g < theta^2 |com_c - z_g|^2.  Every
+ *            body of c is within sqrt(diag2_c) of com_c and every target
+ *            within sqrt(diag2_g) of z_g, and (b_c + b_g)^2 <= 2 (b_c^2 +
+ *            b_g^2), so both expansions converge for theta < 1/sqrt(2)
+ *            and their size-to-distance ratio is below sqrt(2) theta; no
+ *            square roots.
+ *   walk     visit(c): MAC_L -> local list; else the monopole acceptance
+ *            test -> far list, evaluated body by body as a quadrupole cell;
+ *            else a leaf -> near list; else visit(left), visit(right).  The
+ *            far and near lists are thus never longer than those of the
+ *            quadrupole cells alone.
+ *   M2L      the cell's potential sum P_c(x) = M/s + (r.Q.r)/(2 s^5),
+ *            r = x - com_c, s^2 = |r|^2 + eps^2, expanded to second order
+ *            about z_g: P0 = P_c(z_g), p = grad P_c(z_g), K = grad grad
+ *            P_c(z_g), with (r = z_g - com_c)
+ *              p_k  = -M r_k/s^3 - 5 (r.Q.r) r_k / (2 s^7) + (Q r)_k / s^5
+ *              K_kl = M (3 r_k r_l / s^5 - delta_kl / s^3)
+ *                     + 35 (r.Q.r) r_k r_l / (2 s^9)
+ *                     - 5 (2 (Q r)_k r_l + 2 (Q r)_l r_k + delta_kl r.Q.r) / (2 s^7)
+ *                     + Q_kl / s^5
+ *            summed over the local list in walk order (Neumaier).
+ *   L2P      at y = x - z_g: a += G (p + K y), phi -= G (P0 + p.y + y.K.y / 2).
+ * ------------------------------------------------------------------------- */
+static int tree_overlap(const int64_t *nodes, int64_t c, int64_t g)
+{
+    const int64_t *nc = nodes + 4 * c, *ng = nodes + 4 * g;
+    return nc[0] < ng[1] && ng[0] < nc[1];
+}
+
+static double tree_centre_dist2(const tree_ctx *t, int64_t c, int64_t g)
+{
+    const double dx = t->com[3 * c] - t->com[3 * g];
+    const double dy = t->com[3 * c + 1] - t->com[3 * g + 1];
+    const double dz = t->com[3 * c + 2] - t->com[3 * g + 2];
+    return (dx * dx + dy * dy) + dz * dz;
+}
+
+/* Local-expansion walk for group node g: appends to loc/far/near (any may be
+ * NULL to count). */
+static void tree_walk_local_rec(const tree_ctx *t, int64_t c, int64_t g, int32_t *loc, int64_t *nl, int32_t *far,
+                                int64_t *nf, int32_t *near, int64_t *nnr)
+{
+    if (!tree_overlap(t->nodes, c, g)) {
+        const double dz2 = tree_centre_dist2(t, c, g);
+        if (t->diag2[c] + t->diag2[g] < t->theta2 * dz2) {
+            if (loc)
+                loc[*nl] = (int32_t)c;
+            ++*nl;
+            return;
+        }
+        if (tree_accept(t, c, g)) {
+            if (far)
+                far[*nf] = (int32_t)c;
+            ++*nf;
+            return;
+        }
+    }
+    const int64_t l = t->nodes[4 * c + 2], r = t->nodes[4 * c + 3];
+    if (l < 0) {
+        if (near)
+            near[*nnr] = (int32_t)c;
+        ++*nnr;
+        return;
+    }
+    tree_walk_local_rec(t, l, g, loc, nl, far, nf, near, nnr);
+    tree_walk_local_rec(t, r, g, loc, nl, far, nf, near, nnr);
+}
+
 typedef struct {
     int64_t nn, ngroups;
     int64_t *nodes, *group_node;
@@ -966,13 +1044,13 @@ int oracle_tree_accel_cells(int64_t n, int32_t leaf, int32_t group, const double
                             double G, double eps, double theta, int32_t cells, int64_t ntarg,
                             const int64_t *targets, double *acc, double *pot)
 {
-    if (!(theta >= 0.0) || (cells != 0 && cells != 2 && cells != 3))
+    if (!(theta >= 0.0) || cells < 0 || cells == 1 || cells > 4)
         return -1;
     tree_data d;
     if (tree_setup(n, leaf, group, x, m, &d) != 0)
         return -1;
     double *pp = NULL;
-    if (cells == 2 || cells == 3) {
+    if (cells >= 2) {
         const size_t per = cells == 2 ? PSEUDO_K * 4 : 6;
         pp = (double *)malloc((size_t)d.nn * per * sizeof(double));
         if (!pp) {
@@ -1002,23 +1080,78 @@ int oracle_tree_accel_cells(int64_t n, int32_t leaf, int32_t group, const double
     for (t = 0; t < ntarg; ++t) {
         const int64_t i = targets ? targets[t] : t;
         const int64_t g = gof[i];
-        int64_t nf = 0, nnr = 0;
-        tree_walk_rec(&tc, 0, g, NULL, &nf, NULL, &nnr);
+        int64_t nl = 0, nf = 0, nnr = 0;
+        if (cells == 4)
+            tree_walk_local_rec(&tc, 0, g, NULL, &nl, NULL, &nf, NULL, &nnr);
+        else
+            tree_walk_rec(&tc, 0, g, NULL, &nf, NULL, &nnr);
+        int32_t *loc = (int32_t *)malloc((size_t)(nl + 1) * sizeof(int32_t));
         int32_t *far = (int32_t *)malloc((size_t)(nf + 1) * sizeof(int32_t));
         int32_t *near = (int32_t *)malloc((size_t)(nnr + 1) * sizeof(int32_t));
-        if (!far || !near) {
+        if (!loc || !far || !near) {
+            free(loc);
             free(far);
             free(near);
             bad = 1;
             continue;
         }
-        int64_t a = 0, b = 0;
-        tree_walk_rec(&tc, 0, g, far, &a, near, &b);
+        int64_t a = 0, b = 0, e = 0;
+        if (cells == 4)
+            tree_walk_local_rec(&tc, 0, g, loc, &e, far, &a, near, &b);
+        else
+            tree_walk_rec(&tc, 0, g, far, &a, near, &b);
         const double xi = x[3 * i], yi = x[3 * i + 1], zi = x[3 * i + 2];
         nsum ax = {0, 0}, ay = {0, 0}, az = {0, 0}, ph = {0, 0};
+        if (nl > 0) {
+            /* M2L over the local list, then L2P at this target */
+            const double *zg = d.com + 3 * g;
+            nsum L[10];
+            for (int k = 0; k < 10; ++k)
+                L[k] = (nsum){0, 0};
+            for (int64_t q = 0; q < nl; ++q) {
+                const int64_t c = loc[q];
+                const double *cm = d.com + 3 * c, *Q = pp + 6 * c;
+                const double M = d.mass[c];
+                const double r[3] = {zg[0] - cm[0], zg[1] - cm[1], zg[2] - cm[2]};
+                const double s2 = ((r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]) + eps2;
+                const double s1 = 1.0 / sqrt(s2);
+                const double s3 = s1 / s2, s5 = s3 / s2, s7 = s5 / s2, s9 = s7 / s2;
+                const double qr[3] = {(Q[0] * r[0] + Q[3] * r[1]) + Q[4] * r[2],
+                                      (Q[3] * r[0] + Q[1] * r[1]) + Q[5] * r[2],
+                                      (Q[4] * r[0] + Q[5] * r[1]) + Q[2] * r[2]};
+                const double rqr = (r[0] * qr[0] + r[1] * qr[1]) + r[2] * qr[2];
+                nsum_add(&L[0], M * s1 + 0.5 * rqr * s5);
+                for (int k = 0; k < 3; ++k)
+                    nsum_add(&L[1 + k], -M * r[k] * s3 - 2.5 * rqr * r[k] * s7 + qr[k] * s5);
+                /* K in the order xx, yy, zz, xy, xz, yz */
+                static const int kk[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
+                static const int qi[6] = {0, 1, 2, 3, 4, 5};
+                for (int u = 0; u < 6; ++u) {
+                    const int k = kk[u][0], l = kk[u][1];
+                    const double dkl = k == l ? 1.0 : 0.0;
+                    const double v = M * (3.0 * r[k] * r[l] * s5 - dkl * s3) + 17.5 * rqr * r[k] * r[l] * s9 -
+                                     2.5 * (2.0 * qr[k] * r[l] + 2.0 * qr[l] * r[k] + dkl * rqr) * s7 +
+                                     Q[qi[u]] * s5;
+                    nsum_add(&L[4 + u], v);
+                }
+            }
+            double c[10];
+            for (int k = 0; k < 10; ++k)
+                c[k] = nsum_val(&L[k]);
+            const double y[3] = {xi - zg[0], yi - zg[1], zi - zg[2]};
+            const double ky[3] = {(c[4] * y[0] + c[7] * y[1]) + c[8] * y[2],
+                                  (c[7] * y[0] + c[5] * y[1]) + c[9] * y[2],
+                                  (c[8] * y[0] + c[9] * y[1]) + c[6] * y[2]};
+            nsum_add(&ax, c[1] + ky[0]);
+            nsum_add(&ay, c[2] + ky[1]);
+            nsum_add(&az, c[3] + ky[2]);
+            const double py = (c[1] * y[0] + c[2] * y[1]) + c[3] * y[2];
+            const double yky = (y[0] * ky[0] + y[1] * ky[1]) + y[2] * ky[2];
+            nsum_add(&ph, c[0] + py + 0.5 * yky);
+        }
         for (int64_t q = 0; q < nf + nnr; ++q) {
             const int64_t c = q < nf ? far[q] : near[q - nf];
-            if (q < nf && cells == 3) {
+            if (q < nf && cells >= 3) {
                 /* quadrupole cell, d = x - com */
                 const double *cm = d.com + 3 * c, *Q = pp + 6 * c;
                 const double M = d.mass[c];
@@ -1076,6 +1209,7 @@ int oracle_tree_accel_cells(int64_t n, int32_t leaf, int32_t group, const double
                 nsum_add(&ph, mj / r);
             }
         }
+        free(loc);
         free(far);
         free(near);
         if (acc) {
@@ -1090,6 +1224,28 @@ int oracle_tree_accel_cells(int64_t n, int32_t leaf, int32_t group, const double
     free(pp);
     tree_free(&d);
     return bad ? -1 : 0;
+}
+
+/* Per-group list sizes of the local-expansion walk: loc_cnt, far_cnt,
+ * near_cnt [ngroups].  Returns 0, or -1 on bad arguments. */
+int oracle_tree_local_counts(int64_t n, int32_t leaf, int32_t group, const double *x, const double *m,
+                             double theta, int64_t *loc_cnt, int64_t *far_cnt, int64_t *near_cnt)
+{
+    if (!(theta >= 0.0))
+        return -1;
+    tree_data d;
+    if (tree_setup(n, leaf, group, x, m, &d) != 0)
+        return -1;
+    tree_ctx tc = {d.nodes, d.com, d.lo, d.hi, d.diag2, theta * theta};
+    for (int64_t q = 0; q < d.ngroups; ++q) {
+        int64_t a = 0, b = 0, e = 0;
+        tree_walk_local_rec(&tc, 0, d.group_node[q], NULL, &e, NULL, &a, NULL, &b);
+        loc_cnt[q] = e;
+        far_cnt[q] = a;
+        near_cnt[q] = b;
+    }
+    tree_free(&d);
+    return 0;
 }
 
 /* The monopole tree force (cells 0 of the above). */
