@@ -716,16 +716,25 @@ static void tree_walk_rec(const tree_ctx *t, int64_t c, int64_t g, int32_t *far,
  *            far and near lists are thus never longer than those of the
  *            quadrupole cells alone.
  *   M2L      the cell's potential sum P_c(x) = M/s + (r.Q.r)/(2 s^5),
- *            r = x - com_c, s^2 = |r|^2 + eps^2, expanded to second order
- *            about z_g: P0 = P_c(z_g), p = grad P_c(z_g), K = grad grad
- *            P_c(z_g), with (r = z_g - com_c)
- *              p_k  = -M r_k/s^3 - 5 (r.Q.r) r_k / (2 s^7) + (Q r)_k / s^5
- *              K_kl = M (3 r_k r_l / s^5 - delta_kl / s^3)
- *                     + 35 (r.Q.r) r_k r_l / (2 s^9)
- *                     - 5 (2 (Q r)_k r_l + 2 (Q r)_l r_k + delta_kl r.Q.r) / (2 s^7)
- *                     + Q_kl / s^5
- *            summed over the local list in walk order (Neumaier).
- *   L2P      at y = x - z_g: a += G (p + K y), phi -= G (P0 + p.y + y.K.y / 2).
+ *            r = x - com_c, s^2 = |r|^2 + eps^2, expanded to third order
+ *            about z_g (one order above the cells', so that the force,
+ *            which loses one order, keeps the cells' third-order error):
+ *            P0 = P_c(z_g), p = grad P_c, K = grad grad P_c, T = the third
+ *            derivatives, at z_g, with r = z_g - com_c and q = Q r:
+ *              p_k   = -M r_k/s^3 - 5 (r.Q.r) r_k / (2 s^7) + q_k / s^5
+ *              K_kl  = M (3 r_k r_l / s^5 - delta_kl / s^3)
+ *                      + 35 (r.Q.r) r_k r_l / (2 s^9)
+ *                      - 5 (2 q_k r_l + 2 q_l r_k + delta_kl r.Q.r) / (2 s^7)
+ *                      + Q_kl / s^5
+ *              T_klm = M (-15 r_k r_l r_m / s^7 + 3 (d_kl r_m + d_km r_l + d_lm r_k) / s^5)
+ *                      - 315 (r.Q.r) r_k r_l r_m / (2 s^11)
+ *                      + 35 (q_k r_l r_m + q_l r_k r_m + q_m r_k r_l) / s^9
+ *                      + 35 (r.Q.r) (d_kl r_m + d_km r_l + d_lm r_k) / (2 s^9)
+ *                      - 5 (Q_kl r_m + Q_km r_l + Q_lm r_k + q_k d_lm + q_l d_km + q_m d_kl) / s^7
+ *            (d = Kronecker delta), summed over the local list in walk order
+ *            (Neumaier).
+ *   L2P      at y = x - z_g: a += G (p + K y + T(y, y) / 2),
+ *            phi -= G (P0 + p.y + y.K.y / 2 + T(y, y, y) / 6).
  * ------------------------------------------------------------------------- */
 static int tree_overlap(const int64_t *nodes, int64_t c, int64_t g)
 {
@@ -1105,49 +1114,81 @@ int oracle_tree_accel_cells(int64_t n, int32_t leaf, int32_t group, const double
         if (nl > 0) {
             /* M2L over the local list, then L2P at this target */
             const double *zg = d.com + 3 * g;
-            nsum L[10];
-            for (int k = 0; k < 10; ++k)
+            nsum L[20];
+            for (int k = 0; k < 20; ++k)
                 L[k] = (nsum){0, 0};
             for (int64_t q = 0; q < nl; ++q) {
                 const int64_t c = loc[q];
-                const double *cm = d.com + 3 * c, *Q = pp + 6 * c;
+                const double *cm = d.com + 3 * c, *Qv = pp + 6 * c;
                 const double M = d.mass[c];
+                const double Q[3][3] = {{Qv[0], Qv[3], Qv[4]}, {Qv[3], Qv[1], Qv[5]}, {Qv[4], Qv[5], Qv[2]}};
                 const double r[3] = {zg[0] - cm[0], zg[1] - cm[1], zg[2] - cm[2]};
                 const double s2 = ((r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]) + eps2;
                 const double s1 = 1.0 / sqrt(s2);
-                const double s3 = s1 / s2, s5 = s3 / s2, s7 = s5 / s2, s9 = s7 / s2;
-                const double qr[3] = {(Q[0] * r[0] + Q[3] * r[1]) + Q[4] * r[2],
-                                      (Q[3] * r[0] + Q[1] * r[1]) + Q[5] * r[2],
-                                      (Q[4] * r[0] + Q[5] * r[1]) + Q[2] * r[2]};
+                const double s3 = s1 / s2, s5 = s3 / s2, s7 = s5 / s2, s9 = s7 / s2, s11 = s9 / s2;
+                double qr[3];
+                for (int k = 0; k < 3; ++k)
+                    qr[k] = (Q[k][0] * r[0] + Q[k][1] * r[1]) + Q[k][2] * r[2];
                 const double rqr = (r[0] * qr[0] + r[1] * qr[1]) + r[2] * qr[2];
                 nsum_add(&L[0], M * s1 + 0.5 * rqr * s5);
                 for (int k = 0; k < 3; ++k)
                     nsum_add(&L[1 + k], -M * r[k] * s3 - 2.5 * rqr * r[k] * s7 + qr[k] * s5);
                 /* K in the order xx, yy, zz, xy, xz, yz */
                 static const int kk[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
-                static const int qi[6] = {0, 1, 2, 3, 4, 5};
                 for (int u = 0; u < 6; ++u) {
                     const int k = kk[u][0], l = kk[u][1];
                     const double dkl = k == l ? 1.0 : 0.0;
                     const double v = M * (3.0 * r[k] * r[l] * s5 - dkl * s3) + 17.5 * rqr * r[k] * r[l] * s9 -
                                      2.5 * (2.0 * qr[k] * r[l] + 2.0 * qr[l] * r[k] + dkl * rqr) * s7 +
-                                     Q[qi[u]] * s5;
+                                     Q[k][l] * s5;
                     nsum_add(&L[4 + u], v);
                 }
+                /* T in the order xxx, yyy, zzz, xxy, xxz, xyy, yyz, xzz, yzz, xyz */
+                static const int tt[10][3] = {{0, 0, 0}, {1, 1, 1}, {2, 2, 2}, {0, 0, 1}, {0, 0, 2},
+                                              {0, 1, 1}, {1, 1, 2}, {0, 2, 2}, {1, 2, 2}, {0, 1, 2}};
+                for (int u = 0; u < 10; ++u) {
+                    const int k = tt[u][0], l = tt[u][1], m2 = tt[u][2];
+                    const double dkl = k == l ? 1.0 : 0.0, dkm = k == m2 ? 1.0 : 0.0, dlm = l == m2 ? 1.0 : 0.0;
+                    const double rrr = r[k] * r[l] * r[m2];
+                    const double dr = dkl * r[m2] + dkm * r[l] + dlm * r[k];
+                    const double v = M * (-15.0 * rrr * s7 + 3.0 * dr * s5) - 157.5 * rqr * rrr * s11 +
+                                     35.0 * (qr[k] * r[l] * r[m2] + qr[l] * r[k] * r[m2] + qr[m2] * r[k] * r[l]) * s9 +
+                                     17.5 * rqr * dr * s9 -
+                                     5.0 * (Q[k][l] * r[m2] + Q[k][m2] * r[l] + Q[l][m2] * r[k] + qr[k] * dlm +
+                                            qr[l] * dkm + qr[m2] * dkl) * s7;
+                    nsum_add(&L[10 + u], v);
+                }
             }
-            double c[10];
-            for (int k = 0; k < 10; ++k)
+            double c[20];
+            for (int k = 0; k < 20; ++k)
                 c[k] = nsum_val(&L[k]);
+            /* full symmetric tensors from the stored components */
+            const double K[3][3] = {{c[4], c[7], c[8]}, {c[7], c[5], c[9]}, {c[8], c[9], c[6]}};
+            double T3[3][3][3];
+            static const int tt[10][3] = {{0, 0, 0}, {1, 1, 1}, {2, 2, 2}, {0, 0, 1}, {0, 0, 2},
+                                          {0, 1, 1}, {1, 1, 2}, {0, 2, 2}, {1, 2, 2}, {0, 1, 2}};
+            for (int u = 0; u < 10; ++u) {
+                const int a3[3] = {tt[u][0], tt[u][1], tt[u][2]};
+                static const int pm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+                for (int w = 0; w < 6; ++w)
+                    T3[a3[pm[w][0]]][a3[pm[w][1]]][a3[pm[w][2]]] = c[10 + u];
+            }
             const double y[3] = {xi - zg[0], yi - zg[1], zi - zg[2]};
-            const double ky[3] = {(c[4] * y[0] + c[7] * y[1]) + c[8] * y[2],
-                                  (c[7] * y[0] + c[5] * y[1]) + c[9] * y[2],
-                                  (c[8] * y[0] + c[9] * y[1]) + c[6] * y[2]};
-            nsum_add(&ax, c[1] + ky[0]);
-            nsum_add(&ay, c[2] + ky[1]);
-            nsum_add(&az, c[3] + ky[2]);
+            double ky[3], tyy[3];
+            for (int k = 0; k < 3; ++k) {
+                ky[k] = (K[k][0] * y[0] + K[k][1] * y[1]) + K[k][2] * y[2];
+                tyy[k] = 0.0;
+                for (int l = 0; l < 3; ++l)
+                    for (int m2 = 0; m2 < 3; ++m2)
+                        tyy[k] += T3[k][l][m2] * y[l] * y[m2];
+            }
+            nsum_add(&ax, c[1] + ky[0] + 0.5 * tyy[0]);
+            nsum_add(&ay, c[2] + ky[1] + 0.5 * tyy[1]);
+            nsum_add(&az, c[3] + ky[2] + 0.5 * tyy[2]);
             const double py = (c[1] * y[0] + c[2] * y[1]) + c[3] * y[2];
             const double yky = (y[0] * ky[0] + y[1] * ky[1]) + y[2] * ky[2];
-            nsum_add(&ph, c[0] + py + 0.5 * yky);
+            const double ytyy = (y[0] * tyy[0] + y[1] * tyy[1]) + y[2] * tyy[2];
+            nsum_add(&ph, c[0] + py + 0.5 * yky + ytyy / 6.0);
         }
         for (int64_t q = 0; q < nf + nnr; ++q) {
             const int64_t c = q < nf ? far[q] : near[q - nf];

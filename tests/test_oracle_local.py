@@ -1,16 +1,21 @@
 """Pins of the oracle's group local expansions (the fast multipole method's
 M2L and L2P steps, taken at the level of the target groups, with cells
-carrying their quadrupole expansion).
+carrying their quadrupole expansion and the local expansion taken to third
+order).
 
 A far probe: a 64-body cell near the origin and 64 massless targets in a
 cluster of size s around R u. With the cell in the targets' local list, the
 local expansion differs from evaluating the cell at each target (the
-quadrupole cells) only by the second-order Taylor remainder. That
-difference must fall as s^3 at fixed R, and as (s/R)^3 relative to the field
-at fixed s, so a wrong gradient or Hessian term fails. The L2P force is
-minus the gradient of the L2P potential in the target position. theta = 0 is
-the direct sum, and in a Plummer tree the error stays near the quadrupole
-cells' and below the monopole cells'.
+quadrupole cells) only by the third-order Taylor remainder. That difference
+must fall as s^4 in the potential and s^3 in the force at fixed R, and as
+(s/R)^4 relative to the field at fixed s, so a wrong term of any order
+fails. At the expansion centre the coefficients are read back (the
+potential and force there, the Hessian from central differences, the third
+derivatives from second differences along the axes and face diagonals) and
+compared with the quadrupole cell's own values and differences. The L2P
+force is minus the gradient of the L2P potential in the target position.
+theta = 0 is the direct sum, and in a Plummer tree the error stays near the
+quadrupole cells' and below the monopole cells'.
 """
 import numpy as np
 import pytest
@@ -49,7 +54,7 @@ def test_probe_puts_the_cell_in_the_local_list(orc):
     assert c["far_cnt"].sum() == 0
 
 
-def test_taylor_remainder_falls_as_s_cubed(orc):
+def test_taylor_remainder_falls_as_s_to_the_fourth(orc):
     """An elongated cell at R = 8 (its quadrupole is a few per cent of the
     field there) and target clusters of s = 0.2 .. 0.025: a wrong term in
     the gradient or Hessian leaves a difference of order s or s^2 that the
@@ -65,9 +70,9 @@ def test_taylor_remainder_falls_as_s_cubed(orc):
     rp = d[:-1, 0] / d[1:, 0]
     ra = d[:-1, 1] / d[1:, 1]
     print("potential remainder ratios", rp, "force remainder ratios", ra)
-    assert np.all((rp > 7.6) & (rp < 8.4)), rp
-    # the force carries the remainder one order lower (the gradient of a cubic)
-    assert np.all((ra > 3.8) & (ra < 4.2)), ra
+    assert np.all((rp > 15.2) & (rp < 16.8)), rp
+    # the force carries the remainder one order lower (the gradient of a quartic)
+    assert np.all((ra > 7.6) & (ra < 8.4)), ra
 
 
 def test_taylor_remainder_falls_with_distance(orc):
@@ -78,7 +83,7 @@ def test_taylor_remainder_falls_with_distance(orc):
         d.append(np.sqrt(np.mean((p4 - p3) ** 2)) / np.abs(p3).mean())
     r = np.array(d[:-1]) / np.array(d[1:])
     print("relative remainder ratios per doubling of R", r)
-    assert np.all((r > 7) & (r < 9)), r
+    assert np.all((r > 15) & (r < 17)), r
 
 
 @pytest.mark.parametrize("eps", [0.0, 0.5])
@@ -143,23 +148,24 @@ def test_lists_are_no_longer_than_the_quadrupole_walks(orc):
 
 def test_expansion_coefficients_at_the_centre(orc):
     """Targets symmetric about z = (8, 1, -0.5) (so the group's centre is z
-    exactly): at z the local expansion must give the quadrupole cell's own
-    potential and force (P0 and p), and across z +- h e_l its force changes
-    by exactly 2 h K e_l, which must equal the central difference of the
-    quadrupole cell's force (the Hessian) to O((h/R)^2)."""
+    exactly) include z, z +- h e_l and z +- h (e_k + e_l).  At z the local
+    expansion gives the quadrupole cell's own potential and force (P0, p);
+    across +-h d its force changes by exactly 2 h K d (central difference) and
+    its second difference is exactly h^2 T(d, d); both must equal the
+    quadrupole cell's differences to O((h/R)^2)."""
     rng = np.random.default_rng(74)
     cell = np.c_[rng.uniform(-0.5, 0.5, (64, 3)) * np.array([2.0, 0.4, 0.3]), rng.uniform(0.5, 1.5, 64)]
     z = np.array([8.0, 1.0, -0.5])
     h = 2.0 ** -10
+    dirs = [np.eye(3)[k] for k in range(3)] + [np.array(v, dtype=float) for v in ((1, 1, 0), (1, 0, 1), (0, 1, 1))]
     offs = [np.zeros(3)]
-    for k in range(3):
-        e = np.zeros(3)
-        e[k] = h
-        offs += [e, -e]
-    for _ in range(28):
+    for d_ in dirs:
+        offs += [h * d_, -h * d_]
+    for _ in range(25):
         v = np.round(rng.uniform(-0.25, 0.25, 3) * 256) / 256
         offs += [v, -v]
     offs.append(np.array([0.0625, 0.03125, 0.0]))
+    assert len(offs) == 64
     tg = np.c_[z + np.array(offs), np.zeros(64)]
     pm = np.r_[cell, tg]
     perm = orc.orb_order(pm, 64)
@@ -179,7 +185,10 @@ def test_expansion_coefficients_at_the_centre(orc):
         a4, p4, a3, p3 = a4[it], p4[it], a3[it], p3[it]
         np.testing.assert_allclose(a4[0], a3[0], rtol=1e-12)
         np.testing.assert_allclose(p4[0], p3[0], rtol=1e-13)
-        K4 = np.stack([(a4[1 + 2 * l] - a4[2 + 2 * l]) / (2 * h) for l in range(3)], axis=1)
-        K3 = np.stack([(a3[1 + 2 * l] - a3[2 + 2 * l]) / (2 * h) for l in range(3)], axis=1)
-        np.testing.assert_allclose(K4, K3, rtol=0, atol=1e-6 * np.abs(K3).max())
-        np.testing.assert_allclose(K4, K4.T, rtol=0, atol=1e-12 * np.abs(K4).max())
+        for j in range(len(dirs)):
+            kd4 = (a4[1 + 2 * j] - a4[2 + 2 * j]) / (2 * h)
+            kd3 = (a3[1 + 2 * j] - a3[2 + 2 * j]) / (2 * h)
+            np.testing.assert_allclose(kd4, kd3, rtol=0, atol=1e-6 * np.abs(kd3).max())
+            td4 = (a4[1 + 2 * j] + a4[2 + 2 * j] - 2 * a4[0]) / h ** 2
+            td3 = (a3[1 + 2 * j] + a3[2 + 2 * j] - 2 * a3[0]) / h ** 2
+            np.testing.assert_allclose(td4, td3, rtol=0, atol=1e-5 * np.abs(td3).max())
