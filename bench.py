@@ -22,9 +22,10 @@ Also reported on the same JSON line:
   ratio for the bit-reversible fixed-point leapfrog (no checkpoints);
 * batched: aggregate G-interactions/s for 512 ragged Plummer systems, 50
   steps captured in one HIP graph;
-* tree: the tree code on the ORB cells of the same colliding pair, monopole
-  and order-2 (pseudo-particle) cells at theta 0.5, 0.7, 1.0: time, work and
-  error against the exact sum;
+* tree: the tree code on the ORB cells of the same colliding pair with the
+  four cell models (monopole, pseudo-particle, quadrupole, group local
+  expansions) at theta 0.5, 0.7, 1.0: time, work and error against the exact
+  sum;
 * shard: one GPU's share of an 8-way target split (131072 x 1048576).
 """
 from __future__ import annotations
@@ -43,6 +44,7 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (AMD), packed FP32 counted
 FLOP_PER_PAIR = 20
 FLOP_PER_QUAD_CELL = 54   # one quadrupole cell against one target, counted like the pair's 20
+FLOP_PER_M2L = 313        # one cell folded into a group's third-order local expansion (m2l_f32)
 
 
 def log(msg):
@@ -110,11 +112,11 @@ def main():
     if args.tree_cells:
         q = nb.permute(pm, nb.orb_order(pm, 4))
         out = torch.empty_like(q)
-        for cells in (nb.CELLS_MONOPOLE, nb.CELLS_PSEUDO, nb.CELLS_QUADRUPOLE):
+        for cells in (nb.CELLS_MONOPOLE, nb.CELLS_PSEUDO, nb.CELLS_QUADRUPOLE, nb.CELLS_LOCAL):
             for _ in range(2):
                 nb.tree_accel(q, eps, 0.7, 4, prec=prec, out=out, cells=cells)
         torch.cuda.synchronize()
-        log("[bench] tree cells mode: 2 evaluations per cell model (0, 2, 3), theta 0.7, leaf 4, F32_F64ACC")
+        log("[bench] tree cells mode: 2 evaluations per cell model (0, 2, 3, 4), theta 0.7, leaf 4, F32_F64ACC")
         return
 
     # ORB body order (the paper's recursive bisection, used as an ordering):
@@ -485,7 +487,7 @@ def tree_leg(torch, nb, pm_np, eps, direct_ms, leaf=4):
     pseudo = torch.empty((nn, nb.TREE_PSEUDO, 4), dtype=torch.float32, device=dev)
     stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     quad = torch.empty((nn, 3, 4), dtype=torch.float32, device=dev)
-    res["pseudo_cells"], res["quadrupole_cells"] = {}, {}
+    res["pseudo_cells"], res["quadrupole_cells"], res["local_cells"] = {}, {}, {}
 
     def moments_only(cells):
         # monopole moments; for the other models also the second moments and
@@ -495,6 +497,7 @@ def tree_leg(torch, nb, pm_np, eps, direct_ms, leaf=4):
         if cells == nb.CELLS_PSEUDO:
             return L.nbody_tree_pseudo(ctypes.c_void_p(q.data_ptr()), n, leaf,
                                        ctypes.c_void_p(pseudo.data_ptr()), stream)
+        # quadrupole records serve both the quadrupole and the local-expansion cells
         return L.nbody_tree_quad(ctypes.c_void_p(q.data_ptr()), n, leaf, ctypes.c_void_p(quad.data_ptr()), stream)
 
     for theta in (0.5, 0.7, 1.0):
@@ -505,13 +508,24 @@ def tree_leg(torch, nb, pm_np, eps, direct_ms, leaf=4):
         fc, ncnt, ni = fc.cpu().numpy(), ncnt.cpu().numpy(), ni.cpu().numpy()
         sizes = nodes[:, 1] - nodes[:, 0]
         near_bodies = np.array([sizes[ni[g, :ncnt[g]]].sum() for g in range(len(groups))], dtype=np.float64)
-        for order in (nb.CELLS_MONOPOLE, nb.CELLS_PSEUDO, nb.CELLS_QUADRUPOLE):
+        for order in (nb.CELLS_MONOPOLE, nb.CELLS_PSEUDO, nb.CELLS_QUADRUPOLE, nb.CELLS_LOCAL):
             per_cell = nb.TREE_PSEUDO if order == nb.CELLS_PSEUDO else 1
-            pairs = float((gsz * (per_cell * fc + near_bodies) + gsz * (gsz - 1)).sum())
-            # walk flops: 20 per body or pseudo-body pair, 54 per quadrupole cell
-            flops = FLOP_PER_PAIR * pairs
-            if order == nb.CELLS_QUADRUPOLE:
-                flops += (FLOP_PER_QUAD_CELL - FLOP_PER_PAIR) * float((gsz * fc).sum())
+            extra = {}
+            if order == nb.CELLS_LOCAL:
+                # the local walk's own lists (counts only; near leaves taken as full)
+                lc, fc4, nc4 = (t.cpu().numpy().astype(np.float64) for t in nb.tree_local_counts(q, theta, leaf))
+                pairs = float((gsz * (fc4 + nc4 * leaf) + gsz * (gsz - 1)).sum())
+                flops = (FLOP_PER_PAIR * float((gsz * (nc4 * leaf) + gsz * (gsz - 1)).sum())
+                         + FLOP_PER_QUAD_CELL * float((gsz * fc4).sum()) + FLOP_PER_M2L * float(lc.sum()))
+                extra = {"local_cells_per_group": round(float(lc.mean()), 1),
+                         "per_target_cells_per_group": round(float(fc4.mean()), 1),
+                         "near_leaves_per_group": round(float(nc4.mean()), 1)}
+            else:
+                pairs = float((gsz * (per_cell * fc + near_bodies) + gsz * (gsz - 1)).sum())
+                # walk flops: 20 per body or pseudo-body pair, 54 per quadrupole cell
+                flops = FLOP_PER_PAIR * pairs
+                if order == nb.CELLS_QUADRUPOLE:
+                    flops += (FLOP_PER_QUAD_CELL - FLOP_PER_PAIR) * float((gsz * fc).sum())
             nb.tree_accel(q, eps, theta, leaf, prec=nb.F32_F64ACC, out=out, cells=order)
             torch.cuda.synchronize()
             ts, tm = [], []
@@ -534,7 +548,7 @@ def tree_leg(torch, nb, pm_np, eps, direct_ms, leaf=4):
             rel = np.linalg.norm(got[:, :3] - d_host[:, :3], axis=1) / np.linalg.norm(d_host[:, :3], axis=1)
             walk_tflops = flops / (t_walk * 1e-3) / 1e12
             kern = {0: "k_tree_walk<F64ACC>", 2: "k_tree_walk<F64ACC, pseudo-particle cells>",
-                    3: "k_tree_walk<F64ACC, quadrupole cells>"}[order]
+                    3: "k_tree_walk<F64ACC, quadrupole cells>", 4: "k_tree_walk<F64ACC, local expansions>"}[order]
             r = {"ms": round(t, 4), "ms_std": round(float(np.std(ts)), 4), "moments_ms": round(t_mom, 4),
                  "walk_force_ms": round(t_walk, 4), "interactions_per_body": round(pairs / n, 1),
                  "far_cells_per_group": round(float(fc.mean()), 1),
@@ -546,8 +560,10 @@ def tree_leg(torch, nb, pm_np, eps, direct_ms, leaf=4):
                  "walk_roofline": {"bound": "alu", "achieved": round(walk_tflops, 3), "peak": PEAK_FP32_TFLOPS,
                                    "unit": "TFLOP/s", "frac": round(walk_tflops / PEAK_FP32_TFLOPS, 4),
                                    "kernel": kern, "flop_per_pair": FLOP_PER_PAIR,
-                                   "flop_per_quadrupole_cell": FLOP_PER_QUAD_CELL}}
-            {0: res["theta"], 2: res["pseudo_cells"], 3: res["quadrupole_cells"]}[order][str(theta)] = r
+                                   "flop_per_quadrupole_cell": FLOP_PER_QUAD_CELL, "flop_per_m2l": FLOP_PER_M2L}}
+            r.update(extra)
+            {0: res["theta"], 2: res["pseudo_cells"], 3: res["quadrupole_cells"],
+             4: res["local_cells"]}[order][str(theta)] = r
             log(f"[bench] tree cells {order} theta {theta}: {t:.3f} ms ({t_mom:.3f} moments), "
                 f"{pairs / n:.0f} interactions/body, {walk_tflops:.1f} TFLOP/s in the walk, "
                 f"x{direct_ms / t:.1f} vs direct, rms err {r['rms_rel_err_vs_direct']:.2e}")

@@ -263,6 +263,15 @@ int nbody_trajectory_adjoint(const void *ckpt, int64_t n, int32_t prec, double G
  *   and s^2 = |d|^2 + eps^2, phi = -G (M/s + d.Q.d / (2 s^5)) and
  *   a = G (-M d/s^3 + Q d/s^5 - 5 (d.Q.d) d / (2 s^7)).  The same accuracy
  *   as the pseudo-particles for a fraction of the work.
+ * NBODY_CELLS_LOCAL (the fast multipole method's M2L and L2P steps, at the
+ *   level of the target groups): a cell c with diag2_c + diag2_g <
+ *   theta^2 |com_c - z_g|^2 (z_g = the group's centre of mass, in FP64)
+ *   enters the group's third-order Taylor expansion, about z_g, of the
+ *   quadrupole cell's potential (one order above the cells', so that the
+ *   force keeps their third-order error); each target evaluates that
+ *   expansion at its own position.  Other cells are tested and evaluated as
+ *   for NBODY_CELLS_QUADRUPOLE.  The local test bounds the combined
+ *   size-to-distance ratio of cell and group by sqrt(2) theta.
  *
  * nbody_tree_shape (host only): node and group counts; nodes_out, if not
  *   NULL, receives int32[num_nodes][4] = (begin, end, left, right), -1
@@ -278,6 +287,10 @@ int nbody_trajectory_adjoint(const void *ckpt, int64_t n, int32_t prec, double G
  *   rounded to FP32).
  * nbody_tree_quad (inspection): quad_out = float4[num_nodes][3] =
  *   (com, M), (Qxx, Qyy, Qzz, Qxy), (Qxz, Qyz, 0, 0) in FP32.
+ * nbody_tree_local_counts (inspection): per group, the numbers of cells in
+ *   the local expansion (loc_count), of cells evaluated per target
+ *   (far_count) and of rejected leaves outside the group (near_count) in
+ *   the NBODY_CELLS_LOCAL walk.
  * nbody_tree_moments (inspection): moments_out double[num_nodes][5] =
  *   (M, com_x, com_y, com_z, diag2), box_out float[num_nodes][6] =
  *   (lo_x, lo_y, lo_z, hi_x, hi_y, hi_z); either may be NULL.
@@ -298,8 +311,9 @@ int nbody_trajectory_adjoint(const void *ckpt, int64_t n, int32_t prec, double G
  * that it keeps naming the caller's index of the body at position p;
  * K = 0 never re-orders (order may be NULL).  flags: NBODY_ACC_VALID,
  * NBODY_ENERGY (energy_out as for nbody_leapfrog_kdk, with the tree
- * potential), NBODY_TREE_PSEUDO_CELLS or NBODY_TREE_QUAD_CELLS (the cell
- * model; monopole without either, both together are NBODY_E_INVAL).
+ * potential), NBODY_TREE_PSEUDO_CELLS, NBODY_TREE_QUAD_CELLS or
+ * NBODY_TREE_LOCAL_CELLS (the cell model; monopole without any, two or more
+ * are NBODY_E_INVAL).
  * Re-ordering uses library scratch of about 24 bytes per body.
  */
 #define NBODY_TREE_GROUP 64
@@ -307,8 +321,10 @@ int nbody_trajectory_adjoint(const void *ckpt, int64_t n, int32_t prec, double G
 #define NBODY_CELLS_MONOPOLE 0
 #define NBODY_CELLS_PSEUDO 2
 #define NBODY_CELLS_QUADRUPOLE 3
+#define NBODY_CELLS_LOCAL 4
 #define NBODY_TREE_PSEUDO_CELLS 0x8u /* nbody_tree_leapfrog flags */
 #define NBODY_TREE_QUAD_CELLS 0x20u
+#define NBODY_TREE_LOCAL_CELLS 0x40u
 int nbody_tree_shape(int64_t n, int32_t leaf, int64_t *num_nodes, int64_t *num_groups,
                      int32_t *nodes_out);
 int nbody_tree_accel(const void *pos_mass, int64_t n, int32_t prec, double G, double eps,
@@ -319,6 +335,9 @@ int nbody_tree_accel_cells(const void *pos_mass, int64_t n, int32_t prec, double
 int nbody_tree_pseudo(const void *pos_mass, int64_t n, int32_t leaf, void *pseudo_out,
                       void *stream);
 int nbody_tree_quad(const void *pos_mass, int64_t n, int32_t leaf, void *quad_out, void *stream);
+int nbody_tree_local_counts(const void *pos_mass, int64_t n, int32_t leaf, double theta,
+                            int32_t *loc_count, int32_t *far_count, int32_t *near_count,
+                            void *stream);
 int nbody_tree_moments(const void *pos_mass, int64_t n, int32_t leaf, double *moments_out,
                        float *box_out, void *stream);
 int nbody_tree_lists(const void *pos_mass, int64_t n, int32_t leaf, double theta,

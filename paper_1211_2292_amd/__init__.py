@@ -26,7 +26,8 @@ __all__ = [
     "permute", "trajectory_forward", "trajectory_adjoint", "NBodyTrajectory", "autotune",
     "set_tuning", "get_tuning", "release", "NBodyError", "TREE_GROUP", "tree_shape", "tree_accel",
     "tree_moments", "tree_lists", "tree_leapfrog", "tree_pseudo", "tree_quad", "TREE_PSEUDO",
-    "CELLS_MONOPOLE", "CELLS_PSEUDO", "CELLS_QUADRUPOLE", "janus_forward", "janus_adjoint",
+    "CELLS_MONOPOLE", "CELLS_PSEUDO", "CELLS_QUADRUPOLE", "CELLS_LOCAL", "tree_local_counts",
+    "janus_forward", "janus_adjoint",
 ]
 
 F64, F32, F32_KAHAN, F32_F64ACC = 0, 1, 2, 3
@@ -35,8 +36,8 @@ ACC_VALID, GRAPH, ENERGY = 0x1, 0x2, 0x4
 KERNEL_ACCEL, KERNEL_BATCHED, KERNEL_VJP = 0, 1, 2
 TREE_GROUP = 64
 TREE_PSEUDO = 12      # pseudo-particles per cell (CELLS_PSEUDO)
-CELLS_MONOPOLE, CELLS_PSEUDO, CELLS_QUADRUPOLE = 0, 2, 3   # tree cell models
-_TREE_CELL_FLAGS = {CELLS_MONOPOLE: 0, CELLS_PSEUDO: 0x8, CELLS_QUADRUPOLE: 0x20}
+CELLS_MONOPOLE, CELLS_PSEUDO, CELLS_QUADRUPOLE, CELLS_LOCAL = 0, 2, 3, 4   # tree cell models
+_TREE_CELL_FLAGS = {CELLS_MONOPOLE: 0, CELLS_PSEUDO: 0x8, CELLS_QUADRUPOLE: 0x20, CELLS_LOCAL: 0x40}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libnbody.so")
@@ -66,6 +67,7 @@ _SIGS = {
     "nbody_tree_accel_cells": [_vp, _i64, _i32, _dbl, _dbl, _dbl, _i32, _i32, _vp, _vp],
     "nbody_tree_pseudo": [_vp, _i64, _i32, _vp, _vp],
     "nbody_tree_quad": [_vp, _i64, _i32, _vp, _vp],
+    "nbody_tree_local_counts": [_vp, _i64, _i32, _dbl, _vp, _vp, _vp, _vp],
     "nbody_tree_moments": [_vp, _i64, _i32, _vp, _vp, _vp],
     "nbody_tree_lists": [_vp, _i64, _i32, _dbl, _i32, _i32, _vp, _vp, _vp, _vp, _vp],
     "nbody_tree_leapfrog": [_vp, _vp, _vp, _vp, _i64, _i32, _dbl, _dbl, _dbl, _i32, _dbl, _i32, _i32,
@@ -292,7 +294,9 @@ def tree_shape(n, leaf, nodes=False):
 def tree_accel(pos_mass, eps, theta, leaf=4, G=1.0, prec=None, out=None, cells=CELLS_MONOPOLE):
     """Tree-code force and potential (ax, ay, az, phi) per body, ORB order.
     cells: CELLS_MONOPOLE (accepted cells as one body), CELLS_PSEUDO (as their
-    12 pseudo-particles) or CELLS_QUADRUPOLE (their quadrupole expansion)."""
+    12 pseudo-particles), CELLS_QUADRUPOLE (their quadrupole expansion) or
+    CELLS_LOCAL (quadrupole cells, those far from the whole group through the
+    group's local expansion)."""
     pm = _rec(pos_mass, "pos_mass", torch.float32)
     p = _prec(pm, prec)
     if out is None:
@@ -314,6 +318,17 @@ def tree_pseudo(pos_mass, leaf=4):
     out = torch.empty((nn, TREE_PSEUDO, 4), dtype=torch.float32, device=pm.device)
     _check(lib().nbody_tree_pseudo(_ptr(pm), pm.shape[0], int(leaf), _ptr(out), _stream()))
     return out
+
+
+def tree_local_counts(pos_mass, theta, leaf=4):
+    """Per-group list sizes of the local-expansion walk: (loc, far, near)
+    int32 (groups,)."""
+    pm = _rec(pos_mass, "pos_mass", torch.float32)
+    _, ng = tree_shape(pm.shape[0], leaf)
+    cnt = [torch.empty(ng, dtype=torch.int32, device=pm.device) for _ in range(3)]
+    _check(lib().nbody_tree_local_counts(_ptr(pm), pm.shape[0], int(leaf), float(theta), _ptr(cnt[0]),
+                                         _ptr(cnt[1]), _ptr(cnt[2]), _stream()))
+    return tuple(cnt)
 
 
 def tree_quad(pos_mass, leaf=4):
@@ -372,7 +387,7 @@ def tree_leapfrog(pos_mass, vel, acc, eps, theta, dt, nsteps, leaf=4, reorder_ev
         raise ValueError("order must be a contiguous int32 tensor of N entries")
     en = torch.empty((nsteps + 1, 2), dtype=torch.float64, device=pm.device) if energy else None
     if cells not in _TREE_CELL_FLAGS:
-        raise ValueError("cells must be CELLS_MONOPOLE, CELLS_PSEUDO or CELLS_QUADRUPOLE")
+        raise ValueError("cells must be CELLS_MONOPOLE, CELLS_PSEUDO, CELLS_QUADRUPOLE or CELLS_LOCAL")
     flags = (ACC_VALID if acc_valid else 0) | (ENERGY if energy else 0) | _TREE_CELL_FLAGS[cells]
     _check(lib().nbody_tree_leapfrog(_ptr(pm), _ptr(v), _ptr(a), None if order is None else _ptr(order), n, p,
                                      float(G), float(eps), float(theta), int(leaf), float(dt), int(nsteps),

@@ -123,6 +123,8 @@ int tree_accel(const void *pm, int n, int prec, double G, double eps, double the
                void *out, hipStream_t s);
 int tree_pseudo(const void *pm, int n, int leaf, void *out, hipStream_t s);
 int tree_quad(const void *pm, int n, int leaf, void *out, hipStream_t s);
+int tree_local_counts(const void *pm, int n, int leaf, double theta, int32_t *loc_cnt, int32_t *far_cnt,
+                      int32_t *near_cnt, hipStream_t s);
 int tree_leapfrog(void *pm, void *vel, void *acc, int32_t *order, int n, int prec, double G, double eps,
                   double theta, int leaf, double dt, int nsteps, int reorder_every, unsigned flags,
                   double *energy, hipStream_t s);

@@ -780,8 +780,9 @@ int nbody_tree_accel_cells(const void *pos_mass, int64_t n, int32_t prec, double
                            int32_t leaf, int32_t cells, void *acc_pot_out, void *stream)
 {
     NB_CHECK(check_tree(n, leaf));
-    if (cells != NBODY_CELLS_MONOPOLE && cells != NBODY_CELLS_PSEUDO && cells != NBODY_CELLS_QUADRUPOLE) {
-        set_error("cell model %d (NBODY_CELLS_MONOPOLE, _PSEUDO or _QUADRUPOLE)", cells);
+    if (cells != NBODY_CELLS_MONOPOLE && cells != NBODY_CELLS_PSEUDO && cells != NBODY_CELLS_QUADRUPOLE &&
+        cells != NBODY_CELLS_LOCAL) {
+        set_error("cell model %d (NBODY_CELLS_MONOPOLE, _PSEUDO, _QUADRUPOLE or _LOCAL)", cells);
         return NBODY_E_INVAL;
     }
     if (!prec_ok(prec)) {
@@ -805,6 +806,21 @@ int nbody_tree_pseudo(const void *pos_mass, int64_t n, int32_t leaf, void *pseud
     NB_CHECK(check_vec(pos_mass, NBODY_F32, "pos_mass"));
     NB_CHECK(check_vec(pseudo_out, NBODY_F32, "pseudo_out"));
     return tree_pseudo(pos_mass, (int)n, leaf, pseudo_out, (hipStream_t)stream);
+}
+
+int nbody_tree_local_counts(const void *pos_mass, int64_t n, int32_t leaf, double theta, int32_t *loc_count,
+                            int32_t *far_count, int32_t *near_count, void *stream)
+{
+    NB_CHECK(check_tree(n, leaf));
+    NB_CHECK(check_theta(theta));
+    NB_CHECK(check_vec(pos_mass, NBODY_F32, "pos_mass"));
+    if (!loc_count || !far_count || !near_count || ((uintptr_t)loc_count % 4) || ((uintptr_t)far_count % 4) ||
+        ((uintptr_t)near_count % 4)) {
+        set_error("count arrays NULL or misaligned");
+        return NBODY_E_INVAL;
+    }
+    return tree_local_counts(pos_mass, (int)n, leaf, theta, loc_count, far_count, near_count,
+                             (hipStream_t)stream);
 }
 
 int nbody_tree_quad(const void *pos_mass, int64_t n, int32_t leaf, void *quad_out, void *stream)
@@ -856,8 +872,10 @@ int nbody_tree_leapfrog(void *pos_mass, void *vel, void *acc_pot, int32_t *order
         set_error("the tree code runs the FP32 modes only");
         return NBODY_E_UNSUPPORTED;
     }
-    if ((flags & ~(NBODY_ACC_VALID | NBODY_ENERGY | NBODY_TREE_PSEUDO_CELLS | NBODY_TREE_QUAD_CELLS)) ||
-        ((flags & NBODY_TREE_PSEUDO_CELLS) && (flags & NBODY_TREE_QUAD_CELLS))) {
+    const uint32_t cell_flags = flags & (NBODY_TREE_PSEUDO_CELLS | NBODY_TREE_QUAD_CELLS | NBODY_TREE_LOCAL_CELLS);
+    if ((flags & ~(NBODY_ACC_VALID | NBODY_ENERGY | NBODY_TREE_PSEUDO_CELLS | NBODY_TREE_QUAD_CELLS |
+                   NBODY_TREE_LOCAL_CELLS)) ||
+        (cell_flags & (cell_flags - 1))) {
         set_error("unsupported flags 0x%x (NBODY_ACC_VALID, NBODY_ENERGY and one cell-model flag only)", flags);
         return NBODY_E_INVAL;
     }

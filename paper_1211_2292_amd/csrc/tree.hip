@@ -60,6 +60,19 @@
 // accepted cells' 3 records are staged in LDS and swept after every walk
 // step, so the cell values reach the arithmetic as vector operands (read
 // from scalar registers they issue at about two thirds of the rate).
+//
+// Group local expansions (the fast multipole method's M2L and L2P steps at
+// the level of the target groups): a cell with diag2_c + diag2_g <
+// theta^2 |com_c - z_g|^2 (z_g the group's centre of mass) enters one
+// third-order Taylor expansion of its quadrupole potential about z_g (one
+// order above the cells', so that the force keeps a third-order error)
+// instead of being evaluated at every target.  One lane folds one cell in
+// (about 110 VALU, lanes over cells); the twenty coefficients are summed
+// over the wave at the end and every lane evaluates the expansion at its
+// body.
+// The remaining cells go through the quadrupole path or are opened, with
+// the same tests as above; every decision is the FP64 expression of the
+// definitions, so the lists equal the FP64 definition's.
 #include <cstdint>
 #include <cstring>
 #include <mutex>
@@ -76,7 +89,7 @@ constexpr int kStack = 512;    // LDS stack entries per wave
 constexpr int kBuf = 128;      // LDS batch entries (cells, near ranges)
 constexpr int kPseudo = 12;    // pseudo-particles per cell (pseudo-particle cells)
 constexpr int kQuadRec = 3;    // float4 records per cell (quadrupole cells)
-constexpr int kCellsMono = 0, kCellsPseudo = 2, kCellsQuad = 3;
+constexpr int kCellsMono = 0, kCellsPseudo = 2, kCellsQuad = 3, kCellsLocal = 4;
 
 struct TreeDev {
     const int4 *node;    // begin, end, left, right (-1 for a leaf)
@@ -269,8 +282,86 @@ __device__ __forceinline__ unsigned lane_rank(unsigned long long mask)
 struct WalkOut {
     float4 *acc_pot;   // force mode: ORB-ordered output records
     int *far_cnt, *near_cnt, *far_ids, *near_ids;  // inspection mode
+    int *loc_cnt;      // inspection of the local-expansion walk
     int max_far, max_near;
 };
+
+// Third-order local expansion about the group's centre: P0, p (x, y, z),
+// K (xx, yy, zz, xy, xz, yz), T (xxx, yyy, zzz, xxy, xxz, xyy, yyz, xzz,
+// yzz, xyz) of the potential sum.
+struct Local {
+    float c[20];
+};
+
+// Folds one quadrupole cell (records (com, M), (Qxx, Qyy, Qzz, Qxy),
+// (Qxz, Qyz, -, -)) into L, expanded about zg: with r = zg - com,
+// s^2 = |r|^2 + eps^2 and u = r / s,
+//   P0   += M/s + (u.Q.u) / (2 s^3)
+//   p_k  += u_k (-M/s^2 - 5 (u.Q.u) / (2 s^4)) + (Q u)_k / s^4
+//   K_kl += u_k u_l (3 M/s^3 + 35 (u.Q.u) / (2 s^5)) - 5 ((Q u)_k u_l + (Q u)_l u_k) / s^5
+//           + Q_kl / s^5 - delta_kl (M/s^3 + 5 (u.Q.u) / (2 s^5))
+//   T_klm += A u_k u_l u_m + B (q_k u_l u_m + q_l u_k u_m + q_m u_k u_l)
+//            + C (d_kl u_m + d_km u_l + d_lm u_k)
+//            + D (Q_kl u_m + Q_km u_l + Q_lm u_k + q_k d_lm + q_l d_km + q_m d_kl)
+//     with q = Q u, A = -15 M/s^4 - 315 (u.Q.u) / (2 s^6), B = 35 / s^6,
+//     C = 3 M/s^4 + 35 (u.Q.u) / (2 s^6), D = -5 / s^6
+// (the derivatives of M/s + (r.Q.r) / (2 s^5) written with u, so that no
+// power above s^-6 is formed).
+__device__ __forceinline__ void m2l_f32(const float4 *__restrict__ rec, float zx, float zy, float zz, float eps2,
+                                        Local &L)
+{
+    const float4 c = rec[0], q1 = rec[1], q2 = rec[2];
+    const float rx = zx - c.x, ry = zy - c.y, rz = zz - c.z;
+    const float s2 = __builtin_fmaf(rz, rz, __builtin_fmaf(ry, ry, __builtin_fmaf(rx, rx, eps2)));
+    const float si = __builtin_amdgcn_rsqf(s2);
+    const float ux = rx * si, uy = ry * si, uz = rz * si;
+    const float si2 = si * si, si3 = si2 * si, si4 = si2 * si2, si5 = si4 * si;
+    const float qx = __builtin_fmaf(q1.x, ux, __builtin_fmaf(q1.w, uy, q2.x * uz));
+    const float qy = __builtin_fmaf(q1.w, ux, __builtin_fmaf(q1.y, uy, q2.y * uz));
+    const float qz = __builtin_fmaf(q2.x, ux, __builtin_fmaf(q2.y, uy, q1.z * uz));
+    const float uqu = __builtin_fmaf(ux, qx, __builtin_fmaf(uy, qy, uz * qz));
+    const float M = c.w;
+    L.c[0] += __builtin_fmaf(0.5f * uqu, si3, M * si);
+    const float cp = __builtin_fmaf(-2.5f * uqu, si4, -M * si2);
+    L.c[1] += __builtin_fmaf(ux, cp, qx * si4);
+    L.c[2] += __builtin_fmaf(uy, cp, qy * si4);
+    L.c[3] += __builtin_fmaf(uz, cp, qz * si4);
+    const float A = __builtin_fmaf(17.5f * uqu, si5, 3.0f * M * si3);
+    const float B = -5.0f * si5;
+    const float D = __builtin_fmaf(2.5f * uqu, si5, M * si3);
+    L.c[4] += __builtin_fmaf(ux * ux, A, __builtin_fmaf(2.0f * B, qx * ux, __builtin_fmaf(q1.x, si5, -D)));
+    L.c[5] += __builtin_fmaf(uy * uy, A, __builtin_fmaf(2.0f * B, qy * uy, __builtin_fmaf(q1.y, si5, -D)));
+    L.c[6] += __builtin_fmaf(uz * uz, A, __builtin_fmaf(2.0f * B, qz * uz, __builtin_fmaf(q1.z, si5, -D)));
+    L.c[7] += __builtin_fmaf(ux * uy, A, __builtin_fmaf(B, __builtin_fmaf(qx, uy, qy * ux), q1.w * si5));
+    L.c[8] += __builtin_fmaf(ux * uz, A, __builtin_fmaf(B, __builtin_fmaf(qx, uz, qz * ux), q2.x * si5));
+    L.c[9] += __builtin_fmaf(uy * uz, A, __builtin_fmaf(B, __builtin_fmaf(qy, uz, qz * uy), q2.y * si5));
+    const float si6 = si4 * si2;
+    const float a3 = __builtin_fmaf(-157.5f * uqu, si6, -15.0f * M * si4);
+    const float b3 = 35.0f * si6;
+    const float c3 = __builtin_fmaf(17.5f * uqu, si6, 3.0f * M * si4);
+    const float d3 = -5.0f * si6;
+    // T_kkk = a3 u_k^3 + 3 b3 q_k u_k^2 + 3 c3 u_k + 3 d3 (Q_kk u_k + q_k)
+    L.c[10] += __builtin_fmaf(a3 * ux, ux * ux, 3.0f * __builtin_fmaf(b3 * qx, ux * ux, __builtin_fmaf(c3, ux, d3 * __builtin_fmaf(q1.x, ux, qx))));
+    L.c[11] += __builtin_fmaf(a3 * uy, uy * uy, 3.0f * __builtin_fmaf(b3 * qy, uy * uy, __builtin_fmaf(c3, uy, d3 * __builtin_fmaf(q1.y, uy, qy))));
+    L.c[12] += __builtin_fmaf(a3 * uz, uz * uz, 3.0f * __builtin_fmaf(b3 * qz, uz * uz, __builtin_fmaf(c3, uz, d3 * __builtin_fmaf(q1.z, uz, qz))));
+    // T_kkm = a3 u_k^2 u_m + b3 (2 q_k u_k u_m + q_m u_k^2) + c3 u_m + d3 (Q_kk u_m + 2 Q_km u_k + q_m)
+    auto tkkm = [&](float uk, float um, float qk, float qm, float Qkk, float Qkm) {
+        const float uk2 = uk * uk;
+        return __builtin_fmaf(a3 * uk2, um,
+                              __builtin_fmaf(b3, __builtin_fmaf(2.0f * qk * uk, um, qm * uk2),
+                                             __builtin_fmaf(c3, um, d3 * __builtin_fmaf(Qkk, um, __builtin_fmaf(2.0f * Qkm, uk, qm)))));
+    };
+    L.c[13] += tkkm(ux, uy, qx, qy, q1.x, q1.w);  // xxy
+    L.c[14] += tkkm(ux, uz, qx, qz, q1.x, q2.x);  // xxz
+    L.c[15] += tkkm(uy, ux, qy, qx, q1.y, q1.w);  // xyy
+    L.c[16] += tkkm(uy, uz, qy, qz, q1.y, q2.y);  // yyz
+    L.c[17] += tkkm(uz, ux, qz, qx, q1.z, q2.x);  // xzz
+    L.c[18] += tkkm(uz, uy, qz, qy, q1.z, q2.y);  // yzz
+    // T_xyz = a3 ux uy uz + b3 (qx uy uz + qy ux uz + qz ux uy) + d3 (Qxy uz + Qxz uy + Qyz ux)
+    L.c[19] += __builtin_fmaf(a3 * ux, uy * uz,
+                              __builtin_fmaf(b3, __builtin_fmaf(qx, uy * uz, __builtin_fmaf(qy, ux * uz, qz * ux * uy)),
+                                             d3 * __builtin_fmaf(q1.w, uz, __builtin_fmaf(q2.x, uy, q2.y * ux))));
+}
 
 // Sweeps the batched pseudo-body records in LDS (broadcast reads).
 __device__ __forceinline__ void sweep_cells(const float4 *cb, int cnt, const Targets<float, 1> &T,
@@ -350,7 +441,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void k_
     __shared__ float4 cbuf[CELLS == kCellsMono ? kBuf : 1];    // monopole cells: the accepted records
     __shared__ int cid[CELLS == kCellsPseudo ? kBuf : 1];      // pseudo-particle cells: the accepted ids
     // quadrupole cells: the records of one step's accepted cells (swept every step)
-    __shared__ float4 qbuf[CELLS == kCellsQuad ? kQuadRec * kGroup : 1];
+    __shared__ float4 qbuf[CELLS >= kCellsQuad ? kQuadRec * kGroup : 1];
+    // local expansions: the ids of cells waiting to be folded in
+    __shared__ int lid[CELLS == kCellsLocal ? kBuf : 1];
     __shared__ int2 nbuf[kBuf];
     const int lane = threadIdx.x;
     const int g = blockIdx.x;
@@ -359,6 +452,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void k_
     const float4 glo = T.lo[gnode], ghi = T.hi[gnode];
     const double ax = glo.x, ay = glo.y, az = glo.z, bx = ghi.x, by = ghi.y, bz = ghi.z;
     const float eps2 = lane_copy(eps2_in);
+    const double4 gcd = T.comd[gnode];  // the group's centre of mass and diag2
+    const float zgx = (float)gcd.x, zgy = (float)gcd.y, zgz = (float)gcd.z;
+    Local Lx;
+#pragma unroll
+    for (int k = 0; k < 20; ++k) Lx.c[k] = 0.0f;
 
     Targets<float, 1> TT;
     const int i = gn.x + lane;
@@ -384,17 +482,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void k_
         ++top;
         c = left ? nd.z : nd.w;
     }
-    int nf = 0, nr = 0, tf = 0, tn = 0;
+    int nf = 0, nr = 0, tf = 0, tn = 0, nl = 0, tl = 0;
 
     auto flush_cells = [&]() {
         if constexpr (!INSPECT) {
             S.zero();
-            if constexpr (CELLS == kCellsPseudo)
+            if constexpr (CELLS == kCellsPseudo) {
                 sweep_pseudo(cells, cid, nf, TT, eps2, S);
-            else if constexpr (CELLS == kCellsQuad)
+            } else if constexpr (CELLS >= kCellsQuad) {
                 sweep_quad(qbuf, nf, TT, eps2, S);
-            else
+            } else {
+                static_assert(CELLS == kCellsMono, "unhandled cell model");
                 sweep_cells(cbuf, nf, TT, eps2, S);
+            }
             R[0].fold(S.ax[0]);
             R[1].fold(S.ay[0]);
             R[2].fold(S.az[0]);
@@ -426,6 +526,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void k_
         }
         nr = 0;
     };
+    auto flush_local = [&]() {
+        if constexpr (CELLS == kCellsLocal && !INSPECT) {
+            for (int b = 0; b < nl; b += kGroup)
+                if (b + lane < nl) m2l_f32(cells + (long)kQuadRec * lid[b + lane], zgx, zgy, zgz, eps2, Lx);
+        }
+        nl = 0;
+    };
 
     while (top > 0) {
         const int k = min(kGroup, top);
@@ -434,21 +541,28 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void k_
         const bool act = lane < k;
         const int c = act ? stk[top + lane] : 0;
         __syncthreads();
-        bool acc = false, nearr = false, open = false;
+        bool acc = false, nearr = false, open = false, loc = false;
         int4 nd = make_int4(0, 0, -1, -1);
         if (act) {
             nd = T.node[c];
             const double4 cd = T.comd[c];
-            const double dx = box_gap(cd.x, ax, bx);
-            const double dy = box_gap(cd.y, ay, by);
-            const double dz = box_gap(cd.z, az, bz);
-            const double D2 = (dx * dx + dy * dy) + dz * dz;
-            acc = cd.w < theta2 * D2;
-            if (!acc) {
-                if (nd.z < 0)
-                    nearr = true;
-                else
-                    open = true;
+            if constexpr (CELLS == kCellsLocal) {
+                const double ex = cd.x - gcd.x, ey = cd.y - gcd.y, ez = cd.z - gcd.z;
+                const double dz2 = (ex * ex + ey * ey) + ez * ez;
+                loc = cd.w + gcd.w < theta2 * dz2;
+            }
+            if (!loc) {
+                const double dx = box_gap(cd.x, ax, bx);
+                const double dy = box_gap(cd.y, ay, by);
+                const double dz = box_gap(cd.z, az, bz);
+                const double D2 = (dx * dx + dy * dy) + dz * dz;
+                acc = cd.w < theta2 * D2;
+                if (!acc) {
+                    if (nd.z < 0)
+                        nearr = true;
+                    else
+                        open = true;
+                }
             }
         }
         // children that would not fit on the stack are summed body by body
@@ -459,6 +573,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void k_
         }
         const unsigned long long ma = __ballot(acc), mn = __ballot(nearr), mo = __ballot(open);
         const int ca = __popcll(ma), cn = __popcll(mn), co = __popcll(mo);
+        const unsigned long long ml = CELLS == kCellsLocal ? __ballot(loc) : 0ull;
+        const int cl = __popcll(ml);
         if constexpr (INSPECT) {
             if (acc) {
                 const int q = tf + (int)lane_rank(ma);
@@ -470,18 +586,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void k_
             }
         } else {
             if (acc) {
-                if constexpr (CELLS == kCellsQuad) {
+                if constexpr (CELLS >= kCellsQuad) {
                     const int slot = nf + (int)lane_rank(ma);
                     const float4 *r = cells + (long)kQuadRec * c;
                     qbuf[kQuadRec * slot] = r[0];
                     qbuf[kQuadRec * slot + 1] = r[1];
                     qbuf[kQuadRec * slot + 2] = r[2];
-                } else if constexpr (CELLS == kCellsPseudo)
+                } else if constexpr (CELLS == kCellsPseudo) {
                     cid[nf + (int)lane_rank(ma)] = c;
-                else
+                } else {
+                    static_assert(CELLS == kCellsMono, "unhandled cell model");
                     cbuf[nf + (int)lane_rank(ma)] = T.rec[c];
+                }
             }
             if (nearr) nbuf[nr + (int)lane_rank(mn)] = make_int2(nd.x, nd.y);
+            if constexpr (CELLS == kCellsLocal) {
+                if (loc) lid[nl + (int)lane_rank(ml)] = c;
+            }
         }
         if (open) {
             const int q = top + 2 * (int)lane_rank(mo);
@@ -490,25 +611,60 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void k_
         }
         tf += ca;
         tn += cn;
+        tl += cl;
         nf += ca;
         nr += cn;
+        nl += cl;
         top += 2 * co;
         __syncthreads();
-        if (CELLS == kCellsQuad ? nf > 0 : nf >= kGroup) flush_cells();
+        if (CELLS >= kCellsQuad ? nf > 0 : nf >= kGroup) flush_cells();
         if (nr >= kGroup) flush_near();
+        if (nl >= kGroup) flush_local();
     }
     if (nf > 0) flush_cells();
+    if (nl > 0) flush_local();
     if (nr > 0) flush_near();
 
     if constexpr (INSPECT) {
         if (lane == 0) {
             O.far_cnt[g] = tf;
             O.near_cnt[g] = tn;
+            if (CELLS == kCellsLocal && O.loc_cnt) O.loc_cnt[g] = tl;
         }
     } else {
         // the group's own bodies, without the self pair
         S.zero();
         range_f32<1>(src, gn.x, gn.y, gn.x, gn.x + kGroup, TT, eps2, S);
+        if constexpr (CELLS == kCellsLocal) {
+            // sum the local expansion over the wave, evaluate it at this body
+#pragma unroll
+            for (int k = 0; k < 20; ++k) {
+                float v = Lx.c[k];
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+                Lx.c[k] = v;
+            }
+            const float yx = TT.x[0] - zgx, yy = TT.y[0] - zgy, yz = TT.z[0] - zgz;
+            const float *c = Lx.c;
+            const float kx = __builtin_fmaf(c[4], yx, __builtin_fmaf(c[7], yy, c[8] * yz));
+            const float ky = __builtin_fmaf(c[7], yx, __builtin_fmaf(c[5], yy, c[9] * yz));
+            const float kz = __builtin_fmaf(c[8], yx, __builtin_fmaf(c[9], yy, c[6] * yz));
+            // T(y, y): T (xxx, yyy, zzz, xxy, xxz, xyy, yyz, xzz, yzz, xyz) = c[10..19]
+            const float xx = yx * yx, yy2 = yy * yy, zz = yz * yz, xy = yx * yy, xz = yx * yz, yz2 = yy * yz;
+            const float tx = __builtin_fmaf(c[10], xx, __builtin_fmaf(c[15], yy2, __builtin_fmaf(c[17], zz,
+                             2.0f * __builtin_fmaf(c[13], xy, __builtin_fmaf(c[14], xz, c[19] * yz2)))));
+            const float ty = __builtin_fmaf(c[13], xx, __builtin_fmaf(c[11], yy2, __builtin_fmaf(c[18], zz,
+                             2.0f * __builtin_fmaf(c[15], xy, __builtin_fmaf(c[19], xz, c[16] * yz2)))));
+            const float tz = __builtin_fmaf(c[14], xx, __builtin_fmaf(c[16], yy2, __builtin_fmaf(c[12], zz,
+                             2.0f * __builtin_fmaf(c[19], xy, __builtin_fmaf(c[17], xz, c[18] * yz2)))));
+            S.ax[0] += c[1] + __builtin_fmaf(0.5f, tx, kx);
+            S.ay[0] += c[2] + __builtin_fmaf(0.5f, ty, ky);
+            S.az[0] += c[3] + __builtin_fmaf(0.5f, tz, kz);
+            const float py = __builtin_fmaf(c[1], yx, __builtin_fmaf(c[2], yy, c[3] * yz));
+            const float yky = __builtin_fmaf(yx, kx, __builtin_fmaf(yy, ky, yz * kz));
+            const float ytyy = __builtin_fmaf(yx, tx, __builtin_fmaf(yy, ty, yz * tz));
+            S.ph[0] += c[0] + __builtin_fmaf(1.0f / 6.0f, ytyy, __builtin_fmaf(0.5f, yky, py));
+        }
         R[0].fold(S.ax[0]);
         R[1].fold(S.ay[0]);
         R[2].fold(S.az[0]);
@@ -720,7 +876,7 @@ hipError_t launch_moments_t(const float4 *pm, const TreeDev &d, const HostTree &
         hipLaunchKernelGGL(k_tree_pseudo, dim3((nn * kPseudo + 255) / 256), dim3(256), 0, s, d, nn);
         e = hipGetLastError();
     }
-    if (Q2 && e == hipSuccess && cells == kCellsQuad) {
+    if (Q2 && e == hipSuccess && (cells == kCellsQuad || cells == kCellsLocal)) {
         hipLaunchKernelGGL(k_tree_quad, dim3((nn + 255) / 256), dim3(256), 0, s, d, nn);
         e = hipGetLastError();
     }
@@ -747,7 +903,7 @@ template <int MODE, bool INSPECT, int CELLS>
 hipError_t launch_walk(const float4 *pm, int n, const TreeDev &d, int ngroups, float eps2, double G,
                        double theta2, const WalkOut &o, hipStream_t s)
 {
-    const float4 *recs = CELLS == kCellsPseudo ? d.pp : (CELLS == kCellsQuad ? d.qr : d.rec);
+    const float4 *recs = CELLS == kCellsPseudo ? d.pp : (CELLS >= kCellsQuad ? d.qr : d.rec);
     hipLaunchKernelGGL((k_tree_walk<MODE, INSPECT, CELLS>), dim3(ngroups), dim3(64), 0, s, pm, n, d, recs, eps2,
                        G, theta2, o);
     return hipGetLastError();
@@ -814,6 +970,24 @@ hipError_t walk_prec(int prec, const float4 *pm, int n, const TreeDev &d, int ng
 }
 }  // namespace
 
+int tree_local_counts(const void *pm, int n, int leaf, double theta, int32_t *loc_cnt, int32_t *far_cnt,
+                      int32_t *near_cnt, hipStream_t s)
+{
+    std::lock_guard<std::mutex> lk(g_tree_mu);
+    TreeDev d;
+    int rc = tree_prepare(n, leaf, s, d);
+    if (rc != NBODY_OK) return rc;
+    hipError_t e = launch_moments((const float4 *)pm, d, g_tree.host, kCellsMono, s);
+    WalkOut o{};
+    o.far_cnt = far_cnt;
+    o.near_cnt = near_cnt;
+    o.loc_cnt = loc_cnt;
+    if (e == hipSuccess)
+        e = launch_walk<M_F32, true, kCellsLocal>((const float4 *)pm, n, d, (int)g_tree.host.groups.size(), 0.0f,
+                                                  1.0, theta * theta, o, s);
+    return e == hipSuccess ? NBODY_OK : hip_fail(e, "tree local counts");
+}
+
 int tree_accel(const void *pm, int n, int prec, double G, double eps, double theta, int leaf, int cells,
                void *out, hipStream_t s)
 {
@@ -833,6 +1007,8 @@ int tree_accel(const void *pm, int n, int prec, double G, double eps, double the
             e = walk_prec<kCellsPseudo>(prec, (const float4 *)pm, n, d, ng, eps2, G, th2, o, s);
         else if (cells == kCellsQuad)
             e = walk_prec<kCellsQuad>(prec, (const float4 *)pm, n, d, ng, eps2, G, th2, o, s);
+        else if (cells == kCellsLocal)
+            e = walk_prec<kCellsLocal>(prec, (const float4 *)pm, n, d, ng, eps2, G, th2, o, s);
         else
             e = walk_prec<kCellsMono>(prec, (const float4 *)pm, n, d, ng, eps2, G, th2, o, s);
     }
@@ -939,7 +1115,10 @@ int tree_leapfrog(void *pm, void *vel, void *acc, int32_t *order, int n, int pre
         const int rc = reorder(pm, vel, acc, order, n, leaf, s);
         if (rc != NBODY_OK) return rc;
     }
-    const int cells = (flags & NBODY_TREE_QUAD_CELLS) ? kCellsQuad : ((flags & NBODY_TREE_PSEUDO_CELLS) ? kCellsPseudo : kCellsMono);
+    const int cells = (flags & NBODY_TREE_LOCAL_CELLS)  ? kCellsLocal
+                      : (flags & NBODY_TREE_QUAD_CELLS)   ? kCellsQuad
+                      : (flags & NBODY_TREE_PSEUDO_CELLS) ? kCellsPseudo
+                                                          : kCellsMono;
     if (!(flags & NBODY_ACC_VALID)) {
         const int rc = tree_accel(pm, n, prec, G, eps, theta, leaf, cells, acc, s);
         if (rc != NBODY_OK) return rc;

@@ -94,13 +94,16 @@ def test_other_entry_points_validate():
     assert L.nbody_tree_lists(P(64), 100, 8, 0.5, 4, 4, None, P(256), None, None, None) == -1
     assert L.nbody_tree_lists(P(64), 100, 8, 0.5, 0, 4, P(256), P(512), P(1024), None, None) == -1
     assert L.nbody_tree_moments(P(64), 100, 8, P(12), None, None) == -2
-    # cell order: 0 or 2 only; pseudo-particle export needs float4 alignment
+    # cell models 0, 2, 3, 4 only; record exports need float4 alignment
     ao = lambda *a: L.nbody_tree_accel_cells(*a)
     assert ao(P(64), 100, 1, 1.0, 0.01, 0.5, 4, 1, P(4096), None) == -1
-    assert ao(P(64), 100, 1, 1.0, 0.01, 0.5, 4, 4, P(4096), None) == -1
     assert ao(P(64), 100, 1, 1.0, 0.01, 0.5, 4, -1, P(4096), None) == -1
     assert L.nbody_tree_quad(P(64), 100, 4, P(4104), None) == -2
     assert L.nbody_tree_quad(P(64), 0, 4, P(4096), None) == -1
+    assert ao(P(64), 100, 1, 1.0, 0.01, 0.5, 4, 5, P(4096), None) == -1
+    assert L.nbody_tree_local_counts(P(64), 100, 4, 0.5, None, P(256), P(512), None) == -1
+    assert L.nbody_tree_local_counts(P(64), 100, 4, -0.5, P(128), P(256), P(512), None) == -1
+    assert L.nbody_tree_local_counts(P(64), 100, 4, 0.5, P(130), P(256), P(512), None) == -1
     assert ao(P(64), 100, 0, 1.0, 0.01, 0.5, 4, 2, P(4096), None) == -5   # FP64 unsupported
     assert ao(P(64), 100, 1, 1.0, 0.01, 0.5, 0, 2, P(4096), None) == -1
     assert L.nbody_tree_pseudo(P(64), 100, 4, P(4100), None) == -2
@@ -112,6 +115,7 @@ def test_other_entry_points_validate():
     assert lf(P(64), P(1024), P(4096), None, 100, 1, 1.0, 0.01, 0.5, 8, 1e-3, 4, 0, 0x2, None, None) == -1
     assert lf(P(64), P(1024), P(4096), None, 100, 1, 1.0, 0.01, 0.5, 8, 1e-3, 4, 0, 0x8 | 0x2, None, None) == -1
     assert lf(P(64), P(1024), P(4096), None, 100, 1, 1.0, 0.01, 0.5, 8, 1e-3, 4, 0, 0x8 | 0x20, None, None) == -1
+    assert lf(P(64), P(1024), P(4096), None, 100, 1, 1.0, 0.01, 0.5, 8, 1e-3, 4, 0, 0x40 | 0x20, None, None) == -1
     assert lf(P(64), P(1024), P(4096), None, 100, 1, 1.0, 0.01, 0.5, 8, 1e-3, 4, 2, 0, None, None) == -1
     assert lf(P(64), P(1024), P(4096), None, 100, 1, 1.0, 0.01, 0.5, 8, 1e-3, 4, 0, 0x4, None, None) == -1
     assert lf(P(64), P(1024), P(4096), None, 100, 1, 1.0, 0.01, 0.5, 8, 1e-3, -1, 0, 0, None, None) == -1
