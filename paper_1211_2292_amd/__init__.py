@@ -27,7 +27,7 @@ __all__ = [
     "set_tuning", "get_tuning", "release", "NBodyError", "TREE_GROUP", "tree_shape", "tree_accel",
     "tree_moments", "tree_lists", "tree_leapfrog", "tree_pseudo", "tree_quad", "TREE_PSEUDO",
     "CELLS_MONOPOLE", "CELLS_PSEUDO", "CELLS_QUADRUPOLE", "CELLS_LOCAL", "tree_local_counts",
-    "janus_forward", "janus_adjoint",
+    "janus_forward", "janus_adjoint", "ReversibleTrajectory",
 ]
 
 F64, F32, F32_KAHAN, F32_F64ACC = 0, 1, 2, 3
@@ -511,6 +511,43 @@ class NBodyTrajectory(torch.autograd.Function):
         pc, vc, mc = trajectory_adjoint(ck, eps, dt, nsteps, ckpt_every, xb, vb, G, prec, scheme,
                                         phibar_T=gphi if with_potential else None)
         return pc[:, :3], vc[:, :3], mc, None, None, None, None, None, None, None, None
+
+
+class ReversibleTrajectory(torch.autograd.Function):
+    """x_T = leapfrog^nsteps(x0, v0; m) on the bit-reversible fixed-point
+    state (janus_forward), differentiable in (x0, v0, m) through the
+    checkpoint-free adjoint (janus_adjoint): the only memory kept is the final
+    int64 state (64 bytes per body), whatever nsteps is.  x0, v0: (N, 3);
+    m: (N,) positive; float32.  Returns (x_T (N, 3), v_T (N, 3)).  Rounding
+    to the fixed-point grid is treated as the identity in the derivative."""
+
+    @staticmethod
+    def forward(ctx, x0, v0, m, eps, dt, nsteps, G=1.0, shift_x=40, shift_v=40):
+        n = x0.shape[0]
+        pm = torch.empty((n, 4), dtype=torch.float32, device=x0.device)
+        pm[:, :3] = x0.detach()
+        pm[:, 3] = m.detach()
+        vel = torch.zeros((n, 4), dtype=torch.float32, device=x0.device)
+        vel[:, :3] = v0.detach()
+        st, pT, vT = janus_forward(pm, vel, eps, dt, nsteps, shift_x, shift_v, G)
+        ctx.save_for_backward(st, pm)
+        ctx.args = (eps, dt, nsteps, G, shift_x, shift_v)
+        return pT[:, :3].clone(), vT[:, :3].clone()
+
+    @staticmethod
+    def backward(ctx, gx, gv):
+        st, pm = ctx.saved_tensors
+        eps, dt, nsteps, G, shift_x, shift_v = ctx.args
+        st = st.clone()  # the adjoint rewinds the state in place
+        n = pm.shape[0]
+        xb = torch.zeros((n, 4), dtype=torch.float32, device=pm.device)
+        vb = torch.zeros((n, 4), dtype=torch.float32, device=pm.device)
+        if gx is not None:
+            xb[:, :3] = gx
+        if gv is not None:
+            vb[:, :3] = gv
+        pc, vc, mc = janus_adjoint(st, pm, eps, dt, nsteps, xb, vb, shift_x, shift_v, G)
+        return pc[:, :3], vc[:, :3], mc, None, None, None, None, None, None
 
 
 def autotune(kernel, prec, n, offsets=None):

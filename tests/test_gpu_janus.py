@@ -94,3 +94,30 @@ def test_nonpositive_mass_is_refused():
     z = torch.zeros_like(p)
     with pytest.raises(nb.NBodyError, match="positive"):
         nb.janus_adjoint(st, p, 0.01, 1e-3, 3, z, z)
+
+
+def test_autograd_function_matches_oracle(orc):
+    """ReversibleTrajectory through torch autograd: L = sum |x_T - y|^2,
+    gradients in (x0, v0, m) against the oracle's FP64 reverse mode (bar 1e-5,
+    as for the adjoint call itself)."""
+    torch, nb = gpu()
+    n, eps, dt, steps = 1024, 0.01, 1e-3, 40
+    pm, v, p, vv = _inputs(torch, n, 640)
+    y = ics.perturbed_snapshot(pm, 641)
+    x0 = p[:, :3].clone().requires_grad_(True)
+    v0 = vv[:, :3].clone().requires_grad_(True)
+    m = p[:, 3].clone().requires_grad_(True)
+    xT, vT = nb.ReversibleTrajectory.apply(x0, v0, m, eps, dt, steps)
+    yd = to_dev(torch, y[:, :3].astype(np.float32), torch.float32)
+    loss = ((xT - yd) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    L, gx, gv, gm = orc.traj_grad(widen32(pm), widen32(np.c_[v[:, :3], np.zeros(n)]), y, eps, dt, steps)
+    e = (normwise(host(x0.grad), gx), normwise(host(v0.grad), gv), normwise(host(m.grad), gm))
+    print("reversible autograd grad errors", e)
+    assert max(e) <= 1e-5
+    # a second backward through a fresh forward gives the same gradient
+    x1 = p[:, :3].clone().requires_grad_(True)
+    xT1, _ = nb.ReversibleTrajectory.apply(x1, vv[:, :3].clone(), m.detach(), eps, dt, steps)
+    ((xT1 - yd) ** 2).sum().backward()
+    assert torch.equal(x1.grad, x0.grad)
