@@ -171,3 +171,35 @@ def test_tree_leapfrog_local_cells(orc):
         x1, v1, a1 = host(q), host(v), host(a)
         np.testing.assert_allclose(x1[:, :3], xk[:, :3] + dt * (vk[:, :3] + h * ak[:, :3]), rtol=0, atol=1e-6)
         np.testing.assert_allclose(v1[:, :3], vk[:, :3] + h * (ak[:, :3] + a1[:, :3]), rtol=0, atol=1e-6)
+
+
+@pytest.mark.parametrize("cells", ["CELLS_PSEUDO", "CELLS_QUADRUPOLE", "CELLS_LOCAL"])
+def test_higher_order_cells_replay_in_a_captured_graph(cells):
+    """After the first call for a shape, a tree force with any cell model is
+    kernel launches only (moments, second moments, cell records, walk):
+    captured in a HIP graph it replays bit for bit like eager calls, with
+    eager work in between."""
+    torch, nb = gpu()
+    cm = getattr(nb, cells)
+    pm, _ = ics.plummer(20000, 670)
+    q, _ = _orb_input(torch, nb, pm, 4)
+    out_e = nb.tree_accel(q, 0.01, 0.6, 4, prec=nb.F32_F64ACC, cells=cm)
+    out_g = torch.empty_like(q)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        nb.tree_accel(q, 0.01, 0.6, 4, prec=nb.F32_F64ACC, out=out_g, cells=cm)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        nb.tree_accel(q, 0.01, 0.6, 4, prec=nb.F32_F64ACC, out=out_g, cells=cm)
+    for rep in range(3):
+        out_g.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        junk = torch.randn(1000, device="cuda").sum()
+        ref = nb.tree_accel(q, 0.01, 0.6, 4, prec=nb.F32_F64ACC, cells=cm)
+        torch.cuda.synchronize()
+        assert torch.equal(out_g, ref) and torch.equal(ref, out_e), rep
+        del junk
