@@ -121,3 +121,25 @@ def test_autograd_function_matches_oracle(orc):
     xT1, _ = nb.ReversibleTrajectory.apply(x1, vv[:, :3].clone(), m.detach(), eps, dt, steps)
     ((xT1 - yd) ** 2).sum().backward()
     assert torch.equal(x1.grad, x0.grad)
+
+
+def test_exact_reversal_at_full_size():
+    """N = 2^20 colliding pair (the headline workload), 2 steps: the reverse
+    pass restores the initial integer state bit for bit at the full size and
+    kernel shape, and the decoded final positions agree with the ordinary
+    leapfrog's to FP32 rounding."""
+    torch, nb = gpu()
+    w = ics.WORKLOADS["collide1m"]
+    pm, v = ics.colliding_pair(w["n"], w["seed"])
+    p = to_dev(torch, np.asarray(pm, dtype=np.float32), torch.float32)
+    vv = to_dev(torch, np.c_[v[:, :3], np.zeros(len(v))].astype(np.float32), torch.float32)
+    print(f"fixed-point reversal N={p.shape[0]}", flush=True)
+    st0, _, _ = nb.janus_forward(p, vv, w["eps"], w["dt"], 0)
+    st, pT, _ = nb.janus_forward(p, vv, w["eps"], w["dt"], 2)
+    xb = torch.zeros_like(p)
+    nb.janus_adjoint(st, p, w["eps"], w["dt"], 2, xb, torch.zeros_like(p))
+    torch.cuda.synchronize()
+    assert torch.equal(st, st0)
+    q, u, a = p.clone(), vv.clone(), torch.empty_like(p)
+    nb.leapfrog_kdk(q, u, a, w["eps"], w["dt"], 2, prec=nb.F32_F64ACC)
+    assert rms_rel(host(pT)[:, :3], host(q)[:, :3]) < 1e-7
