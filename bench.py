@@ -62,6 +62,8 @@ def main():
                     help="two tree evaluations (theta 0.7, leaf 8) of the workload for counter runs")
     ap.add_argument("--tree-cells", action="store_true",
                     help="two tree evaluations (theta 0.7, leaf 4) per cell model for trace and counter runs")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="the adjoint leg alone (plain, checkpointed and fixed-point), for trace runs")
     ap.add_argument("--counters", action="store_true",
                     help="counter-collection mode: two force launches of the headline workload "
                          "and one 1 GiB device copy (the copy calibrates byte counters); no JSON")
@@ -107,6 +109,10 @@ def main():
             nb.tree_accel(q, eps, 0.7, 8, prec=prec, out=out)
         torch.cuda.synchronize()
         log("[bench] tree counters mode: 2 tree evaluations, theta 0.7, leaf 8, F32_F64ACC")
+        return
+
+    if args.adjoint:
+        print(json.dumps(adjoint_leg(torch, nb, ics, dev)))
         return
 
     if args.tree_cells:
