@@ -358,7 +358,12 @@ int nbody_tree_leapfrog(void *pos_mass, void *vel, void *acc_pot, int32_t *order
  * Subtracting the same integers undoes a step exactly, so the adjoint rebuilds
  * every position bit for bit from the final state and stores nothing per step.
  * state: int64 [2n][4], rows [0, n) = (X, Y, Z, 0), rows [n, 2n) =
- * (VX, VY, VZ, 0); 32-byte aligned device memory.  |X|, |V| < 2^53.
+ * (VX, VY, VZ, 0); 32-byte aligned device memory.  |X|, |V| < 2^53 (not
+ * checked).  shift_x, shift_v in [0, 60] (else NBODY_E_INVAL).  Both calls
+ * use one kernel shape per n, independent of tuning pins and the tune cache:
+ * the reverse pass must reproduce the forward's forces bit for bit.  They
+ * use library scratch (force and VJP partials, three records per body):
+ * overlapping calls on one device race.
  * nbody_janus_forward: encodes pos_mass/vel (float4, masses in w), runs
  *   nsteps, writes the final state, the decoded positions with the masses
  *   (pos_mass_out) and, if not NULL, the decoded velocities (vel_out).

@@ -927,7 +927,9 @@ int nbody_janus_forward(const void *pos_mass, const void *vel, int64_t n, double
         return NBODY_E_ALIGN;
     }
     const int ni = (int)n;
-    const Tune t = janus_tune(lookup_tune(2, NBODY_F32_F64ACC, n));
+    // one shape per n, independent of tuning pins and the tune cache, so that
+    // a later adjoint call reproduces these force bits exactly
+    const Tune t = janus_tune(default_tune(2, NBODY_F32_F64ACC, n, n));
     void *acc = scratch(kSlotAdj0, (size_t)n * 16);
     void *partial = nullptr;
     if (const size_t pb = accel_partial_bytes(NBODY_F32_F64ACC, ni, t)) partial = scratch(kSlotPartial, pb);
@@ -964,7 +966,7 @@ int nbody_janus_adjoint(void *state, const void *pos_mass, int64_t n, double G, 
     const size_t rb = (size_t)n * 16;
     const double h = 0.5 * dt;
     hipStream_t s = (hipStream_t)stream;
-    const Tune t = janus_tune(lookup_tune(2, prec, n));
+    const Tune t = janus_tune(default_tune(2, prec, n, n));  // the forward's shape
     void *acc = scratch(kSlotAdj0, rb);
     void *dec = scratch(kSlotAdj1, rb);
     char *scbuf = (char *)scratch(kSlotAdj4, rb + 256);

@@ -143,3 +143,21 @@ def test_exact_reversal_at_full_size():
     q, u, a = p.clone(), vv.clone(), torch.empty_like(p)
     nb.leapfrog_kdk(q, u, a, w["eps"], w["dt"], 2, prec=nb.F32_F64ACC)
     assert rms_rel(host(pT)[:, :3], host(q)[:, :3]) < 1e-7
+
+
+def test_reversal_survives_a_tuning_change_between_calls():
+    """Pinning another kernel shape for the VJP between the forward and the
+    adjoint does not change the fixed-point path's forces: the state still
+    comes back bit for bit."""
+    torch, nb = gpu()
+    _, _, p, vv = _inputs(torch, 3000, 650)
+    st0, _, _ = nb.janus_forward(p, vv, 0.01, 1e-3, 0)
+    st, _, _ = nb.janus_forward(p, vv, 0.01, 1e-3, 10)
+    try:
+        nb.set_tuning(nb.KERNEL_VJP, nb.F32_F64ACC, 1, 4, 1024, 0)
+        z = torch.zeros_like(p)
+        nb.janus_adjoint(st, p, 0.01, 1e-3, 10, z, z)
+        torch.cuda.synchronize()
+    finally:
+        nb.set_tuning(nb.KERNEL_VJP, nb.F32_F64ACC)
+    assert torch.equal(st, st0)
