@@ -27,11 +27,17 @@
  * - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *   Every call is stream-ordered and asynchronous: it validates its
  *   arguments on the host, enqueues kernels and returns.  No call below
- *   synchronises the device except nbody_autotune(), nbody_release(), and a
+ *   synchronises the device except nbody_autotune(), nbody_release(), a
  *   call that needs more library scratch than any earlier call on the device
- *   (growing a scratch buffer waits for the work that may still use it).
- *   Calls that share library scratch (the same entry point on one device)
- *   must not run concurrently on different streams.
+ *   (growing a scratch buffer waits for the work that may still use it), a
+ *   tree call for a new (n, leaf) (it uploads the node table), and
+ *   nbody_janus_adjoint (its mass check).  Calls that share library scratch
+ *   (the same entry point on one device) must not run concurrently on
+ *   different streams.
+ * - A caller may capture calls into its own HIP graph after one eager call
+ *   of the same shapes (which allocates the scratch and tables they use).
+ *   The graph stays valid until a call grows library scratch, a tree call
+ *   changes (n, leaf), or nbody_release() runs.
  * - Return value: NBODY_OK (0) or a negative status.  On a validation error
  *   nothing has been enqueued.  nbody_last_error() gives a thread-local
  *   message for the last failing call.  The library never aborts or exits.
