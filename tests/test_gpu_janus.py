@@ -161,3 +161,31 @@ def test_reversal_survives_a_tuning_change_between_calls():
     finally:
         nb.set_tuning(nb.KERNEL_VJP, nb.F32_F64ACC)
     assert torch.equal(st, st0)
+
+
+@pytest.mark.parametrize("n,steps,G,sx,sv", [(1, 5, 1.0, 40, 40), (2, 7, 1.0, 40, 40), (500, 0, 1.0, 40, 40),
+                                             (700, 9, 2.5, 40, 40), (600, 6, 1.0, 50, 34)])
+def test_reversal_edge_cases(n, steps, G, sx, sv):
+    """One and two bodies, zero steps (the adjoint passes the cotangents
+    through), G != 1 (G sits in the kick and the cotangent scale) and other
+    fixed-point shifts: the state comes back bit for bit."""
+    torch, nb = gpu()
+    pm, v = ics.plummer(max(n, 2), 660 + n)
+    pm, v = pm[:n].copy(), v[:n].copy()
+    pm[:, 3] = 1.0 / n
+    p = to_dev(torch, np.asarray(pm, dtype=np.float32), torch.float32)
+    vv = to_dev(torch, np.c_[v[:, :3], np.zeros(n)].astype(np.float32), torch.float32)
+    st0, _, _ = nb.janus_forward(p, vv, 0.01, 1e-3, 0, sx, sv, G)
+    st, pT, vT = nb.janus_forward(p, vv, 0.01, 1e-3, steps, sx, sv, G)
+    xb = torch.randn_like(p); xb[:, 3] = 0
+    vb = torch.randn_like(p); vb[:, 3] = 0
+    pc, vc, mc = nb.janus_adjoint(st, p, 0.01, 1e-3, steps, xb, vb, sx, sv, G)
+    torch.cuda.synchronize()
+    assert torch.equal(st, st0)
+    if steps == 0:
+        assert torch.equal(pc[:, :3], xb[:, :3]) and torch.equal(vc[:, :3], vb[:, :3])
+        assert torch.all(mc == 0)
+    if n == 1:
+        # a lone body moves in a straight line and feels nothing
+        np.testing.assert_allclose(host(pT)[0, :3], pm[0, :3] + steps * 1e-3 * v[0, :3], rtol=0, atol=1e-6)
+        assert torch.equal(pc[:, :3], xb[:, :3])
