@@ -229,7 +229,7 @@ def main():
         result["fp64"] = fp64_leg(torch, nb, ics, dev)
         result["adjoint"] = adjoint_leg(torch, nb, ics, dev)
         result["batched"] = batched_leg(torch, nb, ics, dev)
-        result["tree"] = tree_leg(torch, nb, pm_np, eps, kern_avg)
+        result["tree"] = tree_leg(torch, nb, pm_np, eps, kern_avg, v_np=v_np, dt=dt)
         result["shard"] = shard_leg(torch, nb, pm, eps, prec)
         result["cpu_baseline"] = cpu_leg(ics, pm0_host, acc0, eps, args.cpu_seconds)
     print(json.dumps(result), flush=True)
@@ -460,11 +460,12 @@ def _tree_groups(nodes, group):
     return out
 
 
-def tree_leg(torch, nb, pm_np, eps, direct_ms, leaf=4):
+def tree_leg(torch, nb, pm_np, eps, direct_ms, leaf=4, v_np=None, dt=5e-4):
     """Tree code on the ORB cells (leaf 4, groups of 64) for the same
     colliding pair at step 0, FP32 pairs with FP64 batch sums: time per
     evaluation, interactions per body, and the error against the exact direct
-    sum computed by the direct kernel on the same ordered input."""
+    sum computed by the direct kernel on the same ordered input; then the
+    tree leapfrog (10 steps, re-ordered by ORB every 10) per cell model."""
     import ctypes
     dev = torch.device("cuda:0")
     n = pm_np.shape[0]
@@ -573,6 +574,27 @@ def tree_leg(torch, nb, pm_np, eps, direct_ms, leaf=4):
             log(f"[bench] tree cells {order} theta {theta}: {t:.3f} ms ({t_mom:.3f} moments), "
                 f"{pairs / n:.0f} interactions/body, {walk_tflops:.1f} TFLOP/s in the walk, "
                 f"x{direct_ms / t:.1f} vs direct, rms err {r['rms_rel_err_vs_direct']:.2e}")
+    if v_np is not None:
+        # whole simulation steps: force, kick/drift, and the ORB re-ordering
+        # (at entry and before the 10th force: 2 passes in the 10 timed steps)
+        vel = torch.as_tensor(v_np, dtype=torch.float32, device=dev).contiguous()
+        res["leapfrog"] = {}
+        for cells, theta in ((nb.CELLS_MONOPOLE, 0.7), (nb.CELLS_QUADRUPOLE, 0.7), (nb.CELLS_LOCAL, 0.7)):
+            qq, vq = p.clone(), vel.clone()
+            acc_t = torch.empty_like(qq)
+            nb.tree_leapfrog(qq, vq, acc_t, eps, theta, dt, 1, leaf, reorder_every=1, cells=cells, prec=nb.F32_F64ACC)
+            torch.cuda.synchronize()
+            steps = 10
+            e0.record()
+            nb.tree_leapfrog(qq, vq, acc_t, eps, theta, dt, steps, leaf, reorder_every=10, acc_valid=True,
+                             cells=cells, prec=nb.F32_F64ACC)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            key = {0: "monopole", 3: "quadrupole", 4: "local"}[cells]
+            res["leapfrog"][key] = {"theta": theta, "ms_per_step": round(ms, 3), "steps": steps, "orb_passes": 2,
+                                    "speedup_vs_direct_step": round(direct_ms / ms, 1)}
+            log(f"[bench] tree leapfrog ({key} cells, theta {theta}): {ms:.3f} ms per step, 2 ORB passes in 10 steps")
     return res
 
 
