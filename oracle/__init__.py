@@ -97,6 +97,10 @@ def _load():
         lib.oracle_tree_local_counts.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _d, _d,
                                                  ctypes.c_double, _i64, _i64, _i64]
         lib.oracle_tree_local_counts.restype = ctypes.c_int
+        lib.oracle_tree_local_lists.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _d, _d,
+                                                ctypes.c_double, _i64, _i64, _i64, _i32, ctypes.c_int64, _i32,
+                                                ctypes.c_int64, _i32, ctypes.c_int64]
+        lib.oracle_tree_local_lists.restype = ctypes.c_int
         lib.oracle_tree_pseudo.argtypes = [ctypes.c_int64, ctypes.c_int32, _d, _d, _d]
         lib.oracle_tree_pseudo.restype = ctypes.c_int
         lib.oracle_pseudo_dirs.argtypes = [_d]
@@ -408,4 +412,26 @@ def tree_local_counts(pos_mass_orb, leaf: int, group: int, theta: float):
                                       _ptr(out["near_cnt"], _i64))
     if rc != 0:
         raise ValueError("oracle_tree_local_counts failed")
+    return out
+
+
+def tree_local_lists(pos_mass_orb, leaf: int, group: int, theta: float):
+    """Lists of the local-expansion walk: dict(loc_cnt, far_cnt, near_cnt
+    (ngroups,), loc, far, near (concatenated node ids in walk order))."""
+    lib = _load()
+    x, m = _split(pos_mass_orb)
+    n = x.shape[0]
+    c = tree_local_counts(pos_mass_orb, leaf, group, theta)
+    ng = c["loc_cnt"].shape[0]
+    out = {k: np.empty(ng, dtype=np.int64) for k in ("loc_cnt", "far_cnt", "near_cnt")}
+    caps = {k: max(int(c[k + "_cnt"].sum()), 1) for k in ("loc", "far", "near")}
+    lists = {k: np.empty(caps[k], dtype=np.int32) for k in caps}
+    rc = lib.oracle_tree_local_lists(n, int(leaf), int(group), _ptr(x, _d), _ptr(m, _d), float(theta),
+                                     _ptr(out["loc_cnt"], _i64), _ptr(out["far_cnt"], _i64),
+                                     _ptr(out["near_cnt"], _i64), _ptr(lists["loc"], _i32), caps["loc"],
+                                     _ptr(lists["far"], _i32), caps["far"], _ptr(lists["near"], _i32), caps["near"])
+    if rc != 0:
+        raise ValueError("oracle_tree_local_lists failed")
+    for k in ("loc", "far", "near"):
+        out[k] = lists[k][:int(out[k + "_cnt"].sum())]
     return out

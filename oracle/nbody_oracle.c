@@ -1267,6 +1267,42 @@ int oracle_tree_accel_cells(int64_t n, int32_t leaf, int32_t group, const double
     return bad ? -1 : 0;
 }
 
+/* Lists of the local-expansion walk for every group, in walk order:
+ * loc/far/near concatenated in group order with capacities; the counts as
+ * in oracle_tree_local_counts.  Returns 0, or -1 on bad arguments or a list
+ * longer than its capacity. */
+int oracle_tree_local_lists(int64_t n, int32_t leaf, int32_t group, const double *x, const double *m,
+                            double theta, int64_t *loc_cnt, int64_t *far_cnt, int64_t *near_cnt, int32_t *loc,
+                            int64_t loc_cap, int32_t *far, int64_t far_cap, int32_t *near, int64_t near_cap)
+{
+    if (!(theta >= 0.0))
+        return -1;
+    tree_data d;
+    if (tree_setup(n, leaf, group, x, m, &d) != 0)
+        return -1;
+    tree_ctx tc = {d.nodes, d.com, d.lo, d.hi, d.diag2, theta * theta};
+    int64_t ol = 0, of = 0, on = 0;
+    int rc = 0;
+    for (int64_t q = 0; q < d.ngroups && rc == 0; ++q) {
+        int64_t a = 0, b = 0, e = 0;
+        tree_walk_local_rec(&tc, 0, d.group_node[q], NULL, &e, NULL, &a, NULL, &b);
+        loc_cnt[q] = e;
+        far_cnt[q] = a;
+        near_cnt[q] = b;
+        if (ol + e > loc_cap || of + a > far_cap || on + b > near_cap) {
+            rc = -1;
+            break;
+        }
+        int64_t a2 = 0, b2 = 0, e2 = 0;
+        tree_walk_local_rec(&tc, 0, d.group_node[q], loc + ol, &e2, far + of, &a2, near + on, &b2);
+        ol += e;
+        of += a;
+        on += b;
+    }
+    tree_free(&d);
+    return rc;
+}
+
 /* Per-group list sizes of the local-expansion walk: loc_cnt, far_cnt,
  * near_cnt [ngroups].  Returns 0, or -1 on bad arguments. */
 int oracle_tree_local_counts(int64_t n, int32_t leaf, int32_t group, const double *x, const double *m,

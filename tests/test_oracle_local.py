@@ -192,3 +192,42 @@ def test_expansion_coefficients_at_the_centre(orc):
             td4 = (a4[1 + 2 * j] + a4[2 + 2 * j] - 2 * a4[0]) / h ** 2
             td3 = (a3[1 + 2 * j] + a3[2 + 2 * j] - 2 * a3[0]) / h ** 2
             np.testing.assert_allclose(td4, td3, rtol=0, atol=1e-5 * np.abs(td3).max())
+
+
+@pytest.mark.parametrize("theta", [0.4, 0.7, 1.0])
+def test_local_walk_partitions_the_bodies_and_honours_its_tests(orc, theta):
+    """For every group: the local, per-target and near lists together cover
+    every body outside the group exactly once (and the group's own leaves are
+    near); every local cell is disjoint from the group and passes
+    diag2_c + diag2_g < theta^2 |com_c - z_g|^2; every per-target cell fails
+    that and passes the monopole acceptance test; every near entry is a leaf.
+    The tests are checked with numpy from the node table and moments."""
+    pm, _ = ics.colliding_pair(6000, 75)
+    q = _orb(orc, pm, 4)
+    n = q.shape[0]
+    nodes = orc.tree_nodes(n, 4)
+    mo = orc.tree_moments(q, 4)
+    L = orc.tree_local_lists(q, 4, 64, theta)
+    gl = orc.tree_lists(q, 4, 64, theta)["group_id"]
+    th2 = theta * theta
+    offs = {k: np.r_[0, np.cumsum(L[k + "_cnt"])] for k in ("loc", "far", "near")}
+    for g, gid in enumerate(gl):
+        gb, ge = nodes[gid, :2]
+        cover = np.zeros(n, dtype=np.int64)
+        for k in ("loc", "far", "near"):
+            for c in L[k][offs[k][g]:offs[k][g + 1]]:
+                b, e = nodes[c, :2]
+                cover[b:e] += 1
+                overlap = b < ge and gb < e
+                dz2 = float(np.sum((mo["com"][c] - mo["com"][gid]) ** 2))
+                local_ok = (not overlap) and mo["diag2"][c] + mo["diag2"][gid] < th2 * dz2
+                gap = np.maximum(np.maximum(mo["lo"][gid] - mo["com"][c], mo["com"][c] - mo["hi"][gid]), 0.0)
+                mono_ok = (not overlap) and mo["diag2"][c] < th2 * float(np.sum(gap ** 2))
+                if k == "loc":
+                    assert local_ok, (g, c)
+                elif k == "far":
+                    assert mono_ok and not local_ok, (g, c)
+                else:
+                    assert nodes[c, 2] < 0, (g, c)
+                    assert overlap or not (local_ok or mono_ok), (g, c)
+        assert np.all(cover == 1), g
