@@ -99,7 +99,10 @@ int nbody_orb_order(const void *pos_mass, int32_t prec, int64_t n, int32_t leaf,
  * Gather or scatter of 16- or 32-byte records through a permutation:
  *   inverse == 0: dst[p] = src[perm[p]]   (apply an ORB order)
  *   inverse != 0: dst[perm[p]] = src[p]   (return results to input order)
- * rec_bytes is 16 or 32.  src and dst must not overlap.
+ * rec_bytes is 16 or 32.  src and dst must not overlap.  perm should hold
+ * every index of [0, n) once; an entry outside [0, n) is skipped (no record is
+ * read or written for it), so the record it would have produced is left as
+ * it was.
  */
 int nbody_permute(const void *src, void *dst, const int32_t *perm, int64_t n,
                   int32_t rec_bytes, int32_t inverse, void *stream);

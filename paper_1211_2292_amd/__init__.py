@@ -134,6 +134,15 @@ def _rec(t: torch.Tensor, name: str, dtype=None) -> torch.Tensor:
     return t
 
 
+def _out(t: torch.Tensor, rows: int, like: torch.Tensor) -> torch.Tensor:
+    """A caller-supplied output: (rows, 4) records of like's dtype on like's
+    device, contiguous (the kernels write exactly that many records)."""
+    _rec(t, "out", like.dtype)
+    if t.shape[0] != rows or t.device != like.device:
+        raise ValueError(f"out must have shape ({rows}, 4) on {like.device}, got {tuple(t.shape)} on {t.device}")
+    return t
+
+
 def _prec(t: torch.Tensor, prec):
     if t.dtype == torch.float64:
         if prec not in (None, F64):
@@ -159,7 +168,7 @@ def accel(pos_mass, eps, G=1.0, prec=None, target_begin=0, target_count=None, ou
     if out is None:
         out = torch.empty((tc, 4), dtype=pm.dtype, device=pm.device)
     else:
-        _rec(out, "out", pm.dtype)
+        _out(out, tc, pm)
     _check(lib().nbody_accel(_ptr(pm), n, p, float(G), float(eps), _ptr(out), int(target_begin), int(tc),
                              _stream()))
     return out
@@ -227,7 +236,7 @@ def batched_accel(pos_mass, offsets, eps, G=1.0, prec=None, eps_per_sys=None, ou
     if out is None:
         out = torch.empty_like(pm)
     else:
-        _rec(out, "out", pm.dtype)
+        _out(out, pm.shape[0], pm)
     eptr = None
     if eps_per_sys is not None:
         if eps_per_sys.dtype != torch.float32 or eps_per_sys.device.type != "cuda" or \
@@ -266,6 +275,8 @@ def permute(src, perm, inverse=False, out=None):
         raise ValueError("perm must be a contiguous int32 GPU tensor of N entries")
     if out is None:
         out = torch.empty_like(s)
+    else:
+        _out(out, s.shape[0], s)
     _check(lib().nbody_permute(_ptr(s), _ptr(out), _ptr(perm), s.shape[0], s.element_size() * 4,
                                1 if inverse else 0, _stream()))
     return out
@@ -302,9 +313,7 @@ def tree_accel(pos_mass, eps, theta, leaf=4, G=1.0, prec=None, out=None, cells=C
     if out is None:
         out = torch.empty_like(pm)
     else:
-        _rec(out, "out", torch.float32)
-        if out.shape != pm.shape:
-            raise ValueError("out must match pos_mass")
+        _out(out, pm.shape[0], pm)
     _check(lib().nbody_tree_accel_cells(_ptr(pm), pm.shape[0], p, float(G), float(eps), float(theta),
                                         int(leaf), int(cells), _ptr(out), _stream()))
     return out

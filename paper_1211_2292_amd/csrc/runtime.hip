@@ -552,7 +552,7 @@ int nbody_energy(const void *pos_mass, const void *vel, const void *acc_pot, int
     }
     hipStream_t s = (hipStream_t)stream;
     // close = open = false: the step kernel only reads and reports energies
-    // (it writes vel back unchanged).
+    // (it stores nothing into pos_mass or vel).
     NB_TRY(launch_step(prec, const_cast<void *>(pos_mass), const_cast<void *>(vel), acc_pot, (int)n,
                        0.0, 0.0, false, false, ep, nullptr, s),
            "energy kernel");
@@ -797,6 +797,10 @@ int nbody_tree_accel_cells(const void *pos_mass, int64_t n, int32_t prec, double
     NB_CHECK(check_theta(theta));
     NB_CHECK(check_vec(pos_mass, prec, "pos_mass"));
     NB_CHECK(check_vec(acc_pot_out, prec, "acc_pot_out"));
+    if (overlap(pos_mass, 16 * (size_t)n, acc_pot_out, 16 * (size_t)n)) {
+        set_error("acc_pot_out overlaps pos_mass");
+        return NBODY_E_INVAL;
+    }
     return tree_accel(pos_mass, (int)n, prec, G, eps, theta, leaf, cells, acc_pot_out, (hipStream_t)stream);
 }
 
@@ -805,6 +809,12 @@ int nbody_tree_pseudo(const void *pos_mass, int64_t n, int32_t leaf, void *pseud
     NB_CHECK(check_tree(n, leaf));
     NB_CHECK(check_vec(pos_mass, NBODY_F32, "pos_mass"));
     NB_CHECK(check_vec(pseudo_out, NBODY_F32, "pseudo_out"));
+    int64_t nn = 0;
+    NB_CHECK(tree_shape((int)n, leaf, &nn, nullptr, nullptr));
+    if (overlap(pos_mass, 16 * (size_t)n, pseudo_out, 16 * (size_t)NBODY_TREE_PSEUDO * nn)) {
+        set_error("pseudo_out overlaps pos_mass");
+        return NBODY_E_INVAL;
+    }
     return tree_pseudo(pos_mass, (int)n, leaf, pseudo_out, (hipStream_t)stream);
 }
 
@@ -828,6 +838,12 @@ int nbody_tree_quad(const void *pos_mass, int64_t n, int32_t leaf, void *quad_ou
     NB_CHECK(check_tree(n, leaf));
     NB_CHECK(check_vec(pos_mass, NBODY_F32, "pos_mass"));
     NB_CHECK(check_vec(quad_out, NBODY_F32, "quad_out"));
+    int64_t nn = 0;
+    NB_CHECK(tree_shape((int)n, leaf, &nn, nullptr, nullptr));
+    if (overlap(pos_mass, 16 * (size_t)n, quad_out, 16 * (size_t)3 * nn)) {
+        set_error("quad_out overlaps pos_mass");
+        return NBODY_E_INVAL;
+    }
     return tree_quad(pos_mass, (int)n, leaf, quad_out, (hipStream_t)stream);
 }
 
@@ -854,6 +870,11 @@ int nbody_tree_lists(const void *pos_mass, int64_t n, int32_t leaf, double theta
         (near_ids && !max_near)) {
         set_error("bad list arguments");
         return NBODY_E_INVAL;
+    }
+    if (((uintptr_t)far_count % 4) || ((uintptr_t)near_count % 4) || ((uintptr_t)far_ids % 4) ||
+        ((uintptr_t)near_ids % 4)) {
+        set_error("count or id arrays not 4-byte aligned");
+        return NBODY_E_ALIGN;
     }
     return tree_lists(pos_mass, (int)n, leaf, theta, max_far, max_near, far_count, near_count, far_ids,
                       near_ids, (hipStream_t)stream);
@@ -887,6 +908,16 @@ int nbody_tree_leapfrog(void *pos_mass, void *vel, void *acc_pot, int32_t *order
     if (reorder_every > 0 && (!order || (uintptr_t)order % 4)) {
         set_error("order must be a 4-byte aligned int32 array when reorder_every > 0");
         return NBODY_E_INVAL;
+    }
+    {
+        const size_t rb = rec_bytes(prec) * (size_t)n;
+        const void *ord = reorder_every > 0 ? order : nullptr;
+        if (overlap(pos_mass, rb, vel, rb) || overlap(pos_mass, rb, acc_pot, rb) || overlap(vel, rb, acc_pot, rb) ||
+            overlap(ord, 4 * (size_t)n, pos_mass, rb) || overlap(ord, 4 * (size_t)n, vel, rb) ||
+            overlap(ord, 4 * (size_t)n, acc_pot, rb)) {
+            set_error("pos_mass, vel, acc_pot and order must not overlap");
+            return NBODY_E_INVAL;
+        }
     }
     if ((flags & NBODY_ENERGY) && (!energy_out || (uintptr_t)energy_out % 8)) {
         set_error("energy_out NULL or misaligned");
@@ -926,6 +957,19 @@ int nbody_janus_forward(const void *pos_mass, const void *vel, int64_t n, double
         set_error("state_out NULL or not 32-byte aligned");
         return NBODY_E_ALIGN;
     }
+    {
+        const size_t rb = 16 * (size_t)n, sb = 64 * (size_t)n;
+        const void *outs[3] = {state_out, pos_mass_out, vel_out};
+        const size_t osz[3] = {sb, rb, rb};
+        for (int i = 0; i < 3; ++i) {
+            bool bad = overlap(outs[i], osz[i], pos_mass, rb) || overlap(outs[i], osz[i], vel, rb);
+            for (int j = i + 1; j < 3; ++j) bad = bad || overlap(outs[i], osz[i], outs[j], osz[j]);
+            if (bad) {
+                set_error("state_out, pos_mass_out and vel_out must not overlap each other or the inputs");
+                return NBODY_E_INVAL;
+            }
+        }
+    }
     const int ni = (int)n;
     // one shape per n, independent of tuning pins and the tune cache, so that
     // a later adjoint call reproduces these force bits exactly
@@ -960,6 +1004,20 @@ int nbody_janus_adjoint(void *state, const void *pos_mass, int64_t n, double G, 
     if (!state || (uintptr_t)state % 32 || !mass_cot || (uintptr_t)mass_cot % 4) {
         set_error("state (32-byte aligned) or mass_cot NULL or misaligned");
         return NBODY_E_ALIGN;
+    }
+    {
+        const size_t rb = 16 * (size_t)n, sb = 64 * (size_t)n, mb = 4 * (size_t)n;
+        const void *bufs[7] = {state, pos_mass, xbar_T, vbar_T, pos_cot, vel_cot, mass_cot};
+        const size_t bsz[7] = {sb, rb, rb, rb, rb, rb, mb};
+        // state is updated in place; pos_cot, vel_cot and mass_cot are
+        // written: none of these may share memory with any other buffer
+        const int written[4] = {0, 4, 5, 6};
+        for (int w : written)
+            for (int j = 0; j < 7; ++j)
+                if (j != w && overlap(bufs[w], bsz[w], bufs[j], bsz[j])) {
+                    set_error("state, pos_cot, vel_cot and mass_cot must not overlap any other buffer");
+                    return NBODY_E_INVAL;
+                }
     }
     const int prec = NBODY_F32_F64ACC;
     const int ni = (int)n;

@@ -96,6 +96,7 @@ __global__ __launch_bounds__(kBlock) void k_permute(const R *__restrict__ src, R
     const int p = blockIdx.x * kBlock + threadIdx.x;
     if (p >= n) return;
     const int q = perm[p];
+    if ((unsigned)q >= (unsigned)n) return;  // not a permutation entry: no access
     if (inverse)
         dst[q] = src[p];
     else

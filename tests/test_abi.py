@@ -140,6 +140,41 @@ def test_other_entry_points_validate():
               None) == -2
 
 
+
+def test_overlapping_buffers_rejected():
+    """Outputs that share memory with an input or with each other are refused
+    before anything is enqueued (addresses only: nothing is dereferenced)."""
+    nb, L = _lib()
+    A, B, C, D = 0x100000, 0x200000, 0x300000, 0x400000
+    # tree force: 100 float4 records = 1600 bytes from A
+    assert L.nbody_tree_accel_cells(P(A), 100, 1, 1.0, 0.01, 0.5, 4, 3, P(A + 1024), None) == -1
+    assert L.nbody_tree_accel(P(A), 100, 1, 1.0, 0.01, 0.5, 4, P(A + 1024), None) == -1
+    # pseudo-particle and quadrupole exports run past the end of pos_mass
+    assert L.nbody_tree_pseudo(P(A), 100, 4, P(A + 1024), None) == -1
+    assert L.nbody_tree_quad(P(A), 100, 4, P(A + 1024), None) == -1
+    # list counts must be int32-aligned
+    assert L.nbody_tree_lists(P(A), 100, 8, 0.5, 0, 0, P(B + 2), P(C), None, None, None) == -2
+    assert L.nbody_tree_lists(P(A), 100, 8, 0.5, 4, 0, P(B), P(C), P(D + 1), None, None) == -2
+    # tree leapfrog: state buffers and the order map are disjoint
+    lf = lambda *a: L.nbody_tree_leapfrog(*a)
+    assert lf(P(A), P(A + 1024), P(C), None, 100, 1, 1.0, 0.01, 0.5, 8, 1e-3, 4, 0, 0, None, None) == -1
+    assert lf(P(A), P(B), P(B + 1584), None, 100, 1, 1.0, 0.01, 0.5, 8, 1e-3, 4, 0, 0, None, None) == -1
+    assert lf(P(A), P(B), P(C), P(B + 64), 100, 1, 1.0, 0.01, 0.5, 8, 1e-3, 4, 1, 0, None, None) == -1
+    # fixed-point leapfrog: the state (64 bytes per body) is disjoint from the rest
+    jf = lambda *a: L.nbody_janus_forward(*a)
+    assert jf(P(A), P(B), 10, 1.0, 0.01, 1e-3, 4, 40, 40, P(C), P(C + 256), None, None) == -1
+    assert jf(P(A), P(B), 10, 1.0, 0.01, 1e-3, 4, 40, 40, P(C), P(A + 64), None, None) == -1
+    assert jf(P(A), P(B), 10, 1.0, 0.01, 1e-3, 4, 40, 40, P(C), P(D), P(D + 128), None) == -1
+    ja = lambda *a: L.nbody_janus_adjoint(*a)
+    assert ja(P(C), P(A), 10, 1.0, 0.01, 1e-3, 2, 40, 40, P(B), P(B + 256), P(D), P(D + 64), P(D + 1024),
+              None) == -1
+    assert ja(P(C), P(A), 10, 1.0, 0.01, 1e-3, 2, 40, 40, P(B), P(B + 256), P(C + 512), P(D), P(D + 1024),
+              None) == -1
+    assert ja(P(C), P(A), 10, 1.0, 0.01, 1e-3, 2, 40, 40, P(B), P(B + 256), P(D), P(D + 512), P(B + 8),
+              None) == -1
+    assert L.nbody_last_error()
+
+
 @pytest.mark.parametrize("n,leaf", [(1, 1), (9, 8), (100, 8), (1000, 3), (4096, 16), (70001, 8), (777, 64)])
 def test_tree_node_table_matches_oracle(orc, n, leaf):
     """The library's tree plan (host code) numbers and splits the nodes

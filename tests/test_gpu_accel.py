@@ -255,3 +255,25 @@ def test_mfma_variant_collide1m_sampled(orc):
     e = rms_rel(out[tg, :3], acc)
     print(f"mfma collide1m: force rms rel {e:.3e}, pot {rms_rel(out[tg, 3], pot):.3e}")
     assert e <= 1e-5
+
+
+def test_caller_outputs_must_fit():
+    """A caller-supplied `out` of the wrong row count or dtype is refused in
+    the binding before any kernel is launched."""
+    torch, nb = gpu()
+    p = torch.rand(300, 4, device="cuda")
+    perm = torch.arange(300, dtype=torch.int32, device="cuda")
+    with pytest.raises(ValueError):
+        nb.accel(p, 0.01, out=torch.empty(299, 4, device="cuda"))
+    with pytest.raises(ValueError):
+        nb.accel(p, 0.01, target_begin=100, target_count=50, out=torch.empty(60, 4, device="cuda"))
+    with pytest.raises(TypeError):
+        nb.accel(p, 0.01, out=torch.empty(300, 4, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        nb.permute(p, perm, out=torch.empty(200, 4, device="cuda"))
+    with pytest.raises(ValueError):
+        nb.batched_accel(p, [0, 100, 300], 0.01, out=torch.empty(100, 4, device="cuda"))
+    with pytest.raises(ValueError):
+        nb.tree_accel(p, 0.01, 0.5, out=torch.empty(30, 4, device="cuda"))
+    out = torch.empty(50, 4, device="cuda")
+    assert nb.accel(p, 0.01, target_begin=100, target_count=50, out=out) is out

@@ -90,3 +90,34 @@ def test_orb_rejects_large_leaf():
     p = to_dev(torch, ics.plummer(100, 213)[0], torch.float32)
     with pytest.raises(nb.NBodyError):
         nb.orb_order(p, 5000)
+
+
+@pytest.mark.parametrize("inverse", [False, True])
+@pytest.mark.parametrize("dtype_name", ["float32", "float64"])
+def test_permute_skips_entries_outside_range(inverse, dtype_name):
+    """An index outside [0, n) in perm is skipped by the gather and the
+    scatter: no record is read or written for it, the others are moved."""
+    torch, nb = gpu()
+    dtype = getattr(torch, dtype_name)
+    n = 1000
+    src = torch.arange(4 * n, dtype=dtype, device="cuda").reshape(n, 4)
+    perm = torch.arange(n - 1, -1, -1, dtype=torch.int32, device="cuda")
+    bad = [3, 500, 999]
+    perm[bad[0]] = -1
+    perm[bad[1]] = n
+    perm[bad[2]] = 2 ** 31 - 1
+    out = torch.full((n, 4), -7.0, dtype=dtype, device="cuda")
+    nb.permute(src, perm, inverse=inverse, out=out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    want = np.full((n, 4), -7.0)
+    s = src.cpu().numpy()
+    for p in range(n):
+        if p in bad:
+            continue
+        q = n - 1 - p
+        if inverse:
+            want[q] = s[p]
+        else:
+            want[p] = s[q]
+    assert np.array_equal(got, want)
