@@ -69,7 +69,7 @@ def main():
                          "and one 1 GiB device copy (the copy calibrates byte counters); no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU target sharding is designed, not built)"}))
         sys.exit(2)
 

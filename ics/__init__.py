@@ -7,8 +7,7 @@ the oracle and the HIP path can both be fed from it without sharing any of
 the method's code.
 
 Workloads follow the paper's n-body setting (Section IV: bodies moving under
-their mutual gravitation) at the sizes and distributions named in the
-workload table of the design doc:
+their mutual gravitation); the generators are:
 
 * ``uniform_ball``   -- uniform density in the unit sphere, at rest.
 * ``plummer``        -- isotropic Plummer sphere (scale radius a, mass M).
