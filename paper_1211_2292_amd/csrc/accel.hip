@@ -71,8 +71,8 @@ __device__ __forceinline__ void wave_f32(const float4 *__restrict__ src, int n, 
         for (int t = 0; t < TPL; ++t)
 #pragma unroll
             for (int c = 0; c < 4; ++c) R[t][c].zero();
-        for (int jc = jb; jc < je; jc += jtile) {
-            const int ce = min(jc + jtile, je);
+        for (int jc = jb, ce; jc < je; jc = ce) {
+            ce = je - jc > jtile ? jc + jtile : je;  // no jc + jtile past je (int range)
             S.zero();
             range_f32<TPL>(src, jc, ce, d0, d1, T, eps2, S);
 #pragma unroll
@@ -163,8 +163,8 @@ __device__ __forceinline__ void wave_f64(const double4 *__restrict__ src, int n,
 #pragma unroll
         for (int c = 0; c < 4; ++c) R[t][c] = 0.0;
     Sums<double, TPL> S;
-    for (int jc = jb; jc < je; jc += jtile) {
-        const int ce = min(jc + jtile, je);
+    for (int jc = jb, ce; jc < je; jc = ce) {
+        ce = je - jc > jtile ? jc + jtile : je;  // no jc + jtile past je (int range)
         S.zero();
         const int lo = min(max(d0, jc), ce);
         const int hi = min(max(d1, jc), ce);

@@ -229,8 +229,8 @@ __device__ __forceinline__ void vjp_general(const V *__restrict__ pm, const V *_
 #pragma unroll
         for (int c = 0; c < kVN; ++c) R[t][c] = 0.0;
     VAcc<T, TPL, PHI> S;
-    for (int jc = jb; jc < je; jc += jtile) {
-        const int ce = min(jc + jtile, je);
+    for (int jc = jb, ce; jc < je; jc = ce) {
+        ce = je - jc > jtile ? jc + jtile : je;  // no jc + jtile past je (int range)
         const int lo = min(max(d0, jc), ce);
         const int hi = min(max(d1, jc), ce);
         S.zero();
@@ -392,8 +392,8 @@ __device__ __forceinline__ void vjp_scaled(const V *__restrict__ pm, const V *__
 #pragma unroll
         for (int c = 0; c < 10; ++c) R[t][c] = 0.0;
     SAcc<T, TPL> S;
-    for (int jc = jb; jc < je; jc += jtile) {
-        const int ce = min(jc + jtile, je);
+    for (int jc = jb, ce; jc < je; jc = ce) {
+        ce = je - jc > jtile ? jc + jtile : je;  // no jc + jtile past je (int range)
         const int lo = min(max(d0, jc), ce);
         const int hi = min(max(d1, jc), ce);
         S.zero();
