@@ -19,6 +19,10 @@
  *     vel       (vx, vy, vz, unused)
  *     acc_pot   (ax, ay, az, phi)   the output of the force evaluation
  *   float4 buffers must be 16-byte aligned, double4 buffers 32-byte aligned.
+ *   Buffers that a call writes must not share memory with the buffers it
+ *   reads or with each other (arrays updated in place, such as the
+ *   integrators' pos_mass, vel and acc_pot, are mutually disjoint); calls
+ *   refuse such arguments with NBODY_E_INVAL.
  * - Law (Section IV; G and Plummer softening eps are parameters):
  *     a_i   =  G sum_{j != i} m_j (x_j - x_i) / (|x_j - x_i|^2 + eps^2)^(3/2)
  *     phi_i = -G sum_{j != i} m_j / (|x_j - x_i|^2 + eps^2)^(1/2)

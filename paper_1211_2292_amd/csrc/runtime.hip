@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <initializer_list>
 #include <map>
 #include <mutex>
 #include <string>
@@ -114,6 +115,27 @@ static bool overlap(const void *a, size_t na, const void *b, size_t nb)
 {
     const char *x = (const char *)a, *y = (const char *)b;
     return a && b && x < y + nb && y < x + na;
+}
+
+struct Buf {
+    const void *p;
+    size_t bytes;
+};
+
+// True (with the error set) when an output shares memory with an input or
+// with another output; NULL buffers are skipped.
+static bool outputs_overlap(std::initializer_list<Buf> outs, std::initializer_list<Buf> ins)
+{
+    for (auto o = outs.begin(); o != outs.end(); ++o) {
+        bool bad = false;
+        for (const Buf &i : ins) bad = bad || overlap(o->p, o->bytes, i.p, i.bytes);
+        for (auto q = o + 1; q != outs.end(); ++q) bad = bad || overlap(o->p, o->bytes, q->p, q->bytes);
+        if (bad) {
+            set_error("an output buffer overlaps an input or another output");
+            return true;
+        }
+    }
+    return false;
 }
 
 #define NB_CHECK(expr)                 \
@@ -544,6 +566,10 @@ int nbody_energy(const void *pos_mass, const void *vel, const void *acc_pot, int
         set_error("energy_out NULL or misaligned");
         return NBODY_E_INVAL;
     }
+    {
+        const size_t rb = rec_bytes(prec) * (size_t)n;
+        if (outputs_overlap({{energy_out, 16}}, {{pos_mass, rb}, {vel, rb}, {acc_pot, rb}})) return NBODY_E_INVAL;
+    }
     const int nb = step_blocks((int)n);
     double *ep = (double *)scratch(kSlotEnergy, sizeof(double) * 2 * nb);
     if (!ep) {
@@ -740,6 +766,7 @@ int nbody_orb_order(const void *pos_mass, int32_t prec, int64_t n, int32_t leaf,
         set_error("perm_out NULL or misaligned");
         return NBODY_E_INVAL;
     }
+    if (outputs_overlap({{perm_out, 4 * (size_t)n}}, {{pos_mass, rec_bytes(prec) * (size_t)n}})) return NBODY_E_INVAL;
     return orb_order(pos_mass, prec, (int)n, leaf, perm_out, (hipStream_t)stream);
 }
 
@@ -829,6 +856,13 @@ int nbody_tree_local_counts(const void *pos_mass, int64_t n, int32_t leaf, doubl
         set_error("count arrays NULL or misaligned");
         return NBODY_E_INVAL;
     }
+    {
+        int64_t ng = 0;
+        NB_CHECK(tree_shape((int)n, leaf, nullptr, &ng, nullptr));
+        const size_t g4 = 4 * (size_t)ng;
+        if (outputs_overlap({{loc_count, g4}, {far_count, g4}, {near_count, g4}}, {{pos_mass, 16 * (size_t)n}}))
+            return NBODY_E_INVAL;
+    }
     return tree_local_counts(pos_mass, (int)n, leaf, theta, loc_count, far_count, near_count,
                              (hipStream_t)stream);
 }
@@ -856,6 +890,10 @@ int nbody_tree_moments(const void *pos_mass, int64_t n, int32_t leaf, double *mo
         set_error("moments_out or box_out misaligned");
         return NBODY_E_ALIGN;
     }
+    int64_t nn = 0;
+    NB_CHECK(tree_shape((int)n, leaf, &nn, nullptr, nullptr));
+    if (outputs_overlap({{moments_out, 40 * (size_t)nn}, {box_out, 24 * (size_t)nn}}, {{pos_mass, 16 * (size_t)n}}))
+        return NBODY_E_INVAL;
     return tree_moments(pos_mass, (int)n, leaf, moments_out, box_out, (hipStream_t)stream);
 }
 
@@ -875,6 +913,15 @@ int nbody_tree_lists(const void *pos_mass, int64_t n, int32_t leaf, double theta
         ((uintptr_t)near_ids % 4)) {
         set_error("count or id arrays not 4-byte aligned");
         return NBODY_E_ALIGN;
+    }
+    {
+        int64_t ng = 0;
+        NB_CHECK(tree_shape((int)n, leaf, nullptr, &ng, nullptr));
+        const size_t g4 = 4 * (size_t)ng;
+        if (outputs_overlap({{far_count, g4}, {near_count, g4}, {far_ids, g4 * (size_t)max_far},
+                             {near_ids, g4 * (size_t)max_near}},
+                            {{pos_mass, 16 * (size_t)n}}))
+            return NBODY_E_INVAL;
     }
     return tree_lists(pos_mass, (int)n, leaf, theta, max_far, max_near, far_count, near_count, far_ids,
                       near_ids, (hipStream_t)stream);
@@ -1083,6 +1130,12 @@ int nbody_trajectory_forward(void *pos_mass, void *vel, int64_t n, int32_t prec,
     NB_CHECK(check_vec(vel, prec, "vel"));
     NB_CHECK(check_vec(ckpt, prec, "ckpt"));
     const size_t rb = rec_bytes(prec) * (size_t)n;
+    if (overlap(pos_mass, rb, vel, rb)) {
+        set_error("pos_mass and vel must not overlap");
+        return NBODY_E_INVAL;
+    }
+    if (outputs_overlap({{ckpt, (size_t)(nsteps / ckpt_every + 1) * 2 * rb}}, {{pos_mass, rb}, {vel, rb}}))
+        return NBODY_E_INVAL;
     void *acc = scratch(kSlotAdj0, rb);
     if (!acc) {
         set_error("cannot allocate trajectory scratch");
@@ -1134,6 +1187,9 @@ int nbody_trajectory_adjoint(const void *ckpt, int64_t n, int32_t prec, double G
     const size_t rb = rec_bytes(prec) * (size_t)n;
     const int C = ckpt_every;
     const int nseg = nsteps / C;
+    if (outputs_overlap({{pos_cot, rb}, {vel_cot, rb}, {mass_cot, mb * (size_t)n}},
+                        {{ckpt, (size_t)(nseg + 1) * 2 * rb}, {xbar_T, rb}, {vbar_T, rb}}))
+        return NBODY_E_INVAL;
     void *acc = scratch(kSlotAdj0, rb);
     char *xs = (char *)scratch(kSlotAdj1, rb * (size_t)(C + 1));
     void *vt = scratch(kSlotAdj2, rb);

@@ -172,6 +172,20 @@ def test_overlapping_buffers_rejected():
               None) == -1
     assert ja(P(C), P(A), 10, 1.0, 0.01, 1e-3, 2, 40, 40, P(B), P(B + 256), P(D), P(D + 512), P(B + 8),
               None) == -1
+    # energies, ORB order, tree inspection and the checkpointed trajectory
+    assert L.nbody_energy(P(A), P(B), P(C), 100, 1, P(C + 1600 - 8), None) == -1
+    assert L.nbody_orb_order(P(A), 1, 100, 8, P(A + 1596), None) == -1
+    assert L.nbody_tree_moments(P(A), 100, 8, P(B), P(B + 64), None) == -1
+    assert L.nbody_tree_moments(P(A), 100, 8, P(A + 8), None, None) == -1
+    assert L.nbody_tree_lists(P(A), 100, 8, 0.5, 0, 0, P(B), P(B + 4), None, None, None) == -1
+    assert L.nbody_tree_lists(P(A), 100, 8, 0.5, 4, 0, P(B), P(C), P(C + 4), None, None) == -1
+    assert L.nbody_tree_local_counts(P(A), 100, 4, 0.5, P(B), P(C), P(B + 4), None) == -1
+    assert L.nbody_trajectory_forward(P(A), P(A + 800), 100, 1, 1.0, 0.01, 1e-3, 20, 20, P(D), None) == -1
+    assert L.nbody_trajectory_forward(P(A), P(B), 100, 1, 1.0, 0.01, 1e-3, 20, 20, P(B + 1024), None) == -1
+    assert L.nbody_trajectory_adjoint(P(A), 100, 1, 1.0, 0.01, 1e-3, 20, 20, P(B), P(C), P(A + 4800),
+                                      P(D), P(D + 4096), 1, None) == -1
+    assert L.nbody_trajectory_adjoint(P(A), 100, 1, 1.0, 0.01, 1e-3, 20, 20, P(B), P(C), P(D),
+                                      P(D + 1024), P(D + 8192), 1, None) == -1
     assert L.nbody_last_error()
 
 
