@@ -113,3 +113,60 @@ def test_batched_leapfrog_graph_matches_eager():
             assert torch.equal(ps, p0[a:b]) and torch.equal(vs, v0[a:b]), s
     finally:
         nb.set_tuning(0, prec)
+
+
+@pytest.mark.parametrize("mode", ["F32_KAHAN", "F64"])
+def test_batched_with_empty_systems(orc, mode):
+    """Systems of zero bodies (first, last and in between) take no work and
+    leave the other systems' results as their standalone evaluations; the
+    batched leapfrog steps over them too."""
+    torch, nb = gpu()
+    prec = getattr(nb, mode)
+    dtype = torch.float64 if mode == "F64" else torch.float32
+    sizes = [0, 5, 0, 0, 70, 1, 0]
+    pm, vel, off = _batch(sizes, 90)
+    p = to_dev(torch, pm, dtype)
+    # the standalone kernel in the batched kernel's shape (one source range)
+    nb.set_tuning(0, prec, *nb.get_tuning(1, prec, pm.shape[0]))
+    try:
+        out = nb.batched_accel(p, off, 0.01, prec=prec)
+        torch.cuda.synchronize()
+        for s in range(len(sizes)):
+            a, b = off[s], off[s + 1]
+            if b > a:
+                ref = nb.accel(p[a:b].contiguous(), 0.01, prec=prec)
+                torch.cuda.synchronize()
+                assert torch.equal(out[a:b], ref), s
+        v = to_dev(torch, vel, dtype)
+        pb, vb, ab = p.clone(), v.clone(), torch.empty_like(p)
+        nb.leapfrog_kdk(pb, vb, ab, 0.01, 1e-3, 3, prec=prec, offsets=off)
+        singles = {}
+        for s in (1, 4):
+            a, b = off[s], off[s + 1]
+            ps, vs, as_ = p[a:b].clone(), v[a:b].clone(), torch.empty_like(p[a:b])
+            nb.leapfrog_kdk(ps, vs, as_, 0.01, 1e-3, 3, prec=prec)
+            singles[s] = (ps, vs)
+        torch.cuda.synchronize()
+    finally:
+        nb.set_tuning(0, prec)
+    src = pm if mode == "F64" else widen32(pm)
+    acc, _ = orc.accel(src[off[4]:off[5]], 0.01)
+    assert rms_rel(host(out)[off[4]:off[5], :3], acc) <= (1e-12 if mode == "F64" else 2e-6)
+    # the batched leapfrog: each non-empty system as if alone
+    for s, (ps, vs) in singles.items():
+        a, b = off[s], off[s + 1]
+        assert torch.equal(pb[a:b], ps), s
+        assert torch.equal(vb[a:b], vs), s
+
+
+def test_empty_target_range():
+    """target_count = 0 is a valid call that writes nothing."""
+    torch, nb = gpu()
+    p = to_dev(torch, ics.plummer(100, 91)[0], torch.float32)
+    out = nb.accel(p, 0.01, target_begin=40, target_count=0)
+    torch.cuda.synchronize()
+    assert out.shape == (0, 4)
+    sentinel = torch.full((5, 4), 7.0, device="cuda")
+    nb.accel(p, 0.01, target_begin=100, target_count=0, out=sentinel[:0])
+    torch.cuda.synchronize()
+    assert torch.all(sentinel == 7.0)
