@@ -27,6 +27,8 @@ Also reported on the same JSON line:
   expansions) at theta 0.5, 0.7, 1.0: time, work and error against the exact
   sum;
 * shard: one GPU's share of an 8-way target split (131072 x 1048576).
+* modes: pure FP32 and Kahan-compensated FP32 sums on the same workload at
+  step 0, each with its time and its error against the oracle sample.
 """
 from __future__ import annotations
 
@@ -43,6 +45,8 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (AMD), packed FP32 counted
 FLOP_PER_PAIR = 20
+VARIANTS = {0: "scalar-load sources", 1: "LDS sources", 2: "matrix-core contraction"}
+VARIANT_KERNELS = {0: "k_accel_f32", 1: "k_accel_lds_f32", 2: "k_accel_mfma_f32"}
 FLOP_PER_QUAD_CELL = 54   # one quadrupole cell against one target, counted like the pair's 20
 FLOP_PER_M2L = 313        # one cell folded into a group's third-order local expansion (m2l_f32)
 
@@ -146,6 +150,7 @@ def main():
     torch.cuda.synchronize()
     acc0 = np.empty((n, 4))
     acc0[perm_host] = acc.cpu().double().numpy()
+    modes = {} if args.no_extras else modes_leg(torch, nb, pm, eps, perm_host)
     energy0 = nb.energy(pm, vel, acc, prec=prec).cpu().numpy()
     h = 0.5 * dt
     nb.kick_drift(pm, vel, acc, h, dt, close=False, open=True, prec=prec)
@@ -208,7 +213,7 @@ def main():
                                "dt=5e-4, leapfrog KDK, NBODY_F32_F64ACC",
                    "n": n, "eps": eps, "dt": dt, "precision": "F32_F64ACC",
                    "kernel_shape": {"tpl": tune[0], "jsplit": tune[1], "jtile": tune[2],
-                                    "variant": ["scalar-load sources", "LDS sources"][tune[3]]}},
+                                    "variant": VARIANTS.get(tune[3], str(tune[3]))}},
         "pct_fp32_peak": round(100 * achieved / PEAK_FP32_TFLOPS, 2),
         "wall_s_timed": round(wall, 3),
         "orb": {"leaf": 256, "order_ms": round(orb_ms, 3), "gather_ms": round(gather_ms, 3)},
@@ -218,7 +223,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
                      "traffic": measured_traffic(tune, n),
-                     "kernel": ("k_accel_lds_f32" if tune[3] else "k_accel_f32") + f"<{tune[0]}, F64ACC>",
+                     "kernel": VARIANT_KERNELS.get(tune[3], "k_accel_f32") + f"<{tune[0]}, F64ACC>",
                      "flop_per_pair": FLOP_PER_PAIR,
                      "avg_launch_ms": round(kern_avg, 4),
                      "launch_ms_std": round(float(np.std(kern_ms)), 4),
@@ -231,7 +236,8 @@ def main():
         result["batched"] = batched_leg(torch, nb, ics, dev)
         result["tree"] = tree_leg(torch, nb, pm_np, eps, kern_avg, v_np=v_np, dt=dt)
         result["shard"] = shard_leg(torch, nb, pm, eps, prec)
-        result["cpu_baseline"] = cpu_leg(ics, pm0_host, acc0, eps, args.cpu_seconds)
+        result["cpu_baseline"] = cpu_leg(ics, pm0_host, acc0, eps, args.cpu_seconds, modes)
+        result["modes"] = modes
     print(json.dumps(result), flush=True)
 
 
@@ -598,8 +604,36 @@ def tree_leg(torch, nb, pm_np, eps, direct_ms, leaf=4, v_np=None, dt=5e-4):
     return res
 
 
-def cpu_leg(ics, pm0_host, acc0, eps, seconds):
-    """FP64 oracle on a bounded sample of targets of the headline workload."""
+def modes_leg(torch, nb, pm, eps, perm_host):
+    """Pure FP32 and Kahan-compensated FP32 sums on the headline workload at
+    its step-0 positions: the time of one force evaluation, and the result in
+    input order, whose error the CPU leg takes against the oracle sample."""
+    n = pm.shape[0]
+    out = torch.empty_like(pm)
+    res = {}
+    for name in ("F32", "F32_KAHAN"):
+        prec = getattr(nb, name)
+        nb.accel(pm, eps, prec=prec, out=out)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(2):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            nb.accel(pm, eps, prec=prec, out=out)
+            b.record()
+            b.synchronize()
+            ts.append(a.elapsed_time(b))
+        host = np.empty((n, 4))
+        host[perm_host] = out.cpu().double().numpy()
+        ms = min(ts)
+        res[name] = {"ms": round(ms, 3), "g_interactions_per_s": round(float(n) * n / ms / 1e6, 2), "_out": host}
+        log(f"[bench] mode {name}: {ms:.2f} ms")
+    return res
+
+
+def cpu_leg(ics, pm0_host, acc0, eps, seconds, modes=None):
+    """FP64 oracle on a bounded sample of targets of the headline workload;
+    also the error of each other mode's result (`modes`) on the same sample."""
     import oracle
     n = pm0_host.shape[0]
     threads = oracle.num_threads()
@@ -622,6 +656,12 @@ def cpu_leg(ics, pm0_host, acc0, eps, seconds):
     gint = k * n / secs / 1e9
     da = np.linalg.norm(acc0[tg, :3] - ref_a, axis=1) / np.linalg.norm(ref_a, axis=1)
     dp = np.abs(acc0[tg, 3] - ref_p) / np.abs(ref_p)
+    for m in (modes or {}).values():
+        out = m.pop("_out")
+        ma = np.linalg.norm(out[tg, :3] - ref_a, axis=1) / np.linalg.norm(ref_a, axis=1)
+        mp = np.abs(out[tg, 3] - ref_p) / np.abs(ref_p)
+        m["error_vs_oracle"] = {"force_rms_rel": float(np.sqrt(np.mean(ma ** 2))), "force_max_rel": float(ma.max()),
+                                "pot_rms_rel": float(np.sqrt(np.mean(mp ** 2))), "targets": int(k)}
     return {"value": round(gint, 5), "unit": "G-interactions/s", "cores": threads, "kind": "oracle",
             "sample": f"{k} sampled targets x {n} sources of the colliding pair, FP64 Neumaier sums",
             "seconds": round(secs, 2),

@@ -60,7 +60,8 @@ extern "C" {
 /* Arithmetic of the force evaluation. */
 typedef enum {
     NBODY_F64 = 0,        /* FP64 state, FP64 pair arithmetic and sums          */
-    NBODY_F32 = 1,        /* FP32 state, FP32 pair arithmetic, FP32 running sum */
+    NBODY_F32 = 1,        /* FP32 pair arithmetic, FP32 per-tile partial sums,
+                             plain FP32 sum across tiles                       */
     NBODY_F32_KAHAN = 2,  /* FP32 pair arithmetic, FP32 per-tile partial sums,
                              Kahan-compensated FP32 sum across tiles           */
     NBODY_F32_F64ACC = 3  /* FP32 pair arithmetic, FP32 per-tile partial sums,

@@ -20,8 +20,7 @@
 //   bit for bit).
 // * Sources are processed in tiles of `jtile`; the FP32 partial sum of a tile
 //   is folded into the running per-target sum by the precision mode (plain
-//   FP32, Kahan-compensated FP32, or FP64).  Pure FP32 mode keeps a single
-//   running FP32 sum.
+//   FP32, Kahan-compensated FP32, or FP64).
 // * The self pair is removed exactly: only the sub-range of sources that
 //   overlaps the wave's own targets runs the masked variant (one compare and
 //   one select per pair); every other source range runs unmasked.
@@ -55,39 +54,28 @@ __device__ __forceinline__ void wave_f32(const float4 *__restrict__ src, int n, 
     }
     const int d0 = t0, d1 = t0 + 64 * TPL;
     Sums<float, TPL> S;
-    S.zero();
-    if constexpr (MODE == M_F32) {
-        range_f32<TPL>(src, jb, je, d0, d1, T, eps2, S);
+    Run<MODE> R[TPL][4];
+#pragma unroll
+    for (int t = 0; t < TPL; ++t)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) R[t][c].zero();
+    for (int jc = jb, ce; jc < je; jc = ce) {
+        ce = je - jc > jtile ? jc + jtile : je;  // no jc + jtile past je (int range)
+        S.zero();
+        // pure FP32 pins the per-source schedule (see sweep_f32)
+        range_f32<TPL, MODE == M_F32>(src, jc, ce, d0, d1, T, eps2, S);
 #pragma unroll
         for (int t = 0; t < TPL; ++t) {
-            res[t][0] = S.ax[t];
-            res[t][1] = S.ay[t];
-            res[t][2] = S.az[t];
-            res[t][3] = S.ph[t];
+            R[t][0].fold(S.ax[t]);
+            R[t][1].fold(S.ay[t]);
+            R[t][2].fold(S.az[t]);
+            R[t][3].fold(S.ph[t]);
         }
-    } else {
-        Run<MODE> R[TPL][4];
-#pragma unroll
-        for (int t = 0; t < TPL; ++t)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) R[t][c].zero();
-        for (int jc = jb, ce; jc < je; jc = ce) {
-            ce = je - jc > jtile ? jc + jtile : je;  // no jc + jtile past je (int range)
-            S.zero();
-            range_f32<TPL>(src, jc, ce, d0, d1, T, eps2, S);
-#pragma unroll
-            for (int t = 0; t < TPL; ++t) {
-                R[t][0].fold(S.ax[t]);
-                R[t][1].fold(S.ay[t]);
-                R[t][2].fold(S.az[t]);
-                R[t][3].fold(S.ph[t]);
-            }
-        }
-#pragma unroll
-        for (int t = 0; t < TPL; ++t)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) res[t][c] = R[t][c].get();
     }
+#pragma unroll
+    for (int t = 0; t < TPL; ++t)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) res[t][c] = R[t][c].get();
 }
 
 // ---- FP64 pair ---------------------------------------------------------------
@@ -252,36 +240,26 @@ __device__ __forceinline__ void block_lds_f32(const float4 *__restrict__ src, in
         sweep_lds<TPL, false>(tile[buf], j0, 0, lo, T, eps2, S);
         sweep_lds<TPL, true>(tile[buf], j0, lo, hi, T, eps2, S);
         sweep_lds<TPL, false>(tile[buf], j0, hi, cnt, T, eps2, S);
-        if constexpr (MODE != M_F32) {
-            since += cnt;
-            if (since >= jtile || jn >= je) {
+        since += cnt;
+        if (since >= jtile || jn >= je) {
 #pragma unroll
-                for (int t = 0; t < TPL; ++t) {
-                    R[t][0].fold(S.ax[t]);
-                    R[t][1].fold(S.ay[t]);
-                    R[t][2].fold(S.az[t]);
-                    R[t][3].fold(S.ph[t]);
-                }
-                S.zero();
-                since = 0;
+            for (int t = 0; t < TPL; ++t) {
+                R[t][0].fold(S.ax[t]);
+                R[t][1].fold(S.ay[t]);
+                R[t][2].fold(S.az[t]);
+                R[t][3].fold(S.ph[t]);
             }
+            S.zero();
+            since = 0;
         }
         if (jn < je) tile[buf ^ 1][threadIdx.x] = pre;
         __syncthreads();
         buf ^= 1;
     }
 #pragma unroll
-    for (int t = 0; t < TPL; ++t) {
-        if constexpr (MODE == M_F32) {
-            res[t][0] = S.ax[t];
-            res[t][1] = S.ay[t];
-            res[t][2] = S.az[t];
-            res[t][3] = S.ph[t];
-        } else {
+    for (int t = 0; t < TPL; ++t)
 #pragma unroll
-            for (int c = 0; c < 4; ++c) res[t][c] = R[t][c].get();
-        }
-    }
+        for (int c = 0; c < 4; ++c) res[t][c] = R[t][c].get();
 }
 
 // ---- FP32 sweep with the source contraction on the matrix cores ---------------
@@ -428,16 +406,14 @@ __global__ __launch_bounds__(kBlock) void k_accel_mfma_f32(const float4 *__restr
         sweep_mfma<false>(src, tl, j0, 0, lo, c, xt.x, xt.y, xt.z, ii, eps2, D, pot);
         sweep_mfma<true>(src, tl, j0, lo, hi, c, xt.x, xt.y, xt.z, ii, eps2, D, pot);
         sweep_mfma<false>(src, tl, j0, hi, cnt, c, xt.x, xt.y, xt.z, ii, eps2, D, pot);
-        if constexpr (MODE != M_F32) {
-            since += cnt;
-            if (since >= jtile || jn >= je) {
+        since += cnt;
+        if (since >= jtile || jn >= je) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k) R[k].fold(D[k]);
-                R[4].fold(pot);
-                D = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-                pot = 0.0f;
-                since = 0;
-            }
+            for (int k = 0; k < 4; ++k) R[k].fold(D[k]);
+            R[4].fold(pot);
+            D = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+            pot = 0.0f;
+            since = 0;
         }
         if (jn < je) tile[buf ^ 1][threadIdx.x] = pre;
         __syncthreads();
@@ -445,13 +421,8 @@ __global__ __launch_bounds__(kBlock) void k_accel_mfma_f32(const float4 *__restr
     }
     if (!active || ii >= tend) return;
     double s[5];
-    if constexpr (MODE == M_F32) {
-        for (int k = 0; k < 4; ++k) s[k] = D[k];
-        s[4] = pot;
-    } else {
 #pragma unroll
-        for (int k = 0; k < 5; ++k) s[k] = R[k].get();
-    }
+    for (int k = 0; k < 5; ++k) s[k] = R[k].get();
     const double rx = (double)xt.x - (double)cen.x, ry = (double)xt.y - (double)cen.y,
                  rz = (double)xt.z - (double)cen.z;
     double res[4] = {s[0] - rx * s[3], s[1] - ry * s[3], s[2] - rz * s[3], s[4]};
