@@ -71,6 +71,9 @@ def main():
     ap.add_argument("--counters", action="store_true",
                     help="counter-collection mode: two force launches of the headline workload "
                          "and one 1 GiB device copy (the copy calibrates byte counters); no JSON")
+    ap.add_argument("--counters-variant", type=int, default=0, choices=(0, 1),
+                    help="with --counters: 0 = the default kernel shape, 1 = sources staged in LDS "
+                         "(2 targets per lane, 4 source splits, tiles of 512)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 "
@@ -97,13 +100,17 @@ def main():
     pm0_host = pm.cpu().double().numpy()
 
     if args.counters:
+        if args.counters_variant == 1:
+            nb.set_tuning(0, prec, 2, 4, 512, 1)
         for _ in range(2):
             nb.accel(pm, eps, prec=prec, out=acc)
+        nb.set_tuning(0, prec)
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        log("[bench] counters mode: 2 force launches, 1 GiB copy (1073741824 B read + written)")
+        log(f"[bench] counters mode: 2 force launches (variant {args.counters_variant}), "
+            "1 GiB copy (1073741824 B read + written)")
         return
 
     if args.tree_counters:
