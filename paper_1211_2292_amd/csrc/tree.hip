@@ -75,7 +75,9 @@
 // definitions, so the lists equal the FP64 definition's.
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <utility>
 #include <vector>
 
 #include "internal.h"
@@ -742,6 +744,25 @@ void groups_rec(HostTree &h, int id)
     groups_rec(h, nd.w);
 }
 
+// (node count, group count) of the plan for `size` bodies without building
+// it: the recursion splits as build_rec does and meets at most two sizes per
+// level, so with the memo it takes O(log(size / leaf)) steps.
+std::pair<int64_t, int64_t> plan_counts(int size, int leaf, std::map<int, std::pair<int64_t, int64_t>> &memo)
+{
+    const auto it = memo.find(size);
+    if (it != memo.end()) return it->second;
+    std::pair<int64_t, int64_t> r(1, 1);
+    if (size > leaf) {
+        const int L = (size + leaf - 1) / leaf;
+        const int k = std::min(size, leaf * ((L + 1) / 2));
+        const auto a = plan_counts(k, leaf, memo), b = plan_counts(size - k, leaf, memo);
+        r.first = 1 + a.first + b.first;
+        r.second = size <= kGroup ? 1 : a.second + b.second;
+    }
+    memo.emplace(size, r);
+    return r;
+}
+
 void plan(HostTree &h, int n, int leaf)
 {
     h = HostTree();
@@ -913,6 +934,13 @@ hipError_t launch_walk(const float4 *pm, int n, const TreeDev &d, int ngroups, f
 
 int tree_shape(int n, int leaf, int64_t *num_nodes, int64_t *num_groups, int32_t *nodes_out)
 {
+    if (!nodes_out) {
+        std::map<int, std::pair<int64_t, int64_t>> memo;
+        const auto c = plan_counts(n, leaf, memo);
+        if (num_nodes) *num_nodes = c.first;
+        if (num_groups) *num_groups = c.second;
+        return NBODY_OK;
+    }
     HostTree h;
     plan(h, n, leaf);
     if (num_nodes) *num_nodes = (int64_t)h.node.size();

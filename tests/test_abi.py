@@ -198,6 +198,19 @@ def test_tree_node_table_matches_oracle(orc, n, leaf):
     want = orc.tree_nodes(n, leaf)
     assert np.array_equal(tab.astype(np.int64), want)
     assert ng == orc._load().oracle_tree_num_groups(n, leaf, nb.TREE_GROUP)
+    # the counts-only call (no table) takes a shortcut and must agree
+    assert nb.tree_shape(n, leaf) == (nn, ng) == (want.shape[0], ng)
+
+
+@pytest.mark.parametrize("n,leaf", [(1 << 20, 4), (10_000_019, 8), (3_000_001, 1), ((1 << 31) - 4096, 64)])
+def test_tree_counts_shortcut_at_large_n(orc, n, leaf):
+    """Node and group counts without building the plan, against the oracle's
+    recursion."""
+    nb, L = _lib()
+    nn, ng = nb.tree_shape(n, leaf)
+    lib = orc._load()
+    assert nn == lib.oracle_tree_nodes(n, leaf, None)
+    assert ng == lib.oracle_tree_num_groups(n, leaf, nb.TREE_GROUP)
 
 
 def test_tuning_pin_roundtrip():
