@@ -171,7 +171,9 @@ def test_full_size_collide1m_sampled(orc):
         out = _run(nb, torch, pm32, w["eps"], mode, torch.float32)
         e = rms_rel(out[tg, :3], acc)
         print(f"collide1m {mode}: force rms rel {e:.3e}, pot rms rel {rms_rel(out[tg, 3], pot):.3e}")
-        assert e <= (1e-4 if mode == "F32" else 1e-5)
+        # every FP32 mode sums per-tile partials, pure FP32 too: all meet 1e-5
+        assert e <= 1e-5
+        assert rms_rel(out[tg, 3], pot) <= 1e-5
 
 
 @pytest.mark.parametrize("mode", ["F32", "F32_KAHAN", "F32_F64ACC"])

@@ -68,8 +68,7 @@ def test_collide1m_20_steps(orc, mode):
     acc1, _ = orc.accel(host(p), w["eps"], targets=tg)
     e1 = rms_rel(host(a)[tg, :3], acc1)
     print(f"collide1m {mode}: step 0 {e0:.2e}, step 20 {e1:.2e}")
-    bar = 1e-4 if mode == "F32" else 1e-5
-    assert e0 <= bar and e1 <= bar
+    assert e0 <= 1e-5 and e1 <= 1e-5
 
 
 def test_gradient_plummer_200_steps(orc):
