@@ -434,8 +434,11 @@ __device__ __forceinline__ void sweep_quad(const float4 *qb, int cnt, const Targ
 
 template <int MODE, bool INSPECT, int CELLS>
 // 7 waves per SIMD: 5 KB of LDS per wave and at most 72 VGPRs (measured
-// faster than 6 waves, and than 8 waves with register spills).
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void k_tree_walk(const float4 *__restrict__ src, int n, TreeDev T,
+// faster than 6 waves, and than 8 waves with register spills).  The local-
+// expansion walk keeps 20 expansion coefficients per lane and cannot reach 7;
+// asked for 5 it fits in 94 VGPRs without spills (left to itself the
+// allocator took 111, 4 waves).
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(CELLS == kCellsLocal ? 5 : 7))) void k_tree_walk(const float4 *__restrict__ src, int n, TreeDev T,
                                                   const float4 *__restrict__ cells, float eps2_in, double G,
                                                   double theta2, WalkOut O)
 {
