@@ -14,6 +14,7 @@ NBODY_F32_KAHAN).
 from __future__ import annotations
 
 import ctypes
+import functools
 import os
 import threading
 
@@ -155,10 +156,29 @@ def _prec(t: torch.Tensor, prec):
     return prec
 
 
+def _on_device(fn):
+    """Runs fn with the device of its GPU tensor arguments current: the
+    library launches on, and keeps its scratch for, the current HIP device.
+    Every GPU tensor argument must be on that one device."""
+    @functools.wraps(fn)
+    def wrapper(*args, **kw):
+        gpu = [a for a in (*args, *kw.values()) if isinstance(a, torch.Tensor) and a.device.type == "cuda"]
+        if not gpu:
+            return fn(*args, **kw)
+        dev = gpu[0].device
+        for t in gpu[1:]:
+            if t.device != dev:
+                raise ValueError(f"GPU tensors of one call must share a device, got {dev} and {t.device}")
+        with torch.cuda.device(dev):
+            return fn(*args, **kw)
+    return wrapper
+
+
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
+@_on_device
 def accel(pos_mass, eps, G=1.0, prec=None, target_begin=0, target_count=None, out=None):
     """Force and potential records for targets [target_begin, +target_count)."""
     pm = _rec(pos_mass, "pos_mass")
@@ -174,6 +194,7 @@ def accel(pos_mass, eps, G=1.0, prec=None, target_begin=0, target_count=None, ou
     return out
 
 
+@_on_device
 def accel_vjp(pos_mass, acc_pot_cot, eps, G=1.0, prec=None, forward=True):
     """(pos_cot (N,4), mass_cot (N,), acc_pot (N,4) or None) at one configuration."""
     pm = _rec(pos_mass, "pos_mass")
@@ -195,6 +216,7 @@ def _offsets(offsets):
     return o, int(o.numel() - 1), ctypes.c_void_p(o.data_ptr())
 
 
+@_on_device
 def leapfrog_kdk(pos_mass, vel, acc_pot, eps, dt, nsteps, G=1.0, prec=None, offsets=None,
                  acc_valid=False, graph=False, energy=False, energy_out=None):
     """nsteps of KDK leapfrog in place; returns the (nsteps+1, 2) FP64 energy
@@ -217,6 +239,7 @@ def leapfrog_kdk(pos_mass, vel, acc_pot, eps, dt, nsteps, G=1.0, prec=None, offs
     return en
 
 
+@_on_device
 def kick_drift(pos_mass, vel, acc_pot, h, dt, close, open, prec=None):
     """Elementwise leapfrog half-step in place (see nbody.h)."""
     pm = _rec(pos_mass, "pos_mass")
@@ -227,6 +250,7 @@ def kick_drift(pos_mass, vel, acc_pot, h, dt, close, open, prec=None):
                                   1 if close else 0, 1 if open else 0, _stream()))
 
 
+@_on_device
 def batched_accel(pos_mass, offsets, eps, G=1.0, prec=None, eps_per_sys=None, out=None):
     pm = _rec(pos_mass, "pos_mass")
     p = _prec(pm, prec)
@@ -248,6 +272,7 @@ def batched_accel(pos_mass, offsets, eps, G=1.0, prec=None, eps_per_sys=None, ou
     return out
 
 
+@_on_device
 def energy(pos_mass, vel, acc_pot, prec=None):
     """FP64 (K, U) of one system as a 2-element float64 GPU tensor."""
     pm = _rec(pos_mass, "pos_mass")
@@ -259,6 +284,7 @@ def energy(pos_mass, vel, acc_pot, prec=None):
     return out
 
 
+@_on_device
 def orb_order(pos_mass, leaf):
     """int32 permutation, perm[p] = original index at position p."""
     pm = _rec(pos_mass, "pos_mass")
@@ -268,6 +294,7 @@ def orb_order(pos_mass, leaf):
     return perm
 
 
+@_on_device
 def permute(src, perm, inverse=False, out=None):
     s = _rec(src, "src")
     if perm.dtype != torch.int32 or perm.device != s.device or not perm.is_contiguous() or \
@@ -302,6 +329,7 @@ def tree_shape(n, leaf, nodes=False):
     return nn.value, ng.value, tab
 
 
+@_on_device
 def tree_accel(pos_mass, eps, theta, leaf=4, G=1.0, prec=None, out=None, cells=CELLS_MONOPOLE):
     """Tree-code force and potential (ax, ay, az, phi) per body, ORB order.
     cells: CELLS_MONOPOLE (accepted cells as one body), CELLS_PSEUDO (as their
@@ -319,6 +347,7 @@ def tree_accel(pos_mass, eps, theta, leaf=4, G=1.0, prec=None, out=None, cells=C
     return out
 
 
+@_on_device
 def tree_pseudo(pos_mass, leaf=4):
     """Pseudo-particles of every node, (num_nodes, 12, 4) float32 =
     (x, y, z, q), for ORB-ordered records."""
@@ -329,6 +358,7 @@ def tree_pseudo(pos_mass, leaf=4):
     return out
 
 
+@_on_device
 def tree_local_counts(pos_mass, theta, leaf=4):
     """Per-group list sizes of the local-expansion walk: (loc, far, near)
     int32 (groups,)."""
@@ -340,6 +370,7 @@ def tree_local_counts(pos_mass, theta, leaf=4):
     return tuple(cnt)
 
 
+@_on_device
 def tree_quad(pos_mass, leaf=4):
     """Quadrupole records of every node, (num_nodes, 3, 4) float32 =
     (com, M), (Qxx, Qyy, Qzz, Qxy), (Qxz, Qyz, 0, 0), for ORB-ordered records."""
@@ -350,6 +381,7 @@ def tree_quad(pos_mass, leaf=4):
     return out
 
 
+@_on_device
 def tree_moments(pos_mass, leaf=4):
     """Node moments (num_nodes, 5) float64 = (M, com_x, com_y, com_z, diag2)
     and boxes (num_nodes, 6) float32 = (lo, hi)."""
@@ -361,6 +393,7 @@ def tree_moments(pos_mass, leaf=4):
     return mom, box
 
 
+@_on_device
 def tree_lists(pos_mass, theta, leaf=4, max_far=None, max_near=None):
     """Per-group interaction lists: (far_count, near_count) int32 (groups,)
     and, when the maxima are given, far_ids (groups, max_far) and near_ids
@@ -378,6 +411,7 @@ def tree_lists(pos_mass, theta, leaf=4, max_far=None, max_near=None):
     return fc, nc, fi, ni
 
 
+@_on_device
 def tree_leapfrog(pos_mass, vel, acc, eps, theta, dt, nsteps, leaf=4, reorder_every=0, order=None,
                   acc_valid=False, energy=False, G=1.0, prec=None, cells=CELLS_MONOPOLE):
     """Kick-drift-kick steps with tree forces, in place on ORB-ordered
@@ -404,6 +438,7 @@ def tree_leapfrog(pos_mass, vel, acc, eps, theta, dt, nsteps, leaf=4, reorder_ev
     return order, en
 
 
+@_on_device
 def trajectory_forward(pos_mass, vel, eps, dt, nsteps, ckpt_every, G=1.0, prec=None):
     """Runs the leapfrog in place and returns the checkpoint tensor
     (nsteps/ckpt_every + 1, 2, N, 4)."""
@@ -417,6 +452,7 @@ def trajectory_forward(pos_mass, vel, eps, dt, nsteps, ckpt_every, G=1.0, prec=N
     return ck
 
 
+@_on_device
 def trajectory_adjoint(ckpt, eps, dt, nsteps, ckpt_every, xbar_T, vbar_T, G=1.0, prec=None,
                        scheme=ADJ_REVERSE, phibar_T=None):
     """(pos_cot (N,4), vel_cot (N,4), mass_cot (N,)) = gradients at the
@@ -445,6 +481,7 @@ def trajectory_adjoint(ckpt, eps, dt, nsteps, ckpt_every, xbar_T, vbar_T, G=1.0,
     return pc, vc, mc
 
 
+@_on_device
 def janus_forward(pos_mass, vel, eps, dt, nsteps, shift_x=40, shift_v=40, G=1.0):
     """Bit-reversible fixed-point kick-drift-kick from float32 records.
     Returns (state int64 (2N, 4), final positions with masses (N, 4),
@@ -461,6 +498,7 @@ def janus_forward(pos_mass, vel, eps, dt, nsteps, shift_x=40, shift_v=40, G=1.0)
     return state, pm_out, v_out
 
 
+@_on_device
 def janus_adjoint(state, pos_mass, eps, dt, nsteps, xbar_T, vbar_T, shift_x=40, shift_v=40, G=1.0):
     """Gradients (pos_cot, vel_cot (N, 4), mass_cot (N,)) for cotangents of the
     final state, rebuilding the trajectory backwards from ``state`` alone;
