@@ -19,6 +19,7 @@
 // in LDS, and writes the final order.
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -547,7 +548,10 @@ void plan_tree(int n, int leaf, std::vector<Level> &levels, std::vector<int2> &f
 std::mutex g_orb_mu;
 void *g_pinned = nullptr;
 size_t g_pinned_size = 0;
-hipEvent_t g_pinned_ev = nullptr;
+// An event belongs to one device: one per device, and the one recorded
+// after the last upload (on whichever device) guards the shared buffer.
+std::map<int, hipEvent_t> g_pinned_evs;
+hipEvent_t g_pinned_last = nullptr;
 
 }  // namespace
 
@@ -595,7 +599,7 @@ int orb_order(const void *pm, int prec, int n, int leaf, int32_t *perm, hipStrea
         // stage the tables through pinned host memory owned by the library;
         // the previous upload must have completed before the buffer is reused
         std::lock_guard<std::mutex> lk(g_orb_mu);
-        if (g_pinned_ev) (void)hipEventSynchronize(g_pinned_ev);
+        if (g_pinned_last) (void)hipEventSynchronize(g_pinned_last);
         if (g_pinned_size < tab.size()) {
             if (g_pinned) (void)hipHostFree(g_pinned);
             g_pinned = nullptr;
@@ -606,7 +610,14 @@ int orb_order(const void *pm, int prec, int n, int leaf, int32_t *perm, hipStrea
             }
             g_pinned_size = std::max<size_t>(tab.size(), 4096);
         }
-        if (!g_pinned_ev && hipEventCreateWithFlags(&g_pinned_ev, hipEventDisableTiming) != hipSuccess) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) {
+            set_error("hipGetDevice failed");
+            return NBODY_E_HIP;
+        }
+        hipEvent_t &ev = g_pinned_evs[dev];
+        if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            ev = nullptr;
             set_error("cannot create ORB event");
             return NBODY_E_HIP;
         }
@@ -615,8 +626,9 @@ int orb_order(const void *pm, int prec, int n, int leaf, int32_t *perm, hipStrea
             hipError_t e = hipMemcpyAsync(dtab, g_pinned, tab.size(), hipMemcpyHostToDevice, s);
             if (e != hipSuccess) return hip_fail(e, "ORB table upload");
         }
-        hipError_t e = hipEventRecord(g_pinned_ev, s);
+        hipError_t e = hipEventRecord(ev, s);
         if (e != hipSuccess) return hip_fail(e, "ORB event");
+        g_pinned_last = ev;
     }
     const int nb = (n + kOrbBlock - 1) / kOrbBlock;
     if (prec == NBODY_F64)
@@ -651,11 +663,12 @@ int orb_order(const void *pm, int prec, int n, int leaf, int32_t *perm, hipStrea
 void orb_release()
 {
     std::lock_guard<std::mutex> lk(g_orb_mu);
-    if (g_pinned_ev) {
-        (void)hipEventSynchronize(g_pinned_ev);
-        (void)hipEventDestroy(g_pinned_ev);
-        g_pinned_ev = nullptr;
+    for (auto &kv : g_pinned_evs) {
+        (void)hipEventSynchronize(kv.second);
+        (void)hipEventDestroy(kv.second);
     }
+    g_pinned_evs.clear();
+    g_pinned_last = nullptr;
     if (g_pinned) (void)hipHostFree(g_pinned);
     g_pinned = nullptr;
     g_pinned_size = 0;

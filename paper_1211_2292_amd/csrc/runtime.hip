@@ -659,6 +659,19 @@ int nbody_leapfrog_kdk(void *pos_mass, void *vel, void *acc_pot, int64_t n,
     }
     if (!ge) {
         GraphEntry e;
+        // frees what this entry holds unless it is handed to the cache
+        struct Undo {
+            GraphEntry &e;
+            bool keep = false;
+            ~Undo()
+            {
+                if (keep) return;
+                if (e.exec) (void)hipGraphExecDestroy(e.exec);
+                if (e.graph) (void)hipGraphDestroy(e.graph);
+                if (e.partial) (void)hipFree(e.partial);
+                if (e.epart) (void)hipFree(e.epart);
+            }
+        } undo{e};
         Tune t = lookup_tune(0, prec, n);
         const size_t pb = plan ? 0 : accel_partial_bytes(prec, (int)n, t);
         if (pb) NB_TRY(hipMalloc(&e.partial, pb), "graph scratch");
@@ -685,15 +698,13 @@ int nbody_leapfrog_kdk(void *pos_mass, void *vel, void *acc_pot, int64_t n,
                                   en, buf, cs);
         hipGraph_t g = nullptr;
         hipError_t ce = hipStreamEndCapture(cs, &g);
-        if (rc != NBODY_OK) {
-            if (g) (void)hipGraphDestroy(g);
-            return rc;
-        }
+        e.graph = g;
+        if (rc != NBODY_OK) return rc;
         if (ce != hipSuccess) return hip_fail(ce, "end capture");
         NB_TRY(hipGraphInstantiate(&e.exec, g, nullptr, nullptr, 0), "graph instantiate");
-        e.graph = g;
         std::lock_guard<std::mutex> lk(g_mu);
         ge = &g_graphs.emplace(key, e).first->second;
+        undo.keep = true;
     }
     NB_TRY(hipGraphLaunch(ge->exec, s), "graph launch");
     return NBODY_OK;
@@ -1431,7 +1442,10 @@ extern "C" int nbody_autotune(int32_t kernel, int32_t prec, int64_t n, const int
     BatchPlan *plan = nullptr;
     hipEvent_t e0, e1;
     NB_TRY(hipEventCreate(&e0), "event");
-    NB_TRY(hipEventCreate(&e1), "event");
+    if (const hipError_t ee = hipEventCreate(&e1); ee != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(ee, "event");
+    }
     Tune best = cands.front();
     float best_ms = 1e30f;
     const int reps = n >= (1 << 19) ? 1 : 3;
