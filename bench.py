@@ -327,6 +327,17 @@ def adjoint_leg(torch, nb, ics, dev):
             return nb.trajectory_adjoint(ck, eps, dt, steps, C, xb, vb, prec=prec, scheme=scheme)
         return run
 
+    def fwd_adj_energy():
+        # loss = final energy 1/2 sum m |v_T|^2 + 1/2 sum m phi(x_T): the
+        # cotangents are m v_T on the velocities and m / 2 on the final potential
+        p, v = p0.clone(), v0.clone()
+        ck = nb.trajectory_forward(p, v, eps, dt, steps, C, prec=prec)
+        m = p[:, 3]
+        vb = torch.zeros_like(p)
+        vb[:, :3] = m[:, None] * v[:, :3]
+        return nb.trajectory_adjoint(ck, eps, dt, steps, C, torch.zeros_like(p), vb, prec=prec,
+                                     scheme=nb.ADJ_REVERSE, phibar_T=0.5 * m)
+
     def timed(fn, reps=3):
         fn()
         torch.cuda.synchronize()
@@ -363,6 +374,7 @@ def adjoint_leg(torch, nb, ics, dev):
     t_plain64 = timed(plain64)
     t_jf = timed(janus_fwd)
     t_ja = timed(janus_fwd_adj)
+    t_en = timed(fwd_adj_energy)
     log(f"[bench] adjoint: plain {t_plain:.1f} ms, fwd+adj reversal {t_rev:.1f} ms "
         f"(ratio {t_rev / t_plain:.2f}), recompute {t_rec:.1f} ms (ratio {t_rec / t_plain:.2f})")
     log(f"[bench] fixed-point: plain F32_F64ACC {t_plain64:.1f} ms, forward {t_jf:.1f} ms, "
@@ -372,6 +384,8 @@ def adjoint_leg(torch, nb, ics, dev):
             "fwd_plus_adjoint_ms": round(t_rev, 3), "ratio": round(t_rev / t_plain, 3),
             "scheme": "time reversal re-anchored at checkpoints (fused force+VJP)",
             "recompute_scheme_ms": round(t_rec, 3), "recompute_scheme_ratio": round(t_rec / t_plain, 3),
+            "energy_loss": {"loss": "final energy 1/2 sum m v^2 + 1/2 sum m phi (cotangent on the final potential)",
+                            "fwd_plus_adjoint_ms": round(t_en, 3), "ratio": round(t_en / t_plain, 3)},
             "fixed_point": {"prec": "F32_F64ACC", "plain_forward_ms": round(t_plain64, 3),
                             "forward_ms": round(t_jf, 3), "fwd_plus_adjoint_ms": round(t_ja, 3),
                             "ratio": round(t_ja / t_plain64, 3), "checkpoints": 0}}
