@@ -34,8 +34,9 @@
  *   synchronises the device except nbody_autotune(), nbody_release(), a
  *   call that needs more library scratch than any earlier call on the device
  *   (growing a scratch buffer waits for the work that may still use it), a
- *   tree call for a new (n, leaf) (it uploads the node table), and
- *   nbody_janus_adjoint (its mass check).  Calls that share library scratch
+ *   tree call for a new (n, leaf) (it uploads the node table),
+ *   nbody_janus_adjoint (its mass check), and nbody_orb_order when
+ *   NBODY_CHECK_INPUTS is set.  Calls that share library scratch
  *   (the same entry point on one device) must not run concurrently on
  *   different streams.
  * - A caller may capture calls into its own HIP graph after one eager call
@@ -95,7 +96,11 @@ enum {
  *   FP32 first.  The result is a pure function of the input (bit-exact).
  * pos_mass: n records (float4 or double4 by prec).  perm_out: int32[n],
  * perm_out[p] = original index of the body at position p.  Uses library
- * scratch of about 40 bytes per body.
+ * scratch of about 40 bytes per body.  Non-finite coordinates make the order
+ * unspecified; with the environment variable NBODY_CHECK_INPUTS set (to
+ * anything but "0") the call first checks every record, synchronises the
+ * stream, and refuses non-finite coordinates or masses with NBODY_E_INVAL
+ * (the message names the first such record).
  */
 int nbody_orb_order(const void *pos_mass, int32_t prec, int64_t n, int32_t leaf,
                     int32_t *perm_out, void *stream);

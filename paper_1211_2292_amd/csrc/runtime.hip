@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -143,6 +144,55 @@ static bool outputs_overlap(std::initializer_list<Buf> outs, std::initializer_li
         int rc_ = (expr);              \
         if (rc_ != NBODY_OK) return rc_; \
     } while (0)
+
+// ---------------------------------------------------------------------------
+// Optional input check (environment variable NBODY_CHECK_INPUTS, not "0")
+// ---------------------------------------------------------------------------
+namespace {
+// Smallest index of a record with a non-finite coordinate or mass.
+template <typename V>
+__global__ void k_first_nonfinite(const V *__restrict__ pm, int n, int *__restrict__ first)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const V p = pm[i];
+    if (!(isfinite(p.x) && isfinite(p.y) && isfinite(p.z) && isfinite(p.w))) atomicMin(first, i);
+}
+
+__global__ void k_set_int(int *__restrict__ p, int v) { *p = v; }
+}  // namespace
+
+static bool check_inputs_enabled()
+{
+    const char *e = getenv("NBODY_CHECK_INPUTS");
+    return e && *e && std::strcmp(e, "0") != 0;
+}
+
+// One pass over the records and a synchronisation of `s`: NBODY_E_INVAL
+// naming the first non-finite record, if any.
+static int check_finite(const void *pm, int prec, int n, hipStream_t s)
+{
+    int *d = (int *)scratch(kSlotOrb4, 64);
+    if (!d) {
+        set_error("cannot allocate input-check scratch");
+        return NBODY_E_NOMEM;
+    }
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, d, INT_MAX);
+    const int nb = (n + 255) / 256;
+    if (prec == NBODY_F64)
+        hipLaunchKernelGGL(k_first_nonfinite<double4>, dim3(nb), dim3(256), 0, s, (const double4 *)pm, n, d);
+    else
+        hipLaunchKernelGGL(k_first_nonfinite<float4>, dim3(nb), dim3(256), 0, s, (const float4 *)pm, n, d);
+    NB_TRY(hipGetLastError(), "input check");
+    int first = INT_MAX;
+    NB_TRY(hipMemcpyAsync(&first, d, sizeof(int), hipMemcpyDeviceToHost, s), "input check");
+    NB_TRY(hipStreamSynchronize(s), "input check");
+    if (first != INT_MAX) {
+        set_error("record %d has a non-finite coordinate or mass", first);
+        return NBODY_E_INVAL;
+    }
+    return NBODY_OK;
+}
 
 // ---------------------------------------------------------------------------
 // Tuning table
@@ -778,6 +828,7 @@ int nbody_orb_order(const void *pos_mass, int32_t prec, int64_t n, int32_t leaf,
         return NBODY_E_INVAL;
     }
     if (outputs_overlap({{perm_out, 4 * (size_t)n}}, {{pos_mass, rec_bytes(prec) * (size_t)n}})) return NBODY_E_INVAL;
+    if (check_inputs_enabled()) NB_CHECK(check_finite(pos_mass, prec, (int)n, (hipStream_t)stream));
     return orb_order(pos_mass, prec, (int)n, leaf, perm_out, (hipStream_t)stream);
 }
 

@@ -121,3 +121,26 @@ def test_permute_skips_entries_outside_range(inverse, dtype_name):
         else:
             want[p] = s[q]
     assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("dtype_name", ["float32", "float64"])
+def test_orb_input_check(monkeypatch, dtype_name):
+    """With NBODY_CHECK_INPUTS set, non-finite records are refused before any
+    ordering work (naming the first one); clean input orders as before."""
+    torch, nb = gpu()
+    dtype = getattr(torch, dtype_name)
+    pm, _ = ics.plummer(5000, 31)
+    p = to_dev(torch, pm, dtype)
+    ref = nb.orb_order(p, 16)
+    monkeypatch.setenv("NBODY_CHECK_INPUTS", "1")
+    assert torch.equal(nb.orb_order(p, 16), ref)
+    bad = p.clone()
+    bad[3000, 3] = float("inf")
+    bad[777, 1] = float("nan")
+    with pytest.raises(nb.NBodyError, match="record 777 "):
+        nb.orb_order(bad, 16)
+    bad[777, 1] = 0.0
+    with pytest.raises(nb.NBodyError, match="record 3000 "):
+        nb.orb_order(bad, 16)
+    monkeypatch.setenv("NBODY_CHECK_INPUTS", "0")
+    assert torch.equal(nb.orb_order(p, 16), ref)
