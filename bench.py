@@ -683,9 +683,19 @@ def cpu_leg(ics, pm0_host, acc0, eps, seconds, modes=None):
         mp = np.abs(out[tg, 3] - ref_p) / np.abs(ref_p)
         m["error_vs_oracle"] = {"force_rms_rel": float(np.sqrt(np.mean(ma ** 2))), "force_max_rel": float(ma.max()),
                                 "pot_rms_rel": float(np.sqrt(np.mean(mp ** 2))), "targets": int(k)}
+    cpu_model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": round(gint, 5), "unit": "G-interactions/s", "cores": threads, "kind": "oracle",
             "sample": f"{k} sampled targets x {n} sources of the colliding pair, FP64 Neumaier sums",
-            "seconds": round(secs, 2),
+            "seconds": round(secs, 2), "cpu_model": cpu_model,
+            "full_evaluation_s_extrapolated": round(float(n) * n / (gint * 1e9), 1),
             "gpu_error_vs_oracle": {"force_rms_rel": float(np.sqrt(np.mean(da ** 2))),
                                     "force_max_rel": float(da.max()),
                                     "pot_rms_rel": float(np.sqrt(np.mean(dp ** 2)))}}

@@ -124,6 +124,28 @@ def test_deterministic_and_mirror_exact():
         assert np.array_equal(c[:, :3], -a[:, :3]) and np.array_equal(c[:, 3], a[:, 3]), mode
 
 
+@pytest.mark.parametrize("mode", ["F64", "F32", "F32_KAHAN", "F32_F64ACC"])
+def test_power_of_two_scaling_exact(mode):
+    """Mass enters each pair term linearly: doubling every mass doubles a and
+    phi bit for bit.  Doubling positions and eps scales every pair distance by
+    2, so a becomes a / 4 and phi becomes phi / 2, exactly as long as the
+    hardware reciprocal square root commutes with powers of four."""
+    torch, nb = gpu()
+    pm, _ = ics.plummer(3000, 19)
+    dtype = torch.float64 if mode == "F64" else torch.float32
+    src = pm if mode == "F64" else widen32(pm)
+    a = _run(nb, torch, src, 0.01, mode, dtype)
+    heavy = src.copy()
+    heavy[:, 3] *= 2.0
+    b = _run(nb, torch, heavy, 0.01, mode, dtype)
+    assert np.array_equal(b, 2.0 * a)
+    wide = src.copy()
+    wide[:, :3] *= 2.0
+    c = _run(nb, torch, wide, 0.02, mode, dtype)
+    assert np.array_equal(c[:, :3], a[:, :3] / 4.0)
+    assert np.array_equal(c[:, 3], a[:, 3] / 2.0)
+
+
 def test_closed_forms_on_gpu():
     """Cube vertices (eps = 0): a = -(1/4 + 1/(4 sqrt2) + 1/(12 sqrt3)) G m x."""
     torch, nb = gpu()
