@@ -683,6 +683,11 @@ def cpu_leg(ics, pm0_host, acc0, eps, seconds, modes=None):
         mp = np.abs(out[tg, 3] - ref_p) / np.abs(ref_p)
         m["error_vs_oracle"] = {"force_rms_rel": float(np.sqrt(np.mean(ma ** 2))), "force_max_rel": float(ma.max()),
                                 "pot_rms_rel": float(np.sqrt(np.mean(mp ** 2))), "targets": int(k)}
+    # one full evaluation of the Plummer sphere of 65536 bodies (4.29e9 pairs)
+    pm65, _ = ics.plummer(65536, 1001)
+    t65 = time.perf_counter()
+    oracle.accel(pm65.astype(np.float32).astype(np.float64), 0.01)
+    t65 = time.perf_counter() - t65
     cpu_model = "unknown"
     try:
         with open("/proc/cpuinfo") as fh:
@@ -696,6 +701,8 @@ def cpu_leg(ics, pm0_host, acc0, eps, seconds, modes=None):
             "sample": f"{k} sampled targets x {n} sources of the colliding pair, FP64 Neumaier sums",
             "seconds": round(secs, 2), "cpu_model": cpu_model,
             "full_evaluation_s_extrapolated": round(float(n) * n / (gint * 1e9), 1),
+            "plummer65536_full_evaluation": {"seconds": round(t65, 2),
+                                             "g_interactions_per_s": round(65536.0 ** 2 / t65 / 1e9, 4)},
             "gpu_error_vs_oracle": {"force_rms_rel": float(np.sqrt(np.mean(da ** 2))),
                                     "force_max_rel": float(da.max()),
                                     "pot_rms_rel": float(np.sqrt(np.mean(dp ** 2)))}}
