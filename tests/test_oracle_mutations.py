@@ -15,7 +15,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "nbody_oracle.c")
 
-# (name, pin files, exact text, replacement); the text must occur once
+# (name, pin files, exact text, replacement[, anchor]); the text must occur
+# once, or, with an anchor, the first occurrence after the anchor is replaced
 MUTANTS = [
     ("force: power 2 instead of 3/2", ["tests/test_oracle_force.py"],
      "const double w = 1.0 / (r2 * r); /* (r^2 + eps^2)^(-3/2) */",
@@ -72,15 +73,41 @@ MUTANTS = [
     ("fixed point: full kicks", ["tests/test_oracle_janus.py"],
      "const double kick_scale = 0.5 * dt * G * ldexp(1.0, sv);",
      "const double kick_scale = dt * G * ldexp(1.0, sv);"),
+    ("fixed point: half drifts", ["tests/test_oracle_janus.py"],
+     "const double drift_scale = dt * ldexp(1.0, sx - sv);",
+     "const double drift_scale = dt * ldexp(1.0, sx - sv - 1);"),
+    ("ORB: keys without the index tie-break", ["tests/test_oracle_orb.py"],
+     "(uint32_t)s[p];", "(uint32_t)0;"),
+    ("local expansion: group size left out of its test", ["tests/test_oracle_local.py"],
+     "if (t->diag2[c] + t->diag2[g] < t->theta2 * dz2) {", "if (t->diag2[c] < t->theta2 * dz2) {"),
+    ("trajectory gradient: drift adjoint with h", ["tests/test_oracle_vjp.py"],
+     "            gv[k] += dt * gx[k];", "            gv[k] += h * gx[k];", "double oracle_traj_grad("),
+    ("trajectory cotangents: drift adjoint with h", ["tests/test_oracle_vjp.py"],
+     "            gv[k] += dt * gx[k];", "            gv[k] += h * gx[k];", "int oracle_traj_grad_cot("),
+    ("trajectory cotangents: VJP at x_0 dropped", ["tests/test_oracle_vjp.py"],
+     "    oracle_vjp(n, xs, m, G, eps, carry, NULL, tx, tm);\n    for (size_t k = 0; k < n3; ++k)\n"
+     "        gx[k] += tx[k];",
+     "    oracle_vjp(n, xs, m, G, eps, carry, NULL, tx, tm);\n    for (size_t k = 0; k < n3; ++k)\n"
+     "        gx[k] += 0.0 * tx[k];", "int oracle_traj_grad_cot("),
+    ("trajectory cotangents: potential's mass term dropped", ["tests/test_oracle_vjp.py"],
+     "            gm[k] += tm[k];\n    }\n    double *carry = a;",
+     "            gm[k] += 0.0 * tm[k];\n    }\n    double *carry = a;"),
 ]
 
 
-@pytest.mark.parametrize("name,pins,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
-def test_planted_mistake_is_caught(tmp_path, name, pins, old, new):
+@pytest.mark.parametrize("spec", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_planted_mistake_is_caught(tmp_path, spec):
+    name, pins, old, new = spec[:4]
     src = open(SRC).read()
-    assert src.count(old) == 1, f"the text of mutant '{name}' must occur once in the oracle"
+    if len(spec) > 4:
+        assert src.count(spec[4]) == 1, f"the anchor of mutant '{name}' must occur once in the oracle"
+        at = src.index(old, src.index(spec[4]))
+        changed = src[:at] + new + src[at + len(old):]
+    else:
+        assert src.count(old) == 1, f"the text of mutant '{name}' must occur once in the oracle"
+        changed = src.replace(old, new)
     mutant = tmp_path / "mutant.c"
-    mutant.write_text(src.replace(old, new))
+    mutant.write_text(changed)
     lib = tmp_path / "libmutant.so"
     subprocess.run(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
                     "-o", str(lib), str(mutant), "-lm"], check=True, capture_output=True)
