@@ -109,6 +109,14 @@ def _load():
         lib.oracle_tree_pseudo.restype = ctypes.c_int
         lib.oracle_pseudo_dirs.argtypes = [_d]
         lib.oracle_pseudo_dirs.restype = None
+        lib.oracle_fmm_lists.argtypes = [ctypes.c_int64, ctypes.c_int32, _d, _d, ctypes.c_double, _i64, _i64,
+                                         _i32, ctypes.c_int64, _i32, ctypes.c_int64]
+        lib.oracle_fmm_lists.restype = ctypes.c_int
+        lib.oracle_fmm_accel.argtypes = [ctypes.c_int64, ctypes.c_int32, _d, _d, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_int64, _i64, _d, _d]
+        lib.oracle_fmm_accel.restype = ctypes.c_int
+        lib.oracle_local_shift.argtypes = [_d, _d, _d]
+        lib.oracle_local_shift.restype = None
         lib.oracle_num_threads.argtypes = []
         lib.oracle_num_threads.restype = ctypes.c_int
         _lib = lib
@@ -438,4 +446,61 @@ def tree_local_lists(pos_mass_orb, leaf: int, group: int, theta: float):
         raise ValueError("oracle_tree_local_lists failed")
     for k in ("loc", "far", "near"):
         out[k] = lists[k][:int(out[k + "_cnt"].sum())]
+    return out
+
+
+def fmm_lists(pos_mass_orb, leaf: int, theta: float):
+    """Interaction lists of the multi-level FMM's dual-tree traversal on the
+    ORB nodes (Section VI's O(N) method): dict(m2l_cnt, p2p_cnt (nn,) per
+    target node, m2l, p2p (source node ids, targets in node order, each
+    target's sources in traversal order))."""
+    lib = _load()
+    x, m = _split(pos_mass_orb)
+    n = x.shape[0]
+    nn = tree_nodes(n, leaf).shape[0]
+    mc = np.empty(nn, dtype=np.int64)
+    pc = np.empty(nn, dtype=np.int64)
+    if lib.oracle_fmm_lists(n, int(leaf), _ptr(x, _d), _ptr(m, _d), float(theta), _ptr(mc, _i64), _ptr(pc, _i64),
+                            None, 0, None, 0) != 0:
+        raise ValueError("oracle_fmm_lists: bad arguments")
+    m2l = np.empty(max(int(mc.sum()), 1), dtype=np.int32)
+    p2p = np.empty(max(int(pc.sum()), 1), dtype=np.int32)
+    if lib.oracle_fmm_lists(n, int(leaf), _ptr(x, _d), _ptr(m, _d), float(theta), _ptr(mc, _i64), _ptr(pc, _i64),
+                            _ptr(m2l, _i32), m2l.shape[0], _ptr(p2p, _i32), p2p.shape[0]) != 0:
+        raise ValueError("oracle_fmm_lists failed")
+    return dict(m2l_cnt=mc, p2p_cnt=pc, m2l=m2l[:int(mc.sum())], p2p=p2p[:int(pc.sum())])
+
+
+def fmm_accel(pos_mass_orb, leaf: int, theta: float, eps: float, G: float = 1.0, targets=None):
+    """Force and potential by the multi-level FMM on the ORB nodes
+    (quadrupole cells, third-order local expansions, L2L down the tree, P2P
+    between leaves).  Returns (acc (T, 3), pot (T,)) for ORB positions
+    ``targets`` (all when None)."""
+    lib = _load()
+    x, m = _split(pos_mass_orb)
+    n = x.shape[0]
+    if targets is None:
+        nt, tp = n, None
+    else:
+        tp = np.ascontiguousarray(np.asarray(targets, dtype=np.int64))
+        if tp.size and (tp.min() < 0 or tp.max() >= n):
+            raise IndexError("target index out of range")
+        nt = tp.shape[0]
+    acc = np.empty((nt, 3))
+    pot = np.empty(nt)
+    rc = lib.oracle_fmm_accel(n, int(leaf), _ptr(x, _d), _ptr(m, _d), float(G), float(eps), float(theta), nt,
+                              None if tp is None else _ptr(tp, _i64), _ptr(acc, _d), _ptr(pot, _d))
+    if rc != 0:
+        raise ValueError("oracle_fmm_accel failed")
+    return acc, pot
+
+
+def local_shift(coeffs, dz) -> np.ndarray:
+    """Re-expansion (L2L) of a cubic local expansion (20 coefficients: P0,
+    p (3), K (xx, yy, zz, xy, xz, yz), T (xxx, yyy, zzz, xxy, xxz, xyy, yyz,
+    xzz, yzz, xyz)) about its centre + dz."""
+    c = np.ascontiguousarray(np.asarray(coeffs, dtype=np.float64))
+    d = np.ascontiguousarray(np.asarray(dz, dtype=np.float64))
+    out = np.empty(20)
+    _load().oracle_local_shift(_ptr(c, _d), _ptr(d, _d), _ptr(out, _d))
     return out

@@ -52,8 +52,9 @@
  *                    above those functions.
  *   oracle_tree_pseudo, oracle_tree_quad, oracle_tree_accel_cells
  *                    Higher-order cells, after the pseudo-particle multipole
- *                    method of Makino (1999), the paper's reference [20],
- *                    which Section VI names as the way past monopole cells:
+ *                    method of Makino (J. Comput. Phys. 151, 1999), the
+ *                    paper's reference [20], which Section VI cites for
+ *                    the O(N) fast multipole method:
  *                    each cell's expansion to quadrupole order is carried
  *                    either by 12 point masses from that method's formula,
  *                    or by the cell's traceless quadrupole tensor with the
@@ -893,7 +894,8 @@ int oracle_tree_lists(int64_t n, int32_t leaf, int32_t group, const double *x, c
 }
 
 /* ---------------------------------------------------------------------------
- * Pseudo-particle multipoles (Makino 1999, the paper's reference [20]).
+ * Pseudo-particle multipoles (Makino, J. Comput. Phys. 151, 1999: the
+ * paper's reference [20], cited in Section VI for the O(N) FMM).
  *
  * Outside a cell the potential of its bodies is the multipole series
  *   phi(R) = -G sum_i m_i sum_l |r_i|^l / |R|^(l+1) P_l(cos angle(r_i, R)),
@@ -1043,6 +1045,96 @@ int oracle_tree_quad(int64_t n, int32_t leaf, const double *x, const double *m, 
     return 0;
 }
 
+/* Third-order local expansion of the potential sum of one quadrupole cell
+ * (mass M, centre of mass cm, traceless Q as (xx, yy, zz, xy, xz, yz))
+ * about the point zg, formulas above; the 20 coefficients
+ *   L[0] = P0, L[1..3] = p, L[4..9] = K (xx, yy, zz, xy, xz, yz),
+ *   L[10..19] = T (xxx, yyy, zzz, xxy, xxz, xyy, yyz, xzz, yzz, xyz)
+ * are added to the running sums L. */
+static const int local_tt[10][3] = {{0, 0, 0}, {1, 1, 1}, {2, 2, 2}, {0, 0, 1}, {0, 0, 2},
+                                    {0, 1, 1}, {1, 1, 2}, {0, 2, 2}, {1, 2, 2}, {0, 1, 2}};
+
+static void local_m2l_add(nsum *L, const double *zg, const double *cm, double M, const double *Qv, double eps2)
+{
+    const double Q[3][3] = {{Qv[0], Qv[3], Qv[4]}, {Qv[3], Qv[1], Qv[5]}, {Qv[4], Qv[5], Qv[2]}};
+    const double r[3] = {zg[0] - cm[0], zg[1] - cm[1], zg[2] - cm[2]};
+    const double s2 = ((r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]) + eps2;
+    const double s1 = 1.0 / sqrt(s2);
+    const double s3 = s1 / s2, s5 = s3 / s2, s7 = s5 / s2, s9 = s7 / s2, s11 = s9 / s2;
+    double qr[3];
+    for (int k = 0; k < 3; ++k)
+        qr[k] = (Q[k][0] * r[0] + Q[k][1] * r[1]) + Q[k][2] * r[2];
+    const double rqr = (r[0] * qr[0] + r[1] * qr[1]) + r[2] * qr[2];
+    nsum_add(&L[0], M * s1 + 0.5 * rqr * s5);
+    for (int k = 0; k < 3; ++k)
+        nsum_add(&L[1 + k], -M * r[k] * s3 - 2.5 * rqr * r[k] * s7 + qr[k] * s5);
+    /* K in the order xx, yy, zz, xy, xz, yz */
+    static const int kk[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
+    for (int u = 0; u < 6; ++u) {
+        const int k = kk[u][0], l = kk[u][1];
+        const double dkl = k == l ? 1.0 : 0.0;
+        const double v = M * (3.0 * r[k] * r[l] * s5 - dkl * s3) + 17.5 * rqr * r[k] * r[l] * s9 -
+                         2.5 * (2.0 * qr[k] * r[l] + 2.0 * qr[l] * r[k] + dkl * rqr) * s7 +
+                         Q[k][l] * s5;
+        nsum_add(&L[4 + u], v);
+    }
+    /* T in the order of local_tt */
+    for (int u = 0; u < 10; ++u) {
+        const int k = local_tt[u][0], l = local_tt[u][1], m2 = local_tt[u][2];
+        const double dkl = k == l ? 1.0 : 0.0, dkm = k == m2 ? 1.0 : 0.0, dlm = l == m2 ? 1.0 : 0.0;
+        const double rrr = r[k] * r[l] * r[m2];
+        const double dr = dkl * r[m2] + dkm * r[l] + dlm * r[k];
+        const double v = M * (-15.0 * rrr * s7 + 3.0 * dr * s5) - 157.5 * rqr * rrr * s11 +
+                         35.0 * (qr[k] * r[l] * r[m2] + qr[l] * r[k] * r[m2] + qr[m2] * r[k] * r[l]) * s9 +
+                         17.5 * rqr * dr * s9 -
+                         5.0 * (Q[k][l] * r[m2] + Q[k][m2] * r[l] + Q[l][m2] * r[k] + qr[k] * dlm +
+                                qr[l] * dkm + qr[m2] * dkl) * s7;
+        nsum_add(&L[10 + u], v);
+    }
+}
+
+/* The full symmetric K (3x3) and T (3x3x3) of the 20 stored coefficients. */
+static void local_tensors(const double *c, double K[3][3], double T3[3][3][3])
+{
+    K[0][0] = c[4];
+    K[1][1] = c[5];
+    K[2][2] = c[6];
+    K[0][1] = K[1][0] = c[7];
+    K[0][2] = K[2][0] = c[8];
+    K[1][2] = K[2][1] = c[9];
+    static const int pm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    for (int u = 0; u < 10; ++u) {
+        const int *a3 = local_tt[u];
+        for (int w = 0; w < 6; ++w)
+            T3[a3[pm[w][0]]][a3[pm[w][1]]][a3[pm[w][2]]] = c[10 + u];
+    }
+}
+
+/* L2P: the expansion c at offset y from its centre.  Adds the gradient
+ * p + K y + T(y, y) / 2 to (ax, ay, az) and the value P0 + p.y + y.K.y / 2 +
+ * T(y, y, y) / 6 to ph (acceleration = G times the former, potential = -G
+ * times the latter). */
+static void local_l2p_add(const double *c, const double *y, nsum *ax, nsum *ay, nsum *az, nsum *ph)
+{
+    double K[3][3], T3[3][3][3];
+    local_tensors(c, K, T3);
+    double ky[3], tyy[3];
+    for (int k = 0; k < 3; ++k) {
+        ky[k] = (K[k][0] * y[0] + K[k][1] * y[1]) + K[k][2] * y[2];
+        tyy[k] = 0.0;
+        for (int l = 0; l < 3; ++l)
+            for (int m2 = 0; m2 < 3; ++m2)
+                tyy[k] += T3[k][l][m2] * y[l] * y[m2];
+    }
+    nsum_add(ax, c[1] + ky[0] + 0.5 * tyy[0]);
+    nsum_add(ay, c[2] + ky[1] + 0.5 * tyy[1]);
+    nsum_add(az, c[3] + ky[2] + 0.5 * tyy[2]);
+    const double py = (c[1] * y[0] + c[2] * y[1]) + c[3] * y[2];
+    const double yky = (y[0] * ky[0] + y[1] * ky[1]) + y[2] * ky[2];
+    const double ytyy = (y[0] * tyy[0] + y[1] * tyy[1]) + y[2] * tyy[2];
+    nsum_add(ph, c[0] + py + 0.5 * yky + ytyy / 6.0);
+}
+
 /* Tree force and potential on targets (ORB positions; NULL = all n).
  * acc: [ntarg][3], pot: [ntarg].  cells 0: an accepted cell acts as one body
  * (M at com); 2: as its 12 pseudo-particles; 3: through its quadrupole
@@ -1119,76 +1211,13 @@ int oracle_tree_accel_cells(int64_t n, int32_t leaf, int32_t group, const double
                 L[k] = (nsum){0, 0};
             for (int64_t q = 0; q < nl; ++q) {
                 const int64_t c = loc[q];
-                const double *cm = d.com + 3 * c, *Qv = pp + 6 * c;
-                const double M = d.mass[c];
-                const double Q[3][3] = {{Qv[0], Qv[3], Qv[4]}, {Qv[3], Qv[1], Qv[5]}, {Qv[4], Qv[5], Qv[2]}};
-                const double r[3] = {zg[0] - cm[0], zg[1] - cm[1], zg[2] - cm[2]};
-                const double s2 = ((r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]) + eps2;
-                const double s1 = 1.0 / sqrt(s2);
-                const double s3 = s1 / s2, s5 = s3 / s2, s7 = s5 / s2, s9 = s7 / s2, s11 = s9 / s2;
-                double qr[3];
-                for (int k = 0; k < 3; ++k)
-                    qr[k] = (Q[k][0] * r[0] + Q[k][1] * r[1]) + Q[k][2] * r[2];
-                const double rqr = (r[0] * qr[0] + r[1] * qr[1]) + r[2] * qr[2];
-                nsum_add(&L[0], M * s1 + 0.5 * rqr * s5);
-                for (int k = 0; k < 3; ++k)
-                    nsum_add(&L[1 + k], -M * r[k] * s3 - 2.5 * rqr * r[k] * s7 + qr[k] * s5);
-                /* K in the order xx, yy, zz, xy, xz, yz */
-                static const int kk[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
-                for (int u = 0; u < 6; ++u) {
-                    const int k = kk[u][0], l = kk[u][1];
-                    const double dkl = k == l ? 1.0 : 0.0;
-                    const double v = M * (3.0 * r[k] * r[l] * s5 - dkl * s3) + 17.5 * rqr * r[k] * r[l] * s9 -
-                                     2.5 * (2.0 * qr[k] * r[l] + 2.0 * qr[l] * r[k] + dkl * rqr) * s7 +
-                                     Q[k][l] * s5;
-                    nsum_add(&L[4 + u], v);
-                }
-                /* T in the order xxx, yyy, zzz, xxy, xxz, xyy, yyz, xzz, yzz, xyz */
-                static const int tt[10][3] = {{0, 0, 0}, {1, 1, 1}, {2, 2, 2}, {0, 0, 1}, {0, 0, 2},
-                                              {0, 1, 1}, {1, 1, 2}, {0, 2, 2}, {1, 2, 2}, {0, 1, 2}};
-                for (int u = 0; u < 10; ++u) {
-                    const int k = tt[u][0], l = tt[u][1], m2 = tt[u][2];
-                    const double dkl = k == l ? 1.0 : 0.0, dkm = k == m2 ? 1.0 : 0.0, dlm = l == m2 ? 1.0 : 0.0;
-                    const double rrr = r[k] * r[l] * r[m2];
-                    const double dr = dkl * r[m2] + dkm * r[l] + dlm * r[k];
-                    const double v = M * (-15.0 * rrr * s7 + 3.0 * dr * s5) - 157.5 * rqr * rrr * s11 +
-                                     35.0 * (qr[k] * r[l] * r[m2] + qr[l] * r[k] * r[m2] + qr[m2] * r[k] * r[l]) * s9 +
-                                     17.5 * rqr * dr * s9 -
-                                     5.0 * (Q[k][l] * r[m2] + Q[k][m2] * r[l] + Q[l][m2] * r[k] + qr[k] * dlm +
-                                            qr[l] * dkm + qr[m2] * dkl) * s7;
-                    nsum_add(&L[10 + u], v);
-                }
+                local_m2l_add(L, zg, d.com + 3 * c, d.mass[c], pp + 6 * c, eps2);
             }
             double c[20];
             for (int k = 0; k < 20; ++k)
                 c[k] = nsum_val(&L[k]);
-            /* full symmetric tensors from the stored components */
-            const double K[3][3] = {{c[4], c[7], c[8]}, {c[7], c[5], c[9]}, {c[8], c[9], c[6]}};
-            double T3[3][3][3];
-            static const int tt[10][3] = {{0, 0, 0}, {1, 1, 1}, {2, 2, 2}, {0, 0, 1}, {0, 0, 2},
-                                          {0, 1, 1}, {1, 1, 2}, {0, 2, 2}, {1, 2, 2}, {0, 1, 2}};
-            for (int u = 0; u < 10; ++u) {
-                const int a3[3] = {tt[u][0], tt[u][1], tt[u][2]};
-                static const int pm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
-                for (int w = 0; w < 6; ++w)
-                    T3[a3[pm[w][0]]][a3[pm[w][1]]][a3[pm[w][2]]] = c[10 + u];
-            }
             const double y[3] = {xi - zg[0], yi - zg[1], zi - zg[2]};
-            double ky[3], tyy[3];
-            for (int k = 0; k < 3; ++k) {
-                ky[k] = (K[k][0] * y[0] + K[k][1] * y[1]) + K[k][2] * y[2];
-                tyy[k] = 0.0;
-                for (int l = 0; l < 3; ++l)
-                    for (int m2 = 0; m2 < 3; ++m2)
-                        tyy[k] += T3[k][l][m2] * y[l] * y[m2];
-            }
-            nsum_add(&ax, c[1] + ky[0] + 0.5 * tyy[0]);
-            nsum_add(&ay, c[2] + ky[1] + 0.5 * tyy[1]);
-            nsum_add(&az, c[3] + ky[2] + 0.5 * tyy[2]);
-            const double py = (c[1] * y[0] + c[2] * y[1]) + c[3] * y[2];
-            const double yky = (y[0] * ky[0] + y[1] * ky[1]) + y[2] * ky[2];
-            const double ytyy = (y[0] * tyy[0] + y[1] * tyy[1]) + y[2] * tyy[2];
-            nsum_add(&ph, c[0] + py + 0.5 * yky + ytyy / 6.0);
+            local_l2p_add(c, y, &ax, &ay, &az, &ph);
         }
         for (int64_t q = 0; q < nf + nnr; ++q) {
             const int64_t c = q < nf ? far[q] : near[q - nf];
@@ -1331,6 +1360,325 @@ int oracle_tree_accel(int64_t n, int32_t leaf, int32_t group, const double *x, c
                       double *pot)
 {
     return oracle_tree_accel_cells(n, leaf, group, x, m, G, eps, theta, 0, ntarg, targets, acc, pot);
+}
+
+/* ---------------------------------------------------------------------------
+ * Multi-level fast multipole method on the ORB hierarchy: the O(N) method
+ * Section VI names (citing its reference [20]) as the way beyond the tree
+ * code, built from the quadrupole cells and third-order local expansions
+ * above.  Readings of this library (the paper gives no formulas):
+ *   cells     every node carries its quadrupole expansion about its centre
+ *             of mass (oracle_tree_quad); every node's local expansion is
+ *             about the same centre, z_A = com_A.
+ *   MAC       nodes A (targets) and B (sources) interact through M2L iff
+ *             they share no body and diag2_A + diag2_B < theta^2
+ *             |com_A - com_B|^2 (the group local test, now between any two
+ *             nodes).
+ *   traversal interact(A, B) from (root, root):
+ *               MAC(A, B)          -> B joins the M2L list of A
+ *               A, B both leaves   -> B joins the P2P list of A
+ *               B a leaf, or A not a leaf with diag2_A >= diag2_B
+ *                                  -> interact(A.left, B), interact(A.right, B)
+ *               else               -> interact(A, B.left), interact(A, B.right)
+ *             Every ordered pair of distinct bodies (i, j) is then counted
+ *             once: through the M2L entry of an ancestor-or-self of i's
+ *             leaf whose source contains j, or through the P2P entry of
+ *             i's leaf whose source leaf contains j.
+ *   M2L       local_m2l_add, summed over a node's list in traversal order.
+ *   L2L       a node's total expansion = its own M2L sum + its parent's
+ *             total re-expanded about its centre (local_shift: a cubic
+ *             re-expanded exactly), coefficient by coefficient.
+ *   L2P, P2P  per body of a leaf: the leaf's total expansion at the body
+ *             (local_l2p_add), then the P2P source leaves in list order body
+ *             by body, skipping the body itself; Neumaier sums.
+ * theta = 0 gives no M2L entry, so the result is the direct sum.
+ * ------------------------------------------------------------------------- */
+
+/* Re-expands the cubic c about its centre z as a cubic about z + dz (exact
+ * up to rounding): with f(y) = P0 + p.y + y.K.y/2 + T(y,y,y)/6,
+ *   P0' = P0 + p.dz + dz.K.dz/2 + T(dz,dz,dz)/6,  p' = p + K dz + T(dz,dz)/2,
+ *   K'  = K + T dz,  T' = T. */
+void oracle_local_shift(const double *c, const double *dz, double *out)
+{
+    double K[3][3], T3[3][3][3];
+    local_tensors(c, K, T3);
+    double kd[3], td[3][3], tdd[3];
+    for (int k = 0; k < 3; ++k) {
+        kd[k] = (K[k][0] * dz[0] + K[k][1] * dz[1]) + K[k][2] * dz[2];
+        for (int l = 0; l < 3; ++l)
+            td[k][l] = (T3[k][l][0] * dz[0] + T3[k][l][1] * dz[1]) + T3[k][l][2] * dz[2];
+        tdd[k] = (td[k][0] * dz[0] + td[k][1] * dz[1]) + td[k][2] * dz[2];
+    }
+    const double pd = (c[1] * dz[0] + c[2] * dz[1]) + c[3] * dz[2];
+    const double dkd = (dz[0] * kd[0] + dz[1] * kd[1]) + dz[2] * kd[2];
+    const double dtdd = (dz[0] * tdd[0] + dz[1] * tdd[1]) + dz[2] * tdd[2];
+    out[0] = c[0] + pd + 0.5 * dkd + dtdd / 6.0;
+    for (int k = 0; k < 3; ++k)
+        out[1 + k] = c[1 + k] + kd[k] + 0.5 * tdd[k];
+    out[4] = c[4] + td[0][0];
+    out[5] = c[5] + td[1][1];
+    out[6] = c[6] + td[2][2];
+    out[7] = c[7] + td[0][1];
+    out[8] = c[8] + td[0][2];
+    out[9] = c[9] + td[1][2];
+    for (int u = 10; u < 20; ++u)
+        out[u] = c[u];
+}
+
+typedef struct {
+    int32_t *a, *b;
+    int64_t n, cap;
+    int fail;
+} fmm_pairs;
+
+static void fmm_push(fmm_pairs *l, int64_t a, int64_t b)
+{
+    if (l->fail)
+        return;
+    if (l->n == l->cap) {
+        const int64_t cap = l->cap ? 2 * l->cap : 1024;
+        int32_t *na = (int32_t *)realloc(l->a, (size_t)cap * sizeof(int32_t));
+        if (na)
+            l->a = na;
+        int32_t *nb = (int32_t *)realloc(l->b, (size_t)cap * sizeof(int32_t));
+        if (nb)
+            l->b = nb;
+        if (!na || !nb) {
+            l->fail = 1;
+            return;
+        }
+        l->cap = cap;
+    }
+    l->a[l->n] = (int32_t)a;
+    l->b[l->n] = (int32_t)b;
+    ++l->n;
+}
+
+typedef struct {
+    const tree_data *d;
+    double theta2;
+    fmm_pairs m2l, p2p;
+} fmm_ctx;
+
+static int fmm_mac(const fmm_ctx *f, int64_t a, int64_t b)
+{
+    const tree_data *d = f->d;
+    if (tree_overlap(d->nodes, a, b))
+        return 0;
+    const double dx = d->com[3 * a] - d->com[3 * b];
+    const double dy = d->com[3 * a + 1] - d->com[3 * b + 1];
+    const double dz = d->com[3 * a + 2] - d->com[3 * b + 2];
+    const double dist2 = (dx * dx + dy * dy) + dz * dz;
+    return d->diag2[a] + d->diag2[b] < f->theta2 * dist2;
+}
+
+static void fmm_interact(fmm_ctx *f, int64_t a, int64_t b)
+{
+    if (fmm_mac(f, a, b)) {
+        fmm_push(&f->m2l, a, b);
+        return;
+    }
+    const int64_t *nodes = f->d->nodes;
+    const int64_t al = nodes[4 * a + 2], ar = nodes[4 * a + 3];
+    const int64_t bl = nodes[4 * b + 2], br = nodes[4 * b + 3];
+    if (al < 0 && bl < 0) {
+        fmm_push(&f->p2p, a, b);
+        return;
+    }
+    if (bl < 0 || (al >= 0 && f->d->diag2[a] >= f->d->diag2[b])) {
+        fmm_interact(f, al, b);
+        fmm_interact(f, ar, b);
+    } else {
+        fmm_interact(f, a, bl);
+        fmm_interact(f, a, br);
+    }
+}
+
+/* Stable grouping of a pair list by target node: cnt[nn] per target,
+ * start[nn] offsets, src[] the sources in traversal order per target. */
+static int fmm_by_target(const fmm_pairs *l, int64_t nn, int64_t *cnt, int64_t *start, int32_t *src)
+{
+    for (int64_t k = 0; k < nn; ++k)
+        cnt[k] = 0;
+    for (int64_t q = 0; q < l->n; ++q)
+        ++cnt[l->a[q]];
+    int64_t o = 0;
+    for (int64_t k = 0; k < nn; ++k) {
+        start[k] = o;
+        o += cnt[k];
+    }
+    int64_t *fill = (int64_t *)malloc((size_t)nn * sizeof(int64_t));
+    if (!fill)
+        return -1;
+    memcpy(fill, start, (size_t)nn * sizeof(int64_t));
+    for (int64_t q = 0; q < l->n; ++q)
+        src[fill[l->a[q]]++] = l->b[q];
+    free(fill);
+    return 0;
+}
+
+static int fmm_run(int64_t n, int32_t leaf, const double *x, const double *m, double theta, tree_data *d,
+                   fmm_ctx *f)
+{
+    memset(f, 0, sizeof *f);
+    if (!(theta >= 0.0) || tree_setup(n, leaf, leaf, x, m, d) != 0)
+        return -1;
+    f->d = d;
+    f->theta2 = theta * theta;
+    fmm_interact(f, 0, 0);
+    if (f->m2l.fail || f->p2p.fail) {
+        tree_free(d);
+        return -1;
+    }
+    return 0;
+}
+
+static void fmm_ctx_free(fmm_ctx *f)
+{
+    free(f->m2l.a);
+    free(f->m2l.b);
+    free(f->p2p.a);
+    free(f->p2p.b);
+}
+
+/* The FMM's lists grouped by target node (node ids in preorder):
+ * m2l_cnt/p2p_cnt [nn]; m2l/p2p the source node ids of every target in
+ * traversal order, targets in node order (NULL to count only; capacities
+ * m2l_cap/p2p_cap).  Returns 0, or -1 on bad arguments or a list longer than
+ * its capacity. */
+int oracle_fmm_lists(int64_t n, int32_t leaf, const double *x, const double *m, double theta, int64_t *m2l_cnt,
+                     int64_t *p2p_cnt, int32_t *m2l, int64_t m2l_cap, int32_t *p2p, int64_t p2p_cap)
+{
+    tree_data d;
+    fmm_ctx f;
+    if (!m2l_cnt || !p2p_cnt || fmm_run(n, leaf, x, m, theta, &d, &f) != 0)
+        return -1;
+    int rc = 0;
+    int64_t *start = (int64_t *)malloc((size_t)d.nn * sizeof(int64_t));
+    int32_t *tmp = (int32_t *)malloc((size_t)(f.m2l.n + f.p2p.n + 1) * sizeof(int32_t));
+    if (!start || !tmp)
+        rc = -1;
+    if (rc == 0) {
+        rc |= fmm_by_target(&f.m2l, d.nn, m2l_cnt, start, tmp);
+        if (rc == 0 && m2l) {
+            if (f.m2l.n > m2l_cap)
+                rc = -1;
+            else
+                memcpy(m2l, tmp, (size_t)f.m2l.n * sizeof(int32_t));
+        }
+    }
+    if (rc == 0) {
+        rc |= fmm_by_target(&f.p2p, d.nn, p2p_cnt, start, tmp);
+        if (rc == 0 && p2p) {
+            if (f.p2p.n > p2p_cap)
+                rc = -1;
+            else
+                memcpy(p2p, tmp, (size_t)f.p2p.n * sizeof(int32_t));
+        }
+    }
+    free(start);
+    free(tmp);
+    fmm_ctx_free(&f);
+    tree_free(&d);
+    return rc;
+}
+
+/* FMM force and potential on targets (ORB positions; NULL = all n).
+ * acc: [ntarg][3], pot: [ntarg].  Returns 0, or -1 on bad arguments. */
+int oracle_fmm_accel(int64_t n, int32_t leaf, const double *x, const double *m, double G, double eps,
+                     double theta, int64_t ntarg, const int64_t *targets, double *acc, double *pot)
+{
+    tree_data d;
+    fmm_ctx f;
+    if (fmm_run(n, leaf, x, m, theta, &d, &f) != 0)
+        return -1;
+    const int64_t nn = d.nn;
+    const double eps2 = eps * eps;
+    double *Q = (double *)malloc((size_t)nn * 6 * sizeof(double));
+    nsum *own = (nsum *)calloc((size_t)nn * 20, sizeof(nsum));
+    double *tot = (double *)malloc((size_t)nn * 20 * sizeof(double));
+    int64_t *pcnt = (int64_t *)malloc((size_t)nn * sizeof(int64_t));
+    int64_t *pstart = (int64_t *)malloc((size_t)nn * sizeof(int64_t));
+    int32_t *psrc = (int32_t *)malloc((size_t)(f.p2p.n + 1) * sizeof(int32_t));
+    int64_t *leaf_of = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    int rc = (Q && own && tot && pcnt && pstart && psrc && leaf_of) ? 0 : -1;
+    if (rc == 0)
+        rc = fmm_by_target(&f.p2p, nn, pcnt, pstart, psrc);
+    if (rc == 0) {
+        tree_quad_fill(&d, x, m, Q);
+        /* M2L in traversal order */
+        for (int64_t q = 0; q < f.m2l.n; ++q) {
+            const int64_t a = f.m2l.a[q], b = f.m2l.b[q];
+            local_m2l_add(own + 20 * a, d.com + 3 * a, d.com + 3 * b, d.mass[b], Q + 6 * b, eps2);
+        }
+        /* L2L top-down: preorder numbering puts every parent before its
+         * children */
+        for (int k = 0; k < 20; ++k)
+            tot[k] = nsum_val(&own[k]);
+        for (int64_t a = 0; a < nn; ++a) {
+            const int64_t ch[2] = {d.nodes[4 * a + 2], d.nodes[4 * a + 3]};
+            if (ch[0] < 0) {
+                for (int64_t p = d.nodes[4 * a]; p < d.nodes[4 * a + 1]; ++p)
+                    leaf_of[p] = a;
+                continue;
+            }
+            for (int h = 0; h < 2; ++h) {
+                const int64_t c = ch[h];
+                const double dz[3] = {d.com[3 * c] - d.com[3 * a], d.com[3 * c + 1] - d.com[3 * a + 1],
+                                      d.com[3 * c + 2] - d.com[3 * a + 2]};
+                double sh[20];
+                oracle_local_shift(tot + 20 * a, dz, sh);
+                for (int k = 0; k < 20; ++k)
+                    tot[20 * c + k] = nsum_val(&own[20 * c + k]) + sh[k];
+            }
+        }
+        int64_t t;
+#pragma omp parallel for schedule(dynamic, 64)
+        for (t = 0; t < ntarg; ++t) {
+            const int64_t i = targets ? targets[t] : t;
+            const int64_t a = leaf_of[i];
+            const double *za = d.com + 3 * a;
+            const double xi = x[3 * i], yi = x[3 * i + 1], zi = x[3 * i + 2];
+            nsum ax = {0, 0}, ay = {0, 0}, az = {0, 0}, ph = {0, 0};
+            const double y[3] = {xi - za[0], yi - za[1], zi - za[2]};
+            local_l2p_add(tot + 20 * a, y, &ax, &ay, &az, &ph);
+            for (int64_t q = pstart[a]; q < pstart[a] + pcnt[a]; ++q) {
+                const int64_t b = psrc[q];
+                for (int64_t j = d.nodes[4 * b]; j < d.nodes[4 * b + 1]; ++j) {
+                    if (j == i)
+                        continue;
+                    const double dx = x[3 * j] - xi;
+                    const double dy = x[3 * j + 1] - yi;
+                    const double dzz = x[3 * j + 2] - zi;
+                    const double r2 = ((dx * dx + dy * dy) + dzz * dzz) + eps2;
+                    const double r = sqrt(r2);
+                    const double w = 1.0 / (r2 * r);
+                    const double mw = m[j] * w;
+                    nsum_add(&ax, mw * dx);
+                    nsum_add(&ay, mw * dy);
+                    nsum_add(&az, mw * dzz);
+                    nsum_add(&ph, m[j] / r);
+                }
+            }
+            if (acc) {
+                acc[3 * t] = G * nsum_val(&ax);
+                acc[3 * t + 1] = G * nsum_val(&ay);
+                acc[3 * t + 2] = G * nsum_val(&az);
+            }
+            if (pot)
+                pot[t] = -G * nsum_val(&ph);
+        }
+    }
+    free(Q);
+    free(own);
+    free(tot);
+    free(pcnt);
+    free(pstart);
+    free(psrc);
+    free(leaf_of);
+    fmm_ctx_free(&f);
+    tree_free(&d);
+    return rc;
 }
 
 /* ---------------------------------------------------------------------------

@@ -92,6 +92,17 @@ MUTANTS = [
     ("trajectory cotangents: potential's mass term dropped", ["tests/test_oracle_vjp.py"],
      "            gm[k] += tm[k];\n    }\n    double *carry = a;",
      "            gm[k] += 0.0 * tm[k];\n    }\n    double *carry = a;"),
+    ("FMM: L2L drops the T term of the gradient", ["tests/test_oracle_fmm.py"],
+     "out[1 + k] = c[1 + k] + kd[k] + 0.5 * tdd[k];", "out[1 + k] = c[1 + k] + kd[k];"),
+    ("FMM: acceptance test without the target's size", ["tests/test_oracle_fmm.py"],
+     "return d->diag2[a] + d->diag2[b] < f->theta2 * dist2;", "return d->diag2[b] < f->theta2 * dist2;"),
+    ("FMM: parent expansion not passed down", ["tests/test_oracle_fmm.py"],
+     "tot[20 * c + k] = nsum_val(&own[20 * c + k]) + sh[k];", "tot[20 * c + k] = nsum_val(&own[20 * c + k]);"),
+    ("FMM: self pair kept in P2P", ["tests/test_oracle_fmm.py"],
+     "                    if (j == i)\n                        continue;\n                    const double dx = x[3 * j] - xi;\n"
+     "                    const double dy = x[3 * j + 1] - yi;\n                    const double dzz",
+     "                    const double dx = x[3 * j] - xi;\n"
+     "                    const double dy = x[3 * j + 1] - yi;\n                    const double dzz"),
 ]
 
 
