@@ -267,9 +267,9 @@ int nbody_trajectory_adjoint(const void *ckpt, int64_t n, int32_t prec, double G
  * Cell models (the acceptance test and the interaction lists are the same
  * for all three):
  * NBODY_CELLS_MONOPOLE: an accepted cell acts as one body (above).
- * NBODY_CELLS_PSEUDO (order 2 by pseudo-particle multipoles: Makino 1999,
- *   the paper's reference [20], named in Section VI as the step past
- *   monopole cells): the cell acts as NBODY_TREE_PSEUDO point masses q_j at
+ * NBODY_CELLS_PSEUDO (order 2 by pseudo-particle multipoles: Makino,
+ *   J. Comput. Phys. 151, 1999, the paper's reference [20], which Section
+ *   VI cites for the O(N) fast multipole method): the cell acts as NBODY_TREE_PSEUDO point masses q_j at
  *   com + a s_j whose multipole expansion about com equals the cell's
  *   through the quadrupole term.  s_j: the unit vertices of the icosahedron,
  *   (0, u, v g), (u, v g, 0), (u g, 0, v) over sqrt(1 + g^2), g the golden
@@ -408,14 +408,16 @@ int nbody_janus_adjoint(void *state, const void *pos_mass, int64_t n, double G, 
  * offsets, 2 = nbody_accel_vjp) on library-owned synthetic inputs,
  * synchronously, and records the fastest in the in-process table (and in the
  * JSON file named by the environment variable NBODY_TUNE_CACHE, if set).
+ * The candidates are (tpl, jsplit, jtile) with variant 0; every candidate
+ * performs the same arithmetic per pair, so tuning changes where partial sums
+ * are folded, never the accuracy class of the result.
  * nbody_set_tuning pins a shape for later calls: tpl (targets per lane:
  * 1, 2, 4), jsplit (independent source ranges per target, 1..32, reduced in
  * fixed order; kernel 1 takes 1), jtile (sources per partial sum, multiple
  * of 8), variant (FP32 force kernel only, apart from 0: 0 = source records
  * through scalar loads; 1 = staged in LDS, jtile a multiple of 256, identical
- * results to 0; 2 = the source contraction on the matrix cores, tpl 1, jtile
- * a multiple of 256, accurate to about 1e-6 in ORB order); kernel and prec as
- * above; tpl = jsplit = jtile = -1 clears it.
+ * results to 0, never chosen by nbody_autotune); kernel and prec as above;
+ * tpl = jsplit = jtile = -1 clears it.
  * nbody_get_tuning reports the shape the library would use.
  */
 int nbody_autotune(int32_t kernel, int32_t prec, int64_t n, const int64_t *offsets_host,

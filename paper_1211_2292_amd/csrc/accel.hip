@@ -262,60 +262,6 @@ __device__ __forceinline__ void block_lds_f32(const float4 *__restrict__ src, in
         for (int c = 0; c < 4; ++c) res[t][c] = R[t][c].get();
 }
 
-// ---- FP32 sweep with the source contraction on the matrix cores ---------------
-// a_t = G sum_j m_j rho_tj^3 (x_j - x_t) is a contraction over the sources.
-// Written relative to a centre C shared by the workgroup,
-//     a_t = G [ sum_j rho_tj^3 m_j (x_j - C)  -  (x_t - C) sum_j rho_tj^3 m_j ],
-// the sums are a (targets x sources) by (sources x 4) product whose second
-// factor, m_j (x_j - C, y_j - C, z_j - C, 1), does not depend on the target.
-// Each lane computes the pair geometry and w = rho^3 for its own target (10
-// VALU per pair: 3 sub, 3 FMA, rsq, 2 mul, 1 FMA for phi) and one
-// V_MFMA_F32_4X4X1_16B_F32 per source folds w into the four sums: operand A
-// is component (lane mod 4) of the weighted source record (from LDS),
-// operand B is the lane's w, and accumulator register k of lane l holds
-// component k for target l.  The cancellation in the last step is bounded by
-// |x_t - C| times the sum of weights, so this form is meant for inputs in ORB
-// order, where a workgroup's targets are spatially compact.
-typedef float v4f __attribute__((ext_vector_type(4)));
-
-template <bool MASK>
-__device__ __forceinline__ void mfma_pair(const float4 b, const float comp, const int j,
-                                          const float xi, const float yi, const float zi,
-                                          const int ii, const float eps2, v4f &D, float &pot)
-{
-    const float dx = b.x - xi;
-    const float dy = b.y - yi;
-    const float dz = b.z - zi;
-    const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
-    float rho = __builtin_amdgcn_rsqf(r2);
-    if (MASK) rho = (j == ii) ? 0.0f : rho;
-    const float w = rho * (rho * rho);
-    pot = __builtin_fmaf(b.w, rho, pot);
-    D = __builtin_amdgcn_mfma_f32_4x4x1f32(comp, w, D, 0, 0, 0);
-}
-
-template <bool MASK>
-__device__ __forceinline__ void sweep_mfma(const float4 *__restrict__ src, const float *tl,
-                                           int jbase, int u0, int u1, int c, float xi, float yi,
-                                           float zi, int ii, float eps2, v4f &D, float &pot)
-{
-    int u = u0;
-    for (; u + kUnroll <= u1; u += kUnroll) {
-        float4 b[kUnroll];
-        float cp[kUnroll];
-#pragma unroll
-        for (int k = 0; k < kUnroll; ++k) {
-            b[k] = src[jbase + u + k];
-            cp[k] = tl[4 * (u + k) + c];
-        }
-#pragma unroll
-        for (int k = 0; k < kUnroll; ++k)
-            mfma_pair<MASK>(b[k], cp[k], jbase + u + k, xi, yi, zi, ii, eps2, D, pot);
-    }
-    for (; u < u1; ++u)
-        mfma_pair<MASK>(src[jbase + u], tl[4 * u + c], jbase + u, xi, yi, zi, ii, eps2, D, pot);
-}
-
 // ---- kernels -------------------------------------------------------------------
 // Source range of split `split` out of `js` over n sources.
 __device__ __forceinline__ void split_range(int n, int js, int split, int &jb, int &je)
@@ -359,82 +305,6 @@ __global__ __launch_bounds__(kBlock) void k_accel_f32(const float4 *__restrict__
                 make_double4(res[t][0], res[t][1], res[t][2], res[t][3]);
         }
     }
-}
-
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_accel_mfma_f32(const float4 *__restrict__ src, int n,
-                                                           float eps2, double G, int tbeg,
-                                                           int tcount, int jtile,
-                                                           float4 *__restrict__ out,
-                                                           void *__restrict__ partial)
-{
-    __shared__ float4 tile[2][kLdsTile];
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int tend = tbeg + tcount;
-    const long t0l = (long)tbeg + ((long)blockIdx.x * (kBlock / 64) + wave) * 64;
-    const bool active = t0l < tend;
-    const int t0 = active ? (int)t0l : tbeg;
-    // centre: the workgroup's first target
-    const float4 cen = src[min(tbeg + (int)blockIdx.x * kBlock, n - 1)];
-    int jb, je;
-    split_range(n, gridDim.y, blockIdx.y, jb, je);
-    const int ii = t0 + lane;
-    const float4 xt = src[min(ii, n - 1)];
-    const int c = lane & 3;
-    const int d0 = t0, d1 = t0 + 64;
-    v4f D = {0.0f, 0.0f, 0.0f, 0.0f};
-    float pot = 0.0f;
-    Run<MODE> R[5];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) R[k].zero();
-    auto weighted = [&](float4 r) {
-        return make_float4(r.w * (r.x - cen.x), r.w * (r.y - cen.y), r.w * (r.z - cen.z), r.w);
-    };
-    float4 pre = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (jb + (int)threadIdx.x < je) pre = weighted(src[jb + threadIdx.x]);
-    tile[0][threadIdx.x] = pre;
-    __syncthreads();
-    int buf = 0, since = 0;
-    for (int j0 = jb; j0 < je; j0 += kLdsTile) {
-        const int cnt = min(kLdsTile, je - j0);
-        const int jn = j0 + kLdsTile;
-        if (jn + (int)threadIdx.x < je) pre = weighted(src[jn + threadIdx.x]);
-        const float *tl = reinterpret_cast<const float *>(tile[buf]);
-        const int lo = min(max(d0, j0), j0 + cnt) - j0;
-        const int hi = min(max(d1, j0), j0 + cnt) - j0;
-        sweep_mfma<false>(src, tl, j0, 0, lo, c, xt.x, xt.y, xt.z, ii, eps2, D, pot);
-        sweep_mfma<true>(src, tl, j0, lo, hi, c, xt.x, xt.y, xt.z, ii, eps2, D, pot);
-        sweep_mfma<false>(src, tl, j0, hi, cnt, c, xt.x, xt.y, xt.z, ii, eps2, D, pot);
-        since += cnt;
-        if (since >= jtile || jn >= je) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) R[k].fold(D[k]);
-            R[4].fold(pot);
-            D = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-            pot = 0.0f;
-            since = 0;
-        }
-        if (jn < je) tile[buf ^ 1][threadIdx.x] = pre;
-        __syncthreads();
-        buf ^= 1;
-    }
-    if (!active || ii >= tend) return;
-    double s[5];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) s[k] = R[k].get();
-    const double rx = (double)xt.x - (double)cen.x, ry = (double)xt.y - (double)cen.y,
-                 rz = (double)xt.z - (double)cen.z;
-    double res[4] = {s[0] - rx * s[3], s[1] - ry * s[3], s[2] - rz * s[3], s[4]};
-    const long k = ii - tbeg;
-    if (gridDim.y == 1)
-        put(out, k, res, G);
-    else if constexpr (MODE == M_F32)  // the split reduction of this mode reads float4
-        reinterpret_cast<float4 *>(partial)[(long)blockIdx.y * tcount + k] =
-            make_float4((float)res[0], (float)res[1], (float)res[2], (float)res[3]);
-    else
-        reinterpret_cast<double4 *>(partial)[(long)blockIdx.y * tcount + k] =
-            make_double4(res[0], res[1], res[2], res[3]);
 }
 
 template <int TPL, int MODE>
@@ -640,23 +510,18 @@ __global__ __launch_bounds__(kBlock) void k_batched_f64(const double4 *__restric
 
 template <int TPL, int MODE>
 hipError_t go_f32(const float4 *pm, int n, float eps2, double G, float4 *out, int tbeg, int tcount,
-                  const Tune &t, void *partial, hipStream_t s)
+                  const Tune &t, void *partial, bool reduce, hipStream_t s)
 {
     const int per_block = (kBlock / 64) * 64 * TPL;
     dim3 grid((tcount + per_block - 1) / per_block, t.jsplit);
-    if (t.variant == 2) {
-        // one target per lane
-        dim3 g1((tcount + kBlock - 1) / kBlock, t.jsplit);
-        hipLaunchKernelGGL((k_accel_mfma_f32<MODE>), g1, dim3(kBlock), 0, s, pm, n, eps2, G, tbeg,
-                           tcount, t.jtile, out, partial);
-    } else if (t.variant == 1)
+    if (t.variant == 1)
         hipLaunchKernelGGL((k_accel_lds_f32<TPL, MODE>), grid, dim3(kBlock), 0, s, pm, n, eps2, G,
                            tbeg, tcount, t.jtile, out, partial);
     else
         hipLaunchKernelGGL((k_accel_f32<TPL, MODE>), grid, dim3(kBlock), 0, s, pm, n, eps2, G, tbeg,
                            tcount, t.jtile, out, partial);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || t.jsplit == 1) return e;
+    if (e != hipSuccess || t.jsplit == 1 || !reduce) return e;
     const int rb = (tcount + kBlock - 1) / kBlock;
     if constexpr (MODE == M_F32)
         hipLaunchKernelGGL(k_split_reduce_f32, dim3(rb), dim3(kBlock), 0, s,
@@ -669,14 +534,14 @@ hipError_t go_f32(const float4 *pm, int n, float eps2, double G, float4 *out, in
 
 template <int TPL>
 hipError_t go_f64(const double4 *pm, int n, double eps2, double G, double4 *out, int tbeg,
-                  int tcount, const Tune &t, void *partial, hipStream_t s)
+                  int tcount, const Tune &t, void *partial, bool reduce, hipStream_t s)
 {
     const int per_block = (kBlock / 64) * 64 * TPL;
     dim3 grid((tcount + per_block - 1) / per_block, t.jsplit);
     hipLaunchKernelGGL((k_accel_f64<TPL>), grid, dim3(kBlock), 0, s, pm, n, eps2, G, tbeg, tcount,
                        t.jtile, out, (double4 *)partial);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || t.jsplit == 1) return e;
+    if (e != hipSuccess || t.jsplit == 1 || !reduce) return e;
     const int rb = (tcount + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_split_reduce<double4>, dim3(rb), dim3(kBlock), 0, s,
                        (const double4 *)partial, t.jsplit, tcount, G, out);
@@ -685,12 +550,12 @@ hipError_t go_f64(const double4 *pm, int n, double eps2, double G, double4 *out,
 
 template <int MODE>
 hipError_t by_tpl_f32(const float4 *pm, int n, float eps2, double G, float4 *out, int tbeg,
-                      int tcount, const Tune &t, void *partial, hipStream_t s)
+                      int tcount, const Tune &t, void *partial, bool reduce, hipStream_t s)
 {
     switch (t.tpl) {
-    case 1: return go_f32<1, MODE>(pm, n, eps2, G, out, tbeg, tcount, t, partial, s);
-    case 2: return go_f32<2, MODE>(pm, n, eps2, G, out, tbeg, tcount, t, partial, s);
-    default: return go_f32<4, MODE>(pm, n, eps2, G, out, tbeg, tcount, t, partial, s);
+    case 1: return go_f32<1, MODE>(pm, n, eps2, G, out, tbeg, tcount, t, partial, reduce, s);
+    case 2: return go_f32<2, MODE>(pm, n, eps2, G, out, tbeg, tcount, t, partial, reduce, s);
+    default: return go_f32<4, MODE>(pm, n, eps2, G, out, tbeg, tcount, t, partial, reduce, s);
     }
 }
 
@@ -722,8 +587,7 @@ bool tune_valid(const Tune &t)
 {
     return (t.tpl == 1 || t.tpl == 2 || t.tpl == 4) && t.jsplit >= 1 && t.jsplit <= 32 &&
            t.jtile >= 8 && t.jtile % kUnroll == 0 && t.jtile <= (1 << 24) &&
-           (t.variant == 0 || ((t.variant == 1 || t.variant == 2) && t.jtile % kLdsTile == 0)) &&
-           (t.variant != 2 || t.tpl == 1);
+           (t.variant == 0 || (t.variant == 1 && t.jtile % kLdsTile == 0));
 }
 
 size_t accel_partial_bytes(int prec, int tcount, const Tune &t)
@@ -736,24 +600,24 @@ size_t accel_partial_bytes(int prec, int tcount, const Tune &t)
 static float eps2_f32(double eps) { return (float)((double)eps * (double)eps); }
 
 hipError_t launch_accel(int prec, const void *pm, int n, double G, double eps, void *out, int tbeg,
-                        int tcount, const Tune &t, void *partial, hipStream_t s)
+                        int tcount, const Tune &t, void *partial, hipStream_t s, bool reduce)
 {
     if (prec == NBODY_F64) {
         const double4 *p = (const double4 *)pm;
         double4 *o = (double4 *)out;
         const double e2 = eps * eps;
         switch (t.tpl) {
-        case 1: return go_f64<1>(p, n, e2, G, o, tbeg, tcount, t, partial, s);
-        default: return go_f64<2>(p, n, e2, G, o, tbeg, tcount, t, partial, s);
+        case 1: return go_f64<1>(p, n, e2, G, o, tbeg, tcount, t, partial, reduce, s);
+        default: return go_f64<2>(p, n, e2, G, o, tbeg, tcount, t, partial, reduce, s);
         }
     }
     const float4 *p = (const float4 *)pm;
     float4 *o = (float4 *)out;
     const float e2 = eps2_f32(eps);
     switch (prec) {
-    case NBODY_F32: return by_tpl_f32<M_F32>(p, n, e2, G, o, tbeg, tcount, t, partial, s);
-    case NBODY_F32_KAHAN: return by_tpl_f32<M_KAHAN>(p, n, e2, G, o, tbeg, tcount, t, partial, s);
-    default: return by_tpl_f32<M_F64ACC>(p, n, e2, G, o, tbeg, tcount, t, partial, s);
+    case NBODY_F32: return by_tpl_f32<M_F32>(p, n, e2, G, o, tbeg, tcount, t, partial, reduce, s);
+    case NBODY_F32_KAHAN: return by_tpl_f32<M_KAHAN>(p, n, e2, G, o, tbeg, tcount, t, partial, reduce, s);
+    default: return by_tpl_f32<M_F64ACC>(p, n, e2, G, o, tbeg, tcount, t, partial, reduce, s);
     }
 }
 

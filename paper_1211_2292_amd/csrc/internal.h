@@ -45,8 +45,11 @@ bool tune_valid(const Tune &t);
 // ---- force (accel.hip) -----------------------------------------------------
 // pm: float4/double4 records; out: target_count records; partial: scratch of
 // jsplit * target_count double4 (F32 mode: float4) records when jsplit > 1.
+// reduce = false leaves a split result in `partial` (out untouched) for a
+// consumer that reduces it itself (launch_reduce_step).
 hipError_t launch_accel(int prec, const void *pm, int n, double G, double eps, void *out,
-                        int tbeg, int tcount, const Tune &t, void *partial, hipStream_t s);
+                        int tbeg, int tcount, const Tune &t, void *partial, hipStream_t s,
+                        bool reduce = true);
 size_t accel_partial_bytes(int prec, int tcount, const Tune &t);
 
 // Batched force over a work list of (system, first target) units sorted
@@ -78,6 +81,12 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_step(int prec, void *pm, void *vel, const void *acc, int n, double h, double dt,
                        bool close, bool open, double *epart, int *eblocks, hipStream_t s);
 int step_blocks(int n);
+// Split reduction of the force (js partial records per body, as left by
+// launch_accel(..., reduce = false) for all n targets) fused with the step:
+// acc receives the reduced force, then the kick/drift of launch_step runs.
+hipError_t launch_reduce_step(int prec, const void *partial, int js, double G, void *pm, void *vel,
+                              void *acc, int n, double h, double dt, bool close, bool open,
+                              double *epart, int *eblocks, hipStream_t s);
 hipError_t launch_energy_final(const double *epart, int nblocks, double *out, hipStream_t s);
 hipError_t launch_permute(const void *src, void *dst, const int32_t *perm, int n, int rec_bytes,
                           bool inverse, hipStream_t s);

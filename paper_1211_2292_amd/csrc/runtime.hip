@@ -276,11 +276,12 @@ static Tune default_tune(int kernel, int prec, int64_t n, int64_t ntarg)
     return t;
 }
 
-static Tune lookup_tune(int kernel, int prec, int64_t n, int64_t ntarg = -1)
+static Tune lookup_tune(int kernel, int prec, int64_t n, int64_t ntarg = -1, bool *pinned = nullptr)
 {
     std::lock_guard<std::mutex> lk(g_mu);
     load_cache_locked();
     auto p = g_pinned.find({kernel, prec});
+    if (pinned) *pinned = p != g_pinned.end();
     if (p != g_pinned.end()) return p->second;
     auto it = g_tuned.find(TuneKey(kernel, prec, log2ceil(n)));
     if (it != g_tuned.end()) return it->second;
@@ -418,26 +419,52 @@ static int leapfrog_enqueue(void *pm, void *vel, void *acc, int n, const BatchPl
 {
     const double h = 0.5 * dt;
     Tune bt = lookup_tune(1, prec, n);
-    auto eval = [&]() -> int {
-        if (plan) return batched_force(prec, pm, *plan, G, nullptr, eps, acc, bt, s);
-        return force(prec, pm, n, G, eps, acc, 0, n, s, buf.partial);
-    };
-    if (!(flags & NBODY_ACC_VALID)) NB_CHECK(eval());
     double *ep = energy ? buf.epart : nullptr;
     int eb = 0;
-    if (nsteps == 0) {
-        if (energy) {
-            NB_TRY(launch_step(prec, pm, vel, acc, n, h, dt, false, false, ep, &eb, s), "step kernel");
-            NB_TRY(launch_energy_final(ep, eb, energy, s), "energy kernel");
+    // A force evaluation followed by the step pass (close, open, energy).
+    // A direct force with a source split leaves its per-split records in
+    // scratch and the step pass reduces them itself (one launch fewer).
+    auto eval_step = [&](bool step, bool close, bool open) -> int {
+        if (!plan) {
+            const Tune t = lookup_tune(0, prec, n);
+            const size_t pb = accel_partial_bytes(prec, n, t);
+            if (pb && step) {
+                void *partial = buf.partial ? buf.partial : scratch(kSlotPartial, pb);
+                if (!partial) {
+                    set_error("cannot allocate %zu bytes of split scratch", pb);
+                    return NBODY_E_NOMEM;
+                }
+                NB_TRY(launch_accel(prec, pm, n, G, eps, acc, 0, n, t, partial, s, false), "force kernel");
+                NB_TRY(launch_reduce_step(prec, partial, t.jsplit, G, pm, vel, acc, n, h, dt, close, open,
+                                          ep, &eb, s),
+                       "reduce + step kernel");
+                return NBODY_OK;
+            }
+            NB_CHECK(force(prec, pm, n, G, eps, acc, 0, n, s, buf.partial));
+        } else {
+            NB_CHECK(batched_force(prec, pm, *plan, G, nullptr, eps, acc, bt, s));
         }
+        if (step) NB_TRY(launch_step(prec, pm, vel, acc, n, h, dt, close, open, ep, &eb, s), "step kernel");
+        return NBODY_OK;
+    };
+    auto step_only = [&](bool close, bool open) -> int {
+        NB_TRY(launch_step(prec, pm, vel, acc, n, h, dt, close, open, ep, &eb, s), "step kernel");
+        return NBODY_OK;
+    };
+    const bool have_acc = (flags & NBODY_ACC_VALID) != 0;
+    if (nsteps == 0) {
+        // a(x_0) and, on request, the energies at t_0
+        if (!have_acc) NB_CHECK(eval_step(energy != nullptr, false, false));
+        else if (energy) NB_CHECK(step_only(false, false));
+        if (energy) NB_TRY(launch_energy_final(ep, eb, energy, s), "energy kernel");
         return NBODY_OK;
     }
-    NB_TRY(launch_step(prec, pm, vel, acc, n, h, dt, false, true, ep, &eb, s), "step kernel");
+    if (!have_acc) NB_CHECK(eval_step(true, false, true));
+    else NB_CHECK(step_only(false, true));
     if (energy) NB_TRY(launch_energy_final(ep, eb, energy, s), "energy kernel");
     for (int k = 0; k < nsteps; ++k) {
-        NB_CHECK(eval());
         const bool last = (k == nsteps - 1);
-        NB_TRY(launch_step(prec, pm, vel, acc, n, h, dt, true, !last, ep, &eb, s), "step kernel");
+        NB_CHECK(eval_step(true, true, !last));
         if (energy) NB_TRY(launch_energy_final(ep, eb, energy + 2 * (k + 1), s), "energy kernel");
     }
     return NBODY_OK;
@@ -471,6 +498,9 @@ using namespace nbi;
 // ===========================================================================
 // C ABI
 // ===========================================================================
+static int check_accel_args(const void *pos_mass, int64_t n, int32_t prec, double G, double eps,
+                            const void *acc_pot_out, int64_t target_begin, int64_t target_count);
+
 extern "C" {
 
 int nbody_version(void) { return 100; }
@@ -502,6 +532,17 @@ static int check_scalars(double G, double eps, double dt = 0.0)
 int nbody_accel(const void *pos_mass, int64_t n, int32_t prec, double G, double eps,
                 void *acc_pot_out, int64_t target_begin, int64_t target_count, void *stream)
 {
+    NB_CHECK(check_accel_args(pos_mass, n, prec, G, eps, acc_pot_out, target_begin, target_count));
+    if (target_count == 0) return NBODY_OK;
+    return force(prec, pos_mass, (int)n, G, eps, acc_pot_out, (int)target_begin, (int)target_count,
+                 (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+static int check_accel_args(const void *pos_mass, int64_t n, int32_t prec, double G, double eps,
+                            const void *acc_pot_out, int64_t target_begin, int64_t target_count)
+{
     NB_CHECK(check_n(n));
     if (!prec_ok(prec)) {
         set_error("bad precision %d", prec);
@@ -520,10 +561,10 @@ int nbody_accel(const void *pos_mass, int64_t n, int32_t prec, double G, double 
         set_error("acc_pot_out overlaps pos_mass");
         return NBODY_E_INVAL;
     }
-    if (target_count == 0) return NBODY_OK;
-    return force(prec, pos_mass, (int)n, G, eps, acc_pot_out, (int)target_begin, (int)target_count,
-                 (hipStream_t)stream);
+    return NBODY_OK;
 }
+
+extern "C" {
 
 int nbody_batched_accel(const void *pos_mass, const int64_t *offsets_host, int32_t nsys,
                         int32_t prec, double G, const float *eps_per_sys, double eps,
@@ -1470,16 +1511,15 @@ extern "C" int nbody_autotune(int32_t kernel, int32_t prec, int64_t n, const int
                     if (js > 1 && n / js < 512) break;
                     const int64_t waves = (n + 64 * tp - 1) / (64 * tp);
                     if (waves * js > 65536 && js > 1) break;
-                    for (int var = 0; var < 3; ++var) {
-                        if (var >= 1 && (kernel != 0 || prec == NBODY_F64)) continue;
-                        if (var == 2 && (tp != 1 || jt % 256)) continue;
-                        Tune t;
-                        t.tpl = tp;
-                        t.jsplit = js;
-                        t.jtile = jt;
-                        t.variant = var;
-                        cands.push_back(t);
-                    }
+                    // Only the scalar-load sweep (variant 0) is a candidate: the
+                    // LDS-staged sweep gives the same results but was slower at
+                    // every measured size; it stays reachable through a pin.
+                    Tune t;
+                    t.tpl = tp;
+                    t.jsplit = js;
+                    t.jtile = jt;
+                    t.variant = 0;
+                    cands.push_back(t);
                 }
             } else {
                 Tune t;

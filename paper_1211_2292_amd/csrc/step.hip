@@ -5,6 +5,8 @@
 //
 // All are HBM-bound streams over 16- or 32-byte records: one record per lane,
 // coalesced 16-byte vector loads and stores, workgroups of 256 lanes.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace nbi {
@@ -31,36 +33,83 @@ __device__ __forceinline__ void block_sum2(double &a, double &b)
 // close: v += h a;  energy partials (1/2 m |v|^2, 1/2 m phi) in FP64;
 // open: v += h a; x += dt v.
 template <typename V, typename S>
+__device__ __forceinline__ void step_one(V *__restrict__ pm, V *__restrict__ vel, int i, const V a,
+                                         S h, S dt, int close, int open, bool energy, double &ek,
+                                         double &eu)
+{
+    V x = pm[i];
+    V v = vel[i];
+    if (close) {
+        v.x = v.x + h * a.x;
+        v.y = v.y + h * a.y;
+        v.z = v.z + h * a.z;
+    }
+    if (energy) {
+        const double vx = v.x, vy = v.y, vz = v.z, m = x.w;
+        ek = 0.5 * m * ((vx * vx + vy * vy) + vz * vz);
+        eu = 0.5 * m * (double)a.w;
+    }
+    if (open) {
+        v.x = v.x + h * a.x;
+        v.y = v.y + h * a.y;
+        v.z = v.z + h * a.z;
+        x.x = x.x + dt * v.x;
+        x.y = x.y + dt * v.y;
+        x.z = x.z + dt * v.z;
+        pm[i] = x;
+    }
+    if (close || open) vel[i] = v;
+}
+
+template <typename V, typename S>
 __global__ __launch_bounds__(kBlock) void k_step(V *__restrict__ pm, V *__restrict__ vel,
                                                  const V *__restrict__ acc, int n, S h, S dt,
                                                  int close, int open, double *__restrict__ epart)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     double ek = 0.0, eu = 0.0;
+    if (i < n) step_one(pm, vel, i, acc[i], h, dt, close, open, epart != nullptr, ek, eu);
+    if (epart) {
+        block_sum2(ek, eu);
+        if (threadIdx.x == 0) {
+            epart[2 * blockIdx.x] = ek;
+            epart[2 * blockIdx.x + 1] = eu;
+        }
+    }
+}
+
+// The force kernel's source-split reduction and the step in one pass: the
+// js partial records of body i are summed in split order and scaled exactly
+// as the stand-alone reduction does (R = the partials' type, GT = the type G
+// is applied in), the record is stored to acc, and the same value drives the
+// kick, drift and energy partials.  Results equal reduce-then-step bit for
+// bit; one launch and one pass over acc fewer.
+template <typename V, typename S, typename P, typename R, typename GT>
+__global__ __launch_bounds__(kBlock) void k_reduce_step(const P *__restrict__ partial, int js, GT G,
+                                                        V *__restrict__ pm, V *__restrict__ vel,
+                                                        V *__restrict__ acc, int n, S h, S dt,
+                                                        int close, int open,
+                                                        double *__restrict__ epart)
+{
+    using E = typename std::conditional<sizeof(V) == 16, float, double>::type;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    double ek = 0.0, eu = 0.0;
     if (i < n) {
-        V x = pm[i];
-        V v = vel[i];
-        const V a = acc[i];
-        if (close) {
-            v.x = v.x + h * a.x;
-            v.y = v.y + h * a.y;
-            v.z = v.z + h * a.z;
+        R r[4] = {R(0), R(0), R(0), R(0)};
+        for (int k = 0; k < js; ++k) {
+            const P q = partial[(long)k * n + i];
+            r[0] += q.x;
+            r[1] += q.y;
+            r[2] += q.z;
+            r[3] += q.w;
         }
-        if (epart) {
-            const double vx = v.x, vy = v.y, vz = v.z, m = x.w;
-            ek = 0.5 * m * ((vx * vx + vy * vy) + vz * vz);
-            eu = 0.5 * m * (double)a.w;
-        }
-        if (open) {
-            v.x = v.x + h * a.x;
-            v.y = v.y + h * a.y;
-            v.z = v.z + h * a.z;
-            x.x = x.x + dt * v.x;
-            x.y = x.y + dt * v.y;
-            x.z = x.z + dt * v.z;
-            pm[i] = x;
-        }
-        if (close || open) vel[i] = v;
+        V a;
+        a.x = (E)(G * r[0]);
+        a.y = (E)(G * r[1]);
+        a.z = (E)(G * r[2]);
+        a.w = (E)(-G * r[3]);
+        acc[i] = a;
+        step_one(pm, vel, i, a, h, dt, close, open, epart != nullptr, ek, eu);
     }
     if (epart) {
         block_sum2(ek, eu);
@@ -142,6 +191,29 @@ hipError_t launch_step(int prec, void *pm, void *vel, const void *acc, int n, do
     else
         hipLaunchKernelGGL((k_step<float4, float>), dim3(nb), dim3(kBlock), 0, s, (float4 *)pm,
                            (float4 *)vel, (const float4 *)acc, n, (float)h, (float)dt, (int)close,
+                           (int)open, epart);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_step(int prec, const void *partial, int js, double G, void *pm, void *vel,
+                              void *acc, int n, double h, double dt, bool close, bool open,
+                              double *epart, int *eblocks, hipStream_t s)
+{
+    const int nb = step_blocks(n);
+    if (eblocks) *eblocks = nb;
+    if (prec == NBODY_F64)
+        hipLaunchKernelGGL((k_reduce_step<double4, double, double4, double, double>), dim3(nb),
+                           dim3(kBlock), 0, s, (const double4 *)partial, js, G, (double4 *)pm,
+                           (double4 *)vel, (double4 *)acc, n, h, dt, (int)close, (int)open, epart);
+    else if (prec == NBODY_F32)
+        hipLaunchKernelGGL((k_reduce_step<float4, float, float4, float, float>), dim3(nb),
+                           dim3(kBlock), 0, s, (const float4 *)partial, js, (float)G, (float4 *)pm,
+                           (float4 *)vel, (float4 *)acc, n, (float)h, (float)dt, (int)close,
+                           (int)open, epart);
+    else
+        hipLaunchKernelGGL((k_reduce_step<float4, float, double4, double, double>), dim3(nb),
+                           dim3(kBlock), 0, s, (const double4 *)partial, js, G, (float4 *)pm,
+                           (float4 *)vel, (float4 *)acc, n, (float)h, (float)dt, (int)close,
                            (int)open, epart);
     return hipGetLastError();
 }

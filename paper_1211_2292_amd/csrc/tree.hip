@@ -38,8 +38,9 @@
 //   which is exact.  In inspection mode the same walk writes the node ids of
 //   the accepted cells and of the rejected leaves instead of summing.
 //
-// Order 2 (pseudo-particle multipoles, Makino 1999, the paper's reference
-// [20], named in Section VI as the next step past monopole cells): an
+// Order 2 (pseudo-particle multipoles: Makino, J. Comput. Phys. 151, 1999,
+// the paper's reference [20], which Section VI cites for the O(N) fast
+// multipole method): an
 // accepted cell acts as 12 point masses q_j at com + a s_j, s_j the unit
 // vertices of the icosahedron, a = half the box diagonal, whose expansion
 // about com equals the cell's through the quadrupole term.  With S the

@@ -82,6 +82,7 @@ def test_other_entry_points_validate():
     assert L.nbody_set_tuning(0, 1, 2, 1, 320, 1) == -1   # LDS variant needs jtile % 256 == 0
     assert L.nbody_set_tuning(0, 0, 1, 1, 512, 1) == -1   # no LDS variant in FP64
     assert L.nbody_set_tuning(2, 1, 1, 1, 512, 1) == -1   # nor for the VJP
+    assert L.nbody_set_tuning(0, 1, 1, 1, 512, 2) == -1   # variants 0 and 1 only
     assert L.nbody_energy(P(64), P(1024), P(4096), 10, 1, None, None) == -1
     # tree code: leaf range, precision, theta, list arguments
     assert L.nbody_tree_shape(100, 0, None, None, None) == -1

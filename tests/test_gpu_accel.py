@@ -227,60 +227,6 @@ def test_lds_variant_equals_scalar_variant(orc, mode, tpl, js, jt):
             assert rms_rel(host(b)[:, :3], acc) <= bar
 
 
-@pytest.mark.parametrize("mode", ["F32_F64ACC", "F32_KAHAN", "F32"])
-def test_mfma_variant_parity(orc, mode):
-    """The matrix-core form (variant 2) against the oracle, on ORB-ordered
-    input (its intended use) and on unordered input, with ragged sizes and
-    source splits."""
-    torch, nb = gpu()
-    prec = getattr(nb, mode)
-    bar_sorted = 1e-4 if mode == "F32" else 1e-5
-    try:
-        for n, js in [(1, 1), (63, 1), (257, 2), (4097, 3), (20000, 8)]:
-            pm, _ = ics.plummer(max(n, 2), 400 + n)
-            pm = widen32(pm[:n])
-            p = to_dev(torch, pm, torch.float32)
-            perm = nb.orb_order(p, 256)
-            q = nb.permute(p, perm)
-            nb.set_tuning(0, prec, 1, js, 512, 2)
-            out_sorted = nb.permute(nb.accel(q, 0.01, prec=prec), perm, inverse=True)
-            out_raw = nb.accel(p, 0.01, prec=prec)
-            torch.cuda.synchronize()
-            if n == 1:
-                assert torch.all(out_raw == 0)
-                continue
-            acc, pot = orc.accel(pm, 0.01)
-            es = rms_rel(host(out_sorted)[:, :3], acc)
-            er = rms_rel(host(out_raw)[:, :3], acc)
-            print(f"mfma {mode} n={n}: ORB-ordered {es:.2e}, unordered {er:.2e}")
-            assert es <= bar_sorted
-            assert rms_rel(host(out_sorted)[:, 3], pot) <= bar_sorted
-            assert er <= 1e-3
-    finally:
-        nb.set_tuning(0, prec)
-
-
-def test_mfma_variant_collide1m_sampled(orc):
-    """Full size, ORB order, the launch shape the benchmark can pick."""
-    torch, nb = gpu()
-    w = ics.WORKLOADS["collide1m"]
-    pm, _ = ics.colliding_pair(w["n"], w["seed"])
-    pm32 = widen32(pm)
-    p = to_dev(torch, pm32, torch.float32)
-    perm = nb.orb_order(p, 256)
-    q = nb.permute(p, perm)
-    try:
-        nb.set_tuning(0, nb.F32_F64ACC, 1, 4, 1024, 2)
-        out = host(nb.permute(nb.accel(q, w["eps"], prec=nb.F32_F64ACC), perm, inverse=True))
-    finally:
-        nb.set_tuning(0, nb.F32_F64ACC)
-    tg = ics.sample_targets(w["n"], 512, w["seed"] + 1)
-    acc, pot = orc.accel(pm32, w["eps"], targets=tg)
-    e = rms_rel(out[tg, :3], acc)
-    print(f"mfma collide1m: force rms rel {e:.3e}, pot {rms_rel(out[tg, 3], pot):.3e}")
-    assert e <= 1e-5
-
-
 def test_caller_outputs_must_fit():
     """A caller-supplied `out` of the wrong row count or dtype is refused in
     the binding before any kernel is launched."""

@@ -1,5 +1,6 @@
 """Order-2 tree cells on the device (the pseudo-particle multipole method of
-the paper's reference [20], Section VI) against the oracle.
+Makino 1999, the paper's reference [20], cited in Section VI) against the
+oracle.
 
 The device builds each cell's 12 pseudo-particles from FP64 second moments
 (parallel-axis rule, bottom-up); the oracle sums the method's mass formula

@@ -1,5 +1,6 @@
 """Pins of the oracle's pseudo-particle cells (the pseudo-particle multipole
-method of the paper's reference [20], named in Section VI): each cell's
+method of Makino 1999, the paper's reference [20], cited in Section VI for
+the O(N) fast multipole method): each cell's
 expansion to quadrupole order about its centre of mass is carried by 12
 point masses on the icosahedron directions.
 
