@@ -129,6 +129,34 @@ int nbody_accel(const void *pos_mass, int64_t n, int32_t prec, double G, double 
                 void *acc_pot_out, int64_t target_begin, int64_t target_count, void *stream);
 
 /*
+ * nbody_accel for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments and validation as nbody_accel; it calls no hipMalloc, hipFree or
+ * other allocating routine.  When the kernel shape splits the source range
+ * (jsplit > 1) the per-split partial records (jsplit * target_count records
+ * of 32 bytes; 16 in NBODY_F32) go to a file-scope device array of
+ * NBODY_NOALLOC_SCRATCH bytes (64 MiB) that each GPU the library runs on
+ * holds until the process ends.
+ *   - If the partials of nbody_accel's shape fit, the same shape runs and the
+ *     result equals nbody_accel's bit for bit.
+ *   - If they do not fit and the shape was chosen by the library (default or
+ *     autotuned), the split count is halved until they fit (one split needs
+ *     no scratch): the partial sums are then grouped differently, within the
+ *     same error bound.
+ *   - If they do not fit and the shape was pinned with nbody_set_tuning, the
+ *     call returns NBODY_E_INVAL before anything is enqueued, with the sizes
+ *     in nbody_last_error().
+ * Every call on a GPU shares that GPU's array: calls that overlap in time on
+ * one GPU (different streams or threads) race and must be ordered by the
+ * caller.  Nothing in the array needs clearing: each call writes every
+ * record it reads.
+ */
+#define NBODY_NOALLOC_SCRATCH (64u << 20)
+int nbody_accel_noalloc(const void *pos_mass, int64_t n, int32_t prec, double G, double eps,
+                        void *acc_pot_out, int64_t target_begin, int64_t target_count,
+                        void *stream);
+
+/*
  * Fused force + vector-Jacobian product at one configuration (derivative of
  * the law above; the paper has no derivatives).  Given cotangents
  * acc_pot_cot = (abar, phibar) per body, writes

@@ -54,6 +54,7 @@ _SIGS = {
     "nbody_orb_order": [_vp, _i32, _i64, _i32, _vp, _vp],
     "nbody_permute": [_vp, _vp, _vp, _i64, _i32, _i32, _vp],
     "nbody_accel": [_vp, _i64, _i32, _dbl, _dbl, _vp, _i64, _i64, _vp],
+    "nbody_accel_noalloc": [_vp, _i64, _i32, _dbl, _dbl, _vp, _i64, _i64, _vp],
     "nbody_accel_vjp": [_vp, _vp, _i64, _i32, _dbl, _dbl, _vp, _vp, _vp, _vp],
     "nbody_leapfrog_kdk": [_vp, _vp, _vp, _i64, _vp, _i32, _i32, _dbl, _dbl, _dbl, _i32,
                            ctypes.c_uint32, _vp, _vp],
@@ -191,6 +192,19 @@ def accel(pos_mass, eps, G=1.0, prec=None, target_begin=0, target_count=None, ou
         _out(out, tc, pm)
     _check(lib().nbody_accel(_ptr(pm), n, p, float(G), float(eps), _ptr(out), int(target_begin), int(tc),
                              _stream()))
+    return out
+
+
+@_on_device
+def accel_noalloc(pos_mass, out, eps, G=1.0, prec=None, target_begin=0):
+    """nbody_accel_noalloc: the force of targets [target_begin, +len(out))
+    into the caller's ``out``, with no device allocation by the library."""
+    pm = _rec(pos_mass, "pos_mass")
+    p = _prec(pm, prec)
+    tc = _rec(out, "out", pm.dtype).shape[0]
+    _out(out, tc, pm)
+    _check(lib().nbody_accel_noalloc(_ptr(pm), pm.shape[0], p, float(G), float(eps), _ptr(out),
+                                     int(target_begin), int(tc), _stream()))
     return out
 
 

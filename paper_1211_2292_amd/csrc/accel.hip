@@ -27,6 +27,8 @@
 // * Small problems split the source range over gridDim.y workgroup rows; the
 //   per-split records go to scratch and are reduced in split order by a
 //   second kernel, so the result never depends on scheduling.
+#include <mutex>
+
 #include "internal.h"
 #include "pair.h"
 
@@ -644,6 +646,42 @@ hipError_t launch_batched(int prec, const void *pm, const int64_t *offsets, cons
     case NBODY_F32_KAHAN: return batched_by_tpl<M_KAHAN>(p, offsets, units, nunits, eps_sys, e2, G, o, t, counter, grid, s);
     default: return batched_by_tpl<M_F64ACC>(p, offsets, units, nunits, eps_sys, e2, G, o, t, counter, grid, s);
     }
+}
+
+// ---- static split scratch (nbody_accel_noalloc) -------------------------------
+// The split partials of the entry point that allocates nothing live in this
+// file-scope device array; every GPU the library runs on holds its own copy
+// for the life of the process.  Host code never passes the array's name to a
+// kernel: its device address is looked up once per device with
+// hipGetSymbolAddress and that address is what the kernels receive.
+__device__ __align__(256) static unsigned char g_split_scratch[kStaticScratchBytes];
+
+void *static_split_scratch()
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        set_error("hipGetDevice: %s", hipGetErrorString(e));
+        return nullptr;
+    }
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device %d beyond the %d devices the static scratch table covers", dev, kMaxDevices);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_split_scratch));
+        if (e != hipSuccess || !p) {
+            set_error("hipGetSymbolAddress(static split scratch): %s", hipGetErrorString(e));
+            return nullptr;
+        }
+        addr[dev] = p;
+    }
+    return addr[dev];
 }
 
 }  // namespace nbi

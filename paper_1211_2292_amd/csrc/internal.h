@@ -52,6 +52,13 @@ hipError_t launch_accel(int prec, const void *pm, int n, double G, double eps, v
                         bool reduce = true);
 size_t accel_partial_bytes(int prec, int tcount, const Tune &t);
 
+// Split partials of nbody_accel_noalloc: a file-scope device array in
+// accel.hip of kStaticScratchBytes.  static_split_scratch() returns its
+// address on the current device (looked up once per device), or nullptr with
+// the error set.
+constexpr size_t kStaticScratchBytes = NBODY_NOALLOC_SCRATCH;
+void *static_split_scratch();
+
 // Batched force over a work list of (system, first target) units sorted
 // longest first.  units: int2[nunits] = (system, target offset within the
 // system); offsets: int64 device copy [nsys+1]; counter: one zeroed uint32

@@ -538,6 +538,36 @@ int nbody_accel(const void *pos_mass, int64_t n, int32_t prec, double G, double 
                  (hipStream_t)stream);
 }
 
+int nbody_accel_noalloc(const void *pos_mass, int64_t n, int32_t prec, double G, double eps,
+                        void *acc_pot_out, int64_t target_begin, int64_t target_count, void *stream)
+{
+    NB_CHECK(check_accel_args(pos_mass, n, prec, G, eps, acc_pot_out, target_begin, target_count));
+    if (target_count == 0) return NBODY_OK;
+    // nbody_accel's kernel shape, so the results are identical, with the
+    // split partials in the static device array.  A library-chosen shape
+    // whose partials would not fit runs with fewer splits; a pinned one is
+    // refused.
+    bool pinned = false;
+    Tune t = lookup_tune(0, prec, n, target_count, &pinned);
+    size_t pb = accel_partial_bytes(prec, (int)target_count, t);
+    if (pb > kStaticScratchBytes && pinned) {
+        set_error("nbody_accel_noalloc: the pinned shape's %d source splits x %lld targets need %zu "
+                  "bytes of split scratch, above the static buffer's %zu",
+                  t.jsplit, (long long)target_count, pb, kStaticScratchBytes);
+        return NBODY_E_INVAL;
+    }
+    while (pb > kStaticScratchBytes) {
+        t.jsplit = t.jsplit / 2 > 1 ? t.jsplit / 2 : 1;
+        pb = accel_partial_bytes(prec, (int)target_count, t);
+    }
+    void *partial = nullptr;
+    if (pb && !(partial = static_split_scratch())) return NBODY_E_HIP;
+    NB_TRY(launch_accel(prec, pos_mass, (int)n, G, eps, acc_pot_out, (int)target_begin,
+                        (int)target_count, t, partial, (hipStream_t)stream),
+           "force kernel");
+    return NBODY_OK;
+}
+
 }  // extern "C"
 
 static int check_accel_args(const void *pos_mass, int64_t n, int32_t prec, double G, double eps,

@@ -60,6 +60,24 @@ def test_accel_validation(args, rc):
     nb, L = _lib()
     assert L.nbody_accel(*args) == rc
     assert L.nbody_last_error()
+    assert L.nbody_accel_noalloc(*args) == rc
+    assert L.nbody_last_error()
+
+
+def test_noalloc_refuses_pinned_split_beyond_static_scratch():
+    """A pinned shape whose split partials exceed the static buffer is
+    refused on the host, before any device call: 32 splits x 2^17 targets x
+    32-byte records = 128 MiB > 64 MiB."""
+    nb, L = _lib()
+    n = 1 << 17
+    assert L.nbody_set_tuning(0, 2, 1, 32, 512, 0) == 0
+    try:
+        assert L.nbody_accel_noalloc(P(1 << 12), n, 2, 1.0, 0.01, P(1 << 40), 0, n, None) == -1
+        msg = L.nbody_last_error()
+        msg = msg.decode() if isinstance(msg, bytes) else msg
+        assert "static buffer" in msg and str(64 << 20) in msg
+    finally:
+        assert L.nbody_set_tuning(0, 2, -1, -1, -1, 0) == 0
 
 
 def test_other_entry_points_validate():
