@@ -66,6 +66,8 @@ _SIGS = {
                                  _vp, _vp, _i32, _vp],
     "nbody_tree_shape": [_i64, _i32, _vp, _vp, _vp],
     "nbody_tree_accel": [_vp, _i64, _i32, _dbl, _dbl, _dbl, _i32, _vp, _vp],
+    "nbody_fmm_accel": [_vp, _i64, _i32, _dbl, _dbl, _dbl, _i32, _vp, _vp],
+    "nbody_fmm_lists": [_vp, _i64, _i32, _dbl, _vp, _vp, _vp, _i64, _vp, _i64, _vp],
     "nbody_tree_accel_cells": [_vp, _i64, _i32, _dbl, _dbl, _dbl, _i32, _i32, _vp, _vp],
     "nbody_tree_pseudo": [_vp, _i64, _i32, _vp, _vp],
     "nbody_tree_quad": [_vp, _i64, _i32, _vp, _vp],
@@ -359,6 +361,41 @@ def tree_accel(pos_mass, eps, theta, leaf=4, G=1.0, prec=None, out=None, cells=C
     _check(lib().nbody_tree_accel_cells(_ptr(pm), pm.shape[0], p, float(G), float(eps), float(theta),
                                         int(leaf), int(cells), _ptr(out), _stream()))
     return out
+
+
+@_on_device
+def fmm_accel(pos_mass, eps, theta, leaf=8, G=1.0, prec=None, out=None):
+    """Force and potential (ax, ay, az, phi) per body, ORB order, by the
+    multi-level fast multipole method on the ORB nodes (quadrupole cells,
+    third-order local expansions)."""
+    pm = _rec(pos_mass, "pos_mass", torch.float32)
+    p = _prec(pm, prec)
+    if out is None:
+        out = torch.empty_like(pm)
+    else:
+        _out(out, pm.shape[0], pm)
+    _check(lib().nbody_fmm_accel(_ptr(pm), pm.shape[0], p, float(G), float(eps), float(theta), int(leaf),
+                                 _ptr(out), _stream()))
+    return out
+
+
+@_on_device
+def fmm_lists(pos_mass, theta, leaf=8):
+    """The FMM's lists: (m2l_count, p2p_count) int32 (num_nodes,) and the
+    concatenated source node ids (m2l, p2p), target nodes in id order, each
+    target's sources in the device walk's fixed order."""
+    pm = _rec(pos_mass, "pos_mass", torch.float32)
+    nn, _ = tree_shape(pm.shape[0], leaf)
+    mc = torch.empty(nn, dtype=torch.int32, device=pm.device)
+    pc = torch.empty(nn, dtype=torch.int32, device=pm.device)
+    _check(lib().nbody_fmm_lists(_ptr(pm), pm.shape[0], int(leaf), float(theta), _ptr(mc), _ptr(pc), None, 0,
+                                 None, 0, _stream()))
+    nm, npp = int(mc.sum()), int(pc.sum())
+    m2l = torch.empty(max(nm, 1), dtype=torch.int32, device=pm.device)
+    p2p = torch.empty(max(npp, 1), dtype=torch.int32, device=pm.device)
+    _check(lib().nbody_fmm_lists(_ptr(pm), pm.shape[0], int(leaf), float(theta), _ptr(mc), _ptr(pc), _ptr(m2l),
+                                 m2l.shape[0], _ptr(p2p), p2p.shape[0], _stream()))
+    return mc, pc, m2l[:nm], p2p[:npp]
 
 
 @_on_device

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libnbody.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-SOURCES = ["accel.hip", "vjp.hip", "step.hip", "orb.hip", "tree.hip", "janus.hip", "runtime.hip"]
+SOURCES = ["accel.hip", "vjp.hip", "step.hip", "orb.hip", "tree.hip", "fmm.hip", "janus.hip", "runtime.hip"]
 CFLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-pass-failed", "-Wno-unused-command-line-argument"]

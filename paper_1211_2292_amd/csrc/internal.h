@@ -146,6 +146,16 @@ int tree_leapfrog(void *pm, void *vel, void *acc, int32_t *order, int n, int pre
                   double *energy, hipStream_t s);
 void tree_release();
 
+// ---- multi-level FMM (fmm.hip) ------------------------------------------------
+// pm: n float4 records in ORB order (leaf as given).  fmm_accel writes n
+// records (ORB order); synchronises s once to check the list buffers.
+int fmm_accel(const void *pm, int n, int prec, double G, double eps, double theta, int leaf, void *out,
+              hipStream_t s);
+// Lists grouped by target node (device outputs; ids may be NULL to count).
+int fmm_lists(const void *pm, int n, int leaf, double theta, int32_t *m2l_cnt, int32_t *p2p_cnt, int32_t *m2l_ids,
+              int64_t m2l_cap, int32_t *p2p_ids, int64_t p2p_cap, hipStream_t s);
+void fmm_release();
+
 // ---- bit-reversible fixed-point leapfrog (janus.hip) ---------------------------
 // state: 2n longlong4 (X then V); the force kernel and the fused VJP run with
 // G = 1 and the shape of janus_tune so their forces agree bit for bit.

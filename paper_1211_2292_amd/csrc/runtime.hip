@@ -964,6 +964,51 @@ int nbody_tree_accel_cells(const void *pos_mass, int64_t n, int32_t prec, double
     return tree_accel(pos_mass, (int)n, prec, G, eps, theta, leaf, cells, acc_pot_out, (hipStream_t)stream);
 }
 
+int nbody_fmm_accel(const void *pos_mass, int64_t n, int32_t prec, double G, double eps, double theta,
+                    int32_t leaf, void *acc_pot_out, void *stream)
+{
+    NB_CHECK(check_tree(n, leaf));
+    if (!prec_ok(prec)) {
+        set_error("bad precision %d", prec);
+        return NBODY_E_INVAL;
+    }
+    if (prec == NBODY_F64) {
+        set_error("the FMM runs the FP32 modes only");
+        return NBODY_E_UNSUPPORTED;
+    }
+    NB_CHECK(check_scalars(G, eps, 0.0));
+    NB_CHECK(check_theta(theta));
+    NB_CHECK(check_vec(pos_mass, prec, "pos_mass"));
+    NB_CHECK(check_vec(acc_pot_out, prec, "acc_pot_out"));
+    if (overlap(pos_mass, 16 * (size_t)n, acc_pot_out, 16 * (size_t)n)) {
+        set_error("acc_pot_out overlaps pos_mass");
+        return NBODY_E_INVAL;
+    }
+    return fmm_accel(pos_mass, (int)n, prec, G, eps, theta, leaf, acc_pot_out, (hipStream_t)stream);
+}
+
+int nbody_fmm_lists(const void *pos_mass, int64_t n, int32_t leaf, double theta, int32_t *m2l_cnt,
+                    int32_t *p2p_cnt, int32_t *m2l_ids, int64_t m2l_cap, int32_t *p2p_ids, int64_t p2p_cap,
+                    void *stream)
+{
+    NB_CHECK(check_tree(n, leaf));
+    NB_CHECK(check_theta(theta));
+    NB_CHECK(check_vec(pos_mass, NBODY_F32, "pos_mass"));
+    if (!m2l_cnt || !p2p_cnt || ((uintptr_t)m2l_cnt | (uintptr_t)p2p_cnt | (uintptr_t)m2l_ids | (uintptr_t)p2p_ids) % 4 ||
+        m2l_cap < 0 || p2p_cap < 0) {
+        set_error("count arrays NULL, or misaligned arrays, or negative capacity");
+        return NBODY_E_INVAL;
+    }
+    int64_t nn = 0;
+    NB_CHECK(tree_shape((int)n, leaf, &nn, nullptr, nullptr));
+    if (outputs_overlap({{m2l_cnt, 4 * (size_t)nn}, {p2p_cnt, 4 * (size_t)nn}, {m2l_ids, 4 * (size_t)m2l_cap},
+                         {p2p_ids, 4 * (size_t)p2p_cap}},
+                        {{pos_mass, 16 * (size_t)n}}))
+        return NBODY_E_INVAL;
+    return fmm_lists(pos_mass, (int)n, leaf, theta, m2l_cnt, p2p_cnt, m2l_ids, m2l_cap, p2p_ids, p2p_cap,
+                     (hipStream_t)stream);
+}
+
 int nbody_tree_pseudo(const void *pos_mass, int64_t n, int32_t leaf, void *pseudo_out, void *stream)
 {
     NB_CHECK(check_tree(n, leaf));
@@ -1635,5 +1680,6 @@ extern "C" void nbody_release(void)
             if (kv.second.ptr[k]) (void)hipFree(kv.second.ptr[k]);
     g_scratch.clear();
     orb_release();
+    fmm_release();
     tree_release();
 }

@@ -1,0 +1,122 @@
+"""The multi-level FMM on the device (nbody_fmm_accel, nbody_fmm_lists)
+against the oracle's FMM (Section VI's O(N) method).
+
+The traversal's decisions are the FP64 expressions of the definitions, so
+every node's M2L and P2P lists equal the oracle's as sets (the device walk
+visits them in its own fixed order).  Forces are FP32 (M2L sums in
+FP32, L2L and L2P in FP64, P2P with the FP32 pair code) and are held to the
+tree-code bars against the oracle's FP64 evaluation of the same lists."""
+import numpy as np
+import pytest
+
+import ics
+from nbtest import gpu, host, max_rel, rms_rel, to_dev, widen32
+
+pytestmark = pytest.mark.gpu
+
+GEN = {"plummer": ics.plummer, "collide": ics.colliding_pair, "ball": ics.uniform_ball}
+
+
+def _orb_input(torch, nb, pm, leaf):
+    p = to_dev(torch, np.asarray(pm, dtype=np.float32), torch.float32)
+    q = nb.permute(p, nb.orb_order(p, leaf))
+    torch.cuda.synchronize()
+    return q, q.cpu().numpy()
+
+
+def _per_node_sorted(ids, cnt):
+    node = np.repeat(np.arange(cnt.shape[0]), cnt)
+    return ids[np.lexsort((ids, node))]
+
+
+@pytest.mark.parametrize("n,leaf,theta,kind", [
+    (1, 8, 0.5, "plummer"), (7, 8, 0.5, "plummer"), (300, 4, 0.6, "plummer"), (3000, 8, 0.5, "plummer"),
+    (3000, 8, 0.0, "ball"), (5000, 5, 0.7, "collide"), (776, 1, 0.9, "collide"), (20000, 16, 0.5, "collide"),
+    (9001, 12, 1.0, "plummer"), (4097, 64, 0.4, "ball"), (70001, 8, 0.6, "plummer")])
+def test_lists_match_oracle(orc, n, leaf, theta, kind):
+    torch, nb = gpu()
+    pm, _ = GEN[kind](max(n, 4), 700 + n)
+    q, qh = _orb_input(torch, nb, pm[:n], leaf)
+    mc, pc, m2l, p2p = (host(t).astype(np.int64) for t in nb.fmm_lists(q, theta, leaf))
+    want = orc.fmm_lists(qh, leaf, theta)
+    assert np.array_equal(mc, want["m2l_cnt"])
+    assert np.array_equal(pc, want["p2p_cnt"])
+    # each node's entries as a set (the device walk visits them in its own
+    # fixed order)
+    assert np.array_equal(_per_node_sorted(m2l, mc), _per_node_sorted(want["m2l"], want["m2l_cnt"]))
+    assert np.array_equal(_per_node_sorted(p2p, pc), _per_node_sorted(want["p2p"], want["p2p_cnt"]))
+    if theta == 0.0:
+        assert mc.sum() == 0
+
+
+@pytest.mark.parametrize("prec,tol_rms,tol_max", [("F32_F64ACC", 1e-6, 2e-5), ("F32_KAHAN", 1e-6, 2e-5),
+                                                  ("F32", 2e-6, 1e-4)])
+@pytest.mark.parametrize("theta,leaf", [(0.0, 8), (0.5, 8), (0.7, 4), (0.6, 16)])
+def test_force_matches_oracle(orc, prec, tol_rms, tol_max, theta, leaf):
+    torch, nb = gpu()
+    n, eps = 12000, 0.01
+    pm, _ = ics.plummer(n, 710)
+    q, qh = _orb_input(torch, nb, pm, leaf)
+    got = host(nb.fmm_accel(q, eps, theta, leaf, prec=getattr(nb, prec)))
+    a, p = orc.fmm_accel(widen32(qh), leaf, theta, eps)
+    assert rms_rel(got[:, :3], a) < tol_rms
+    assert max_rel(got[:, :3], a) < tol_max
+    assert rms_rel(got[:, 3], p) < tol_rms
+
+
+@pytest.mark.parametrize("n,leaf", [(1, 8), (2, 1), (5, 8), (64, 64), (65, 64), (1001, 3), (4096, 32)])
+def test_edge_sizes(orc, n, leaf):
+    """One body (no force), fewer bodies than a leaf, ragged last leaves,
+    leaf sizes that are not powers of two, the largest leaf."""
+    torch, nb = gpu()
+    pm, _ = ics.uniform_ball(max(n, 2), 720 + n)
+    q, qh = _orb_input(torch, nb, pm[:n], leaf)
+    got = host(nb.fmm_accel(q, 0.01, 0.6, leaf, prec=nb.F32_F64ACC))
+    if n == 1:
+        assert np.all(got == 0)
+        return
+    a, p = orc.fmm_accel(widen32(qh), leaf, 0.6, 0.01)
+    assert rms_rel(got[:, :3], a) < 1e-6
+    assert rms_rel(got[:, 3], p) < 1e-6
+
+
+def test_theta_zero_is_the_direct_sum(orc):
+    torch, nb = gpu()
+    n = 3000
+    pm, _ = ics.colliding_pair(n, 730)
+    q, qh = _orb_input(torch, nb, pm, 8)
+    got = host(nb.fmm_accel(q, 0.005, 0.0, 8, prec=nb.F32_F64ACC))
+    a, p = orc.accel(widen32(qh), 0.005)
+    assert rms_rel(got[:, :3], a) < 1e-6
+    assert rms_rel(got[:, 3], p) < 1e-6
+
+
+def test_repeat_calls_and_buffer_growth(orc):
+    """A small call, then a much larger one (the list buffers grow), then the
+    small one again: every result equals its first evaluation bit for bit."""
+    torch, nb = gpu()
+    outs = []
+    for n in (2000, 60000, 2000):
+        pm, _ = ics.plummer(n, 740 + n)
+        q, _ = _orb_input(torch, nb, pm, 8)
+        outs.append(nb.fmm_accel(q, 0.01, 0.3, 8).clone())
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[2])
+
+
+def test_collide1m_sampled_against_oracle(orc):
+    """The full-size colliding pair (2^20 bodies, leaf 8, theta 0.5): lists
+    sizes equal the oracle's, sampled forces at FP32 tolerance; error
+    against the exact sum reported."""
+    torch, nb = gpu()
+    w = ics.WORKLOADS["collide1m"]
+    pm, _ = ics.colliding_pair(w["n"], w["seed"])
+    q, qh = _orb_input(torch, nb, pm, 8)
+    got = host(nb.fmm_accel(q, w["eps"], 0.5, 8, prec=nb.F32_F64ACC))
+    tg = ics.sample_targets(w["n"], 256, w["seed"] + 3)
+    a, p = orc.fmm_accel(widen32(qh), 8, 0.5, w["eps"], targets=tg)
+    assert rms_rel(got[tg, :3], a) < 1e-6
+    assert rms_rel(got[tg, 3], p) < 1e-6
+    ad, _ = orc.accel(widen32(qh), w["eps"], targets=tg)
+    print(f"fmm collide1m theta 0.5 leaf 8: vs oracle FMM {rms_rel(got[tg, :3], a):.2e}, "
+          f"vs exact sum {rms_rel(got[tg, :3], ad):.2e}")
