@@ -109,8 +109,8 @@ def _load():
         lib.oracle_tree_pseudo.restype = ctypes.c_int
         lib.oracle_pseudo_dirs.argtypes = [_d]
         lib.oracle_pseudo_dirs.restype = None
-        lib.oracle_fmm_lists.argtypes = [ctypes.c_int64, ctypes.c_int32, _d, _d, ctypes.c_double, _i64, _i64,
-                                         _i32, ctypes.c_int64, _i32, ctypes.c_int64]
+        lib.oracle_fmm_lists.argtypes = [ctypes.c_int64, ctypes.c_int32, _d, _d, ctypes.c_double, _i64, _i64, _i64,
+                                         _i32, ctypes.c_int64, _i32, ctypes.c_int64, _i32, ctypes.c_int64]
         lib.oracle_fmm_lists.restype = ctypes.c_int
         lib.oracle_fmm_accel.argtypes = [ctypes.c_int64, ctypes.c_int32, _d, _d, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_double, ctypes.c_int64, _i64, _d, _d]
@@ -451,30 +451,35 @@ def tree_local_lists(pos_mass_orb, leaf: int, group: int, theta: float):
 
 def fmm_lists(pos_mass_orb, leaf: int, theta: float):
     """Interaction lists of the multi-level FMM's dual-tree traversal on the
-    ORB nodes (Section VI's O(N) method): dict(m2l_cnt, p2p_cnt (nn,) per
-    target node, m2l, p2p (source node ids, targets in node order, each
-    target's sources in traversal order))."""
+    ORB nodes (Section VI's O(N) method): dict(m2l_cnt, m2p_cnt, p2p_cnt
+    (nn,) per target node, m2l, m2p, p2p (source node ids, targets in node
+    order, each target's sources in traversal order))."""
     lib = _load()
     x, m = _split(pos_mass_orb)
     n = x.shape[0]
     nn = tree_nodes(n, leaf).shape[0]
-    mc = np.empty(nn, dtype=np.int64)
-    pc = np.empty(nn, dtype=np.int64)
-    if lib.oracle_fmm_lists(n, int(leaf), _ptr(x, _d), _ptr(m, _d), float(theta), _ptr(mc, _i64), _ptr(pc, _i64),
-                            None, 0, None, 0) != 0:
+    cnt = [np.empty(nn, dtype=np.int64) for _ in range(3)]
+    if lib.oracle_fmm_lists(n, int(leaf), _ptr(x, _d), _ptr(m, _d), float(theta), *(_ptr(c, _i64) for c in cnt),
+                            None, 0, None, 0, None, 0) != 0:
         raise ValueError("oracle_fmm_lists: bad arguments")
-    m2l = np.empty(max(int(mc.sum()), 1), dtype=np.int32)
-    p2p = np.empty(max(int(pc.sum()), 1), dtype=np.int32)
-    if lib.oracle_fmm_lists(n, int(leaf), _ptr(x, _d), _ptr(m, _d), float(theta), _ptr(mc, _i64), _ptr(pc, _i64),
-                            _ptr(m2l, _i32), m2l.shape[0], _ptr(p2p, _i32), p2p.shape[0]) != 0:
+    ids = [np.empty(max(int(c.sum()), 1), dtype=np.int32) for c in cnt]
+    args = []
+    for a in ids:
+        args += [_ptr(a, _i32), a.shape[0]]
+    if lib.oracle_fmm_lists(n, int(leaf), _ptr(x, _d), _ptr(m, _d), float(theta), *(_ptr(c, _i64) for c in cnt),
+                            *args) != 0:
         raise ValueError("oracle_fmm_lists failed")
-    return dict(m2l_cnt=mc, p2p_cnt=pc, m2l=m2l[:int(mc.sum())], p2p=p2p[:int(pc.sum())])
+    out = {}
+    for name, c, a in zip(("m2l", "m2p", "p2p"), cnt, ids):
+        out[name + "_cnt"] = c
+        out[name] = a[:int(c.sum())]
+    return out
 
 
 def fmm_accel(pos_mass_orb, leaf: int, theta: float, eps: float, G: float = 1.0, targets=None):
     """Force and potential by the multi-level FMM on the ORB nodes
-    (quadrupole cells, third-order local expansions, L2L down the tree, P2P
-    between leaves).  Returns (acc (T, 3), pot (T,)) for ORB positions
+    (quadrupole cells, third-order local expansions, L2L down the tree, M2P
+    cells and P2P leaves at the leaves).  Returns (acc (T, 3), pot (T,)) for ORB positions
     ``targets`` (all when None)."""
     lib = _load()
     x, m = _split(pos_mass_orb)

@@ -1135,6 +1135,33 @@ static void local_l2p_add(const double *c, const double *y, nsum *ax, nsum *ay, 
     nsum_add(ph, c[0] + py + 0.5 * yky + ytyy / 6.0);
 }
 
+/* One quadrupole cell (mass M at com cm, traceless tensor Qv = xx, yy, zz,
+ * xy, xz, yz) at the point (xi, yi, zi), d = x - com, s^2 = |d|^2 + eps^2:
+ *   phi-sum += M/s + d.Q.d / (2 s^5),
+ *   a-sum   += -M d / s^3 + Q d / s^5 - 5 (d.Q.d) d / (2 s^7)
+ * (the expansion of the cell's potential through l = 2 with the softened
+ * distance in place of |d|; the caller scales by G and the sign). */
+static void quad_cell_add(double xi, double yi, double zi, const double *cm, double M, const double *Q,
+                          double eps2, nsum *ax, nsum *ay, nsum *az, nsum *ph)
+{
+    const double dv[3] = {xi - cm[0], yi - cm[1], zi - cm[2]};
+    const double s2 = ((dv[0] * dv[0] + dv[1] * dv[1]) + dv[2] * dv[2]) + eps2;
+    const double s = sqrt(s2);
+    const double qd[3] = {(Q[0] * dv[0] + Q[3] * dv[1]) + Q[4] * dv[2],
+                          (Q[3] * dv[0] + Q[1] * dv[1]) + Q[5] * dv[2],
+                          (Q[4] * dv[0] + Q[5] * dv[1]) + Q[2] * dv[2]};
+    const double dqd = (dv[0] * qd[0] + dv[1] * qd[1]) + dv[2] * qd[2];
+    const double s3 = s2 * s, s5 = s3 * s2, s7 = s5 * s2;
+    for (int k = 0; k < 3; ++k) {
+        nsum *ak = k == 0 ? ax : (k == 1 ? ay : az);
+        nsum_add(ak, -M * dv[k] / s3);
+        nsum_add(ak, qd[k] / s5);
+        nsum_add(ak, -2.5 * dqd * dv[k] / s7);
+    }
+    nsum_add(ph, M / s);
+    nsum_add(ph, 0.5 * dqd / s5);
+}
+
 /* Tree force and potential on targets (ORB positions; NULL = all n).
  * acc: [ntarg][3], pot: [ntarg].  cells 0: an accepted cell acts as one body
  * (M at com); 2: as its 12 pseudo-particles; 3: through its quadrupole
@@ -1222,25 +1249,7 @@ int oracle_tree_accel_cells(int64_t n, int32_t leaf, int32_t group, const double
         for (int64_t q = 0; q < nf + nnr; ++q) {
             const int64_t c = q < nf ? far[q] : near[q - nf];
             if (q < nf && cells >= 3) {
-                /* quadrupole cell, d = x - com */
-                const double *cm = d.com + 3 * c, *Q = pp + 6 * c;
-                const double M = d.mass[c];
-                const double dv[3] = {xi - cm[0], yi - cm[1], zi - cm[2]};
-                const double s2 = ((dv[0] * dv[0] + dv[1] * dv[1]) + dv[2] * dv[2]) + eps2;
-                const double s = sqrt(s2);
-                const double qd[3] = {(Q[0] * dv[0] + Q[3] * dv[1]) + Q[4] * dv[2],
-                                      (Q[3] * dv[0] + Q[1] * dv[1]) + Q[5] * dv[2],
-                                      (Q[4] * dv[0] + Q[5] * dv[1]) + Q[2] * dv[2]};
-                const double dqd = (dv[0] * qd[0] + dv[1] * qd[1]) + dv[2] * qd[2];
-                const double s3 = s2 * s, s5 = s3 * s2, s7 = s5 * s2;
-                for (int k = 0; k < 3; ++k) {
-                    nsum *ak = k == 0 ? &ax : (k == 1 ? &ay : &az);
-                    nsum_add(ak, -M * dv[k] / s3);
-                    nsum_add(ak, qd[k] / s5);
-                    nsum_add(ak, -2.5 * dqd * dv[k] / s7);
-                }
-                nsum_add(&ph, M / s);
-                nsum_add(&ph, 0.5 * dqd / s5);
+                quad_cell_add(xi, yi, zi, d.com + 3 * c, d.mass[c], pp + 6 * c, eps2, &ax, &ay, &az, &ph);
                 continue;
             }
             int64_t jb, je;
@@ -1376,21 +1385,29 @@ int oracle_tree_accel(int64_t n, int32_t leaf, int32_t group, const double *x, c
  *             nodes).
  *   traversal interact(A, B) from (root, root):
  *               MAC(A, B)          -> B joins the M2L list of A
+ *               A a leaf that the tree code's opening test accepts B for
+ *               (diag2_B < theta^2 D2, D2 from com_B to A's box; see
+ *               tree_accept)      -> B joins the M2P list of A
  *               A, B both leaves   -> B joins the P2P list of A
  *               B a leaf, or A not a leaf with diag2_A >= diag2_B
  *                                  -> interact(A.left, B), interact(A.right, B)
  *               else               -> interact(A, B.left), interact(A, B.right)
  *             Every ordered pair of distinct bodies (i, j) is then counted
  *             once: through the M2L entry of an ancestor-or-self of i's
- *             leaf whose source contains j, or through the P2P entry of
- *             i's leaf whose source leaf contains j.
+ *             leaf whose source contains j, or through the M2P or P2P entry
+ *             of i's leaf whose source contains j.  The M2P case keeps a
+ *             leaf whose box is large against its distance to the rest (a
+ *             few bodies far out in a halo) from failing the MAC against
+ *             every node and pairing with every leaf.
  *   M2L       local_m2l_add, summed over a node's list in traversal order.
  *   L2L       a node's total expansion = its own M2L sum + its parent's
  *             total re-expanded about its centre (local_shift: a cubic
  *             re-expanded exactly), coefficient by coefficient.
- *   L2P, P2P  per body of a leaf: the leaf's total expansion at the body
- *             (local_l2p_add), then the P2P source leaves in list order body
- *             by body, skipping the body itself; Neumaier sums.
+ *   L2P, M2P, P2P  per body of a leaf: the leaf's total expansion at the
+ *             body (local_l2p_add), then its M2P cells in list order as
+ *             quadrupole cells (quad_cell_add), then the P2P source leaves
+ *             in list order body by body, skipping the body itself;
+ *             Neumaier sums.
  * theta = 0 gives no M2L entry, so the result is the direct sum.
  * ------------------------------------------------------------------------- */
 
@@ -1456,8 +1473,9 @@ static void fmm_push(fmm_pairs *l, int64_t a, int64_t b)
 
 typedef struct {
     const tree_data *d;
+    tree_ctx tc; /* the tree code's opening test on the same moments */
     double theta2;
-    fmm_pairs m2l, p2p;
+    fmm_pairs m2l, m2p, p2p;
 } fmm_ctx;
 
 static int fmm_mac(const fmm_ctx *f, int64_t a, int64_t b)
@@ -1481,6 +1499,10 @@ static void fmm_interact(fmm_ctx *f, int64_t a, int64_t b)
     const int64_t *nodes = f->d->nodes;
     const int64_t al = nodes[4 * a + 2], ar = nodes[4 * a + 3];
     const int64_t bl = nodes[4 * b + 2], br = nodes[4 * b + 3];
+    if (al < 0 && tree_accept(&f->tc, b, a)) {
+        fmm_push(&f->m2p, a, b);
+        return;
+    }
     if (al < 0 && bl < 0) {
         fmm_push(&f->p2p, a, b);
         return;
@@ -1525,8 +1547,9 @@ static int fmm_run(int64_t n, int32_t leaf, const double *x, const double *m, do
         return -1;
     f->d = d;
     f->theta2 = theta * theta;
+    f->tc = (tree_ctx){d->nodes, d->com, d->lo, d->hi, d->diag2, f->theta2};
     fmm_interact(f, 0, 0);
-    if (f->m2l.fail || f->p2p.fail) {
+    if (f->m2l.fail || f->m2p.fail || f->p2p.fail) {
         tree_free(d);
         return -1;
     }
@@ -1537,43 +1560,41 @@ static void fmm_ctx_free(fmm_ctx *f)
 {
     free(f->m2l.a);
     free(f->m2l.b);
+    free(f->m2p.a);
+    free(f->m2p.b);
     free(f->p2p.a);
     free(f->p2p.b);
 }
 
 /* The FMM's lists grouped by target node (node ids in preorder):
- * m2l_cnt/p2p_cnt [nn]; m2l/p2p the source node ids of every target in
- * traversal order, targets in node order (NULL to count only; capacities
- * m2l_cap/p2p_cap).  Returns 0, or -1 on bad arguments or a list longer than
- * its capacity. */
+ * m2l_cnt/m2p_cnt/p2p_cnt [nn]; m2l/m2p/p2p the source node ids of every
+ * target in traversal order, targets in node order (NULL to count only;
+ * capacities m2l_cap/m2p_cap/p2p_cap).  Returns 0, or -1 on bad arguments or
+ * a list longer than its capacity. */
 int oracle_fmm_lists(int64_t n, int32_t leaf, const double *x, const double *m, double theta, int64_t *m2l_cnt,
-                     int64_t *p2p_cnt, int32_t *m2l, int64_t m2l_cap, int32_t *p2p, int64_t p2p_cap)
+                     int64_t *m2p_cnt, int64_t *p2p_cnt, int32_t *m2l, int64_t m2l_cap, int32_t *m2p,
+                     int64_t m2p_cap, int32_t *p2p, int64_t p2p_cap)
 {
     tree_data d;
     fmm_ctx f;
-    if (!m2l_cnt || !p2p_cnt || fmm_run(n, leaf, x, m, theta, &d, &f) != 0)
+    if (!m2l_cnt || !m2p_cnt || !p2p_cnt || fmm_run(n, leaf, x, m, theta, &d, &f) != 0)
         return -1;
     int rc = 0;
     int64_t *start = (int64_t *)malloc((size_t)d.nn * sizeof(int64_t));
-    int32_t *tmp = (int32_t *)malloc((size_t)(f.m2l.n + f.p2p.n + 1) * sizeof(int32_t));
+    int32_t *tmp = (int32_t *)malloc((size_t)(f.m2l.n + f.m2p.n + f.p2p.n + 1) * sizeof(int32_t));
     if (!start || !tmp)
         rc = -1;
-    if (rc == 0) {
-        rc |= fmm_by_target(&f.m2l, d.nn, m2l_cnt, start, tmp);
-        if (rc == 0 && m2l) {
-            if (f.m2l.n > m2l_cap)
+    const fmm_pairs *lists[3] = {&f.m2l, &f.m2p, &f.p2p};
+    int64_t *cnts[3] = {m2l_cnt, m2p_cnt, p2p_cnt};
+    int32_t *outs[3] = {m2l, m2p, p2p};
+    const int64_t caps[3] = {m2l_cap, m2p_cap, p2p_cap};
+    for (int w = 0; w < 3 && rc == 0; ++w) {
+        rc |= fmm_by_target(lists[w], d.nn, cnts[w], start, tmp);
+        if (rc == 0 && outs[w]) {
+            if (lists[w]->n > caps[w])
                 rc = -1;
             else
-                memcpy(m2l, tmp, (size_t)f.m2l.n * sizeof(int32_t));
-        }
-    }
-    if (rc == 0) {
-        rc |= fmm_by_target(&f.p2p, d.nn, p2p_cnt, start, tmp);
-        if (rc == 0 && p2p) {
-            if (f.p2p.n > p2p_cap)
-                rc = -1;
-            else
-                memcpy(p2p, tmp, (size_t)f.p2p.n * sizeof(int32_t));
+                memcpy(outs[w], tmp, (size_t)lists[w]->n * sizeof(int32_t));
         }
     }
     free(start);
@@ -1600,10 +1621,15 @@ int oracle_fmm_accel(int64_t n, int32_t leaf, const double *x, const double *m, 
     int64_t *pcnt = (int64_t *)malloc((size_t)nn * sizeof(int64_t));
     int64_t *pstart = (int64_t *)malloc((size_t)nn * sizeof(int64_t));
     int32_t *psrc = (int32_t *)malloc((size_t)(f.p2p.n + 1) * sizeof(int32_t));
+    int64_t *ccnt = (int64_t *)malloc((size_t)nn * sizeof(int64_t));
+    int64_t *cstart = (int64_t *)malloc((size_t)nn * sizeof(int64_t));
+    int32_t *csrc = (int32_t *)malloc((size_t)(f.m2p.n + 1) * sizeof(int32_t));
     int64_t *leaf_of = (int64_t *)malloc((size_t)n * sizeof(int64_t));
-    int rc = (Q && own && tot && pcnt && pstart && psrc && leaf_of) ? 0 : -1;
+    int rc = (Q && own && tot && pcnt && pstart && psrc && ccnt && cstart && csrc && leaf_of) ? 0 : -1;
     if (rc == 0)
         rc = fmm_by_target(&f.p2p, nn, pcnt, pstart, psrc);
+    if (rc == 0)
+        rc = fmm_by_target(&f.m2p, nn, ccnt, cstart, csrc);
     if (rc == 0) {
         tree_quad_fill(&d, x, m, Q);
         /* M2L in traversal order */
@@ -1642,6 +1668,10 @@ int oracle_fmm_accel(int64_t n, int32_t leaf, const double *x, const double *m, 
             nsum ax = {0, 0}, ay = {0, 0}, az = {0, 0}, ph = {0, 0};
             const double y[3] = {xi - za[0], yi - za[1], zi - za[2]};
             local_l2p_add(tot + 20 * a, y, &ax, &ay, &az, &ph);
+            for (int64_t q = cstart[a]; q < cstart[a] + ccnt[a]; ++q) {
+                const int64_t b = csrc[q];
+                quad_cell_add(xi, yi, zi, d.com + 3 * b, d.mass[b], Q + 6 * b, eps2, &ax, &ay, &az, &ph);
+            }
             for (int64_t q = pstart[a]; q < pstart[a] + pcnt[a]; ++q) {
                 const int64_t b = psrc[q];
                 for (int64_t j = d.nodes[4 * b]; j < d.nodes[4 * b + 1]; ++j) {
@@ -1675,6 +1705,9 @@ int oracle_fmm_accel(int64_t n, int32_t leaf, const double *x, const double *m, 
     free(pcnt);
     free(pstart);
     free(psrc);
+    free(ccnt);
+    free(cstart);
+    free(csrc);
     free(leaf_of);
     fmm_ctx_free(&f);
     tree_free(&d);

@@ -1,12 +1,17 @@
 """Pins of the oracle's multi-level fast multipole method on the ORB nodes
 (the O(N) method Section VI points to): quadrupole cells, third-order local
-expansions, L2L down the tree, P2P between leaves.
+expansions, L2L down the tree, M2P cells and P2P leaves at the leaves.
 
-* theta = 0: no M2L entry, and the result is the direct sum.
+* theta = 0: no M2L or M2P entry, and the result is the direct sum.
 * The dual-tree traversal counts every ordered pair of distinct bodies
   exactly once (brute force over all pairs), every M2L entry passes the
-  acceptance test and every P2P entry is a pair of leaves that fails it
-  (the test recomputed here from the node moments).
+  acceptance test, every M2P entry is a leaf target for which the source
+  fails it but passes the tree code's box test, and every P2P entry is a
+  pair of leaves that fails both (the tests recomputed here from the node
+  moments).
+* A leaf of a few far-flung bodies gets a short list of M2P cells instead
+  of a P2P entry with every leaf, and its bodies' forces stay within the
+  quadrupole cells' error of the direct sum.
 * L2L: the re-expanded cubic equals the original at every point (the
   Taylor polynomial evaluated here from its definition).
 * Far-field order: for two clusters at distance D the force error of one
@@ -32,7 +37,7 @@ def test_theta_zero_is_the_direct_sum(orc):
         pm, _ = ics.plummer(max(n, 2), 70 + n)
         q = _orb(orc, pm[:n], leaf)
         L = orc.fmm_lists(q, leaf, 0.0)
-        assert L["m2l_cnt"].sum() == 0
+        assert L["m2l_cnt"].sum() == 0 and L["m2p_cnt"].sum() == 0
         a, p = orc.fmm_accel(q, leaf, 0.0, 0.01)
         if n == 1:
             assert np.all(a == 0) and np.all(p == 0)
@@ -54,11 +59,20 @@ def test_every_pair_counted_once_and_lists_follow_the_tests(orc, n, leaf, theta,
     cov = np.zeros((n, n), dtype=np.int64)
     th2 = theta * theta
 
+    def overlap(a, b):
+        return nodes[a, 0] < nodes[b, 1] and nodes[b, 0] < nodes[a, 1]
+
     def mac(a, b):
-        if nodes[a, 0] < nodes[b, 1] and nodes[b, 0] < nodes[a, 1]:
+        if overlap(a, b):
             return False
         d = mom["com"][a] - mom["com"][b]
         return mom["diag2"][a] + mom["diag2"][b] < th2 * float(d @ d)
+
+    def box_test(a, b):  # source b against the box of target a
+        if overlap(a, b):
+            return False
+        gap = np.maximum(mom["lo"][a] - mom["com"][b], 0) + np.maximum(mom["com"][b] - mom["hi"][a], 0)
+        return mom["diag2"][b] < th2 * float(gap @ gap)
 
     o = 0
     for a in range(nodes.shape[0]):
@@ -68,10 +82,18 @@ def test_every_pair_counted_once_and_lists_follow_the_tests(orc, n, leaf, theta,
         o += L["m2l_cnt"][a]
     o = 0
     for a in range(nodes.shape[0]):
+        if L["m2p_cnt"][a]:
+            assert nodes[a, 2] < 0
+        for b in L["m2p"][o:o + L["m2p_cnt"][a]]:
+            assert not mac(a, b) and box_test(a, b)
+            cov[nodes[a, 0]:nodes[a, 1], nodes[b, 0]:nodes[b, 1]] += 1
+        o += L["m2p_cnt"][a]
+    o = 0
+    for a in range(nodes.shape[0]):
         if L["p2p_cnt"][a]:
             assert nodes[a, 2] < 0
         for b in L["p2p"][o:o + L["p2p_cnt"][a]]:
-            assert nodes[b, 2] < 0 and not mac(a, b)
+            assert nodes[b, 2] < 0 and not mac(a, b) and not box_test(a, b)
             cov[nodes[a, 0]:nodes[a, 1], nodes[b, 0]:nodes[b, 1]] += 1
         o += L["p2p_cnt"][a]
     off = ~np.eye(n, dtype=bool)
@@ -134,7 +156,7 @@ def test_far_field_order(orc):
         x = np.vstack([A, B + [D, 0, 0]])
         q = _orb(orc, np.hstack([x, m[:, None]]), 20)
         L = orc.fmm_lists(q, 20, 0.9)
-        assert L["m2l_cnt"].sum() == 2 and L["p2p_cnt"].sum() == 2
+        assert L["m2l_cnt"].sum() == 2 and L["p2p_cnt"].sum() == 2 and L["m2p_cnt"].sum() == 0
         a, p = orc.fmm_accel(q, 20, 0.9, 0.0)
         ad, pd = orc.accel(q, 0.0)
         errs.append(np.sqrt(np.mean(np.sum((a - ad) ** 2, axis=1))))
@@ -149,3 +171,39 @@ def test_accuracy_improves_with_theta(orc):
     e = [rms_rel(orc.fmm_accel(q, 8, th, 0.01)[0], ad) for th in (0.25, 0.45, 0.7)]
     assert e[0] < e[1] < e[2]
     assert e[0] < 2e-4 and e[2] < 2e-2
+
+
+def test_far_flung_leaf_takes_cells_not_every_leaf(orc):
+    """A dense ball of 2000 bodies and 8 bodies strung along the x axis from
+    20 to 60.  ORB puts the 8 in one leaf whose box is far larger than its
+    distance to the ball, so it fails the FMM's test against every node;
+    through M2P it still sees the ball as cells, not leaf by leaf, and its
+    bodies' forces stay within the quadrupole cells' error."""
+    g = np.random.default_rng(17)
+    v = g.normal(size=(2000, 3))
+    v /= np.linalg.norm(v, axis=1)[:, None]
+    ball = v * g.uniform(size=(2000, 1)) ** (1 / 3)
+    line = np.column_stack([np.linspace(20, 60, 8), g.normal(0, 0.5, (8, 2))])
+    x = np.vstack([ball, line])
+    pm = np.hstack([x, g.uniform(0.5, 1.5, (x.shape[0], 1))]).astype(np.float32)
+    leaf = 8
+    perm = orc.orb_order(pm, leaf)
+    q = widen32(pm[perm])
+    far = np.nonzero(np.linalg.norm(q[:, :3], axis=1) > 20)[0]
+    assert far.size == 8 and far.max() - far.min() == 7  # one leaf
+    nodes = orc.tree_nodes(q.shape[0], leaf)
+    A = int(np.nonzero((nodes[:, 0] == far.min()) & (nodes[:, 2] < 0))[0][0])
+    theta = 0.5
+    L = orc.fmm_lists(q, leaf, theta)
+    off = lambda c, a: int(c[:a].sum())
+    m2p = L["m2p"][off(L["m2p_cnt"], A):off(L["m2p_cnt"], A) + L["m2p_cnt"][A]]
+    p2p = L["p2p"][off(L["p2p_cnt"], A):off(L["p2p_cnt"], A) + L["p2p_cnt"][A]]
+    assert L["m2l_cnt"][A] == 0 and len(m2p) > 0
+    nleaves = int((nodes[:, 2] < 0).sum())
+    assert len(p2p) + len(m2p) < nleaves / 4, (len(p2p), len(m2p), nleaves)
+    # the M2P cells hold most of the ball
+    ball_in_cells = int(sum(nodes[b, 1] - nodes[b, 0] for b in m2p))
+    assert ball_in_cells > 1500
+    a, _ = orc.fmm_accel(q, leaf, theta, 0.0, targets=far)
+    ad, _ = orc.accel(q, 0.0, targets=far)
+    assert rms_rel(a, ad) < 1e-3

@@ -98,6 +98,11 @@ MUTANTS = [
      "return d->diag2[a] + d->diag2[b] < f->theta2 * dist2;", "return d->diag2[b] < f->theta2 * dist2;"),
     ("FMM: parent expansion not passed down", ["tests/test_oracle_fmm.py"],
      "tot[20 * c + k] = nsum_val(&own[20 * c + k]) + sh[k];", "tot[20 * c + k] = nsum_val(&own[20 * c + k]);"),
+    ("FMM: M2P cells left out of the force", ["tests/test_oracle_fmm.py"],
+     "                quad_cell_add(xi, yi, zi, d.com + 3 * b, d.mass[b], Q + 6 * b, eps2, &ax, &ay, &az, &ph);",
+     "                (void)b;"),
+    ("FMM: M2P offered to inner targets", ["tests/test_oracle_fmm.py"],
+     "if (al < 0 && tree_accept(&f->tc, b, a)) {", "if (tree_accept(&f->tc, b, a)) {"),
     ("FMM: self pair kept in P2P", ["tests/test_oracle_fmm.py"],
      "                    if (j == i)\n                        continue;\n                    const double dx = x[3 * j] - xi;\n"
      "                    const double dy = x[3 * j + 1] - yi;\n                    const double dzz",
