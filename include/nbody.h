@@ -404,33 +404,37 @@ int nbody_tree_leapfrog(void *pos_mass, void *vel, void *acc_pot, int32_t *order
  *   MAC:       target node A and source node B interact through M2L iff they
  *              share no body and diag2_A + diag2_B < theta^2 |com_A - com_B|^2
  *              (FP64, as in the group local expansions).
- *   traversal: from (root, root): MAC -> B joins A's M2L list; both leaves ->
- *              B joins A's P2P list; B a leaf, or A an inner node with diag2_A
- *              >= diag2_B -> (A.left, B), (A.right, B); else (A, B.left),
- *              (A, B.right).
+ *   traversal: from (root, root): MAC -> B joins A's M2L list; A a leaf and
+ *              B accepted by the tree code's opening test against A's box
+ *              (diag2_B < theta^2 D2, D2 the squared distance from com_B to
+ *              the box) -> B joins A's M2P list; both leaves -> B joins A's
+ *              P2P list; B a leaf, or A an inner node with diag2_A >= diag2_B
+ *              -> (A.left, B), (A.right, B); else (A, B.left), (A, B.right).
  *   M2L:       B's quadrupole potential as a third-order Taylor expansion
  *              about com_A (as NBODY_CELLS_LOCAL), FP32, summed over A's list.
  *   L2L:       a node's expansion = its own M2L sum + its parent's expansion
  *              re-expanded about its centre (exact for a cubic), FP64.
- *   L2P, P2P:  every body of a leaf evaluates the leaf's expansion (FP64) and
- *              sums its P2P source leaves body by body with the FP32 pair code,
- *              partials folded by prec.
- * theta = 0 gives no M2L entry: the direct sum, at a P2P cost of (n/leaf)^2
- * leaf pairs.  List buffers are library-owned and grow as needed; each call
- * synchronises its stream once to check them.
+ *   L2P, M2P, P2P: every body of a leaf evaluates the leaf's expansion
+ *              (FP64), its M2P cells as quadrupole cells (as
+ *              NBODY_CELLS_QUAD) and its P2P source leaves body by body, with
+ *              FP32 arithmetic; each lane's FP32 partial sums are folded by
+ *              prec.
+ * theta = 0 gives no M2L or M2P entry: the direct sum, at a P2P cost of
+ * (n/leaf)^2 leaf pairs.  List buffers are library-owned and grow as needed;
+ * each call synchronises its stream once to check them.
  * nbody_fmm_accel: acc_pot_out = n float4 (ax, ay, az, phi) in ORB order.
- * nbody_fmm_lists (inspection, synchronous): m2l_cnt, p2p_cnt = int32[num
- *   nodes] list lengths per target node; m2l_ids, p2p_ids (may be NULL) the
- *   source node ids, target nodes in id order, each target's entries in
- *   the device walk's fixed order (as sets they are the recursion's lists);
- *   NBODY_E_INVAL if a list exceeds its capacity.  All arrays are device
- *   memory.
+ * nbody_fmm_lists (inspection, synchronous): m2l_cnt, m2p_cnt, p2p_cnt =
+ *   int32[num nodes] list lengths per target node; m2l_ids, m2p_ids, p2p_ids
+ *   (may be NULL) the source node ids, target nodes in id order, each
+ *   target's entries in the device walk's fixed order (as sets they are the
+ *   recursion's lists); NBODY_E_INVAL if a list exceeds its capacity.  All
+ *   arrays are device memory.
  */
 int nbody_fmm_accel(const void *pos_mass, int64_t n, int32_t prec, double G, double eps, double theta,
                     int32_t leaf, void *acc_pot_out, void *stream);
 int nbody_fmm_lists(const void *pos_mass, int64_t n, int32_t leaf, double theta, int32_t *m2l_cnt,
-                    int32_t *p2p_cnt, int32_t *m2l_ids, int64_t m2l_cap, int32_t *p2p_ids, int64_t p2p_cap,
-                    void *stream);
+                    int32_t *m2p_cnt, int32_t *p2p_cnt, int32_t *m2l_ids, int64_t m2l_cap, int32_t *m2p_ids,
+                    int64_t m2p_cap, int32_t *p2p_ids, int64_t p2p_cap, void *stream);
 
 /*
  * Bit-reversible kick-drift-kick and its checkpoint-free adjoint (the

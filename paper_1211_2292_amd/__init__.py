@@ -67,7 +67,7 @@ _SIGS = {
     "nbody_tree_shape": [_i64, _i32, _vp, _vp, _vp],
     "nbody_tree_accel": [_vp, _i64, _i32, _dbl, _dbl, _dbl, _i32, _vp, _vp],
     "nbody_fmm_accel": [_vp, _i64, _i32, _dbl, _dbl, _dbl, _i32, _vp, _vp],
-    "nbody_fmm_lists": [_vp, _i64, _i32, _dbl, _vp, _vp, _vp, _i64, _vp, _i64, _vp],
+    "nbody_fmm_lists": [_vp, _i64, _i32, _dbl, _vp, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _i64, _vp],
     "nbody_tree_accel_cells": [_vp, _i64, _i32, _dbl, _dbl, _dbl, _i32, _i32, _vp, _vp],
     "nbody_tree_pseudo": [_vp, _i64, _i32, _vp, _vp],
     "nbody_tree_quad": [_vp, _i64, _i32, _vp, _vp],
@@ -381,21 +381,22 @@ def fmm_accel(pos_mass, eps, theta, leaf=8, G=1.0, prec=None, out=None):
 
 @_on_device
 def fmm_lists(pos_mass, theta, leaf=8):
-    """The FMM's lists: (m2l_count, p2p_count) int32 (num_nodes,) and the
-    concatenated source node ids (m2l, p2p), target nodes in id order, each
-    target's sources in the device walk's fixed order."""
+    """The FMM's lists: (m2l_count, m2p_count, p2p_count) int32 (num_nodes,)
+    and the concatenated source node ids (m2l, m2p, p2p), target nodes in id
+    order, each target's sources in the device walk's fixed order."""
     pm = _rec(pos_mass, "pos_mass", torch.float32)
     nn, _ = tree_shape(pm.shape[0], leaf)
-    mc = torch.empty(nn, dtype=torch.int32, device=pm.device)
-    pc = torch.empty(nn, dtype=torch.int32, device=pm.device)
-    _check(lib().nbody_fmm_lists(_ptr(pm), pm.shape[0], int(leaf), float(theta), _ptr(mc), _ptr(pc), None, 0,
-                                 None, 0, _stream()))
-    nm, npp = int(mc.sum()), int(pc.sum())
-    m2l = torch.empty(max(nm, 1), dtype=torch.int32, device=pm.device)
-    p2p = torch.empty(max(npp, 1), dtype=torch.int32, device=pm.device)
-    _check(lib().nbody_fmm_lists(_ptr(pm), pm.shape[0], int(leaf), float(theta), _ptr(mc), _ptr(pc), _ptr(m2l),
-                                 m2l.shape[0], _ptr(p2p), p2p.shape[0], _stream()))
-    return mc, pc, m2l[:nm], p2p[:npp]
+    cnt = [torch.empty(nn, dtype=torch.int32, device=pm.device) for _ in range(3)]
+    _check(lib().nbody_fmm_lists(_ptr(pm), pm.shape[0], int(leaf), float(theta), *(_ptr(c) for c in cnt),
+                                 None, 0, None, 0, None, 0, _stream()))
+    tot = [int(c.sum()) for c in cnt]
+    ids = [torch.empty(max(t, 1), dtype=torch.int32, device=pm.device) for t in tot]
+    args = []
+    for a in ids:
+        args += [_ptr(a), a.shape[0]]
+    _check(lib().nbody_fmm_lists(_ptr(pm), pm.shape[0], int(leaf), float(theta), *(_ptr(c) for c in cnt), *args,
+                                 _stream()))
+    return (*cnt, *(a[:t] for a, t in zip(ids, tot)))
 
 
 @_on_device

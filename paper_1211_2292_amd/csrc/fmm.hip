@@ -2,20 +2,24 @@
 //
 // Section VI names the fast multipole method (its reference [20]) as the O(N)
 // successor of the tree code.  Built here from the tree code's pieces: the
-// ORB nodes with their FP64 moments and quadrupole records (tree.hip), the
-// quadrupole cell's M2L into a third-order local expansion (m2l_f32), and
-// the FP32 pair code of the direct sum (pair.h).  Definitions shared with the
-// FP64 oracle (every node's lists are equal to the oracle's as sets):
+// ORB nodes with their FP64 moments, boxes and quadrupole records
+// (tree.hip), the quadrupole cell's evaluation at a body and its M2L into a
+// third-order local expansion (tree_shared.h), and the FP32 pair code of the
+// direct sum (pair.h).  Definitions shared with the FP64 oracle (every node's
+// lists are equal to the oracle's as sets):
 // * MAC: target node A and source node B interact through M2L iff they share
 //   no body and diag2_A + diag2_B < theta^2 |com_A - com_B|^2 (FP64).
-// * Dual-tree traversal from (root, root): MAC -> B joins A's M2L list; two
-//   leaves -> B joins A's P2P list; B a leaf, or A an inner node with
-//   diag2_A >= diag2_B -> the pair passes to both children of A; otherwise
-//   the pair is replaced by (A, B.left), (A, B.right).
+// * Dual-tree traversal from (root, root): MAC -> B joins A's M2L list; A a
+//   leaf and B accepted by the tree code's opening test against A's box
+//   (diag2_B < theta^2 D2, D2 the squared distance from com_B to the box) ->
+//   B joins A's M2P list; two leaves -> B joins A's P2P list; B a leaf, or A
+//   an inner node with diag2_A >= diag2_B -> the pair passes to both
+//   children of A; otherwise the pair is replaced by (A, B.left),
+//   (A, B.right).
 // * A node's total local expansion = its own M2L sum + its parent's total
 //   re-expanded about its centre of mass (exact for a cubic); every body of
-//   a leaf evaluates its leaf's expansion and sums its P2P source leaves body
-//   by body without the self pair.
+//   a leaf evaluates its leaf's expansion, its M2P cells as quadrupole cells
+//   and its P2P source leaves body by body without the self pair.
 //
 // Device schedule:
 // * Traversal, top-down by node depth.  For a target node A the pairs (A, .)
@@ -23,18 +27,18 @@
 //   pass-down list) closed under source splits: one wave per node pops up to
 //   64 pending sources per step from an LDS stack, one per lane, and
 //   classifies them (ballot ranks give every output a fixed position).  Each
-//   depth runs three kernels: count, scan (offsets, one workgroup), fill.
-//   Lists live in library buffers; writes are bounds-checked and an overflow
-//   flag makes the host grow the buffers and run again.
+//   depth runs a count walk, a two-kernel scan (block sums, then offsets)
+//   and a fill walk.  Lists live in library buffers; writes are
+//   bounds-checked and an overflow flag makes the host grow the buffers and
+//   run again.
 // * M2L: one wave per node, one source cell per lane, the twenty
 //   coefficients summed over the wave in a fixed butterfly (FP32).
 // * L2L: one thread per node, depth by depth, in FP64.
-// * Leaves: one wave per leaf, 64 / P lanes per target (P the leaf size
-//   rounded up to a power of two).  The P2P source leaves are staged in LDS
-//   in batches of up to 512 bodies and swept with the direct kernel's pair
-//   code (partials folded by the precision mode once per batch), then a
-//   fixed butterfly over the target's lanes and the FP64 evaluation of the
-//   leaf's expansion.
+// * Leaves: one wave per leaf.  Each lane holds up to 8 of the leaf's
+//   targets in registers and takes one source body (P2P) or cell (M2P) at a
+//   time, so one load serves up to 8 pairs.  The lanes' FP32 partial sums are
+//   folded by the precision mode in lane order through LDS, then each target
+//   adds its leaf's expansion in FP64.
 #include <algorithm>
 #include <cstring>
 #include <mutex>
@@ -56,24 +60,43 @@ namespace {
 
 constexpr int kFmmStack = 64;     // bound on the tree height the traversal admits
 constexpr int kWalkStack = 2048;  // LDS stack entries per walking wave (64 per source depth + refill)
-constexpr int kTotWords = 3 + kFmmStack;  // list totals; node depth < tree height + 1 <= kFmmStack
+
+// List kinds; per-node counts and offsets are stored [kind][nn].
+constexpr int kM2L = 0, kP2P = 1, kM2P = 2, kPass = 3, kKinds = 4;
+// tot: [0] the overflow flag; for the three interaction lists the running
+// total before depth d at tot_at(kind, d); the pass-down total of depth d at
+// tot_at(kPass, d).
+constexpr int kRunStride = kFmmStack + 1;
+constexpr int kTotWords = 1 + kKinds * kRunStride;
+__host__ __device__ constexpr int tot_at(int kind, int d) { return 1 + kind * kRunStride + d; }
+
+constexpr int kScanBlock = 1024;  // positions per scan block (256 threads x 4)
 
 struct FmmDev {
     const int4 *node;
     const double4 *comd;
+    const float4 *lo, *hi;
     const float4 *qr;
     const int *parent;
     int nn;
-    int *cnt;   // [3][nn]: M2L, P2P, pass-down counts per node
-    int *lcnt;  // [3][nn]: the same counts at each node's position in depth order
-    int *off;   // [3][nn]: M2L and P2P offsets (global), pass-down offsets (in the level's buffer)
-    int *m2l, *p2p, *pass0, *pass1;
-    long cap_m2l, cap_p2p, cap_pass;
-    unsigned long long *tot;  // running M2L total, running P2P total, overflow flag, then the
-                              // pass-down total of every depth
+    int *cnt;   // [kKinds][nn] counts per node
+    int *lcnt;  // [kKinds][nn] the same counts at each node's position in depth order
+    int *off;   // [kKinds][nn] offsets (global; pass-down: in the depth's buffer)
+    int *m2l;   // source node ids
+    int *p2p;   // the first body of each source leaf
+    int *m2p;   // source node ids
+    int *pass0, *pass1;
+    long cap_m2l, cap_p2p, cap_m2p, cap_pass;
+    long *bsum;               // [blocks][kKinds] scan block sums
+    unsigned long long *tot;  // see tot_at
     float *own;               // [nn][20] own M2L sums
     double *loc;              // [nn][20] total expansions
 };
+
+__device__ __forceinline__ long cap_of(const FmmDev &F, int kind)
+{
+    return kind == kM2L ? F.cap_m2l : (kind == kP2P ? F.cap_p2p : (kind == kM2P ? F.cap_m2p : F.cap_pass));
+}
 
 __device__ __forceinline__ bool fmm_overlap(int4 a, int4 b) { return a.x < b.y && b.x < a.y; }
 
@@ -82,12 +105,22 @@ __device__ __forceinline__ unsigned fmm_rank(unsigned long long mask)
     return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
 }
 
+// Bounds-checked store of one list entry at base + rank among the lanes of
+// mask; returns false when it does not fit.
+__device__ __forceinline__ bool put_entry(int *list, long cap, long base, unsigned long long mask, int value)
+{
+    const long q = base + (long)fmm_rank(mask);
+    if (q >= cap) return false;
+    list[q] = value;
+    return true;
+}
+
 // One wave per target node of one depth: the walk of its inherited
 // sources.  The pending sources sit on an LDS stack; each step pops up to 64
-// of them (one per lane) and classifies each: M2L, P2P, pass-down (to both
-// children of A) or split (both children of B pushed).  Ballot ranks keep
-// every output in a fixed order, so the count pass (FILL = false) and the
-// fill pass (FILL = true, at the scanned offsets) produce the same lists.
+// of them (one per lane) and classifies each: M2L, M2P, P2P, pass-down (to
+// both children of A) or split (both children of B pushed).  Ballot ranks
+// keep every output in a fixed order, so the count pass (FILL = false) and
+// the fill pass (FILL = true, at the scanned offsets) produce the same lists.
 template <bool FILL>
 __global__ __launch_bounds__(64) void k_fmm_walk(FmmDev F, const int *__restrict__ ids, int first, int count,
                                                  int parity, double theta2)
@@ -100,24 +133,35 @@ __global__ __launch_bounds__(64) void k_fmm_walk(FmmDev F, const int *__restrict
     const int4 na = F.node[A];
     const double4 ca = F.comd[A];
     const bool aleaf = na.z < 0;
+    double bx0 = 0.0, by0 = 0.0, bz0 = 0.0, bx1 = 0.0, by1 = 0.0, bz1 = 0.0;  // A's box (M2P test)
+    if (aleaf) {
+        const float4 l = F.lo[A], h = F.hi[A];
+        bx0 = l.x;
+        by0 = l.y;
+        bz0 = l.z;
+        bx1 = h.x;
+        by1 = h.y;
+        bz1 = h.z;
+    }
     const int nn = F.nn;
     const int *in = nullptr;
     int nin = 1;
     if (A != 0) {
         const int P = F.parent[A];
-        nin = F.cnt[2 * nn + P];
-        const long base = F.off[2 * nn + P];
+        nin = F.cnt[kPass * nn + P];
+        const long base = F.off[kPass * nn + P];
         if (base + nin > F.cap_pass) nin = (int)max(0L, F.cap_pass - base);  // the parent's depth overflowed
         in = (parity ? F.pass0 : F.pass1) + base;  // the previous depth's buffer
     }
     int *pass_out = parity ? F.pass1 : F.pass0;
-    long om = 0, op = 0, opass = 0;
+    long om = 0, op = 0, oc = 0, oq = 0;
     if (FILL) {
-        om = F.off[A];
-        op = F.off[nn + A];
-        opass = F.off[2 * nn + A];
+        om = F.off[kM2L * nn + A];
+        op = F.off[kP2P * nn + A];
+        oc = F.off[kM2P * nn + A];
+        oq = F.off[kPass * nn + A];
     }
-    int cm = 0, cp = 0, cq = 0, top = 0, next = 0;
+    int cm = 0, cp = 0, cc = 0, cq = 0, top = 0, next = 0;
     bool bad = false;
     for (;;) {
         if (top < 64 && next < nin) {  // refill from the inherited list
@@ -134,17 +178,25 @@ __global__ __launch_bounds__(64) void k_fmm_walk(FmmDev F, const int *__restrict
         int B = act ? stk[top + lane] : 0;
         __syncthreads();
         if ((unsigned)B >= (unsigned)nn) B = 0;  // only after an overflow upstream
-        bool m2l = false, p2p = false, pass = false, split = false;
+        bool m2l = false, m2p = false, p2p = false, pass = false, split = false;
         int4 nb = make_int4(0, 0, -1, -1);
         if (act) {
             nb = F.node[B];
             const double4 cb = F.comd[B];
-            if (!fmm_overlap(na, nb)) {
+            const bool apart = !fmm_overlap(na, nb);
+            if (apart) {
                 const double dx = ca.x - cb.x, dy = ca.y - cb.y, dz = ca.z - cb.z;
                 const double dist2 = (dx * dx + dy * dy) + dz * dz;
                 m2l = ca.w + cb.w < theta2 * dist2;
             }
-            if (!m2l) {
+            if (!m2l && aleaf && apart) {
+                const double gx = box_gap(cb.x, bx0, bx1);
+                const double gy = box_gap(cb.y, by0, by1);
+                const double gz = box_gap(cb.z, bz0, bz1);
+                const double D2 = (gx * gx + gy * gy) + gz * gz;
+                m2p = cb.w < theta2 * D2;
+            }
+            if (!m2l && !m2p) {
                 const bool bleaf = nb.z < 0;
                 if (aleaf && bleaf)
                     p2p = true;
@@ -154,25 +206,16 @@ __global__ __launch_bounds__(64) void k_fmm_walk(FmmDev F, const int *__restrict
                     split = true;
             }
         }
-        const unsigned long long mm = __ballot(m2l), mp = __ballot(p2p), mq = __ballot(pass), ms = __ballot(split);
+        const unsigned long long mm = __ballot(m2l), mc = __ballot(m2p), mp = __ballot(p2p), mq = __ballot(pass),
+                                 ms = __ballot(split);
         if (FILL) {
-            if (m2l) {
-                const long q = om + cm + (long)fmm_rank(mm);
-                if (q < F.cap_m2l) F.m2l[q] = B;
-                else bad = true;
-            }
-            if (p2p) {  // a source leaf is stored as its first body
-                const long q = op + cp + (long)fmm_rank(mp);
-                if (q < F.cap_p2p) F.p2p[q] = nb.x;
-                else bad = true;
-            }
-            if (pass) {
-                const long q = opass + cq + (long)fmm_rank(mq);
-                if (q < F.cap_pass) pass_out[q] = B;
-                else bad = true;
-            }
+            if (m2l && !put_entry(F.m2l, F.cap_m2l, om + cm, mm, B)) bad = true;
+            if (m2p && !put_entry(F.m2p, F.cap_m2p, oc + cc, mc, B)) bad = true;
+            if (p2p && !put_entry(F.p2p, F.cap_p2p, op + cp, mp, nb.x)) bad = true;  // a leaf as its first body
+            if (pass && !put_entry(pass_out, F.cap_pass, oq + cq, mq, B)) bad = true;
         }
         cm += __popcll(mm);
+        cc += __popcll(mc);
         cp += __popcll(mp);
         cq += __popcll(mq);
         const int ns = __popcll(ms);
@@ -189,61 +232,113 @@ __global__ __launch_bounds__(64) void k_fmm_walk(FmmDev F, const int *__restrict
         __syncthreads();
     }
     if (!FILL && lane == 0) {
-        F.cnt[A] = cm;
-        F.cnt[nn + A] = cp;
-        F.cnt[2 * nn + A] = cq;
-        F.lcnt[first + t] = cm;
-        F.lcnt[nn + first + t] = cp;
-        F.lcnt[2 * nn + first + t] = cq;
+        const int c4[kKinds] = {cm, cp, cc, cq};
+#pragma unroll
+        for (int q = 0; q < kKinds; ++q) {
+            F.cnt[q * nn + A] = c4[q];
+            F.lcnt[q * nn + first + t] = c4[q];
+        }
     }
-    if (__ballot(bad) && lane == 0) atomicOr(&F.tot[2], 1ull);
+    if (__ballot(bad) && lane == 0) atomicOr(&F.tot[0], 1ull);
 }
 
-// One workgroup: exclusive scans of the three counts over one depth's nodes
-// (in the order of ids).  M2L and P2P offsets continue the running totals;
-// pass-down offsets start at 0 in the depth's buffer.  Each thread sums a
-// contiguous chunk, the 1024 chunk sums are scanned in LDS (Hillis-Steele),
-// and each thread writes its chunk's offsets.
-__global__ __launch_bounds__(1024) void k_fmm_scan(FmmDev F, const int *__restrict__ ids, int first, int count,
-                                                   int depth)
+// Sum over the wave of four values (fixed butterfly).
+__device__ __forceinline__ void wave_sum4(long (&s)[kKinds])
 {
-    __shared__ long part[2][3][1024];
-    const int tid = threadIdx.x;
-    const int per = (count + 1023) / 1024;
-    const int b = min(count, tid * per), e = min(count, b + per);
-    const int nn = F.nn;
-    const int *lc = F.lcnt + first;
-    long s[3] = {0, 0, 0};
-#pragma unroll 4
-    for (int k = b; k < e; ++k)
-        for (int q = 0; q < 3; ++q) s[q] += lc[q * nn + k];
-    for (int q = 0; q < 3; ++q) part[0][q][tid] = s[q];
+#pragma unroll
+    for (int q = 0; q < kKinds; ++q)
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) s[q] += __shfl_xor(s[q], o);
+}
+
+// Scan, first kernel: the four count sums of each block of kScanBlock
+// positions of one depth.
+__global__ __launch_bounds__(256) void k_fmm_scan_part(FmmDev F, int first, int count)
+{
+    __shared__ long red[4][kKinds];
+    const int tid = threadIdx.x, b = blockIdx.x, nn = F.nn;
+    long s[kKinds] = {0, 0, 0, 0};
+#pragma unroll
+    for (int r = 0; r < kScanBlock / 256; ++r) {
+        const int pos = b * kScanBlock + r * 256 + tid;
+        if (pos < count)
+#pragma unroll
+            for (int q = 0; q < kKinds; ++q) s[q] += F.lcnt[q * nn + first + pos];
+    }
+    wave_sum4(s);
+    if ((tid & 63) == 0)
+#pragma unroll
+        for (int q = 0; q < kKinds; ++q) red[tid >> 6][q] = s[q];
     __syncthreads();
-    int cur = 0;
-    for (int d = 1; d < 1024; d <<= 1) {  // inclusive scan of the chunk sums
-        for (int q = 0; q < 3; ++q)
-            part[cur ^ 1][q][tid] = part[cur][q][tid] + (tid >= d ? part[cur][q][tid - d] : 0L);
-        cur ^= 1;
-        __syncthreads();
+    if (tid < kKinds) F.bsum[(long)b * kKinds + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+}
+
+// Scan, second kernel: block b adds the sums of the blocks before it to the
+// running totals, scans its positions (4 contiguous per thread) and writes
+// every node's offsets; the last block stores the totals for the next depth
+// and raises the overflow flag when a list passes its capacity.
+__global__ __launch_bounds__(256) void k_fmm_scan_fin(FmmDev F, const int *__restrict__ ids, int first, int count,
+                                                      int depth, int nblk)
+{
+    __shared__ long wsum[4][kKinds];
+    __shared__ long bbase[kKinds];
+    const int tid = threadIdx.x, b = blockIdx.x, nn = F.nn;
+    const int lane = tid & 63, wv = tid >> 6;
+    if (wv == 0) {
+        long s[kKinds] = {0, 0, 0, 0};
+        for (int k = lane; k < b; k += 64)
+#pragma unroll
+            for (int q = 0; q < kKinds; ++q) s[q] += F.bsum[(long)k * kKinds + q];
+        wave_sum4(s);
+        if (lane == 0)
+#pragma unroll
+            for (int q = 0; q < kKinds; ++q) bbase[q] = (q < kPass ? (long)F.tot[tot_at(q, depth)] : 0L) + s[q];
     }
-    long o[3];
-    for (int q = 0; q < 3; ++q) {
-        const long base = q < 2 ? (long)F.tot[q] : 0L;
-        o[q] = base + part[cur][q][tid] - s[q];
-    }
-    __syncthreads();  // every thread has read the running totals
-    if (tid < 3) {
-        const long run = (tid < 2 ? (long)F.tot[tid] : 0L) + part[cur][tid][1023];
-        F.tot[tid < 2 ? tid : 3 + depth] = (unsigned long long)run;
-        const long cap = tid == 0 ? F.cap_m2l : (tid == 1 ? F.cap_p2p : F.cap_pass);
-        if (run > cap || run > (long)INT32_MAX) atomicOr(&F.tot[2], 1ull);
-    }
-    for (int k = b; k < e; ++k) {
-        const int A = ids[k];
-        for (int q = 0; q < 3; ++q) {
-            F.off[q * nn + A] = (int)min(o[q], (long)INT32_MAX);
-            o[q] += lc[q * nn + k];
+    const int p0 = b * kScanBlock + 4 * tid;
+    int v[4][kKinds];
+    long s[kKinds] = {0, 0, 0, 0};
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < kKinds; ++q) {
+            v[r][q] = p0 + r < count ? F.lcnt[q * nn + first + p0 + r] : 0;
+            s[q] += v[r][q];
         }
+    long inc[kKinds];
+#pragma unroll
+    for (int q = 0; q < kKinds; ++q) inc[q] = s[q];
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1)
+#pragma unroll
+        for (int q = 0; q < kKinds; ++q) {
+            const long y = __shfl_up(inc[q], d);
+            if (lane >= d) inc[q] += y;
+        }
+    if (lane == 63)
+#pragma unroll
+        for (int q = 0; q < kKinds; ++q) wsum[wv][q] = inc[q];
+    __syncthreads();
+    long o[kKinds];
+#pragma unroll
+    for (int q = 0; q < kKinds; ++q) {
+        long pre = bbase[q];
+        for (int w = 0; w < wv; ++w) pre += wsum[w][q];
+        o[q] = pre + inc[q] - s[q];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        if (p0 + r >= count) break;
+        const int A = ids[p0 + r];
+#pragma unroll
+        for (int q = 0; q < kKinds; ++q) {
+            F.off[q * nn + A] = (int)min(o[q], (long)INT32_MAX);
+            o[q] += v[r][q];
+        }
+    }
+    if (b == nblk - 1 && tid < kKinds) {
+        const long run = bbase[tid] + (wsum[0][tid] + wsum[1][tid]) + (wsum[2][tid] + wsum[3][tid]);
+        F.tot[tid < kPass ? tot_at(tid, depth + 1) : tot_at(kPass, depth)] = (unsigned long long)run;
+        if (run > cap_of(F, tid) || run > (long)INT32_MAX) atomicOr(&F.tot[0], 1ull);
     }
 }
 
@@ -253,8 +348,8 @@ __global__ __launch_bounds__(256) void k_fmm_m2l(FmmDev F, float eps2)
     const int A = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (A >= F.nn) return;
-    const int c = F.cnt[A];
-    const long o = F.off[A];
+    const int c = F.cnt[kM2L * F.nn + A];
+    const long o = F.off[kM2L * F.nn + A];
     const double4 ca = F.comd[A];
     const float zx = (float)ca.x, zy = (float)ca.y, zz = (float)ca.z;
     Local L;
@@ -341,98 +436,120 @@ __global__ __launch_bounds__(256) void k_fmm_l2l(FmmDev F, const int *__restrict
     for (int k = 10; k < 20; ++k) out[k] = c[k] + (double)own[k];
 }
 
-// Leaves: one wave per leaf; LPT lanes per target.  A P2P entry is the
-// first body of a source leaf (every leaf holds `leaf` bodies except the
-// last, which ends at n).  Lanes read the entries 64 at a time; every source
-// body is then loaded straight from memory (the sources of one leaf are
-// spatial neighbours, mostly cache hits) with the entry's base broadcast
-// from its lane, several loads in flight per lane, and swept with the
-// direct kernel's pair code.
-template <int MODE, int LPT>
+// Leaves: one wave per leaf.  The leaf's P = TPL * NTG target slots (its
+// size rounded up to a power of two) form NTG groups of TPL targets; the
+// LG = 64 / NTG lanes of a group hold its targets in registers and share its
+// sources out, one per lane at a time:
+// * P2P: up to 64 entries are read at once (a source leaf is stored as its
+//   first body; every leaf holds `leaf` bodies except the last, which ends
+//   at n); their (entry, body) pairs are numbered e * 2^lb + body and lane v
+//   of a group takes v, v + LG, ... (the entry's first body read from the
+//   lane that loaded it).  The leaf's own entry is swept apart with the self
+//   pair masked.
+// * M2P: lane v takes cells v, v + LG, ... as quadrupole cells.
+// * Each lane's FP32 partial sums are folded by the precision mode over the
+//   group's lanes in lane order (through LDS); each target then adds its
+//   leaf's expansion in FP64 and is stored.
+template <int MODE, int TPL, int NTG>
 __global__ __launch_bounds__(64) void k_fmm_leaf(const float4 *__restrict__ src, FmmDev F,
                                                  const int *__restrict__ leaves, int nleaves, float eps2_in,
-                                                 double G, float4 *__restrict__ out, int n, int leaf)
+                                                 double G, float4 *__restrict__ out, int n, int leaf, int lb)
 {
-    constexpr int P = 64 / LPT;                  // target slots (>= the leaf size)
-    constexpr int BPL = P >= LPT ? P / LPT : 1;  // bodies of one entry per lane
-    constexpr int EPS = P >= LPT ? 1 : LPT / P;  // entries per step
-    constexpr int UNR = BPL >= 8 ? 1 : 8 / BPL;  // steps per unrolled block (8 loads in flight)
+    constexpr int P = TPL * NTG;
+    constexpr int LG = 64 / NTG;
+    constexpr int UNR = TPL >= 8 ? 2 : (TPL >= 4 ? 4 : 8);  // source loads in flight per lane
+    __shared__ float red[64][4 * TPL + 1];
+    __shared__ double fin[P][4];
     const int w = blockIdx.x;
-    const int lane = threadIdx.x;
     if (w >= nleaves) return;
+    const int lane = threadIdx.x;
+    const int g = lane / LG, v = lane % LG;
     const int A = leaves[w];
     const int4 na = F.node[A];
     const int nn = F.nn;
-    const int u = lane % LPT;
-    const int i = na.x + lane / LPT;
     const float eps2 = lane_copy(eps2_in);
-    Targets<float, 1> T;
-    {
-        const float4 p = src[min(i, na.y - 1)];
-        T.x[0] = p.x;
-        T.y[0] = p.y;
-        T.z[0] = p.z;
-        T.i[0] = i;
-    }
-    Run<MODE> R[4];
+    Targets<float, TPL> T;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) R[c].zero();
-    const int cp = F.cnt[nn + A];
-    const long op = F.off[nn + A];
+    for (int t = 0; t < TPL; ++t) {
+        const int i = na.x + g * TPL + t;
+        const float4 p = src[min(i, na.y - 1)];
+        T.x[t] = p.x;
+        T.y[t] = p.y;
+        T.z[t] = p.z;
+        T.i[t] = i;
+    }
+    Sums<float, TPL> S;
+    S.zero();
+    // P2P
+    const int cp = F.cnt[kP2P * nn + A];
+    const long op = F.off[kP2P * nn + A];
     const int cpc = (int)min((long)cp, max(0L, F.cap_p2p - op));
-    // lane's entry within a step and its body slot
-    const int esub = EPS > 1 ? u / P : 0;
-    const int b0 = EPS > 1 ? u % P : u;
+    const int bmask = (1 << lb) - 1;
+    bool self = false;
     for (int base = 0; base < cpc; base += 64) {
         const int k = min(64, cpc - base);
-        const int mybeg = lane < k ? F.p2p[op + base + lane] : 0;
-        Sums<float, 1> S;
-        S.zero();
-        for (int e0 = 0; e0 < k; e0 += EPS * UNR) {
-            float4 sv[UNR][BPL];
-            int sj[UNR][BPL];
-            bool ok[UNR][BPL];
+        const int mybeg = lane < k ? F.p2p[op + base + lane] : -1;
+        self = self || __ballot(mybeg == na.x) != 0ull;
+        const int npairs = k << lb;
+        for (int q0 = 0; q0 < npairs; q0 += LG * UNR) {
+            float4 sv[UNR];
+            int sj[UNR];
+            bool ok[UNR];
 #pragma unroll
             for (int r = 0; r < UNR; ++r) {
-                const int e = e0 + r * EPS + esub;
-                int bg;
-                if constexpr (EPS > 1)
-                    bg = __shfl(mybeg, min(e, 63));
-                else
-                    bg = __builtin_amdgcn_readlane(mybeg, min(e0 + r, 63));
-                const int len = (unsigned)bg < (unsigned)n ? min(leaf, n - bg) : 0;
-#pragma unroll
-                for (int q = 0; q < BPL; ++q) {
-                    const int body = b0 + q * LPT;
-                    ok[r][q] = e < k && body < len;
-                    sj[r][q] = bg + body;
-                    sv[r][q] = src[ok[r][q] ? sj[r][q] : 0];
-                }
+                const int q = q0 + r * LG + v;
+                const int bg = __shfl(mybeg, (q >> lb) & 63);
+                const int body = q & bmask;
+                const int len = ((unsigned)bg < (unsigned)n && bg != na.x) ? min(leaf, n - bg) : 0;
+                ok[r] = q < npairs && body < len;
+                sj[r] = bg + body;
+                sv[r] = src[ok[r] ? sj[r] : 0];
             }
 #pragma unroll
             for (int r = 0; r < UNR; ++r)
-#pragma unroll
-                for (int q = 0; q < BPL; ++q)
-                    if (ok[r][q]) pair_f32<1, true>(sv[r][q], sj[r][q], T, eps2, S);
+                if (ok[r]) pair_f32<TPL, false>(sv[r], sj[r], T, eps2, S);
         }
-        R[0].fold(S.ax[0]);
-        R[1].fold(S.ay[0]);
-        R[2].fold(S.az[0]);
-        R[3].fold(S.ph[0]);
     }
-    double r[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        double v = R[c].get();
-#pragma unroll
-        for (int s = LPT / 2; s >= 1; s >>= 1) v += __shfl_xor(v, s);
-        r[c] = v;
+    if (self) {  // the leaf's own bodies, without the self pair
+        for (int q = v; q < na.y - na.x; q += LG) pair_f32<TPL, true>(src[na.x + q], na.x + q, T, eps2, S);
     }
-    if (u != 0 || i >= na.y) return;
+    // M2P
+    const int cc = F.cnt[kM2P * nn + A];
+    const long oc = F.off[kM2P * nn + A];
+    const int ccc = (int)min((long)cc, max(0L, F.cap_m2p - oc));
+    for (int k = v; k < ccc; k += LG) {
+        const int B = F.m2p[oc + k];
+        if ((unsigned)B < (unsigned)nn) {
+            const float4 *rc = F.qr + (long)kQuadRec * B;
+            quad_f32<TPL>(rc[0], rc[1], rc[2], T, eps2, S);
+        }
+    }
+    // fold the group's lanes in lane order
+#pragma unroll
+    for (int t = 0; t < TPL; ++t) {
+        red[lane][4 * t] = S.ax[t];
+        red[lane][4 * t + 1] = S.ay[t];
+        red[lane][4 * t + 2] = S.az[t];
+        red[lane][4 * t + 3] = S.ph[t];
+    }
+    __syncthreads();
+    for (int s = lane; s < 4 * P; s += 64) {
+        const int slot = s >> 2, comp = s & 3;
+        const int gg = slot / TPL, t = slot % TPL;
+        Run<MODE> R;
+        R.zero();
+        for (int u = 0; u < LG; ++u) R.fold(red[gg * LG + u][4 * t + comp]);
+        fin[slot][comp] = R.get();
+    }
+    __syncthreads();
+    const int i = na.x + lane;
+    if (lane >= P || i >= na.y) return;
+    double r[4] = {fin[lane][0], fin[lane][1], fin[lane][2], fin[lane][3]};
     // the leaf's expansion at this body, in FP64
+    const float4 pt = src[i];
     const double *c = F.loc + 20L * A;
     const double4 ca = F.comd[A];
-    const double y[3] = {(double)T.x[0] - ca.x, (double)T.y[0] - ca.y, (double)T.z[0] - ca.z};
+    const double y[3] = {(double)pt.x - ca.x, (double)pt.y - ca.y, (double)pt.z - ca.z};
     double ky[3], ty[3][3], tyy[3];
     fmm_contract(c, y, ky, ty, tyy);
     r[0] += c[1] + ky[0] + 0.5 * tyy[0];
@@ -455,15 +572,17 @@ __global__ void k_fmm_zero_tot(unsigned long long *tot, int count)
 
 // ---- host side -----------------------------------------------------------------
 struct FmmPlan {
-    int n = 0, leaf = 0, dev = -1, nn = 0, depth = 0;
+    int n = 0, leaf = 0, dev = -1, nn = 0, depth = 0, max_level = 0;
     std::vector<int> parent, by_depth, depth_off;
     int *d_parent = nullptr, *d_by_depth = nullptr, *d_leaves = nullptr;
 };
 
 struct FmmBufs {
-    int dev = -1, nn = 0;
-    long cap_m2l = 0, cap_p2p = 0, cap_pass = 0;
-    int *cnt = nullptr, *lcnt = nullptr, *off = nullptr, *m2l = nullptr, *p2p = nullptr, *pass0 = nullptr, *pass1 = nullptr;
+    int dev = -1, nn = 0, nblk = 0;
+    long cap[kKinds] = {0, 0, 0, 0};
+    int *cnt = nullptr, *lcnt = nullptr, *off = nullptr, *list[3] = {nullptr, nullptr, nullptr};
+    int *pass0 = nullptr, *pass1 = nullptr;
+    long *bsum = nullptr;
     unsigned long long *tot = nullptr;
     float *own = nullptr;
     double *loc = nullptr;
@@ -486,10 +605,10 @@ void free_bufs(FmmBufs &b)
     (void)hipFree(b.cnt);
     (void)hipFree(b.lcnt);
     (void)hipFree(b.off);
-    (void)hipFree(b.m2l);
-    (void)hipFree(b.p2p);
+    for (int *l : b.list) (void)hipFree(l);
     (void)hipFree(b.pass0);
     (void)hipFree(b.pass1);
+    (void)hipFree(b.bsum);
     (void)hipFree(b.tot);
     (void)hipFree(b.own);
     (void)hipFree(b.loc);
@@ -521,7 +640,11 @@ int make_plan(const HostTree &h, int n, int leaf, int dev, hipStream_t s)
     p.depth = *std::max_element(dep.begin(), dep.end());
     p.depth_off.assign(p.depth + 2, 0);
     for (int v : dep) ++p.depth_off[v + 1];
-    for (int k = 0; k <= p.depth; ++k) p.depth_off[k + 1] += p.depth_off[k];
+    p.max_level = 0;
+    for (int k = 0; k <= p.depth; ++k) {
+        p.max_level = std::max(p.max_level, p.depth_off[k + 1]);
+        p.depth_off[k + 1] += p.depth_off[k];
+    }
     p.by_depth.assign(nn, 0);
     std::vector<int> pos(p.depth_off.begin(), p.depth_off.end() - 1);
     for (int a = 0; a < nn; ++a) p.by_depth[pos[dep[a]]++] = a;
@@ -550,42 +673,43 @@ int make_plan(const HostTree &h, int n, int leaf, int dev, hipStream_t s)
     return NBODY_OK;
 }
 
-// Buffers for nn nodes with at least the given list capacities.
-int make_bufs(int nn, int dev, long cap_m2l, long cap_p2p, long cap_pass)
+// Buffers for nn nodes (at most max_level on one depth) with at least the
+// given list capacities (M2L, P2P, M2P, pass-down).
+int make_bufs(int nn, int max_level, int dev, const long (&want)[kKinds])
 {
     FmmBufs &b = g_bufs;
-    if (b.cnt && b.dev == dev && b.nn >= nn && b.cap_m2l >= cap_m2l && b.cap_p2p >= cap_p2p &&
-        b.cap_pass >= cap_pass)
-        return NBODY_OK;
-    cap_m2l = std::max(cap_m2l, b.dev == dev ? b.cap_m2l : 0L);
-    cap_p2p = std::max(cap_p2p, b.dev == dev ? b.cap_p2p : 0L);
-    cap_pass = std::max(cap_pass, b.dev == dev ? b.cap_pass : 0L);
+    const int nblk = std::max(1, (max_level + kScanBlock - 1) / kScanBlock);
+    bool fits = b.cnt && b.dev == dev && b.nn >= nn && b.nblk >= nblk;
+    for (int q = 0; q < kKinds; ++q) fits = fits && b.cap[q] >= want[q];
+    if (fits) return NBODY_OK;
+    long cap[kKinds];
+    for (int q = 0; q < kKinds; ++q) cap[q] = std::max(want[q], b.dev == dev ? b.cap[q] : 0L);
     nn = std::max(nn, b.dev == dev ? b.nn : 0);
+    const int nb = std::max(nblk, b.dev == dev ? b.nblk : 0);
     if (b.cnt) {
         (void)hipDeviceSynchronize();
         free_bufs(b);
     }
-    bool ok = hipMalloc(&b.cnt, 3 * (size_t)nn * sizeof(int)) == hipSuccess &&
-              hipMalloc(&b.lcnt, 3 * (size_t)nn * sizeof(int)) == hipSuccess &&
-              hipMalloc(&b.off, 3 * (size_t)nn * sizeof(int)) == hipSuccess &&
-              hipMalloc(&b.m2l, (size_t)cap_m2l * sizeof(int)) == hipSuccess &&
-              hipMalloc(&b.p2p, (size_t)cap_p2p * sizeof(int)) == hipSuccess &&
-              hipMalloc(&b.pass0, (size_t)cap_pass * sizeof(int)) == hipSuccess &&
-              hipMalloc(&b.pass1, (size_t)cap_pass * sizeof(int)) == hipSuccess &&
-              hipMalloc(&b.tot, kTotWords * sizeof(unsigned long long)) == hipSuccess &&
-              hipMalloc(&b.own, 20 * (size_t)nn * sizeof(float)) == hipSuccess &&
-              hipMalloc(&b.loc, 20 * (size_t)nn * sizeof(double)) == hipSuccess;
+    const size_t per = kKinds * (size_t)nn * sizeof(int);
+    bool ok = hipMalloc(&b.cnt, per) == hipSuccess && hipMalloc(&b.lcnt, per) == hipSuccess &&
+              hipMalloc(&b.off, per) == hipSuccess;
+    for (int q = 0; q < 3 && ok; ++q) ok = hipMalloc(&b.list[q], (size_t)cap[q] * sizeof(int)) == hipSuccess;
+    ok = ok && hipMalloc(&b.pass0, (size_t)cap[kPass] * sizeof(int)) == hipSuccess &&
+         hipMalloc(&b.pass1, (size_t)cap[kPass] * sizeof(int)) == hipSuccess &&
+         hipMalloc(&b.bsum, (size_t)nb * kKinds * sizeof(long)) == hipSuccess &&
+         hipMalloc(&b.tot, kTotWords * sizeof(unsigned long long)) == hipSuccess &&
+         hipMalloc(&b.own, 20 * (size_t)nn * sizeof(float)) == hipSuccess &&
+         hipMalloc(&b.loc, 20 * (size_t)nn * sizeof(double)) == hipSuccess;
     if (!ok) {
         free_bufs(b);
-        set_error("cannot allocate FMM lists (%ld M2L, %ld P2P, %ld pass-down entries)", cap_m2l, cap_p2p,
-                  cap_pass);
+        set_error("cannot allocate FMM lists (%ld M2L, %ld P2P, %ld M2P, %ld pass-down entries)", cap[kM2L],
+                  cap[kP2P], cap[kM2P], cap[kPass]);
         return NBODY_E_NOMEM;
     }
     b.dev = dev;
     b.nn = nn;
-    b.cap_m2l = cap_m2l;
-    b.cap_p2p = cap_p2p;
-    b.cap_pass = cap_pass;
+    b.nblk = nb;
+    for (int q = 0; q < kKinds; ++q) b.cap[q] = cap[q];
     return NBODY_OK;
 }
 
@@ -594,19 +718,24 @@ FmmDev dev_view(const TreeDev &d, const FmmPlan &p, const FmmBufs &b)
     FmmDev F;
     F.node = d.node;
     F.comd = d.comd;
+    F.lo = d.lo;
+    F.hi = d.hi;
     F.qr = d.qr;
     F.parent = p.d_parent;
     F.nn = p.nn;
     F.cnt = b.cnt;
     F.lcnt = b.lcnt;
     F.off = b.off;
-    F.m2l = b.m2l;
-    F.p2p = b.p2p;
+    F.m2l = b.list[kM2L];
+    F.p2p = b.list[kP2P];
+    F.m2p = b.list[kM2P];
     F.pass0 = b.pass0;
     F.pass1 = b.pass1;
-    F.cap_m2l = b.cap_m2l;
-    F.cap_p2p = b.cap_p2p;
-    F.cap_pass = b.cap_pass;
+    F.cap_m2l = b.cap[kM2L];
+    F.cap_p2p = b.cap[kP2P];
+    F.cap_m2p = b.cap[kM2P];
+    F.cap_pass = b.cap[kPass];
+    F.bsum = b.bsum;
     F.tot = b.tot;
     F.own = b.own;
     F.loc = b.loc;
@@ -616,13 +745,15 @@ FmmDev dev_view(const TreeDev &d, const FmmPlan &p, const FmmBufs &b)
 // The traversal: count, scan and fill per depth.
 hipError_t launch_traversal(const FmmDev &F, const FmmPlan &p, double theta2, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_fmm_zero_tot, dim3(1), dim3(64), 0, s, F.tot, kTotWords);
+    hipLaunchKernelGGL(k_fmm_zero_tot, dim3(1), dim3(256), 0, s, F.tot, kTotWords);
     hipError_t e = hipGetLastError();
     for (int d = 0; d <= p.depth && e == hipSuccess; ++d) {
         const int first = p.depth_off[d], count = p.depth_off[d + 1] - first;
         const int *ids = p.d_by_depth + first;
+        const int nblk = (count + kScanBlock - 1) / kScanBlock;
         hipLaunchKernelGGL(k_fmm_walk<false>, dim3(count), dim3(64), 0, s, F, ids, first, count, d & 1, theta2);
-        hipLaunchKernelGGL(k_fmm_scan, dim3(1), dim3(1024), 0, s, F, ids, first, count, d);
+        hipLaunchKernelGGL(k_fmm_scan_part, dim3(nblk), dim3(256), 0, s, F, first, count);
+        hipLaunchKernelGGL(k_fmm_scan_fin, dim3(nblk), dim3(256), 0, s, F, ids, first, count, d, nblk);
         hipLaunchKernelGGL(k_fmm_walk<true>, dim3(count), dim3(64), 0, s, F, ids, first, count, d & 1, theta2);
         e = hipGetLastError();
     }
@@ -633,22 +764,29 @@ template <int MODE>
 hipError_t launch_leaves_mode(const float4 *pm, const FmmDev &F, const FmmPlan &p, int nleaves, int n, int leaf,
                               float eps2, double G, float4 *out, hipStream_t s)
 {
-    int P2 = 1;
-    while (P2 < leaf) P2 *= 2;
+    int lb = 0;
+    while ((1 << lb) < leaf) ++lb;
     const dim3 grid(nleaves), blk(64);
-#define NB_FMM_LEAF(L) \
-    hipLaunchKernelGGL((k_fmm_leaf<MODE, L>), grid, blk, 0, s, pm, F, p.d_leaves, nleaves, eps2, G, out, n, leaf)
-    switch (64 / P2) {
-    case 64: NB_FMM_LEAF(64); break;
-    case 32: NB_FMM_LEAF(32); break;
-    case 16: NB_FMM_LEAF(16); break;
-    case 8: NB_FMM_LEAF(8); break;
-    case 4: NB_FMM_LEAF(4); break;
-    case 2: NB_FMM_LEAF(2); break;
-    default: NB_FMM_LEAF(1); break;
+#define NB_FMM_LEAF(TPL, NTG)                                                                                  \
+    hipLaunchKernelGGL((k_fmm_leaf<MODE, TPL, NTG>), grid, blk, 0, s, pm, F, p.d_leaves, nleaves, eps2, G, out, \
+                       n, leaf, lb)
+    switch (lb) {
+    case 0: NB_FMM_LEAF(1, 1); break;
+    case 1: NB_FMM_LEAF(2, 1); break;
+    case 2: NB_FMM_LEAF(4, 1); break;
+    case 3: NB_FMM_LEAF(8, 1); break;
+    case 4: NB_FMM_LEAF(8, 2); break;
+    case 5: NB_FMM_LEAF(8, 4); break;
+    default: NB_FMM_LEAF(8, 8); break;
     }
 #undef NB_FMM_LEAF
     return hipGetLastError();
+}
+
+// Final list totals (M2L, P2P, M2P) after the deepest depth.
+void list_totals(const unsigned long long *tot, int depth, unsigned long long (&out)[3])
+{
+    for (int q = 0; q < 3; ++q) out[q] = tot[tot_at(q, depth + 1)];
 }
 
 // Runs the traversal (and, with out != nullptr, the whole FMM) until the
@@ -661,20 +799,21 @@ int fmm_run(const void *pm, int n, int prec, double G, double eps, double theta,
         set_error("hipGetDevice failed");
         return NBODY_E_HIP;
     }
+    if (leaf > 64) {
+        set_error("the FMM takes leaves of at most 64 bodies");
+        return NBODY_E_INVAL;
+    }
     NB_CHECK_RC(tree_quad_prepare(pm, n, leaf, s, d, h));
     NB_CHECK_RC(make_plan(*h, n, leaf, dev, s));
     const FmmPlan &p = g_plan;
     const int nn = p.nn;
     const int nleaves = (int)h->leaves.size();
-    long want_m2l = std::max(1024L, 64L * nn), want_p2p = std::max(1024L, 512L * nleaves);
-    long want_pass = std::max(1024L, 16L * nn);
-    if (g_bufs.dev == dev) {
-        want_m2l = std::max(want_m2l, g_bufs.cap_m2l);
-        want_p2p = std::max(want_p2p, g_bufs.cap_p2p);
-        want_pass = std::max(want_pass, g_bufs.cap_pass);
-    }
+    long want[kKinds] = {std::max(1024L, 64L * nn), std::max(1024L, 512L * nleaves), std::max(1024L, 16L * nleaves),
+                         std::max(1024L, 16L * nn)};
+    if (g_bufs.dev == dev)
+        for (int q = 0; q < kKinds; ++q) want[q] = std::max(want[q], g_bufs.cap[q]);
     for (int attempt = 0; attempt < 16; ++attempt) {
-        NB_CHECK_RC(make_bufs(nn, dev, want_m2l, want_p2p, want_pass));
+        NB_CHECK_RC(make_bufs(nn, p.max_level, dev, want));
         const FmmDev F = dev_view(d, p, g_bufs);
         hipError_t e = launch_traversal(F, p, theta * theta, s);
         if (e == hipSuccess && out) {
@@ -702,29 +841,30 @@ int fmm_run(const void *pm, int n, int prec, double G, double eps, double theta,
         e = hipMemcpyAsync(tot, g_bufs.tot, sizeof tot, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(e, "FMM list check");
-        if (!tot[2]) return NBODY_OK;
+        if (!tot[0]) return NBODY_OK;
         // Grow what overflowed and run again.  The totals are exact up to the
         // first depth whose pass-down list overflowed and short beyond it, so
         // every attempt makes at least one more depth exact.
-        unsigned long long pass_max = 0;
+        unsigned long long pass_max = 0, lt[3];
         bool pass_over = false;
         for (int dd = 0; dd <= p.depth; ++dd) {
-            pass_max = std::max(pass_max, tot[3 + dd]);
-            pass_over = pass_over || tot[3 + dd] > (unsigned long long)g_bufs.cap_pass;
+            pass_max = std::max(pass_max, tot[tot_at(kPass, dd)]);
+            pass_over = pass_over || tot[tot_at(kPass, dd)] > (unsigned long long)g_bufs.cap[kPass];
         }
+        list_totals(tot, p.depth, lt);
         auto grow = [](long cap, unsigned long long need, bool doubled) {
             long w = std::max(cap, (long)std::min<unsigned long long>(need + need / 4 + 1024, 1ull << 40));
             return doubled ? std::max(w, 2 * cap) : w;
         };
-        want_pass = grow(g_bufs.cap_pass, pass_max, pass_over);
-        want_m2l = grow(g_bufs.cap_m2l, tot[0], false);
-        want_p2p = grow(g_bufs.cap_p2p, tot[1], false);
-        if (want_m2l > (long)INT32_MAX || want_p2p > (long)INT32_MAX || want_pass > (long)INT32_MAX) {
-            set_error("FMM lists beyond 2^31 entries (M2L %llu, P2P %llu, pass-down %llu counted so far; "
-                      "theta too small for this n and leaf)",
-                      tot[0], tot[1], pass_max);
-            return NBODY_E_UNSUPPORTED;
-        }
+        want[kPass] = grow(g_bufs.cap[kPass], pass_max, pass_over);
+        for (int q = 0; q < 3; ++q) want[q] = grow(g_bufs.cap[q], lt[q], false);
+        for (int q = 0; q < kKinds; ++q)
+            if (want[q] > (long)INT32_MAX) {
+                set_error("FMM lists beyond 2^31 entries (M2L %llu, P2P %llu, M2P %llu, pass-down %llu counted so "
+                          "far; theta too small for this n and leaf)",
+                          lt[0], lt[1], lt[2], pass_max);
+                return NBODY_E_UNSUPPORTED;
+            }
     }
     set_error("FMM lists did not fit after repeated growth");
     return NBODY_E_NOMEM;
@@ -742,8 +882,8 @@ int fmm_accel(const void *pm, int n, int prec, double G, double eps, double thet
     return fmm_run(pm, n, prec, G, eps, theta, leaf, out, s, d, h);
 }
 
-int fmm_lists(const void *pm, int n, int leaf, double theta, int32_t *m2l_cnt, int32_t *p2p_cnt, int32_t *m2l_ids,
-              int64_t m2l_cap, int32_t *p2p_ids, int64_t p2p_cap, hipStream_t s)
+int fmm_lists(const void *pm, int n, int leaf, double theta, int32_t *const cnt_out[3], int32_t *const ids_out[3],
+              const int64_t caps[3], hipStream_t s)
 {
     std::lock_guard<std::mutex> lt(tree_mutex());
     std::lock_guard<std::mutex> lf(g_fmm_mu);
@@ -751,40 +891,44 @@ int fmm_lists(const void *pm, int n, int leaf, double theta, int32_t *m2l_cnt, i
     const HostTree *h = nullptr;
     NB_CHECK_RC(fmm_run(pm, n, NBODY_F32, 1.0, 0.0, theta, leaf, nullptr, s, d, h));
     const int nn = g_plan.nn;
-    std::vector<int> cnt(3 * (size_t)nn), off(3 * (size_t)nn);
-    unsigned long long tot[4];
+    std::vector<int> cnt(kKinds * (size_t)nn), off(kKinds * (size_t)nn);
+    unsigned long long tot[kTotWords], tl[3];
     hipError_t e = hipMemcpyAsync(cnt.data(), g_bufs.cnt, cnt.size() * sizeof(int), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(off.data(), g_bufs.off, off.size() * sizeof(int), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(tot, g_bufs.tot, sizeof tot, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "FMM list download");
-    std::vector<int> mc(cnt.begin(), cnt.begin() + nn), pc(cnt.begin() + nn, cnt.begin() + 2 * nn);
-    e = hipMemcpyAsync(m2l_cnt, mc.data(), nn * sizeof(int), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(p2p_cnt, pc.data(), nn * sizeof(int), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(e, "FMM count upload");
-    for (int which = 0; which < 2; ++which) {
-        int32_t *dst = which ? p2p_ids : m2l_ids;
+    list_totals(tot, g_plan.depth, tl);
+    // the public order is (M2L, M2P, P2P)
+    const int kind_of[3] = {kM2L, kM2P, kP2P};
+    for (int w = 0; w < 3; ++w) {
+        e = hipMemcpyAsync(cnt_out[w], cnt.data() + (size_t)kind_of[w] * nn, nn * sizeof(int), hipMemcpyHostToDevice,
+                           s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "FMM count upload");
+    }
+    for (int w = 0; w < 3; ++w) {
+        const int q = kind_of[w];
+        int32_t *dst = ids_out[w];
         if (!dst) continue;
-        const long total = (long)tot[which];
-        const int64_t cap = which ? p2p_cap : m2l_cap;
-        if (total > cap) {
-            set_error("%s list of %ld entries exceeds the capacity %lld", which ? "P2P" : "M2L", total,
-                      (long long)cap);
+        const long total = (long)tl[q];
+        if (total > caps[w]) {
+            static const char *names[3] = {"M2L", "M2P", "P2P"};
+            set_error("%s list of %ld entries exceeds the capacity %lld", names[w], total, (long long)caps[w]);
             return NBODY_E_INVAL;
         }
         std::vector<int> all(std::max(total, 1L)), grouped(std::max(total, 1L));
-        e = hipMemcpyAsync(all.data(), which ? g_bufs.p2p : g_bufs.m2l, total * sizeof(int), hipMemcpyDeviceToHost, s);
+        e = hipMemcpyAsync(all.data(), g_bufs.list[q], total * sizeof(int), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(e, "FMM list download");
         long o = 0;
         for (int a = 0; a < nn; ++a) {  // node order, each node's entries in walk order
-            const int c = cnt[(size_t)which * nn + a], b = off[(size_t)which * nn + a];
+            const int c = cnt[(size_t)q * nn + a], b = off[(size_t)q * nn + a];
             std::memcpy(grouped.data() + o, all.data() + b, (size_t)c * sizeof(int));
             o += c;
         }
-        if (which == 1)  // P2P entries hold the source leaf's first body: back to node ids
-            for (long q = 0; q < total; ++q) grouped[q] = h->leaves[grouped[q] / leaf];
+        if (q == kP2P)  // P2P entries hold the source leaf's first body: back to node ids
+            for (long k = 0; k < total; ++k) grouped[k] = h->leaves[grouped[k] / leaf];
         e = hipMemcpyAsync(dst, grouped.data(), total * sizeof(int), hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(e, "FMM list upload");

@@ -151,9 +151,11 @@ void tree_release();
 // records (ORB order); synchronises s once to check the list buffers.
 int fmm_accel(const void *pm, int n, int prec, double G, double eps, double theta, int leaf, void *out,
               hipStream_t s);
-// Lists grouped by target node (device outputs; ids may be NULL to count).
-int fmm_lists(const void *pm, int n, int leaf, double theta, int32_t *m2l_cnt, int32_t *p2p_cnt, int32_t *m2l_ids,
-              int64_t m2l_cap, int32_t *p2p_ids, int64_t p2p_cap, hipStream_t s);
+// fmm_lists: per-node counts and concatenated source ids of the (M2L, M2P,
+// P2P) lists, grouped by target node (device outputs; ids_out entries may be
+// NULL to count only).
+int fmm_lists(const void *pm, int n, int leaf, double theta, int32_t *const cnt_out[3], int32_t *const ids_out[3],
+              const int64_t caps[3], hipStream_t s);
 void fmm_release();
 
 // ---- bit-reversible fixed-point leapfrog (janus.hip) ---------------------------

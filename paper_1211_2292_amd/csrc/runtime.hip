@@ -988,25 +988,30 @@ int nbody_fmm_accel(const void *pos_mass, int64_t n, int32_t prec, double G, dou
 }
 
 int nbody_fmm_lists(const void *pos_mass, int64_t n, int32_t leaf, double theta, int32_t *m2l_cnt,
-                    int32_t *p2p_cnt, int32_t *m2l_ids, int64_t m2l_cap, int32_t *p2p_ids, int64_t p2p_cap,
-                    void *stream)
+                    int32_t *m2p_cnt, int32_t *p2p_cnt, int32_t *m2l_ids, int64_t m2l_cap, int32_t *m2p_ids,
+                    int64_t m2p_cap, int32_t *p2p_ids, int64_t p2p_cap, void *stream)
 {
     NB_CHECK(check_tree(n, leaf));
     NB_CHECK(check_theta(theta));
     NB_CHECK(check_vec(pos_mass, NBODY_F32, "pos_mass"));
-    if (!m2l_cnt || !p2p_cnt || ((uintptr_t)m2l_cnt | (uintptr_t)p2p_cnt | (uintptr_t)m2l_ids | (uintptr_t)p2p_ids) % 4 ||
-        m2l_cap < 0 || p2p_cap < 0) {
+    if (!m2l_cnt || !m2p_cnt || !p2p_cnt ||
+        ((uintptr_t)m2l_cnt | (uintptr_t)m2p_cnt | (uintptr_t)p2p_cnt | (uintptr_t)m2l_ids | (uintptr_t)m2p_ids |
+         (uintptr_t)p2p_ids) % 4 ||
+        m2l_cap < 0 || m2p_cap < 0 || p2p_cap < 0) {
         set_error("count arrays NULL, or misaligned arrays, or negative capacity");
         return NBODY_E_INVAL;
     }
     int64_t nn = 0;
     NB_CHECK(tree_shape((int)n, leaf, &nn, nullptr, nullptr));
-    if (outputs_overlap({{m2l_cnt, 4 * (size_t)nn}, {p2p_cnt, 4 * (size_t)nn}, {m2l_ids, 4 * (size_t)m2l_cap},
+    if (outputs_overlap({{m2l_cnt, 4 * (size_t)nn}, {m2p_cnt, 4 * (size_t)nn}, {p2p_cnt, 4 * (size_t)nn},
+                         {m2l_ids, 4 * (size_t)m2l_cap}, {m2p_ids, 4 * (size_t)m2p_cap},
                          {p2p_ids, 4 * (size_t)p2p_cap}},
                         {{pos_mass, 16 * (size_t)n}}))
         return NBODY_E_INVAL;
-    return fmm_lists(pos_mass, (int)n, leaf, theta, m2l_cnt, p2p_cnt, m2l_ids, m2l_cap, p2p_ids, p2p_cap,
-                     (hipStream_t)stream);
+    int32_t *const cnt[3] = {m2l_cnt, m2p_cnt, p2p_cnt};
+    int32_t *const ids[3] = {m2l_ids, m2p_ids, p2p_ids};
+    const int64_t caps[3] = {m2l_cap, m2p_cap, p2p_cap};
+    return fmm_lists(pos_mass, (int)n, leaf, theta, cnt, ids, caps, (hipStream_t)stream);
 }
 
 int nbody_tree_pseudo(const void *pos_mass, int64_t n, int32_t leaf, void *pseudo_out, void *stream)

@@ -259,11 +259,6 @@ __global__ __launch_bounds__(256) void k_tree_quad(TreeDev T, int nn)
     o[2] = make_float4((float)(3.0 * B.x), (float)(3.0 * B.y), 0.0f, 0.0f);
 }
 
-__device__ __forceinline__ double box_gap(double p, double a, double b)
-{
-    return p < a ? a - p : (p > b ? p - b : 0.0);
-}
-
 __device__ __forceinline__ unsigned lane_rank(unsigned long long mask)
 {
     return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
@@ -305,31 +300,6 @@ __device__ __forceinline__ void sweep_pseudo(const float4 *__restrict__ pp, cons
 #pragma unroll
         for (int u = 0; u < kPseudo; ++u) pair_f32<1, false>(b[u], u, T, eps2, S);
     }
-}
-
-// One quadrupole cell against the lane's target: c = (com, M),
-// q1 = (Qxx, Qyy, Qzz, Qxy), q2 = (Qxz, Qyz, -, -).
-__device__ __forceinline__ void quad_f32(const float4 c, const float4 q1, const float4 q2,
-                                         const Targets<float, 1> &T, float eps2, Sums<float, 1> &S)
-{
-    const float dx = c.x - T.x[0];
-    const float dy = c.y - T.y[0];
-    const float dz = c.z - T.z[0];
-    const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
-    const float ri = __builtin_amdgcn_rsqf(r2);
-    const float ri2 = ri * ri;
-    const float ri3 = ri2 * ri;
-    const float ri5 = ri3 * ri2;
-    const float qx = __builtin_fmaf(q1.x, dx, __builtin_fmaf(q1.w, dy, q2.x * dz));
-    const float qy = __builtin_fmaf(q1.w, dx, __builtin_fmaf(q1.y, dy, q2.y * dz));
-    const float qz = __builtin_fmaf(q2.x, dx, __builtin_fmaf(q2.y, dy, q1.z * dz));
-    const float dqd = __builtin_fmaf(dx, qx, __builtin_fmaf(dy, qy, dz * qz));
-    const float t5 = dqd * ri5;
-    S.ph[0] = __builtin_fmaf(0.5f, t5, __builtin_fmaf(c.w, ri, S.ph[0]));
-    const float k = __builtin_fmaf(2.5f * t5, ri2, c.w * ri3);
-    S.ax[0] = __builtin_fmaf(-qx, ri5, __builtin_fmaf(k, dx, S.ax[0]));
-    S.ay[0] = __builtin_fmaf(-qy, ri5, __builtin_fmaf(k, dy, S.ay[0]));
-    S.az[0] = __builtin_fmaf(-qz, ri5, __builtin_fmaf(k, dz, S.az[0]));
 }
 
 // Sweeps the quadrupole records batched in LDS (broadcast reads into vector

@@ -1,13 +1,15 @@
 // Tree tables shared by the tree walks (tree.hip) and the multi-level fast
 // multipole method (fmm.hip): the device view of the ORB node table and its
-// per-node moments and cell records, the host plan of the node table, and
-// the quadrupole cell's M2L into a third-order local expansion.
+// per-node moments and cell records, the host plan of the node table, the
+// box distance of the opening test, the quadrupole cell's evaluation at a
+// target and its M2L into a third-order local expansion.
 #pragma once
 
 #include <mutex>
 #include <vector>
 
 #include "internal.h"
+#include "pair.h"
 
 namespace nbi {
 
@@ -42,6 +44,43 @@ int tree_quad_prepare(const void *pm, int n, int leaf, hipStream_t s, TreeDev &d
 std::mutex &tree_mutex();
 
 namespace {
+
+// Distance along one axis from p to the interval [a, b] (0 inside).
+__device__ __forceinline__ double box_gap(double p, double a, double b)
+{
+    return p < a ? a - p : (p > b ? p - b : 0.0);
+}
+
+// One quadrupole cell against the lane's TPL targets: c = (com, M),
+// q1 = (Qxx, Qyy, Qzz, Qxy), q2 = (Qxz, Qyz, -, -).  With d = com - x and
+// s^2 = |d|^2 + eps^2: phi-sum += M/s + d.Q.d / (2 s^5),
+// a-sum += M d / s^3 + 5 (d.Q.d) d / (2 s^7) - Q d / s^5.
+template <int TPL>
+__device__ __forceinline__ void quad_f32(const float4 c, const float4 q1, const float4 q2,
+                                         const Targets<float, TPL> &T, float eps2, Sums<float, TPL> &S)
+{
+#pragma unroll
+    for (int t = 0; t < TPL; ++t) {
+        const float dx = c.x - T.x[t];
+        const float dy = c.y - T.y[t];
+        const float dz = c.z - T.z[t];
+        const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
+        const float ri = __builtin_amdgcn_rsqf(r2);
+        const float ri2 = ri * ri;
+        const float ri3 = ri2 * ri;
+        const float ri5 = ri3 * ri2;
+        const float qx = __builtin_fmaf(q1.x, dx, __builtin_fmaf(q1.w, dy, q2.x * dz));
+        const float qy = __builtin_fmaf(q1.w, dx, __builtin_fmaf(q1.y, dy, q2.y * dz));
+        const float qz = __builtin_fmaf(q2.x, dx, __builtin_fmaf(q2.y, dy, q1.z * dz));
+        const float dqd = __builtin_fmaf(dx, qx, __builtin_fmaf(dy, qy, dz * qz));
+        const float t5 = dqd * ri5;
+        S.ph[t] = __builtin_fmaf(0.5f, t5, __builtin_fmaf(c.w, ri, S.ph[t]));
+        const float k = __builtin_fmaf(2.5f * t5, ri2, c.w * ri3);
+        S.ax[t] = __builtin_fmaf(-qx, ri5, __builtin_fmaf(k, dx, S.ax[t]));
+        S.ay[t] = __builtin_fmaf(-qy, ri5, __builtin_fmaf(k, dy, S.ay[t]));
+        S.az[t] = __builtin_fmaf(-qz, ri5, __builtin_fmaf(k, dz, S.az[t]));
+    }
+}
 
 // Third-order local expansion about a centre z: P0, p (x, y, z),
 // K (xx, yy, zz, xy, xz, yz), T (xxx, yyy, zzz, xxy, xxz, xyy, yyz, xzz,

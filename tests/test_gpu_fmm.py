@@ -2,9 +2,9 @@
 against the oracle's FMM (Section VI's O(N) method).
 
 The traversal's decisions are the FP64 expressions of the definitions, so
-every node's M2L and P2P lists equal the oracle's as sets (the device walk
-visits them in its own fixed order).  Forces are FP32 (M2L sums in
-FP32, L2L and L2P in FP64, P2P with the FP32 pair code) and are held to the
+every node's M2L, M2P and P2P lists equal the oracle's as sets (the device
+walk visits them in its own fixed order).  Forces are FP32 (M2L sums, M2P
+cells and P2P pairs in FP32, L2L and L2P in FP64) and are held to the
 tree-code bars against the oracle's FP64 evaluation of the same lists."""
 import numpy as np
 import pytest
@@ -37,16 +37,18 @@ def test_lists_match_oracle(orc, n, leaf, theta, kind):
     torch, nb = gpu()
     pm, _ = GEN[kind](max(n, 4), 700 + n)
     q, qh = _orb_input(torch, nb, pm[:n], leaf)
-    mc, pc, m2l, p2p = (host(t).astype(np.int64) for t in nb.fmm_lists(q, theta, leaf))
+    got = dict(zip(("m2l_cnt", "m2p_cnt", "p2p_cnt", "m2l", "m2p", "p2p"),
+                   (host(t).astype(np.int64) for t in nb.fmm_lists(q, theta, leaf))))
     want = orc.fmm_lists(qh, leaf, theta)
-    assert np.array_equal(mc, want["m2l_cnt"])
-    assert np.array_equal(pc, want["p2p_cnt"])
-    # each node's entries as a set (the device walk visits them in its own
-    # fixed order)
-    assert np.array_equal(_per_node_sorted(m2l, mc), _per_node_sorted(want["m2l"], want["m2l_cnt"]))
-    assert np.array_equal(_per_node_sorted(p2p, pc), _per_node_sorted(want["p2p"], want["p2p_cnt"]))
+    for kind in ("m2l", "m2p", "p2p"):
+        c = got[kind + "_cnt"]
+        assert np.array_equal(c, want[kind + "_cnt"]), kind
+        # each node's entries as a set (the device walk visits them in its
+        # own fixed order)
+        assert np.array_equal(_per_node_sorted(got[kind], c),
+                              _per_node_sorted(want[kind], want[kind + "_cnt"])), kind
     if theta == 0.0:
-        assert mc.sum() == 0
+        assert got["m2l_cnt"].sum() == 0 and got["m2p_cnt"].sum() == 0
 
 
 @pytest.mark.parametrize("prec,tol_rms,tol_max", [("F32_F64ACC", 1e-6, 2e-5), ("F32_KAHAN", 1e-6, 2e-5),
@@ -76,6 +78,28 @@ def test_edge_sizes(orc, n, leaf):
         assert np.all(got == 0)
         return
     a, p = orc.fmm_accel(widen32(qh), leaf, 0.6, 0.01)
+    assert rms_rel(got[:, :3], a) < 1e-6
+    assert rms_rel(got[:, 3], p) < 1e-6
+
+
+def test_far_flung_leaf(orc):
+    """A dense ball and 8 bodies strung far out along x: their leaf takes M2P
+    cells rather than every leaf; lists and forces match the oracle."""
+    torch, nb = gpu()
+    g = np.random.default_rng(17)
+    v = g.normal(size=(2000, 3))
+    v /= np.linalg.norm(v, axis=1)[:, None]
+    ball = v * g.uniform(size=(2000, 1)) ** (1 / 3)
+    line = np.column_stack([np.linspace(20, 60, 8), g.normal(0, 0.5, (8, 2))])
+    x = np.vstack([ball, line])
+    pm = np.hstack([x, g.uniform(0.5, 1.5, (x.shape[0], 1))]).astype(np.float32)
+    q, qh = _orb_input(torch, nb, pm, 8)
+    mc, cc, pc = (host(t).astype(np.int64) for t in nb.fmm_lists(q, 0.5, 8)[:3])
+    want = orc.fmm_lists(qh, 8, 0.5)
+    assert np.array_equal(cc, want["m2p_cnt"]) and np.array_equal(pc, want["p2p_cnt"])
+    assert cc.sum() > 0
+    got = host(nb.fmm_accel(q, 0.0, 0.5, 8, prec=nb.F32_F64ACC))
+    a, p = orc.fmm_accel(widen32(qh), 8, 0.5, 0.0)
     assert rms_rel(got[:, :3], a) < 1e-6
     assert rms_rel(got[:, 3], p) < 1e-6
 
