@@ -66,6 +66,8 @@ def main():
                     help="two tree evaluations (theta 0.7, leaf 8) of the workload for counter runs")
     ap.add_argument("--tree-cells", action="store_true",
                     help="two tree evaluations (theta 0.7, leaf 4) per cell model for trace and counter runs")
+    ap.add_argument("--fmm", action="store_true",
+                    help="two multi-level FMM evaluations (theta 0.5, leaf 8) of the workload for trace runs")
     ap.add_argument("--adjoint", action="store_true",
                     help="the adjoint leg alone (plain, checkpointed and fixed-point), for trace runs")
     ap.add_argument("--counters", action="store_true",
@@ -124,6 +126,15 @@ def main():
 
     if args.adjoint:
         print(json.dumps(adjoint_leg(torch, nb, ics, dev)))
+        return
+
+    if args.fmm:
+        q = nb.permute(pm, nb.orb_order(pm, 8))
+        out = torch.empty_like(q)
+        for _ in range(2):
+            nb.fmm_accel(q, eps, 0.5, 8, prec=prec, out=out)
+        torch.cuda.synchronize()
+        log("[bench] fmm mode: 2 evaluations, theta 0.5, leaf 8, F32_F64ACC")
         return
 
     if args.tree_cells:
@@ -242,6 +253,7 @@ def main():
         result["adjoint"] = adjoint_leg(torch, nb, ics, dev)
         result["batched"] = batched_leg(torch, nb, ics, dev)
         result["tree"] = tree_leg(torch, nb, pm_np, eps, kern_avg, v_np=v_np, dt=dt)
+        result["fmm"] = fmm_leg(torch, nb, pm_np, eps, kern_avg)
         result["shard"] = shard_leg(torch, nb, pm, eps, prec)
         result["cpu_baseline"] = cpu_leg(ics, pm0_host, acc0, eps, args.cpu_seconds, modes)
         result["modes"] = modes
@@ -508,6 +520,54 @@ def _tree_groups(nodes, group):
         else:
             stack.extend((r, l))
     return out
+
+
+def fmm_leg(torch, nb, pm_np, eps, direct_ms, fmm_args=None):
+    """Multi-level FMM on the ORB nodes for the same colliding pair at step 0
+    (F32_F64ACC): time per evaluation (ORB order excluded, as in the tree
+    leg), list sizes, flop rate and the error against the exact direct sum on
+    the same ordered input, per leaf size and theta."""
+    dev = torch.device("cuda:0")
+    n = pm_np.shape[0]
+    p = torch.as_tensor(pm_np, dtype=torch.float32, device=dev).contiguous()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res = {"workload": "colliding Plummer pair, N=1048576, eps=0.005, step 0, F32_F64ACC; quadrupole cells, "
+                       "third-order local expansions, L2L, M2P cells and leaf-leaf P2P at the leaves", "runs": {}}
+    for leaf, thetas in (fmm_args or ((8, (0.4, 0.5, 0.6, 0.7, 0.8)), (16, (0.4, 0.5)))):
+        q = nb.permute(p, nb.orb_order(p, leaf))
+        direct = nb.accel(q, eps, prec=nb.F32_F64ACC).cpu().double().numpy()
+        _, _, nodes = nb.tree_shape(n, leaf, nodes=True)
+        size = (nodes[:, 1] - nodes[:, 0]).astype(np.float64)
+        out = torch.empty_like(q)
+        for theta in thetas:
+            nb.fmm_accel(q, eps, theta, leaf, out=out)  # sizes the list buffers
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(5):
+                e0.record()
+                nb.fmm_accel(q, eps, theta, leaf, out=out)
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            t = float(np.mean(ts))
+            got = out.cpu().double().numpy()
+            rel = np.linalg.norm(got[:, :3] - direct[:, :3], axis=1) / np.linalg.norm(direct[:, :3], axis=1)
+            mc, cc, pc, _, m2p, p2p = (x.cpu().numpy().astype(np.int64) for x in nb.fmm_lists(q, theta, leaf))
+            tgt = np.repeat(np.arange(nodes.shape[0]), pc)
+            pairs = float((size[tgt] * size[p2p]).sum())
+            cells = float((size * cc).sum())  # M2P: one quadrupole cell per body of the target leaf
+            flops = FLOP_PER_PAIR * pairs + FLOP_PER_M2L * float(mc.sum()) + FLOP_PER_QUAD_CELL * cells
+            r = {"ms": round(t, 4), "ms_std": round(float(np.std(ts)), 4),
+                 "m2l_per_node": round(float(mc.sum()) / nodes.shape[0], 1),
+                 "m2p_cells_per_body": round(cells / n, 1),
+                 "p2p_interactions_per_body": round(pairs / n, 1),
+                 "gflop": round(flops / 1e9, 2), "tflops": round(flops / (t * 1e-3) / 1e12, 2),
+                 "speedup_vs_direct_kernel": round(direct_ms / t, 1),
+                 "rms_rel_err_vs_direct": float(np.sqrt(np.mean(rel ** 2))), "max_rel_err_vs_direct": float(rel.max())}
+            res["runs"][f"leaf{leaf}_theta{theta}"] = r
+            log(f"[bench] fmm leaf {leaf} theta {theta}: {t:.3f} ms, {r['m2l_per_node']} M2L/node, "
+                f"{r['p2p_interactions_per_body']:.0f} P2P/body, {r['tflops']} TFLOP/s, rms err {r['rms_rel_err_vs_direct']:.2e}")
+    return res
 
 
 def tree_leg(torch, nb, pm_np, eps, direct_ms, leaf=4, v_np=None, dt=5e-4):

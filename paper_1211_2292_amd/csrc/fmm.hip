@@ -789,8 +789,9 @@ void list_totals(const unsigned long long *tot, int depth, unsigned long long (&
     for (int q = 0; q < 3; ++q) out[q] = tot[tot_at(q, depth + 1)];
 }
 
-// Runs the traversal (and, with out != nullptr, the whole FMM) until the
-// lists fit their buffers.  Called with the tree and FMM locks held.
+// Runs the traversal until the lists fit their buffers (one stream
+// synchronisation per attempt), then, with out != nullptr, the evaluation.
+// Called with the tree and FMM locks held.
 int fmm_run(const void *pm, int n, int prec, double G, double eps, double theta, int leaf, void *out,
             hipStream_t s, TreeDev &d, const HostTree *&h)
 {
@@ -816,7 +817,13 @@ int fmm_run(const void *pm, int n, int prec, double G, double eps, double theta,
         NB_CHECK_RC(make_bufs(nn, p.max_level, dev, want));
         const FmmDev F = dev_view(d, p, g_bufs);
         hipError_t e = launch_traversal(F, p, theta * theta, s);
-        if (e == hipSuccess && out) {
+        if (e != hipSuccess) return hip_fail(e, "FMM traversal");
+        unsigned long long tot[kTotWords];
+        e = hipMemcpyAsync(tot, g_bufs.tot, sizeof tot, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "FMM list check");
+        if (!tot[0]) {  // the lists fit: evaluate
+            if (!out) return NBODY_OK;
             const float eps2 = (float)(eps * eps);
             hipLaunchKernelGGL(k_fmm_m2l, dim3((nn + 3) / 4), dim3(256), 0, s, F, eps2);
             e = hipGetLastError();
@@ -835,13 +842,8 @@ int fmm_run(const void *pm, int n, int prec, double G, double eps, double theta,
                 default: e = launch_leaves_mode<M_F64ACC>(x, F, p, nleaves, n, leaf, eps2, G, o, s); break;
                 }
             }
+            return e == hipSuccess ? NBODY_OK : hip_fail(e, "FMM kernels");
         }
-        if (e != hipSuccess) return hip_fail(e, "FMM kernels");
-        unsigned long long tot[kTotWords];
-        e = hipMemcpyAsync(tot, g_bufs.tot, sizeof tot, hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return hip_fail(e, "FMM list check");
-        if (!tot[0]) return NBODY_OK;
         // Grow what overflowed and run again.  The totals are exact up to the
         // first depth whose pass-down list overflowed and short beyond it, so
         // every attempt makes at least one more depth exact.
