@@ -32,17 +32,22 @@
  *   Every call is stream-ordered and asynchronous: it validates its
  *   arguments on the host, enqueues kernels and returns.  No call below
  *   synchronises the device except nbody_autotune(), nbody_release(), a
- *   call that needs more library scratch than any earlier call on the device
- *   (growing a scratch buffer waits for the work that may still use it), a
  *   tree call for a new (n, leaf) (it uploads the node table),
- *   nbody_janus_adjoint (its mass check), and nbody_orb_order when
- *   NBODY_CHECK_INPUTS is set.  Calls that share library scratch
- *   (the same entry point on one device) must not run concurrently on
- *   different streams.
+ *   nbody_janus_adjoint (its mass check), nbody_orb_order when
+ *   NBODY_CHECK_INPUTS is set, and the FMM calls (one stream
+ *   synchronisation each, to check their list buffers).
+ * - Library scratch is one buffer per purpose and device, shared by all
+ *   streams.  A call that needs more than any earlier one allocates a larger
+ *   buffer (a power of two in size) and does not wait: the one it replaces
+ *   may still be read by enqueued work or by a captured graph, so it stays
+ *   allocated until nbody_release().  Calls that share library scratch (the
+ *   same entry point on one device, or the entry points that share a
+ *   purpose: force, VJP and the integrators' partial sums) must not run
+ *   concurrently on different streams.
  * - A caller may capture calls into its own HIP graph after one eager call
  *   of the same shapes (which allocates the scratch and tables they use).
- *   The graph stays valid until a call grows library scratch, a tree call
- *   changes (n, leaf), or nbody_release() runs.
+ *   The graph stays valid until a tree call changes (n, leaf) or
+ *   nbody_release() runs.
  * - Return value: NBODY_OK (0) or a negative status.  On a validation error
  *   nothing has been enqueued.  nbody_last_error() gives a thread-local
  *   message for the last failing call.  The library never aborts or exits.

@@ -48,34 +48,40 @@ int hip_fail(hipError_t e, const char *what)
     } while (0)
 
 // ---------------------------------------------------------------------------
-// Library scratch: one growable device buffer per slot and device.
+// Library scratch: one growable device buffer per slot and device.  A slot
+// that must grow gets a new buffer and retires the old one without waiting:
+// work already enqueued, or a graph captured earlier, may still use it, so
+// it stays allocated until nbody_release().  Sizes are powers of two, so a
+// slot's retired buffers add up to less than its current one.
 // ---------------------------------------------------------------------------
 static std::mutex g_mu;
 
 struct DevScratch {
     void *ptr[kNumSlots] = {};
     size_t size[kNumSlots] = {};
+    std::vector<void *> retired;
 };
 static std::map<int, DevScratch> g_scratch;
 
 void *scratch(int slot, size_t bytes)
 {
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        set_error("hipGetDevice failed");
+        return nullptr;
+    }
     std::lock_guard<std::mutex> lk(g_mu);
     DevScratch &d = g_scratch[dev];
     if (d.size[slot] >= bytes && d.ptr[slot]) return d.ptr[slot];
-    if (d.ptr[slot]) {
-        // Work already enqueued may still use the old buffer.
-        (void)hipDeviceSynchronize();
-        (void)hipFree(d.ptr[slot]);
-        d.ptr[slot] = nullptr;
-        d.size[slot] = 0;
-    }
-    size_t want = std::max<size_t>(bytes, 256);
-    want = (want + 4095) & ~size_t(4095);
+    size_t want = 4096;
+    while (want < bytes) want <<= 1;
     void *p = nullptr;
-    if (hipMalloc(&p, want) != hipSuccess) return nullptr;
+    if (hipMalloc(&p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("cannot allocate %zu bytes of library scratch", want);
+        return nullptr;
+    }
+    if (d.ptr[slot]) d.retired.push_back(d.ptr[slot]);
     d.ptr[slot] = p;
     d.size[slot] = want;
     return p;
@@ -1680,9 +1686,11 @@ extern "C" void nbody_release(void)
         (void)hipFree(kv.second.d_counter);
     }
     g_plans.clear();
-    for (auto &kv : g_scratch)
+    for (auto &kv : g_scratch) {
         for (int k = 0; k < kNumSlots; ++k)
             if (kv.second.ptr[k]) (void)hipFree(kv.second.ptr[k]);
+        for (void *p : kv.second.retired) (void)hipFree(p);
+    }
     g_scratch.clear();
     orb_release();
     fmm_release();

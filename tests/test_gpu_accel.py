@@ -247,3 +247,35 @@ def test_caller_outputs_must_fit():
         nb.tree_accel(p, 0.01, 0.5, out=torch.empty(30, 4, device="cuda"))
     out = torch.empty(50, 4, device="cuda")
     assert nb.accel(p, 0.01, target_begin=100, target_count=50, out=out) is out
+
+
+def test_scratch_growth_does_not_wait():
+    """A call that needs a larger split buffer than any earlier one gets a
+    new buffer without waiting for the work that may still use the old one:
+    it returns while a 2^19-body force launch is still running, and that
+    launch's result equals a later evaluation bit for bit."""
+    import time
+    torch, nb = gpu()
+    mode = nb.F32_F64ACC
+    nb.release()  # no library scratch yet
+    nb.set_tuning(0, mode, tpl=1, jsplit=8, jtile=512)
+    try:
+        pm1, _ = ics.plummer(1 << 19, 750)
+        pm2, _ = ics.plummer(1 << 20, 751)
+        q1 = to_dev(torch, pm1, torch.float32)
+        q2 = to_dev(torch, pm2, torch.float32)
+        out2 = torch.empty((q2.shape[0], 4), dtype=torch.float32, device=q2.device)
+        torch.cuda.synchronize()
+        out1 = nb.accel(q1, 0.01, prec=mode)  # about 75 ms on the device
+        t0 = time.perf_counter()
+        nb.accel(q2, 0.01, prec=mode, out=out2)  # twice the split scratch of the call before
+        waited = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        again = nb.accel(q1, 0.01, prec=mode)
+        torch.cuda.synchronize()
+        assert torch.equal(out1, again)
+        assert torch.isfinite(out2).all()
+        assert waited < 0.03, f"the growing call took {waited * 1e3:.1f} ms on the host"
+    finally:
+        nb.set_tuning(0, mode)
+        nb.release()
