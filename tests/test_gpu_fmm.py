@@ -32,7 +32,7 @@ def _per_node_sorted(ids, cnt):
 @pytest.mark.parametrize("n,leaf,theta,kind", [
     (1, 8, 0.5, "plummer"), (7, 8, 0.5, "plummer"), (300, 4, 0.6, "plummer"), (3000, 8, 0.5, "plummer"),
     (3000, 8, 0.0, "ball"), (5000, 5, 0.7, "collide"), (776, 1, 0.9, "collide"), (20000, 16, 0.5, "collide"),
-    (9001, 12, 1.0, "plummer"), (4097, 64, 0.4, "ball"), (70001, 8, 0.6, "plummer")])
+    (9001, 12, 1.0, "plummer"), (4097, 64, 0.4, "ball"), (70001, 8, 0.6, "plummer"), (5000, 8, 5.0, "plummer")])
 def test_lists_match_oracle(orc, n, leaf, theta, kind):
     torch, nb = gpu()
     pm, _ = GEN[kind](max(n, 4), 700 + n)
@@ -144,3 +144,31 @@ def test_collide1m_sampled_against_oracle(orc):
     ad, _ = orc.accel(widen32(qh), w["eps"], targets=tg)
     print(f"fmm collide1m theta 0.5 leaf 8: vs oracle FMM {rms_rel(got[tg, :3], a):.2e}, "
           f"vs exact sum {rms_rel(got[tg, :3], ad):.2e}")
+
+
+def test_coincident_bodies_and_g(orc):
+    """Every body at one point: no expansion is ever used, forces are exactly
+    zero and the potential is -G (M - m_i) / eps; G scales the result."""
+    torch, nb = gpu()
+    n, leaf = 200, 4
+    pm = np.zeros((n, 4), dtype=np.float32)
+    pm[:, :3] = [0.25, -1.5, 3.0]
+    pm[:, 3] = np.linspace(0.5, 1.5, n)
+    q, qh = _orb_input(torch, nb, pm, leaf)
+    for theta in (0.5, 5.0):
+        mc, cc, pc = (host(t) for t in nb.fmm_lists(q, theta, leaf)[:3])
+        assert mc.sum() == 0 and cc.sum() == 0
+        got = host(nb.fmm_accel(q, 0.1, theta, leaf, G=2.0, prec=nb.F32_F64ACC))
+        assert np.all(got[:, :3] == 0)
+        _, p = orc.fmm_accel(widen32(qh), leaf, theta, 0.1, G=2.0)
+        assert rms_rel(got[:, 3], p) < 1e-6
+
+
+def test_g_scales_the_result(orc):
+    torch, nb = gpu()
+    pm, _ = ics.plummer(6000, 760)
+    q, qh = _orb_input(torch, nb, pm, 8)
+    got = host(nb.fmm_accel(q, 0.01, 0.6, 8, G=2.5, prec=nb.F32_F64ACC))
+    a, p = orc.fmm_accel(widen32(qh), 8, 0.6, 0.01, G=2.5)
+    assert rms_rel(got[:, :3], a) < 1e-6
+    assert rms_rel(got[:, 3], p) < 1e-6

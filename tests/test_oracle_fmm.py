@@ -207,3 +207,21 @@ def test_far_flung_leaf_takes_cells_not_every_leaf(orc):
     a, _ = orc.fmm_accel(q, leaf, theta, 0.0, targets=far)
     ad, _ = orc.accel(q, 0.0, targets=far)
     assert rms_rel(a, ad) < 1e-3
+
+
+def test_coincident_bodies_take_no_expansion(orc):
+    """Every body at one point: every box has zero size and every pair of
+    nodes zero distance, so no test passes and the FMM is the direct sum
+    (with softening), whatever theta."""
+    n, leaf = 200, 4
+    pm = np.zeros((n, 4))
+    pm[:, :3] = [0.25, -1.5, 3.0]
+    pm[:, 3] = np.linspace(0.5, 1.5, n)
+    q = _orb(orc, pm, leaf)
+    for theta in (0.5, 5.0):
+        L = orc.fmm_lists(q, leaf, theta)
+        assert L["m2l_cnt"].sum() == 0 and L["m2p_cnt"].sum() == 0
+        a, p = orc.fmm_accel(q, leaf, theta, 0.1, G=2.0)
+        assert np.all(a == 0)
+        # phi_i = -G (M - m_i) / eps
+        np.testing.assert_allclose(p, -2.0 * (q[:, 3].sum() - q[:, 3]) / 0.1, rtol=1e-13)
