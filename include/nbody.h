@@ -426,7 +426,12 @@ int nbody_tree_leapfrog(void *pos_mass, void *vel, void *acc_pot, int32_t *order
  *              prec.
  * theta = 0 gives no M2L or M2P entry: the direct sum, at a P2P cost of
  * (n/leaf)^2 leaf pairs.  List buffers are library-owned and grow as needed;
- * each call synchronises its stream once to check them.
+ * each call synchronises its stream once to check them.  The traversal
+ * writes each node's lists in one pass into slots sized for the largest
+ * node of its depth (about five times the entries); when that would take
+ * more than an eighth of the device's memory (or more than the environment
+ * variable NBODY_FMM_SLOT_MB, in MiB, if set) it counts, scans and fills
+ * compact lists instead.  Both give the same lists and results.
  * nbody_fmm_accel: acc_pot_out = n float4 (ax, ay, az, phi) in ORB order.
  * nbody_fmm_lists (inspection, synchronous): m2l_cnt, m2p_cnt, p2p_cnt =
  *   int32[num nodes] list lengths per target node; m2l_ids, m2p_ids, p2p_ids

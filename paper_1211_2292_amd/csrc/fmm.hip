@@ -27,10 +27,12 @@
 //   pass-down list) closed under source splits: one wave per node pops up to
 //   64 pending sources per step from an LDS stack, one per lane, and
 //   classifies them (ballot ranks give every output a fixed position).  Each
-//   depth runs a count walk, a two-kernel scan (block sums, then offsets)
-//   and a fill walk.  Lists live in library buffers; writes are
-//   bounds-checked and an overflow flag makes the host grow the buffers and
-//   run again.
+//   depth runs one walk that writes every node's lists into slots of a
+//   per-depth capacity; when that layout would take more than its memory
+//   budget, each depth instead runs a count walk, a two-kernel scan (block
+//   sums, then offsets) and a fill walk into compact lists.  Writes are
+//   bounds-checked and an overflow flag makes the host resize (from the
+//   exact counts) and run again.
 // * M2L: one wave per node, one source cell per lane, the twenty
 //   coefficients summed over the wave in a fixed butterfly (FP32).
 // * L2L: one thread per node, depth by depth, in FP64.
@@ -40,6 +42,8 @@
 //   folded by the precision mode in lane order through LDS, then each target
 //   adds its leaf's expansion in FP64.
 #include <algorithm>
+#include <array>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <type_traits>
@@ -105,26 +109,43 @@ __device__ __forceinline__ unsigned fmm_rank(unsigned long long mask)
     return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
 }
 
-// Bounds-checked store of one list entry at base + rank among the lanes of
-// mask; returns false when it does not fit.
-__device__ __forceinline__ bool put_entry(int *list, long cap, long base, unsigned long long mask, int value)
+// Bounds-checked store of one list entry: the entry's index in its list is
+// done + its rank among the lanes of mask, stored at base + index if the
+// index is below cap (the list's room); returns false when it does not fit.
+__device__ __forceinline__ bool put_entry(int *list, long base, long done, long cap, unsigned long long mask,
+                                          int value)
 {
-    const long q = base + (long)fmm_rank(mask);
+    const long q = done + (long)fmm_rank(mask);
     if (q >= cap) return false;
-    list[q] = value;
+    list[base + q] = value;
     return true;
 }
+
+// Walk passes.  kWalkCount counts every list of every node; kWalkFill writes
+// them at the offsets the scan derived from the counts; kWalkSlot writes
+// them, in one pass, into per-node slots of a per-depth capacity (and
+// records the exact counts, so that slots too small can be resized).
+enum { kWalkCount = 0, kWalkFill = 1, kWalkSlot = 2 };
+
+// Slot layout of one depth: list kind k of the node at position t of the
+// depth starts at base[k] + t * cap[k] (the pass-down list in the depth's
+// ping-pong buffer); prev_pass is the previous depth's pass-down capacity.
+struct SlotDepth {
+    long base[kKinds];
+    int cap[kKinds];
+    int prev_pass;
+};
 
 // One wave per target node of one depth: the walk of its inherited
 // sources.  The pending sources sit on an LDS stack; each step pops up to 64
 // of them (one per lane) and classifies each: M2L, M2P, P2P, pass-down (to
 // both children of A) or split (both children of B pushed).  Ballot ranks
-// keep every output in a fixed order, so the count pass (FILL = false) and
-// the fill pass (FILL = true, at the scanned offsets) produce the same lists.
-template <bool FILL>
+// keep every output in a fixed order, so every pass produces the same lists.
+template <int WMODE>
 __global__ __launch_bounds__(64) void k_fmm_walk(FmmDev F, const int *__restrict__ ids, int first, int count,
-                                                 int parity, double theta2)
+                                                 int parity, double theta2, SlotDepth sd)
 {
+    constexpr bool FILL = WMODE != kWalkCount;
     __shared__ int stk[kWalkStack];
     const int lane = threadIdx.x;
     const int t = blockIdx.x;
@@ -150,16 +171,32 @@ __global__ __launch_bounds__(64) void k_fmm_walk(FmmDev F, const int *__restrict
         const int P = F.parent[A];
         nin = F.cnt[kPass * nn + P];
         const long base = F.off[kPass * nn + P];
+        if (WMODE == kWalkSlot) nin = min(nin, sd.prev_pass);  // the parent's slot overflowed
         if (base + nin > F.cap_pass) nin = (int)max(0L, F.cap_pass - base);  // the parent's depth overflowed
         in = (parity ? F.pass0 : F.pass1) + base;  // the previous depth's buffer
     }
     int *pass_out = parity ? F.pass1 : F.pass0;
     long om = 0, op = 0, oc = 0, oq = 0;
-    if (FILL) {
+    // room of each list: the slot in the one-pass layout, else all of the buffer
+    long rm = F.cap_m2l, rp = F.cap_p2p, rc = F.cap_m2p, rq = F.cap_pass;
+    if (WMODE == kWalkSlot) {
+        om = sd.base[kM2L] + (long)t * sd.cap[kM2L];
+        op = sd.base[kP2P] + (long)t * sd.cap[kP2P];
+        oc = sd.base[kM2P] + (long)t * sd.cap[kM2P];
+        oq = sd.base[kPass] + (long)t * sd.cap[kPass];
+        rm = sd.cap[kM2L];
+        rp = sd.cap[kP2P];
+        rc = sd.cap[kM2P];
+        rq = sd.cap[kPass];
+    } else if (FILL) {
         om = F.off[kM2L * nn + A];
         op = F.off[kP2P * nn + A];
         oc = F.off[kM2P * nn + A];
         oq = F.off[kPass * nn + A];
+        rm -= om;  // offsets are global: the room is the rest of the buffer
+        rp -= op;
+        rc -= oc;
+        rq -= oq;
     }
     int cm = 0, cp = 0, cc = 0, cq = 0, top = 0, next = 0;
     bool bad = false;
@@ -209,10 +246,10 @@ __global__ __launch_bounds__(64) void k_fmm_walk(FmmDev F, const int *__restrict
         const unsigned long long mm = __ballot(m2l), mc = __ballot(m2p), mp = __ballot(p2p), mq = __ballot(pass),
                                  ms = __ballot(split);
         if (FILL) {
-            if (m2l && !put_entry(F.m2l, F.cap_m2l, om + cm, mm, B)) bad = true;
-            if (m2p && !put_entry(F.m2p, F.cap_m2p, oc + cc, mc, B)) bad = true;
-            if (p2p && !put_entry(F.p2p, F.cap_p2p, op + cp, mp, nb.x)) bad = true;  // a leaf as its first body
-            if (pass && !put_entry(pass_out, F.cap_pass, oq + cq, mq, B)) bad = true;
+            if (m2l && !put_entry(F.m2l, om, cm, rm, mm, B)) bad = true;
+            if (m2p && !put_entry(F.m2p, oc, cc, rc, mc, B)) bad = true;
+            if (p2p && !put_entry(F.p2p, op, cp, rp, mp, nb.x)) bad = true;  // a leaf as its first body
+            if (pass && !put_entry(pass_out, oq, cq, rq, mq, B)) bad = true;
         }
         cm += __popcll(mm);
         cc += __popcll(mc);
@@ -231,12 +268,16 @@ __global__ __launch_bounds__(64) void k_fmm_walk(FmmDev F, const int *__restrict
         top += 2 * ns;
         __syncthreads();
     }
-    if (!FILL && lane == 0) {
+    if (WMODE != kWalkFill && lane == 0) {
         const int c4[kKinds] = {cm, cp, cc, cq};
+        const long o4[kKinds] = {om, op, oc, oq};
 #pragma unroll
         for (int q = 0; q < kKinds; ++q) {
             F.cnt[q * nn + A] = c4[q];
-            F.lcnt[q * nn + first + t] = c4[q];
+            if (WMODE == kWalkCount)
+                F.lcnt[q * nn + first + t] = c4[q];
+            else
+                F.off[q * nn + A] = (int)o4[q];
         }
     }
     if (__ballot(bad) && lane == 0) atomicOr(&F.tot[0], 1ull);
@@ -565,6 +606,25 @@ __global__ __launch_bounds__(64) void k_fmm_leaf(const float4 *__restrict__ src,
         put(out, i, r, G);
 }
 
+// Export of one list kind: node a's entries go, in walk order, to
+// dst[dst_off[a] ...]; a P2P entry (a leaf's first body) becomes the leaf's
+// node id when leaves != nullptr.  One wave per node.
+__global__ __launch_bounds__(256) void k_fmm_export(const int *__restrict__ list, const int *__restrict__ cnt,
+                                                    const int *__restrict__ off, const long *__restrict__ dst_off,
+                                                    int nn, const int *__restrict__ leaves, int leaf,
+                                                    int *__restrict__ dst)
+{
+    const int a = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (a >= nn) return;
+    const int c = cnt[a];
+    const long o = off[a], t = dst_off[a];
+    for (int k = lane; k < c; k += 64) {
+        const int v = list[o + k];
+        dst[t + k] = leaves ? leaves[v / leaf] : v;
+    }
+}
+
 __global__ void k_fmm_zero_tot(unsigned long long *tot, int count)
 {
     for (int k = threadIdx.x; k < count; k += blockDim.x) tot[k] = 0ull;
@@ -588,9 +648,21 @@ struct FmmBufs {
     double *loc = nullptr;
 };
 
+// One-pass slot layout for the current plan: per depth, the room of each
+// list per node (grown from the exact counts whenever a walk overflowed).
+struct SlotPlan {
+    int nn = 0, dev = -1;
+    std::vector<SlotDepth> depth;
+    long total[kKinds] = {0, 0, 0, 0};  // slots per list kind (pass-down: the larger ping-pong half)
+    bool disabled = false;              // the layout outgrew its memory budget: count, scan and fill
+    long budget = 0;                    // entries the layout may take: an eighth of the device's memory,
+                                        // or NBODY_FMM_SLOT_MB MiB if that is less
+};
+
 std::mutex g_fmm_mu;
 FmmPlan g_plan;
 FmmBufs g_bufs;
+SlotPlan g_slots;
 
 void free_plan(FmmPlan &p)
 {
@@ -751,13 +823,112 @@ hipError_t launch_traversal(const FmmDev &F, const FmmPlan &p, double theta2, hi
         const int first = p.depth_off[d], count = p.depth_off[d + 1] - first;
         const int *ids = p.d_by_depth + first;
         const int nblk = (count + kScanBlock - 1) / kScanBlock;
-        hipLaunchKernelGGL(k_fmm_walk<false>, dim3(count), dim3(64), 0, s, F, ids, first, count, d & 1, theta2);
+        hipLaunchKernelGGL(k_fmm_walk<kWalkCount>, dim3(count), dim3(64), 0, s, F, ids, first, count, d & 1,
+                           theta2, SlotDepth{});
         hipLaunchKernelGGL(k_fmm_scan_part, dim3(nblk), dim3(256), 0, s, F, first, count);
         hipLaunchKernelGGL(k_fmm_scan_fin, dim3(nblk), dim3(256), 0, s, F, ids, first, count, d, nblk);
-        hipLaunchKernelGGL(k_fmm_walk<true>, dim3(count), dim3(64), 0, s, F, ids, first, count, d & 1, theta2);
+        hipLaunchKernelGGL(k_fmm_walk<kWalkFill>, dim3(count), dim3(64), 0, s, F, ids, first, count, d & 1,
+                           theta2, SlotDepth{});
         e = hipGetLastError();
     }
     return e;
+}
+
+// The one-pass traversal: one walk per depth into the slots of g_slots.
+hipError_t launch_traversal_slots(const FmmDev &F, const FmmPlan &p, double theta2, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fmm_zero_tot, dim3(1), dim3(256), 0, s, F.tot, kTotWords);
+    hipError_t e = hipGetLastError();
+    for (int d = 0; d <= p.depth && e == hipSuccess; ++d) {
+        const int first = p.depth_off[d], count = p.depth_off[d + 1] - first;
+        hipLaunchKernelGGL(k_fmm_walk<kWalkSlot>, dim3(count), dim3(64), 0, s, F, p.d_by_depth + first, first,
+                           count, d & 1, theta2, g_slots.depth[d]);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+// Sets the slot layout from per-depth rooms: cap[d][k] entries per node.
+void slots_layout(const FmmPlan &p, const std::vector<std::array<long, kKinds>> &cap)
+{
+    SlotPlan &S = g_slots;
+    S.depth.assign(p.depth + 1, SlotDepth{});
+    for (int k = 0; k < kKinds; ++k) S.total[k] = 0;
+    for (int d = 0; d <= p.depth; ++d) {
+        const long cnt = p.depth_off[d + 1] - p.depth_off[d];
+        SlotDepth &sd = S.depth[d];
+        for (int k = 0; k < kKinds; ++k) {
+            sd.cap[k] = (int)cap[d][k];
+            if (k == kPass) {
+                sd.base[k] = 0;  // each depth starts its ping-pong half at 0
+                S.total[k] = std::max(S.total[k], cnt * cap[d][k]);
+            } else {
+                sd.base[k] = S.total[k];
+                S.total[k] += cnt * cap[d][k];
+            }
+        }
+        sd.prev_pass = d > 0 ? (int)cap[d - 1][kPass] : 0;
+    }
+}
+
+// Rooms for a first attempt: modest guesses where a depth has the nodes a
+// list needs (inner nodes pass down, leaves take M2P and P2P), none elsewhere.
+void slots_initial(const FmmPlan &p, const HostTree &h)
+{
+    std::vector<std::array<long, kKinds>> cap(p.depth + 1);
+    for (int d = 0; d <= p.depth; ++d) {
+        bool inner = false, leafy = false;
+        for (int q = p.depth_off[d]; q < p.depth_off[d + 1]; ++q) (h.node[p.by_depth[q]].z < 0 ? leafy : inner) = true;
+        cap[d] = {128, leafy ? 512 : 0, leafy ? 64 : 0, inner ? 512 : 0};
+    }
+    slots_layout(p, cap);
+    g_slots.nn = p.nn;
+    g_slots.dev = p.dev;
+    g_slots.disabled = false;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) total_b = 0;
+    g_slots.budget = (long)(total_b / 8 / sizeof(int));
+    if (const char *mb = std::getenv("NBODY_FMM_SLOT_MB"))  // a smaller budget, in MiB
+        g_slots.budget = std::min(g_slots.budget, std::max(0L, std::atol(mb)) * (1L << 20) / (long)sizeof(int));
+}
+
+// Entries the current slot layout needs (both pass-down halves).
+long slots_need()
+{
+    long need = 0;
+    for (int k = 0; k < kKinds; ++k) need += (k == kPass ? 2 : 1) * g_slots.total[k];
+    return need;
+}
+
+// After an overflow: every room becomes at least the largest count of its
+// depth (exact up to the first depth whose pass-down lists overflowed) plus
+// an eighth.  Returns false when the layout would pass its memory budget.
+bool slots_regrow(const FmmPlan &p, const std::vector<int> &cnt, long budget_entries)
+{
+    const int nn = p.nn;
+    std::vector<std::array<long, kKinds>> cap(p.depth + 1);
+    long need = 0;
+    for (int d = 0; d <= p.depth; ++d) {
+        for (int k = 0; k < kKinds; ++k) {
+            long mx = 0;
+            for (int q = p.depth_off[d]; q < p.depth_off[d + 1]; ++q)
+                mx = std::max(mx, (long)cnt[(size_t)k * nn + p.by_depth[q]]);
+            const long old = g_slots.depth[d].cap[k];
+            cap[d][k] = mx > old ? mx + mx / 8 + 8 : old;
+        }
+    }
+    const auto saved = g_slots.depth;
+    long saved_total[kKinds];
+    std::copy(g_slots.total, g_slots.total + kKinds, saved_total);
+    slots_layout(p, cap);
+    for (int k = 0; k < kKinds; ++k) need += (k == kPass ? 2 : 1) * g_slots.total[k];
+    bool ok = need <= budget_entries;
+    for (int k = 0; k < kKinds; ++k) ok = ok && g_slots.total[k] <= (long)INT32_MAX;
+    if (!ok) {  // keep the old layout; the caller falls back to count, scan and fill
+        g_slots.depth = saved;
+        std::copy(saved_total, saved_total + kKinds, g_slots.total);
+    }
+    return ok;
 }
 
 template <int MODE>
@@ -813,10 +984,18 @@ int fmm_run(const void *pm, int n, int prec, double G, double eps, double theta,
                          std::max(1024L, 16L * nn)};
     if (g_bufs.dev == dev)
         for (int q = 0; q < kKinds; ++q) want[q] = std::max(want[q], g_bufs.cap[q]);
-    for (int attempt = 0; attempt < 16; ++attempt) {
+    // One pass into per-node slots while the layout fits its budget;
+    // otherwise count, scan and fill into compact lists.
+    if (g_slots.nn != nn || g_slots.dev != dev || (int)g_slots.depth.size() != p.depth + 1) slots_initial(p, *h);
+    bool slots = !g_slots.disabled && slots_need() <= g_slots.budget;
+    // A pass-down list that overflowed truncates what the depths below it see,
+    // so each attempt makes at least one more depth exact.
+    for (int attempt = 0; attempt < p.depth + 16; ++attempt) {
+        if (slots)
+            for (int q = 0; q < kKinds; ++q) want[q] = std::max(want[q], std::max(1024L, g_slots.total[q]));
         NB_CHECK_RC(make_bufs(nn, p.max_level, dev, want));
         const FmmDev F = dev_view(d, p, g_bufs);
-        hipError_t e = launch_traversal(F, p, theta * theta, s);
+        hipError_t e = slots ? launch_traversal_slots(F, p, theta * theta, s) : launch_traversal(F, p, theta * theta, s);
         if (e != hipSuccess) return hip_fail(e, "FMM traversal");
         unsigned long long tot[kTotWords];
         e = hipMemcpyAsync(tot, g_bufs.tot, sizeof tot, hipMemcpyDeviceToHost, s);
@@ -843,6 +1022,17 @@ int fmm_run(const void *pm, int n, int prec, double G, double eps, double theta,
                 }
             }
             return e == hipSuccess ? NBODY_OK : hip_fail(e, "FMM kernels");
+        }
+        if (slots) {  // resize the slots from the exact counts and run again
+            std::vector<int> cnt(kKinds * (size_t)nn);
+            e = hipMemcpyAsync(cnt.data(), g_bufs.cnt, cnt.size() * sizeof(int), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return hip_fail(e, "FMM count download");
+            if (!slots_regrow(p, cnt, g_slots.budget)) {
+                slots = false;
+                g_slots.disabled = true;
+            }
+            continue;
         }
         // Grow what overflowed and run again.  The totals are exact up to the
         // first depth whose pass-down list overflowed and short beyond it, so
@@ -894,13 +1084,13 @@ int fmm_lists(const void *pm, int n, int leaf, double theta, int32_t *const cnt_
     NB_CHECK_RC(fmm_run(pm, n, NBODY_F32, 1.0, 0.0, theta, leaf, nullptr, s, d, h));
     const int nn = g_plan.nn;
     std::vector<int> cnt(kKinds * (size_t)nn), off(kKinds * (size_t)nn);
-    unsigned long long tot[kTotWords], tl[3];
     hipError_t e = hipMemcpyAsync(cnt.data(), g_bufs.cnt, cnt.size() * sizeof(int), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(off.data(), g_bufs.off, off.size() * sizeof(int), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(tot, g_bufs.tot, sizeof tot, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "FMM list download");
-    list_totals(tot, g_plan.depth, tl);
+    long tl[3] = {0, 0, 0};  // list totals (M2L, P2P, M2P) from the per-node counts
+    for (int q = 0; q < 3; ++q)
+        for (int a = 0; a < nn; ++a) tl[q] += cnt[(size_t)q * nn + a];
     // the public order is (M2L, M2P, P2P)
     const int kind_of[3] = {kM2L, kM2P, kP2P};
     for (int w = 0; w < 3; ++w) {
@@ -919,21 +1109,24 @@ int fmm_lists(const void *pm, int n, int leaf, double theta, int32_t *const cnt_
             set_error("%s list of %ld entries exceeds the capacity %lld", names[w], total, (long long)caps[w]);
             return NBODY_E_INVAL;
         }
-        std::vector<int> all(std::max(total, 1L)), grouped(std::max(total, 1L));
-        e = hipMemcpyAsync(all.data(), g_bufs.list[q], total * sizeof(int), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return hip_fail(e, "FMM list download");
+        std::vector<long> dst_off(nn);
         long o = 0;
         for (int a = 0; a < nn; ++a) {  // node order, each node's entries in walk order
-            const int c = cnt[(size_t)q * nn + a], b = off[(size_t)q * nn + a];
-            std::memcpy(grouped.data() + o, all.data() + b, (size_t)c * sizeof(int));
-            o += c;
+            dst_off[a] = o;
+            o += cnt[(size_t)q * nn + a];
         }
-        if (q == kP2P)  // P2P entries hold the source leaf's first body: back to node ids
-            for (long k = 0; k < total; ++k) grouped[k] = h->leaves[grouped[k] / leaf];
-        e = hipMemcpyAsync(dst, grouped.data(), total * sizeof(int), hipMemcpyHostToDevice, s);
+        long *d_off = nullptr;
+        e = hipMalloc(&d_off, (size_t)nn * sizeof(long));
+        if (e == hipSuccess) e = hipMemcpyAsync(d_off, dst_off.data(), (size_t)nn * sizeof(long), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_fmm_export, dim3((nn + 3) / 4), dim3(256), 0, s, g_bufs.list[q],
+                               g_bufs.cnt + (size_t)q * nn, g_bufs.off + (size_t)q * nn, (const long *)d_off, nn,
+                               q == kP2P ? (const int *)g_plan.d_leaves : nullptr, leaf, dst);
+            e = hipGetLastError();
+        }
         if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return hip_fail(e, "FMM list upload");
+        (void)hipFree(d_off);
+        if (e != hipSuccess) return hip_fail(e, "FMM list export");
     }
     return NBODY_OK;
 }
@@ -943,6 +1136,7 @@ void fmm_release()
     std::lock_guard<std::mutex> lf(g_fmm_mu);
     free_plan(g_plan);
     free_bufs(g_bufs);
+    g_slots = SlotPlan();
 }
 
 }  // namespace nbi

@@ -172,3 +172,28 @@ def test_g_scales_the_result(orc):
     a, p = orc.fmm_accel(widen32(qh), 8, 0.6, 0.01, G=2.5)
     assert rms_rel(got[:, :3], a) < 1e-6
     assert rms_rel(got[:, 3], p) < 1e-6
+
+
+def test_compact_lists_equal_the_slot_layout(orc):
+    """With the slot layout's memory budget set to nothing, the traversal
+    counts, scans and fills compact lists instead; the lists and the forces
+    are the same, bit for bit."""
+    import os
+    torch, nb = gpu()
+    pm, _ = ics.plummer(20000, 770)
+    q, _ = _orb_input(torch, nb, pm, 8)
+    nb.release()
+    slot = nb.fmm_accel(q, 0.01, 0.5, 8, prec=nb.F32_F64ACC).clone()
+    slot_lists = [t.clone() for t in nb.fmm_lists(q, 0.5, 8)]
+    os.environ["NBODY_FMM_SLOT_MB"] = "0"
+    try:
+        nb.release()
+        compact = nb.fmm_accel(q, 0.01, 0.5, 8, prec=nb.F32_F64ACC).clone()
+        compact_lists = nb.fmm_lists(q, 0.5, 8)
+    finally:
+        del os.environ["NBODY_FMM_SLOT_MB"]
+        nb.release()
+    torch.cuda.synchronize()
+    assert torch.equal(slot, compact)
+    for a, b in zip(slot_lists, compact_lists):
+        assert torch.equal(a, b)
