@@ -265,6 +265,31 @@ __device__ __forceinline__ void block_lds_f32(const float4 *__restrict__ src, in
 }
 
 // ---- kernels -------------------------------------------------------------------
+// The chip hands workgroups to its 8 XCDs in turn (linear workgroup id modulo
+// 8), and each XCD has its own L2.  When the source range is split in a
+// multiple of 8, workgroup (bx, by) = (target block, source split) is taken
+// from the linear id so that XCD x runs only the splits x J/8 .. (x + 1) J/8
+// - 1, one after the other with the target blocks fastest: the waves on an
+// XCD then stream one source segment at a time, which stays in that L2, and
+// each segment is fetched from memory about once instead of once per pass of
+// the resident waves.  Any other split count keeps the plain mapping.  Either
+// way every (bx, by) is run exactly once, so results do not depend on it.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ void xcd_block(int &bx, int &by)
+{
+    const int gx = gridDim.x, J = gridDim.y;
+    if (J % kXcds) {
+        bx = blockIdx.x;
+        by = blockIdx.y;
+        return;
+    }
+    const long L = (long)blockIdx.y * gx + blockIdx.x;
+    const long i = L / kXcds;  // this workgroup's place in its XCD's sequence
+    by = (int)(L % kXcds) * (J / kXcds) + (int)(i / gx);
+    bx = (int)(i % gx);
+}
+
 // Source range of split `split` out of `js` over n sources.
 __device__ __forceinline__ void split_range(int n, int js, int split, int &jb, int &je)
 {
@@ -281,11 +306,13 @@ __global__ __launch_bounds__(kBlock) void k_accel_f32(const float4 *__restrict__
 {
     constexpr int WT = 64 * TPL;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int t0 = tbeg + (blockIdx.x * (kBlock / 64) + wave) * WT;
+    int bx, by;
+    xcd_block(bx, by);
+    const int t0 = tbeg + (bx * (kBlock / 64) + wave) * WT;
     const int tend = tbeg + tcount;
     if (t0 >= tend) return;
     int jb, je;
-    split_range(n, gridDim.y, blockIdx.y, jb, je);
+    split_range(n, gridDim.y, by, jb, je);
     double res[TPL][4];
     wave_f32<TPL, MODE>(src, n, t0, jb, je, jtile, eps2, res);
     const int lane = threadIdx.x & 63;
@@ -300,10 +327,10 @@ __global__ __launch_bounds__(kBlock) void k_accel_f32(const float4 *__restrict__
             else
                 put(out, k, res[t], G);
         } else if constexpr (MODE == M_F32) {
-            reinterpret_cast<float4 *>(partial)[(long)blockIdx.y * tcount + k] =
+            reinterpret_cast<float4 *>(partial)[(long)by * tcount + k] =
                 make_float4((float)res[t][0], (float)res[t][1], (float)res[t][2], (float)res[t][3]);
         } else {
-            reinterpret_cast<double4 *>(partial)[(long)blockIdx.y * tcount + k] =
+            reinterpret_cast<double4 *>(partial)[(long)by * tcount + k] =
                 make_double4(res[t][0], res[t][1], res[t][2], res[t][3]);
         }
     }
@@ -321,11 +348,13 @@ __global__ __launch_bounds__(kBlock) void k_accel_lds_f32(const float4 *__restri
     const int tend = tbeg + tcount;
     // waves past the last target still take part in the shared tile loop
     // (on a valid target range) but store nothing
-    const long t0l = (long)tbeg + ((long)blockIdx.x * (kBlock / 64) + wave) * WT;
+    int bx, by;
+    xcd_block(bx, by);
+    const long t0l = (long)tbeg + ((long)bx * (kBlock / 64) + wave) * WT;
     const bool active = t0l < tend;
     const int t0 = active ? (int)t0l : tbeg;
     int jb, je;
-    split_range(n, gridDim.y, blockIdx.y, jb, je);
+    split_range(n, gridDim.y, by, jb, je);
     double res[TPL][4];
     block_lds_f32<TPL, MODE>(src, n, t0, jb, je, jtile, eps2, tile, res);
     if (!active) return;
@@ -341,10 +370,10 @@ __global__ __launch_bounds__(kBlock) void k_accel_lds_f32(const float4 *__restri
             else
                 put(out, k, res[t], G);
         } else if constexpr (MODE == M_F32) {
-            reinterpret_cast<float4 *>(partial)[(long)blockIdx.y * tcount + k] =
+            reinterpret_cast<float4 *>(partial)[(long)by * tcount + k] =
                 make_float4((float)res[t][0], (float)res[t][1], (float)res[t][2], (float)res[t][3]);
         } else {
-            reinterpret_cast<double4 *>(partial)[(long)blockIdx.y * tcount + k] =
+            reinterpret_cast<double4 *>(partial)[(long)by * tcount + k] =
                 make_double4(res[t][0], res[t][1], res[t][2], res[t][3]);
         }
     }
@@ -358,11 +387,13 @@ __global__ __launch_bounds__(kBlock) void k_accel_f64(const double4 *__restrict_
 {
     constexpr int WT = 64 * TPL;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int t0 = tbeg + (blockIdx.x * (kBlock / 64) + wave) * WT;
+    int bx, by;
+    xcd_block(bx, by);
+    const int t0 = tbeg + (bx * (kBlock / 64) + wave) * WT;
     const int tend = tbeg + tcount;
     if (t0 >= tend) return;
     int jb, je;
-    split_range(n, gridDim.y, blockIdx.y, jb, je);
+    split_range(n, gridDim.y, by, jb, je);
     double res[TPL][4];
     wave_f64<TPL>(src, n, t0, jb, je, jtile, eps2, res);
     const int lane = threadIdx.x & 63;
@@ -374,7 +405,7 @@ __global__ __launch_bounds__(kBlock) void k_accel_f64(const double4 *__restrict_
         if (gridDim.y == 1)
             put(out, k, res[t], G);
         else
-            partial[(long)blockIdx.y * tcount + k] = make_double4(res[t][0], res[t][1], res[t][2], res[t][3]);
+            partial[(long)by * tcount + k] = make_double4(res[t][0], res[t][1], res[t][2], res[t][3]);
     }
 }
 

@@ -241,6 +241,21 @@ def test_tuning_pin_roundtrip():
     assert t[0] in (1, 2, 4) and t[2] % 8 == 0 and t[3] in (0, 1)
 
 
+def test_default_splits_take_the_xcd_mapping():
+    """Without a pin or a tuned entry, the force kernel splits 2^20 sources
+    in 8 (a multiple of the 8 XCDs, 2 MiB per split); small n keep splits of
+    at least 256 sources."""
+    import os
+    if os.environ.get("NBODY_TUNE_CACHE"):
+        pytest.skip("a tuning cache may hold a measured shape")
+    nb, L = _lib()
+    assert nb.get_tuning(0, 2, 1 << 20)[1] == 8
+    assert nb.get_tuning(0, 2, 1 << 22)[1] == 8
+    assert nb.get_tuning(0, 2, 1 << 17)[1] == 32
+    assert nb.get_tuning(0, 2, 1024)[1] == 4
+    assert nb.get_tuning(0, 2, 1023)[1] == 2
+
+
 def test_missing_library_fails_loudly(tmp_path):
     """Without the built library the binding raises instead of computing
     anything elsewhere."""
