@@ -296,6 +296,11 @@ int nbody_trajectory_adjoint(const void *ckpt, int64_t n, int32_t prec, double G
  * uploads the node table and synchronizes the stream; later calls are
  * asynchronous.  The tree tables are library scratch (about 430 bytes per
  * node) shared by all tree calls on a device: overlapping calls race.
+ * With group local expansions (NBODY_CELLS_LOCAL) and 8192 groups or more,
+ * the groups whose boxes are among the largest 1/16 (by a histogram of
+ * diag2) are walked first, since their walks cost several times the mean;
+ * the environment variable NBODY_TREE_ORDER=0 keeps ORB order.  The results
+ * do not depend on the order.
  *
  * Cell models (the acceptance test and the interaction lists are the same
  * for all three):

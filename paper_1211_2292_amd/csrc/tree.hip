@@ -75,6 +75,7 @@
 // the same tests as above; every decision is the FP64 expression of the
 // definitions, so the lists equal the FP64 definition's.
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -321,7 +322,7 @@ template <int MODE, bool INSPECT, int CELLS>
 // allocator took 111, 4 waves).
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(CELLS == kCellsLocal ? 5 : 7))) void k_tree_walk(const float4 *__restrict__ src, int n, TreeDev T,
                                                   const float4 *__restrict__ cells, float eps2_in, double G,
-                                                  double theta2, WalkOut O)
+                                                  double theta2, WalkOut O, const int *__restrict__ order)
 {
     __shared__ int stk[kStack];
     __shared__ float4 cbuf[CELLS == kCellsMono ? kBuf : 1];    // monopole cells: the accepted records
@@ -332,7 +333,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(CELLS == kCe
     __shared__ int lid[CELLS == kCellsLocal ? kBuf : 1];
     __shared__ int2 nbuf[kBuf];
     const int lane = threadIdx.x;
-    const int g = blockIdx.x;
+    const int g = order ? order[blockIdx.x] : (int)blockIdx.x;
     const int gnode = T.groups[g];
     const int4 gn = T.node[gnode];
     const float4 glo = T.lo[gnode], ghi = T.hi[gnode];
@@ -567,6 +568,134 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(CELLS == kCe
     }
 }
 
+// Dispatch order of the local-expansion walk.  A group whose box is large
+// (a few far-flung bodies, as in the halo of a Plummer sphere) finds few
+// cells far enough for its expansion, evaluates the rest per target, and
+// its walk costs several times the mean (at 2^20 on the colliding pair, up
+// to 3.3 times).  Taken in ORB order, such groups start late and leave most
+// of the chip idle behind them; started first, they overlap with the rest
+// (measured 7-10% faster at theta 0.5-1.0).  The monopole and quadrupole
+// walks, whose costs vary less, measured no gain and keep ORB order, which
+// L2 locality favours.  k_order_bins puts each group's diag2 in one of 1024 bins by its
+// FP32 bit pattern (exponent and two mantissa bits); k_group_order, one
+// workgroup, takes the bins from the top down until they hold 1/16 of the
+// groups and writes a stable partition of the group indices: those groups,
+// then the others, each in ORB order.  Only the order in which the
+// workgroups run changes, never what a group computes.
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderBins = 1024;
+constexpr int kOrderMinGroups = 8192;  // fewer groups run in about one round
+
+// One thread per group; each workgroup also writes the histogram of its
+// kOrderThreads groups' bins (a row of kOrderBins counts).
+__global__ __launch_bounds__(kOrderThreads) void k_order_bins(TreeDev T, int ng)
+{
+    static_assert(kOrderBins == kOrderThreads, "one bin per thread");
+    __shared__ int lh[kOrderBins];
+    const int t = threadIdx.x;
+    lh[t] = 0;
+    __syncthreads();
+    const int g = blockIdx.x * kOrderThreads + t;
+    if (g < ng) {
+        const unsigned b = min(__float_as_uint((float)T.comd[T.groups[g]].w) >> 21, (unsigned)(kOrderBins - 1));
+        T.obin[g] = (unsigned short)b;
+        atomicAdd(&lh[b], 1);
+    }
+    __syncthreads();
+    T.ohist[(long)blockIdx.x * kOrderBins + t] = lh[t];
+}
+
+// Inclusive sum over the workgroup's threads (within each wave by shuffles,
+// then over the waves' totals in LDS), and the workgroup's total; every
+// thread must call it.
+__device__ __forceinline__ int block_incl_sum(int *sc, int v, int &total)
+{
+    constexpr int kWaves = kOrderThreads / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(v, o);
+        if (lane >= o) v += u;
+    }
+    if (lane == 63) sc[w] = v;
+    __syncthreads();
+    int before = 0, all = 0;
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) {
+        const int s = sc[k];
+        before += k < w ? s : 0;
+        all += s;
+    }
+    __syncthreads();
+    total = all;
+    return before + v;
+}
+
+// Chunks of kOrderChunk groups: loaded coalesced (kOrderPer per thread,
+// strided), then read from LDS as one contiguous run per thread.
+constexpr int kOrderPer = 16;
+constexpr int kOrderChunk = kOrderPer * kOrderThreads;
+
+__global__ __launch_bounds__(kOrderThreads) void k_group_order(TreeDev T, int ng)
+{
+    static_assert(kOrderBins == kOrderThreads, "one bin per thread");
+    __shared__ int hist[kOrderBins];
+    __shared__ int sc[kOrderThreads / 64];
+    __shared__ unsigned short cb[kOrderChunk];
+    __shared__ int cut, ftot;
+    const unsigned short *__restrict__ bin = T.obin;
+    const int t = threadIdx.x;
+    {
+        // bin t summed over k_order_bins' workgroup rows
+        const int rows = (ng + kOrderThreads - 1) / kOrderThreads;
+        int s = 0;
+#pragma unroll 16
+        for (int r = 0; r < rows; ++r) s += T.ohist[(long)r * kOrderBins + t];
+        hist[t] = s;
+    }
+    if (t == 0) cut = 0;
+    __syncthreads();
+    // groups in bins >= kOrderBins - 1 - t, counted from the top bin down
+    const int want = max(1, ng / 16);
+    const int h = hist[kOrderBins - 1 - t];
+    int all;  // = ng
+    const int top = block_incl_sum(sc, h, all);
+    (void)all;
+    if (top >= want && top - h < want) {
+        cut = kOrderBins - 1 - t;
+        ftot = top;
+    }
+    __syncthreads();
+    const int c = cut, F = ftot;
+    int done = 0;  // taken groups in the chunks before this one
+    for (int c0 = 0; c0 < ng; c0 += kOrderChunk) {
+#pragma unroll
+        for (int k = 0; k < kOrderPer; ++k) {
+            const int g = c0 + k * kOrderThreads + t;
+            cb[k * kOrderThreads + t] = g < ng ? bin[g] : 0;
+        }
+        __syncthreads();
+        const int r0 = t * kOrderPer;  // this thread's run in the chunk
+        int first = 0;
+#pragma unroll
+        for (int k = 0; k < kOrderPer; ++k) first += c0 + r0 + k < ng && cb[r0 + k] >= c;
+        int chunk_taken;
+        const int incl = block_incl_sum(sc, first, chunk_taken);
+        int a = done + incl - first;
+        int b = F + (c0 + r0) - a;  // the others before this run come after all taken groups
+        for (int k = 0; k < kOrderPer; ++k) {
+            const int g = c0 + r0 + k;
+            if (g >= ng) break;
+            if (cb[r0 + k] >= c)
+                T.order[a++] = g;
+            else
+                T.order[b++] = g;
+        }
+        done += chunk_taken;
+        __syncthreads();  // cb is reused by the next chunk
+    }
+}
+
 __global__ void k_tree_export(TreeDev T, int nn, double *__restrict__ mom, float *__restrict__ box)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -709,7 +838,10 @@ int tree_prepare(int n, int leaf, hipStream_t s, TreeDev &out)
     const size_t o_s2b = o_s2a + align256(nn * sizeof(double4));
     const size_t o_pp = o_s2b + align256(nn * sizeof(double4));
     const size_t o_qr = o_pp + align256(nn * kPseudo * sizeof(float4));
-    const size_t total = o_qr + align256(nn * kQuadRec * sizeof(float4));
+    const size_t o_ord = o_qr + align256(nn * kQuadRec * sizeof(float4));
+    const size_t o_obin = o_ord + align256(ng * sizeof(int));
+    const size_t o_ohist = o_obin + align256(ng * sizeof(unsigned short));
+    const size_t total = o_ohist + align256((ng + kOrderThreads - 1) / kOrderThreads * kOrderBins * sizeof(int));
     if (C.mem) {
         // work already enqueued may still read the old tables
         (void)hipDeviceSynchronize();
@@ -736,6 +868,9 @@ int tree_prepare(int n, int leaf, hipStream_t s, TreeDev &out)
     d.s2b = (double4 *)(base + o_s2b);
     d.pp = (float4 *)(base + o_pp);
     d.qr = (float4 *)(base + o_qr);
+    d.order = (int *)(base + o_ord);
+    d.obin = (unsigned short *)(base + o_obin);
+    d.ohist = (int *)(base + o_ohist);
     // pageable copies complete on the host side before returning; the vectors
     // stay alive in the cache in any case
     C.host = std::move(h);
@@ -803,8 +938,19 @@ hipError_t launch_walk(const float4 *pm, int n, const TreeDev &d, int ngroups, f
                        double theta2, const WalkOut &o, hipStream_t s)
 {
     const float4 *recs = CELLS == kCellsPseudo ? d.pp : (CELLS >= kCellsQuad ? d.qr : d.rec);
+    // the local-expansion force walk over many groups runs the largest boxes
+    // first (unless NBODY_TREE_ORDER=0); the other walks and inspection keep
+    // ORB order
+    const int *order = nullptr;
+    const char *env = getenv("NBODY_TREE_ORDER");
+    if (!INSPECT && CELLS == kCellsLocal && ngroups >= kOrderMinGroups && !(env && env[0] == '0')) {
+        hipLaunchKernelGGL(k_order_bins, dim3((ngroups + kOrderThreads - 1) / kOrderThreads), dim3(kOrderThreads), 0,
+                           s, d, ngroups);
+        hipLaunchKernelGGL(k_group_order, dim3(1), dim3(kOrderThreads), 0, s, d, ngroups);
+        order = d.order;
+    }
     hipLaunchKernelGGL((k_tree_walk<MODE, INSPECT, CELLS>), dim3(ngroups), dim3(64), 0, s, pm, n, d, recs, eps2,
-                       G, theta2, o);
+                       G, theta2, o, order);
     return hipGetLastError();
 }
 

@@ -27,6 +27,9 @@ struct TreeDev {
     double4 *s2a, *s2b;  // second moment about com: (xx, yy, zz, xy), (xz, yz, -, -)
     float4 *pp;          // pseudo-particle cells: kPseudo records (x, y, z, q) per node
     float4 *qr;          // quadrupole cells: (com, M), (Qxx, Qyy, Qzz, Qxy), (Qxz, Qyz, 0, 0)
+    int *order;          // dispatch order of the local-expansion walk (group indices)
+    unsigned short *obin;  // per group: the diag2 bin that sets the order
+    int *ohist;          // per 1024 groups: a histogram of those bins
 };
 
 struct HostTree {

@@ -183,6 +183,39 @@ def test_large_sampled_and_error_against_direct(orc):
     assert trunc < 0.1 * theta ** 2
 
 
+@pytest.mark.parametrize("cells,ocells", [("CELLS_LOCAL", 4), ("CELLS_MONOPOLE", 0)])
+def test_dispatch_order_changes_nothing(orc, cells, ocells):
+    """With 8192 groups or more the local-expansion walk runs the groups with
+    the largest boxes first (the monopole walk keeps ORB order either way).
+    Every body's result equals the ORB-order walk's (NBODY_TREE_ORDER=0) bit
+    for bit, every output record is written, and sampled targets match the
+    oracle.  A Plummer sphere of 2^19 bodies with leaf 4 has exactly 8192
+    groups of 64."""
+    import os
+    torch, nb = gpu()
+    n, leaf, theta, eps = 1 << 19, 4, 0.6, 0.01
+    pm, _ = ics.plummer(n, 780)
+    q, qh = _orb_input(torch, nb, pm, leaf)
+    assert nb.tree_shape(n, leaf)[1] == 8192
+    c = getattr(nb, cells)
+    out = torch.full_like(q, float("nan"))
+    nb.tree_accel(q, eps, theta, leaf, prec=nb.F32_F64ACC, out=out, cells=c)
+    os.environ["NBODY_TREE_ORDER"] = "0"
+    try:
+        ref = torch.full_like(q, float("nan"))
+        nb.tree_accel(q, eps, theta, leaf, prec=nb.F32_F64ACC, out=ref, cells=c)
+    finally:
+        del os.environ["NBODY_TREE_ORDER"]
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(out).all())
+    assert torch.equal(out, ref)
+    tg = np.random.default_rng(9).choice(n, 64, replace=False)
+    a, p = orc.tree_accel(widen32(qh), leaf, 64, theta, eps, targets=tg, cells=ocells)
+    got = host(out)
+    assert rms_rel(got[tg, :3], a) < 1e-6
+    assert rms_rel(got[tg, 3], p) < 1e-6
+
+
 def test_repeat_and_shape_change_same_bits():
     """Cached tables: the same call twice gives the same bits, also after a
     call of another shape in between."""
