@@ -329,30 +329,34 @@ def test_tree_leapfrog_energy():
     assert abs((k_end + u_end) / e[-1] - 1.0) < 1e-12
 
 
-def test_tree_force_replays_in_a_captured_graph():
+@pytest.mark.parametrize("n,cells", [(20000, "CELLS_MONOPOLE"), (1 << 19, "CELLS_LOCAL")])
+def test_tree_force_replays_in_a_captured_graph(n, cells):
     """After the first call for a shape (which uploads the node table), the
     tree force is kernel launches only: captured in a HIP graph it replays
-    bit for bit like eager calls, with eager work in between."""
+    bit for bit like eager calls, with eager work in between.  At 2^19
+    bodies the local-expansion walk's dispatch-order kernels are captured
+    too."""
     torch, nb = gpu()
-    pm, _ = ics.plummer(20000, 410)
+    c = getattr(nb, cells)
+    pm, _ = ics.plummer(n, 410)
     q, _ = _orb_input(torch, nb, pm, 4)
-    out_e = nb.tree_accel(q, 0.01, 0.6, 4, prec=nb.F32_F64ACC)
+    out_e = nb.tree_accel(q, 0.01, 0.6, 4, prec=nb.F32_F64ACC, cells=c)
     out_g = torch.empty_like(q)
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
-        nb.tree_accel(q, 0.01, 0.6, 4, prec=nb.F32_F64ACC, out=out_g)
+        nb.tree_accel(q, 0.01, 0.6, 4, prec=nb.F32_F64ACC, out=out_g, cells=c)
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
-        nb.tree_accel(q, 0.01, 0.6, 4, prec=nb.F32_F64ACC, out=out_g)
+        nb.tree_accel(q, 0.01, 0.6, 4, prec=nb.F32_F64ACC, out=out_g, cells=c)
     for rep in range(3):
         out_g.zero_()
         graph.replay()
         torch.cuda.synchronize()
         junk = torch.randn(1000, device="cuda").sum()
-        ref = nb.tree_accel(q, 0.01, 0.6, 4, prec=nb.F32_F64ACC)
+        ref = nb.tree_accel(q, 0.01, 0.6, 4, prec=nb.F32_F64ACC, cells=c)
         torch.cuda.synchronize()
         assert torch.equal(out_g, ref) and torch.equal(ref, out_e), rep
         del junk
