@@ -73,9 +73,8 @@ def test_ragged_sizes(orc, n, mode):
 @pytest.mark.parametrize("mode", ["F64", "F32_KAHAN", "F32"])
 def test_kernel_shapes(orc, tpl, js, jt, mode):
     """Every tuning shape gives the same answer (to rounding) as the oracle.
-    Split counts that are multiples of 8 take the XCD workgroup mapping (8
-    and 32 splits: one and four per XCD; 24: three, with a last workgroup row
-    of a ragged target count)."""
+    (The sources fit in one XCD's L2 here, so every shape keeps the plain
+    workgroup order; test_xcd_order_shapes covers the XCD order.)"""
     torch, nb = gpu()
     if mode == "F64" and tpl == 4:
         pytest.skip("FP64 kernel has tpl 1 and 2")
@@ -92,6 +91,36 @@ def test_kernel_shapes(orc, tpl, js, jt, mode):
     acc, pot = orc.accel(src, 0.01)
     bar = 1e-12 if mode == "F64" else 2e-6
     assert rms_rel(out[:, :3], acc) <= bar and rms_rel(out[:, 3], pot) <= bar
+
+
+@pytest.mark.parametrize("mode,n,tpl,js,jt", [("F32_F64ACC", 300001, 1, 8, 512), ("F32_KAHAN", 300001, 2, 24, 256),
+                                             ("F32", 300001, 1, 32, 512), ("F64", 150001, 1, 8, 512),
+                                             ("F64", 150001, 2, 16, 64)])
+def test_xcd_order_shapes(orc, mode, n, tpl, js, jt):
+    """Split counts that are multiples of 8, over sources larger than one
+    XCD's 4 MiB L2, take the XCD workgroup order (XCD x runs splits x J/8 to
+    (x + 1) J/8 - 1): 8, 16, 24 and 32 splits (one to four per XCD), ragged
+    target counts, FP32 and FP64 records.  Every output record is written
+    and sampled targets match the oracle."""
+    torch, nb = gpu()
+    pm, _ = ics.plummer(n, 11 + js)
+    dtype = torch.float64 if mode == "F64" else torch.float32
+    src = pm if mode == "F64" else widen32(pm)
+    prec = getattr(nb, mode)
+    nb.set_tuning(0, prec, tpl, js, jt)
+    try:
+        p = to_dev(torch, src, dtype)
+        out = torch.full_like(p, float("nan"))
+        nb.accel(p, 0.01, prec=prec, out=out)
+        torch.cuda.synchronize()
+    finally:
+        nb.set_tuning(0, prec)
+    got = host(out)
+    assert np.isfinite(got).all()
+    tg = ics.sample_targets(n, 256, 5 + js)
+    acc, pot = orc.accel(src, 0.01, targets=tg)
+    bar = 1e-12 if mode == "F64" else (1e-5 if mode == "F32" else 2e-6)
+    assert rms_rel(got[tg, :3], acc) <= bar and rms_rel(got[tg, 3], pot) <= bar
 
 
 @pytest.mark.parametrize("mode", ["F64", "F32_KAHAN"])
