@@ -75,7 +75,7 @@ def main():
                          "and one 1 GiB device copy (the copy calibrates byte counters); no JSON")
     ap.add_argument("--counters-variant", type=int, default=0, choices=(0, 1),
                     help="with --counters: 0 = the default kernel shape, 1 = sources staged in LDS "
-                         "(2 targets per lane, 4 source splits, tiles of 512)")
+                         "(2 targets per lane, 8 source splits, tiles of 512)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 "
@@ -103,7 +103,7 @@ def main():
 
     if args.counters:
         if args.counters_variant == 1:
-            nb.set_tuning(0, prec, 2, 4, 512, 1)
+            nb.set_tuning(0, prec, 2, 8, 512, 1)
         for _ in range(2):
             nb.accel(pm, eps, prec=prec, out=acc)
         nb.set_tuning(0, prec)
