@@ -283,6 +283,224 @@ __global__ __launch_bounds__(64) void k_fmm_walk(FmmDev F, const int *__restrict
     if (__ballot(bad) && lane == 0) atomicOr(&F.tot[0], 1ull);
 }
 
+// TPW target nodes per wave: positions TPW b .. TPW b + TPW - 1 of
+// one depth.  Below the root every depth holds whole sibling pairs, adjacent
+// in preorder, so targets 2j and 2j + 1 are the children of one parent and
+// inherit the same list; each distinct inherited list is loaded once.  The
+// stack holds the union of the targets' pending sources, each entry tagged
+// with the targets that still need it (bit k for target k, in the four high
+// bits of the entry; node ids stay below 2^28, which the host checks).  A
+// popped source is gathered once and classified for each of its targets by
+// the same tests as the one-target walk; it is split (children pushed,
+// tagged with the targets that split it) if any target splits it.  Each
+// target's lists are written at ballot ranks in pop order, so every pass
+// produces the same lists for a target: the same entries as the one-target
+// walk's, in another order.
+constexpr unsigned kTagShift = 28, kIdMask = (1u << kTagShift) - 1;
+
+template <int WMODE, int TPW>
+__global__ __launch_bounds__(64) void k_fmm_walk_multi(FmmDev F, const int *__restrict__ ids, int first, int count,
+                                                       int parity, double theta2, SlotDepth sd)
+{
+    constexpr bool FILL = WMODE != kWalkCount;
+    __shared__ unsigned stk[kWalkStack];
+    const int lane = threadIdx.x;
+    const int nn = F.nn;
+    int *pass_out = parity ? F.pass1 : F.pass0;
+    const int *pass_in = parity ? F.pass0 : F.pass1;  // the previous depth's buffer
+    int tpos[TPW], A[TPW], parent[TPW];
+    int4 na[TPW];
+    double4 ca[TPW];
+    bool aleaf[TPW], live[TPW];
+    double b0[TPW][3], b1[TPW][3];  // each target's box (M2P test)
+    long o[TPW][kKinds], room[TPW][kKinds];
+    int c[TPW][kKinds];
+    // inherited lists: segment g is list seg_in[g] of seg_n[g] entries for the targets seg_tag[g]
+    const int *seg_in[TPW];
+    int seg_n[TPW];
+    unsigned seg_tag[TPW];
+    int nseg = 0;
+#pragma unroll
+    for (int k = 0; k < TPW; ++k) {
+        tpos[k] = TPW * blockIdx.x + k;
+        live[k] = tpos[k] < count;
+        A[k] = live[k] ? ids[tpos[k]] : ids[TPW * blockIdx.x];
+        na[k] = F.node[A[k]];
+        ca[k] = F.comd[A[k]];
+        aleaf[k] = na[k].z < 0;
+        const float4 l = F.lo[A[k]], h = F.hi[A[k]];
+        b0[k][0] = l.x;
+        b0[k][1] = l.y;
+        b0[k][2] = l.z;
+        b1[k][0] = h.x;
+        b1[k][1] = h.y;
+        b1[k][2] = h.z;
+        parent[k] = A[k] == 0 ? -1 : F.parent[A[k]];
+#pragma unroll
+        for (int q = 0; q < kKinds; ++q) {
+            c[k][q] = 0;
+            if (WMODE == kWalkSlot) {
+                o[k][q] = sd.base[q] + (long)tpos[k] * sd.cap[q];
+                room[k][q] = sd.cap[q];
+            } else if (FILL) {
+                o[k][q] = F.off[q * nn + A[k]];
+                room[k][q] = cap_of(F, q) - o[k][q];  // offsets are global: the rest of the buffer
+            } else {
+                o[k][q] = 0;
+                room[k][q] = cap_of(F, q);
+            }
+        }
+        if (!live[k]) continue;
+        if (k > 0 && live[k - 1] && parent[k] >= 0 && parent[k] == parent[k - 1]) {
+            seg_tag[nseg - 1] |= 1u << k;  // the sibling's list serves both
+            continue;
+        }
+        if (A[k] == 0) {
+            seg_in[nseg] = nullptr;
+            seg_n[nseg] = 1;
+        } else {
+            int m = F.cnt[kPass * nn + parent[k]];
+            const long base = F.off[kPass * nn + parent[k]];
+            if (WMODE == kWalkSlot) m = min(m, sd.prev_pass);  // the parent's slot overflowed
+            if (base + m > F.cap_pass) m = (int)max(0L, F.cap_pass - base);  // the parent's depth overflowed
+            seg_in[nseg] = pass_in + base;
+            seg_n[nseg] = m;
+        }
+        seg_tag[nseg] = 1u << k;
+        ++nseg;
+    }
+    int seg = 0, next = 0, top = 0;
+    bool bad = false;
+    for (;;) {
+        while (top < 64 && seg < nseg) {  // refill
+            const int m = seg_n[seg];
+            const int take = min(64, m - next);
+            if (take > 0) {
+                if (lane < take)
+                    stk[top + lane] = (seg_in[seg] ? (unsigned)seg_in[seg][next + lane] : 0u) |
+                                      (seg_tag[seg] << kTagShift);
+                top += take;
+                next += take;
+            }
+            if (next >= m) {
+                ++seg;
+                next = 0;
+            }
+        }
+        if (top == 0) break;
+        const int kpop = min(64, top);
+        top -= kpop;
+        __syncthreads();
+        const bool act = lane < kpop;
+        const unsigned e = act ? stk[top + lane] : 0u;
+        __syncthreads();
+        int B = (int)(e & kIdMask);
+        const unsigned tag = e >> kTagShift;
+        if ((unsigned)B >= (unsigned)nn) B = 0;  // only after an overflow upstream
+        int4 nb = make_int4(0, 0, -1, -1);
+        double4 cb = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (act) {
+            nb = F.node[B];
+            cb = F.comd[B];
+        }
+        unsigned split_tag = 0;
+#pragma unroll
+        for (int k = 0; k < TPW; ++k) {
+            bool m2l = false, m2p = false, p2p = false, pass = false, split = false;
+            if (act && (tag >> k & 1u)) {
+                const bool apart = !fmm_overlap(na[k], nb);
+                if (apart) {
+                    const double dx = ca[k].x - cb.x, dy = ca[k].y - cb.y, dz = ca[k].z - cb.z;
+                    const double dist2 = (dx * dx + dy * dy) + dz * dz;
+                    m2l = ca[k].w + cb.w < theta2 * dist2;
+                }
+                if (!m2l && aleaf[k] && apart) {
+                    const double gx = box_gap(cb.x, b0[k][0], b1[k][0]);
+                    const double gy = box_gap(cb.y, b0[k][1], b1[k][1]);
+                    const double gz = box_gap(cb.z, b0[k][2], b1[k][2]);
+                    const double D2 = (gx * gx + gy * gy) + gz * gz;
+                    m2p = cb.w < theta2 * D2;
+                }
+                if (!m2l && !m2p) {
+                    const bool bleaf = nb.z < 0;
+                    if (aleaf[k] && bleaf)
+                        p2p = true;
+                    else if (bleaf || (!aleaf[k] && ca[k].w >= cb.w))
+                        pass = true;
+                    else
+                        split = true;
+                }
+            }
+            const unsigned long long mm = __ballot(m2l), mc = __ballot(m2p), mp = __ballot(p2p),
+                                     mq = __ballot(pass);
+            if (FILL) {
+                if (m2l && !put_entry(F.m2l, o[k][kM2L], c[k][kM2L], room[k][kM2L], mm, B)) bad = true;
+                if (m2p && !put_entry(F.m2p, o[k][kM2P], c[k][kM2P], room[k][kM2P], mc, B)) bad = true;
+                if (p2p && !put_entry(F.p2p, o[k][kP2P], c[k][kP2P], room[k][kP2P], mp, nb.x)) bad = true;
+                if (pass && !put_entry(pass_out, o[k][kPass], c[k][kPass], room[k][kPass], mq, B)) bad = true;
+            }
+            c[k][kM2L] += __popcll(mm);
+            c[k][kM2P] += __popcll(mc);
+            c[k][kP2P] += __popcll(mp);
+            c[k][kPass] += __popcll(mq);
+            if (split) split_tag |= 1u << k;
+        }
+        const unsigned long long ms = __ballot(split_tag != 0);
+        const int ns = __popcll(ms);
+        if (top + 2 * ns > kWalkStack) {  // cannot happen for trees the host admits
+            bad = true;
+            break;
+        }
+        if (split_tag) {
+            const int q = top + 2 * (int)fmm_rank(ms);
+            stk[q] = (unsigned)nb.w | (split_tag << kTagShift);
+            stk[q + 1] = (unsigned)nb.z | (split_tag << kTagShift);
+        }
+        top += 2 * ns;
+        __syncthreads();
+    }
+    if (WMODE != kWalkFill && lane == 0) {
+#pragma unroll
+        for (int k = 0; k < TPW; ++k) {
+            if (!live[k]) continue;
+#pragma unroll
+            for (int q = 0; q < kKinds; ++q) {
+                F.cnt[q * nn + A[k]] = c[k][q];
+                if (WMODE == kWalkCount)
+                    F.lcnt[q * nn + first + tpos[k]] = c[k][q];
+                else
+                    F.off[q * nn + A[k]] = (int)o[k][q];
+            }
+        }
+    }
+    if (__ballot(bad) && lane == 0) atomicOr(&F.tot[0], 1ull);
+}
+
+// Target nodes per wave at a depth of `count` nodes: the deep depths, with
+// enough nodes to fill the chip more than once, walk 2 per wave (half the
+// waves, each source gathered once for both); the others 1, for
+// parallelism.  Measured at 2^20 (leaf 8, theta 0.5): the depths of 8192 to
+// 131072 nodes took 239-1019 us against 311-1141 us with one target per
+// wave, and 708-1299 us with 4 per wave from 32768 nodes on.
+constexpr int kPairNodes = 8192;
+int walk_tpw(int count, int nn)
+{
+    if (nn > (int)kIdMask) return 1;
+    return count >= kPairNodes ? 2 : 1;
+}
+
+template <int WMODE>
+void launch_walk_depth(int tpw, const FmmDev &F, const int *ids, int first, int count, int parity, double theta2,
+                       const SlotDepth &sd, hipStream_t s)
+{
+    if (tpw == 2)
+        hipLaunchKernelGGL((k_fmm_walk_multi<WMODE, 2>), dim3((count + 1) / 2), dim3(64), 0, s, F, ids, first, count,
+                           parity, theta2, sd);
+    else
+        hipLaunchKernelGGL(k_fmm_walk<WMODE>, dim3(count), dim3(64), 0, s, F, ids, first, count, parity, theta2,
+                           sd);
+}
+
 // Sum over the wave of four values (fixed butterfly).
 __device__ __forceinline__ void wave_sum4(long (&s)[kKinds])
 {
@@ -823,12 +1041,11 @@ hipError_t launch_traversal(const FmmDev &F, const FmmPlan &p, double theta2, hi
         const int first = p.depth_off[d], count = p.depth_off[d + 1] - first;
         const int *ids = p.d_by_depth + first;
         const int nblk = (count + kScanBlock - 1) / kScanBlock;
-        hipLaunchKernelGGL(k_fmm_walk<kWalkCount>, dim3(count), dim3(64), 0, s, F, ids, first, count, d & 1,
-                           theta2, SlotDepth{});
+        const int tpw = walk_tpw(count, F.nn);
+        launch_walk_depth<kWalkCount>(tpw, F, ids, first, count, d & 1, theta2, SlotDepth{}, s);
         hipLaunchKernelGGL(k_fmm_scan_part, dim3(nblk), dim3(256), 0, s, F, first, count);
         hipLaunchKernelGGL(k_fmm_scan_fin, dim3(nblk), dim3(256), 0, s, F, ids, first, count, d, nblk);
-        hipLaunchKernelGGL(k_fmm_walk<kWalkFill>, dim3(count), dim3(64), 0, s, F, ids, first, count, d & 1,
-                           theta2, SlotDepth{});
+        launch_walk_depth<kWalkFill>(tpw, F, ids, first, count, d & 1, theta2, SlotDepth{}, s);
         e = hipGetLastError();
     }
     return e;
@@ -841,8 +1058,9 @@ hipError_t launch_traversal_slots(const FmmDev &F, const FmmPlan &p, double thet
     hipError_t e = hipGetLastError();
     for (int d = 0; d <= p.depth && e == hipSuccess; ++d) {
         const int first = p.depth_off[d], count = p.depth_off[d + 1] - first;
-        hipLaunchKernelGGL(k_fmm_walk<kWalkSlot>, dim3(count), dim3(64), 0, s, F, p.d_by_depth + first, first,
-                           count, d & 1, theta2, g_slots.depth[d]);
+        const int tpw = walk_tpw(count, F.nn);
+        launch_walk_depth<kWalkSlot>(tpw, F, p.d_by_depth + first, first, count, d & 1, theta2, g_slots.depth[d],
+                                     s);
         e = hipGetLastError();
     }
     return e;

@@ -51,6 +51,37 @@ def test_lists_match_oracle(orc, n, leaf, theta, kind):
         assert got["m2l_cnt"].sum() == 0 and got["m2p_cnt"].sum() == 0
 
 
+@pytest.mark.parametrize("n,leaf,theta,kind", [(262144, 8, 0.5, "collide"), (300001, 4, 0.6, "plummer")])
+def test_lists_match_oracle_two_targets_per_wave(orc, n, leaf, theta, kind):
+    """Depths of 32768 nodes or more are walked two target nodes per wave,
+    two siblings (the union of their inherited sources, each tagged with the
+    targets that need it): every node's lists still equal the oracle's as
+    sets, and the forces on sampled targets match the oracle's FMM."""
+    torch, nb = gpu()
+    pm, _ = GEN[kind](n, 790 + n)
+    q, qh = _orb_input(torch, nb, pm, leaf)
+    nodes = nb.tree_shape(n, leaf, nodes=True)[2]
+    depth = np.zeros(nodes.shape[0], dtype=np.int64)
+    for a in range(nodes.shape[0]):  # preorder: parents first
+        for ch in nodes[a, 2:]:
+            if ch >= 0:
+                depth[ch] = depth[a] + 1
+    per_depth = np.bincount(depth)
+    assert per_depth.max() >= 32768
+    got = dict(zip(("m2l_cnt", "m2p_cnt", "p2p_cnt", "m2l", "m2p", "p2p"),
+                   (host(t).astype(np.int64) for t in nb.fmm_lists(q, theta, leaf))))
+    want = orc.fmm_lists(qh, leaf, theta)
+    for k in ("m2l", "m2p", "p2p"):
+        c = got[k + "_cnt"]
+        assert np.array_equal(c, want[k + "_cnt"]), k
+        assert np.array_equal(_per_node_sorted(got[k], c), _per_node_sorted(want[k], want[k + "_cnt"])), k
+    out = host(nb.fmm_accel(q, 0.01, theta, leaf, prec=nb.F32_F64ACC))
+    tg = ics.sample_targets(n, 128, 3)
+    a, p = orc.fmm_accel(widen32(qh), leaf, theta, 0.01, targets=tg)
+    assert rms_rel(out[tg, :3], a) < 1e-6
+    assert rms_rel(out[tg, 3], p) < 1e-6
+
+
 @pytest.mark.parametrize("prec,tol_rms,tol_max", [("F32_F64ACC", 1e-6, 2e-5), ("F32_KAHAN", 1e-6, 2e-5),
                                                   ("F32", 2e-6, 1e-4)])
 @pytest.mark.parametrize("theta,leaf", [(0.0, 8), (0.5, 8), (0.7, 4), (0.6, 16)])
