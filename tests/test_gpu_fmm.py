@@ -205,13 +205,15 @@ def test_g_scales_the_result(orc):
     assert rms_rel(got[:, 3], p) < 1e-6
 
 
-def test_compact_lists_equal_the_slot_layout(orc):
+@pytest.mark.parametrize("n", [20000, 262144])
+def test_compact_lists_equal_the_slot_layout(orc, n):
     """With the slot layout's memory budget set to nothing, the traversal
     counts, scans and fills compact lists instead; the lists and the forces
-    are the same, bit for bit."""
+    are the same, bit for bit (at 2^18 also with the deep depths walked two
+    target nodes per wave)."""
     import os
     torch, nb = gpu()
-    pm, _ = ics.plummer(20000, 770)
+    pm, _ = ics.plummer(n, 770)
     q, _ = _orb_input(torch, nb, pm, 8)
     nb.release()
     slot = nb.fmm_accel(q, 0.01, 0.5, 8, prec=nb.F32_F64ACC).clone()
