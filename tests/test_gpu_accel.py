@@ -123,6 +123,29 @@ def test_xcd_order_shapes(orc, mode, n, tpl, js, jt):
     assert rms_rel(got[tg, :3], acc) <= bar and rms_rel(got[tg, 3], pot) <= bar
 
 
+def test_xcd_order_target_subset(orc):
+    """A target range (one GPU's share) over sources larger than an XCD's L2,
+    split 8 ways in the XCD order: the records of exactly the requested
+    targets are written and match the oracle."""
+    torch, nb = gpu()
+    n, tb, tc = 300001, 1000, 200001
+    pm, _ = ics.plummer(n, 23)
+    src = widen32(pm)
+    nb.set_tuning(0, nb.F32_F64ACC, 1, 8, 512)
+    try:
+        p = to_dev(torch, src, torch.float32)
+        out = torch.full((tc, 4), float("nan"), dtype=torch.float32, device=p.device)
+        nb.accel(p, 0.01, prec=nb.F32_F64ACC, target_begin=tb, target_count=tc, out=out)
+        torch.cuda.synchronize()
+    finally:
+        nb.set_tuning(0, nb.F32_F64ACC)
+    got = host(out)
+    assert np.isfinite(got).all()
+    k = ics.sample_targets(tc, 256, 29)
+    acc, pot = orc.accel(src, 0.01, targets=tb + k)
+    assert rms_rel(got[k, :3], acc) <= 2e-6 and rms_rel(got[k, 3], pot) <= 2e-6
+
+
 @pytest.mark.parametrize("mode", ["F64", "F32_KAHAN"])
 def test_target_subsets(orc, mode):
     torch, nb = gpu()
