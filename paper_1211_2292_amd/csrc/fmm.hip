@@ -26,8 +26,9 @@
 //   of the recursion are those inherited from its parent (the parent's
 //   pass-down list) closed under source splits: one wave per node pops up to
 //   64 pending sources per step from an LDS stack, one per lane, and
-//   classifies them (ballot ranks give every output a fixed position).  Each
-//   depth runs one walk that writes every node's lists into slots of a
+//   classifies them (ballot ranks give every output a fixed position); at
+//   the deep depths one wave walks two sibling nodes, gathering each source
+//   once for both.  Each depth runs one walk that writes every node's lists into slots of a
 //   per-depth capacity; when that layout would take more than its memory
 //   budget, each depth instead runs a count walk, a two-kernel scan (block
 //   sums, then offsets) and a fill walk into compact lists.  Writes are

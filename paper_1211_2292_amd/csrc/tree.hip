@@ -37,6 +37,8 @@
 //   whose children would overflow the stack is summed body by body instead,
 //   which is exact.  In inspection mode the same walk writes the node ids of
 //   the accepted cells and of the rejected leaves instead of summing.
+// * k_order_bins, k_group_order: the order in which the local-expansion walk
+//   takes its groups when there are many (largest boxes first; see there).
 //
 // Order 2 (pseudo-particle multipoles: Makino, J. Comput. Phys. 151, 1999,
 // the paper's reference [20], which Section VI cites for the O(N) fast
