@@ -183,20 +183,22 @@ def test_large_sampled_and_error_against_direct(orc):
     assert trunc < 0.1 * theta ** 2
 
 
-@pytest.mark.parametrize("cells,ocells", [("CELLS_LOCAL", 4), ("CELLS_MONOPOLE", 0)])
-def test_dispatch_order_changes_nothing(orc, cells, ocells):
+@pytest.mark.parametrize("n,ng,cells,ocells", [(1 << 19, 8192, "CELLS_LOCAL", 4), (1 << 19, 8192, "CELLS_MONOPOLE", 0),
+                                              (1100001, 29241, "CELLS_LOCAL", 4)])
+def test_dispatch_order_changes_nothing(orc, n, ng, cells, ocells):
     """With 8192 groups or more the local-expansion walk runs the groups with
     the largest boxes first (the monopole walk keeps ORB order either way).
     Every body's result equals the ORB-order walk's (NBODY_TREE_ORDER=0) bit
     for bit, every output record is written, and sampled targets match the
     oracle.  A Plummer sphere of 2^19 bodies with leaf 4 has exactly 8192
-    groups of 64."""
+    groups of 64; 1100001 bodies give 29241 groups, more than one chunk of
+    the ordering kernel and not a multiple of its 1024 threads."""
     import os
     torch, nb = gpu()
-    n, leaf, theta, eps = 1 << 19, 4, 0.6, 0.01
+    leaf, theta, eps = 4, 0.6, 0.01
     pm, _ = ics.plummer(n, 780)
     q, qh = _orb_input(torch, nb, pm, leaf)
-    assert nb.tree_shape(n, leaf)[1] == 8192
+    assert nb.tree_shape(n, leaf)[1] == ng
     c = getattr(nb, cells)
     out = torch.full_like(q, float("nan"))
     nb.tree_accel(q, eps, theta, leaf, prec=nb.F32_F64ACC, out=out, cells=c)
