@@ -578,12 +578,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(CELLS == kCe
 // of the chip idle behind them; started first, they overlap with the rest
 // (measured 7-10% faster at theta 0.5-1.0).  The monopole and quadrupole
 // walks, whose costs vary less, measured no gain and keep ORB order, which
-// L2 locality favours.  k_order_bins puts each group's diag2 in one of 1024 bins by its
-// FP32 bit pattern (exponent and two mantissa bits); k_group_order, one
-// workgroup, takes the bins from the top down until they hold 1/16 of the
-// groups and writes a stable partition of the group indices: those groups,
-// then the others, each in ORB order.  Only the order in which the
-// workgroups run changes, never what a group computes.
+// L2 locality favours.  k_order_bins puts each group's diag2 in one of 1024
+// bins by its FP32 bit pattern (exponent and two mantissa bits);
+// k_group_order, one workgroup, takes the bins from the top down until they
+// hold 1/16 of the groups and writes a stable partition of the group
+// indices: those groups, then the others, each in ORB order.  Only the order
+// in which the workgroups run changes, never what a group computes.
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderBins = 1024;
 constexpr int kOrderMinGroups = 8192;  // fewer groups run in about one round
@@ -608,9 +608,9 @@ __global__ __launch_bounds__(kOrderThreads) void k_order_bins(TreeDev T, int ng)
 }
 
 // Inclusive sum over the workgroup's threads (within each wave by shuffles,
-// then over the waves' totals in LDS), and the workgroup's total; every
-// thread must call it.
-__device__ __forceinline__ int block_incl_sum(int *sc, int v, int &total)
+// then over the waves' totals in LDS), and the workgroup's total if asked
+// for; every thread must call it.
+__device__ __forceinline__ int block_incl_sum(int *sc, int v, int *total = nullptr)
 {
     constexpr int kWaves = kOrderThreads / 64;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -629,7 +629,7 @@ __device__ __forceinline__ int block_incl_sum(int *sc, int v, int &total)
         all += s;
     }
     __syncthreads();
-    total = all;
+    if (total) *total = all;
     return before + v;
 }
 
@@ -660,9 +660,7 @@ __global__ __launch_bounds__(kOrderThreads) void k_group_order(TreeDev T, int ng
     // groups in bins >= kOrderBins - 1 - t, counted from the top bin down
     const int want = max(1, ng / 16);
     const int h = hist[kOrderBins - 1 - t];
-    int all;  // = ng
-    const int top = block_incl_sum(sc, h, all);
-    (void)all;
+    const int top = block_incl_sum(sc, h);
     if (top >= want && top - h < want) {
         cut = kOrderBins - 1 - t;
         ftot = top;
@@ -682,7 +680,7 @@ __global__ __launch_bounds__(kOrderThreads) void k_group_order(TreeDev T, int ng
 #pragma unroll
         for (int k = 0; k < kOrderPer; ++k) first += c0 + r0 + k < ng && cb[r0 + k] >= c;
         int chunk_taken;
-        const int incl = block_incl_sum(sc, first, chunk_taken);
+        const int incl = block_incl_sum(sc, first, &chunk_taken);
         int a = done + incl - first;
         int b = F + (c0 + r0) - a;  // the others before this run come after all taken groups
         for (int k = 0; k < kOrderPer; ++k) {
