@@ -295,6 +295,24 @@ __device__ __forceinline__ uint32_t block_reduce_u32(uint32_t v, bool is_min, ui
     return r;
 }
 
+// Inclusive sum over the workgroup's threads (one 256-thread workgroup):
+// within each wave by shuffles, then the totals of the waves before it.
+__device__ __forceinline__ uint32_t block_incl_scan_u32(uint32_t v, uint32_t *scratch)
+{
+    static_assert(kOrbBlock == 256, "one bin per thread");
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)v, o);
+        if (lane >= o) v += y;
+    }
+    __syncthreads();
+    if (lane == 63) scratch[w] = v;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int k = 0; k < w; ++k) before += scratch[k];
+    return v + before;
+}
+
 // Finishes the recursion of a node of at most 64 bodies (positions
 // [lo, lo + m) of idx) with one wave, one position per lane, every node of a
 // level split at once.  keys: per-wave LDS of 3 x 64 total-order keys.  The
@@ -454,26 +472,22 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_block(const int2 *__restrict_
         for (int round = 0; round < 8; ++round) {
             __syncthreads();
             h[threadIdx.x] = 0u;
+            const uint64_t prefix = kth_s;
+            const uint32_t kr = krem_s;
             __syncthreads();
             const int shift = 56 - 8 * round;
-            const uint64_t prefix = kth_s;
             for (int e = threadIdx.x; e < m; e += kOrbBlock) {
                 const uint64_t key = body_key(xyz, n, axis, idx[lo + e]);
                 if (round == 0 || (key >> (shift + 8)) == prefix) atomicAdd(&h[(key >> shift) & 0xFF], 1u);
             }
             __syncthreads();
-            if (threadIdx.x == 0) {
-                uint32_t acc = 0, kr = krem_s;
-                int bin = 255;
-                for (int b = 0; b < 256; ++b) {
-                    if (acc + h[b] >= kr) {
-                        bin = b;
-                        break;
-                    }
-                    acc += h[b];
-                }
-                kth_s = (prefix << 8) | (uint64_t)bin;
-                krem_s = kr - acc;
+            // the bin holding rank kr (1-based): the one thread whose
+            // inclusive sum over the bins reaches kr first decides
+            const uint32_t hv = h[threadIdx.x];
+            const uint32_t inc = block_incl_scan_u32(hv, red);
+            if (inc >= kr && inc - hv < kr) {
+                kth_s = (prefix << 8) | (uint64_t)threadIdx.x;
+                krem_s = kr - (inc - hv);
             }
         }
         __syncthreads();
