@@ -409,9 +409,10 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_block(const int2 *__restrict_
 {
     __shared__ int32_t idx[kMaxBlockSeg];
     __shared__ int32_t tmp[kMaxBlockSeg];
+    __shared__ uint32_t akey[kMaxBlockSeg];  // the current node's keys along its split axis
     __shared__ uint32_t h[256];
     __shared__ uint32_t red[kOrbBlock / 64];
-    __shared__ uint32_t cnt[2];
+    __shared__ uint32_t wl[kOrbBlock / 64], wr[kOrbBlock / 64];
     __shared__ uint64_t kth_s;
     __shared__ uint32_t krem_s;
     constexpr int kMaxTask = kMaxBlockSeg / kWaveSeg * 2 + 2;
@@ -464,6 +465,8 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_block(const int2 *__restrict_
         const int axis = pick_axis(bb);
         const int L = (m + leaf - 1) / leaf;
         const int k = min(m, leaf * ((L + 1) / 2));
+        // the split axis's keys, gathered once for the 8 rounds and the partition
+        for (int e = threadIdx.x; e < m; e += kOrbBlock) akey[e] = tkey(xyz[(size_t)axis * n + idx[lo + e]]);
         // radix select of the k-th smallest key
         if (threadIdx.x == 0) {
             kth_s = 0;
@@ -477,7 +480,7 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_block(const int2 *__restrict_
             __syncthreads();
             const int shift = 56 - 8 * round;
             for (int e = threadIdx.x; e < m; e += kOrbBlock) {
-                const uint64_t key = body_key(xyz, n, axis, idx[lo + e]);
+                const uint64_t key = ((uint64_t)akey[e] << 32) | (uint32_t)idx[lo + e];
                 if (round == 0 || (key >> (shift + 8)) == prefix) atomicAdd(&h[(key >> shift) & 0xFF], 1u);
             }
             __syncthreads();
@@ -492,19 +495,48 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_block(const int2 *__restrict_
         }
         __syncthreads();
         const uint64_t kth = kth_s;
-        if (threadIdx.x == 0) cnt[0] = cnt[1] = 0u;
-        __syncthreads();
-        for (int e = threadIdx.x; e < m; e += kOrbBlock) {
-            const int b = idx[lo + e];
-            if (body_key(xyz, n, axis, b) <= kth) {
-                const uint32_t q = atomicAdd(&cnt[0], 1u);
-                if (q < (uint32_t)k) tmp[lo + q] = b;
-            } else {
-                const uint32_t q = atomicAdd(&cnt[1], 1u);
-                if (q < (uint32_t)(m - k)) tmp[lo + k + q] = b;
+        // partition: keys <= the k-th key go left, in position order within
+        // each side (ballot ranks, then the waves before, then the chunks
+        // before); the order inside a side does not change the result
+        {
+            const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+            int dl = 0, dr = 0;  // entries placed by the chunks before
+            for (int e0 = 0; e0 < m; e0 += kOrbBlock) {
+                const int e = e0 + threadIdx.x;
+                const bool act = e < m;
+                const int b = act ? idx[lo + e] : 0;
+                const bool left = act && (((uint64_t)akey[act ? e : 0] << 32) | (uint32_t)b) <= kth;
+                const bool right = act && !left;
+                const unsigned long long bl = __ballot(left), br = __ballot(right);
+                if (lane == 0) {
+                    wl[w] = (uint32_t)__popcll(bl);
+                    wr[w] = (uint32_t)__popcll(br);
+                }
+                __syncthreads();
+                int pl = 0, pr = 0, cl = 0, cr = 0;
+                for (int v = 0; v < kOrbBlock / 64; ++v) {
+                    if (v < w) {
+                        pl += (int)wl[v];
+                        pr += (int)wr[v];
+                    }
+                    cl += (int)wl[v];
+                    cr += (int)wr[v];
+                }
+                const int rl = __builtin_amdgcn_mbcnt_hi((unsigned)(bl >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bl, 0u));
+                const int rr = __builtin_amdgcn_mbcnt_hi((unsigned)(br >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)br, 0u));
+                if (left) {
+                    const int q = dl + pl + rl;
+                    if (q < k) tmp[lo + q] = b;
+                }
+                if (right) {
+                    const int q = dr + pr + rr;
+                    if (q < m - k) tmp[lo + k + q] = b;
+                }
+                dl += cl;
+                dr += cr;
+                __syncthreads();  // wl, wr are reused by the next chunk
             }
         }
-        __syncthreads();
         for (int e = threadIdx.x; e < m; e += kOrbBlock) idx[lo + e] = tmp[lo + e];
         __syncthreads();
         // right first so that the left child is processed next
