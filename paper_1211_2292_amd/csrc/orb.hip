@@ -31,6 +31,7 @@ constexpr int kSmall = 2048;        // phase A splits segments larger than this
 constexpr int kMaxBlockSeg = 4096;  // largest segment phase B accepts (and max leaf)
 constexpr int kChunk = 4096;        // elements per phase-A workgroup
 constexpr int kOrbBlock = 256;
+constexpr int kChunkPer = kChunk / kOrbBlock;  // elements per thread of a phase-A workgroup
 
 namespace {
 
@@ -57,32 +58,41 @@ __device__ __forceinline__ int pick_axis(const uint32_t *bb)
     return axis;
 }
 
-__device__ __forceinline__ uint64_t body_key(const float *__restrict__ xyz, int n, int axis, int b)
-{
-    return ((uint64_t)tkey(xyz[(size_t)axis * n + b]) << 32) | (uint32_t)b;
-}
-
+// FP32 coordinates by original index (xyz), and their total-order keys in
+// the current order (identity at the start).
 template <typename V>
 __global__ __launch_bounds__(kOrbBlock) void k_orb_coords(const V *__restrict__ pm, int n,
                                                           float *__restrict__ xyz,
+                                                          uint32_t *__restrict__ keys,
                                                           int32_t *__restrict__ cur)
 {
     const int i = blockIdx.x * kOrbBlock + threadIdx.x;
     if (i >= n) return;
     const V p = pm[i];
-    xyz[i] = (float)p.x;
-    xyz[(size_t)n + i] = (float)p.y;
-    xyz[2 * (size_t)n + i] = (float)p.z;
+    const float f[3] = {(float)p.x, (float)p.y, (float)p.z};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        xyz[(size_t)a * n + i] = f[a];
+        keys[(size_t)a * n + i] = tkey(f[a]);
+    }
     cur[i] = i;
 }
 
 // Per-segment state of one phase-A level.
+enum SegMode : int {
+    kSelect = 0,  // radix select: histogram the next digit inside the prefix
+    kFind = 1,    // one key holds the prefix: the next pass reads it whole
+    kDone = 2,    // the k-th key is known
+};
 struct SegState {
     uint32_t bb[6];    // min keys x,y,z then max keys x,y,z
     int axis;
     int krem;          // rank still to find inside the current prefix
     uint64_t prefix;   // digits of the k-th key found so far
+    uint64_t full;     // the k-th key, written by the kFind pass
     uint32_t lcnt, rcnt;
+    uint32_t arrived;  // workgroups of the current launch done with the segment
+    int mode;          // SegMode
 };
 
 // seg table: (start, size, k) per segment; chunk table: (seg, begin, end)
@@ -101,7 +111,10 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_init(const int3 *__restrict__
         z.axis = 0;
         z.krem = segs[s].z;
         z.prefix = 0;
+        z.full = 0;
         z.lcnt = z.rcnt = 0;
+        z.arrived = 0;
+        z.mode = kSelect;
         st[s] = z;
     }
     hist[(size_t)s * 256 + threadIdx.x] = 0u;
@@ -116,183 +129,6 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v)
 {
     for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o));
     return v;
-}
-
-__global__ __launch_bounds__(kOrbBlock) void k_orb_bbox(const int3 *__restrict__ chunks,
-                                                        const float *__restrict__ xyz, int n,
-                                                        const int32_t *__restrict__ cur,
-                                                        SegState *__restrict__ st)
-{
-    const int3 c = chunks[blockIdx.x];
-    uint32_t lo[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, hi[3] = {0u, 0u, 0u};
-    for (int p = c.y + threadIdx.x; p < c.z; p += kOrbBlock) {
-        const int b = cur[p];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const uint32_t k = tkey(xyz[(size_t)a * n + b]);
-            lo[a] = min(lo[a], k);
-            hi[a] = max(hi[a], k);
-        }
-    }
-    __shared__ uint32_t red[kOrbBlock / 64][6];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        lo[a] = wave_min(lo[a]);
-        hi[a] = wave_max(hi[a]);
-    }
-    if (lane == 0)
-        for (int a = 0; a < 3; ++a) {
-            red[w][a] = lo[a];
-            red[w][3 + a] = hi[a];
-        }
-    __syncthreads();
-    if (threadIdx.x < 6) {
-        uint32_t v = red[0][threadIdx.x];
-        for (int k = 1; k < kOrbBlock / 64; ++k)
-            v = threadIdx.x < 3 ? min(v, red[k][threadIdx.x]) : max(v, red[k][threadIdx.x]);
-        if (threadIdx.x < 3)
-            atomicMin(&st[c.x].bb[threadIdx.x], v);
-        else
-            atomicMax(&st[c.x].bb[threadIdx.x], v);
-    }
-}
-
-__global__ __launch_bounds__(kOrbBlock) void k_orb_axis(int nseg, SegState *__restrict__ st)
-{
-    const int s = blockIdx.x * kOrbBlock + threadIdx.x;
-    if (s < nseg) st[s].axis = pick_axis(st[s].bb);
-}
-
-// Histogram of digit `round` (8 bits, most significant first) of the keys
-// that share the prefix found so far.
-__global__ __launch_bounds__(kOrbBlock) void k_orb_hist(const int3 *__restrict__ chunks,
-                                                        const float *__restrict__ xyz, int n,
-                                                        const int32_t *__restrict__ cur,
-                                                        const SegState *__restrict__ st,
-                                                        uint32_t *__restrict__ hist, int round)
-{
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0u;
-    __syncthreads();
-    const int3 c = chunks[blockIdx.x];
-    const int axis = st[c.x].axis;
-    const uint64_t prefix = st[c.x].prefix;
-    const int shift = 56 - 8 * round;
-    for (int p = c.y + threadIdx.x; p < c.z; p += kOrbBlock) {
-        const uint64_t key = body_key(xyz, n, axis, cur[p]);
-        if (round == 0 || (key >> (shift + 8)) == prefix) atomicAdd(&h[(key >> shift) & 0xFF], 1u);
-    }
-    __syncthreads();
-    const uint32_t v = h[threadIdx.x];
-    if (v) atomicAdd(&hist[(size_t)c.x * 256 + threadIdx.x], v);
-}
-
-// One wave per segment: the bin holding rank krem, then clear the bins.
-__global__ __launch_bounds__(64) void k_orb_pick(int nseg, SegState *__restrict__ st,
-                                                 uint32_t *__restrict__ hist)
-{
-    const int s = blockIdx.x;
-    if (s >= nseg) return;
-    const int lane = threadIdx.x;
-    uint32_t *hs = hist + (size_t)s * 256;
-    uint32_t c[4], tot = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        c[q] = hs[4 * lane + q];
-        tot += c[q];
-    }
-    // inclusive scan of the per-lane totals across the wave
-    uint32_t inc = tot;
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = (uint32_t)__shfl_up((int)inc, o);
-        if (lane >= o) inc += y;
-    }
-    const uint32_t before = inc - tot;
-    const uint32_t krem = (uint32_t)st[s].krem;
-    // the lane whose range contains rank krem (1-based) decides
-    if (before < krem && krem <= inc) {
-        uint32_t acc = before;
-        int bin = 4 * lane;
-        for (int q = 0; q < 4; ++q) {
-            if (acc + c[q] >= krem) {
-                bin = 4 * lane + q;
-                break;
-            }
-            acc += c[q];
-        }
-        st[s].prefix = (st[s].prefix << 8) | (uint64_t)bin;
-        st[s].krem = (int)(krem - acc);
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) hs[4 * lane + q] = 0u;
-}
-
-// Keys <= the k-th key go left.  Slots are handed out per workgroup with one
-// atomic per side; the order inside a side is irrelevant to the result.
-__global__ __launch_bounds__(kOrbBlock) void k_orb_partition(const int3 *__restrict__ chunks,
-                                                             const int3 *__restrict__ segs,
-                                                             const float *__restrict__ xyz, int n,
-                                                             const int32_t *__restrict__ cur,
-                                                             SegState *__restrict__ st,
-                                                             int32_t *__restrict__ tmp)
-{
-    __shared__ uint32_t nl, nr, bl, br;
-    if (threadIdx.x == 0) nl = nr = 0u;
-    __syncthreads();
-    const int3 c = chunks[blockIdx.x];
-    const int axis = st[c.x].axis;
-    const uint64_t kth = st[c.x].prefix;
-    // count
-    for (int p = c.y + threadIdx.x; p < c.z; p += kOrbBlock) {
-        const uint64_t key = body_key(xyz, n, axis, cur[p]);
-        if (key <= kth)
-            atomicAdd(&nl, 1u);
-        else
-            atomicAdd(&nr, 1u);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        bl = atomicAdd(&st[c.x].lcnt, nl);
-        br = atomicAdd(&st[c.x].rcnt, nr);
-        nl = nr = 0u;
-    }
-    __syncthreads();
-    const int3 sg = segs[c.x];
-    // exactly k keys are <= the k-th key; the guards only keep a violated
-    // precondition (non-finite coordinates) inside the segment
-    for (int p = c.y + threadIdx.x; p < c.z; p += kOrbBlock) {
-        const int b = cur[p];
-        const uint64_t key = body_key(xyz, n, axis, b);
-        if (key <= kth) {
-            const uint32_t q = bl + atomicAdd(&nl, 1u);
-            if (q < (uint32_t)sg.z) tmp[sg.x + q] = b;
-        } else {
-            const uint32_t q = br + atomicAdd(&nr, 1u);
-            if (q < (uint32_t)(sg.y - sg.z)) tmp[sg.x + sg.z + q] = b;
-        }
-    }
-}
-
-__global__ __launch_bounds__(kOrbBlock) void k_orb_copyback(const int3 *__restrict__ chunks,
-                                                            const int32_t *__restrict__ tmp,
-                                                            int32_t *__restrict__ cur)
-{
-    const int3 c = chunks[blockIdx.x];
-    for (int p = c.y + threadIdx.x; p < c.z; p += kOrbBlock) cur[p] = tmp[p];
-}
-
-// ---- phase B: one workgroup finishes one segment in LDS --------------------
-__device__ __forceinline__ uint32_t block_reduce_u32(uint32_t v, bool is_min, uint32_t *scratch)
-{
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    v = is_min ? wave_min(v) : wave_max(v);
-    __syncthreads();
-    if (lane == 0) scratch[w] = v;
-    __syncthreads();
-    uint32_t r = scratch[0];
-    for (int k = 1; k < kOrbBlock / 64; ++k) r = is_min ? min(r, scratch[k]) : max(r, scratch[k]);
-    return r;
 }
 
 // Inclusive sum over the workgroup's threads (one 256-thread workgroup):
@@ -311,6 +147,295 @@ __device__ __forceinline__ uint32_t block_incl_scan_u32(uint32_t v, uint32_t *sc
     uint32_t before = 0;
     for (int k = 0; k < w; ++k) before += scratch[k];
     return v + before;
+}
+
+// Hand-off between the workgroups of one launch, with no cache-wide fence (a
+// device-scope fence writes back and invalidates the XCD's whole L2 on this
+// GPU, which costs more than the pass it would guard).  Every value that
+// another workgroup reads is written by a device-scope atomic whose returned
+// value the writing thread waits for (so the update has been performed at the
+// device's coherence point before its workgroup arrives), and is read with
+// device-scope loads.
+template <typename T>
+__device__ __forceinline__ T load_dev(const T *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void store_dev(T *p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// waits until v, returned by an atomic, has arrived
+template <typename T>
+__device__ __forceinline__ void performed(T v)
+{
+    asm volatile("" ::"v"(v));
+}
+
+// Called by every thread of a workgroup after its atomics for segment s: true
+// in the workgroup that finishes the segment last.  No workgroup waits for
+// another.
+__device__ __forceinline__ bool last_of_segment(SegState *__restrict__ st, int s,
+                                                const int3 *__restrict__ segs, int *flag)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t nch = (uint32_t)((segs[s].y + kChunk - 1) / kChunk);
+        *flag = atomicAdd(&st[s].arrived, 1u) == nch - 1;
+    }
+    __syncthreads();
+    return *flag != 0;
+}
+
+// Key bounding box of each segment; the workgroup that finishes a segment
+// picks its split axis.  keys: the three axes' total-order keys in the
+// current order (axis a at a * n).
+__global__ __launch_bounds__(kOrbBlock) void k_orb_bbox(const int3 *__restrict__ chunks,
+                                                        const int3 *__restrict__ segs,
+                                                        const uint32_t *__restrict__ keys, int n,
+                                                        SegState *__restrict__ st)
+{
+    const int3 c = chunks[blockIdx.x];
+    uint32_t lo[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, hi[3] = {0u, 0u, 0u};
+    // a fixed number of elements per thread, so that all their loads are in
+    // flight together
+    // (positions past the chunk's end read its last element again: no branch
+    // around the loads)
+#pragma unroll
+    for (int u = 0; u < kChunkPer; ++u) {
+        const int p = min(c.y + u * kOrbBlock + (int)threadIdx.x, c.z - 1);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const uint32_t k = keys[(size_t)a * n + p];
+            lo[a] = min(lo[a], k);
+            hi[a] = max(hi[a], k);
+        }
+    }
+    __shared__ uint32_t red[kOrbBlock / 64][6];
+    __shared__ int last;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = wave_min(lo[a]);
+        hi[a] = wave_max(hi[a]);
+    }
+    if (lane == 0)
+        for (int a = 0; a < 3; ++a) {
+            red[w][a] = lo[a];
+            red[w][3 + a] = hi[a];
+        }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        uint32_t v = red[0][threadIdx.x];
+        for (int k = 1; k < kOrbBlock / 64; ++k)
+            v = threadIdx.x < 3 ? min(v, red[k][threadIdx.x]) : max(v, red[k][threadIdx.x]);
+        performed(threadIdx.x < 3 ? atomicMin(&st[c.x].bb[threadIdx.x], v)
+                                  : atomicMax(&st[c.x].bb[threadIdx.x], v));
+    }
+    if (!last_of_segment(st, c.x, segs, &last)) return;
+    if (threadIdx.x == 0) {
+        uint32_t bb[6];
+        for (int a = 0; a < 6; ++a) bb[a] = load_dev(&st[c.x].bb[a]);
+        st[c.x].axis = pick_axis(bb);
+        store_dev(&st[c.x].arrived, 0u);
+    }
+}
+
+// One pass of the radix select of every segment, for digit `round` (8 bits,
+// most significant first) of the 64-bit key (total-order key along the
+// segment's axis, original index).  kSelect: count the digit of the keys
+// inside the prefix found so far; the workgroup that finishes the segment
+// picks the bin holding rank krem and clears the counts.  If that bin holds a
+// single key, the next pass (kFind) only reads it whole.  keys: as for
+// k_orb_bbox; cur: original index per position.
+__global__ __launch_bounds__(kOrbBlock) void k_orb_hist(const int3 *__restrict__ chunks,
+                                                        const int3 *__restrict__ segs,
+                                                        const uint32_t *__restrict__ keys, int n,
+                                                        const int32_t *__restrict__ cur,
+                                                        SegState *__restrict__ st,
+                                                        uint32_t *__restrict__ hist, int round)
+{
+    __shared__ uint32_t h[256];
+    __shared__ uint32_t red[kOrbBlock / 64];
+    __shared__ int last;
+    const int3 c = chunks[blockIdx.x];
+    // the state was written by earlier launches only
+    const int mode = st[c.x].mode;
+    if (mode == kDone) return;  // the whole segment returns: nobody arrives
+    const int axis = st[c.x].axis;
+    const uint64_t prefix = st[c.x].prefix;
+    const int shift = 56 - 8 * round;
+    const uint32_t *ka = keys + (size_t)axis * n;
+    // the index (low 32 bits) matters from round 4 on, and to read the key whole
+    const bool need_idx = round >= 4 || mode == kFind;
+    // positions past the chunk's end read its last element (no branch around
+    // the loads, so they are all in flight together) and are masked below
+    uint64_t key[kChunkPer];
+    if (need_idx) {
+#pragma unroll
+        for (int u = 0; u < kChunkPer; ++u) {
+            const int p = min(c.y + u * kOrbBlock + (int)threadIdx.x, c.z - 1);
+            key[u] = ((uint64_t)ka[p] << 32) | (uint32_t)cur[p];
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < kChunkPer; ++u) {
+            const int p = min(c.y + u * kOrbBlock + (int)threadIdx.x, c.z - 1);
+            key[u] = (uint64_t)ka[p] << 32;
+        }
+    }
+    if (mode == kFind) {
+#pragma unroll
+        for (int u = 0; u < kChunkPer; ++u) {
+            const int p = c.y + u * kOrbBlock + threadIdx.x;
+            if (p < c.z && (key[u] >> (shift + 8)) == prefix)
+                performed(__hip_atomic_exchange(&st[c.x].full, key[u], __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT));
+        }
+        if (!last_of_segment(st, c.x, segs, &last)) return;
+        if (threadIdx.x == 0) {
+            st[c.x].prefix = load_dev(&st[c.x].full);
+            st[c.x].mode = kDone;
+            store_dev(&st[c.x].arrived, 0u);
+        }
+        return;
+    }
+    h[threadIdx.x] = 0u;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kChunkPer; ++u) {
+        const int p = c.y + u * kOrbBlock + threadIdx.x;
+        if (p < c.z && (round == 0 || (key[u] >> (shift + 8)) == prefix))
+            atomicAdd(&h[(key[u] >> shift) & 0xFF], 1u);
+    }
+    __syncthreads();
+    uint32_t *hs = hist + (size_t)c.x * 256;
+    const uint32_t v = h[threadIdx.x];
+    if (v) performed(atomicAdd(&hs[threadIdx.x], v));
+    if (!last_of_segment(st, c.x, segs, &last)) return;
+    const uint32_t cnt = load_dev(&hs[threadIdx.x]);
+    store_dev(&hs[threadIdx.x], 0u);
+    const uint32_t inc = block_incl_scan_u32(cnt, red);
+    const uint32_t krem = (uint32_t)st[c.x].krem;
+    if (inc >= krem && inc - cnt < krem) {
+        st[c.x].prefix = (prefix << 8) | (uint64_t)threadIdx.x;
+        st[c.x].krem = (int)(krem - (inc - cnt));
+        st[c.x].mode = (cnt == 1u && round < 7) ? kFind : kSelect;
+    }
+    if (threadIdx.x == 0) store_dev(&st[c.x].arrived, 0u);
+}
+
+// Keys <= the k-th key go left.  Each workgroup takes one run of slots per
+// side with one atomic each and fills it in position order (ballot ranks);
+// the order of the runs is irrelevant to the result.  The original indices
+// go to tmp, the three axes' keys to keys_out, both in the new order.
+__global__ __launch_bounds__(kOrbBlock) void k_orb_partition(const int3 *__restrict__ chunks,
+                                                             const int3 *__restrict__ segs,
+                                                             const uint32_t *__restrict__ keys,
+                                                             uint32_t *__restrict__ keys_out, int n,
+                                                             const int32_t *__restrict__ cur,
+                                                             SegState *__restrict__ st,
+                                                             int32_t *__restrict__ tmp)
+{
+    constexpr int kW = kOrbBlock / 64;
+    __shared__ uint32_t cl[kChunkPer * kW], cr[kChunkPer * kW];
+    __shared__ uint32_t bl, br;
+    const int3 c = chunks[blockIdx.x];
+    const int axis = st[c.x].axis;
+    const uint64_t kth = st[c.x].prefix;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t below = (1ull << lane) - 1ull;
+    const uint32_t *ka = keys + (size_t)axis * n;
+    // this thread's bodies and their sides, loaded together
+    int bod[kChunkPer];
+    uint32_t rank[kChunkPer];
+    bool lft[kChunkPer];
+#pragma unroll
+    for (int u = 0; u < kChunkPer; ++u) {
+        const int p = c.y + u * kOrbBlock + threadIdx.x;
+        const int q = min(p, c.z - 1);  // loads without a branch, masked below
+        const int b = cur[q];
+        lft[u] = (((uint64_t)ka[q] << 32) | (uint32_t)b) <= kth;
+        bod[u] = p < c.z ? b : -1;
+    }
+    // rank inside the (step, wave) group by ballots, group totals in LDS
+#pragma unroll
+    for (int u = 0; u < kChunkPer; ++u) {
+        const uint64_t ml = __ballot(bod[u] >= 0 && lft[u]);
+        const uint64_t mr = __ballot(bod[u] >= 0 && !lft[u]);
+        rank[u] = (uint32_t)__popcll((lft[u] ? ml : mr) & below);
+        if (lane == 0) {
+            cl[u * kW + w] = (uint32_t)__popcll(ml);
+            cr[u * kW + w] = (uint32_t)__popcll(mr);
+        }
+    }
+    __syncthreads();
+    // exclusive scans over the kChunkPer * kW groups (position order), by wave 0
+    static_assert(kChunkPer * kW == 64, "one group per lane of wave 0");
+    if (w == 0) {
+        const uint32_t a = cl[lane], b = cr[lane];
+        uint32_t ia = a, ib = b;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t ya = (uint32_t)__shfl_up((int)ia, o), yb = (uint32_t)__shfl_up((int)ib, o);
+            if (lane >= o) {
+                ia += ya;
+                ib += yb;
+            }
+        }
+        cl[lane] = ia - a;
+        cr[lane] = ib - b;
+        if (lane == 63) {
+            bl = atomicAdd(&st[c.x].lcnt, ia);
+            br = atomicAdd(&st[c.x].rcnt, ib);
+        }
+    }
+    __syncthreads();
+    const int3 sg = segs[c.x];
+    // exactly k keys are <= the k-th key; the guards only keep a violated
+    // precondition (non-finite coordinates) inside the segment
+#pragma unroll
+    for (int u = 0; u < kChunkPer; ++u) {
+        const int b = bod[u];
+        if (b < 0) continue;
+        const int p = c.y + u * kOrbBlock + threadIdx.x;
+        int d;
+        if (lft[u]) {
+            const uint32_t q = bl + cl[u * kW + w] + rank[u];
+            if (q >= (uint32_t)sg.z) continue;
+            d = sg.x + (int)q;
+        } else {
+            const uint32_t q = br + cr[u * kW + w] + rank[u];
+            if (q >= (uint32_t)(sg.y - sg.z)) continue;
+            d = sg.x + sg.z + (int)q;
+        }
+        tmp[d] = b;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) keys_out[(size_t)a * n + d] = keys[(size_t)a * n + p];
+    }
+}
+
+// The clamp only keeps a broken invariant (a slot left unfilled) from turning
+// into out-of-bounds reads later: every slot is filled.
+__global__ __launch_bounds__(kOrbBlock) void k_orb_copyback(const int3 *__restrict__ chunks,
+                                                            const int32_t *__restrict__ tmp, int n,
+                                                            int32_t *__restrict__ cur)
+{
+    const int3 c = chunks[blockIdx.x];
+    for (int p = c.y + threadIdx.x; p < c.z; p += kOrbBlock) cur[p] = (int32_t)min((uint32_t)tmp[p], (uint32_t)(n - 1));
+}
+
+// ---- phase B: one workgroup finishes one segment in LDS --------------------
+__device__ __forceinline__ uint32_t block_reduce_u32(uint32_t v, bool is_min, uint32_t *scratch)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    v = is_min ? wave_min(v) : wave_max(v);
+    __syncthreads();
+    if (lane == 0) scratch[w] = v;
+    __syncthreads();
+    uint32_t r = scratch[0];
+    for (int k = 1; k < kOrbBlock / 64; ++k) r = is_min ? min(r, scratch[k]) : max(r, scratch[k]);
+    return r;
 }
 
 // Finishes the recursion of a node of at most 64 bodies (positions
@@ -630,7 +755,9 @@ int orb_order(const void *pm, int prec, int n, int leaf, int32_t *perm, hipStrea
     tab.insert(tab.end(), (const char *)finals.data(), (const char *)(finals.data() + finals.size()));
     pad();
     const size_t nbytes = (size_t)n * 4;
-    float *xyz = (float *)scratch(kSlotOrb0, 3 * nbytes);
+    // xyz by original index, then two buffers of the three axes' keys in the
+    // current order (each level reads one and writes the other)
+    float *xyz = (float *)scratch(kSlotOrb0, 9 * nbytes);
     int32_t *cur = (int32_t *)scratch(kSlotOrb1, nbytes);
     int32_t *tmp = (int32_t *)scratch(kSlotOrb2, nbytes);
     char *dtab = (char *)scratch(kSlotOrb3, tab.size() + 16);
@@ -639,6 +766,7 @@ int orb_order(const void *pm, int prec, int n, int leaf, int32_t *perm, hipStrea
         set_error("cannot allocate ORB scratch");
         return NBODY_E_NOMEM;
     }
+    uint32_t *kbuf[2] = {(uint32_t *)(xyz + 3 * (size_t)n), (uint32_t *)(xyz + 6 * (size_t)n)};
     SegState *st = (SegState *)state;
     uint32_t *hist = (uint32_t *)(state + ((maxseg * sizeof(SegState) + 63) & ~size_t(63)));
     {
@@ -678,24 +806,25 @@ int orb_order(const void *pm, int prec, int n, int leaf, int32_t *perm, hipStrea
     }
     const int nb = (n + kOrbBlock - 1) / kOrbBlock;
     if (prec == NBODY_F64)
-        hipLaunchKernelGGL(k_orb_coords<double4>, dim3(nb), dim3(kOrbBlock), 0, s, (const double4 *)pm, n, xyz, cur);
+        hipLaunchKernelGGL(k_orb_coords<double4>, dim3(nb), dim3(kOrbBlock), 0, s, (const double4 *)pm, n, xyz,
+                           kbuf[0], cur);
     else
-        hipLaunchKernelGGL(k_orb_coords<float4>, dim3(nb), dim3(kOrbBlock), 0, s, (const float4 *)pm, n, xyz, cur);
+        hipLaunchKernelGGL(k_orb_coords<float4>, dim3(nb), dim3(kOrbBlock), 0, s, (const float4 *)pm, n, xyz,
+                           kbuf[0], cur);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "ORB coordinates");
     for (size_t l = 0; l < levels.size(); ++l) {
         const int nseg = (int)levels[l].segs.size(), nch = (int)levels[l].chunks.size();
         const int3 *segs = (const int3 *)(dtab + off[l].first);
         const int3 *chunks = (const int3 *)(dtab + off[l].second);
+        const uint32_t *keys = kbuf[l & 1];
         hipLaunchKernelGGL(k_orb_init, dim3(nseg), dim3(256), 0, s, segs, nseg, st, hist);
-        hipLaunchKernelGGL(k_orb_bbox, dim3(nch), dim3(kOrbBlock), 0, s, chunks, xyz, n, cur, st);
-        hipLaunchKernelGGL(k_orb_axis, dim3((nseg + kOrbBlock - 1) / kOrbBlock), dim3(kOrbBlock), 0, s, nseg, st);
-        for (int r = 0; r < 8; ++r) {
-            hipLaunchKernelGGL(k_orb_hist, dim3(nch), dim3(kOrbBlock), 0, s, chunks, xyz, n, cur, st, hist, r);
-            hipLaunchKernelGGL(k_orb_pick, dim3(nseg), dim3(64), 0, s, nseg, st, hist);
-        }
-        hipLaunchKernelGGL(k_orb_partition, dim3(nch), dim3(kOrbBlock), 0, s, chunks, segs, xyz, n, cur, st, tmp);
-        hipLaunchKernelGGL(k_orb_copyback, dim3(nch), dim3(kOrbBlock), 0, s, chunks, tmp, cur);
+        hipLaunchKernelGGL(k_orb_bbox, dim3(nch), dim3(kOrbBlock), 0, s, chunks, segs, keys, n, st);
+        for (int r = 0; r < 8; ++r)
+            hipLaunchKernelGGL(k_orb_hist, dim3(nch), dim3(kOrbBlock), 0, s, chunks, segs, keys, n, cur, st, hist, r);
+        hipLaunchKernelGGL(k_orb_partition, dim3(nch), dim3(kOrbBlock), 0, s, chunks, segs, keys, kbuf[(l + 1) & 1],
+                           n, cur, st, tmp);
+        hipLaunchKernelGGL(k_orb_copyback, dim3(nch), dim3(kOrbBlock), 0, s, chunks, tmp, n, cur);
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "ORB level");
     }
