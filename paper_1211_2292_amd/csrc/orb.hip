@@ -78,6 +78,23 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_coords(const V *__restrict__ 
     cur[i] = i;
 }
 
+// Radix select over the 64-bit key in kRounds digits, most significant
+// first: kDigit bits each, the last one taking the rest.
+constexpr int kDigit = 8;
+constexpr int kBins = 1 << kDigit;
+constexpr int kRounds = (64 + kDigit - 1) / kDigit;
+__host__ __device__ constexpr int digit_shift(int round)
+{
+    return 64 - kDigit * (round + 1) > 0 ? 64 - kDigit * (round + 1) : 0;
+}
+// bits above the digit of `round`: the prefix found before it
+__host__ __device__ constexpr int prefix_shift(int round)
+{
+    return round == 0 ? 64 : digit_shift(round - 1);
+}
+static_assert(kBins % kOrbBlock == 0, "whole bins per thread");
+constexpr int kBinsPer = kBins / kOrbBlock;
+
 // Per-segment state of one phase-A level.
 enum SegMode : int {
     kSelect = 0,  // radix select: histogram the next digit inside the prefix
@@ -86,38 +103,54 @@ enum SegMode : int {
 };
 struct SegState {
     uint32_t bb[6];    // min keys x,y,z then max keys x,y,z
-    int axis;
     int krem;          // rank still to find inside the current prefix
+    int mode;          // SegMode
     uint64_t prefix;   // digits of the k-th key found so far
     uint64_t full;     // the k-th key, written by the kFind pass
     uint32_t lcnt, rcnt;
-    uint32_t arrived;  // workgroups of the current launch done with the segment
-    int mode;          // SegMode
+    uint32_t arrived;  // workgroups of the current pass done with the segment
+    uint32_t pad;
 };
 
-// seg table: (start, size, k) per segment; chunk table: (seg, begin, end)
+__device__ __forceinline__ void init_state(SegState *st, int k)
+{
+    SegState z;
+    for (int a = 0; a < 3; ++a) {
+        z.bb[a] = 0xFFFFFFFFu;
+        z.bb[3 + a] = 0u;
+    }
+    z.krem = k;
+    z.mode = kSelect;
+    z.prefix = 0;
+    z.full = 0;
+    z.lcnt = z.rcnt = 0;
+    z.arrived = 0;
+    z.pad = 0;
+    *st = z;
+}
+
+// the segment's split axis, from its key box (complete once the pass that
+// accumulated it has ended)
+__device__ __forceinline__ int seg_axis(const SegState *st)
+{
+    uint32_t bb[6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) bb[a] = st->bb[a];
+    return pick_axis(bb);
+}
+
+// Tables: segs (start, size, k) per segment of a level, chunks (segment,
+// begin, end), kids (next-level segment of the left and of the right part,
+// -1 where that part is finished by phase B).
+// First level: its states, and every histogram row cleared (the passes
+// leave them cleared after that).  One workgroup per row.
 __global__ __launch_bounds__(kOrbBlock) void k_orb_init(const int3 *__restrict__ segs, int nseg,
                                                         SegState *__restrict__ st,
                                                         uint32_t *__restrict__ hist)
 {
     const int s = blockIdx.x;
-    if (s >= nseg) return;
-    if (threadIdx.x == 0) {
-        SegState z;
-        for (int a = 0; a < 3; ++a) {
-            z.bb[a] = 0xFFFFFFFFu;
-            z.bb[3 + a] = 0u;
-        }
-        z.axis = 0;
-        z.krem = segs[s].z;
-        z.prefix = 0;
-        z.full = 0;
-        z.lcnt = z.rcnt = 0;
-        z.arrived = 0;
-        z.mode = kSelect;
-        st[s] = z;
-    }
-    hist[(size_t)s * 256 + threadIdx.x] = 0u;
+    if (s < nseg && threadIdx.x == 0) init_state(&st[s], segs[s].z);
+    for (int j = threadIdx.x; j < kBins; j += kOrbBlock) hist[(size_t)s * kBins + j] = 0u;
 }
 
 __device__ __forceinline__ uint32_t wave_min(uint32_t v)
@@ -188,20 +221,26 @@ __device__ __forceinline__ bool last_of_segment(SegState *__restrict__ st, int s
     return *flag != 0;
 }
 
-// Key bounding box of each segment; the workgroup that finishes a segment
-// picks its split axis.  keys: the three axes' total-order keys in the
-// current order (axis a at a * n).
+__device__ __forceinline__ void box_atomics(uint32_t *bb, const uint32_t *v)
+{
+    if (threadIdx.x < 3)
+        atomicMin(&bb[threadIdx.x], v[threadIdx.x]);
+    else if (threadIdx.x < 6)
+        atomicMax(&bb[threadIdx.x], v[threadIdx.x]);
+}
+
+// Key bounding box of each segment of the first level (the partition
+// accumulates it for the later levels).  keys: the three axes' total-order
+// keys in the current order (axis a at a * n).
 __global__ __launch_bounds__(kOrbBlock) void k_orb_bbox(const int3 *__restrict__ chunks,
-                                                        const int3 *__restrict__ segs,
                                                         const uint32_t *__restrict__ keys, int n,
                                                         SegState *__restrict__ st)
 {
     const int3 c = chunks[blockIdx.x];
     uint32_t lo[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, hi[3] = {0u, 0u, 0u};
     // a fixed number of elements per thread, so that all their loads are in
-    // flight together
-    // (positions past the chunk's end read its last element again: no branch
-    // around the loads)
+    // flight together (positions past the chunk's end read its last element
+    // again: no branch around the loads)
 #pragma unroll
     for (int u = 0; u < kChunkPer; ++u) {
         const int p = min(c.y + u * kOrbBlock + (int)threadIdx.x, c.z - 1);
@@ -213,7 +252,7 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_bbox(const int3 *__restrict__
         }
     }
     __shared__ uint32_t red[kOrbBlock / 64][6];
-    __shared__ int last;
+    __shared__ uint32_t tot[6];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -230,45 +269,45 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_bbox(const int3 *__restrict__
         uint32_t v = red[0][threadIdx.x];
         for (int k = 1; k < kOrbBlock / 64; ++k)
             v = threadIdx.x < 3 ? min(v, red[k][threadIdx.x]) : max(v, red[k][threadIdx.x]);
-        performed(threadIdx.x < 3 ? atomicMin(&st[c.x].bb[threadIdx.x], v)
-                                  : atomicMax(&st[c.x].bb[threadIdx.x], v));
+        tot[threadIdx.x] = v;
     }
-    if (!last_of_segment(st, c.x, segs, &last)) return;
-    if (threadIdx.x == 0) {
-        uint32_t bb[6];
-        for (int a = 0; a < 6; ++a) bb[a] = load_dev(&st[c.x].bb[a]);
-        st[c.x].axis = pick_axis(bb);
-        store_dev(&st[c.x].arrived, 0u);
-    }
+    __syncthreads();
+    box_atomics(st[c.x].bb, tot);
 }
 
-// One pass of the radix select of every segment, for digit `round` (8 bits,
-// most significant first) of the 64-bit key (total-order key along the
-// segment's axis, original index).  kSelect: count the digit of the keys
-// inside the prefix found so far; the workgroup that finishes the segment
-// picks the bin holding rank krem and clears the counts.  If that bin holds a
-// single key, the next pass (kFind) only reads it whole.  keys: as for
-// k_orb_bbox; cur: original index per position.
+// One pass of the radix select of every segment, for digit `round` of the
+// 64-bit key (total-order key along the segment's axis, original index).
+// kSelect: count the digit of the keys inside the prefix found so far; the
+// workgroup that finishes the segment picks the bin holding rank krem and
+// clears the counts.  If that bin holds a single key, the next pass (kFind)
+// only reads it whole.  keys: as for k_orb_bbox; cur: original index per
+// position.  The first pass also sets up the states of the next level
+// (st_next), which the partition fills in.
 __global__ __launch_bounds__(kOrbBlock) void k_orb_hist(const int3 *__restrict__ chunks,
                                                         const int3 *__restrict__ segs,
                                                         const uint32_t *__restrict__ keys, int n,
                                                         const int32_t *__restrict__ cur,
                                                         SegState *__restrict__ st,
-                                                        uint32_t *__restrict__ hist, int round)
+                                                        uint32_t *__restrict__ hist, int round,
+                                                        const int3 *__restrict__ segs_next, int nseg_next,
+                                                        SegState *__restrict__ st_next)
 {
-    __shared__ uint32_t h[256];
+    __shared__ uint32_t h[kBins];
     __shared__ uint32_t red[kOrbBlock / 64];
     __shared__ int last;
+    if (round == 0 && threadIdx.x == 0)
+        for (int s = blockIdx.x; s < nseg_next; s += gridDim.x) init_state(&st_next[s], segs_next[s].z);
     const int3 c = chunks[blockIdx.x];
     // the state was written by earlier launches only
     const int mode = st[c.x].mode;
     if (mode == kDone) return;  // the whole segment returns: nobody arrives
-    const int axis = st[c.x].axis;
     const uint64_t prefix = st[c.x].prefix;
-    const int shift = 56 - 8 * round;
-    const uint32_t *ka = keys + (size_t)axis * n;
-    // the index (low 32 bits) matters from round 4 on, and to read the key whole
-    const bool need_idx = round >= 4 || mode == kFind;
+    const int shift = digit_shift(round), pshift = prefix_shift(round);
+    const uint32_t dmask = (1u << (pshift - shift)) - 1u;
+    const uint32_t *ka = keys + (size_t)seg_axis(&st[c.x]) * n;
+    // the index (low 32 bits) matters once the digit reaches below bit 32, and
+    // to read the key whole
+    const bool need_idx = shift < 32 || mode == kFind;
     // positions past the chunk's end read its last element (no branch around
     // the loads, so they are all in flight together) and are masked below
     uint64_t key[kChunkPer];
@@ -285,11 +324,12 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_hist(const int3 *__restrict__
             key[u] = (uint64_t)ka[p] << 32;
         }
     }
+    // (round 0 has no prefix: a shift by 64 is not defined, so test it apart)
     if (mode == kFind) {
 #pragma unroll
         for (int u = 0; u < kChunkPer; ++u) {
             const int p = c.y + u * kOrbBlock + threadIdx.x;
-            if (p < c.z && (key[u] >> (shift + 8)) == prefix)
+            if (p < c.z && (round == 0 || (key[u] >> pshift) == prefix))
                 performed(__hip_atomic_exchange(&st[c.x].full, key[u], __ATOMIC_RELAXED,
                                                 __HIP_MEMORY_SCOPE_AGENT));
         }
@@ -301,27 +341,50 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_hist(const int3 *__restrict__
         }
         return;
     }
-    h[threadIdx.x] = 0u;
+#pragma unroll
+    for (int j = 0; j < kBinsPer; ++j) h[j * kOrbBlock + threadIdx.x] = 0u;
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < kChunkPer; ++u) {
         const int p = c.y + u * kOrbBlock + threadIdx.x;
-        if (p < c.z && (round == 0 || (key[u] >> (shift + 8)) == prefix))
-            atomicAdd(&h[(key[u] >> shift) & 0xFF], 1u);
+        if (p < c.z && (round == 0 || (key[u] >> pshift) == prefix))
+            atomicAdd(&h[(uint32_t)(key[u] >> shift) & dmask], 1u);
     }
     __syncthreads();
-    uint32_t *hs = hist + (size_t)c.x * 256;
-    const uint32_t v = h[threadIdx.x];
-    if (v) performed(atomicAdd(&hs[threadIdx.x], v));
+    uint32_t *hs = hist + (size_t)c.x * kBins;
+#pragma unroll
+    for (int j = 0; j < kBinsPer; ++j) {
+        const uint32_t v = h[j * kOrbBlock + threadIdx.x];
+        if (v) performed(atomicAdd(&hs[j * kOrbBlock + threadIdx.x], v));
+    }
     if (!last_of_segment(st, c.x, segs, &last)) return;
-    const uint32_t cnt = load_dev(&hs[threadIdx.x]);
-    store_dev(&hs[threadIdx.x], 0u);
-    const uint32_t inc = block_incl_scan_u32(cnt, red);
+    // the last workgroup: thread t holds bins [t * kBinsPer, (t + 1) * kBinsPer)
+    uint32_t cnt[kBinsPer], tot = 0;
+#pragma unroll
+    for (int j = 0; j < kBinsPer; ++j) {
+        cnt[j] = load_dev(&hs[threadIdx.x * kBinsPer + j]);
+        store_dev(&hs[threadIdx.x * kBinsPer + j], 0u);
+        tot += cnt[j];
+    }
+    const uint32_t inc = block_incl_scan_u32(tot, red);
     const uint32_t krem = (uint32_t)st[c.x].krem;
-    if (inc >= krem && inc - cnt < krem) {
-        st[c.x].prefix = (prefix << 8) | (uint64_t)threadIdx.x;
-        st[c.x].krem = (int)(krem - (inc - cnt));
-        st[c.x].mode = (cnt == 1u && round < 7) ? kFind : kSelect;
+    if (inc >= krem && inc - tot < krem) {
+        // the first of this thread's bins where the running count reaches krem
+        uint32_t acc = inc - tot, before = 0, c1 = 0;
+        int jb = -1;
+#pragma unroll
+        for (int j = 0; j < kBinsPer; ++j) {
+            if (jb < 0 && acc + cnt[j] >= krem) {
+                jb = j;
+                before = acc;
+                c1 = cnt[j];
+            }
+            acc += cnt[j];
+        }
+        const uint32_t bin = (uint32_t)(threadIdx.x * kBinsPer + jb);
+        st[c.x].prefix = (round == 0 ? 0ull : prefix << (pshift - shift)) | bin;
+        st[c.x].krem = (int)(krem - before);
+        st[c.x].mode = (c1 == 1u && round < kRounds - 1) ? kFind : kSelect;
     }
     if (threadIdx.x == 0) store_dev(&st[c.x].arrived, 0u);
 }
@@ -329,24 +392,29 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_hist(const int3 *__restrict__
 // Keys <= the k-th key go left.  Each workgroup takes one run of slots per
 // side with one atomic each and fills it in position order (ballot ranks);
 // the order of the runs is irrelevant to the result.  The original indices
-// go to tmp, the three axes' keys to keys_out, both in the new order.
+// go to cur_out and the three axes' keys to keys_out, both in the new order.
+// Each side's key box is accumulated into its next-level state (if it has
+// one).
 __global__ __launch_bounds__(kOrbBlock) void k_orb_partition(const int3 *__restrict__ chunks,
                                                              const int3 *__restrict__ segs,
+                                                             const int2 *__restrict__ kids,
                                                              const uint32_t *__restrict__ keys,
                                                              uint32_t *__restrict__ keys_out, int n,
                                                              const int32_t *__restrict__ cur,
+                                                             int32_t *__restrict__ cur_out,
                                                              SegState *__restrict__ st,
-                                                             int32_t *__restrict__ tmp)
+                                                             SegState *__restrict__ st_next)
 {
     constexpr int kW = kOrbBlock / 64;
     __shared__ uint32_t cl[kChunkPer * kW], cr[kChunkPer * kW];
     __shared__ uint32_t bl, br;
+    __shared__ uint32_t box[kW][12];
+    __shared__ uint32_t tot[12];
     const int3 c = chunks[blockIdx.x];
-    const int axis = st[c.x].axis;
     const uint64_t kth = st[c.x].prefix;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint64_t below = (1ull << lane) - 1ull;
-    const uint32_t *ka = keys + (size_t)axis * n;
+    const uint32_t *ka = keys + (size_t)seg_axis(&st[c.x]) * n;
     // this thread's bodies and their sides, loaded together
     int bod[kChunkPer];
     uint32_t rank[kChunkPer];
@@ -392,82 +460,109 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_partition(const int3 *__restr
     }
     __syncthreads();
     const int3 sg = segs[c.x];
-    // exactly k keys are <= the k-th key; the guards only keep a violated
-    // precondition (non-finite coordinates) inside the segment
+    // box of each side: min keys x,y,z then max keys x,y,z; left then right
+    uint32_t bx[12];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        bx[a] = bx[6 + a] = 0xFFFFFFFFu;
+        bx[3 + a] = bx[9 + a] = 0u;
+    }
+    // destinations; exactly k keys are <= the k-th key, and the guards only
+    // keep a violated precondition (non-finite coordinates) inside the segment
+    int dst[kChunkPer];
 #pragma unroll
     for (int u = 0; u < kChunkPer; ++u) {
-        const int b = bod[u];
-        if (b < 0) continue;
-        const int p = c.y + u * kOrbBlock + threadIdx.x;
-        int d;
-        if (lft[u]) {
-            const uint32_t q = bl + cl[u * kW + w] + rank[u];
-            if (q >= (uint32_t)sg.z) continue;
-            d = sg.x + (int)q;
-        } else {
-            const uint32_t q = br + cr[u * kW + w] + rank[u];
-            if (q >= (uint32_t)(sg.y - sg.z)) continue;
-            d = sg.x + sg.z + (int)q;
-        }
-        tmp[d] = b;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) keys_out[(size_t)a * n + d] = keys[(size_t)a * n + p];
+        const uint32_t q = (lft[u] ? bl + cl[u * kW + w] : br + cr[u * kW + w]) + rank[u];
+        const bool fits = lft[u] ? q < (uint32_t)sg.z : q < (uint32_t)(sg.y - sg.z);
+        dst[u] = bod[u] >= 0 && fits ? sg.x + (lft[u] ? 0 : sg.z) + (int)q : -1;
+        if (dst[u] >= 0) cur_out[dst[u]] = bod[u];
     }
-}
-
-// The clamp only keeps a broken invariant (a slot left unfilled) from turning
-// into out-of-bounds reads later: every slot is filled.
-__global__ __launch_bounds__(kOrbBlock) void k_orb_copyback(const int3 *__restrict__ chunks,
-                                                            const int32_t *__restrict__ tmp, int n,
-                                                            int32_t *__restrict__ cur)
-{
-    const int3 c = chunks[blockIdx.x];
-    for (int p = c.y + threadIdx.x; p < c.z; p += kOrbBlock) cur[p] = (int32_t)min((uint32_t)tmp[p], (uint32_t)(n - 1));
+    // one axis at a time: all of the thread's loads first, then the stores
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        uint32_t kv[kChunkPer];
+#pragma unroll
+        for (int u = 0; u < kChunkPer; ++u) kv[u] = keys[(size_t)a * n + min(c.y + u * kOrbBlock + (int)threadIdx.x, c.z - 1)];
+#pragma unroll
+        for (int u = 0; u < kChunkPer; ++u) {
+            if (dst[u] < 0) continue;
+            keys_out[(size_t)a * n + dst[u]] = kv[u];
+            const int o = lft[u] ? 0 : 6;
+            bx[o + a] = min(bx[o + a], kv[u]);
+            bx[o + 3 + a] = max(bx[o + 3 + a], kv[u]);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 12; ++j) bx[j] = (j % 6) < 3 ? wave_min(bx[j]) : wave_max(bx[j]);
+    if (lane == 0)
+#pragma unroll
+        for (int j = 0; j < 12; ++j) box[w][j] = bx[j];
+    __syncthreads();
+    if (threadIdx.x < 12) {
+        const int j = threadIdx.x;
+        uint32_t v = box[0][j];
+        for (int k = 1; k < kW; ++k) v = (j % 6) < 3 ? min(v, box[k][j]) : max(v, box[k][j]);
+        tot[j] = v;
+    }
+    __syncthreads();
+    const int2 kd = kids[c.x];
+    if (kd.x >= 0) box_atomics(st_next[kd.x].bb, tot);
+    if (kd.y >= 0) box_atomics(st_next[kd.y].bb, tot + 6);
 }
 
 // ---- phase B: one workgroup finishes one segment in LDS --------------------
-__device__ __forceinline__ uint32_t block_reduce_u32(uint32_t v, bool is_min, uint32_t *scratch)
+// The segment's keys are loaded once, coalesced, from the key buffer that
+// holds it (phase A leaves them in the segment's order) and stay in their
+// slots; the recursion permutes slot numbers only.
+
+// Box of a node (min keys x,y,z then max keys x,y,z), over the whole
+// workgroup: two barriers for all six values.
+__device__ __forceinline__ void block_box(uint32_t *bb, uint32_t (*red)[6])
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    v = is_min ? wave_min(v) : wave_max(v);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) bb[j] = j < 3 ? wave_min(bb[j]) : wave_max(bb[j]);
     __syncthreads();
-    if (lane == 0) scratch[w] = v;
+    if (lane == 0)
+#pragma unroll
+        for (int j = 0; j < 6; ++j) red[w][j] = bb[j];
     __syncthreads();
-    uint32_t r = scratch[0];
-    for (int k = 1; k < kOrbBlock / 64; ++k) r = is_min ? min(r, scratch[k]) : max(r, scratch[k]);
-    return r;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        uint32_t v = red[0][j];
+        for (int k = 1; k < kOrbBlock / 64; ++k) v = j < 3 ? min(v, red[k][j]) : max(v, red[k][j]);
+        bb[j] = v;
+    }
 }
 
 // Finishes the recursion of a node of at most 64 bodies (positions
-// [lo, lo + m) of idx) with one wave, one position per lane, every node of a
+// [lo, lo + m) of pos) with one wave, one position per lane, every node of a
 // level split at once.  keys: per-wave LDS of 3 x 64 total-order keys.  The
 // k smallest keys of a node are found by ranking (keys and indices are
 // distinct), then each leaf is ordered by original index.
 constexpr int kWaveSeg = 64;
 
-__device__ void orb_wave(int32_t *idx, uint32_t (*keys)[kWaveSeg], int lo, int m, int leaf,
-                         const float *__restrict__ xyz, int n, int lane)
+__device__ void orb_wave(int32_t *pos, const uint32_t (*skey)[kSmall], const int32_t *gid,
+                         uint32_t (*keys)[kWaveSeg], int32_t *wid, int lo, int m, int leaf, int lane)
 {
-    int b = lane < m ? idx[lo + lane] : -1;
-    uint32_t kx = 0, ky = 0, kz = 0;
+    const int s = lane < m ? pos[lo + lane] : 0;  // this lane's slot
+    const uint32_t kx = skey[0][s], ky = skey[1][s], kz = skey[2][s];
+    const int b = gid[s];
+    int slo = 0, sm = m;  // the node holding this lane's entry (relative to lo)
+    int at = lane;        // this lane's entry's current position (relative to lo)
     if (lane < m) {
-        kx = tkey(xyz[b]);
-        ky = tkey(xyz[(size_t)n + b]);
-        kz = tkey(xyz[2 * (size_t)n + b]);
+        keys[0][lane] = kx;
+        keys[1][lane] = ky;
+        keys[2][lane] = kz;
+        wid[lane] = b;
     }
-    int slo = 0, sm = m;  // the node holding this lane's position (relative to lo)
     for (;;) {
         const bool split = lane < m && sm > leaf;
         if (!__any(split)) break;
-        if (lane < m) {
-            keys[0][lane] = kx;
-            keys[1][lane] = ky;
-            keys[2][lane] = kz;
-        }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        int pos = lane;
+        int to = at;
         int k = sm;
         if (split) {
             uint32_t bb[6] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0u, 0u};
@@ -483,10 +578,9 @@ __device__ void orb_wave(int32_t *idx, uint32_t (*keys)[kWaveSeg], int lo, int m
             int r = 0;
             for (int f = slo; f < slo + sm; ++f) {
                 const uint32_t v = keys[axis][f];
-                const int bf = idx[lo + f];
-                r += (v < mine) || (v == mine && bf < b);
+                r += (v < mine) || (v == mine && wid[f] < b);
             }
-            pos = slo + r;
+            to = slo + r;
             const int L = (sm + leaf - 1) / leaf;
             k = min(sm, leaf * ((L + 1) / 2));
         }
@@ -494,21 +588,13 @@ __device__ void orb_wave(int32_t *idx, uint32_t (*keys)[kWaveSeg], int lo, int m
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         if (lane < m) {
-            idx[lo + pos] = b;
-            keys[0][pos] = kx;
-            keys[1][pos] = ky;
-            keys[2][pos] = kz;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (lane < m) {
-            b = idx[lo + lane];
-            kx = keys[0][lane];
-            ky = keys[1][lane];
-            kz = keys[2][lane];
+            keys[0][to] = kx;
+            keys[1][to] = ky;
+            keys[2][to] = kz;
+            wid[to] = b;
+            at = to;
             if (split) {
-                if (lane - slo < k) {
+                if (to - slo < k) {
                     sm = k;
                 } else {
                     slo += k;
@@ -517,35 +603,238 @@ __device__ void orb_wave(int32_t *idx, uint32_t (*keys)[kWaveSeg], int lo, int m
             }
         }
     }
-    // leaves: ascending original index
-    int r = 0;
-    if (lane < m)
-        for (int f = slo; f < slo + sm; ++f) r += idx[lo + f] < b;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (lane < m) idx[lo + slo + r] = b;
+    // leaves: ascending original index
+    int r = 0;
+    if (lane < m)
+        for (int f = slo; f < slo + sm; ++f) r += wid[f] < b;
+    if (lane < m) pos[lo + slo + r] = s;
 }
 
-__global__ __launch_bounds__(kOrbBlock) void k_orb_block(const int2 *__restrict__ segs,
-                                                         const float *__restrict__ xyz, int n,
-                                                         const int32_t *__restrict__ cur, int leaf,
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Nodes of at most kWaveNode bodies are split by one wave each, several
+// subtrees at once.
+constexpr int kWaveNode = 512;
+
+// One wave finishes the subtree of node [lo0, lo0 + m0) of pos: the same
+// splits as the block-wide path (radix select of the k-th key with a
+// 256-bin histogram hw of the wave's own, ballot-ranked partition through
+// tmp), nodes of at most 64 bodies by orb_wave, leaves by rank.
+__device__ void wave_subtree(int32_t *pos, int32_t *tmp, uint32_t *akey, const uint32_t (*skey)[kSmall],
+                             const int32_t *gid, uint32_t *hw, uint32_t (*wk)[kWaveSeg], int32_t *wid, int lo0,
+                             int m0, int leaf, int lane)
+{
+    int stk_lo[16], stk_m[16], sp = 0;  // uniform across the wave
+    stk_lo[0] = lo0;
+    stk_m[0] = m0;
+    sp = 1;
+    while (sp > 0) {
+        --sp;
+        const int lo = stk_lo[sp], m = stk_m[sp];
+        if (m <= kWaveSeg) {
+            orb_wave(pos, skey, gid, wk, wid, lo, m, leaf, lane);
+            wave_sync();
+            continue;
+        }
+        if (m <= leaf) {
+            for (int e = lane; e < m; e += 64) {
+                const int s = pos[lo + e], v = gid[s];
+                int r = 0;
+                for (int f = 0; f < m; ++f) r += gid[pos[lo + f]] < v;
+                tmp[lo + r] = s;
+            }
+            wave_sync();
+            for (int e = lane; e < m; e += 64) pos[lo + e] = tmp[lo + e];
+            wave_sync();
+            continue;
+        }
+        uint32_t bb[6] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0u, 0u};
+        for (int e = lane; e < m; e += 64) {
+            const int s = pos[lo + e];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const uint32_t v = skey[a][s];
+                bb[a] = min(bb[a], v);
+                bb[3 + a] = max(bb[3 + a], v);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 6; ++j) bb[j] = j < 3 ? wave_min(bb[j]) : wave_max(bb[j]);
+        const int axis = pick_axis(bb);
+        const int L = (m + leaf - 1) / leaf;
+        const int k = min(m, leaf * ((L + 1) / 2));
+        for (int e = lane; e < m; e += 64) akey[lo + e] = skey[axis][pos[lo + e]];
+        wave_sync();
+        // radix select, 8 bits a round, with the single-key exit
+        uint64_t prefix = 0;
+        uint32_t kr = (uint32_t)k;
+        bool one = false;
+        for (int round = 0; round < 8; ++round) {
+            const int shift = 56 - 8 * round;
+            if (one) {
+                // the one key whose digits above `shift` are the prefix
+                uint64_t found = 0;
+                bool hit = false;
+                for (int e = lane; e < m; e += 64) {
+                    const uint64_t key = ((uint64_t)akey[lo + e] << 32) | (uint32_t)gid[pos[lo + e]];
+                    if ((key >> (shift + 8)) == prefix) {
+                        found = key;
+                        hit = true;
+                    }
+                }
+                const uint64_t who = __ballot(hit);
+                const int src = who ? __ffsll((long long)who) - 1 : 0;
+                prefix = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(found >> 32), src) << 32) |
+                         (uint32_t)__shfl((int)(uint32_t)found, src);
+                break;
+            }
+            for (int j = lane; j < 256; j += 64) hw[j] = 0u;
+            wave_sync();
+            for (int e = lane; e < m; e += 64) {
+                const uint64_t key = ((uint64_t)akey[lo + e] << 32) | (uint32_t)gid[pos[lo + e]];
+                if (round == 0 || (key >> (shift + 8)) == prefix) atomicAdd(&hw[(key >> shift) & 0xFF], 1u);
+            }
+            wave_sync();
+            uint32_t c[4], tot = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                c[q] = hw[4 * lane + q];
+                tot += c[q];
+            }
+            uint32_t inc = tot;
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = (uint32_t)__shfl_up((int)inc, o);
+                if (lane >= o) inc += y;
+            }
+            const bool mine = inc >= kr && inc - tot < kr;
+            int bin = 0;
+            uint32_t nkr = 0, bc = 0;
+            if (mine) {
+                // the first of this lane's bins where the running count reaches kr
+                uint32_t acc = inc - tot, before = 0;
+                int jb = -1;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (jb < 0 && acc + c[j] >= kr) {
+                        jb = j;
+                        before = acc;
+                        bc = c[j];
+                    }
+                    acc += c[j];
+                }
+                bin = 4 * lane + jb;
+                nkr = kr - before;
+            }
+            const uint64_t who = __ballot(mine);
+            const int src = who ? __ffsll((long long)who) - 1 : 0;
+            bin = __shfl(bin, src);
+            kr = (uint32_t)__shfl((int)nkr, src);
+            one = __shfl((int)bc, src) == 1;
+            prefix = (prefix << 8) | (uint64_t)bin;
+            wave_sync();  // hw is cleared again by the next round
+        }
+        const uint64_t kth = prefix;
+        // partition, 64 entries at a time, in position order within each side
+        int dl = 0, dr = 0;
+        for (int e0 = 0; e0 < m; e0 += 64) {
+            const int e = e0 + lane;
+            const bool act = e < m;
+            const int s = act ? pos[lo + e] : 0;
+            const bool left = act && (((uint64_t)akey[lo + (act ? e : 0)] << 32) | (uint32_t)gid[s]) <= kth;
+            const bool right = act && !left;
+            const unsigned long long bl = __ballot(left), br = __ballot(right);
+            const int rl = __builtin_amdgcn_mbcnt_hi((unsigned)(bl >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bl, 0u));
+            const int rr = __builtin_amdgcn_mbcnt_hi((unsigned)(br >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)br, 0u));
+            if (left && dl + rl < k) tmp[lo + dl + rl] = s;
+            if (right && dr + rr < m - k) tmp[lo + k + dr + rr] = s;
+            dl += __popcll(bl);
+            dr += __popcll(br);
+        }
+        wave_sync();
+        for (int e = lane; e < m; e += 64) pos[lo + e] = tmp[lo + e];
+        wave_sync();
+        // right first so that the left child is processed next
+        stk_lo[sp] = lo + k;
+        stk_m[sp] = m - k;
+        ++sp;
+        stk_lo[sp] = lo;
+        stk_m[sp] = k;
+        ++sp;
+    }
+}
+
+// Orders positions [lo, lo + m) of pos by original index (a leaf), through tmp.
+__device__ __forceinline__ void block_leaf(int32_t *pos, int32_t *tmp, const int32_t *gid, int lo, int m)
+{
+    for (int e = threadIdx.x; e < m; e += kOrbBlock) {
+        const int s = pos[lo + e], v = gid[s];
+        int r = 0;
+        for (int f = 0; f < m; ++f) r += gid[pos[lo + f]] < v;
+        tmp[lo + r] = s;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < m; e += kOrbBlock) pos[lo + e] = tmp[lo + e];
+    __syncthreads();
+}
+
+// segs: (start, size, which buffer pair holds it).  keys0/1: the three axes'
+// keys in the order of cur0/1 (axis a at a * n).
+__global__ __launch_bounds__(kOrbBlock) void k_orb_block(const int3 *__restrict__ segs,
+                                                         const uint32_t *__restrict__ keys0,
+                                                         const uint32_t *__restrict__ keys1,
+                                                         const int32_t *__restrict__ cur0,
+                                                         const int32_t *__restrict__ cur1, int n, int leaf,
                                                          int32_t *__restrict__ perm)
 {
-    __shared__ int32_t idx[kMaxBlockSeg];
-    __shared__ int32_t tmp[kMaxBlockSeg];
-    __shared__ uint32_t akey[kMaxBlockSeg];  // the current node's keys along its split axis
+    __shared__ uint32_t skey[3][kSmall];      // keys by slot
+    __shared__ int32_t gid[kMaxBlockSeg];     // original index by slot
+    __shared__ int32_t pos[kSmall];           // slots in the current order
+    __shared__ int32_t tmp[kSmall];
+    __shared__ uint32_t akey[kSmall];         // the current node's keys along its split axis
     __shared__ uint32_t h[256];
     __shared__ uint32_t red[kOrbBlock / 64];
+    __shared__ uint32_t red6[kOrbBlock / 64][6];
     __shared__ uint32_t wl[kOrbBlock / 64], wr[kOrbBlock / 64];
     __shared__ uint64_t kth_s;
-    __shared__ uint32_t krem_s;
-    constexpr int kMaxTask = kMaxBlockSeg / kWaveSeg * 2 + 2;
+    __shared__ uint32_t krem_s, one_s;
+    constexpr int kMaxTask = 64;
     __shared__ int2 task[kMaxTask];
+    __shared__ uint32_t hw[kOrbBlock / 64][256];
     __shared__ uint32_t wkeys[kOrbBlock / 64][3][kWaveSeg];
-    const int2 sg = segs[blockIdx.x];
+    __shared__ int32_t wgid[kOrbBlock / 64][kWaveSeg];
+    const int3 sg = segs[blockIdx.x];
     const int start = sg.x, size = sg.y;
-    for (int e = threadIdx.x; e < size; e += kOrbBlock) idx[e] = cur[start + e];
+    const int32_t *cur = sg.z ? cur1 : cur0;
+    const uint32_t *keys = sg.z ? keys1 : keys0;
+    // the clamp only keeps a broken invariant (an unfilled slot) from turning
+    // into out-of-bounds writes: every slot is filled
+    for (int e = threadIdx.x; e < size; e += kOrbBlock) gid[e] = (int32_t)min((uint32_t)cur[start + e], (uint32_t)(n - 1));
+    if (size > kSmall) {
+        // at most max(kSmall, leaf) bodies reach this kernel: a larger
+        // segment is one leaf, written in ascending original index (ranks;
+        // the indices are distinct)
+        __syncthreads();
+        for (int e = threadIdx.x; e < size; e += kOrbBlock) {
+            const int v = gid[e];
+            int r = 0;
+            for (int f = 0; f < size; ++f) r += gid[f] < v;
+            perm[start + r] = v;
+        }
+        return;
+    }
+    for (int e = threadIdx.x; e < size; e += kOrbBlock) {
+        pos[e] = e;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) skey[a][e] = keys[(size_t)a * n + start + e];
+    }
     __syncthreads();
     int ntask = 0;  // same value in every thread: the loop below is uniform
     int stk_lo[24], stk_m[24], sp = 0;
@@ -555,57 +844,59 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_block(const int2 *__restrict_
     while (sp > 0) {
         --sp;
         const int lo = stk_lo[sp], m = stk_m[sp];
-        if (m <= kWaveSeg && ntask < kMaxTask) {
-            // finished by one wave below, all small nodes in parallel (past
-            // the list's capacity the block-wide path below takes them)
+        if (m <= kWaveNode && ntask < kMaxTask) {
+            // its subtree is finished by one wave below, several at once
+            // (past the list's capacity the block-wide path takes them)
             if (threadIdx.x == 0) task[ntask] = make_int2(lo, m);
             ++ntask;
             continue;
         }
         if (m <= leaf) {
-            // leaf: ascending original index (rank of each element; distinct)
-            for (int e = threadIdx.x; e < m; e += kOrbBlock) {
-                const int v = idx[lo + e];
-                int r = 0;
-                for (int f = 0; f < m; ++f) r += idx[lo + f] < v;
-                tmp[lo + r] = v;
-            }
-            __syncthreads();
-            for (int e = threadIdx.x; e < m; e += kOrbBlock) idx[lo + e] = tmp[lo + e];
-            __syncthreads();
+            block_leaf(pos, tmp, gid, lo, m);
             continue;
         }
         // bounding box and axis
-        uint32_t bb[6];
-        for (int a = 0; a < 3; ++a) {
-            uint32_t mn = 0xFFFFFFFFu, mx = 0u;
-            for (int e = threadIdx.x; e < m; e += kOrbBlock) {
-                const uint32_t k = tkey(xyz[(size_t)a * n + idx[lo + e]]);
-                mn = min(mn, k);
-                mx = max(mx, k);
+        uint32_t bb[6] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0u, 0u};
+        for (int e = threadIdx.x; e < m; e += kOrbBlock) {
+            const int s = pos[lo + e];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const uint32_t v = skey[a][s];
+                bb[a] = min(bb[a], v);
+                bb[3 + a] = max(bb[3 + a], v);
             }
-            bb[a] = block_reduce_u32(mn, true, red);
-            bb[3 + a] = block_reduce_u32(mx, false, red);
         }
+        block_box(bb, red6);
         const int axis = pick_axis(bb);
         const int L = (m + leaf - 1) / leaf;
         const int k = min(m, leaf * ((L + 1) / 2));
-        // the split axis's keys, gathered once for the 8 rounds and the partition
-        for (int e = threadIdx.x; e < m; e += kOrbBlock) akey[e] = tkey(xyz[(size_t)axis * n + idx[lo + e]]);
-        // radix select of the k-th smallest key
+        // the split axis's keys in node order, for the rounds and the partition
+        for (int e = threadIdx.x; e < m; e += kOrbBlock) akey[e] = skey[axis][pos[lo + e]];
+        // radix select of the k-th smallest key (total-order key, original
+        // index), 8 bits a round; once the bin holding it holds it alone, one
+        // pass reads it whole
         if (threadIdx.x == 0) {
             kth_s = 0;
             krem_s = (uint32_t)k;
+            one_s = 0u;
         }
         for (int round = 0; round < 8; ++round) {
             __syncthreads();
             h[threadIdx.x] = 0u;
             const uint64_t prefix = kth_s;
             const uint32_t kr = krem_s;
-            __syncthreads();
             const int shift = 56 - 8 * round;
+            if (one_s) {
+                // the one key whose digits above `shift` are the prefix
+                for (int e = threadIdx.x; e < m; e += kOrbBlock) {
+                    const uint64_t key = ((uint64_t)akey[e] << 32) | (uint32_t)gid[pos[lo + e]];
+                    if ((key >> (shift + 8)) == prefix) kth_s = key;
+                }
+                break;
+            }
+            __syncthreads();
             for (int e = threadIdx.x; e < m; e += kOrbBlock) {
-                const uint64_t key = ((uint64_t)akey[e] << 32) | (uint32_t)idx[lo + e];
+                const uint64_t key = ((uint64_t)akey[e] << 32) | (uint32_t)gid[pos[lo + e]];
                 if (round == 0 || (key >> (shift + 8)) == prefix) atomicAdd(&h[(key >> shift) & 0xFF], 1u);
             }
             __syncthreads();
@@ -616,6 +907,7 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_block(const int2 *__restrict_
             if (inc >= kr && inc - hv < kr) {
                 kth_s = (prefix << 8) | (uint64_t)threadIdx.x;
                 krem_s = kr - (inc - hv);
+                one_s = hv == 1u;
             }
         }
         __syncthreads();
@@ -629,8 +921,8 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_block(const int2 *__restrict_
             for (int e0 = 0; e0 < m; e0 += kOrbBlock) {
                 const int e = e0 + threadIdx.x;
                 const bool act = e < m;
-                const int b = act ? idx[lo + e] : 0;
-                const bool left = act && (((uint64_t)akey[act ? e : 0] << 32) | (uint32_t)b) <= kth;
+                const int s = act ? pos[lo + e] : 0;
+                const bool left = act && (((uint64_t)akey[act ? e : 0] << 32) | (uint32_t)gid[s]) <= kth;
                 const bool right = act && !left;
                 const unsigned long long bl = __ballot(left), br = __ballot(right);
                 if (lane == 0) {
@@ -651,18 +943,18 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_block(const int2 *__restrict_
                 const int rr = __builtin_amdgcn_mbcnt_hi((unsigned)(br >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)br, 0u));
                 if (left) {
                     const int q = dl + pl + rl;
-                    if (q < k) tmp[lo + q] = b;
+                    if (q < k) tmp[lo + q] = s;
                 }
                 if (right) {
                     const int q = dr + pr + rr;
-                    if (q < m - k) tmp[lo + k + q] = b;
+                    if (q < m - k) tmp[lo + k + q] = s;
                 }
                 dl += cl;
                 dr += cr;
                 __syncthreads();  // wl, wr are reused by the next chunk
             }
         }
-        for (int e = threadIdx.x; e < m; e += kOrbBlock) idx[lo + e] = tmp[lo + e];
+        for (int e = threadIdx.x; e < m; e += kOrbBlock) pos[lo + e] = tmp[lo + e];
         __syncthreads();
         // right first so that the left child is processed next
         stk_lo[sp] = lo + k;
@@ -677,29 +969,33 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_block(const int2 *__restrict_
         const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
         for (int t = w; t < ntask; t += kOrbBlock / 64) {
             const int2 tk = task[t];
-            orb_wave(idx, wkeys[w], tk.x, tk.y, leaf, xyz, n, lane);
+            wave_subtree(pos, tmp, akey, skey, gid, hw[w], wkeys[w], wgid[w], tk.x, tk.y, leaf, lane);
         }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < size; e += kOrbBlock) perm[start + e] = idx[e];
+    for (int e = threadIdx.x; e < size; e += kOrbBlock) perm[start + e] = gid[pos[e]];
 }
 
 // ---- host side --------------------------------------------------------------
 struct Level {
     std::vector<int3> segs;    // (start, size, k)
     std::vector<int3> chunks;  // (segment, begin, end)
+    std::vector<int2> kids;    // next-level segment of the left, right part (-1: phase B)
 };
 
-void plan_tree(int n, int leaf, std::vector<Level> &levels, std::vector<int2> &finals)
+// Level l reads the index and key buffers l % 2 and writes (l + 1) % 2, so a
+// segment at depth d sits in buffer d % 2: finals are (start, size, d % 2).
+void plan_tree(int n, int leaf, std::vector<Level> &levels, std::vector<int3> &finals)
 {
     const int cut = std::max(kSmall, leaf);
     std::vector<int2> cur = {make_int2(0, n)};
-    while (!cur.empty()) {
+    for (int depth = 0; !cur.empty(); ++depth) {
         Level lv;
         std::vector<int2> next;
+        int nid = 0;  // the next level numbers its segments in the order of `next`
         for (const int2 &s : cur) {
             if (s.y <= cut) {
-                finals.push_back(s);
+                finals.push_back(make_int3(s.x, s.y, depth & 1));
                 continue;
             }
             const int L = (s.y + leaf - 1) / leaf;
@@ -708,6 +1004,9 @@ void plan_tree(int n, int leaf, std::vector<Level> &levels, std::vector<int2> &f
             lv.segs.push_back(make_int3(s.x, s.y, k));
             for (int b = s.x; b < s.x + s.y; b += kChunk)
                 lv.chunks.push_back(make_int3(id, b, std::min(b + kChunk, s.x + s.y)));
+            const int kl = k > cut ? nid++ : -1;
+            const int kr = s.y - k > cut ? nid++ : -1;
+            lv.kids.push_back(make_int2(kl, kr));
             next.push_back(make_int2(s.x, k));
             next.push_back(make_int2(s.x + k, s.y - k));
         }
@@ -733,42 +1032,51 @@ int orb_order(const void *pm, int prec, int n, int leaf, int32_t *perm, hipStrea
         return NBODY_E_UNSUPPORTED;
     }
     std::vector<Level> levels;
-    std::vector<int2> finals;
+    std::vector<int3> finals;
     plan_tree(n, leaf, levels, finals);
-    // one table upload: per level segs then chunks, then the final segments
-    // sections start on 16-byte boundaries (int2 entries need 8-byte alignment)
+    // one table upload: per level segs, chunks and kids, then the final
+    // segments; sections start on 16-byte boundaries (int2 entries need
+    // 8-byte alignment)
     std::vector<char> tab;
     auto pad = [&tab]() { tab.resize((tab.size() + 15) & ~size_t(15), 0); };
-    std::vector<std::pair<size_t, size_t>> off;  // byte offsets of segs, chunks per level
+    auto put = [&tab, &pad](const void *p, size_t bytes) {
+        const size_t at = tab.size();
+        tab.insert(tab.end(), (const char *)p, (const char *)p + bytes);
+        pad();
+        return at;
+    };
+    struct Off {
+        size_t segs, chunks, kids;
+    };
+    std::vector<Off> off;
     size_t maxseg = 1;
     for (const Level &lv : levels) {
-        const size_t a = tab.size();
-        tab.insert(tab.end(), (const char *)lv.segs.data(), (const char *)(lv.segs.data() + lv.segs.size()));
-        pad();
-        const size_t b = tab.size();
-        tab.insert(tab.end(), (const char *)lv.chunks.data(), (const char *)(lv.chunks.data() + lv.chunks.size()));
-        pad();
-        off.push_back({a, b});
+        Off o;
+        o.segs = put(lv.segs.data(), lv.segs.size() * sizeof(int3));
+        o.chunks = put(lv.chunks.data(), lv.chunks.size() * sizeof(int3));
+        o.kids = put(lv.kids.data(), lv.kids.size() * sizeof(int2));
+        off.push_back(o);
         maxseg = std::max(maxseg, lv.segs.size());
     }
-    const size_t foff = tab.size();
-    tab.insert(tab.end(), (const char *)finals.data(), (const char *)(finals.data() + finals.size()));
-    pad();
+    const size_t foff = put(finals.data(), finals.size() * sizeof(int3));
     const size_t nbytes = (size_t)n * 4;
     // xyz by original index, then two buffers of the three axes' keys in the
     // current order (each level reads one and writes the other)
     float *xyz = (float *)scratch(kSlotOrb0, 9 * nbytes);
-    int32_t *cur = (int32_t *)scratch(kSlotOrb1, nbytes);
-    int32_t *tmp = (int32_t *)scratch(kSlotOrb2, nbytes);
+    // original index per position, same two-buffer scheme as the keys
+    int32_t *cbuf[2] = {(int32_t *)scratch(kSlotOrb1, nbytes), (int32_t *)scratch(kSlotOrb2, nbytes)};
     char *dtab = (char *)scratch(kSlotOrb3, tab.size() + 16);
-    char *state = (char *)scratch(kSlotOrb4, maxseg * (sizeof(SegState) + 256 * 4) + 64);
-    if (!xyz || !cur || !tmp || !dtab || !state) {
+    // states of two levels (the partition fills in the next one's), then one
+    // histogram row per segment
+    const size_t stbytes = (maxseg * sizeof(SegState) + 63) & ~size_t(63);
+    char *state = (char *)scratch(kSlotOrb4, 2 * stbytes + maxseg * kBins * 4 + 64);
+    if (!xyz || !cbuf[0] || !cbuf[1] || !dtab || !state) {
         set_error("cannot allocate ORB scratch");
         return NBODY_E_NOMEM;
     }
     uint32_t *kbuf[2] = {(uint32_t *)(xyz + 3 * (size_t)n), (uint32_t *)(xyz + 6 * (size_t)n)};
-    SegState *st = (SegState *)state;
-    uint32_t *hist = (uint32_t *)(state + ((maxseg * sizeof(SegState) + 63) & ~size_t(63)));
+    SegState *st[2] = {(SegState *)state, (SegState *)(state + stbytes)};
+    uint32_t *hist = (uint32_t *)(state + 2 * stbytes);
     {
         // stage the tables through pinned host memory owned by the library;
         // the previous upload must have completed before the buffer is reused
@@ -807,29 +1115,35 @@ int orb_order(const void *pm, int prec, int n, int leaf, int32_t *perm, hipStrea
     const int nb = (n + kOrbBlock - 1) / kOrbBlock;
     if (prec == NBODY_F64)
         hipLaunchKernelGGL(k_orb_coords<double4>, dim3(nb), dim3(kOrbBlock), 0, s, (const double4 *)pm, n, xyz,
-                           kbuf[0], cur);
+                           kbuf[0], cbuf[0]);
     else
         hipLaunchKernelGGL(k_orb_coords<float4>, dim3(nb), dim3(kOrbBlock), 0, s, (const float4 *)pm, n, xyz,
-                           kbuf[0], cur);
+                           kbuf[0], cbuf[0]);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "ORB coordinates");
     for (size_t l = 0; l < levels.size(); ++l) {
         const int nseg = (int)levels[l].segs.size(), nch = (int)levels[l].chunks.size();
-        const int3 *segs = (const int3 *)(dtab + off[l].first);
-        const int3 *chunks = (const int3 *)(dtab + off[l].second);
-        const uint32_t *keys = kbuf[l & 1];
-        hipLaunchKernelGGL(k_orb_init, dim3(nseg), dim3(256), 0, s, segs, nseg, st, hist);
-        hipLaunchKernelGGL(k_orb_bbox, dim3(nch), dim3(kOrbBlock), 0, s, chunks, segs, keys, n, st);
-        for (int r = 0; r < 8; ++r)
-            hipLaunchKernelGGL(k_orb_hist, dim3(nch), dim3(kOrbBlock), 0, s, chunks, segs, keys, n, cur, st, hist, r);
-        hipLaunchKernelGGL(k_orb_partition, dim3(nch), dim3(kOrbBlock), 0, s, chunks, segs, keys, kbuf[(l + 1) & 1],
-                           n, cur, st, tmp);
-        hipLaunchKernelGGL(k_orb_copyback, dim3(nch), dim3(kOrbBlock), 0, s, chunks, tmp, n, cur);
+        const int3 *segs = (const int3 *)(dtab + off[l].segs);
+        const int3 *chunks = (const int3 *)(dtab + off[l].chunks);
+        const int2 *kids = (const int2 *)(dtab + off[l].kids);
+        const bool more = l + 1 < levels.size();
+        const int3 *segs_next = more ? (const int3 *)(dtab + off[l + 1].segs) : nullptr;
+        const int nseg_next = more ? (int)levels[l + 1].segs.size() : 0;
+        const int i = (int)(l & 1), o = 1 - i;
+        if (l == 0) {
+            hipLaunchKernelGGL(k_orb_init, dim3((unsigned)maxseg), dim3(kOrbBlock), 0, s, segs, nseg, st[i], hist);
+            hipLaunchKernelGGL(k_orb_bbox, dim3(nch), dim3(kOrbBlock), 0, s, chunks, kbuf[i], n, st[i]);
+        }
+        for (int r = 0; r < kRounds; ++r)
+            hipLaunchKernelGGL(k_orb_hist, dim3(nch), dim3(kOrbBlock), 0, s, chunks, segs, kbuf[i], n, cbuf[i],
+                               st[i], hist, r, segs_next, nseg_next, st[o]);
+        hipLaunchKernelGGL(k_orb_partition, dim3(nch), dim3(kOrbBlock), 0, s, chunks, segs, kids, kbuf[i], kbuf[o],
+                           n, cbuf[i], cbuf[o], st[i], st[o]);
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "ORB level");
     }
     hipLaunchKernelGGL(k_orb_block, dim3((unsigned)finals.size()), dim3(kOrbBlock), 0, s,
-                       (const int2 *)(dtab + foff), xyz, n, cur, leaf, perm);
+                       (const int3 *)(dtab + foff), kbuf[0], kbuf[1], cbuf[0], cbuf[1], n, leaf, perm);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "ORB leaves");
     return NBODY_OK;
