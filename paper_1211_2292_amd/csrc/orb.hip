@@ -27,7 +27,7 @@
 
 namespace nbi {
 
-constexpr int kSmall = 2048;        // phase A splits segments larger than this
+constexpr int kSmall = 1024;        // phase A splits segments larger than this
 constexpr int kMaxBlockSeg = 4096;  // largest segment phase B accepts (and max leaf)
 constexpr int kChunk = 4096;        // elements per phase-A workgroup
 constexpr int kOrbBlock = 256;
@@ -622,34 +622,40 @@ __device__ __forceinline__ void wave_sync()
 
 // Nodes of at most kWaveNode bodies are split by one wave each, several
 // subtrees at once.
-constexpr int kWaveNode = 512;
+constexpr int kWaveNode = 256;
+constexpr int kStack = 24;  // node stack entries (the recursion is at most 12 deep)
 
 // One wave finishes the subtree of node [lo0, lo0 + m0) of pos: the same
 // splits as the block-wide path (radix select of the k-th key with a
 // 256-bin histogram hw of the wave's own, ballot-ranked partition through
 // tmp), nodes of at most 64 bodies by orb_wave, leaves by rank.
 __device__ void wave_subtree(int32_t *pos, int32_t *tmp, uint32_t *akey, const uint32_t (*skey)[kSmall],
-                             const int32_t *gid, uint32_t *hw, uint32_t (*wk)[kWaveSeg], int32_t *wid, int lo0,
-                             int m0, int leaf, int lane)
+                             const int32_t *gid, uint32_t *hw, uint32_t (*wk)[kWaveSeg], int32_t *wid, int2 *stk,
+                             int lo0, int m0, int leaf, int lane)
 {
-    int stk_lo[16], stk_m[16], sp = 0;  // uniform across the wave
-    stk_lo[0] = lo0;
-    stk_m[0] = m0;
-    sp = 1;
+    // node stack in LDS (stk: this wave's kStack entries); sp is uniform
+    int sp = 1;
+    if (lane == 0) stk[0] = make_int2(lo0, m0);
+    wave_sync();
     while (sp > 0) {
         --sp;
-        const int lo = stk_lo[sp], m = stk_m[sp];
+        const int2 nd = stk[sp];
+        const int lo = nd.x, m = nd.y;
+        wave_sync();  // read before the pushes below overwrite the entry
         if (m <= kWaveSeg) {
             orb_wave(pos, skey, gid, wk, wid, lo, m, leaf, lane);
             wave_sync();
             continue;
         }
         if (m <= leaf) {
+            // leaf: ranks by original index over a contiguous copy
+            for (int e = lane; e < m; e += 64) akey[lo + e] = (uint32_t)gid[pos[lo + e]];
+            wave_sync();
             for (int e = lane; e < m; e += 64) {
-                const int s = pos[lo + e], v = gid[s];
+                const uint32_t v = akey[lo + e];
                 int r = 0;
-                for (int f = 0; f < m; ++f) r += gid[pos[lo + f]] < v;
-                tmp[lo + r] = s;
+                for (int f = 0; f < m; ++f) r += akey[lo + f] < v;
+                tmp[lo + r] = pos[lo + e];
             }
             wave_sync();
             for (int e = lane; e < m; e += 64) pos[lo + e] = tmp[lo + e];
@@ -760,25 +766,28 @@ __device__ void wave_subtree(int32_t *pos, int32_t *tmp, uint32_t *akey, const u
         }
         wave_sync();
         for (int e = lane; e < m; e += 64) pos[lo + e] = tmp[lo + e];
-        wave_sync();
         // right first so that the left child is processed next
-        stk_lo[sp] = lo + k;
-        stk_m[sp] = m - k;
-        ++sp;
-        stk_lo[sp] = lo;
-        stk_m[sp] = k;
-        ++sp;
+        if (lane == 0) {
+            stk[sp] = make_int2(lo + k, m - k);
+            stk[sp + 1] = make_int2(lo, k);
+        }
+        sp += 2;
+        wave_sync();
     }
 }
 
 // Orders positions [lo, lo + m) of pos by original index (a leaf), through tmp.
-__device__ __forceinline__ void block_leaf(int32_t *pos, int32_t *tmp, const int32_t *gid, int lo, int m)
+__device__ __forceinline__ void block_leaf(int32_t *pos, int32_t *tmp, uint32_t *val, const int32_t *gid, int lo,
+                                           int m)
 {
+    // ranks by original index over a contiguous copy (val)
+    for (int e = threadIdx.x; e < m; e += kOrbBlock) val[lo + e] = (uint32_t)gid[pos[lo + e]];
+    __syncthreads();
     for (int e = threadIdx.x; e < m; e += kOrbBlock) {
-        const int s = pos[lo + e], v = gid[s];
+        const uint32_t v = val[lo + e];
         int r = 0;
-        for (int f = 0; f < m; ++f) r += gid[pos[lo + f]] < v;
-        tmp[lo + r] = s;
+        for (int f = 0; f < m; ++f) r += val[lo + f] < v;
+        tmp[lo + r] = pos[lo + e];
     }
     __syncthreads();
     for (int e = threadIdx.x; e < m; e += kOrbBlock) pos[lo + e] = tmp[lo + e];
@@ -794,11 +803,16 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_block(const int3 *__restrict_
                                                          const int32_t *__restrict__ cur1, int n, int leaf,
                                                          int32_t *__restrict__ perm)
 {
-    __shared__ uint32_t skey[3][kSmall];      // keys by slot
-    __shared__ int32_t gid[kMaxBlockSeg];     // original index by slot
-    __shared__ int32_t pos[kSmall];           // slots in the current order
-    __shared__ int32_t tmp[kSmall];
-    __shared__ uint32_t akey[kSmall];         // the current node's keys along its split axis
+    // one buffer: keys by slot (3 x kSmall), original index by slot, slots in
+    // the current order, partition target, the current node's keys along
+    // its split axis; a segment that is one leaf only needs its indices
+    __shared__ uint32_t lds[7 * kSmall];
+    static_assert(7 * kSmall >= kMaxBlockSeg, "a one-leaf segment's indices fit");
+    uint32_t (*skey)[kSmall] = reinterpret_cast<uint32_t (*)[kSmall]>(lds);
+    int32_t *gid = reinterpret_cast<int32_t *>(lds + 3 * kSmall);
+    int32_t *pos = reinterpret_cast<int32_t *>(lds + 4 * kSmall);
+    int32_t *tmp = reinterpret_cast<int32_t *>(lds + 5 * kSmall);
+    uint32_t *akey = lds + 6 * kSmall;
     __shared__ uint32_t h[256];
     __shared__ uint32_t red[kOrbBlock / 64];
     __shared__ uint32_t red6[kOrbBlock / 64][6];
@@ -810,40 +824,44 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_block(const int3 *__restrict_
     __shared__ uint32_t hw[kOrbBlock / 64][256];
     __shared__ uint32_t wkeys[kOrbBlock / 64][3][kWaveSeg];
     __shared__ int32_t wgid[kOrbBlock / 64][kWaveSeg];
+    __shared__ int2 stk[kOrbBlock / 64 + 1][kStack];  // node stacks: the waves', then the block's
     const int3 sg = segs[blockIdx.x];
     const int start = sg.x, size = sg.y;
     const int32_t *cur = sg.z ? cur1 : cur0;
     const uint32_t *keys = sg.z ? keys1 : keys0;
     // the clamp only keeps a broken invariant (an unfilled slot) from turning
     // into out-of-bounds writes: every slot is filled
-    for (int e = threadIdx.x; e < size; e += kOrbBlock) gid[e] = (int32_t)min((uint32_t)cur[start + e], (uint32_t)(n - 1));
     if (size > kSmall) {
         // at most max(kSmall, leaf) bodies reach this kernel: a larger
         // segment is one leaf, written in ascending original index (ranks;
         // the indices are distinct)
+        int32_t *big = reinterpret_cast<int32_t *>(lds);
+        for (int e = threadIdx.x; e < size; e += kOrbBlock) big[e] = (int32_t)min((uint32_t)cur[start + e], (uint32_t)(n - 1));
         __syncthreads();
         for (int e = threadIdx.x; e < size; e += kOrbBlock) {
-            const int v = gid[e];
+            const int v = big[e];
             int r = 0;
-            for (int f = 0; f < size; ++f) r += gid[f] < v;
+            for (int f = 0; f < size; ++f) r += big[f] < v;
             perm[start + r] = v;
         }
         return;
     }
     for (int e = threadIdx.x; e < size; e += kOrbBlock) {
+        gid[e] = (int32_t)min((uint32_t)cur[start + e], (uint32_t)(n - 1));
         pos[e] = e;
 #pragma unroll
         for (int a = 0; a < 3; ++a) skey[a][e] = keys[(size_t)a * n + start + e];
     }
+    int2 *bstk = stk[kOrbBlock / 64];
+    if (threadIdx.x == 0) bstk[0] = make_int2(0, size);
     __syncthreads();
     int ntask = 0;  // same value in every thread: the loop below is uniform
-    int stk_lo[24], stk_m[24], sp = 0;
-    stk_lo[0] = 0;
-    stk_m[0] = size;
-    sp = 1;
+    int sp = 1;
     while (sp > 0) {
         --sp;
-        const int lo = stk_lo[sp], m = stk_m[sp];
+        const int2 nd = bstk[sp];
+        const int lo = nd.x, m = nd.y;
+        __syncthreads();  // read before the pushes below overwrite the entry
         if (m <= kWaveNode && ntask < kMaxTask) {
             // its subtree is finished by one wave below, several at once
             // (past the list's capacity the block-wide path takes them)
@@ -852,7 +870,7 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_block(const int3 *__restrict_
             continue;
         }
         if (m <= leaf) {
-            block_leaf(pos, tmp, gid, lo, m);
+            block_leaf(pos, tmp, akey, gid, lo, m);
             continue;
         }
         // bounding box and axis
@@ -955,21 +973,20 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_block(const int3 *__restrict_
             }
         }
         for (int e = threadIdx.x; e < m; e += kOrbBlock) pos[lo + e] = tmp[lo + e];
-        __syncthreads();
         // right first so that the left child is processed next
-        stk_lo[sp] = lo + k;
-        stk_m[sp] = m - k;
-        ++sp;
-        stk_lo[sp] = lo;
-        stk_m[sp] = k;
-        ++sp;
+        if (threadIdx.x == 0) {
+            bstk[sp] = make_int2(lo + k, m - k);
+            bstk[sp + 1] = make_int2(lo, k);
+        }
+        sp += 2;
+        __syncthreads();
     }
     __syncthreads();
     {
         const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
         for (int t = w; t < ntask; t += kOrbBlock / 64) {
             const int2 tk = task[t];
-            wave_subtree(pos, tmp, akey, skey, gid, hw[w], wkeys[w], wgid[w], tk.x, tk.y, leaf, lane);
+            wave_subtree(pos, tmp, akey, skey, gid, hw[w], wkeys[w], wgid[w], stk[w], tk.x, tk.y, leaf, lane);
         }
     }
     __syncthreads();
