@@ -82,7 +82,6 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_coords(const V *__restrict__ 
 // first: kDigit bits each, the last one taking the rest.
 constexpr int kDigit = 8;
 constexpr int kBins = 1 << kDigit;
-constexpr int kRounds = (64 + kDigit - 1) / kDigit;
 __host__ __device__ constexpr int digit_shift(int round)
 {
     return 64 - kDigit * (round + 1) > 0 ? 64 - kDigit * (round + 1) : 0;
@@ -94,6 +93,11 @@ __host__ __device__ constexpr int prefix_shift(int round)
 }
 static_assert(kBins % kOrbBlock == 0, "whole bins per thread");
 constexpr int kBinsPer = kBins / kOrbBlock;
+// The rounds over the coordinate's 32 bits run as histogram passes; the
+// index bits, which only matter between equal coordinates, are settled by
+// one pass over those bodies (k_orb_ties).
+constexpr int kCoordRounds = 32 / kDigit;
+static_assert(32 % kDigit == 0 && digit_shift(kCoordRounds - 1) == 32, "digits end at the coordinate");
 
 // Per-segment state of one phase-A level.
 enum SegMode : int {
@@ -109,7 +113,7 @@ struct SegState {
     uint64_t full;     // the k-th key, written by the kFind pass
     uint32_t lcnt, rcnt;
     uint32_t arrived;  // workgroups of the current pass done with the segment
-    uint32_t pad;
+    uint32_t ties;     // bodies whose coordinate equals the k-th key's (k_orb_ties)
 };
 
 __device__ __forceinline__ void init_state(SegState *st, int k)
@@ -125,7 +129,7 @@ __device__ __forceinline__ void init_state(SegState *st, int k)
     z.full = 0;
     z.lcnt = z.rcnt = 0;
     z.arrived = 0;
-    z.pad = 0;
+    z.ties = 0;
     *st = z;
 }
 
@@ -384,9 +388,90 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_hist(const int3 *__restrict__
         const uint32_t bin = (uint32_t)(threadIdx.x * kBinsPer + jb);
         st[c.x].prefix = (round == 0 ? 0ull : prefix << (pshift - shift)) | bin;
         st[c.x].krem = (int)(krem - before);
-        st[c.x].mode = (c1 == 1u && round < kRounds - 1) ? kFind : kSelect;
+        st[c.x].mode = (c1 == 1u && round < kCoordRounds - 1) ? kFind : kSelect;
     }
     if (threadIdx.x == 0) store_dev(&st[c.x].arrived, 0u);
+}
+
+// After the coordinate rounds: the k-th key's coordinate c is known, and its
+// rank krem among the bodies with coordinate c.  Their original indices are
+// gathered into cand (at the segment's own positions), and the workgroup that
+// finishes the segment selects the krem-th smallest of them (radix select
+// over the 32-bit index; a single body needs none).
+__global__ __launch_bounds__(kOrbBlock) void k_orb_ties(const int3 *__restrict__ chunks,
+                                                        const int3 *__restrict__ segs,
+                                                        const uint32_t *__restrict__ keys, int n,
+                                                        const int32_t *__restrict__ cur,
+                                                        SegState *__restrict__ st,
+                                                        uint32_t *__restrict__ cand)
+{
+    __shared__ uint32_t h[256];
+    __shared__ uint32_t red[kOrbBlock / 64];
+    __shared__ uint32_t sel_s, krem_s;
+    __shared__ int last;
+    const int3 c = chunks[blockIdx.x];
+    if (st[c.x].mode == kDone) return;  // the whole segment returns: nobody arrives
+    const uint32_t coord = (uint32_t)st[c.x].prefix;  // the prefix is the coordinate key here
+    const int3 sg = segs[c.x];
+    const uint32_t *ka = keys + (size_t)seg_axis(&st[c.x]) * n;
+    const int lane = threadIdx.x & 63;
+    uint32_t kv[kChunkPer];
+#pragma unroll
+    for (int u = 0; u < kChunkPer; ++u) kv[u] = ka[min(c.y + u * kOrbBlock + (int)threadIdx.x, c.z - 1)];
+#pragma unroll
+    for (int u = 0; u < kChunkPer; ++u) {
+        const int p = c.y + u * kOrbBlock + threadIdx.x;
+        const bool hit = p < c.z && kv[u] == coord;
+        const uint64_t mk = __ballot(hit);
+        if (!mk) continue;
+        // one slot run per wave and step
+        uint32_t base = 0;
+        if (lane == __ffsll((long long)mk) - 1) base = atomicAdd(&st[c.x].ties, (uint32_t)__popcll(mk));
+        base = (uint32_t)__shfl((int)base, __ffsll((long long)mk) - 1);
+        if (hit) {
+            const uint32_t q = base + (uint32_t)__popcll(mk & ((1ull << lane) - 1ull));
+            if (q < (uint32_t)sg.y)
+                performed(__hip_atomic_exchange(&cand[sg.x + q], (uint32_t)cur[p], __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT));
+        }
+    }
+    if (!last_of_segment(st, c.x, segs, &last)) return;
+    const uint32_t T = min(load_dev(&st[c.x].ties), (uint32_t)sg.y);
+    const uint32_t *cs = cand + sg.x;
+    uint32_t sel = 0;
+    if (T == 1u) {
+        sel = load_dev(&cs[0]);
+    } else {
+        if (threadIdx.x == 0) {
+            sel_s = 0u;
+            krem_s = (uint32_t)st[c.x].krem;
+        }
+        for (int round = 0; round < 4; ++round) {
+            __syncthreads();
+            h[threadIdx.x] = 0u;
+            const uint32_t prefix = sel_s, kr = krem_s;
+            const int shift = 24 - 8 * round;
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < T; i += kOrbBlock) {
+                const uint32_t v = load_dev(&cs[i]);
+                if (round == 0 || (v >> (shift + 8)) == prefix) atomicAdd(&h[(v >> shift) & 0xFFu], 1u);
+            }
+            __syncthreads();
+            const uint32_t hv = h[threadIdx.x];
+            const uint32_t inc = block_incl_scan_u32(hv, red);
+            if (inc >= kr && inc - hv < kr) {
+                sel_s = (prefix << 8) | (uint32_t)threadIdx.x;
+                krem_s = kr - (inc - hv);
+            }
+        }
+        __syncthreads();
+        sel = sel_s;
+    }
+    if (threadIdx.x == 0) {
+        st[c.x].prefix = ((uint64_t)coord << 32) | sel;
+        st[c.x].mode = kDone;
+        store_dev(&st[c.x].arrived, 0u);
+    }
 }
 
 // Keys <= the k-th key go left.  Each workgroup takes one run of slots per
@@ -440,9 +525,10 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_partition(const int3 *__restr
     }
     __syncthreads();
     // exclusive scans over the kChunkPer * kW groups (position order), by wave 0
-    static_assert(kChunkPer * kW == 64, "one group per lane of wave 0");
+    static_assert(kChunkPer * kW <= 64, "one group per lane of wave 0");
     if (w == 0) {
-        const uint32_t a = cl[lane], b = cr[lane];
+        const bool g = lane < kChunkPer * kW;
+        const uint32_t a = g ? cl[lane] : 0u, b = g ? cr[lane] : 0u;
         uint32_t ia = a, ib = b;
         for (int o = 1; o < 64; o <<= 1) {
             const uint32_t ya = (uint32_t)__shfl_up((int)ia, o), yb = (uint32_t)__shfl_up((int)ib, o);
@@ -451,8 +537,10 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_partition(const int3 *__restr
                 ib += yb;
             }
         }
-        cl[lane] = ia - a;
-        cr[lane] = ib - b;
+        if (g) {
+            cl[lane] = ia - a;
+            cr[lane] = ib - b;
+        }
         if (lane == 63) {
             bl = atomicAdd(&st[c.x].lcnt, ia);
             br = atomicAdd(&st[c.x].rcnt, ib);
@@ -1079,7 +1167,7 @@ int orb_order(const void *pm, int prec, int n, int leaf, int32_t *perm, hipStrea
     const size_t nbytes = (size_t)n * 4;
     // xyz by original index, then two buffers of the three axes' keys in the
     // current order (each level reads one and writes the other)
-    float *xyz = (float *)scratch(kSlotOrb0, 9 * nbytes);
+    float *xyz = (float *)scratch(kSlotOrb0, 10 * nbytes);
     // original index per position, same two-buffer scheme as the keys
     int32_t *cbuf[2] = {(int32_t *)scratch(kSlotOrb1, nbytes), (int32_t *)scratch(kSlotOrb2, nbytes)};
     char *dtab = (char *)scratch(kSlotOrb3, tab.size() + 16);
@@ -1092,6 +1180,7 @@ int orb_order(const void *pm, int prec, int n, int leaf, int32_t *perm, hipStrea
         return NBODY_E_NOMEM;
     }
     uint32_t *kbuf[2] = {(uint32_t *)(xyz + 3 * (size_t)n), (uint32_t *)(xyz + 6 * (size_t)n)};
+    uint32_t *cand = (uint32_t *)(xyz + 9 * (size_t)n);  // tied bodies' indices (k_orb_ties)
     SegState *st[2] = {(SegState *)state, (SegState *)(state + stbytes)};
     uint32_t *hist = (uint32_t *)(state + 2 * stbytes);
     {
@@ -1151,9 +1240,11 @@ int orb_order(const void *pm, int prec, int n, int leaf, int32_t *perm, hipStrea
             hipLaunchKernelGGL(k_orb_init, dim3((unsigned)maxseg), dim3(kOrbBlock), 0, s, segs, nseg, st[i], hist);
             hipLaunchKernelGGL(k_orb_bbox, dim3(nch), dim3(kOrbBlock), 0, s, chunks, kbuf[i], n, st[i]);
         }
-        for (int r = 0; r < kRounds; ++r)
+        for (int r = 0; r < kCoordRounds; ++r)
             hipLaunchKernelGGL(k_orb_hist, dim3(nch), dim3(kOrbBlock), 0, s, chunks, segs, kbuf[i], n, cbuf[i],
                                st[i], hist, r, segs_next, nseg_next, st[o]);
+        hipLaunchKernelGGL(k_orb_ties, dim3(nch), dim3(kOrbBlock), 0, s, chunks, segs, kbuf[i], n, cbuf[i], st[i],
+                           cand);
         hipLaunchKernelGGL(k_orb_partition, dim3(nch), dim3(kOrbBlock), 0, s, chunks, segs, kids, kbuf[i], kbuf[o],
                            n, cbuf[i], cbuf[o], st[i], st[o]);
         e = hipGetLastError();
