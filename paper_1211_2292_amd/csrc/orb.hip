@@ -9,14 +9,24 @@
 //   * the host computes the whole segment tree (sizes and left counts) once;
 //   * the device only decides which bodies go left, by finding the k-th
 //     smallest 64-bit key (total-order FP32 coordinate, original index) of
-//     each segment exactly, with an 8-bit-digit radix select;
-//   * bodies may be partitioned in any order (integer atomics hand out
-//     slots), because every later decision depends on set membership only and
-//     every leaf is finally sorted by original index.
-// Phase A handles segments larger than kSmall bodies with multi-workgroup
-// kernels over fixed-size chunks; phase B finishes every remaining segment
-// (at most max(kSmall, leaf) <= kMaxBlockSeg bodies) inside one workgroup,
-// in LDS, and writes the final order.
+//     each segment exactly, with a radix select;
+//   * bodies may be partitioned in any order, because every later decision
+//     depends on set membership only and every leaf is finally sorted by
+//     original index.
+// Phase A handles segments larger than kSmall bodies, one level of the tree
+// per step, with multi-workgroup kernels over fixed-size chunks.  The three
+// axes' keys travel with the index array (two buffers, read and written in
+// turn), so every pass reads them coalesced.  A level is: four histogram
+// passes over the coordinate's 8-bit digits (k_orb_hist; the workgroup that
+// finishes a segment picks the bin, and once the bin holds a single key one
+// pass reads it whole), one pass that settles ties between equal coordinates
+// by index (k_orb_ties), and the partition (k_orb_partition), which also
+// accumulates each part's key box for the next level.  Phase B (k_orb_block)
+// finishes every remaining segment (at most max(kSmall, leaf) <=
+// kMaxBlockSeg bodies) inside one workgroup: the segment's keys are loaded
+// into LDS once, nodes above kWaveNode bodies are split by the workgroup,
+// smaller ones by one wave each, nodes of at most 64 bodies by ranking
+// inside the wave, and the final order is written.
 #include <algorithm>
 #include <cstring>
 #include <map>
