@@ -88,8 +88,9 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_coords(const V *__restrict__ 
     cur[i] = i;
 }
 
-// Radix select over the 64-bit key in kRounds digits, most significant
-// first: kDigit bits each, the last one taking the rest.
+// Radix select over the 64-bit key (coordinate key in the high half, index
+// in the low half) in digits of kDigit bits, most significant first;
+// digit_shift(r) is the lowest bit of digit r.
 constexpr int kDigit = 8;
 constexpr int kBins = 1 << kDigit;
 __host__ __device__ constexpr int digit_shift(int round)
