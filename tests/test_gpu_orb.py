@@ -54,6 +54,21 @@ def test_orb_ties_and_signed_zeros(orc):
         assert np.array_equal(got, want), (n, leaf)
 
 
+def test_orb_coincident_bodies(orc):
+    """Every body at one point, then at two: every split is decided by the
+    index alone, so the tie pass selects over whole segments."""
+    torch, nb = gpu()
+    g = ics.rng(212)
+    for n, leaf, npts in [(6000, 4, 1), (6000, 1000, 1), (9000, 8, 2), (2500, 1, 2)]:
+        pos = np.zeros((n, 4), dtype=np.float32)
+        pts = g.standard_normal((npts, 3)).astype(np.float32)
+        pos[:, :3] = pts[g.integers(0, npts, size=n)]
+        pos[:, 3] = 1.0
+        want = orc.orb_order(pos, leaf)
+        got = _gpu_perm(torch, nb, pos, leaf, torch.float32)
+        assert np.array_equal(got, want), (n, leaf, npts)
+
+
 def test_orb_full_size_collide1m(orc):
     torch, nb = gpu()
     w = ics.WORKLOADS["collide1m"]
