@@ -148,9 +148,13 @@ def main():
         return
 
     # ORB body order (the paper's recursive bisection, used as an ordering):
-    # timed once, then the state is gathered into that order
-    e_a, e_b, e_c = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    # the first call also allocates the library's ORB buffers and stages its
+    # tables; a second call of the same shape is timed as well, then the
+    # state is gathered into that order
+    e_a, e_b, e_c, e_d = (torch.cuda.Event(enable_timing=True) for _ in range(4))
     torch.cuda.synchronize()
+    e_d.record()
+    nb.orb_order(pm, 256)
     e_a.record()
     perm = nb.orb_order(pm, 256)
     e_b.record()
@@ -158,9 +162,10 @@ def main():
     vel = nb.permute(vel, perm)
     e_c.record()
     torch.cuda.synchronize()
+    orb_first_ms = e_d.elapsed_time(e_a)
     orb_ms, gather_ms = e_a.elapsed_time(e_b), e_b.elapsed_time(e_c)
     perm_host = perm.cpu().numpy()
-    log(f"[bench] ORB order {orb_ms:.2f} ms, gather {gather_ms:.3f} ms")
+    log(f"[bench] ORB order {orb_ms:.2f} ms (first call {orb_first_ms:.2f} ms), gather {gather_ms:.3f} ms")
 
     # first evaluation (step 0 forces, kept for the accuracy check, returned
     # to the input order)
@@ -234,7 +239,8 @@ def main():
                                     "variant": VARIANTS.get(tune[3], str(tune[3]))}},
         "pct_fp32_peak": round(100 * achieved / PEAK_FP32_TFLOPS, 2),
         "wall_s_timed": round(wall, 3),
-        "orb": {"leaf": 256, "order_ms": round(orb_ms, 3), "gather_ms": round(gather_ms, 3)},
+        "orb": {"leaf": 256, "order_ms": round(orb_ms, 3), "first_call_ms": round(orb_first_ms, 3),
+                "gather_ms": round(gather_ms, 3)},
         "energy_fp64": {"E0": float(energy0.sum()), "E_end": float(energy1.sum()),
                         "rel_change": float(energy1.sum() / energy0.sum() - 1.0),
                         "steps": args.steps + args.warmup + 1},
