@@ -102,8 +102,11 @@ __host__ __device__ constexpr int prefix_shift(int round)
 {
     return round == 0 ? 64 : digit_shift(round - 1);
 }
-static_assert(kBins % kOrbBlock == 0, "whole bins per thread");
-constexpr int kBinsPer = kBins / kOrbBlock;
+// The histogram, tie and partition passes run 512 threads per chunk: more
+// waves per CU to hide their latency, without more workgroups per segment.
+constexpr int kPassBlock = 512;
+constexpr int kPassPer = kChunk / kPassBlock;
+static_assert(kBins <= kPassBlock, "one bin per thread");
 // The rounds over the coordinate's 32 bits run as histogram passes; the
 // index bits, which only matter between equal coordinates, are settled by
 // one pass over those bodies (k_orb_ties).
@@ -179,11 +182,10 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v)
     return v;
 }
 
-// Inclusive sum over the workgroup's threads (one 256-thread workgroup):
-// within each wave by shuffles, then the totals of the waves before it.
+// Inclusive sum over the workgroup's threads: within each wave by shuffles,
+// then the totals of the waves before it (scratch: one entry per wave).
 __device__ __forceinline__ uint32_t block_incl_scan_u32(uint32_t v, uint32_t *scratch)
 {
-    static_assert(kOrbBlock == 256, "one bin per thread");
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int o = 1; o < 64; o <<= 1) {
         const uint32_t y = (uint32_t)__shfl_up((int)v, o);
@@ -298,7 +300,7 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_bbox(const int3 *__restrict__
 // only reads it whole.  keys: as for k_orb_bbox; cur: original index per
 // position.  The first pass also sets up the states of the next level
 // (st_next), which the partition fills in.
-__global__ __launch_bounds__(kOrbBlock) void k_orb_hist(const int3 *__restrict__ chunks,
+__global__ __launch_bounds__(kPassBlock) void k_orb_hist(const int3 *__restrict__ chunks,
                                                         const int3 *__restrict__ segs,
                                                         const uint32_t *__restrict__ keys, int n,
                                                         const int32_t *__restrict__ cur,
@@ -308,7 +310,7 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_hist(const int3 *__restrict__
                                                         SegState *__restrict__ st_next)
 {
     __shared__ uint32_t h[kBins];
-    __shared__ uint32_t red[kOrbBlock / 64];
+    __shared__ uint32_t red[kPassBlock / 64];
     __shared__ int last;
     if (round == 0 && threadIdx.x == 0)
         for (int s = blockIdx.x; s < nseg_next; s += gridDim.x) init_state(&st_next[s], segs_next[s].z);
@@ -325,25 +327,25 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_hist(const int3 *__restrict__
     const bool need_idx = shift < 32 || mode == kFind;
     // positions past the chunk's end read its last element (no branch around
     // the loads, so they are all in flight together) and are masked below
-    uint64_t key[kChunkPer];
+    uint64_t key[kPassPer];
     if (need_idx) {
 #pragma unroll
-        for (int u = 0; u < kChunkPer; ++u) {
-            const int p = min(c.y + u * kOrbBlock + (int)threadIdx.x, c.z - 1);
+        for (int u = 0; u < kPassPer; ++u) {
+            const int p = min(c.y + u * kPassBlock + (int)threadIdx.x, c.z - 1);
             key[u] = ((uint64_t)ka[p] << 32) | (uint32_t)cur[p];
         }
     } else {
 #pragma unroll
-        for (int u = 0; u < kChunkPer; ++u) {
-            const int p = min(c.y + u * kOrbBlock + (int)threadIdx.x, c.z - 1);
+        for (int u = 0; u < kPassPer; ++u) {
+            const int p = min(c.y + u * kPassBlock + (int)threadIdx.x, c.z - 1);
             key[u] = (uint64_t)ka[p] << 32;
         }
     }
     // (round 0 has no prefix: a shift by 64 is not defined, so test it apart)
     if (mode == kFind) {
 #pragma unroll
-        for (int u = 0; u < kChunkPer; ++u) {
-            const int p = c.y + u * kOrbBlock + threadIdx.x;
+        for (int u = 0; u < kPassPer; ++u) {
+            const int p = c.y + u * kPassBlock + threadIdx.x;
             if (p < c.z && (round == 0 || (key[u] >> pshift) == prefix))
                 performed(__hip_atomic_exchange(&st[c.x].full, key[u], __ATOMIC_RELAXED,
                                                 __HIP_MEMORY_SCOPE_AGENT));
@@ -356,50 +358,33 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_hist(const int3 *__restrict__
         }
         return;
     }
-#pragma unroll
-    for (int j = 0; j < kBinsPer; ++j) h[j * kOrbBlock + threadIdx.x] = 0u;
+    if (threadIdx.x < kBins) h[threadIdx.x] = 0u;
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < kChunkPer; ++u) {
-        const int p = c.y + u * kOrbBlock + threadIdx.x;
+    for (int u = 0; u < kPassPer; ++u) {
+        const int p = c.y + u * kPassBlock + threadIdx.x;
         if (p < c.z && (round == 0 || (key[u] >> pshift) == prefix))
             atomicAdd(&h[(uint32_t)(key[u] >> shift) & dmask], 1u);
     }
     __syncthreads();
     uint32_t *hs = hist + (size_t)c.x * kBins;
-#pragma unroll
-    for (int j = 0; j < kBinsPer; ++j) {
-        const uint32_t v = h[j * kOrbBlock + threadIdx.x];
-        if (v) performed(atomicAdd(&hs[j * kOrbBlock + threadIdx.x], v));
+    if (threadIdx.x < kBins) {
+        const uint32_t v = h[threadIdx.x];
+        if (v) performed(atomicAdd(&hs[threadIdx.x], v));
     }
     if (!last_of_segment(st, c.x, segs, &last)) return;
-    // the last workgroup: thread t holds bins [t * kBinsPer, (t + 1) * kBinsPer)
-    uint32_t cnt[kBinsPer], tot = 0;
-#pragma unroll
-    for (int j = 0; j < kBinsPer; ++j) {
-        cnt[j] = load_dev(&hs[threadIdx.x * kBinsPer + j]);
-        store_dev(&hs[threadIdx.x * kBinsPer + j], 0u);
-        tot += cnt[j];
+    // the last workgroup: thread t < kBins holds bin t
+    uint32_t cnt = 0;
+    if (threadIdx.x < kBins) {
+        cnt = load_dev(&hs[threadIdx.x]);
+        store_dev(&hs[threadIdx.x], 0u);
     }
-    const uint32_t inc = block_incl_scan_u32(tot, red);
+    const uint32_t inc = block_incl_scan_u32(cnt, red);
     const uint32_t krem = (uint32_t)st[c.x].krem;
-    if (inc >= krem && inc - tot < krem) {
-        // the first of this thread's bins where the running count reaches krem
-        uint32_t acc = inc - tot, before = 0, c1 = 0;
-        int jb = -1;
-#pragma unroll
-        for (int j = 0; j < kBinsPer; ++j) {
-            if (jb < 0 && acc + cnt[j] >= krem) {
-                jb = j;
-                before = acc;
-                c1 = cnt[j];
-            }
-            acc += cnt[j];
-        }
-        const uint32_t bin = (uint32_t)(threadIdx.x * kBinsPer + jb);
-        st[c.x].prefix = (round == 0 ? 0ull : prefix << (pshift - shift)) | bin;
-        st[c.x].krem = (int)(krem - before);
-        st[c.x].mode = (c1 == 1u && round < kCoordRounds - 1) ? kFind : kSelect;
+    if (inc >= krem && inc - cnt < krem) {
+        st[c.x].prefix = (round == 0 ? 0ull : prefix << (pshift - shift)) | (uint64_t)threadIdx.x;
+        st[c.x].krem = (int)(krem - (inc - cnt));
+        st[c.x].mode = (cnt == 1u && round < kCoordRounds - 1) ? kFind : kSelect;
     }
     if (threadIdx.x == 0) store_dev(&st[c.x].arrived, 0u);
 }
@@ -409,7 +394,7 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_hist(const int3 *__restrict__
 // gathered into cand (at the segment's own positions), and the workgroup that
 // finishes the segment selects the krem-th smallest of them (radix select
 // over the 32-bit index; a single body needs none).
-__global__ __launch_bounds__(kOrbBlock) void k_orb_ties(const int3 *__restrict__ chunks,
+__global__ __launch_bounds__(kPassBlock) void k_orb_ties(const int3 *__restrict__ chunks,
                                                         const int3 *__restrict__ segs,
                                                         const uint32_t *__restrict__ keys, int n,
                                                         const int32_t *__restrict__ cur,
@@ -417,7 +402,7 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_ties(const int3 *__restrict__
                                                         uint32_t *__restrict__ cand)
 {
     __shared__ uint32_t h[256];
-    __shared__ uint32_t red[kOrbBlock / 64];
+    __shared__ uint32_t red[kPassBlock / 64];
     __shared__ uint32_t sel_s, krem_s;
     __shared__ int last;
     const int3 c = chunks[blockIdx.x];
@@ -426,12 +411,12 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_ties(const int3 *__restrict__
     const int3 sg = segs[c.x];
     const uint32_t *ka = keys + (size_t)seg_axis(&st[c.x]) * n;
     const int lane = threadIdx.x & 63;
-    uint32_t kv[kChunkPer];
+    uint32_t kv[kPassPer];
 #pragma unroll
-    for (int u = 0; u < kChunkPer; ++u) kv[u] = ka[min(c.y + u * kOrbBlock + (int)threadIdx.x, c.z - 1)];
+    for (int u = 0; u < kPassPer; ++u) kv[u] = ka[min(c.y + u * kPassBlock + (int)threadIdx.x, c.z - 1)];
 #pragma unroll
-    for (int u = 0; u < kChunkPer; ++u) {
-        const int p = c.y + u * kOrbBlock + threadIdx.x;
+    for (int u = 0; u < kPassPer; ++u) {
+        const int p = c.y + u * kPassBlock + threadIdx.x;
         const bool hit = p < c.z && kv[u] == coord;
         const uint64_t mk = __ballot(hit);
         if (!mk) continue;
@@ -459,16 +444,16 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_ties(const int3 *__restrict__
         }
         for (int round = 0; round < 4; ++round) {
             __syncthreads();
-            h[threadIdx.x] = 0u;
+            if (threadIdx.x < 256) h[threadIdx.x] = 0u;
             const uint32_t prefix = sel_s, kr = krem_s;
             const int shift = 24 - 8 * round;
             __syncthreads();
-            for (uint32_t i = threadIdx.x; i < T; i += kOrbBlock) {
+            for (uint32_t i = threadIdx.x; i < T; i += kPassBlock) {
                 const uint32_t v = load_dev(&cs[i]);
                 if (round == 0 || (v >> (shift + 8)) == prefix) atomicAdd(&h[(v >> shift) & 0xFFu], 1u);
             }
             __syncthreads();
-            const uint32_t hv = h[threadIdx.x];
+            const uint32_t hv = threadIdx.x < 256 ? h[threadIdx.x] : 0u;
             const uint32_t inc = block_incl_scan_u32(hv, red);
             if (inc >= kr && inc - hv < kr) {
                 sel_s = (prefix << 8) | (uint32_t)threadIdx.x;
@@ -491,7 +476,7 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_ties(const int3 *__restrict__
 // go to cur_out and the three axes' keys to keys_out, both in the new order.
 // Each side's key box is accumulated into its next-level state (if it has
 // one).
-__global__ __launch_bounds__(kOrbBlock) void k_orb_partition(const int3 *__restrict__ chunks,
+__global__ __launch_bounds__(kPassBlock) void k_orb_partition(const int3 *__restrict__ chunks,
                                                              const int3 *__restrict__ segs,
                                                              const int2 *__restrict__ kids,
                                                              const uint32_t *__restrict__ keys,
@@ -501,8 +486,8 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_partition(const int3 *__restr
                                                              SegState *__restrict__ st,
                                                              SegState *__restrict__ st_next)
 {
-    constexpr int kW = kOrbBlock / 64;
-    __shared__ uint32_t cl[kChunkPer * kW], cr[kChunkPer * kW];
+    constexpr int kW = kPassBlock / 64;
+    __shared__ uint32_t cl[kPassPer * kW], cr[kPassPer * kW];
     __shared__ uint32_t bl, br;
     __shared__ uint32_t box[kW][12];
     __shared__ uint32_t tot[12];
@@ -512,12 +497,12 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_partition(const int3 *__restr
     const uint64_t below = (1ull << lane) - 1ull;
     const uint32_t *ka = keys + (size_t)seg_axis(&st[c.x]) * n;
     // this thread's bodies and their sides, loaded together
-    int bod[kChunkPer];
-    uint32_t rank[kChunkPer];
-    bool lft[kChunkPer];
+    int bod[kPassPer];
+    uint32_t rank[kPassPer];
+    bool lft[kPassPer];
 #pragma unroll
-    for (int u = 0; u < kChunkPer; ++u) {
-        const int p = c.y + u * kOrbBlock + threadIdx.x;
+    for (int u = 0; u < kPassPer; ++u) {
+        const int p = c.y + u * kPassBlock + threadIdx.x;
         const int q = min(p, c.z - 1);  // loads without a branch, masked below
         const int b = cur[q];
         lft[u] = (((uint64_t)ka[q] << 32) | (uint32_t)b) <= kth;
@@ -525,7 +510,7 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_partition(const int3 *__restr
     }
     // rank inside the (step, wave) group by ballots, group totals in LDS
 #pragma unroll
-    for (int u = 0; u < kChunkPer; ++u) {
+    for (int u = 0; u < kPassPer; ++u) {
         const uint64_t ml = __ballot(bod[u] >= 0 && lft[u]);
         const uint64_t mr = __ballot(bod[u] >= 0 && !lft[u]);
         rank[u] = (uint32_t)__popcll((lft[u] ? ml : mr) & below);
@@ -535,10 +520,10 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_partition(const int3 *__restr
         }
     }
     __syncthreads();
-    // exclusive scans over the kChunkPer * kW groups (position order), by wave 0
-    static_assert(kChunkPer * kW <= 64, "one group per lane of wave 0");
+    // exclusive scans over the kPassPer * kW groups (position order), by wave 0
+    static_assert(kPassPer * kW <= 64, "one group per lane of wave 0");
     if (w == 0) {
-        const bool g = lane < kChunkPer * kW;
+        const bool g = lane < kPassPer * kW;
         const uint32_t a = g ? cl[lane] : 0u, b = g ? cr[lane] : 0u;
         uint32_t ia = a, ib = b;
         for (int o = 1; o < 64; o <<= 1) {
@@ -568,9 +553,9 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_partition(const int3 *__restr
     }
     // destinations; exactly k keys are <= the k-th key, and the guards only
     // keep a violated precondition (non-finite coordinates) inside the segment
-    int dst[kChunkPer];
+    int dst[kPassPer];
 #pragma unroll
-    for (int u = 0; u < kChunkPer; ++u) {
+    for (int u = 0; u < kPassPer; ++u) {
         const uint32_t q = (lft[u] ? bl + cl[u * kW + w] : br + cr[u * kW + w]) + rank[u];
         const bool fits = lft[u] ? q < (uint32_t)sg.z : q < (uint32_t)(sg.y - sg.z);
         dst[u] = bod[u] >= 0 && fits ? sg.x + (lft[u] ? 0 : sg.z) + (int)q : -1;
@@ -579,11 +564,11 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_partition(const int3 *__restr
     // one axis at a time: all of the thread's loads first, then the stores
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        uint32_t kv[kChunkPer];
+        uint32_t kv[kPassPer];
 #pragma unroll
-        for (int u = 0; u < kChunkPer; ++u) kv[u] = keys[(size_t)a * n + min(c.y + u * kOrbBlock + (int)threadIdx.x, c.z - 1)];
+        for (int u = 0; u < kPassPer; ++u) kv[u] = keys[(size_t)a * n + min(c.y + u * kPassBlock + (int)threadIdx.x, c.z - 1)];
 #pragma unroll
-        for (int u = 0; u < kChunkPer; ++u) {
+        for (int u = 0; u < kPassPer; ++u) {
             if (dst[u] < 0) continue;
             keys_out[(size_t)a * n + dst[u]] = kv[u];
             const int o = lft[u] ? 0 : 6;
@@ -1252,11 +1237,11 @@ int orb_order(const void *pm, int prec, int n, int leaf, int32_t *perm, hipStrea
             hipLaunchKernelGGL(k_orb_bbox, dim3(nch), dim3(kOrbBlock), 0, s, chunks, kbuf[i], n, st[i]);
         }
         for (int r = 0; r < kCoordRounds; ++r)
-            hipLaunchKernelGGL(k_orb_hist, dim3(nch), dim3(kOrbBlock), 0, s, chunks, segs, kbuf[i], n, cbuf[i],
+            hipLaunchKernelGGL(k_orb_hist, dim3(nch), dim3(kPassBlock), 0, s, chunks, segs, kbuf[i], n, cbuf[i],
                                st[i], hist, r, segs_next, nseg_next, st[o]);
-        hipLaunchKernelGGL(k_orb_ties, dim3(nch), dim3(kOrbBlock), 0, s, chunks, segs, kbuf[i], n, cbuf[i], st[i],
+        hipLaunchKernelGGL(k_orb_ties, dim3(nch), dim3(kPassBlock), 0, s, chunks, segs, kbuf[i], n, cbuf[i], st[i],
                            cand);
-        hipLaunchKernelGGL(k_orb_partition, dim3(nch), dim3(kOrbBlock), 0, s, chunks, segs, kids, kbuf[i], kbuf[o],
+        hipLaunchKernelGGL(k_orb_partition, dim3(nch), dim3(kPassBlock), 0, s, chunks, segs, kids, kbuf[i], kbuf[o],
                            n, cbuf[i], cbuf[o], st[i], st[o]);
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "ORB level");
