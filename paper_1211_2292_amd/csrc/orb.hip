@@ -650,6 +650,8 @@ __device__ void orb_wave(int32_t *pos, const uint32_t (*skey)[kSmall], const int
         int k = sm;
         if (split) {
             uint32_t bb[6] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0u, 0u};
+            // (unrolled so that several LDS reads are in flight per wait)
+#pragma unroll 4
             for (int f = slo; f < slo + sm; ++f)
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
@@ -660,6 +662,7 @@ __device__ void orb_wave(int32_t *pos, const uint32_t (*skey)[kSmall], const int
             const int axis = pick_axis(bb);
             const uint32_t mine = axis == 0 ? kx : (axis == 1 ? ky : kz);
             int r = 0;
+#pragma unroll 4
             for (int f = slo; f < slo + sm; ++f) {
                 const uint32_t v = keys[axis][f];
                 r += (v < mine) || (v == mine && wid[f] < b);
@@ -693,6 +696,7 @@ __device__ void orb_wave(int32_t *pos, const uint32_t (*skey)[kSmall], const int
     // leaves: ascending original index
     int r = 0;
     if (lane < m)
+#pragma unroll 4
         for (int f = slo; f < slo + sm; ++f) r += wid[f] < b;
     if (lane < m) pos[lo + slo + r] = s;
 }
@@ -738,6 +742,7 @@ __device__ void wave_subtree(int32_t *pos, int32_t *tmp, uint32_t *akey, const u
             for (int e = lane; e < m; e += 64) {
                 const uint32_t v = akey[lo + e];
                 int r = 0;
+#pragma unroll 4
                 for (int f = 0; f < m; ++f) r += akey[lo + f] < v;
                 tmp[lo + r] = pos[lo + e];
             }
@@ -870,6 +875,7 @@ __device__ __forceinline__ void block_leaf(int32_t *pos, int32_t *tmp, uint32_t 
     for (int e = threadIdx.x; e < m; e += kOrbBlock) {
         const uint32_t v = val[lo + e];
         int r = 0;
+#pragma unroll 4
         for (int f = 0; f < m; ++f) r += val[lo + f] < v;
         tmp[lo + r] = pos[lo + e];
     }
