@@ -794,7 +794,9 @@ __device__ void wave_subtree(int32_t *pos, int32_t *tmp, uint32_t *akey, const u
             for (int j = lane; j < 256; j += 64) hw[j] = 0u;
             wave_sync();
             for (int e = lane; e < m; e += 64) {
-                const uint64_t key = ((uint64_t)akey[lo + e] << 32) | (uint32_t)gid[pos[lo + e]];
+                // the first four digits are the coordinate key's: no index needed
+                uint64_t key = (uint64_t)akey[lo + e] << 32;
+                if (round >= 4) key |= (uint32_t)gid[pos[lo + e]];
                 if (round == 0 || (key >> (shift + 8)) == prefix) atomicAdd(&hw[(key >> shift) & 0xFF], 1u);
             }
             wave_sync();
@@ -843,7 +845,9 @@ __device__ void wave_subtree(int32_t *pos, int32_t *tmp, uint32_t *akey, const u
             const int e = e0 + lane;
             const bool act = e < m;
             const int s = act ? pos[lo + e] : 0;
-            const bool left = act && (((uint64_t)akey[lo + (act ? e : 0)] << 32) | (uint32_t)gid[s]) <= kth;
+            // (key, index) <= kth; the index only decides between equal keys
+            const uint32_t hk = akey[lo + (act ? e : 0)], kh = (uint32_t)(kth >> 32);
+            const bool left = act && (hk < kh || (hk == kh && (uint32_t)gid[s] <= (uint32_t)kth));
             const bool right = act && !left;
             const unsigned long long bl = __ballot(left), br = __ballot(right);
             const int rl = __builtin_amdgcn_mbcnt_hi((unsigned)(bl >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bl, 0u));
@@ -1004,7 +1008,9 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_block(const int3 *__restrict_
             }
             __syncthreads();
             for (int e = threadIdx.x; e < m; e += kOrbBlock) {
-                const uint64_t key = ((uint64_t)akey[e] << 32) | (uint32_t)gid[pos[lo + e]];
+                // the first four digits are the coordinate key's: no index needed
+                uint64_t key = (uint64_t)akey[e] << 32;
+                if (round >= 4) key |= (uint32_t)gid[pos[lo + e]];
                 if (round == 0 || (key >> (shift + 8)) == prefix) atomicAdd(&h[(key >> shift) & 0xFF], 1u);
             }
             __syncthreads();
@@ -1030,7 +1036,9 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_block(const int3 *__restrict_
                 const int e = e0 + threadIdx.x;
                 const bool act = e < m;
                 const int s = act ? pos[lo + e] : 0;
-                const bool left = act && (((uint64_t)akey[act ? e : 0] << 32) | (uint32_t)gid[s]) <= kth;
+                // (key, index) <= kth; the index only decides between equal keys
+                const uint32_t hk = akey[act ? e : 0], kh = (uint32_t)(kth >> 32);
+                const bool left = act && (hk < kh || (hk == kh && (uint32_t)gid[s] <= (uint32_t)kth));
                 const bool right = act && !left;
                 const unsigned long long bl = __ballot(left), br = __ballot(right);
                 if (lane == 0) {
