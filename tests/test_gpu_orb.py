@@ -19,7 +19,7 @@ def _gpu_perm(torch, nb, pos4, leaf, dtype):
 
 @pytest.mark.parametrize("n,leaf", [(1, 1), (2, 1), (7, 2), (100, 1), (100, 7), (2049, 16), (4097, 64),
                                     (10000, 1), (10000, 256), (20000, 4096), (65536, 128), (70001, 3),
-                                    (3000, 2500), (9000, 2100)])
+                                    (3000, 2500), (9000, 2100), (131073, 2), (300007, 5)])
 def test_orb_bitexact_plummer(orc, n, leaf):
     torch, nb = gpu()
     pm, _ = ics.plummer(max(n, 2), 200 + n)
