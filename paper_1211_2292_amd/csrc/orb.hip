@@ -125,7 +125,7 @@ struct SegState {
     int mode;          // SegMode
     uint64_t prefix;   // digits of the k-th key found so far
     uint64_t full;     // the k-th key, written by the kFind pass
-    uint32_t lcnt, rcnt;
+    uint64_t placed;   // partition: bodies placed (high half) and placed left (low half)
     uint32_t arrived;  // workgroups of the current pass done with the segment
     uint32_t ties;     // bodies whose coordinate equals the k-th key's (k_orb_ties)
 };
@@ -141,7 +141,7 @@ __device__ __forceinline__ void init_state(SegState *st, int k)
     z.mode = kSelect;
     z.prefix = 0;
     z.full = 0;
-    z.lcnt = z.rcnt = 0;
+    z.placed = 0;
     z.arrived = 0;
     z.ties = 0;
     *st = z;
@@ -538,8 +538,13 @@ __global__ __launch_bounds__(kPassBlock) void k_orb_partition(const int3 *__rest
             cr[lane] = ib - b;
         }
         if (lane == 63) {
-            bl = atomicAdd(&st[c.x].lcnt, ia);
-            br = atomicAdd(&st[c.x].rcnt, ib);
+            // one atomic for both runs: the bodies placed before this
+            // workgroup, and how many of them went left
+            const unsigned long long was =
+                atomicAdd(reinterpret_cast<unsigned long long *>(&st[c.x].placed),
+                          ((unsigned long long)(ia + ib) << 32) | ia);
+            bl = (uint32_t)was;
+            br = (uint32_t)(was >> 32) - (uint32_t)was;
         }
     }
     __syncthreads();
