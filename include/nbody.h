@@ -101,7 +101,7 @@ enum {
  *   FP32 first.  The result is a pure function of the input (bit-exact).
  * pos_mass: n records (float4 or double4 by prec).  perm_out: int32[n],
  * perm_out[p] = original index of the body at position p.  Uses library
- * scratch of about 48 bytes per body.  Non-finite coordinates make the order
+ * scratch of about 36 bytes per body.  Non-finite coordinates make the order
  * unspecified; with the environment variable NBODY_CHECK_INPUTS set (to
  * anything but "0") the call first checks every record, synchronises the
  * stream, and refuses non-finite coordinates or masses with NBODY_E_INVAL

@@ -68,11 +68,10 @@ __device__ __forceinline__ int pick_axis(const uint32_t *bb)
     return axis;
 }
 
-// FP32 coordinates by original index (xyz), and their total-order keys in
-// the current order (identity at the start).
+// Total-order keys of the FP32 coordinates in the current order (identity at
+// the start).
 template <typename V>
 __global__ __launch_bounds__(kOrbBlock) void k_orb_coords(const V *__restrict__ pm, int n,
-                                                          float *__restrict__ xyz,
                                                           uint32_t *__restrict__ keys,
                                                           int32_t *__restrict__ cur)
 {
@@ -81,10 +80,7 @@ __global__ __launch_bounds__(kOrbBlock) void k_orb_coords(const V *__restrict__ 
     const V p = pm[i];
     const float f[3] = {(float)p.x, (float)p.y, (float)p.z};
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        xyz[(size_t)a * n + i] = f[a];
-        keys[(size_t)a * n + i] = tkey(f[a]);
-    }
+    for (int a = 0; a < 3; ++a) keys[(size_t)a * n + i] = tkey(f[a]);
     cur[i] = i;
 }
 
@@ -1180,9 +1176,9 @@ int orb_order(const void *pm, int prec, int n, int leaf, int32_t *perm, hipStrea
     }
     const size_t foff = put(finals.data(), finals.size() * sizeof(int3));
     const size_t nbytes = (size_t)n * 4;
-    // xyz by original index, then two buffers of the three axes' keys in the
-    // current order (each level reads one and writes the other)
-    float *xyz = (float *)scratch(kSlotOrb0, 10 * nbytes);
+    // two buffers of the three axes' keys in the current order (each level
+    // reads one and writes the other), then the tie pass's candidates
+    uint32_t *kmem = (uint32_t *)scratch(kSlotOrb0, 7 * nbytes);
     // original index per position, same two-buffer scheme as the keys
     int32_t *cbuf[2] = {(int32_t *)scratch(kSlotOrb1, nbytes), (int32_t *)scratch(kSlotOrb2, nbytes)};
     char *dtab = (char *)scratch(kSlotOrb3, tab.size() + 16);
@@ -1190,12 +1186,12 @@ int orb_order(const void *pm, int prec, int n, int leaf, int32_t *perm, hipStrea
     // histogram row per segment
     const size_t stbytes = (maxseg * sizeof(SegState) + 63) & ~size_t(63);
     char *state = (char *)scratch(kSlotOrb4, 2 * stbytes + maxseg * kBins * 4 + 64);
-    if (!xyz || !cbuf[0] || !cbuf[1] || !dtab || !state) {
+    if (!kmem || !cbuf[0] || !cbuf[1] || !dtab || !state) {
         set_error("cannot allocate ORB scratch");
         return NBODY_E_NOMEM;
     }
-    uint32_t *kbuf[2] = {(uint32_t *)(xyz + 3 * (size_t)n), (uint32_t *)(xyz + 6 * (size_t)n)};
-    uint32_t *cand = (uint32_t *)(xyz + 9 * (size_t)n);  // tied bodies' indices (k_orb_ties)
+    uint32_t *kbuf[2] = {kmem, kmem + 3 * (size_t)n};
+    uint32_t *cand = kmem + 6 * (size_t)n;  // tied bodies' indices (k_orb_ties)
     SegState *st[2] = {(SegState *)state, (SegState *)(state + stbytes)};
     uint32_t *hist = (uint32_t *)(state + 2 * stbytes);
     {
@@ -1235,10 +1231,10 @@ int orb_order(const void *pm, int prec, int n, int leaf, int32_t *perm, hipStrea
     }
     const int nb = (n + kOrbBlock - 1) / kOrbBlock;
     if (prec == NBODY_F64)
-        hipLaunchKernelGGL(k_orb_coords<double4>, dim3(nb), dim3(kOrbBlock), 0, s, (const double4 *)pm, n, xyz,
+        hipLaunchKernelGGL(k_orb_coords<double4>, dim3(nb), dim3(kOrbBlock), 0, s, (const double4 *)pm, n,
                            kbuf[0], cbuf[0]);
     else
-        hipLaunchKernelGGL(k_orb_coords<float4>, dim3(nb), dim3(kOrbBlock), 0, s, (const float4 *)pm, n, xyz,
+        hipLaunchKernelGGL(k_orb_coords<float4>, dim3(nb), dim3(kOrbBlock), 0, s, (const float4 *)pm, n,
                            kbuf[0], cbuf[0]);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "ORB coordinates");
