@@ -467,7 +467,7 @@ __global__ __launch_bounds__(kPassBlock) void k_orb_ties(const int3 *__restrict_
 }
 
 // Keys <= the k-th key go left.  Each workgroup takes one run of slots per
-// side with one atomic each and fills it in position order (ballot ranks);
+// side (one 64-bit atomic gives both) and fills it in position order (ballot ranks);
 // the order of the runs is irrelevant to the result.  The original indices
 // go to cur_out and the three axes' keys to keys_out, both in the new order.
 // Each side's key box is accumulated into its next-level state (if it has
